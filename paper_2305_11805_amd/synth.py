@@ -1,0 +1,282 @@
+"""Seeded synthetic inputs: atomic configurations, descriptor hyperparameters
+and random MLP weights.
+
+This module only draws inputs.  It holds none of the method's arithmetic (no
+descriptor, network or force code) and is the one module shared by the GPU
+path's callers and by the tests that feed the same arrays to the oracle.
+
+Workloads stand in for the paper's data sets, which are not available here:
+  * configs 0 and 2: small organic molecules with {H, C, N, O} (the rMD17
+    benchmark of Sec. III.A) -- non-periodic clusters;
+  * configs 1, 3, 4: bulk periodic cells (the Carbon data of Sec. III.B and
+    the repeated MD evaluation of Table II).
+Placement is random sequential addition (RSA): uniform candidates, rejected
+when closer than d_min to an accepted atom (minimum image in periodic boxes).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+SEED_BASE = 1000
+
+
+@dataclass
+class System:
+    """A batch of structures.  Atoms of structure c are [atom_ptr[c], atom_ptr[c+1])."""
+    pos: np.ndarray        # [N, 3] float64 (Angstrom)
+    species: np.ndarray    # [N] int32
+    atom_ptr: np.ndarray   # [B+1] int64
+    cell: np.ndarray       # [B, 3, 3] float64, rows = lattice vectors a, b, c
+    pbc: np.ndarray        # [B, 3] uint8
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_structs(self) -> int:
+        return int(self.atom_ptr.shape[0] - 1)
+
+
+@dataclass
+class MBPParams:
+    """Descriptor hyperparameters (grids as explicit arrays)."""
+    n_species: int
+    rc: float
+    eta_rad: float
+    rs_rad: np.ndarray
+    theta_s: np.ndarray
+    eta_ang: float
+    rs_ang: np.ndarray
+    zeta: float = 50.0
+    eps: float = 1e-3
+
+    @property
+    def n_rad(self) -> int:
+        return int(len(self.rs_rad))
+
+    @property
+    def n_theta(self) -> int:
+        return int(len(self.theta_s))
+
+    @property
+    def n_rs_ang(self) -> int:
+        return int(len(self.rs_ang))
+
+    @property
+    def dim(self) -> int:
+        S = self.n_species
+        return self.n_rad * S + self.n_theta * self.n_rs_ang * S * (S + 1) // 2
+
+
+# A model is a list over species of (widths, activations, [W_l], [b_l]) with
+# W_l of shape [widths[l], widths[l-1]] in float64.
+Model = List[Tuple[List[int], List[str], List[np.ndarray], List[np.ndarray]]]
+
+
+@dataclass
+class Workload:
+    name: str
+    system: System
+    params: MBPParams
+    model: Model
+    seed: int
+    extra: dict = field(default_factory=dict)
+
+
+def mbp_params(n_species, rc, n_rad, n_theta, n_rs_ang, eta_rad=16.0, eta_ang=12.0, zeta=50.0,
+               eps=1e-3, r_min=0.5) -> MBPParams:
+    """Evenly spaced grids: radial centres r_min..rc (inclusive), angular
+    radial centres r_min..rc (inclusive), angle centres (p + 1/2) pi / n_theta."""
+    return MBPParams(
+        n_species=n_species, rc=float(rc), eta_rad=float(eta_rad),
+        rs_rad=np.linspace(r_min, rc, n_rad), theta_s=(np.arange(n_theta) + 0.5) * np.pi / n_theta,
+        eta_ang=float(eta_ang), rs_ang=np.linspace(r_min, rc, n_rs_ang), zeta=float(zeta), eps=float(eps))
+
+
+def random_model(n_species, D, hidden: Sequence[int], seed, act="gaussian", in_scale=1.0) -> Model:
+    """Per-species MLP D -> hidden... -> 1 with W, b ~ N(0, 1/fan_in), seeded
+    per species and layer.  The first layer's draws are multiplied by
+    in_scale (the inverse of a typical descriptor magnitude) so that the
+    Gaussian units are neither saturated nor flat."""
+    model = []
+    widths = [D] + list(hidden) + [1]
+    acts = [act] * len(hidden) + ["linear"]
+    for s in range(n_species):
+        Ws, bs = [], []
+        for l in range(1, len(widths)):
+            rng = np.random.Generator(np.random.PCG64([seed, s, l]))
+            std = 1.0 / np.sqrt(widths[l - 1])
+            W = rng.normal(0.0, std, size=(widths[l], widths[l - 1]))
+            b = rng.normal(0.0, std, size=(widths[l],))
+            if l == 1:
+                W *= in_scale
+            Ws.append(W)
+            bs.append(b)
+        model.append((list(widths), list(acts), Ws, bs))
+    return model
+
+
+# ----------------------------------------------------------------------------
+# placement
+# ----------------------------------------------------------------------------
+
+def rsa_cluster(rng, n, box, d_min, max_tries=100000) -> np.ndarray:
+    """n points uniform in [0, box)^3, none closer than d_min (no periodicity)."""
+    pts = np.empty((n, 3))
+    k, tries = 0, 0
+    while k < n:
+        c = rng.uniform(0.0, box, size=3)
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("RSA did not converge")
+        if k and np.min(np.sum((pts[:k] - c) ** 2, axis=1)) < d_min * d_min:
+            continue
+        pts[k] = c
+        k += 1
+    return pts
+
+
+def rsa_periodic(rng, n, L, d_min) -> np.ndarray:
+    """n points uniform in a periodic cube of side L with minimum-image
+    distance >= d_min, placed in batches (candidates are accepted in draw
+    order, so the result is the sequential RSA of the drawn stream)."""
+    from scipy.spatial import cKDTree
+
+    acc = np.empty((0, 3))
+    while acc.shape[0] < n:
+        need = n - acc.shape[0]
+        cand = rng.uniform(0.0, L, size=(max(64, int(need * 1.15) + 16), 3))
+        cand = np.minimum(cand, np.nextafter(L, 0.0))
+        if acc.shape[0]:
+            tree = cKDTree(acc, boxsize=L)
+            dist, _ = tree.query(cand, k=1, distance_upper_bound=d_min)
+            cand = cand[~(dist < d_min)]
+        if cand.shape[0] == 0:
+            continue
+        ctree = cKDTree(cand, boxsize=L)
+        pairs = ctree.query_pairs(d_min, output_type="ndarray")
+        keep = np.ones(cand.shape[0], bool)
+        if pairs.size:
+            conflicts = [[] for _ in range(cand.shape[0])]
+            for a, b in pairs:
+                lo, hi = (a, b) if a < b else (b, a)
+                conflicts[hi].append(lo)
+            for idx in range(cand.shape[0]):
+                if conflicts[idx] and any(keep[j] for j in conflicts[idx]):
+                    keep[idx] = False
+        acc = np.concatenate([acc, cand[keep][:need]])
+    return acc
+
+
+def _cube(L):
+    return np.diag([L, L, L]).astype(np.float64)
+
+
+def clusters_system(rng, sizes, box_of, d_min, n_species, species_p=None) -> System:
+    pos, sp, ptr, cell = [], [], [0], []
+    for n in sizes:
+        L = box_of(n)
+        pos.append(rsa_cluster(rng, n, L, d_min))
+        sp.append(rng.choice(n_species, size=n, p=species_p).astype(np.int32))
+        ptr.append(ptr[-1] + n)
+        cell.append(_cube(L))
+    B = len(sizes)
+    return System(np.concatenate(pos), np.concatenate(sp), np.asarray(ptr, np.int64), np.stack(cell),
+                  np.zeros((B, 3), np.uint8))
+
+
+def bulk_system(rng, n, density, d_min, species_counts) -> System:
+    L = (n / density) ** (1.0 / 3.0)
+    pos = rsa_periodic(rng, n, L, d_min)
+    sp = np.concatenate([np.full(c, s, np.int32) for s, c in enumerate(species_counts)])
+    rng.shuffle(sp)
+    return System(pos, sp, np.asarray([0, n], np.int64), _cube(L)[None], np.ones((1, 3), np.uint8))
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+# ----------------------------------------------------------------------------
+
+# Scale applied to the first-layer weights: sqrt(D) over the typical RMS norm
+# of a descriptor row of that workload (rounded), so that first-layer
+# pre-activations are O(1) and the Gaussian units are in their sensitive
+# range.  A fixed constant per workload, not computed from the data.
+IN_SCALE = {0: 14.0, 1: 0.45, 2: 12.0, 3: 3.3, 4: 0.6}
+
+
+def config(idx: int, scale: float = 1.0) -> Workload:
+    """Workload `idx` (0..4).  `scale` < 1 shrinks bulk systems (same density
+    and hyperparameters) for fast tests; it does not apply to clusters."""
+    seed = SEED_BASE + idx
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if idx == 0:
+        sys = clusters_system(rng, [12] * 16, lambda n: 6.0, 0.9, 4)
+        p = mbp_params(4, 4.6, 16, 8, 4)
+        model = random_model(4, p.dim, [64, 32], seed, in_scale=IN_SCALE[0])
+        name = "16 clusters x 12 atoms, 4 species, Rc 4.6, 16 + 8x4 bins, MLP D-64-32-1"
+    elif idx == 1:
+        n = max(16, int(round(4096 * scale)))
+        sys = bulk_system(rng, n, 0.1, 1.2, [n])
+        p = mbp_params(1, 5.0, 32, 8, 8)
+        model = random_model(1, p.dim, [128, 128], seed, in_scale=IN_SCALE[1])
+        name = f"periodic bulk {n} atoms, 1 species, rho 0.1, Rc 5.0, 32 + 8x8 bins, MLP D-128-128-1"
+    elif idx == 2:
+        nb = max(1, int(round(2048 * scale)))
+        sizes = rng.integers(5, 61, size=nb)
+        sys = clusters_system(rng, sizes, lambda n: (n / 0.05) ** (1.0 / 3.0), 0.9, 4)
+        p = mbp_params(4, 4.6, 16, 8, 4)
+        model = random_model(4, p.dim, [64, 32], seed, in_scale=IN_SCALE[2])
+        name = f"{nb} clusters of 5-60 atoms, 4 species, rho 0.05, Rc 4.6, 16 + 8x4 bins, MLP D-64-32-1"
+    elif idx == 3:
+        n = max(64, int(round(32768 * scale)) // 4 * 4)
+        sys = bulk_system(rng, n, 0.09, 1.2, [n // 4] * 4)
+        p = mbp_params(4, 5.0, 32, 8, 8)
+        model = random_model(4, p.dim, [128, 128], seed, in_scale=IN_SCALE[3])
+        name = f"periodic bulk {n} atoms, 4 species, rho 0.09, Rc 5.0, 32 + 8x8 bins, MLP D-128-128-1"
+    elif idx == 4:
+        n = max(64, int(round(262144 * scale)) // 2 * 2)
+        sys = bulk_system(rng, n, 0.09, 1.2, [n // 2] * 2)
+        p = mbp_params(2, 6.0, 48, 8, 8)
+        model = random_model(2, p.dim, [128, 128], seed, in_scale=IN_SCALE[4])
+        name = f"periodic bulk {n} atoms, 2 species, rho 0.09, Rc 6.0, 48 + 8x8 bins, MLP D-128-128-1"
+    else:
+        raise ValueError(idx)
+    extra = {}
+    if idx == 4:
+        extra = {"skin": 0.5, "steps": 100, "step_sigma": 0.02}
+    return Workload(name, sys, p, model, seed, extra)
+
+
+def md_displacements(seed: int, n_atoms: int, steps: int, sigma: float):
+    """Generator of per-step Gaussian displacements (cumulative random walk)."""
+    rng = np.random.Generator(np.random.PCG64([seed, 7]))
+    for _ in range(steps):
+        yield rng.normal(0.0, sigma, size=(n_atoms, 3))
+
+
+def energy_targets(seed: int, n_structs: int) -> np.ndarray:
+    """Seeded targets T_c ~ N(0, 1) for the energy loss."""
+    return np.random.Generator(np.random.PCG64([seed, 11])).normal(size=n_structs)
+
+
+def single(pos, species, cell=None, pbc=(0, 0, 0)) -> System:
+    """One structure from explicit arrays (tests and small examples)."""
+    pos = np.asarray(pos, np.float64).reshape(-1, 3)
+    if cell is None:
+        span = np.ptp(pos, axis=0) if pos.shape[0] else np.zeros(3)
+        cell = np.diag(np.maximum(span, 1.0) + 1.0)
+    return System(pos, np.asarray(species, np.int32), np.asarray([0, pos.shape[0]], np.int64),
+                  np.asarray(cell, np.float64).reshape(1, 3, 3), np.asarray(pbc, np.uint8).reshape(1, 3))
+
+
+def concat(systems: Sequence[System]) -> System:
+    ptr = [0]
+    for s in systems:
+        ptr += list(ptr[-1] + np.diff(s.atom_ptr))
+    return System(np.concatenate([s.pos for s in systems]), np.concatenate([s.species for s in systems]),
+                  np.asarray(ptr, np.int64), np.concatenate([s.cell for s in systems]),
+                  np.concatenate([s.pbc for s in systems]))

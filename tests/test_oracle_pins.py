@@ -1,0 +1,438 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself.
+
+Each test checks the oracle against something the paper or the mathematics
+fixes: the descriptor sizes the paper prints, closed forms for two and three
+atoms (written with the textbook cosine cutoff and the published ANI angular
+term, not the oracle's formulas), invariances, additivity, force identities,
+central finite differences, an independent numpy neighbor enumeration, and
+a textbook dense network in torch float64.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2305_11805_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def small_params(S=2, rc=4.0, n_rad=6, n_theta=4, n_rs=3, eps=1e-3, zeta=6.0):
+    return synth.mbp_params(S, rc, n_rad, n_theta, n_rs, eta_rad=4.0, eta_ang=3.0, zeta=zeta, eps=eps)
+
+
+def fc_textbook(r, rc):
+    return np.where(r < rc, 0.5 * (1.0 + np.cos(np.pi * r / rc)), 0.0)
+
+
+def random_cluster(rng, n, box=5.0, d_min=0.9, S=2):
+    pos = synth.rsa_cluster(rng, n, box, d_min)
+    return synth.single(pos, rng.integers(0, S, n), cell=np.eye(3) * box)
+
+
+def small_periodic(rng, n=10, S=2, tric=True, L=4.5):
+    cell = np.array([[L, 0, 0], [0.6, L * 0.95, 0], [-0.4, 0.7, L * 1.05]]) if tric else np.eye(3) * L
+    frac = rng.uniform(0, 1, (n, 3))
+    return synth.single(frac @ cell, rng.integers(0, S, n), cell=cell, pbc=(1, 1, 1))
+
+
+# ----------------------------------------------------------------------------
+# descriptor layout: the sizes printed in the paper
+# ----------------------------------------------------------------------------
+
+def test_descriptor_dim_matches_paper(O):
+    with open(os.path.join(GOLDEN, "descriptor_sizes.json")) as f:
+        cases = json.load(f)["cases"]
+    for c in cases:
+        assert O.descriptor_dim(c["n_species"], c["n_rad"], c["n_theta"], c["n_rs_ang"]) == c["dim"], c["cite"]
+
+
+# ----------------------------------------------------------------------------
+# neighbor sets
+# ----------------------------------------------------------------------------
+
+def numpy_neighbors(sys, cutoff, K=4):
+    """Independent enumeration: every atom pair of a structure, images |n| <= K."""
+    out = set()
+    for c in range(sys.n_structs):
+        a0, a1 = sys.atom_ptr[c], sys.atom_ptr[c + 1]
+        H = sys.cell[c]
+        rng_ = [range(-K, K + 1) if sys.pbc[c, d] else range(0, 1) for d in range(3)]
+        imgs = np.array(list(itertools.product(*rng_)), dtype=np.float64)
+        for i in range(a0, a1):
+            for j in range(a0, a1):
+                d = sys.pos[j] - sys.pos[i] + imgs @ H
+                r2 = np.sum(d * d, axis=1)
+                for k in np.nonzero(r2 < cutoff * cutoff)[0]:
+                    n = tuple(int(v) for v in imgs[k])
+                    if i == j and n == (0, 0, 0):
+                        continue
+                    out.add((i, j) + n)
+    return out
+
+
+def list_as_set(nl, rows=None):
+    s = set()
+    off = nl["offsets"]
+    for r in range(len(off) - 1):
+        i = r if rows is None else rows[r]
+        for e in range(off[r], off[r + 1]):
+            s.add((int(i), int(nl["nbr"][e])) + tuple(int(v) for v in nl["shift"][e]))
+    return s
+
+
+def test_neighbors_vs_numpy_enumeration(O):
+    rng = np.random.Generator(np.random.PCG64(1))
+    systems = [small_periodic(rng, 8, tric=True, L=3.2),   # cell narrower than 2 rc: many images
+               small_periodic(rng, 12, tric=False, L=6.0),
+               random_cluster(rng, 15)]
+    for sys in systems:
+        ref = numpy_neighbors(sys, 3.5)
+        assert list_as_set(O.neighbors_brute(sys, 3.5)) == ref
+        assert list_as_set(O.neighbors_cells(sys, 3.5)) == ref
+
+
+def test_neighbors_cells_equal_brute_and_sorted(O):
+    rng = np.random.Generator(np.random.PCG64(2))
+    w = synth.config(1, scale=0.15)
+    sys = w.system
+    # unwrap positions: shift random atoms by whole lattice vectors + put some
+    # outside the box, the list must not change apart from the image shifts
+    s2 = synth.System(sys.pos.copy(), sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+    k = rng.integers(-2, 3, size=(sys.n_atoms, 3))
+    s2.pos = s2.pos + k @ sys.cell[0]
+    for s in (sys, s2):
+        a = O.neighbors_brute(s, 5.0)
+        b = O.neighbors_cells(s, 5.0)
+        for key in ("offsets", "nbr", "shift"):
+            assert np.array_equal(a[key], b[key])
+        # rows sorted by (j, n)
+        off = a["offsets"]
+        for r in range(0, len(off) - 1, 37):
+            keys = [(a["nbr"][e],) + tuple(a["shift"][e]) for e in range(off[r], off[r + 1])]
+            assert keys == sorted(keys)
+    # image shifts of the unwrapped copy compensate the lattice shifts exactly
+    a, b = O.neighbors_brute(sys, 5.0), O.neighbors_brute(s2, 5.0)
+    for r in range(sys.n_atoms):
+        e0, e1 = a["offsets"][r], a["offsets"][r + 1]
+        j = a["nbr"][e0:e1]
+        assert np.array_equal(j, b["nbr"][e0:e1])
+        assert np.array_equal(b["shift"][e0:e1], a["shift"][e0:e1] + k[r] - k[j])
+
+
+def test_neighbors_image_bound_not_binding(O):
+    rng = np.random.Generator(np.random.PCG64(3))
+    sys = small_periodic(rng, 9, tric=True, L=3.0)
+    a = O.neighbors_brute(sys, 4.0)
+    b = O.neighbors_brute(sys, 4.0, extra_images=2)
+    for key in ("offsets", "nbr", "shift"):
+        assert np.array_equal(a[key], b[key])
+
+
+def test_neighbors_symmetric_and_subset_rows(O):
+    rng = np.random.Generator(np.random.PCG64(4))
+    sys = synth.concat([small_periodic(rng, 10), random_cluster(rng, 12)])
+    nl = O.neighbors_brute(sys, 3.7)
+    s = list_as_set(nl)
+    for (i, j, a, b, c) in s:
+        assert (j, i, -a, -b, -c) in s
+    rows = np.array([3, 0, 15, 7])
+    sub = O.neighbors_cells(sys, 3.7, rows=rows)
+    assert list_as_set(sub, rows) == {t for t in s if t[0] in set(rows.tolist())}
+
+
+# ----------------------------------------------------------------------------
+# closed forms for two and three atoms
+# ----------------------------------------------------------------------------
+
+def test_radial_two_atoms_closed_form(O):
+    p = small_params(S=3)
+    r = 2.3
+    sys = synth.single([[0, 0, 0], [r, 0, 0]], [0, 2])
+    nl = O.neighbors_brute(sys, p.rc)
+    G = O.descriptors(p, sys, nl)
+    expect_i = np.zeros(p.dim)
+    expect_i[2 * p.n_rad:3 * p.n_rad] = np.exp(-p.eta_rad * (r - p.rs_rad) ** 2) * fc_textbook(r, p.rc)
+    expect_j = np.zeros(p.dim)
+    expect_j[0:p.n_rad] = expect_i[2 * p.n_rad:3 * p.n_rad]
+    np.testing.assert_allclose(G[0], expect_i, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(G[1], expect_j, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("theta", [np.pi / 2, 2 * np.pi / 3, 0.7])
+def test_angular_three_atoms_ani_form(O, theta):
+    """eps = 0: the angular term is the published ANI function
+    2^(1-zeta) (1 + cos(theta - theta_s))^zeta exp(-eta (r_avg - Rs)^2) fc fc."""
+    p = small_params(S=3, eps=0.0)
+    r1, r2 = 1.7, 2.6
+    pos = [[0, 0, 0], [r1, 0, 0], [r2 * np.cos(theta), r2 * np.sin(theta), 0]]
+    sys = synth.single(pos, [1, 2, 1])           # neighbor species 2 and 1 -> pair block (1, 2)
+    nl = O.neighbors_brute(sys, p.rc)
+    G = O.descriptors(p, sys, nl)[0]
+    S, nb = 3, p.n_theta * p.n_rs_ang
+    blocks = [(a, b) for a in range(S) for b in range(a, S)]
+    off = p.n_rad * S + blocks.index((1, 2)) * nb
+    expect = np.zeros(p.dim)
+    expect[2 * p.n_rad:3 * p.n_rad] = np.exp(-p.eta_rad * (r1 - p.rs_rad) ** 2) * fc_textbook(r1, p.rc)
+    expect[1 * p.n_rad:2 * p.n_rad] = np.exp(-p.eta_rad * (r2 - p.rs_rad) ** 2) * fc_textbook(r2, p.rc)
+    ang = 2.0 ** (1 - p.zeta) * (1 + np.cos(theta - p.theta_s)) ** p.zeta
+    rad = np.exp(-p.eta_ang * ((r1 + r2) / 2 - p.rs_ang) ** 2)
+    expect[off:off + nb] = (rad[:, None] * ang[None, :]).ravel() * fc_textbook(r1, p.rc) * fc_textbook(r2, p.rc)
+    np.testing.assert_allclose(G, expect, rtol=1e-12, atol=1e-15)
+
+
+def test_angular_right_angle_with_eps(O):
+    """theta = pi/2 and eps > 0: cos = 0, sin^2 = 1, so
+    x_p = (1 + sqrt(1 + eps) sin(ts_p)) / (1 + sqrt(1 + eps))."""
+    p = small_params(S=1, eps=0.05)
+    r = 2.0
+    sys = synth.single([[0, 0, 0], [r, 0, 0], [0, 0, r]], [0, 0, 0])
+    G = O.descriptors(p, sys, O.neighbors_brute(sys, p.rc))[0]
+    e = p.eps
+    x = (1 + np.sqrt(1 + e) * np.sin(p.theta_s)) / (1 + np.sqrt(1 + e))
+    rad = np.exp(-p.eta_ang * (r - p.rs_ang) ** 2)
+    ang = (rad[:, None] * (2 * x ** p.zeta)[None, :]).ravel() * fc_textbook(r, p.rc) ** 2
+    np.testing.assert_allclose(G[p.n_rad:], ang, rtol=1e-12)
+
+
+def test_cutoff_smooth_vanishing(O):
+    p = small_params(S=1)
+    rc = p.rc
+    vals, avals = [], []
+    for delta in [1e-2, 1e-3, 1e-4]:
+        sys = synth.single([[0, 0, 0], [rc - delta, 0, 0], [0, rc - delta, 0]], [0, 0, 0])
+        G = O.descriptors(p, sys, O.neighbors_brute(sys, rc))[0]
+        vals.append(np.max(np.abs(G[:p.n_rad])) / delta ** 2)
+        avals.append(np.max(np.abs(G[p.n_rad:])) / delta ** 4)
+    # radial part vanishes quadratically (fc ~ delta^2), angular part as
+    # fc(r_j) fc(r_k) ~ delta^4: the ratios stay bounded and converge
+    assert vals[-1] < 10.0 and abs(vals[-1] - vals[-2]) < 0.01 * vals[-2]
+    assert avals[-1] > 0.0 and abs(avals[-1] - avals[-2]) < 0.01 * avals[-2]
+    # just outside: nothing
+    sys = synth.single([[0, 0, 0], [rc + 1e-9, 0, 0]], [0, 0])
+    assert np.all(O.descriptors(p, sys, O.neighbors_brute(sys, rc)) == 0.0)
+
+
+def test_descriptors_nonnegative(O):
+    w = synth.config(0)
+    G = O.descriptors(w.params, w.system, O.neighbors_brute(w.system, w.params.rc))
+    assert np.all(G >= 0.0)
+
+
+# ----------------------------------------------------------------------------
+# invariances (Sec. I) and locality / additivity
+# ----------------------------------------------------------------------------
+
+def random_rotation(rng):
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    return q * np.sign(np.linalg.det(q))
+
+
+def test_invariances(O):
+    rng = np.random.Generator(np.random.PCG64(5))
+    p = small_params(S=2, rc=3.6)
+    for sys in (random_cluster(rng, 14), small_periodic(rng, 11, tric=True, L=4.0)):
+        G0 = O.descriptors(p, sys, O.neighbors_brute(sys, p.rc))
+        scale = np.max(np.abs(G0))
+        # translation
+        t = synth.System(sys.pos + np.array([3.1, -7.2, 0.4]), sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+        np.testing.assert_allclose(O.descriptors(p, t, O.neighbors_brute(t, p.rc)), G0, rtol=1e-12, atol=1e-12 * scale)
+        # rotation of positions and cell
+        R = random_rotation(rng)
+        rsys = synth.System(sys.pos @ R.T, sys.species, sys.atom_ptr, sys.cell @ R.T, sys.pbc)
+        np.testing.assert_allclose(O.descriptors(p, rsys, O.neighbors_brute(rsys, p.rc)), G0, rtol=1e-12,
+                                   atol=1e-12 * scale)
+        # permutation of atoms
+        perm = rng.permutation(sys.n_atoms)
+        psys = synth.System(sys.pos[perm], sys.species[perm], sys.atom_ptr, sys.cell, sys.pbc)
+        np.testing.assert_allclose(O.descriptors(p, psys, O.neighbors_brute(psys, p.rc)), G0[perm], rtol=1e-12,
+                                   atol=1e-12 * scale)
+
+
+def small_model(p, seed=7, hidden=(8, 5)):
+    return synth.random_model(p.n_species, p.dim, list(hidden), seed, in_scale=1.0)
+
+
+def test_additivity_separated_clusters(O):
+    rng = np.random.Generator(np.random.PCG64(6))
+    p = small_params(S=2)
+    m = small_model(p)
+    A, B = random_cluster(rng, 9), random_cluster(rng, 7)
+    joint_pos = np.concatenate([A.pos, B.pos + np.array([20.0, 0, 0])])
+    joint = synth.single(joint_pos, np.concatenate([A.species, B.species]), cell=np.eye(3) * 30)
+    EA = O.energy_forces(p, m, A, O.neighbors_brute(A, p.rc))[0]
+    EB = O.energy_forces(p, m, B, O.neighbors_brute(B, p.rc))[0]
+    EJ = O.energy_forces(p, m, joint, O.neighbors_brute(joint, p.rc))[0]
+    batch = synth.concat([A, B])
+    EBt = O.energy_forces(p, m, batch, O.neighbors_brute(batch, p.rc))[0]
+    np.testing.assert_allclose(EJ[0], EA[0] + EB[0], rtol=1e-13)
+    np.testing.assert_allclose(EBt, [EA[0], EB[0]], rtol=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# forces
+# ----------------------------------------------------------------------------
+
+def total_energy(O, p, m, sys):
+    return O.energy_forces(p, m, sys, O.neighbors_brute(sys, p.rc))[0].sum()
+
+
+@pytest.mark.parametrize("kind", ["cluster", "periodic"])
+def test_forces_match_central_differences(O, kind):
+    rng = np.random.Generator(np.random.PCG64(8))
+    p = small_params(S=2, rc=3.8)
+    m = small_model(p, hidden=(10, 6))
+    sys = random_cluster(rng, 10) if kind == "cluster" else small_periodic(rng, 9, tric=True, L=4.2)
+    _, _, F = O.energy_forces(p, m, sys, O.neighbors_brute(sys, p.rc))
+    h = 1e-5
+    for k in range(sys.n_atoms):
+        for a in range(3):
+            pp = sys.pos.copy(); pp[k, a] += h
+            pm = sys.pos.copy(); pm[k, a] -= h
+            sp = synth.System(pp, sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+            sm = synth.System(pm, sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+            fd = -(total_energy(O, p, m, sp) - total_energy(O, p, m, sm)) / (2 * h)
+            assert abs(fd - F[k, a]) < 1e-6 * max(1.0, abs(F[k, a])), (k, a, fd, F[k, a])
+
+
+def test_force_sum_and_torque_vanish(O):
+    rng = np.random.Generator(np.random.PCG64(9))
+    p = small_params(S=2, rc=3.8)
+    m = small_model(p)
+    cl = random_cluster(rng, 13)
+    _, _, F = O.energy_forces(p, m, cl, O.neighbors_brute(cl, p.rc))
+    scale = np.abs(F).max()
+    assert np.abs(F.sum(0)).max() < 1e-12 * scale * cl.n_atoms
+    assert np.abs(np.cross(cl.pos, F).sum(0)).max() < 1e-11 * scale * cl.n_atoms
+    per = small_periodic(rng, 10, tric=True, L=4.0)
+    _, _, F = O.energy_forces(p, m, per, O.neighbors_brute(per, p.rc))
+    assert np.abs(F.sum(0)).max() < 1e-12 * np.abs(F).max() * per.n_atoms
+
+
+def test_subset_forces_equal_full(O):
+    w = synth.config(1, scale=0.05)
+    sys, p, m = w.system, w.params, w.model
+    full = O.neighbors_cells(sys, p.rc)
+    _, Ea, F = O.energy_forces(p, m, sys, full)
+    targets = np.array([0, 17, 100, sys.n_atoms - 1])
+    rows = set(targets.tolist())
+    for t in targets:
+        rows.update(full["nbr"][full["offsets"][t]:full["offsets"][t + 1]].tolist())
+    rows = np.array(sorted(rows))
+    sub = O.neighbors_cells(sys, p.rc, rows=rows)
+    E_rows, F_t = O.forces(p, m, sys, sub, targets)
+    np.testing.assert_allclose(F_t, F[targets], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(E_rows, Ea[rows], rtol=1e-13)
+
+
+def test_descriptor_jacobian_central_differences(O):
+    rng = np.random.Generator(np.random.PCG64(10))
+    p = small_params(S=2, rc=3.8)
+    sys = random_cluster(rng, 7)
+    nl = O.neighbors_brute(sys, p.rc)
+    G, dG = O.descriptors(p, sys, nl, jacobian=True)
+    h = 1e-6
+    for r in range(sys.n_atoms):
+        for e in range(nl["offsets"][r], nl["offsets"][r + 1]):
+            j = nl["nbr"][e]
+            for a in range(3):
+                # moving x_j alone changes d_e only (clusters: one image per pair)
+                pp = sys.pos.copy(); pp[j, a] += h
+                pm = sys.pos.copy(); pm[j, a] -= h
+                Gp = O.descriptors(p, synth.System(pp, sys.species, sys.atom_ptr, sys.cell, sys.pbc), nl)
+                Gm = O.descriptors(p, synth.System(pm, sys.species, sys.atom_ptr, sys.cell, sys.pbc), nl)
+                fd = (Gp[r] - Gm[r]) / (2 * h)
+                np.testing.assert_allclose(dG[e, :, a], fd, rtol=1e-6, atol=1e-8 * max(1.0, np.abs(G[r]).max()))
+
+
+# ----------------------------------------------------------------------------
+# MLP, Eq. (1), against a textbook dense network (torch float64)
+# ----------------------------------------------------------------------------
+
+def torch_mlp_energy(torch, layers, acts, g):
+    a = g
+    for (W, b), act in zip(layers, acts):
+        z = a @ W.T + b
+        if act == "gaussian":
+            a = torch.exp(-z * z)
+        elif act == "relu":
+            a = torch.relu(z)
+        elif act == "tanh":
+            a = torch.tanh(z)
+        else:
+            a = z
+    return a[:, 0]
+
+
+@pytest.mark.parametrize("act", ["gaussian", "relu", "tanh"])
+def test_mlp_forward_backward_vs_torch(O, act):
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(11))
+    D, S, n = 20, 3, 40
+    model = synth.random_model(S, D, [16, 9], 123, act=act)
+    G = rng.uniform(0, 2, (n, D))
+    sp = rng.integers(0, S, n).astype(np.int32)
+    E, lam = O.mlp(model, sp, G)
+    for s in range(S):
+        idx = sp == s
+        g = torch.tensor(G[idx], dtype=torch.float64, requires_grad=True)
+        layers = [(torch.tensor(W), torch.tensor(b)) for W, b in zip(model[s][2], model[s][3])]
+        e = torch_mlp_energy(torch, layers, model[s][1], g)
+        e.sum().backward()
+        np.testing.assert_allclose(E[idx], e.detach().numpy(), rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(lam[idx], g.grad.numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_energy_loss_weight_gradient_vs_torch(O):
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(12))
+    p = small_params(S=2, rc=3.8)
+    model = small_model(p, hidden=(7, 4))
+    sys = synth.concat([random_cluster(rng, n) for n in (5, 8, 6)])
+    nl = O.neighbors_brute(sys, p.rc)
+    T = np.array([0.3, -1.0, 0.5])
+    L, Es, flat = O.energy_loss_grad(p, model, sys, nl, T)
+    G = O.descriptors(p, sys, nl)
+    tparams = [[(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True))
+                for W, b in zip(m[2], m[3])] for m in model]
+    E_atoms = torch.zeros(sys.n_atoms, dtype=torch.float64)
+    for s in range(2):
+        idx = np.nonzero(sys.species == s)[0]
+        e = torch_mlp_energy(torch, tparams[s], model[s][1], torch.tensor(G[idx]))
+        E_atoms = E_atoms.index_put((torch.tensor(idx),), e)
+    Ec = torch.stack([E_atoms[sys.atom_ptr[c]:sys.atom_ptr[c + 1]].sum() for c in range(3)])
+    Lt = ((Ec - torch.tensor(T)) ** 2).mean()
+    Lt.backward()
+    assert abs(L - Lt.item()) < 1e-13 * max(1, abs(L))
+    np.testing.assert_allclose(Es, Ec.detach().numpy(), rtol=1e-13)
+    grads = O.unflatten_grads(model, flat)
+    for s in range(2):
+        for (dW, db), (W, b) in zip(grads[s], tparams[s]):
+            np.testing.assert_allclose(dW, W.grad.numpy(), rtol=1e-11, atol=1e-14)
+            np.testing.assert_allclose(db, b.grad.numpy(), rtol=1e-11, atol=1e-14)
+
+
+def test_energy_loss_weight_gradient_fd(O):
+    rng = np.random.Generator(np.random.PCG64(13))
+    p = small_params(S=2, rc=3.8)
+    model = small_model(p, hidden=(6, 4))
+    sys = synth.concat([random_cluster(rng, n) for n in (6, 5)])
+    nl = O.neighbors_brute(sys, p.rc)
+    T = np.array([0.2, -0.4])
+    L, _, flat = O.energy_loss_grad(p, model, sys, nl, T)
+    h = 1e-6
+    for (s, l, idx) in [(0, 0, (1, 3)), (1, 1, (2, 0)), (1, 2, (0, 1))]:
+        def loss_with(delta):
+            mm = [(m[0], m[1], [w.copy() for w in m[2]], [b.copy() for b in m[3]]) for m in model]
+            mm[s][2][l][idx] += delta
+            return O.energy_loss_grad(p, mm, sys, nl, T)[0]
+        fd = (loss_with(h) - loss_with(-h)) / (2 * h)
+        g = O.unflatten_grads(model, flat)[s][l][0][idx]
+        assert abs(fd - g) < 1e-6 * max(1.0, abs(g))
