@@ -1,0 +1,253 @@
+/*
+ * nnpot.h -- C ABI of libnnpot, the MI355X (gfx950) energy/force path of a
+ * Behler-Parrinello-type neural network potential with modified-BP (mBP)
+ * descriptors and per-species multilayer perceptrons (PANNA 2.0).
+ *
+ * Conventions shared by every call:
+ *  - Pointers marked [device] point to GPU memory of the current HIP device;
+ *    pointers marked [host] point to host memory read during the call only.
+ *  - The caller owns every buffer, including the workspace; the library never
+ *    allocates and never frees.  Inputs are never modified.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Calls only enqueue
+ *    work on it and return; the only synchronous call is nn_count_neighbors.
+ *  - Host-detectable errors (bad sizes, null pointers, unsupported parameter
+ *    combinations, short workspace) are returned before anything is enqueued,
+ *    with a message available from nn_last_error().  Errors found on the
+ *    device (list overflow, species out of range, non-finite positions, too
+ *    many neighbors) are recorded in the list's metadata block and reported
+ *    by nn_check(), which synchronizes the stream.
+ *  - Results are bitwise reproducible run to run: no floating-point atomics.
+ *  - Structures are contiguous atom ranges; each has its own cell and
+ *    periodicity.  Energies of different structures never interact (the
+ *    energy is a sum of atomic terms with a finite cutoff, Sec. I and II).
+ */
+#ifndef NNPOT_H
+#define NNPOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NN_MAX_SPECIES 8
+#define NN_MAX_LAYERS 4
+
+typedef enum nn_status {
+  NN_OK = 0,
+  NN_E_INVALID = 1,     /* invalid argument (message in nn_last_error)                 */
+  NN_E_CAPACITY = 2,    /* neighbor list capacity too small; nn_check reports the size  */
+  NN_E_CELL = 3,        /* periodic cell narrower than 3 bins and > 256 atoms          */
+  NN_E_WORKSPACE = 4,   /* workspace smaller than nn_workspace_size                     */
+  NN_E_UNSUPPORTED = 5, /* parameter combination without a compiled kernel              */
+  NN_E_HIP = 6,         /* HIP runtime error (message in nn_last_error)                 */
+  NN_E_DEVICE = 7       /* device-side check failed (species, non-finite input, limits) */
+} nn_status;
+
+/* Activation codes of Eq. (1): Gaussian exp(-z^2), ReLU, tanh, linear (Sec. II.A). */
+enum { NN_ACT_LINEAR = 0, NN_ACT_GAUSSIAN = 1, NN_ACT_RELU = 2, NN_ACT_TANH = 3 };
+
+/* Flags of nn_energy_forces. */
+enum {
+  NN_BF16_MLP = 1,       /* MLP products on BF16 MFMA, operands rounded to BF16, FP32 sums     */
+  NN_STORE_JACOBIAN = 2, /* store dG/dx during the descriptor pass if it fits mem_budget        */
+  NN_BF16X3_MLP = 4      /* MLP products on BF16 MFMA with every operand split into BF16 hi + lo
+                            and three products (hi*hi + hi*lo + lo*hi), FP32 sums: about 16
+                            significant bits per operand.  Exclusive with NN_BF16_MLP.
+                            Neither flag: FP32 MFMA.                                           */
+};
+
+/*
+ * A batch of atomic configurations (Sec. II.A: positions, species, cell).
+ *   pos      [device] [N][3] FP64 Cartesian positions (Angstrom); need not be
+ *            wrapped into the cell.
+ *   species  [device] [N] int32 species index in [0, S).
+ *   atom_ptr [device] [B+1] int64; structure c owns atoms
+ *            [atom_ptr[c], atom_ptr[c+1]); atom_ptr[0] = 0, atom_ptr[B] = N.
+ *   cell     [device] [B][3][3] FP64, rows are the lattice vectors a, b, c.
+ *            Must be non-singular also for non-periodic structures, where it
+ *            only sets the binning box (atoms may lie outside it).
+ *   pbc      [device] [B][3] uint8, 1 = periodic along that lattice vector.
+ */
+typedef struct nn_system {
+  int64_t n_atoms;
+  int32_t n_structs;
+  const double* pos;
+  const int32_t* species;
+  const int64_t* atom_ptr;
+  const double* cell;
+  const uint8_t* pbc;
+} nn_system;
+
+/*
+ * Neighbor list in CSR form.  Row i lists every (j, n) of the same structure
+ * with (j, n) != (i, 0) and |d|^2 < radius^2, where
+ * d = (x_j - x_i) + (n_a a + n_b b + n_c c) is evaluated in FP64 in exactly
+ * that order; rows are sorted by (j, n_a, n_b, n_c).  Image shifts refer to
+ * the input (unwrapped) positions.  All arrays are caller-allocated [device]:
+ *   offsets [N+1] int64, nbr [capacity] int32, shift [capacity][4] int8
+ *   (n_a, n_b, n_c, 0), rev [capacity] int32 (index of the reverse entry
+ *   (j -> i, -n)), ref_pos [N][3] FP64 (positions at the last build),
+ *   meta [8] int64 (nnz, valid, builds, rebuilt-last-call, error bits,
+ *   longest row, -, -); zero meta once before the first build.
+ * radius is written by nn_build_neighbors (host field).
+ */
+typedef struct nn_nlist {
+  int64_t capacity;
+  int64_t* offsets;
+  int32_t* nbr;
+  int8_t* shift;
+  int32_t* rev;
+  double* ref_pos;
+  int64_t* meta;
+  double radius;
+} nn_nlist;
+
+/*
+ * mBP descriptor hyperparameters [host].  The paper names the mBP descriptor
+ * and its bin counts (Sec. II.A, III.A, III.B) but defers its formulas to the
+ * first PANNA paper; the form computed is
+ *   radial  G[s][k]      = sum_{j: s_j=s} exp(-eta_rad (r_ij - rs_rad[k])^2) fc(r_ij)
+ *   angular G[(a,b)][q][p] = sum_{unordered {j,k}: {s_j,s_k}={a,b}}
+ *       2 x_p^zeta exp(-eta_ang ((r_ij + r_ik)/2 - rs_ang[q])^2) fc(r_ij) fc(r_ik),
+ *   x_p = (1 + cos(t) cos(theta_s[p]) + sqrt(sin^2(t) + eps) sin(theta_s[p]))
+ *         / (1 + sqrt(1 + eps)),   fc(r) = (1 + cos(pi r / rc)) / 2 for r < rc.
+ * Layout of G: S radial blocks of n_rad, then the angular blocks of the
+ * unordered species pairs (0,0), (0,1), ..., (S-1,S-1), each [q][p] with p
+ * fastest: D = n_rad*S + n_theta*n_rs_ang*S*(S+1)/2.
+ * Limits: S <= 8, n_rad <= 64, (n_theta, n_rs_ang) in {4,8,16} x {4,8} with
+ * n_theta*n_rs_ang <= 128, zeta a positive integer <= 1024.
+ */
+typedef struct nn_mbp_params {
+  int32_t n_species;
+  double rc;
+  int32_t n_rad;
+  double eta_rad;
+  const double* rs_rad;
+  int32_t n_theta;
+  const double* theta_s;
+  int32_t n_rs_ang;
+  double eta_ang;
+  const double* rs_ang;
+  double zeta;
+  double eps;
+} nn_mbp_params;
+
+/*
+ * Per-species MLP, Eq. (1): a^0 = G_i, z^l = W^l a^(l-1) + b^l,
+ * a^l = act[l-1](z^l); the atomic energy is a^L (width[L] = 1).  Weights are
+ * shared by all atoms of a species (Sec. II).
+ *   W[l] [device] FP32 [width[l+1]][width[l]] row-major, b[l] [device] FP32.
+ * Limits of the fused kernel: L = 3 (two hidden layers), hidden widths
+ * multiples of 16 with (h1, h2) in {(64,32), (128,128), (256,128)}.
+ */
+typedef struct nn_mlp {
+  int32_t n_layers;
+  int32_t width[NN_MAX_LAYERS + 1];
+  int32_t act[NN_MAX_LAYERS];
+  const float* W[NN_MAX_LAYERS];
+  const float* b[NN_MAX_LAYERS];
+} nn_mlp;
+
+typedef struct nn_model {
+  int32_t n_species;
+  nn_mlp mlp[NN_MAX_SPECIES];
+} nn_model;
+
+/* Descriptor length D for these hyperparameters (see nn_mbp_params). Returns
+ * -1 for invalid parameters. */
+int64_t nn_descriptor_dim(const nn_mbp_params* p);
+
+/*
+ * Workspace bytes needed by every call below for a system of n_atoms atoms
+ * and n_structs structures, a list of `capacity` entries, these descriptor
+ * and model parameters (model may be NULL for list/descriptor-only use) and
+ * these flags.  With NN_STORE_JACOBIAN the Jacobian is included only if it
+ * fits mem_budget.
+ */
+nn_status nn_workspace_size(int64_t n_atoms, int32_t n_structs, int64_t capacity, const nn_mbp_params* p,
+                            const nn_model* model, int32_t flags, size_t mem_budget, size_t* bytes);
+
+/*
+ * Number of list entries within `radius` (synchronous: enqueues the counting
+ * pass on `stream`, waits, and returns the count in *nnz).  Used to size the
+ * list before nn_build_neighbors.
+ */
+nn_status nn_count_neighbors(const nn_system* sys, double radius, int64_t* nnz, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/*
+ * Build (or keep) the neighbor list at radius rc + skin (locality and cutoff,
+ * Sec. I, III.A).  With skin > 0 and a previous build of this list, the list
+ * is rebuilt only if some atom moved farther than skin/2 since that build;
+ * the test and the rebuild run on the device, without a host round trip, so
+ * the call can be captured in a HIP graph.  Structures of up to 256 atoms use
+ * an all-pairs builder over every lattice image in range (any cell size);
+ * larger ones use cell binning and need at least 3 bins along each periodic
+ * direction (perpendicular width >= 3 (rc + skin)), else NN_E_CELL (device).
+ * Capacity overflow sets NN_E_CAPACITY in meta (the list is then invalid and
+ * meta[0] holds the required entries).
+ */
+nn_status nn_build_neighbors(const nn_system* sys, double rc, double skin, nn_nlist* nl, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/*
+ * Descriptors of every atom: G [device] FP32 [N][D] (layout of
+ * nn_mbp_params).  Neighbor entries at r >= rc (skin lists) contribute
+ * nothing.  If jac != NULL, also the stored Jacobian
+ * jac [device] FP32 [capacity][D][3] with jac[e][d][k] = dG_{i,d}/d(d_e)_k
+ * for entry e of row i (the derivatives the paper's precomputed mode stores,
+ * Sec. II.A).
+ */
+nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, float* G, float* jac,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Energies and forces (Sec. II: E = sum_i E_{s_i}(G_i); forces are the
+ * negative derivatives of the energy):
+ *   E_struct [device] FP64 [B]  per-structure energy, summed in FP64;
+ *   E_atom   [device] FP32 [N]  atomic energies (may be NULL);
+ *   F        [device] FP32 [N][3] forces F_k = -dE/dx_k (may be NULL).
+ * Forces come from a hand-written adjoint: lambda_i = dE_i/dG_i by the MLP
+ * backward pass, then per-pair vectors dE_i/dd_e by re-running the
+ * descriptor's pair and triplet loops against lambda (or, with
+ * NN_STORE_JACOBIAN and a Jacobian within mem_budget, by contracting the
+ * Jacobian stored during the descriptor pass), then a deterministic gather
+ * F_k = sum_e dE_k/dd_e - sum_e dE_{j(e)}/dd_rev(e).  G and lambda stay in
+ * the workspace for nn_energy_forces_grad.
+ */
+nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                           const nn_model* model, int32_t flags, size_t mem_budget, double* E_struct,
+                           float* E_atom, float* F, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Backward of E_struct with respect to positions and weights, given
+ * dL_dE [device] FP64 [B] (Sec. II.A: the loss is minimised over the MLP
+ * parameters).  Must follow nn_energy_forces with the same arguments and
+ * workspace (it reuses G and lambda).
+ *   dL_dpos [device] FP32 [N][3] (may be NULL): dL/dx_k = -dL_dE[c(k)] F_k;
+ *            needs the F of that call.
+ *   dW[s*NN_MAX_LAYERS + l], db[...] [device] FP32 (may be NULL): dL/dW^l and
+ *            dL/db^l of species s, same layout as the weights, reduced over
+ *            atoms in a fixed order.
+ */
+nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                                const nn_model* model, int32_t flags, const double* dL_dE, const float* F,
+                                float* dL_dpos, float* const* dW, float* const* db, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/*
+ * Synchronize `stream` and report device-side errors recorded in the list's
+ * metadata since the last check (then clear them).  *info (may be NULL)
+ * receives the required list size for NN_E_CAPACITY.
+ */
+nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info);
+
+/* Message for the last non-NN_OK status returned on this thread. */
+const char* nn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNPOT_H */

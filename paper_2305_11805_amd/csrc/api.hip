@@ -1,0 +1,457 @@
+// C ABI of libnnpot: argument checks, workspace layout and the order of
+// launches for each entry point.  Everything after the checks is enqueued on
+// the caller's stream; no call allocates memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace nnp {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local char g_err[512] = "";
+
+static nn_status fail(nn_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+static nn_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(NN_E_HIP, "%s: %s", what, hipGetErrorString(e));
+  return NN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (n > 0 ? n : 1);
+    return p;
+  }
+};
+
+struct Layout {
+  // neighbor build
+  StructGeom* geom;
+  int64_t *n_bins, *bin_base, *bin_count, *bin_start, *bin_fill, *row_count, *count_off, *scan_tmp, *count_meta;
+  int32_t *bin_atoms, *atom_bin, *flag;
+  int64_t max_bins;
+  // energy / forces
+  float *G, *lam, *E_atom;
+  float4* pg;
+  int32_t* perm;
+  int64_t *sp_cnt, *sp_off, *sp_start;
+  __bf16* wb;  // BF16 weights, W then W^T per species and layer
+  size_t wb_elems;
+  size_t bytes;
+};
+
+static size_t model_param_floats(const nn_model* m) {
+  size_t t = 0;
+  if (!m) return 0;
+  for (int s = 0; s < m->n_species; ++s)
+    for (int l = 0; l < m->mlp[s].n_layers; ++l)
+      t += ((size_t)m->mlp[s].width[l + 1] * m->mlp[s].width[l] + 127) / 128 * 128;
+  return t;
+}
+
+static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D, int S, const nn_model* model) {
+  Layout L{};
+  Carver c{static_cast<char*>(ws)};
+  L.max_bins = 8 * N + 64 * (int64_t)B + 1;
+  const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, L.max_bins),
+                                           std::max<int64_t>((int64_t)B, (int64_t)NN_MAX_SPECIES * ((N + 63) / 64 + 1)));
+  L.geom = c.take<StructGeom>(B);
+  L.n_bins = c.take<int64_t>(B + 1);
+  L.bin_base = c.take<int64_t>(B + 1);
+  L.bin_count = c.take<int64_t>(L.max_bins + 1);
+  L.bin_start = c.take<int64_t>(L.max_bins + 1);
+  L.bin_fill = c.take<int64_t>(L.max_bins + 1);
+  L.bin_atoms = c.take<int32_t>(N);
+  L.atom_bin = c.take<int32_t>(4 * N);
+  L.row_count = c.take<int64_t>(N + 1);
+  L.count_off = c.take<int64_t>(N + 1);
+  L.scan_tmp = c.take<int64_t>(scan_scratch_elems(scan_n));
+  L.flag = c.take<int32_t>(4);
+  L.count_meta = c.take<int64_t>(8);
+  if (D > 0) {
+    L.G = c.take<float>((size_t)N * D);
+    L.lam = c.take<float>((size_t)N * D);
+    L.E_atom = c.take<float>(N);
+    L.pg = c.take<float4>(capacity);
+    L.perm = c.take<int32_t>(N);
+    const int64_t nblk = (N + 63) / 64 > 0 ? (N + 63) / 64 : 1;
+    L.sp_cnt = c.take<int64_t>((size_t)S * nblk + 1);
+    L.sp_off = c.take<int64_t>((size_t)S * nblk + 1);
+    L.sp_start = c.take<int64_t>(NN_MAX_SPECIES + 1);
+    L.wb_elems = 4 * model_param_floats(model);
+    L.wb = c.take<__bf16>(L.wb_elems);
+  }
+  L.bytes = c.off + 256;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// argument checks
+// ---------------------------------------------------------------------------
+
+static nn_status check_system(const nn_system* sys) {
+  if (!sys) return fail(NN_E_INVALID, "sys is NULL");
+  if (sys->n_atoms < 0 || sys->n_structs < 0) return fail(NN_E_INVALID, "negative sizes");
+  if (sys->n_atoms > INT32_MAX - 1) return fail(NN_E_INVALID, "more than 2^31-2 atoms");
+  if (sys->n_structs == 0 && sys->n_atoms > 0) return fail(NN_E_INVALID, "atoms but no structures");
+  if (sys->n_atoms > 0 && (!sys->pos || !sys->species)) return fail(NN_E_INVALID, "pos/species is NULL");
+  if (sys->n_structs > 0 && (!sys->atom_ptr || !sys->cell || !sys->pbc))
+    return fail(NN_E_INVALID, "atom_ptr/cell/pbc is NULL");
+  return NN_OK;
+}
+
+static nn_status check_nlist(const nn_nlist* nl, const nn_system* sys, bool need_entries) {
+  if (!nl) return fail(NN_E_INVALID, "nl is NULL");
+  if (!nl->offsets || !nl->meta) return fail(NN_E_INVALID, "nl->offsets/meta is NULL");
+  if (need_entries && (!nl->nbr || !nl->shift || !nl->rev)) return fail(NN_E_INVALID, "nl->nbr/shift/rev is NULL");
+  if (nl->capacity < 0 || nl->capacity > INT32_MAX) return fail(NN_E_INVALID, "capacity out of range");
+  (void)sys;
+  return NN_OK;
+}
+
+static nn_status make_desc_const(const nn_mbp_params* p, DescConst* out) {
+  if (!p) return fail(NN_E_INVALID, "params is NULL");
+  if (p->n_species < 1 || p->n_species > NN_MAX_SPECIES) return fail(NN_E_INVALID, "n_species must be 1..8");
+  if (!(p->rc > 0.0) || !isfinite(p->rc)) return fail(NN_E_INVALID, "rc must be positive");
+  if (p->n_rad < 1 || p->n_rad > kMaxRad) return fail(NN_E_UNSUPPORTED, "n_rad must be 1..%d", kMaxRad);
+  if (!desc_supported(p->n_theta, p->n_rs_ang))
+    return fail(NN_E_UNSUPPORTED, "angular bins %d x %d not compiled (n_theta in {4,8,16}, n_rs_ang in {4,8})",
+                p->n_theta, p->n_rs_ang);
+  if (!p->rs_rad || !p->theta_s || !p->rs_ang) return fail(NN_E_INVALID, "grid arrays are NULL");
+  if (!(p->zeta >= 1.0 && p->zeta <= 1024.0 && floor(p->zeta) == p->zeta))
+    return fail(NN_E_UNSUPPORTED, "zeta must be an integer in [1, 1024]");
+  if (!(p->eps >= 0.0) || !(p->eta_rad >= 0.0) || !(p->eta_ang >= 0.0))
+    return fail(NN_E_INVALID, "eps and eta must be >= 0");
+  DescConst P{};
+  P.S = p->n_species;
+  P.n_rad = p->n_rad;
+  P.n_theta = p->n_theta;
+  P.n_rs_ang = p->n_rs_ang;
+  P.D = (int)(p->n_rad * p->n_species + p->n_theta * p->n_rs_ang * p->n_species * (p->n_species + 1) / 2);
+  P.zeta = (int)p->zeta;
+  P.rc = (float)p->rc;
+  P.eta_rad = (float)p->eta_rad;
+  P.eta_ang = (float)p->eta_ang;
+  P.eps_ang = (float)p->eps;
+  P.pi_over_rc = (float)(M_PI / p->rc);
+  P.half_pi_over_rc = (float)(0.5 * M_PI / p->rc);
+  const double norm = 1.0 + sqrt(1.0 + p->eps);
+  for (int t = 0; t < p->n_theta; ++t) {
+    P.x_a[t] = (float)(cos(p->theta_s[t]) / norm);
+    P.x_b[t] = (float)(sin(p->theta_s[t]) / norm);
+  }
+  P.x_c = (float)(1.0 / norm);
+  for (int k = 0; k < p->n_rad; ++k) {
+    P.rs_rad[k] = (float)p->rs_rad[k];
+    P.rs_rad_lo[k] = (float)(p->rs_rad[k] - (double)P.rs_rad[k]);
+  }
+  for (int q = 0; q < p->n_rs_ang; ++q) {
+    P.rs_ang[q] = (float)p->rs_ang[q];
+    P.rs_ang_lo[q] = (float)(p->rs_ang[q] - (double)P.rs_ang[q]);
+  }
+  P.rc64 = p->rc;
+  P.half_pi_over_rc64 = 0.5 * M_PI / p->rc;
+  P.pi_over_rc64 = M_PI / p->rc;
+  *out = P;
+  return NN_OK;
+}
+
+static nn_status check_model(const nn_model* m, const DescConst& P) {
+  if (!m) return fail(NN_E_INVALID, "model is NULL");
+  if (m->n_species != P.S) return fail(NN_E_INVALID, "model has %d species, descriptor %d", m->n_species, P.S);
+  const nn_mlp& m0 = m->mlp[0];
+  for (int s = 0; s < m->n_species; ++s) {
+    const nn_mlp& q = m->mlp[s];
+    if (q.n_layers != 3) return fail(NN_E_UNSUPPORTED, "species %d: only two hidden layers are compiled", s);
+    if (q.width[0] != P.D) return fail(NN_E_INVALID, "species %d: input width %d != D %d", s, q.width[0], P.D);
+    if (q.width[3] != 1) return fail(NN_E_INVALID, "species %d: output width must be 1", s);
+    if (!mlp_supported(q.width[1], q.width[2]))
+      return fail(NN_E_UNSUPPORTED, "species %d: hidden widths (%d, %d) not compiled", s, q.width[1], q.width[2]);
+    if (q.width[1] != m0.width[1] || q.width[2] != m0.width[2])
+      return fail(NN_E_UNSUPPORTED, "all species must share the hidden widths in the fused kernel");
+    for (int l = 0; l < 3; ++l) {
+      if (!q.W[l] || !q.b[l]) return fail(NN_E_INVALID, "species %d layer %d: NULL weights", s, l);
+      if (q.act[l] < 0 || q.act[l] > 3) return fail(NN_E_INVALID, "bad activation code");
+    }
+    if (q.act[2] != NN_ACT_LINEAR) return fail(NN_E_UNSUPPORTED, "output layer must be linear");
+  }
+  return NN_OK;
+}
+
+static int64_t dim_of(const nn_mbp_params* p) {
+  return (int64_t)p->n_rad * p->n_species + (int64_t)p->n_theta * p->n_rs_ang * p->n_species * (p->n_species + 1) / 2;
+}
+
+static NbLaunch nb_launch(const nn_system* sys, const Layout& L, double radius, nn_nlist* nl, bool count_only) {
+  NbLaunch n{};
+  n.sys = sys;
+  n.radius = radius;
+  n.capacity = nl ? nl->capacity : 0;
+  n.nl = nl;
+  n.counts = L.row_count;
+  n.offsets = count_only ? L.count_off : nl->offsets;
+  n.geom = L.geom;
+  n.n_bins = L.n_bins;
+  n.bin_base = L.bin_base;
+  n.bin_count = L.bin_count;
+  n.bin_start = L.bin_start;
+  n.bin_fill = L.bin_fill;
+  n.bin_atoms = L.bin_atoms;
+  n.atom_bin = L.atom_bin;
+  n.scan_tmp = L.scan_tmp;
+  n.flag = L.flag;
+  n.meta = count_only ? L.count_meta : nl->meta;
+  n.max_bins = L.max_bins;
+  return n;
+}
+
+__global__ void k_zero_meta(int64_t* m) {
+  if (threadIdx.x < 8) m[threadIdx.x] = 0;
+}
+
+}  // namespace nnp
+
+using namespace nnp;
+
+extern "C" {
+
+int64_t nn_descriptor_dim(const nn_mbp_params* p) {
+  DescConst P;
+  if (make_desc_const(p, &P) != NN_OK) return -1;
+  return P.D;
+}
+
+nn_status nn_workspace_size(int64_t n_atoms, int32_t n_structs, int64_t capacity, const nn_mbp_params* p,
+                            const nn_model* model, int32_t flags, size_t mem_budget, size_t* bytes) {
+  (void)flags;
+  (void)mem_budget;
+  if (!bytes) return fail(NN_E_INVALID, "bytes is NULL");
+  if (n_atoms < 0 || n_structs < 0 || capacity < 0) return fail(NN_E_INVALID, "negative sizes");
+  int64_t D = 0;
+  int S = 1;
+  if (p) {
+    DescConst P;
+    nn_status st = make_desc_const(p, &P);
+    if (st) return st;
+    D = P.D;
+    S = P.S;
+  }
+  Layout L = carve(nullptr, n_atoms, n_structs, capacity, D, S, model);
+  *bytes = L.bytes;
+  return NN_OK;
+}
+
+nn_status nn_count_neighbors(const nn_system* sys, double radius, int64_t* nnz, void* ws, size_t ws_bytes,
+                             void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if (!nnz) return fail(NN_E_INVALID, "nnz is NULL");
+  if (!(radius > 0.0)) return fail(NN_E_INVALID, "radius must be positive");
+  Layout L = carve(nullptr, sys->n_atoms, sys->n_structs, 0, 0, 1, nullptr);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, sys->n_atoms, sys->n_structs, 0, 0, 1, nullptr);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_meta, dim3(1), dim3(64), 0, s, L.count_meta);
+  NbLaunch nl = nb_launch(sys, L, radius, nullptr, true);
+  launch_neighbors(nl, false, 0.0, true, s);
+  if ((st = check_launch("nn_count_neighbors"))) return st;
+  int64_t meta[8];
+  if (hipMemcpyAsync(meta, L.count_meta, sizeof meta, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(NN_E_HIP, "nn_count_neighbors: %s", hipGetErrorString(hipGetLastError()));
+  if (meta[kMetaErr] & kErrPtr) return fail(NN_E_INVALID, "atom_ptr must run from 0 to N without decreasing");
+  if (meta[kMetaErr] & (kErrCell | kErrNonFinite | kErrShift | kErrTooMany))
+    return fail(meta[kMetaErr] & kErrCell ? NN_E_CELL : NN_E_DEVICE, "neighbor count failed (error bits %lld)",
+                (long long)meta[kMetaErr]);
+  *nnz = meta[kMetaNnz];
+  return NN_OK;
+}
+
+nn_status nn_build_neighbors(const nn_system* sys, double rc, double skin, nn_nlist* nl, void* ws, size_t ws_bytes,
+                             void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  if (!(rc > 0.0) || !(skin >= 0.0)) return fail(NN_E_INVALID, "rc must be > 0 and skin >= 0");
+  if (skin > 0.0 && !nl->ref_pos) return fail(NN_E_INVALID, "skin > 0 needs nl->ref_pos");
+  Layout L = carve(nullptr, sys->n_atoms, sys->n_structs, nl->capacity, 0, 1, nullptr);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, sys->n_atoms, sys->n_structs, nl->capacity, 0, 1, nullptr);
+  hipStream_t s = (hipStream_t)stream;
+  NbLaunch nb = nb_launch(sys, L, rc + skin, nl, false);
+  launch_neighbors(nb, skin > 0.0, skin, false, s);
+  nl->radius = rc + skin;
+  return check_launch("nn_build_neighbors");
+}
+
+nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, float* G, float* jac,
+                         void* ws, size_t ws_bytes, void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if (!G && sys->n_atoms > 0) return fail(NN_E_INVALID, "G is NULL");
+  if (jac) return fail(NN_E_UNSUPPORTED, "stored Jacobian output is not available in this build");
+  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
+  (void)ws;
+  (void)ws_bytes;
+  hipStream_t s = (hipStream_t)stream;
+  launch_desc_fwd(*sys, *nl, P, G, s);
+  return check_launch("nn_descriptors");
+}
+
+nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
+                           int32_t flags, size_t mem_budget, double* E_struct, float* E_atom, float* F, void* ws,
+                           size_t ws_bytes, void* stream) {
+  (void)mem_budget;
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((st = check_model(model, P))) return st;
+  if (!E_struct && sys->n_structs > 0) return fail(NN_E_INVALID, "E_struct is NULL");
+  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
+  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN)) return fail(NN_E_INVALID, "unknown flags");
+  if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
+    return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
+  const int64_t N = sys->n_atoms;
+  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  hipStream_t s = (hipStream_t)stream;
+  const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
+  const bool bf16 = mode != 0;
+  if (N == 0) {
+    if (sys->n_structs > 0) launch_energy_reduce(L.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+    return check_launch("nn_energy_forces");
+  }
+  // species grouping
+  launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+  // model as seen by the kernels
+  MlpArgs a{};
+  a.model.S = P.S;
+  ConvJob job{};
+  size_t wofs = 0;
+  for (int sp = 0; sp < P.S; ++sp) {
+    const nn_mlp& q = model->mlp[sp];
+    MlpDev& d = a.model.m[sp];
+    d.n_layers = q.n_layers;
+    for (int l = 0; l <= q.n_layers; ++l) d.width[l] = q.width[l];
+    for (int l = 0; l < q.n_layers; ++l) {
+      d.act[l] = q.act[l];
+      d.W[l] = q.W[l];
+      d.b[l] = q.b[l];
+    }
+    if (bf16) {
+      for (int l = 0; l < 2; ++l) {
+        const size_t n = ((size_t)q.width[l + 1] * q.width[l] + 127) / 128 * 128;
+        __bf16* w = L.wb + wofs;
+        wofs += 4 * n;
+        d.Wb[l] = w;
+        d.Wl[l] = w + n;
+        d.WbT[l] = w + 2 * n;
+        d.WlT[l] = w + 3 * n;
+        job.src[job.n] = q.W[l];
+        job.hi[job.n] = w;
+        job.lo[job.n] = w + n;
+        job.hiT[job.n] = w + 2 * n;
+        job.loT[job.n] = w + 3 * n;
+        job.rows[job.n] = q.width[l + 1];
+        job.cols[job.n] = q.width[l];
+        ++job.n;
+      }
+    }
+  }
+  if (bf16) launch_convert_bf16(job, s);
+  // descriptors
+  launch_desc_fwd(*sys, *nl, P, L.G, s);
+  // MLP energies and lambda
+  a.G = L.G;
+  a.perm = L.perm;
+  a.sp_start = L.sp_start;
+  a.E_atom = E_atom ? E_atom : L.E_atom;
+  a.lambda = F ? L.lam : nullptr;
+  a.D = P.D;
+  launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
+  launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+  if (F) {
+    launch_desc_adj(*sys, *nl, P, L.lam, L.pg, s);
+    launch_force_gather(*sys, *nl, L.pg, F, s);
+  }
+  return check_launch("nn_energy_forces");
+}
+
+nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                                const nn_model* model, int32_t flags, const double* dL_dE, const float* F,
+                                float* dL_dpos, float* const* dW, float* const* db, void* ws, size_t ws_bytes,
+                                void* stream) {
+  (void)sys;
+  (void)nl;
+  (void)p;
+  (void)model;
+  (void)flags;
+  (void)dL_dE;
+  (void)F;
+  (void)dL_dpos;
+  (void)dW;
+  (void)db;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return fail(NN_E_UNSUPPORTED, "nn_energy_forces_grad is not available in this build");
+}
+
+nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {
+  if (!nl || !nl->meta) return fail(NN_E_INVALID, "nl/meta is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  int64_t meta[8];
+  if (hipMemcpyAsync(meta, nl->meta, sizeof meta, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(NN_E_HIP, "nn_check: %s", hipGetErrorString(hipGetLastError()));
+  const int64_t err = meta[kMetaErr];
+  if (info) *info = meta[kMetaNnz];
+  if (err) {
+    hipLaunchKernelGGL(k_zero_meta, dim3(1), dim3(1), 0, s, nl->meta + kMetaErr);  // clears error word only
+    (void)hipStreamSynchronize(s);
+  }
+  if (err & kErrPtr) return fail(NN_E_INVALID, "atom_ptr must run from 0 to N without decreasing");
+  if (err & kErrCapacity)
+    return fail(NN_E_CAPACITY, "neighbor list needs %lld entries, capacity %lld", (long long)meta[kMetaNnz],
+                (long long)nl->capacity);
+  if (err & kErrCell) return fail(NN_E_CELL, "periodic cell narrower than 3 bins for a structure over 256 atoms");
+  if (err & kErrSpecies) return fail(NN_E_DEVICE, "species index out of range");
+  if (err & kErrNonFinite) return fail(NN_E_DEVICE, "non-finite position");
+  if (err & kErrShift) return fail(NN_E_DEVICE, "lattice image index beyond int8");
+  if (err & kErrTooMany) return fail(NN_E_DEVICE, "too many neighbors (> %d inside rc or > %d per row)", kMaxNb, kRowMax);
+  return NN_OK;
+}
+
+const char* nn_last_error(void) { return g_err; }
+
+}  // extern "C"

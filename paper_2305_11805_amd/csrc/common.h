@@ -1,0 +1,157 @@
+// Internal definitions shared by the HIP translation units of libnnpot.
+// Not part of the public C ABI (that is include/nnpot.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nnpot.h"
+
+namespace nnp {
+
+constexpr int kWave = 64;
+constexpr int kMaxRad = 64;      // radial bins per species
+constexpr int kMaxTheta = 16;    // angle bins
+constexpr int kMaxRsAng = 8;     // average-radius bins
+constexpr int kMaxNb = 192;      // neighbors inside rc held per atom on chip
+constexpr int kSmallMax = 256;   // structures up to this size use the all-pairs list builder
+constexpr int kRowMax = 1024;    // list entries per row the row sorter accepts
+
+// Device error bits, OR-ed into nl->meta[kMetaErr].
+enum : int64_t {
+  kErrCapacity = 1,   // list capacity exceeded (required size in meta[kMetaNnz])
+  kErrCell = 2,       // periodic cell too narrow and structure too large for all-pairs
+  kErrSpecies = 4,    // species index out of range
+  kErrNonFinite = 8,  // non-finite position
+  kErrTooMany = 16,   // more than kMaxNb neighbors inside rc, or a row over kRowMax
+  kErrShift = 32,     // lattice image index does not fit in int8
+  kErrPtr = 64,       // atom_ptr not 0 .. N nondecreasing
+};
+
+// Layout of the device metadata block of a neighbor list (nl->meta, int64[8]).
+enum { kMetaNnz = 0, kMetaValid = 1, kMetaBuilds = 2, kMetaRebuilt = 3, kMetaErr = 4, kMetaMaxRow = 5 };
+
+// Per-structure geometry computed on the device before binning.
+struct alignas(16) StructGeom {
+  double h[9];      // cell rows a, b, c
+  double inv[9];    // inverse: s = x * inv
+  int32_t nb[3];    // bins per direction (large path) or image bound K (small path)
+  int32_t small;    // 1: all-pairs path
+  int64_t bin_base; // first bin of this structure
+  int64_t n_bins;
+};
+
+// FP32 constants of the descriptor, passed by value to the kernels.
+struct DescConst {
+  int32_t S, n_rad, n_theta, n_rs_ang, D, zeta;  // zeta: integer exponent
+  float rc, eta_rad, eta_ang, eps_ang;
+  float pi_over_rc, half_pi_over_rc, fc_scale;   // pi/rc, pi/(2 rc)
+  float x_a[kMaxTheta], x_b[kMaxTheta], x_c;     // x = c*x_a + ssm*x_b + x_c
+  float rs_rad[kMaxRad], rs_rad_lo[kMaxRad];   // centre = hi + lo (double-float)
+  float rs_ang[kMaxRsAng], rs_ang_lo[kMaxRsAng];
+  double rc64, half_pi_over_rc64, pi_over_rc64;
+};
+
+// One species' MLP as seen by the kernels.
+struct MlpDev {
+  int32_t n_layers;
+  int32_t width[NN_MAX_LAYERS + 1];
+  int32_t act[NN_MAX_LAYERS];
+  const float* W[NN_MAX_LAYERS];       // [w_out][w_in] FP32
+  const float* b[NN_MAX_LAYERS];
+  const __bf16* Wb[NN_MAX_LAYERS];     // BF16 hi part [w_out][w_in] (BF16 modes)
+  const __bf16* Wl[NN_MAX_LAYERS];     // BF16 lo part, W - hi (split mode)
+  const __bf16* WbT[NN_MAX_LAYERS];    // transposed hi [w_in][w_out]
+  const __bf16* WlT[NN_MAX_LAYERS];    // transposed lo
+};
+struct ModelDev {
+  int32_t S;
+  MlpDev m[NN_MAX_SPECIES];
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Displacement from atom i to image n of atom j, FP64, in the fixed order
+// d = (x_j - x_i) + ((n_a a + n_b b) + n_c c), no contraction.
+__device__ __forceinline__ void displacement64(const double* __restrict__ xi, const double* __restrict__ xj,
+                                               const double* h, int na, int nb, int nc, double d[3]) {
+#pragma clang fp contract(off)
+  for (int k = 0; k < 3; ++k) {
+    double t = (double)na * h[0 + k];
+    t = t + (double)nb * h[3 + k];
+    t = t + (double)nc * h[6 + k];
+    d[k] = (xj[k] - xi[k]) + t;
+  }
+}
+
+__device__ __forceinline__ double norm2_64(const double d[3]) {
+#pragma clang fp contract(off)
+  return (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+}
+
+// ------------------------------------------------------------------------
+// host-side launch helpers (defined in the .hip files)
+// ------------------------------------------------------------------------
+
+size_t scan_scratch_elems(int64_t n);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s,
+                        const int32_t* predicate);
+
+// neighbors.hip
+struct NbLaunch {
+  const nn_system* sys;
+  double radius;
+  int64_t capacity;
+  nn_nlist* nl;      // null in count-only mode
+  int64_t* counts;   // row counts [N+1]
+  int64_t* offsets;  // scan output [N+1]: nl->offsets or scratch
+  StructGeom* geom;
+  int64_t* n_bins;   // [B+1]
+  int64_t* bin_base; // [B+1]
+  int64_t* bin_count;
+  int64_t* bin_start;
+  int64_t* bin_fill;
+  int32_t* bin_atoms;
+  int32_t* atom_bin;
+  int64_t* scan_tmp;
+  int32_t* flag;
+  int64_t* meta;
+  int64_t max_bins;
+};
+void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_only, hipStream_t s);
+
+// descriptors.hip
+bool desc_supported(int nt, int nra);
+void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s);
+void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
+                     hipStream_t s);
+void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, hipStream_t s);
+
+// mlp.hip
+struct MlpArgs {
+  ModelDev model;
+  const float* G;           // [N][D]
+  const int32_t* perm;      // [N] atoms grouped by species
+  const int64_t* sp_start;  // [S+1]
+  float* E_atom;            // [N]
+  float* lambda;            // [N][D] (null: energies only)
+  int D;
+};
+struct ConvJob {
+  int n;
+  const float* src[NN_MAX_SPECIES * 2];
+  __bf16* hi[NN_MAX_SPECIES * 2];
+  __bf16* lo[NN_MAX_SPECIES * 2];
+  __bf16* hiT[NN_MAX_SPECIES * 2];
+  __bf16* loT[NN_MAX_SPECIES * 2];
+  int rows[NN_MAX_SPECIES * 2], cols[NN_MAX_SPECIES * 2];
+};
+void launch_species_group(const int32_t* species, int64_t N, int S, int64_t* cnt, int64_t* off, int64_t* scan_tmp,
+                          int32_t* perm, int64_t* sp_start, hipStream_t s);
+bool mlp_supported(int h1, int h2);
+void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s);  // mode 0 FP32, 1 BF16, 2 split BF16
+void launch_convert_bf16(const ConvJob& job, hipStream_t s);
+void launch_energy_reduce(const float* E_atom, const int64_t* atom_ptr, int32_t B, int64_t N, double* E_struct,
+                          hipStream_t s);
+
+}  // namespace nnp

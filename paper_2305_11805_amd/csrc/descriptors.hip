@@ -1,0 +1,554 @@
+// mBP descriptors and their adjoint on gfx950.
+//
+// One 64-lane wave per atom.  The wave stages the atom's neighbors inside rc
+// in LDS, sorted by species (stable).  Per neighbor the pair geometry is
+// formed once from FP64 positions -- d = (x_j - x_i) + image shift, r, the
+// unit vector d/r, rc - r and the cosine cutoff -- and rounded to FP32 only
+// after the subtractions that would otherwise cancel (r is kept as a hi/lo
+// float pair).  Everything per triplet is FP32.
+//
+// Forward (radial + angular descriptor, Sec. II.A / III.A):
+//   radial: lane k owns radial bin k and sums over the neighbors of each
+//   species segment;
+//   angular: for every unordered species pair block (a <= b) the block's
+//   triplets are dealt to lanes 64 at a time; each lane accumulates the
+//   separable product  A_p(theta) * R_q(r_avg) * 2 fc fc  into n_theta x
+//   n_rs_ang registers, and a transposing butterfly over the wave leaves one
+//   summed bin per lane.
+//
+// Adjoint (forces, Sec. II: forces are derivatives of the energy): given
+// lambda_i = dE_i/dG_i, produce dE_i/dd_e for every neighbor entry e.
+//   radial: lane <-> neighbor;
+//   angular: lane <-> neighbor j on a circular schedule: at step s lane j
+//   takes the pair (j, (j + s) mod n), so every unordered pair is visited
+//   once and, within one step, no two lanes touch the same partner k.  The
+//   j-side gradient accumulates in registers, the k-side one is added to a
+//   per-neighbor LDS slot; since no two lanes of an instruction share a slot
+//   and instructions retire in program order, the sums are bitwise
+//   reproducible.
+#include <math.h>
+
+#include "common.h"
+
+namespace nnp {
+
+struct AtomNb {
+  float4 d[kMaxNb];   // unit vector d/r (x, y, z), r (hi)
+  float4 f[kMaxNb];   // fc, dfc/dr, r (lo), (entry index << 4 | species) as bits
+  int seg[NN_MAX_SPECIES + 1];
+  int n;
+  int bad;
+};
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ int nb_species(const float4& f) { return __float_as_int(f.w) & 15; }
+__device__ __forceinline__ int nb_entry(const float4& f) { return __float_as_int(f.w) >> 4; }
+
+__device__ __forceinline__ int struct_of_atom(const int64_t* atom_ptr, int32_t B, int64_t i) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (atom_ptr[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Stage the neighbors of atom i inside rc into LDS, sorted by species.
+// Entries at r >= rc get a zero pair gradient if pg != nullptr.
+__device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, const int64_t* __restrict__ offsets,
+                                const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
+                                const DescConst& P, int64_t* meta, float4* __restrict__ pg) {
+  const int lane = threadIdx.x;
+  const int c = struct_of_atom(sys.atom_ptr, sys.n_structs, i);
+  double h[9];
+  for (int k = 0; k < 9; ++k) h[k] = sys.cell[9 * (int64_t)c + k];
+  const double xi[3] = {sys.pos[3 * i], sys.pos[3 * i + 1], sys.pos[3 * i + 2]};
+  const int64_t e0 = offsets[i], e1 = offsets[i + 1];
+  const double rc2 = P.rc64 * P.rc64;
+  const int S = P.S;
+  const char4* sh4 = reinterpret_cast<const char4*>(shift);
+  int cnt[NN_MAX_SPECIES];
+  for (int s = 0; s < NN_MAX_SPECIES; ++s) cnt[s] = 0;
+  bool bad = false;
+  // pass A: count neighbors inside rc per species
+  for (int64_t base = e0; base < e1; base += kWave) {
+    int64_t e = base + lane;
+    bool valid = false;
+    int sp = 0;
+    if (e < e1) {
+      int32_t j = nbr[e];
+      char4 s4 = sh4[e];
+      double d[3];
+      displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d);
+      valid = norm2_64(d) < rc2;
+      sp = sys.species[j];
+      if (valid && (sp < 0 || sp >= S)) {
+        bad = true;
+        valid = false;
+      }
+    }
+    for (int s = 0; s < S; ++s) cnt[s] += __popcll(__ballot(valid && sp == s));
+  }
+  if (__any(bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+  int total = 0;
+  if (lane == 0) {
+    for (int s = 0; s < S; ++s) {
+      nb.seg[s] = total;
+      total += cnt[s];
+    }
+    nb.seg[S] = total;
+    nb.n = total;
+    nb.bad = total > kMaxNb;
+    if (total > kMaxNb) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+  }
+  __syncthreads();
+  if (nb.bad) return;
+  int run[NN_MAX_SPECIES];
+  for (int s = 0; s < S; ++s) run[s] = nb.seg[s];
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // pass B: pair geometry, scattered in species order
+  for (int64_t base = e0; base < e1; base += kWave) {
+    int64_t e = base + lane;
+    bool valid = false;
+    int sp = 0;
+    double d[3] = {0, 0, 0};
+    double r2 = 0;
+    if (e < e1) {
+      int32_t j = nbr[e];
+      char4 s4 = sh4[e];
+      displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d);
+      r2 = norm2_64(d);
+      valid = r2 < rc2;
+      sp = sys.species[j];
+      if (sp < 0 || sp >= S) valid = false;
+      if (!valid && pg) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    int slot = 0;
+    for (int s = 0; s < S; ++s) {
+      uint64_t m = __ballot(valid && sp == s);
+      if (valid && sp == s) slot = run[s] + __popcll(m & lt_mask);
+      run[s] += __popcll(m);
+    }
+    if (valid) {
+      const double r = sqrt(r2);
+      const double ir = 1.0 / r;
+      const double u = P.rc64 - r;  // formed in FP64: no cancellation near rc
+      const float r_hi = (float)r;
+      const float r_lo = (float)(r - (double)r_hi);
+      const float sa = sinf((float)(P.half_pi_over_rc64 * u));
+      const float fc = sa * sa;  // sin^2(pi (rc - r) / (2 rc))
+      // dfc/dr = -(pi / 2rc) sin(pi r / rc), and sin(pi r / rc) = sin(pi (rc - r) / rc)
+      const float dfc = (float)(-0.5 * P.pi_over_rc64) * sinf((float)(P.pi_over_rc64 * u));
+      nb.d[slot] = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
+      nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
+    }
+  }
+  __syncthreads();
+}
+
+// x^e for a small positive integer e, on an array (exponent bits outside).
+template <int N>
+__device__ __forceinline__ void ipow_array(const float (&x)[N], int e, float (&out)[N]) {
+  float base[N];
+#pragma unroll
+  for (int p = 0; p < N; ++p) {
+    out[p] = 1.0f;
+    base[p] = x[p];
+  }
+  while (e) {
+    if (e & 1) {
+#pragma unroll
+      for (int p = 0; p < N; ++p) out[p] *= base[p];
+    }
+    e >>= 1;
+    if (e) {
+#pragma unroll
+      for (int p = 0; p < N; ++p) base[p] *= base[p];
+    }
+  }
+}
+
+__device__ __forceinline__ int pair_block(int S, int a, int b) {
+  if (a > b) {
+    int t = a;
+    a = b;
+    b = t;
+  }
+  return a * S - a * (a - 1) / 2 + (b - a);
+}
+
+__device__ __forceinline__ int bitrev(int v, int bits) {
+  return bits == 0 ? 0 : (int)(__builtin_bitreverse32((unsigned)v) >> (32 - bits));
+}
+
+// Angle terms of one triplet from the two unit vectors: cos(theta), the
+// smoothed sine sqrt(sin^2 + eps), and the average radius as hi (exact half
+// of a rounded sum) + lo (the rounding error of that sum plus the lo parts).
+struct TripGeom {
+  float c, ssm, rbar, rbar_lo;
+};
+
+__device__ __forceinline__ TripGeom triplet_geom(const float4& u, const float4& fu, const float4& v, const float4& fv,
+                                                 float eps) {
+  TripGeom t;
+  t.c = fmaf(u.x, v.x, fmaf(u.y, v.y, u.z * v.z));
+  const float cx = fmaf(u.y, v.z, -u.z * v.y);
+  const float cy = fmaf(u.z, v.x, -u.x * v.z);
+  const float cz = fmaf(u.x, v.y, -u.y * v.x);
+  t.ssm = sqrtf(fmaf(cx, cx, fmaf(cy, cy, fmaf(cz, cz, eps))));
+  const float s = u.w + v.w;  // TwoSum: s + err == u.w + v.w exactly
+  const float bb = s - u.w;
+  const float err = (u.w - (s - bb)) + (v.w - bb);
+  t.rbar = 0.5f * s;
+  t.rbar_lo = 0.5f * (err + fu.z + fv.z);
+  return t;
+}
+
+// Transposing butterfly: on entry every lane holds NB partial sums; on exit
+// lane l holds, in v[r] (r < max(1, NB/64)), the wave-wide sum of bin
+// (bitrev_S(l mod 2^S) << (L - S)) + r, with L = log2 NB and S = min(L, 6).
+template <int NB>
+__device__ __forceinline__ void butterfly(float (&v)[NB]) {
+  constexpr int L = __builtin_ctz(NB);
+  constexpr int S = L < 6 ? L : 6;
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int st = 0; st < S; ++st) {
+    const int half = NB >> (st + 1);
+    const bool up = (lane >> st) & 1;
+#pragma unroll
+    for (int t = 0; t < half; ++t) {
+      float lo = v[t], hi = v[t + half];
+      float send = up ? lo : hi;
+      float keep = up ? hi : lo;
+      v[t] = keep + __shfl_xor(send, 1 << st);
+    }
+  }
+#pragma unroll
+  for (int m = 1 << S; m < 64; m <<= 1) v[0] += __shfl_xor(v[0], m);
+}
+
+template <int NT, int NRA>
+__global__ void __launch_bounds__(64) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
+                                                 DescConst P, float* __restrict__ G, int64_t* meta) {
+  constexpr int NB = NT * NRA;
+  __shared__ AtomNb nb;
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  float* Gi = G + i * (int64_t)P.D;
+  if (meta[kMetaValid] != 1) {  // no valid list: never read its entries
+    for (int d = lane; d < P.D; d += kWave) Gi[d] = 0.f;
+    return;
+  }
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr);
+  if (nb.bad) {
+    for (int d = lane; d < P.D; d += kWave) Gi[d] = 0.f;
+    return;
+  }
+  const int S = P.S;
+  const float eta_r2 = P.eta_rad * 1.4426950408889634f;
+  const float eta_a2 = P.eta_ang * 1.4426950408889634f;
+  // radial bins
+  for (int k0 = 0; k0 < P.n_rad; k0 += kWave) {
+    const int k = k0 + lane;
+    const float rs = k < P.n_rad ? P.rs_rad[k] : 0.f;
+    const float rs_lo = k < P.n_rad ? P.rs_rad_lo[k] : 0.f;
+    for (int s = 0; s < S; ++s) {
+      float acc = 0.f;
+      for (int t = nb.seg[s]; t < nb.seg[s + 1]; ++t) {
+        const float dr = (nb.d[t].w - rs) + (nb.f[t].z - rs_lo);
+        acc = fmaf(fexp2(-eta_r2 * dr * dr), nb.f[t].x, acc);
+      }
+      if (k < P.n_rad) Gi[s * P.n_rad + k] = acc;
+    }
+  }
+  // angular blocks
+  const int ang0 = P.n_rad * S;
+  for (int a = 0; a < S; ++a) {
+    for (int b = a; b < S; ++b) {
+      const int na = nb.seg[a + 1] - nb.seg[a], nbb = nb.seg[b + 1] - nb.seg[b];
+      const int T = (a == b) ? na * (na - 1) / 2 : na * nbb;
+      float acc[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) acc[t] = 0.f;
+      for (int t0 = 0; t0 < T; t0 += kWave) {
+        const int t = t0 + lane;
+        if (t < T) {
+          int j, k;
+          if (a == b) {
+            int kk = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
+            while (kk * (kk - 1) / 2 > t) --kk;
+            while ((kk + 1) * kk / 2 <= t) ++kk;
+            j = nb.seg[a] + (t - kk * (kk - 1) / 2);
+            k = nb.seg[a] + kk;
+          } else {
+            j = nb.seg[a] + t / nbb;
+            k = nb.seg[b] + t % nbb;
+          }
+          const float4 u = nb.d[j], v = nb.d[k];
+          const float4 fu = nb.f[j], fv = nb.f[k];
+          const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+          const float F2 = 2.0f * fu.x * fv.x;
+          float x[NT], A[NT];
+#pragma unroll
+          for (int p = 0; p < NT; ++p) x[p] = fmaf(g.c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
+          ipow_array<NT>(x, P.zeta, A);
+#pragma unroll
+          for (int q = 0; q < NRA; ++q) {
+            const float dq = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
+            const float R = fexp2(-eta_a2 * dq * dq) * F2;
+#pragma unroll
+            for (int p = 0; p < NT; ++p) acc[q * NT + p] = fmaf(A[p], R, acc[q * NT + p]);
+          }
+        }
+      }
+      butterfly<NB>(acc);
+      constexpr int L = __builtin_ctz(NB);
+      constexpr int SS = L < 6 ? L : 6;
+      constexpr int PER = NB >> SS;
+      float* out = Gi + ang0 + pair_block(S, a, b) * NB;
+      if (lane < (1 << SS)) {
+        const int base = bitrev(lane, SS) << (L - SS);
+#pragma unroll
+        for (int r = 0; r < PER; ++r) out[base + r] = acc[r];
+      }
+    }
+  }
+}
+
+// Per-pair energy gradients dE_i/dd_e (float4 per entry, w unused) from
+// lambda_i = dE_i/dG_i.
+template <int NT, int NRA, bool ONE_SPECIES>
+__global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
+                                                 DescConst P, const float* __restrict__ lambda,
+                                                 float4* __restrict__ pg, int64_t* meta) {
+  constexpr int NB = NT * NRA;
+  constexpr int NBP = NB + 4;  // padded block stride in LDS (bank spread)
+  __shared__ AtomNb nb;
+  __shared__ float gx[kMaxNb], gy[kMaxNb], gz[kMaxNb];
+  extern __shared__ float dyn_lds[];  // [S * n_rad] radial lambda, then the angular blocks
+  float* lam_r = dyn_lds;
+  float* lam_a = dyn_lds + P.S * P.n_rad;
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
+  const int64_t e0 = offsets[i];
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, pg);
+  if (nb.bad) {
+    for (int64_t e = e0 + lane; e < offsets[i + 1]; e += kWave) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const int S = P.S;
+  const int n = nb.n;
+  const float* lam = lambda + i * (int64_t)P.D;
+  const int ang0 = P.n_rad * S;
+  const int nblk = S * (S + 1) / 2;
+  for (int d = lane; d < ang0; d += kWave) lam_r[d] = lam[d];
+  for (int d = lane; d < nblk * NB; d += kWave) lam_a[(d / NB) * NBP + d % NB] = lam[ang0 + d];
+  for (int t = lane; t < n; t += kWave) {
+    gx[t] = 0.f;
+    gy[t] = 0.f;
+    gz[t] = 0.f;
+  }
+  __syncthreads();
+  const float eta_r2 = P.eta_rad * 1.4426950408889634f;
+  const float eta_a2 = P.eta_ang * 1.4426950408889634f;
+  // radial: lane <-> neighbor; dE/dd = (dE/dr) d/r
+  for (int t0 = 0; t0 < n; t0 += kWave) {
+    const int t = t0 + lane;
+    if (t < n) {
+      const float4 u = nb.d[t], fu = nb.f[t];
+      const float* lr = lam_r + nb_species(fu) * P.n_rad;
+      float gr = 0.f;
+      for (int k = 0; k < P.n_rad; ++k) {
+        const float dr = (u.w - P.rs_rad[k]) + (fu.z - P.rs_rad_lo[k]);
+        const float g = fexp2(-eta_r2 * dr * dr);
+        gr = fmaf(lr[k] * g, fmaf(-2.0f * P.eta_rad * dr, fu.x, fu.y), gr);
+      }
+      atomicAdd(&gx[t], gr * u.x);
+      atomicAdd(&gy[t], gr * u.y);
+      atomicAdd(&gz[t], gr * u.z);
+    }
+  }
+  __syncthreads();
+  float Lr[ONE_SPECIES ? NB : 1];
+  if constexpr (ONE_SPECIES) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t) Lr[t] = lam_a[t];
+  }
+  const int zeta1 = P.zeta - 1;
+  const float zf = (float)P.zeta;
+  // angular: circular schedule over the species-sorted list
+  for (int j0 = 0; j0 < n; j0 += kWave) {
+    const int j = j0 + lane;
+    const bool active = j < n;
+    float4 u = make_float4(1.f, 0.f, 0.f, 1.f), fu = make_float4(0.f, 0.f, 0.f, 0.f);
+    int sj = 0;
+    if (active) {
+      u = nb.d[j];
+      fu = nb.f[j];
+      sj = nb_species(fu);
+    }
+    const float iru = frcp(u.w);
+    float ax = 0.f, ay = 0.f, az = 0.f;
+    const int smax = n / 2;  // s = n/2 only for j < n/2 when n is even
+    for (int s = 1; s <= smax; ++s) {
+      const bool take = active && !((n % 2 == 0) && s == n / 2 && j >= n / 2);
+      int k = j + s;
+      if (k >= n) k -= n;
+      if (take) {
+        const float4 v = nb.d[k];
+        const float4 fv = nb.f[k];
+        const float* La = lam_a;
+        if (!ONE_SPECIES) La = lam_a + pair_block(S, sj, nb_species(fv)) * NBP;
+        const float irv = frcp(v.w);
+        const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+        const float c = g.c;
+        const float F2 = 2.0f * fu.x * fv.x;
+        float x[NT], P1[NT], A[NT];
+#pragma unroll
+        for (int p = 0; p < NT; ++p) x[p] = fmaf(c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
+        ipow_array<NT>(x, zeta1, P1);
+#pragma unroll
+        for (int p = 0; p < NT; ++p) A[p] = P1[p] * x[p];
+        float R[NRA], dq[NRA];
+#pragma unroll
+        for (int q = 0; q < NRA; ++q) {
+          dq[q] = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
+          R[q] = fexp2(-eta_a2 * dq[q] * dq[q]);
+        }
+        float T[NRA], U[NT];
+#pragma unroll
+        for (int p = 0; p < NT; ++p) U[p] = 0.f;
+#pragma unroll
+        for (int q = 0; q < NRA; ++q) {
+          float tq = 0.f;
+#pragma unroll
+          for (int p = 0; p < NT; ++p) {
+            float l;
+            if constexpr (ONE_SPECIES) l = Lr[q * NT + p];
+            else l = La[q * NT + p];
+            tq = fmaf(l, A[p], tq);
+            U[p] = fmaf(l, R[q], U[p]);
+          }
+          T[q] = tq;
+        }
+        // E_t = F2 sum_q R_q T_q, T_q = sum_p lambda_qp A_p
+        float dEdF2 = 0.f, dEdravg = 0.f;
+#pragma unroll
+        for (int q = 0; q < NRA; ++q) {
+          dEdF2 = fmaf(T[q], R[q], dEdF2);
+          dEdravg = fmaf(T[q] * R[q], dq[q], dEdravg);
+        }
+        dEdravg *= -2.0f * P.eta_ang * F2;
+        float dEdc = 0.f, dEdssm = 0.f;
+#pragma unroll
+        for (int p = 0; p < NT; ++p) {
+          const float gp = U[p] * P1[p];
+          dEdc = fmaf(gp, P.x_a[p], dEdc);
+          dEdssm = fmaf(gp, P.x_b[p], dEdssm);
+        }
+        dEdc *= zf * F2;
+        dEdssm *= zf * F2;
+        // sin^2 = 1 - cos^2, so d ssm / d cos = -cos / ssm
+        const float coef = dEdc - dEdssm * c * frcp(g.ssm);
+        const float dEdru = 0.5f * dEdravg + dEdF2 * 2.0f * fu.y * fv.x;
+        const float dEdrv = 0.5f * dEdravg + dEdF2 * 2.0f * fu.x * fv.y;
+        // d cos / d d_u = (v^ - cos u^) / r_u
+        const float cu = coef * iru, cv = coef * irv;
+        ax += cu * (v.x - c * u.x) + dEdru * u.x;
+        ay += cu * (v.y - c * u.y) + dEdru * u.y;
+        az += cu * (v.z - c * u.z) + dEdru * u.z;
+        atomicAdd(&gx[k], cv * (u.x - c * v.x) + dEdrv * v.x);
+        atomicAdd(&gy[k], cv * (u.y - c * v.y) + dEdrv * v.y);
+        atomicAdd(&gz[k], cv * (u.z - c * v.z) + dEdrv * v.z);
+      }
+    }
+    if (active) {
+      atomicAdd(&gx[j], ax);
+      atomicAdd(&gy[j], ay);
+      atomicAdd(&gz[j], az);
+    }
+  }
+  __syncthreads();
+  for (int t = lane; t < n; t += kWave) pg[e0 + nb_entry(nb.f[t])] = make_float4(gx[t], gy[t], gz[t], 0.f);
+}
+
+// F_k = sum over entries e of row k of (pg[e] - pg[rev[e]]), in row order.
+__global__ void k_force_gather(int64_t N, const int64_t* __restrict__ offsets, const int32_t* __restrict__ rev,
+                               const float4* __restrict__ pg, float* __restrict__ F, const int64_t* meta) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  float fx = 0.f, fy = 0.f, fz = 0.f;
+  const bool valid = meta[kMetaValid] == 1;
+  for (int64_t e = offsets[k]; valid && e < offsets[k + 1]; ++e) {
+    const float4 a = pg[e], b = pg[rev[e]];
+    fx += a.x - b.x;
+    fy += a.y - b.y;
+    fz += a.z - b.z;
+  }
+  F[3 * k] = fx;
+  F[3 * k + 1] = fy;
+  F[3 * k + 2] = fz;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int NT, int NRA>
+static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
+  hipLaunchKernelGGL((k_desc_fwd<NT, NRA>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets, nl.nbr,
+                     nl.shift, P, G, nl.meta);
+}
+
+template <int NT, int NRA>
+static void launch_adj_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
+                         hipStream_t s) {
+  const size_t lds = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
+  if (P.S == 1)
+    hipLaunchKernelGGL((k_desc_adj<NT, NRA, true>), dim3((unsigned)sys.n_atoms), dim3(64), lds, s, sys, nl.offsets,
+                       nl.nbr, nl.shift, P, lam, pg, nl.meta);
+  else
+    hipLaunchKernelGGL((k_desc_adj<NT, NRA, false>), dim3((unsigned)sys.n_atoms), dim3(64), lds, s, sys, nl.offsets,
+                       nl.nbr, nl.shift, P, lam, pg, nl.meta);
+}
+
+bool desc_supported(int nt, int nra) {
+  return (nt == 4 || nt == 8 || nt == 16) && (nra == 4 || nra == 8) && nt * nra <= 128;
+}
+
+#define NNP_DISPATCH(NT_, NRA_, CALL)                                          \
+  do {                                                                         \
+    if (nt == 4 && nra == 4) { constexpr int NT_ = 4, NRA_ = 4; CALL; }        \
+    else if (nt == 4 && nra == 8) { constexpr int NT_ = 4, NRA_ = 8; CALL; }   \
+    else if (nt == 8 && nra == 4) { constexpr int NT_ = 8, NRA_ = 4; CALL; }   \
+    else if (nt == 8 && nra == 8) { constexpr int NT_ = 8, NRA_ = 8; CALL; }   \
+    else if (nt == 16 && nra == 4) { constexpr int NT_ = 16, NRA_ = 4; CALL; } \
+    else if (nt == 16 && nra == 8) { constexpr int NT_ = 16, NRA_ = 8; CALL; } \
+  } while (0)
+
+void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
+  if (sys.n_atoms == 0) return;
+  const int nt = P.n_theta, nra = P.n_rs_ang;
+  NNP_DISPATCH(A, B, (launch_fwd_t<A, B>(sys, nl, P, G, s)));
+}
+
+void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
+                     hipStream_t s) {
+  if (sys.n_atoms == 0) return;
+  const int nt = P.n_theta, nra = P.n_rs_ang;
+  NNP_DISPATCH(A, B, (launch_adj_t<A, B>(sys, nl, P, lam, pg, s)));
+}
+
+void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, hipStream_t s) {
+  if (sys.n_atoms == 0) return;
+  hipLaunchKernelGGL(k_force_gather, dim3((unsigned)((sys.n_atoms + 255) / 256)), dim3(256), 0, s, sys.n_atoms,
+                     nl.offsets, nl.rev, pg, F, nl.meta);
+}
+
+}  // namespace nnp

@@ -1,0 +1,442 @@
+// Per-species MLP of Eq. (1) (Sec. II.A) on MFMA, fused forward + backward.
+//
+// Atoms are grouped by species (stable counting sort), then one wave takes a
+// tile of 16 atoms of one species through
+//   z1 = W1 G + b1, a1 = act(z1);  z2 = W2 a1 + b2, a2 = act(z2);
+//   E = w3 . a2 + b3;
+//   delta2 = w3 * act'(z2);  delta1 = (W2^T delta2) * act'(z1);
+//   lambda = W1^T delta1 = dE/dG.
+// The two hidden layers run on 16x16 MFMA tiles (FP32: 16x16x4, BF16:
+// 16x16x32 with FP32 accumulation); the width-1 output layer is a dot
+// product.  act'(z) stays in registers in the MFMA output layout, where the
+// backward pass needs it elementwise; activations and deltas pass through
+// LDS to become the next product's row operand.
+#include <math.h>
+
+#include "common.h"
+
+namespace nnp {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kTile = 16;
+
+__device__ __forceinline__ float act_f(int code, float z) {
+  switch (code) {
+    case NN_ACT_GAUSSIAN: return __builtin_amdgcn_exp2f(-1.4426950408889634f * z * z);
+    case NN_ACT_RELU: return z > 0.f ? z : 0.f;
+    case NN_ACT_TANH: return tanhf(z);
+    default: return z;
+  }
+}
+__device__ __forceinline__ float act_d(int code, float z, float a) {
+  switch (code) {
+    case NN_ACT_GAUSSIAN: return -2.0f * z * a;
+    case NN_ACT_RELU: return z > 0.f ? 1.f : 0.f;
+    case NN_ACT_TANH: return 1.0f - a * a;
+    default: return 1.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// species grouping: perm lists atoms species by species, in atom order
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(64) k_sp_count(const int32_t* __restrict__ species, int64_t N, int S, int64_t nblk,
+                                                 int64_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int sp = i < N ? species[i] : -1;
+  for (int s = 0; s < S; ++s) {
+    uint64_t m = __ballot(sp == s);
+    if (threadIdx.x == 0) cnt[(int64_t)s * nblk + blockIdx.x] = __popcll(m);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_sp_scatter(const int32_t* __restrict__ species, int64_t N, int S, int64_t nblk,
+                                                   const int64_t* __restrict__ off, int32_t* __restrict__ perm,
+                                                   int64_t* __restrict__ sp_start) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int sp = i < N ? species[i] : -1;
+  const int lane = threadIdx.x;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (int s = 0; s < S; ++s) {
+    uint64_t m = __ballot(sp == s);
+    if (sp == s) perm[off[(int64_t)s * nblk + blockIdx.x] + __popcll(m & lt)] = (int32_t)i;
+  }
+  if (blockIdx.x == 0 && lane <= S) sp_start[lane] = off[(int64_t)lane * nblk];
+}
+
+// ---------------------------------------------------------------------------
+// fused MLP tile kernel
+// ---------------------------------------------------------------------------
+
+
+// Row operand of a 16x16x4 FP32 MFMA from a row-major [16][ld] buffer.
+__device__ __forceinline__ float a_f32(const float* buf, int ld, int k0) {
+  const int l = threadIdx.x;
+  return buf[(l & 15) * ld + k0 + (l >> 4)];
+}
+
+// Products in the MLP run in one of three modes:
+//   kFp32  - FP32 operands, v_mfma_f32_16x16x4_f32;
+//   kBf16  - operands rounded to BF16, v_mfma_f32_16x16x32_bf16, FP32 sums;
+//   kBf16x3 - each operand split x = hi + lo with hi, lo in BF16 and the
+//            product taken as hi*hi + hi*lo + lo*hi (three BF16 MFMAs, FP32
+//            sums): about 16 significant bits per operand.
+enum { kFp32 = 0, kBf16 = 1, kBf16x3 = 2 };
+
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const __bf16 h = (__bf16)x[q];
+    hi[q] = h;
+    lo[q] = (__bf16)(x[q] - (float)h);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ floatx4 mma_bf16(floatx4 acc, const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                            const bf16x8& bl) {
+  if constexpr (MODE == kBf16x3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+// A fragment (row lm, 8 consecutive k from kb) of a row-major FP32 LDS buffer.
+template <int MODE>
+__device__ __forceinline__ void a_frag_lds(const float* buf, int ld, int lm, int kb, bf16x8& hi, bf16x8& lo) {
+  float x[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) x[q] = buf[lm * ld + kb + q];
+  if constexpr (MODE == kBf16x3) split8(x, hi, lo);
+  else
+#pragma unroll
+    for (int q = 0; q < 8; ++q) hi[q] = (__bf16)x[q];
+}
+
+// B fragment: 8 consecutive BF16 values at p (hi) and p_lo (lo), zero past n.
+template <int MODE>
+__device__ __forceinline__ void b_frag(const __bf16* p, const __bf16* p_lo, int avail, bf16x8& hi, bf16x8& lo) {
+  if (avail >= 8) {
+    hi = *reinterpret_cast<const bf16x8*>(p);
+    if constexpr (MODE == kBf16x3) lo = *reinterpret_cast<const bf16x8*>(p_lo);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      hi[q] = q < avail ? p[q] : (__bf16)0.f;
+      if constexpr (MODE == kBf16x3) lo[q] = q < avail ? p_lo[q] : (__bf16)0.f;
+    }
+  }
+}
+
+template <int H1T, int H2T, int MODE>
+__global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
+  constexpr int H1 = H1T * 16, H2 = H2T * 16;
+  constexpr int HM = H1 > H2 ? H1 : H2;
+  constexpr bool BF = MODE != kFp32;
+  __shared__ float buf[kTile * (HM + 4)];
+  __shared__ int32_t rows[kTile];
+  const int lane = threadIdx.x;
+  const int S = args.model.S;
+  // which species / tile
+  int64_t t = blockIdx.x;
+  int s = 0;
+  int64_t r0 = 0, ns = 0;
+  for (; s < S; ++s) {
+    ns = args.sp_start[s + 1] - args.sp_start[s];
+    const int64_t nt = (ns + kTile - 1) / kTile;
+    if (t < nt) break;
+    t -= nt;
+  }
+  if (s >= S) return;
+  r0 = args.sp_start[s] + t * kTile;
+  const int nrows = (int)min<int64_t>(kTile, args.sp_start[s] + ns - r0);
+  if (lane < kTile) rows[lane] = lane < nrows ? args.perm[r0 + lane] : -1;
+  __syncthreads();
+  const MlpDev& M = args.model.m[s];
+  const int D = args.D;
+  const int lm = lane & 15;   // row (A operand) / column (B, C)
+  const int lk = lane >> 4;   // k group (A, B) / row group (C)
+  const int arow = rows[lm];
+  const float* Grow = args.G + (int64_t)(arow < 0 ? 0 : arow) * D;
+  const int act1 = M.act[0], act2 = M.act[1];
+  constexpr int LD = HM + 4;
+  bf16x8 ah{}, al{}, bh{}, bl{};
+
+  // ---- layer 1: z1 = G W1^T + b1 ----
+  floatx4 acc1[H1T];
+#pragma unroll
+  for (int n = 0; n < H1T; ++n) acc1[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF) {
+    for (int k0 = 0; k0 < D; k0 += 32) {
+      const int kb = k0 + 8 * lk;
+      float x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] = (arow >= 0 && kb + q < D) ? Grow[kb + q] : 0.f;
+      if constexpr (MODE == kBf16x3) split8(x, ah, al);
+      else
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ah[q] = (__bf16)x[q];
+#pragma unroll
+      for (int n = 0; n < H1T; ++n) {
+        const int64_t off = (int64_t)(n * 16 + lm) * D + kb;
+        b_frag<MODE>(M.Wb[0] + off, M.Wl[0] + off, D - kb, bh, bl);
+        acc1[n] = mma_bf16<MODE>(acc1[n], ah, al, bh, bl);
+      }
+    }
+  } else {
+    const float* W1 = M.W[0];
+    for (int k0 = 0; k0 < D; k0 += 4) {
+      const int k = k0 + lk;
+      const float a = (arow >= 0 && k < D) ? Grow[k] : 0.f;
+#pragma unroll
+      for (int n = 0; n < H1T; ++n) {
+        const float b = k < D ? W1[(int64_t)(n * 16 + lm) * D + k] : 0.f;
+        acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[n], 0, 0, 0);
+      }
+    }
+  }
+  float d1[H1T][4];  // act'(z1) in C layout: row 4*lk + j, column n*16 + lm
+#pragma unroll
+  for (int n = 0; n < H1T; ++n) {
+    const float bias = M.b[0][n * 16 + lm];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = acc1[n][j] + bias;
+      const float a = act_f(act1, z);
+      d1[n][j] = act_d(act1, z, a);
+      buf[(4 * lk + j) * LD + n * 16 + lm] = a;
+    }
+  }
+  __syncthreads();
+
+  // ---- layer 2: z2 = a1 W2^T + b2 ----
+  floatx4 acc2[H2T];
+#pragma unroll
+  for (int n = 0; n < H2T; ++n) acc2[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF) {
+    for (int k0 = 0; k0 < H1; k0 += 32) {
+      const int kb = k0 + 8 * lk;
+      a_frag_lds<MODE>(buf, LD, lm, kb, ah, al);
+#pragma unroll
+      for (int n = 0; n < H2T; ++n) {
+        const int64_t off = (int64_t)(n * 16 + lm) * H1 + kb;
+        b_frag<MODE>(M.Wb[1] + off, M.Wl[1] + off, 8, bh, bl);
+        acc2[n] = mma_bf16<MODE>(acc2[n], ah, al, bh, bl);
+      }
+    }
+  } else {
+    const float* W2 = M.W[1];
+    for (int k0 = 0; k0 < H1; k0 += 4) {
+      const float a = a_f32(buf, LD, k0);
+#pragma unroll
+      for (int n = 0; n < H2T; ++n) {
+        const float b = W2[(int64_t)(n * 16 + lm) * H1 + k0 + lk];
+        acc2[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2[n], 0, 0, 0);
+      }
+    }
+  }
+  // ---- output E = w3 . a2 + b3, delta2 = w3 * act'(z2) ----
+  const float* w3 = M.W[2];
+  float e[4] = {0.f, 0.f, 0.f, 0.f};
+  float dl2[H2T][4];
+#pragma unroll
+  for (int n = 0; n < H2T; ++n) {
+    const float bias = M.b[1][n * 16 + lm];
+    const float w = w3[n * 16 + lm];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = acc2[n][j] + bias;
+      const float a = act_f(act2, z);
+      e[j] = fmaf(a, w, e[j]);
+      dl2[n][j] = w * act_d(act2, z, a);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float v = e[j];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    e[j] = v;
+  }
+  if (lm == 0) {
+    const float b3 = M.b[2][0];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = rows[4 * lk + j];
+      if (r >= 0) args.E_atom[r] = e[j] + b3;
+    }
+  }
+  if (args.lambda == nullptr) return;
+  __syncthreads();
+  // ---- delta1 = (delta2 W2) * act'(z1) ----
+#pragma unroll
+  for (int n = 0; n < H2T; ++n)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) buf[(4 * lk + j) * LD + n * 16 + lm] = dl2[n][j];
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < H1T; ++n) acc1[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (BF) {
+    for (int k0 = 0; k0 < H2; k0 += 32) {  // B = W2 [H2][H1] read through W2^T [H1][H2]
+      const int kb = k0 + 8 * lk;
+      a_frag_lds<MODE>(buf, LD, lm, kb, ah, al);
+#pragma unroll
+      for (int n = 0; n < H1T; ++n) {
+        const int64_t off = (int64_t)(n * 16 + lm) * H2 + kb;
+        b_frag<MODE>(M.WbT[1] + off, M.WlT[1] + off, 8, bh, bl);
+        acc1[n] = mma_bf16<MODE>(acc1[n], ah, al, bh, bl);
+      }
+    }
+  } else {
+    const float* W2 = M.W[1];  // [H2][H1]: B[k][n] = W2[k][n]
+    for (int k0 = 0; k0 < H2; k0 += 4) {
+      const float a = a_f32(buf, LD, k0);
+#pragma unroll
+      for (int n = 0; n < H1T; ++n) {
+        const float b = W2[(int64_t)(k0 + lk) * H1 + n * 16 + lm];
+        acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[n], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n = 0; n < H1T; ++n)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) buf[(4 * lk + j) * LD + n * 16 + lm] = acc1[n][j] * d1[n][j];
+  __syncthreads();
+  // ---- lambda = delta1 W1, D columns in chunks of 8 tiles ----
+  constexpr int CH = 8;
+  for (int c0 = 0; c0 < D; c0 += CH * 16) {
+    floatx4 acc[CH];
+#pragma unroll
+    for (int n = 0; n < CH; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (BF) {
+      for (int k0 = 0; k0 < H1; k0 += 32) {  // B = W1 [H1][D] read through W1^T [D][H1]
+        const int kb = k0 + 8 * lk;
+        a_frag_lds<MODE>(buf, LD, lm, kb, ah, al);
+#pragma unroll
+        for (int n = 0; n < CH; ++n) {
+          const int col = c0 + n * 16 + lm;
+          const int64_t off = (int64_t)(col < D ? col : 0) * H1 + kb;
+          b_frag<MODE>(M.WbT[0] + off, M.WlT[0] + off, col < D ? 8 : 0, bh, bl);
+          acc[n] = mma_bf16<MODE>(acc[n], ah, al, bh, bl);
+        }
+      }
+    } else {
+      const float* W1 = M.W[0];  // [H1][D]: B[k][n] = W1[k][n]
+      for (int k0 = 0; k0 < H1; k0 += 4) {
+        const float a = a_f32(buf, LD, k0);
+#pragma unroll
+        for (int n = 0; n < CH; ++n) {
+          const int col = c0 + n * 16 + lm;
+          const float b = col < D ? W1[(int64_t)(k0 + lk) * D + col] : 0.f;
+          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[n], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < CH; ++n) {
+      const int col = c0 + n * 16 + lm;
+      if (col < D) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = rows[4 * lk + j];
+          if (r >= 0) args.lambda[(int64_t)r * D + col] = acc[n][j];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 weight copies: hi = bf16(W), lo = bf16(W - hi), each also transposed;
+// one launch for all species and layers
+// ---------------------------------------------------------------------------
+
+__global__ void k_convert_bf16(ConvJob job) {
+  for (int m = 0; m < job.n; ++m) {
+    const int R = job.rows[m], Cc = job.cols[m];
+    const int64_t total = (int64_t)R * Cc;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+      const int r = (int)(idx / Cc), c = (int)(idx % Cc);
+      const float w = job.src[m][idx];
+      const __bf16 h = (__bf16)w;
+      const __bf16 l = (__bf16)(w - (float)h);
+      job.hi[m][idx] = h;
+      job.lo[m][idx] = l;
+      job.hiT[m][(int64_t)c * R + r] = h;
+      job.loT[m][(int64_t)c * R + r] = l;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-structure energy, FP64, fixed-order tree
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) k_energy_reduce(const float* __restrict__ E_atom,
+                                                       const int64_t* __restrict__ atom_ptr, int64_t N,
+                                                       double* __restrict__ E_struct) {
+  __shared__ double sh[256];
+  const int c = blockIdx.x;
+  const int64_t a0 = min(max(atom_ptr[c], (int64_t)0), N), a1 = min(max(atom_ptr[c + 1], a0), N);
+  double acc = 0.0;
+  for (int64_t a = a0 + threadIdx.x; a < a1; a += 256) acc += (double)E_atom[a];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E_struct[c] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+void launch_species_group(const int32_t* species, int64_t N, int S, int64_t* cnt, int64_t* off, int64_t* scan_tmp,
+                          int32_t* perm, int64_t* sp_start, hipStream_t s) {
+  const int64_t nblk = (N + 63) / 64 > 0 ? (N + 63) / 64 : 1;
+  hipLaunchKernelGGL(k_sp_count, dim3((unsigned)nblk), dim3(64), 0, s, species, N, S, nblk, cnt);
+  exclusive_scan_i64(cnt, off, (int64_t)S * nblk, scan_tmp, s, nullptr);
+  hipLaunchKernelGGL(k_sp_scatter, dim3((unsigned)nblk), dim3(64), 0, s, species, N, S, nblk, off, perm, sp_start);
+}
+
+bool mlp_supported(int h1, int h2) {
+  return (h1 == 64 && h2 == 32) || (h1 == 128 && h2 == 128) || (h1 == 256 && h2 == 128);
+}
+
+template <int A, int B>
+static void launch_mlp_t(const MlpArgs& a, int mode, int64_t n_tiles, hipStream_t s) {
+  if (mode == kBf16x3) hipLaunchKernelGGL((k_mlp<A, B, kBf16x3>), dim3((unsigned)n_tiles), dim3(64), 0, s, a);
+  else if (mode == kBf16) hipLaunchKernelGGL((k_mlp<A, B, kBf16>), dim3((unsigned)n_tiles), dim3(64), 0, s, a);
+  else hipLaunchKernelGGL((k_mlp<A, B, kFp32>), dim3((unsigned)n_tiles), dim3(64), 0, s, a);
+}
+
+void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s) {
+  const int64_t n_tiles = (N + kTile - 1) / kTile + a.model.S;
+  if (N == 0) return;
+  if (h1 == 64 && h2 == 32) launch_mlp_t<4, 2>(a, mode, n_tiles, s);
+  else if (h1 == 128 && h2 == 128) launch_mlp_t<8, 8>(a, mode, n_tiles, s);
+  else if (h1 == 256 && h2 == 128) launch_mlp_t<16, 8>(a, mode, n_tiles, s);
+}
+
+void launch_convert_bf16(const ConvJob& job, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_bf16, dim3(256), dim3(256), 0, s, job);
+}
+
+void launch_energy_reduce(const float* E_atom, const int64_t* atom_ptr, int32_t B, int64_t N, double* E_struct,
+                          hipStream_t s) {
+  if (B == 0) return;
+  hipLaunchKernelGGL(k_energy_reduce, dim3((unsigned)B), dim3(256), 0, s, E_atom, atom_ptr, N, E_struct);
+}
+
+}  // namespace nnp

@@ -1,0 +1,632 @@
+// Neighbor lists on the device: cell binning for large structures,
+// all-pairs over lattice images for small ones, canonical row order and
+// reverse-entry index.  Locality and cutoff: Sec. I and Sec. III.A.
+//
+// Every kernel of a (re)build reads a device flag first and exits when the
+// skin test decided that the previous list is still valid, so the whole
+// build can sit in a captured graph without host decisions.
+#include <math.h>
+
+#include "common.h"
+
+namespace nnp {
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int64 (n + 1 outputs: out[n] = total)
+// ---------------------------------------------------------------------------
+
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+size_t scan_scratch_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 2; }
+
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    int64_t add = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  int64_t incl = sh[t];
+  *total = sh[kScanBlock - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_reduce(const int64_t* __restrict__ in, int64_t n, int64_t* __restrict__ partial,
+                              const int32_t* pred) {
+  if (pred && !*pred) return;
+  __shared__ int64_t sh[kScanBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) s += (base + k < n) ? in[base + k] : 0;
+  int64_t tot;
+  block_exclusive_scan(s, sh, &tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_partials(int64_t* partial, int64_t nb, const int32_t* pred) {
+  if (pred && !*pred) return;
+  __shared__ int64_t sh[kScanBlock];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanBlock) {
+    int64_t idx = base + threadIdx.x;
+    int64_t v = idx < nb ? partial[idx] : 0;
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(v, sh, &tot);
+    if (idx < nb) partial[idx] = ex + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) partial[nb] = carry;
+}
+
+__global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t n, const int64_t* __restrict__ partial,
+                             int64_t nb, int64_t* __restrict__ out, const int32_t* pred) {
+  if (pred && !*pred) return;
+  __shared__ int64_t sh[kScanBlock];
+  int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int64_t v[kScanItems];
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    s += v[k];
+  }
+  int64_t tot;
+  int64_t ex = block_exclusive_scan(s, sh, &tot) + partial[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = ex;
+    ex += v[k];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
+}
+
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s,
+                        const int32_t* pred) {
+  int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb == 0) nb = 1;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, scratch, pred);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanBlock), 0, s, scratch, nb, pred);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, scratch, nb, out, pred);
+}
+
+// ---------------------------------------------------------------------------
+// skin test and build predicate
+// ---------------------------------------------------------------------------
+
+// flag[0] = 1 if the list must be (re)built.
+__global__ void k_skin_init(int32_t* flag, const int64_t* meta, int use_skin) {
+  flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
+}
+
+// atom_ptr must run from 0 to N without decreasing; otherwise nothing is
+// built (and the list is marked invalid, so no later kernel reads it).
+__global__ void k_check_ptr(const int64_t* __restrict__ atom_ptr, int32_t B, int64_t N, int64_t* meta, int32_t* flag) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (c == 0) bad = atom_ptr[0] != 0 || atom_ptr[B] != N;
+  if (c < B) bad = bad || atom_ptr[c + 1] < atom_ptr[c];
+  if (bad) {
+    atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrPtr);
+    meta[kMetaValid] = 0;
+    flag[0] = 0;
+    flag[1] = 0;
+  }
+}
+
+__global__ void k_skin_check(const double* __restrict__ pos, const double* __restrict__ ref, int64_t n,
+                             double half_skin2, const int64_t* meta, int32_t* flag, int use_skin) {
+  if (!use_skin || meta[kMetaValid] != 1) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool move = false;
+  if (i < n) {
+    double dx = pos[3 * i] - ref[3 * i], dy = pos[3 * i + 1] - ref[3 * i + 1], dz = pos[3 * i + 2] - ref[3 * i + 2];
+    double d2 = dx * dx + dy * dy + dz * dz;
+    move = !(d2 <= half_skin2);  // also catches NaN
+  }
+  if (__any(move) && lane_id() == 0) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// per-structure geometry
+// ---------------------------------------------------------------------------
+
+__device__ void inverse3(const double h[9], double inv[9]) {
+  double c00 = h[4] * h[8] - h[5] * h[7];
+  double c01 = h[5] * h[6] - h[3] * h[8];
+  double c02 = h[3] * h[7] - h[4] * h[6];
+  double det = h[0] * c00 + h[1] * c01 + h[2] * c02;
+  double id = 1.0 / det;
+  inv[0] = c00 * id;
+  inv[1] = (h[2] * h[7] - h[1] * h[8]) * id;
+  inv[2] = (h[1] * h[5] - h[2] * h[4]) * id;
+  inv[3] = c01 * id;
+  inv[4] = (h[0] * h[8] - h[2] * h[6]) * id;
+  inv[5] = (h[2] * h[3] - h[0] * h[5]) * id;
+  inv[6] = c02 * id;
+  inv[7] = (h[1] * h[6] - h[0] * h[7]) * id;
+  inv[8] = (h[0] * h[4] - h[1] * h[3]) * id;
+}
+
+__device__ void perp_widths(const double* h, double w[3]) {
+  const double *a = h, *b = h + 3, *c = h + 6;
+  double bc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2], b[0] * c[1] - b[1] * c[0]};
+  double ca[3] = {c[1] * a[2] - c[2] * a[1], c[2] * a[0] - c[0] * a[2], c[0] * a[1] - c[1] * a[0]};
+  double ab[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+  double vol = fabs(a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2]);
+  w[0] = vol / sqrt(bc[0] * bc[0] + bc[1] * bc[1] + bc[2] * bc[2]);
+  w[1] = vol / sqrt(ca[0] * ca[0] + ca[1] * ca[1] + ca[2] * ca[2]);
+  w[2] = vol / sqrt(ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
+}
+
+__device__ __forceinline__ void frac(const double* inv, const double* x, double s[3]) {
+  for (int d = 0; d < 3; ++d) s[d] = x[0] * inv[d] + x[1] * inv[3 + d] + x[2] * inv[6 + d];
+}
+
+// One 64-thread block per structure.  Small structures (<= kSmallMax atoms)
+// take the all-pairs path with an image bound K_d = floor(radius/w_d +
+// spread_d) + 1 on periodic directions (spread of the fractional
+// coordinates); larger ones are binned with bins >= radius wide.
+__global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                          const double* __restrict__ cell, const uint8_t* __restrict__ pbc, int32_t B,
+                          double radius, StructGeom* __restrict__ geom, int64_t* __restrict__ n_bins,
+                          int64_t* meta, const int32_t* flag) {
+  if (!*flag) return;
+  const int c = blockIdx.x;
+  if (c >= B) return;
+  __shared__ double h[9], inv[9];
+  __shared__ double lo[3][64], hi[3][64];
+  if (threadIdx.x < 9) h[threadIdx.x] = cell[9 * (int64_t)c + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0) inverse3(h, inv);
+  __syncthreads();
+  const int64_t a0 = atom_ptr[c], a1 = atom_ptr[c + 1];
+  const int64_t nc = a1 - a0;
+  const bool small = nc <= kSmallMax;
+  double l[3] = {1e300, 1e300, 1e300}, u[3] = {-1e300, -1e300, -1e300};
+  if (small) {
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += 64) {
+      double s[3];
+      frac(inv, pos + 3 * a, s);
+      for (int d = 0; d < 3; ++d) {
+        l[d] = fmin(l[d], s[d]);
+        u[d] = fmax(u[d], s[d]);
+      }
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    lo[d][threadIdx.x] = l[d];
+    hi[d][threadIdx.x] = u[d];
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int t = 1; t < 64; ++t)
+    for (int d = 0; d < 3; ++d) {
+      l[d] = fmin(l[d], lo[d][t]);
+      u[d] = fmax(u[d], hi[d][t]);
+    }
+  double w[3];
+  perp_widths(h, w);
+  StructGeom g;
+  for (int k = 0; k < 9; ++k) {
+    g.h[k] = h[k];
+    g.inv[k] = inv[k];
+  }
+  g.small = small ? 1 : 0;
+  int64_t nbins = 0;
+  if (small) {
+    for (int d = 0; d < 3; ++d) {
+      double K = pbc[3 * c + d] && nc > 0 ? floor(radius / w[d] + (u[d] - l[d])) + 1.0 : 0.0;
+      if (!(K <= 127.0)) {
+        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
+        K = 0.0;
+      }
+      g.nb[d] = (int)K;
+    }
+  } else {
+    int minb[3];
+    for (int d = 0; d < 3; ++d) {
+      double k = floor(w[d] / (radius * (1.0 + 1e-6)));
+      if (!(k >= 1.0)) k = 1.0;
+      if (k > 1024.0) k = 1024.0;
+      g.nb[d] = (int)k;
+      minb[d] = pbc[3 * c + d] ? 3 : 1;
+      if (g.nb[d] < minb[d]) {
+        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrCell);
+        g.nb[d] = minb[d];
+      }
+    }
+    // keep the bin count near the atom count (dilute boxes): merge bins
+    const int64_t cap = 8 * nc + 64;
+    for (int it = 0; it < 64 && (int64_t)g.nb[0] * g.nb[1] * g.nb[2] > cap; ++it) {
+      int d = 0;
+      for (int e = 1; e < 3; ++e)
+        if (g.nb[e] - minb[e] > g.nb[d] - minb[d]) d = e;
+      if (g.nb[d] <= minb[d]) break;
+      g.nb[d] = max(minb[d], (g.nb[d] + 1) / 2);
+    }
+    nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+  }
+  g.n_bins = nbins;
+  g.bin_base = 0;
+  geom[c] = g;
+  n_bins[c] = nbins;
+}
+
+__global__ void k_nb_set_base(StructGeom* geom, const int64_t* base, int32_t B, const int32_t* flag) {
+  if (!*flag) return;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < B) geom[c].bin_base = base[c];
+}
+
+__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v, const int32_t* flag) {
+  if (flag && !*flag) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__device__ __forceinline__ int struct_of(const int64_t* atom_ptr, int32_t B, int64_t i) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (atom_ptr[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Bin coordinates of an atom of a binned structure; m is the whole-cell
+// offset removed on periodic directions.
+__device__ __forceinline__ void bin_coords(const StructGeom& g, const uint8_t* pbc3, const double* x, int b3[3],
+                                           int m[3]) {
+  double s[3];
+  frac(g.inv, x, s);
+  for (int d = 0; d < 3; ++d) {
+    double t = s[d];
+    m[d] = 0;
+    if (pbc3[d]) {
+      double f = floor(t);
+      m[d] = (int)fmin(fmax(f, -1073741824.0), 1073741824.0);
+      t = t - f;
+    }
+    double kf = fmin(fmax(floor(t * g.nb[d]), 0.0), (double)(g.nb[d] - 1));
+    b3[d] = (int)kf;
+  }
+}
+
+__global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                         const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
+                         int64_t* __restrict__ bin_count, int32_t* __restrict__ atom_bin, int64_t* meta,
+                         const int32_t* flag) {
+  if (!*flag) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* x = pos + 3 * i;
+  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+    atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
+    atom_bin[4 * i] = -1;
+    return;
+  }
+  int c = struct_of(atom_ptr, B, i);
+  const StructGeom& g = geom[c];
+  if (g.small) {
+    atom_bin[4 * i] = -1;
+    return;
+  }
+  int b3[3], m[3];
+  bin_coords(g, pbc + 3 * c, x, b3, m);
+  int64_t bin = g.bin_base + ((int64_t)b3[0] * g.nb[1] + b3[1]) * g.nb[2] + b3[2];
+  atom_bin[4 * i + 0] = (int32_t)bin;
+  atom_bin[4 * i + 1] = m[0];
+  atom_bin[4 * i + 2] = m[1];
+  atom_bin[4 * i + 3] = m[2];
+  atomicAdd((unsigned long long*)&bin_count[bin], 1ull);
+}
+
+__global__ void k_nb_scatter(int64_t N, const int32_t* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
+                             int64_t* __restrict__ bin_fill, int32_t* __restrict__ bin_atoms, const int32_t* flag) {
+  if (!*flag) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int32_t bin = atom_bin[4 * i];
+  if (bin < 0) return;
+  unsigned long long k = atomicAdd((unsigned long long*)&bin_fill[bin], 1ull);
+  bin_atoms[bin_start[bin] + (int64_t)k] = (int32_t)i;
+}
+
+// Enumerate the candidates of atom i and apply the inclusion test; emit(j,
+// na, nb, nc) is called for every accepted entry.  Returns false if an
+// image index does not fit in int8.
+template <typename Emit>
+__device__ bool enumerate_row(int64_t i, const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                              const uint8_t* __restrict__ pbc, int32_t B, const StructGeom* __restrict__ geom,
+                              const int64_t* __restrict__ bin_start, const int32_t* __restrict__ bin_atoms,
+                              const int32_t* __restrict__ atom_bin, double r2max, Emit emit) {
+  const int c = struct_of(atom_ptr, B, i);
+  const StructGeom& g = geom[c];
+  const double* xi = pos + 3 * i;
+  bool ok = true;
+  if (g.small) {
+    const int K0 = g.nb[0], K1 = g.nb[1], K2 = g.nb[2];
+    for (int64_t j = atom_ptr[c]; j < atom_ptr[c + 1]; ++j) {
+      const double* xj = pos + 3 * j;
+      for (int na = -K0; na <= K0; ++na)
+        for (int nb = -K1; nb <= K1; ++nb)
+          for (int nc = -K2; nc <= K2; ++nc) {
+            if (j == i && na == 0 && nb == 0 && nc == 0) continue;
+            double d[3];
+            displacement64(xi, xj, g.h, na, nb, nc, d);
+            if (norm2_64(d) < r2max) emit((int32_t)j, na, nb, nc);
+          }
+    }
+    return ok;
+  }
+  const uint8_t* p3 = pbc + 3 * c;
+  int bi[3], mi[3];
+  {
+    int32_t bin = atom_bin[4 * i];
+    int64_t local = bin - g.bin_base;
+    bi[2] = (int)(local % g.nb[2]);
+    local /= g.nb[2];
+    bi[1] = (int)(local % g.nb[1]);
+    bi[0] = (int)(local / g.nb[1]);
+    mi[0] = atom_bin[4 * i + 1];
+    mi[1] = atom_bin[4 * i + 2];
+    mi[2] = atom_bin[4 * i + 3];
+  }
+  for (int da = -1; da <= 1; ++da)
+    for (int db = -1; db <= 1; ++db)
+      for (int dc = -1; dc <= 1; ++dc) {
+        int dd[3] = {da, db, dc}, bb[3], wr[3];
+        bool skip = false;
+        for (int d = 0; d < 3; ++d) {
+          int k = bi[d] + dd[d];
+          wr[d] = 0;
+          if (k < 0 || k >= g.nb[d]) {
+            if (!p3[d]) {
+              skip = true;
+              break;
+            }
+            wr[d] = k < 0 ? -1 : 1;
+            k -= wr[d] * g.nb[d];
+          }
+          bb[d] = k;
+        }
+        if (skip) continue;
+        int64_t bin = g.bin_base + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
+        for (int64_t t = bin_start[bin]; t < bin_start[bin + 1]; ++t) {
+          int32_t j = bin_atoms[t];
+          int n[3];
+          for (int d = 0; d < 3; ++d) n[d] = p3[d] ? wr[d] + mi[d] - atom_bin[4 * j + 1 + d] : 0;
+          if (j == i && n[0] == 0 && n[1] == 0 && n[2] == 0) continue;
+          double dv[3];
+          displacement64(xi, pos + 3 * (int64_t)j, g.h, n[0], n[1], n[2], dv);
+          if (norm2_64(dv) < r2max) {
+            if (n[0] < -127 || n[0] > 127 || n[1] < -127 || n[1] > 127 || n[2] < -127 || n[2] > 127) ok = false;
+            emit(j, n[0], n[1], n[2]);
+          }
+        }
+      }
+  return ok;
+}
+
+__global__ void k_nb_count(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                           const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
+                           const int64_t* __restrict__ bin_start, const int32_t* __restrict__ bin_atoms,
+                           const int32_t* __restrict__ atom_bin, double r2max, int64_t* __restrict__ row_count,
+                           int64_t* meta, const int32_t* flag) {
+  if (!*flag) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* x = pos + 3 * i;
+  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
+    row_count[i] = 0;
+    atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
+    return;
+  }
+  int64_t cnt = 0;
+  bool ok = enumerate_row(i, pos, atom_ptr, pbc, B, geom, bin_start, bin_atoms, atom_bin, r2max,
+                          [&](int32_t, int, int, int) { ++cnt; });
+  if (!ok) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
+  if (cnt > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+  atomicMax((unsigned long long*)&meta[kMetaMaxRow], (unsigned long long)cnt);
+  row_count[i] = cnt;
+}
+
+// After the scan of row counts: record nnz, check the capacity, and decide
+// whether the fill runs (flag[1]).
+__global__ void k_nb_capacity(const int64_t* offsets, int64_t N, int64_t capacity, int64_t* meta, int32_t* flag) {
+  if (!flag[0]) {
+    flag[1] = 0;
+    meta[kMetaRebuilt] = 0;
+    return;
+  }
+  int64_t nnz = offsets[N];
+  meta[kMetaNnz] = nnz;
+  meta[kMetaRebuilt] = 1;
+  if (nnz > capacity || (meta[kMetaErr] & (kErrShift | kErrTooMany | kErrNonFinite | kErrCell))) {
+    if (nnz > capacity) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrCapacity);
+    meta[kMetaValid] = 0;
+    flag[1] = 0;
+  } else {
+    flag[1] = 1;
+  }
+}
+
+__global__ void k_nb_fill(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                          const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
+                          const int64_t* __restrict__ bin_start, const int32_t* __restrict__ bin_atoms,
+                          const int32_t* __restrict__ atom_bin, double r2max, const int64_t* __restrict__ offsets,
+                          int32_t* __restrict__ nbr, int8_t* __restrict__ shift, const int32_t* flag) {
+  if (!flag[1]) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double* x = pos + 3 * i;
+  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) return;
+  int64_t out = offsets[i];
+  const int64_t end = offsets[i + 1];
+  enumerate_row(i, pos, atom_ptr, pbc, B, geom, bin_start, bin_atoms, atom_bin, r2max,
+                [&](int32_t j, int na, int nb, int nc) {
+                  if (out < end) {
+                    nbr[out] = j;
+                    char4 s;
+                    s.x = (signed char)na;
+                    s.y = (signed char)nb;
+                    s.z = (signed char)nc;
+                    s.w = 0;
+                    reinterpret_cast<char4*>(shift)[out] = s;
+                  }
+                  ++out;
+                });
+}
+
+__device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) {
+  return ((uint64_t)(uint32_t)j << 24) | ((uint64_t)(uint8_t)(s.x + 128) << 16) |
+         ((uint64_t)(uint8_t)(s.y + 128) << 8) | (uint64_t)(uint8_t)(s.z + 128);
+}
+
+// Sort each row by (j, n_a, n_b, n_c): one 64-thread block per row, bitonic
+// sort in LDS (rows up to kRowMax entries).
+__global__ void __launch_bounds__(64) k_nb_sort_rows(int64_t N, const int64_t* __restrict__ offsets,
+                                                     int32_t* __restrict__ nbr, int8_t* __restrict__ shift,
+                                                     const int32_t* flag) {
+  if (!flag[1]) return;
+  __shared__ uint64_t key[kRowMax];
+  const int64_t i = blockIdx.x;
+  if (i >= N) return;
+  const int64_t e0 = offsets[i];
+  const int len = (int)(offsets[i + 1] - e0);
+  if (len <= 1 || len > kRowMax) return;
+  int P = 1;
+  while (P < len) P <<= 1;
+  char4* sh4 = reinterpret_cast<char4*>(shift);
+  for (int t = threadIdx.x; t < P; t += 64) key[t] = t < len ? entry_key(nbr[e0 + t], sh4[e0 + t]) : ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int t = threadIdx.x; t < P; t += 64) {
+        int partner = t ^ jj;
+        if (partner > t) {
+          uint64_t a = key[t], b = key[partner];
+          bool up = (t & k) == 0;
+          if ((a > b) == up) {
+            key[t] = b;
+            key[partner] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < len; t += 64) {
+    uint64_t k = key[t];
+    nbr[e0 + t] = (int32_t)(k >> 24);
+    char4 s;
+    s.x = (signed char)((int)((k >> 16) & 255) - 128);
+    s.y = (signed char)((int)((k >> 8) & 255) - 128);
+    s.z = (signed char)((int)(k & 255) - 128);
+    s.w = 0;
+    sh4[e0 + t] = s;
+  }
+}
+
+// Reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
+// found by binary search in the sorted row.  The list is exactly symmetric
+// because the FP64 displacement of the reverse entry is the exact negation.
+__global__ void __launch_bounds__(64) k_nb_rev(int64_t N, const int64_t* __restrict__ offsets,
+                                               const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
+                                               int32_t* __restrict__ rev, int64_t* meta, const int32_t* flag) {
+  if (!flag[1]) return;
+  const int64_t i = blockIdx.x;
+  if (i >= N) return;
+  const char4* sh4 = reinterpret_cast<const char4*>(shift);
+  for (int64_t e = offsets[i] + threadIdx.x; e < offsets[i + 1]; e += 64) {
+    int32_t j = nbr[e];
+    char4 s = sh4[e];
+    char4 ns;
+    ns.x = (signed char)(-s.x);
+    ns.y = (signed char)(-s.y);
+    ns.z = (signed char)(-s.z);
+    ns.w = 0;
+    uint64_t want = entry_key((int32_t)i, ns);
+    int64_t lo = offsets[j], hi = offsets[j + 1] - 1, found = -1;
+    while (lo <= hi) {
+      int64_t mid = (lo + hi) >> 1;
+      uint64_t k = entry_key(nbr[mid], sh4[mid]);
+      if (k == want) {
+        found = mid;
+        break;
+      }
+      if (k < want) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    // a missing reverse entry cannot happen for an exactly symmetric list;
+    // point at the entry itself (zero net force) and flag it
+    rev[e] = (int32_t)(found >= 0 ? found : e);
+    if (found < 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+  }
+}
+
+__global__ void k_nb_finish(const double* __restrict__ pos, double* __restrict__ ref_pos, int64_t N, int64_t* meta,
+                            const int32_t* flag) {
+  if (!flag[1]) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 3 * N && ref_pos) ref_pos[i] = pos[i];
+  if (i == 0) {
+    meta[kMetaValid] = 1;
+    meta[kMetaBuilds] += 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+
+void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_only, hipStream_t s) {
+  const nn_system* sys = L.sys;
+  const int64_t N = sys->n_atoms;
+  const int32_t B = sys->n_structs;
+  const unsigned gN = (unsigned)((N + 255) / 256 > 0 ? (N + 255) / 256 : 1);
+  hipLaunchKernelGGL(k_skin_init, dim3(1), dim3(1), 0, s, L.flag, L.meta, use_skin ? 1 : 0);
+  if (use_skin && L.nl && L.nl->ref_pos && N > 0)
+    hipLaunchKernelGGL(k_skin_check, dim3(gN), dim3(256), 0, s, sys->pos, L.nl->ref_pos, N, 0.25 * skin * skin,
+                       L.meta, L.flag, 1);
+  hipLaunchKernelGGL(k_check_ptr, dim3((B + 256) / 256), dim3(256), 0, s, sys->atom_ptr, B, N, L.meta, L.flag);
+  if (B > 0)
+    hipLaunchKernelGGL(k_nb_geom, dim3(B), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B, L.radius,
+                       L.geom, L.n_bins, L.meta, L.flag);
+  exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
+  if (B > 0)
+    hipLaunchKernelGGL(k_nb_set_base, dim3((B + 255) / 256), dim3(256), 0, s, L.geom, L.bin_base, B, L.flag);
+  const unsigned gB = (unsigned)((L.max_bins + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_fill_i64, dim3(gB), dim3(256), 0, s, L.bin_count, L.max_bins + 1, (int64_t)0, L.flag);
+  hipLaunchKernelGGL(k_fill_i64, dim3(gB), dim3(256), 0, s, L.bin_fill, L.max_bins + 1, (int64_t)0, L.flag);
+  const double r2 = L.radius * L.radius;
+  if (N > 0)
+    hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
+                       L.bin_count, L.atom_bin, L.meta, L.flag);
+  exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag);
+  if (N > 0) {
+    hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, L.atom_bin, L.bin_start, L.bin_fill, L.bin_atoms,
+                       L.flag);
+    hipLaunchKernelGGL(k_nb_count, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
+                       L.bin_start, L.bin_atoms, L.atom_bin, r2, L.counts, L.meta, L.flag);
+  }
+  exclusive_scan_i64(L.counts, L.offsets, N, L.scan_tmp, s, L.flag);
+  hipLaunchKernelGGL(k_nb_capacity, dim3(1), dim3(1), 0, s, L.offsets, N,
+                     count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag);
+  if (count_only || N == 0) return;
+  nn_nlist* nl = L.nl;
+  hipLaunchKernelGGL(k_nb_fill, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
+                     L.bin_start, L.bin_atoms, L.atom_bin, r2, nl->offsets, nl->nbr, nl->shift, L.flag);
+  hipLaunchKernelGGL(k_nb_sort_rows, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, L.flag);
+  hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev, L.meta,
+                     L.flag);
+  hipLaunchKernelGGL(k_nb_finish, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, s, sys->pos, nl->ref_pos, N,
+                     L.meta, L.flag);
+}
+
+}  // namespace nnp

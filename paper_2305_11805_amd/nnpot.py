@@ -1,0 +1,284 @@
+"""ctypes binding of libnnpot (include/nnpot.h).
+
+The functions nn_* below have the names and arguments of the C ABI; they only
+marshal arguments.  Device memory comes from torch tensors on the current HIP
+device and work is enqueued on torch's current stream.  `Potential` bundles
+the buffers one evaluation needs.  There is no fallback: if libnnpot.so is
+missing, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnnpot.so")
+
+NN_MAX_SPECIES = 8
+NN_MAX_LAYERS = 4
+NN_BF16_MLP = 1
+NN_STORE_JACOBIAN = 2
+NN_BF16X3_MLP = 4
+ACT = {"linear": 0, "gaussian": 1, "relu": 2, "tanh": 3}
+STATUS = {0: "NN_OK", 1: "NN_E_INVALID", 2: "NN_E_CAPACITY", 3: "NN_E_CELL", 4: "NN_E_WORKSPACE",
+          5: "NN_E_UNSUPPORTED", 6: "NN_E_HIP", 7: "NN_E_DEVICE"}
+
+
+class NNError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class nn_system(C.Structure):
+    _fields_ = [("n_atoms", C.c_int64), ("n_structs", C.c_int32), ("pos", C.c_void_p), ("species", C.c_void_p),
+                ("atom_ptr", C.c_void_p), ("cell", C.c_void_p), ("pbc", C.c_void_p)]
+
+
+class nn_nlist(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("offsets", C.c_void_p), ("nbr", C.c_void_p), ("shift", C.c_void_p),
+                ("rev", C.c_void_p), ("ref_pos", C.c_void_p), ("meta", C.c_void_p), ("radius", C.c_double)]
+
+
+class nn_mbp_params(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("rc", C.c_double), ("n_rad", C.c_int32), ("eta_rad", C.c_double),
+                ("rs_rad", C.c_void_p), ("n_theta", C.c_int32), ("theta_s", C.c_void_p), ("n_rs_ang", C.c_int32),
+                ("eta_ang", C.c_double), ("rs_ang", C.c_void_p), ("zeta", C.c_double), ("eps", C.c_double)]
+
+
+class nn_mlp(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("width", C.c_int32 * (NN_MAX_LAYERS + 1)),
+                ("act", C.c_int32 * NN_MAX_LAYERS), ("W", C.c_void_p * NN_MAX_LAYERS),
+                ("b", C.c_void_p * NN_MAX_LAYERS)]
+
+
+class nn_model(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("mlp", nn_mlp * NN_MAX_SPECIES)]
+
+
+_lib = None
+EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_check", "nn_last_error")
+
+
+def lib():
+    """Open libnnpot.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2305_11805_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, SZ, D = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.c_double
+        L.nn_descriptor_dim.restype = I64
+        L.nn_descriptor_dim.argtypes = [P]
+        L.nn_workspace_size.restype = I32
+        L.nn_workspace_size.argtypes = [I64, I32, I64, P, P, I32, SZ, C.POINTER(SZ)]
+        L.nn_count_neighbors.restype = I32
+        L.nn_count_neighbors.argtypes = [P, D, C.POINTER(I64), P, SZ, P]
+        L.nn_build_neighbors.restype = I32
+        L.nn_build_neighbors.argtypes = [P, D, D, P, P, SZ, P]
+        L.nn_descriptors.restype = I32
+        L.nn_descriptors.argtypes = [P, P, P, P, P, P, SZ, P]
+        L.nn_energy_forces.restype = I32
+        L.nn_energy_forces.argtypes = [P, P, P, P, I32, SZ, P, P, P, P, SZ, P]
+        L.nn_energy_forces_grad.restype = I32
+        L.nn_energy_forces_grad.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, SZ, P]
+        L.nn_check.restype = I32
+        L.nn_check.argtypes = [P, P, C.POINTER(I64)]
+        L.nn_last_error.restype = C.c_char_p
+        L.nn_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _ok(status: int):
+    if status != 0:
+        raise NNError(status, lib().nn_last_error().decode())
+
+
+def _p(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, same names
+# ---------------------------------------------------------------------------
+
+def nn_descriptor_dim(params: nn_mbp_params) -> int:
+    return int(lib().nn_descriptor_dim(C.byref(params)))
+
+
+def nn_workspace_size(n_atoms, n_structs, capacity, params=None, model=None, flags=0, mem_budget=0) -> int:
+    out = C.c_size_t(0)
+    _ok(lib().nn_workspace_size(n_atoms, n_structs, capacity, C.byref(params) if params else None,
+                                C.byref(model) if model else None, flags, mem_budget, C.byref(out)))
+    return int(out.value)
+
+
+def nn_count_neighbors(sys: nn_system, radius: float, ws, stream=None) -> int:
+    n = C.c_int64(0)
+    _ok(lib().nn_count_neighbors(C.byref(sys), radius, C.byref(n), _p(ws), ws.numel(), _stream(stream)))
+    return int(n.value)
+
+
+def nn_build_neighbors(sys: nn_system, rc: float, skin: float, nl: nn_nlist, ws, stream=None):
+    _ok(lib().nn_build_neighbors(C.byref(sys), rc, skin, C.byref(nl), _p(ws), ws.numel(), _stream(stream)))
+
+
+def nn_descriptors(sys, nl, params, G, jac, ws, stream=None):
+    _ok(lib().nn_descriptors(C.byref(sys), C.byref(nl), C.byref(params), _p(G), _p(jac), _p(ws),
+                             0 if ws is None else ws.numel(), _stream(stream)))
+
+
+def nn_energy_forces(sys, nl, params, model, flags, mem_budget, E_struct, E_atom, F, ws, stream=None):
+    _ok(lib().nn_energy_forces(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, mem_budget,
+                               _p(E_struct), _p(E_atom), _p(F), _p(ws), ws.numel(), _stream(stream)))
+
+
+def nn_energy_forces_grad(sys, nl, params, model, flags, dL_dE, F, dL_dpos, dW, db, ws, stream=None):
+    _ok(lib().nn_energy_forces_grad(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, _p(dL_dE),
+                                    _p(F), _p(dL_dpos), dW, db, _p(ws), ws.numel(), _stream(stream)))
+
+
+def nn_check(nl: nn_nlist, stream=None) -> int:
+    info = C.c_int64(0)
+    st = lib().nn_check(C.byref(nl), _stream(stream), C.byref(info))
+    if st != 0:
+        raise NNError(st, lib().nn_last_error().decode())
+    return int(info.value)
+
+
+def nn_last_error() -> str:
+    return lib().nn_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# device buffers for one system
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DeviceModel:
+    struct: nn_model
+    tensors: list  # keeps the FP32 weight tensors alive
+    grads: Optional[list] = None
+
+
+def make_params(p) -> tuple:
+    """nn_mbp_params from an object with the descriptor hyperparameters
+    (host arrays are kept alive in the returned tuple)."""
+    rs_rad = np.ascontiguousarray(p.rs_rad, np.float64)
+    th = np.ascontiguousarray(p.theta_s, np.float64)
+    rs_ang = np.ascontiguousarray(p.rs_ang, np.float64)
+    s = nn_mbp_params(p.n_species, p.rc, rs_rad.size, p.eta_rad, rs_rad.ctypes.data, th.size, th.ctypes.data,
+                      rs_ang.size, p.eta_ang, rs_ang.ctypes.data, p.zeta, p.eps)
+    return s, (rs_rad, th, rs_ang)
+
+
+def make_model(model, device="cuda") -> DeviceModel:
+    """Upload per-species (widths, acts, [W], [b]) FP64 host weights as FP32."""
+    import torch
+    m = nn_model()
+    m.n_species = len(model)
+    keep = []
+    for s, (widths, acts, Ws, bs) in enumerate(model):
+        q = m.mlp[s]
+        q.n_layers = len(Ws)
+        for l, w in enumerate(widths):
+            q.width[l] = int(w)
+        for l, a in enumerate(acts):
+            q.act[l] = ACT[a] if isinstance(a, str) else int(a)
+        for l, (W, b) in enumerate(zip(Ws, bs)):
+            tw = torch.tensor(np.asarray(W, np.float32), device=device).contiguous()
+            tb = torch.tensor(np.asarray(b, np.float32), device=device).contiguous()
+            keep += [tw, tb]
+            q.W[l] = tw.data_ptr()
+            q.b[l] = tb.data_ptr()
+    return DeviceModel(m, keep)
+
+
+class Potential:
+    """Device-side buffers for evaluating one system: positions, list,
+    workspace and outputs.  All compute runs in libnnpot."""
+
+    def __init__(self, system, params, model=None, capacity: Optional[int] = None, skin: float = 0.0,
+                 capacity_margin: float = 1.25, flags: int = 0, device="cuda"):
+        import torch
+        lib()
+        self.torch = torch
+        self.dev = torch.device(device)
+        self.N, self.B = system.n_atoms, system.n_structs
+        self.params_host = params
+        self.params, self._keep_params = make_params(params)
+        self.D = nn_descriptor_dim(self.params)
+        if self.D < 0:
+            raise NNError(1, nn_last_error())
+        self.rc, self.skin, self.flags = float(params.rc), float(skin), flags
+        t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
+        self.pos = t(system.pos, torch.float64)
+        self.species = t(system.species, torch.int32)
+        self.atom_ptr = t(system.atom_ptr, torch.int64)
+        self.cell = t(np.asarray(system.cell, np.float64).reshape(-1, 9), torch.float64)
+        self.pbc = t(np.asarray(system.pbc, np.uint8).reshape(-1, 3), torch.uint8)
+        self.sys = nn_system(self.N, self.B, self.pos.data_ptr(), self.species.data_ptr(), self.atom_ptr.data_ptr(),
+                             self.cell.data_ptr(), self.pbc.data_ptr())
+        self.dmodel = make_model(model, device) if model is not None else None
+        ws0 = nn_workspace_size(self.N, self.B, 0)
+        self.ws = torch.empty(ws0, dtype=torch.uint8, device=self.dev)
+        if capacity is None:
+            n = nn_count_neighbors(self.sys, self.rc + self.skin, self.ws)
+            capacity = int(n * capacity_margin) + 64
+        self.capacity = int(capacity)
+        z = lambda n, dt: torch.zeros(n, dtype=dt, device=self.dev)
+        self.offsets = z(self.N + 1, torch.int64)
+        self.nbr = z(self.capacity, torch.int32)
+        self.shift = z((self.capacity, 4), torch.int8)
+        self.rev = z(self.capacity, torch.int32)
+        self.ref_pos = z((self.N, 3), torch.float64)
+        self.meta = z(8, torch.int64)
+        self.nl = nn_nlist(self.capacity, self.offsets.data_ptr(), self.nbr.data_ptr(), self.shift.data_ptr(),
+                           self.rev.data_ptr(), self.ref_pos.data_ptr(), self.meta.data_ptr(), 0.0)
+        ws = nn_workspace_size(self.N, self.B, self.capacity, self.params,
+                               self.dmodel.struct if self.dmodel else None, flags, 0)
+        self.ws = torch.empty(ws, dtype=torch.uint8, device=self.dev)
+        self.E_struct = z(self.B, torch.float64)
+        self.E_atom = z(self.N, torch.float32)
+        self.F = z((self.N, 3), torch.float32)
+        self.G = None
+
+    def set_positions(self, pos):
+        self.pos.copy_(self.torch.as_tensor(pos, dtype=self.torch.float64))
+
+    def build_neighbors(self, check: bool = True):
+        nn_build_neighbors(self.sys, self.rc, self.skin, self.nl, self.ws)
+        if check:
+            nn_check(self.nl)
+
+    def descriptors(self):
+        if self.G is None:
+            self.G = self.torch.zeros((self.N, self.D), dtype=self.torch.float32, device=self.dev)
+        nn_descriptors(self.sys, self.nl, self.params, self.G, None, self.ws)
+        return self.G
+
+    def energy_forces(self, flags: Optional[int] = None, forces: bool = True, mem_budget: int = 0):
+        f = self.flags if flags is None else flags
+        nn_energy_forces(self.sys, self.nl, self.params, self.dmodel.struct, f, mem_budget, self.E_struct,
+                         self.E_atom, self.F if forces else None, self.ws)
+        return self.E_struct, self.E_atom, self.F
+
+    def neighbor_list_host(self):
+        """(offsets, nbr, shift[:, :3]) copied to the host (after a sync)."""
+        self.torch.cuda.synchronize()
+        off = self.offsets.cpu().numpy()
+        nnz = int(off[-1])
+        return {"offsets": off, "nbr": self.nbr[:nnz].cpu().numpy(),
+                "shift": self.shift[:nnz, :3].cpu().numpy().astype(np.int32), "rev": self.rev[:nnz].cpu().numpy()}

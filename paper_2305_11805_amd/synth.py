@@ -276,7 +276,7 @@ def single(pos, species, cell=None, pbc=(0, 0, 0)) -> System:
 def concat(systems: Sequence[System]) -> System:
     ptr = [0]
     for s in systems:
-        ptr += list(ptr[-1] + np.diff(s.atom_ptr))
+        ptr += list(ptr[-1] + np.cumsum(np.diff(s.atom_ptr)))
     return System(np.concatenate([s.pos for s in systems]), np.concatenate([s.species for s in systems]),
                   np.asarray(ptr, np.int64), np.concatenate([s.cell for s in systems]),
                   np.concatenate([s.pbc for s in systems]))

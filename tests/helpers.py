@@ -1,0 +1,53 @@
+"""Shared helpers of the GPU parity tests (comparison rules and oracle glue)."""
+import numpy as np
+
+import oracle
+from paper_2305_11805_amd import synth
+
+# Tolerances stated for the method (energies per atom, forces per component).
+E_TOL = 1e-4   # eV/atom
+F_TOL = 1e-3   # eV/A
+G_REL = 1e-5   # descriptors, relative, with a floor of 1e-6 of the row maximum
+
+
+def descriptor_errors(G_gpu, G_ref):
+    """Max of |dG| / (1e-5 max(|G_ref|, 1e-6 max_row |G_ref|)) -> pass if <= 1."""
+    G_gpu = np.asarray(G_gpu, np.float64)
+    row_max = np.max(np.abs(G_ref), axis=1, keepdims=True)
+    floor = np.maximum(np.abs(G_ref), 1e-6 * row_max)
+    ratio = np.abs(G_gpu - G_ref) / (G_REL * np.maximum(floor, 1e-300))
+    return float(ratio.max()) if ratio.size else 0.0
+
+
+def list_rows_equal(gpu, ref, rows=None):
+    """Rows of a GPU list (all rows) equal the oracle's rows exactly."""
+    off_g, off_r = gpu["offsets"], ref["offsets"]
+    rows = range(len(off_r) - 1) if rows is None else rows
+    for k, i in enumerate(rows):
+        a0, a1 = off_g[i], off_g[i + 1]
+        b0, b1 = off_r[k], off_r[k + 1]
+        if a1 - a0 != b1 - b0:
+            return False, f"row {i}: {a1 - a0} vs {b1 - b0} entries"
+        if not np.array_equal(gpu["nbr"][a0:a1], ref["nbr"][b0:b1]):
+            return False, f"row {i}: neighbors differ"
+        if not np.array_equal(gpu["shift"][a0:a1], ref["shift"][b0:b1]):
+            return False, f"row {i}: shifts differ"
+    return True, ""
+
+
+def oracle_full(w, rows_cells=True):
+    """Oracle E_struct, E_atom, F of a whole workload (small sizes)."""
+    s = w.system
+    nl = oracle.neighbors_cells(s, w.params.rc) if rows_cells else oracle.neighbors_brute(s, w.params.rc)
+    return oracle.energy_forces(w.params, w.model, s, nl)
+
+
+def oracle_sampled_forces(w, targets):
+    """Oracle forces on `targets` and energies of their rows, at any size."""
+    s, p = w.system, w.params
+    own = oracle.neighbors_cells(s, p.rc, rows=np.asarray(targets, np.int64))
+    rows = set(int(t) for t in targets) | set(own["nbr"].tolist())
+    rows = np.array(sorted(rows), np.int64)
+    nl = oracle.neighbors_cells(s, p.rc, rows=rows)
+    E_rows, F = oracle.forces(p, w.model, s, nl, np.asarray(targets, np.int64))
+    return rows, E_rows, F

@@ -1,0 +1,157 @@
+"""HIP path vs the FP64 oracle, element by element, on seeded workloads.
+
+Neighbor lists must be identical (same rows, same order, same image
+shifts); descriptors within 1e-5 relative (floor 1e-6 of the row maximum);
+energies within 1e-4 eV/atom and forces within 1e-3 eV/A, in FP32 and in
+BF16-MLP mode.  Sizes span several tiles and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11805_amd import nnpot, synth
+
+from helpers import E_TOL, F_TOL, descriptor_errors, list_rows_equal
+
+pytestmark = pytest.mark.gpu
+
+
+def small_periodic_batch():
+    rng = np.random.Generator(np.random.PCG64(77))
+    p = synth.mbp_params(2, 4.0, 16, 8, 4)
+    systems = []
+    for L, n, tric in [(3.3, 6, True), (5.0, 14, False), (7.5, 40, True)]:
+        cell = np.array([[L, 0, 0], [0.5, L * 0.97, 0], [-0.3, 0.6, L * 1.04]]) if tric else np.eye(3) * L
+        frac = rng.uniform(0, 1, (n, 3))
+        pos = frac @ cell + rng.integers(-1, 2, (n, 3)) @ cell  # unwrapped by whole cells
+        systems.append(synth.single(pos, rng.integers(0, 2, n), cell=cell, pbc=(1, 1, 1)))
+    cl = synth.clusters_system(rng, [9, 1, 23], lambda n: 5.0, 0.9, 2)
+    sys = synth.concat(systems + [cl])
+    model = synth.random_model(2, p.dim, [64, 32], 5, in_scale=3.0)
+    return synth.Workload("small periodic cells + clusters", sys, p, model, 77)
+
+
+CASES = {
+    "cfg0": lambda: synth.config(0),
+    "cfg1": lambda: synth.config(1),
+    "cfg2s": lambda: synth.config(2, scale=0.05),
+    "cfg3s": lambda: synth.config(3, scale=0.1),
+    "cfg4s": lambda: synth.config(4, scale=1 / 64),
+    "smallcells": small_periodic_batch,
+}
+
+_cache = {}
+
+
+def workload(name):
+    if name not in _cache:
+        w = CASES[name]()
+        nl = oracle.neighbors_cells(w.system, w.params.rc)
+        _cache[name] = (w, nl)
+    return _cache[name]
+
+
+def oracle_eval(name):
+    key = name + ":ef"
+    if key not in _cache:
+        w, nl = workload(name)
+        G = oracle.descriptors(w.params, w.system, nl)
+        Es, Ea, F = oracle.energy_forces(w.params, w.model, w.system, nl)
+        _cache[key] = (G, Es, Ea, F)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_neighbor_list_identical(name):
+    w, ref = workload(name)
+    print(f"[neighbors] {name}: {w.name}", flush=True)
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    got = pot.neighbor_list_host()
+    assert np.array_equal(got["offsets"], ref["offsets"])
+    ok, msg = list_rows_equal(got, ref)
+    assert ok, msg
+    # reverse index: rev(e) is the entry (j -> i, -n)
+    off = got["offsets"]
+    row_of = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    rev = got["rev"]
+    assert np.array_equal(got["nbr"][rev], row_of)
+    assert np.array_equal(got["shift"][rev], -got["shift"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_descriptors_match_oracle(name):
+    w, nl = workload(name)
+    print(f"[descriptors] {name}", flush=True)
+    G_ref = oracle_eval(name)[0]
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    G = pot.descriptors().cpu().numpy()
+    nnpot.nn_check(pot.nl)
+    err = descriptor_errors(G, G_ref)
+    print(f"  max |dG| / tol = {err:.3f}", flush=True)
+    assert err <= 1.0
+
+
+def run_energy_forces(name, flags):
+    w, nl = workload(name)
+    _, Es_ref, Ea_ref, F_ref = oracle_eval(name)
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    Es, Ea, F = pot.energy_forces(flags=flags)
+    nnpot.nn_check(pot.nl)
+    Es, Ea, F = Es.cpu().numpy(), Ea.cpu().numpy(), F.cpu().numpy()
+    n_c = np.diff(w.system.atom_ptr)
+    err = {"e_atom_struct": np.max(np.abs(Es - Es_ref) / np.maximum(n_c, 1)),
+           "e_atom": np.max(np.abs(Ea - Ea_ref)), "f_max": np.max(np.abs(F - F_ref)),
+           "f_rms": np.sqrt(np.mean((F - F_ref) ** 2)), "f_scale": np.abs(F_ref).max(),
+           "e_scale": np.abs(Ea_ref).max()}
+    print("  " + "  ".join(f"{k} {v:.2e}" for k, v in err.items()), flush=True)
+    return err
+
+
+# FP32 MFMA, and BF16 MFMA with split (hi + lo) operands: the stated
+# tolerances, 1e-4 eV/atom and 1e-3 eV/A.
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_forces_match_oracle(name, mode):
+    print(f"[energy/forces] {name} {mode}", flush=True)
+    err = run_energy_forces(name, {"fp32": 0, "bf16x3": nnpot.NN_BF16X3_MLP}[mode])
+    assert err["e_atom_struct"] <= E_TOL
+    assert err["f_max"] <= F_TOL
+
+
+# Plain BF16 operands (unit roundoff u = 2^-9 on G, weights, activations and
+# deltas): errors scale with u times the magnitudes; bound 16 u of the
+# largest atomic energy / force component.
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_forces_plain_bf16_within_rounding_bound(name):
+    print(f"[energy/forces] {name} bf16", flush=True)
+    err = run_energy_forces(name, nnpot.NN_BF16_MLP)
+    u = 2.0 ** -9
+    assert err["e_atom"] <= 16 * u * max(1.0, err["e_scale"])
+    assert err["f_max"] <= 16 * u * max(1.0, err["f_scale"])
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg3s"])
+def test_bitwise_deterministic(name):
+    w, _ = workload(name)
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    outs = []
+    for _ in range(3):
+        pot.build_neighbors()
+        Es, Ea, F = pot.energy_forces()
+        outs.append((Es.cpu().numpy().copy(), Ea.cpu().numpy().copy(), F.cpu().numpy().copy(),
+                     pot.descriptors().cpu().numpy().copy()))
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_force_sum_vanishes_periodic():
+    w, _ = workload("cfg1")
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    _, _, F = pot.energy_forces()
+    F = F.double().cpu().numpy()
+    assert np.abs(F.sum(0)).max() < 1e-6 * np.abs(F).max() * F.shape[0]
