@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Energy + force throughput of the mBP / per-species MLP path on one MI355X.
+
+One step = one pass of the whole path over the resident input: neighbor-list
+build (cell binning, FP64 inclusion test, row sort, reverse index), species
+grouping, radial + angular descriptors, per-species MLP forward + backward,
+FP64 per-structure energies, descriptor adjoint and force gather.  Inputs are
+synthetic (seeded RSA bulk cell: 4096 atoms, rho = 0.1 A^-3, Rc = 5 A,
+32 radial + 8x8 angular bins, MLP 96-128-128-1) and sit in HBM before the
+timed region.
+
+Prints one JSON line: atoms/s, the roofline position of the dominant kernel
+(timed live with HIP events on the stream it runs on) and the FP64 oracle's
+own throughput on the host cores over a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
+PEAK_HBM_GBS = 8000.0
+METRIC = "energy+force atoms/sec at stated force error vs FP64 oracle; HBM GB/s"
+
+
+def ipow_mults(e: int) -> int:
+    """Multiplications of binary exponentiation x^e (squarings + extra products)."""
+    return (e.bit_length() - 1) + (bin(e).count("1") - 1) if e > 0 else 0
+
+
+def flop_model(p, n_valid):
+    """Algorithmic FP32 work of the two descriptor kernels (FMA = 2 flops,
+    each exp2 / sqrt / reciprocal = 1): per (pair, radial bin), per triplet
+    (separable angular form) and per pair."""
+    NT, NR = p.n_theta, p.n_rs_ang
+    z = int(p.zeta)
+    P = float(np.sum(n_valid))
+    T = float(np.sum(n_valid * (n_valid - 1) / 2))
+    geom = 33
+    fwd_trip = geom + 4 * NT + NT * ipow_mults(z) + 7 * NR + 2 * NT * NR
+    adj_trip = geom + 4 * NT + NT * ipow_mults(z - 1) + NT + 6 * NR + 4 * NT * NR + 5 * NR + 5 * NT + 35
+    fwd = T * fwd_trip + P * p.n_rad * 8
+    adj = T * adj_trip + P * (p.n_rad * 12 + 6)
+    return {"pairs": P, "triplets": T, "desc_fwd": fwd, "desc_adj": adj,
+            "per_triplet": {"desc_fwd": fwd_trip, "desc_adj": adj_trip}}
+
+
+def valid_neighbor_counts(pot, rc):
+    nl = pot.neighbor_list_host()
+    pos = pot.pos.cpu().numpy()
+    cell = pot.cell.cpu().numpy().reshape(-1, 3, 3)
+    ptr = pot.atom_ptr.cpu().numpy()
+    off = nl["offsets"]
+    rows = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    struct = np.searchsorted(ptr, rows, side="right") - 1
+    d = pos[nl["nbr"]] - pos[rows] + np.einsum("ek,ekl->el", nl["shift"].astype(np.float64), cell[struct])
+    valid = np.sum(d * d, axis=1) < rc * rc
+    return np.bincount(rows[valid], minlength=len(off) - 1)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2305_11805_amd", "csrc", "descriptors.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The FP64 oracle as it stands, on the host cores: per-atom energy and
+    per-pair gradients (all of the E + F work) for a bounded sample of rows."""
+    import oracle
+    oracle.build(force=False)
+    s, p = w.system, w.params
+    n = 64
+    rows = np.arange(min(n, s.n_atoms))
+    t0 = time.perf_counter()
+    nl = oracle.neighbors_cells(s, p.rc, rows=rows)
+    oracle.atom_energies(p, w.model, s, nl, pair_grads=True)
+    dt = time.perf_counter() - t0
+    n2 = int(min(s.n_atoms, max(n, n * target_s / max(dt, 1e-3))))
+    rows = np.arange(n2)
+    t0 = time.perf_counter()
+    nl = oracle.neighbors_cells(s, p.rc, rows=rows)
+    oracle.atom_energies(p, w.model, s, nl, pair_grads=True)
+    dt = time.perf_counter() - t0
+    return {"value": n2 / dt, "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"E + per-pair dE/dd of the first {n2} of {s.n_atoms} atoms (FP64, OpenMP over atoms), "
+                      f"{dt:.1f} s"}
+
+
+def sampled_force_error(w, F, n=16, seed=0):
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.sort(rng.choice(w.system.n_atoms, size=min(n, w.system.n_atoms), replace=False))
+    own = oracle.neighbors_cells(w.system, w.params.rc, rows=t)
+    rows = np.array(sorted(set(t.tolist()) | set(own["nbr"].tolist())), np.int64)
+    nl = oracle.neighbors_cells(w.system, w.params.rc, rows=rows)
+    _, F_ref = oracle.forces(w.params, w.model, w.system, nl, t)
+    return float(np.max(np.abs(F[t] - F_ref)))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1, help="workload index 0-4 (default: 1)")
+    ap.add_argument("--mode", choices=["fp32", "bf16", "bf16x3"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2305_11805_amd import nnpot, synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    w = synth.config(args.config)
+    s, p = w.system, w.params
+    flags = {"fp32": 0, "bf16": nnpot.NN_BF16_MLP, "bf16x3": nnpot.NN_BF16X3_MLP}[args.mode]
+    skin = float(w.extra.get("skin", 0.0))
+    pot = nnpot.Potential(s, p, w.model, skin=skin, flags=flags)
+
+    def step():
+        nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+        nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, flags, 0, pot.E_struct,
+                               pot.E_atom, pot.F, pot.ws)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    nnpot.nn_check(pot.nl)
+
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nnpot.nn_timing(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    stages = nnpot.nn_timing_read()
+    nnpot.nn_timing(False)
+    nnpot.nn_check(pot.nl)
+
+    if args.calib_copy_mib > 0:
+        a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    ms_per_step = total_ms / args.steps
+    value = s.n_atoms * args.steps / (total_ms / 1e3)
+    n_valid = valid_neighbor_counts(pot, p.rc)
+    fm = flop_model(p, n_valid)
+    single_kernel = ["desc_adj", "desc_fwd", "mlp", "force_gather", "energy"]
+    dom = max(single_kernel, key=lambda k: stages[k][0])
+    dom_ms = stages[dom][0] / max(stages[dom][1], 1)
+    F = pot.F.cpu().numpy()
+    if dom in ("desc_adj", "desc_fwd"):
+        achieved = fm[dom] / (dom_ms / 1e3) / 1e12
+        roof = {"kernel": {"desc_adj": "k_desc_adj", "desc_fwd": "k_desc_fwd"}[dom], "bound": "alu",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(dom_ms, 5), "algorithmic_flops_per_launch": fm[dom],
+                "flops_per_triplet": fm["per_triplet"][dom]}
+    else:
+        roof = {"kernel": dom, "bound": "mfma", "achieved": None, "peak": None, "unit": None, "frac": None,
+                "traffic": None, "avg_launch_ms": round(dom_ms, 5)}
+    prof = os.path.join(ROOT, "profiles", "counters.json")
+    if os.path.exists(prof):
+        with open(prof) as f:
+            cnt = json.load(f)
+        key = f"{roof['kernel']}:{w.name}"
+        if key in cnt and cnt[key].get("source_hash") == source_hash():
+            roof["traffic"] = cnt[key]["hbm_bytes_per_launch"]
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16-mlp/f32",
+                                                        "bf16x3": "bf16x3-mlp/f32"}[args.mode],
+        "data": "synthetic (seeded RSA positions, seeded N(0, 1/fan_in) weights)",
+        "config": {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
+                   "neighbor_build_each_step": True, "seed": w.seed},
+        "roofline": roof,
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
+        "pairs_per_step": fm["pairs"], "triplets_per_step": fm["triplets"],
+        "force_err_max_sampled_eV_per_A": sampled_force_error(w, F),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

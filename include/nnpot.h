@@ -247,6 +247,28 @@ nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info);
 /* Message for the last non-NN_OK status returned on this thread. */
 const char* nn_last_error(void);
 
+/*
+ * Stage timing (a tracing aid, off by default).  While enabled, every stage
+ * the calls above enqueue is bracketed by two HIP events recorded on the
+ * caller's stream (do not enable it while capturing a graph).
+ * nn_timing_read synchronizes those events and returns, per stage, the
+ * summed elapsed milliseconds and the number of launches since the last
+ * nn_timing(1); both arrays [host] have NN_STAGE_COUNT entries.
+ */
+enum {
+  NN_STAGE_NEIGHBORS = 0,   /* skin test + list (re)build                   */
+  NN_STAGE_SPECIES = 1,     /* grouping of atoms by species                  */
+  NN_STAGE_WEIGHTS = 2,     /* BF16 weight copies                            */
+  NN_STAGE_DESC_FWD = 3,    /* radial + angular descriptors                  */
+  NN_STAGE_MLP = 4,         /* per-species MLP forward + backward            */
+  NN_STAGE_ENERGY = 5,      /* per-structure FP64 energy                     */
+  NN_STAGE_DESC_ADJ = 6,    /* descriptor adjoint: per-pair gradients        */
+  NN_STAGE_FORCE_GATHER = 7,/* per-atom forces from per-pair gradients       */
+  NN_STAGE_COUNT = 8
+};
+nn_status nn_timing(int32_t enable);
+nn_status nn_timing_read(double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -31,6 +33,50 @@ static nn_status check_launch(const char* what) {
   if (e != hipSuccess) return fail(NN_E_HIP, "%s: %s", what, hipGetErrorString(e));
   return NN_OK;
 }
+
+// ---------------------------------------------------------------------------
+// stage timing with HIP events
+// ---------------------------------------------------------------------------
+
+struct TimedLaunch {
+  int stage;
+  hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimedLaunch> g_tl;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches of one stage on stream s when timing is on.
+struct StageTimer {
+  int stage;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(int st, hipStream_t st_s) : stage(st), s(st_s) {
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (!g_timing) return;
+    a = take_event();
+    b = take_event();
+    if (a && b) (void)hipEventRecord(a, s);
+  }
+  ~StageTimer() {
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (!(a && b)) return;
+    (void)hipEventRecord(b, s);
+    g_tl.push_back({stage, a, b});
+  }
+};
 
 // ---------------------------------------------------------------------------
 // workspace layout
@@ -303,7 +349,10 @@ nn_status nn_build_neighbors(const nn_system* sys, double rc, double skin, nn_nl
   L = carve(ws, sys->n_atoms, sys->n_structs, nl->capacity, 0, 1, nullptr);
   hipStream_t s = (hipStream_t)stream;
   NbLaunch nb = nb_launch(sys, L, rc + skin, nl, false);
-  launch_neighbors(nb, skin > 0.0, skin, false, s);
+  {
+    StageTimer t(NN_STAGE_NEIGHBORS, s);
+    launch_neighbors(nb, skin > 0.0, skin, false, s);
+  }
   nl->radius = rc + skin;
   return check_launch("nn_build_neighbors");
 }
@@ -321,7 +370,10 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   (void)ws;
   (void)ws_bytes;
   hipStream_t s = (hipStream_t)stream;
-  launch_desc_fwd(*sys, *nl, P, G, s);
+  {
+    StageTimer t(NN_STAGE_DESC_FWD, s);
+    launch_desc_fwd(*sys, *nl, P, G, s);
+  }
   return check_launch("nn_descriptors");
 }
 
@@ -352,7 +404,10 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     return check_launch("nn_energy_forces");
   }
   // species grouping
-  launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+  {
+    StageTimer t(NN_STAGE_SPECIES, s);
+    launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+  }
   // model as seen by the kernels
   MlpArgs a{};
   a.model.S = P.S;
@@ -388,9 +443,15 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
       }
     }
   }
-  if (bf16) launch_convert_bf16(job, s);
+  if (bf16) {
+    StageTimer t(NN_STAGE_WEIGHTS, s);
+    launch_convert_bf16(job, s);
+  }
   // descriptors
-  launch_desc_fwd(*sys, *nl, P, L.G, s);
+  {
+    StageTimer t(NN_STAGE_DESC_FWD, s);
+    launch_desc_fwd(*sys, *nl, P, L.G, s);
+  }
   // MLP energies and lambda
   a.G = L.G;
   a.perm = L.perm;
@@ -398,10 +459,20 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   a.E_atom = E_atom ? E_atom : L.E_atom;
   a.lambda = F ? L.lam : nullptr;
   a.D = P.D;
-  launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
-  launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+  {
+    StageTimer t(NN_STAGE_MLP, s);
+    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
+  }
+  {
+    StageTimer t(NN_STAGE_ENERGY, s);
+    launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+  }
   if (F) {
-    launch_desc_adj(*sys, *nl, P, L.lam, L.pg, s);
+    {
+      StageTimer t(NN_STAGE_DESC_ADJ, s);
+      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, s);
+    }
+    StageTimer t(NN_STAGE_FORCE_GATHER, s);
     launch_force_gather(*sys, *nl, L.pg, F, s);
   }
   return check_launch("nn_energy_forces");
@@ -453,5 +524,34 @@ nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {
 }
 
 const char* nn_last_error(void) { return g_err; }
+
+nn_status nn_timing(int32_t enable) {
+  std::lock_guard<std::mutex> g(g_tmu);
+  for (auto& t : g_tl) {
+    (void)hipEventSynchronize(t.b);
+    g_event_pool.push_back(t.a);
+    g_event_pool.push_back(t.b);
+  }
+  g_tl.clear();
+  g_timing = enable != 0;
+  return NN_OK;
+}
+
+nn_status nn_timing_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return fail(NN_E_INVALID, "ms/launches is NULL");
+  std::lock_guard<std::mutex> g(g_tmu);
+  for (int k = 0; k < NN_STAGE_COUNT; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto& t : g_tl) {
+    if (hipEventSynchronize(t.b) != hipSuccess) return fail(NN_E_HIP, "nn_timing_read: event sync failed");
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, t.a, t.b) != hipSuccess) return fail(NN_E_HIP, "nn_timing_read: elapsed failed");
+    ms[t.stage] += e;
+    launches[t.stage] += 1;
+  }
+  return NN_OK;
+}
 
 }  // extern "C"

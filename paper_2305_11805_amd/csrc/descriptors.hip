@@ -478,22 +478,35 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
   for (int t = lane; t < n; t += kWave) pg[e0 + nb_entry(nb.f[t])] = make_float4(gx[t], gy[t], gz[t], 0.f);
 }
 
-// F_k = sum over entries e of row k of (pg[e] - pg[rev[e]]), in row order.
-__global__ void k_force_gather(int64_t N, const int64_t* __restrict__ offsets, const int32_t* __restrict__ rev,
-                               const float4* __restrict__ pg, float* __restrict__ F, const int64_t* meta) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
+// F_k = sum over entries e of row k of (pg[e] - pg[rev[e]]).  Sixteen lanes
+// per atom take the row's entries round robin; the partial sums are combined
+// by a fixed xor-shuffle tree, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ rev, const float4* __restrict__ pg,
+                                                      float* __restrict__ F, const int64_t* meta) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sub = threadIdx.x & 15;
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  const bool valid = meta[kMetaValid] == 1;
-  for (int64_t e = offsets[k]; valid && e < offsets[k + 1]; ++e) {
-    const float4 a = pg[e], b = pg[rev[e]];
-    fx += a.x - b.x;
-    fy += a.y - b.y;
-    fz += a.z - b.z;
+  if (k < N && meta[kMetaValid] == 1) {
+    const int64_t e1 = offsets[k + 1];
+    for (int64_t e = offsets[k] + sub; e < e1; e += 16) {
+      const float4 a = pg[e], b = pg[rev[e]];
+      fx += a.x - b.x;
+      fy += a.y - b.y;
+      fz += a.z - b.z;
+    }
   }
-  F[3 * k] = fx;
-  F[3 * k + 1] = fy;
-  F[3 * k + 2] = fz;
+#pragma unroll
+  for (int m = 8; m > 0; m >>= 1) {
+    fx += __shfl_xor(fx, m, 16);
+    fy += __shfl_xor(fy, m, 16);
+    fz += __shfl_xor(fz, m, 16);
+  }
+  if (sub == 0 && k < N) {
+    F[3 * k] = fx;
+    F[3 * k + 1] = fy;
+    F[3 * k + 2] = fz;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -547,7 +560,7 @@ void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& 
 
 void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, hipStream_t s) {
   if (sys.n_atoms == 0) return;
-  hipLaunchKernelGGL(k_force_gather, dim3((unsigned)((sys.n_atoms + 255) / 256)), dim3(256), 0, s, sys.n_atoms,
+  hipLaunchKernelGGL(k_force_gather, dim3((unsigned)((sys.n_atoms * 16 + 255) / 256)), dim3(256), 0, s, sys.n_atoms,
                      nl.offsets, nl.rev, pg, F, nl.meta);
 }
 

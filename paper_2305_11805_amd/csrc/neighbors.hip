@@ -337,103 +337,174 @@ __global__ void k_nb_scatter(int64_t N, const int32_t* __restrict__ atom_bin, co
   bin_atoms[bin_start[bin] + (int64_t)k] = (int32_t)i;
 }
 
-// Enumerate the candidates of atom i and apply the inclusion test; emit(j,
-// na, nb, nc) is called for every accepted entry.  Returns false if an
-// image index does not fit in int8.
-template <typename Emit>
-__device__ bool enumerate_row(int64_t i, const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
-                              const uint8_t* __restrict__ pbc, int32_t B, const StructGeom* __restrict__ geom,
-                              const int64_t* __restrict__ bin_start, const int32_t* __restrict__ bin_atoms,
-                              const int32_t* __restrict__ atom_bin, double r2max, Emit emit) {
+__device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc) {
+  return ((uint64_t)(uint32_t)j << 24) | ((uint64_t)(uint8_t)(na + 128) << 16) | ((uint64_t)(uint8_t)(nb + 128) << 8) |
+         (uint64_t)(uint8_t)(nc + 128);
+}
+__device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry_key(j, s.x, s.y, s.z); }
+
+// One wave per atom i enumerates its candidates, 64 at a time, and applies
+// the FP64 inclusion test; accepted entries are counted with ballots.
+//   COUNT: row_count[i] = number of entries.
+//   FILL : the entries' keys (j, n_a, n_b, n_c) are collected in LDS, sorted
+//          (bitonic) and written to the row at offsets[i].
+// Small structures: candidates are every (j, image) with |n_d| <= K_d.
+// Binned structures: the atoms of the 27 bins around i's bin, with the image
+// that the bin wrap and the whole-cell offsets of i and j imply.
+template <bool FILL>
+__global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                                                const uint8_t* __restrict__ pbc, int32_t B, int64_t N,
+                                                const StructGeom* __restrict__ geom,
+                                                const int64_t* __restrict__ bin_start,
+                                                const int32_t* __restrict__ bin_atoms,
+                                                const int32_t* __restrict__ atom_bin, double r2max,
+                                                int64_t* __restrict__ row_count, const int64_t* __restrict__ offsets,
+                                                int32_t* __restrict__ nbr, int8_t* __restrict__ shift, int64_t* meta,
+                                                const int32_t* flag) {
+  if (FILL ? !flag[1] : !flag[0]) return;
+  __shared__ uint64_t key[FILL ? kRowMax : 1];
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (i >= N) return;
+  const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+  if (!(isfinite(xi[0]) && isfinite(xi[1]) && isfinite(xi[2]))) {
+    if (!FILL && lane == 0) {
+      row_count[i] = 0;
+      atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
+    }
+    return;
+  }
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int c = struct_of(atom_ptr, B, i);
   const StructGeom& g = geom[c];
-  const double* xi = pos + 3 * i;
-  bool ok = true;
+  int count = 0;
+  bool shift_bad = false;
+  auto test = [&](bool active, int32_t j, int na, int nb, int nc) {
+    bool acc = false;
+    if (active && !(j == i && na == 0 && nb == 0 && nc == 0)) {
+      double d[3];
+      displacement64(xi, pos + 3 * (int64_t)j, g.h, na, nb, nc, d);
+      acc = norm2_64(d) < r2max;
+      if (acc && (na < -127 || na > 127 || nb < -127 || nb > 127 || nc < -127 || nc > 127)) {
+        shift_bad = true;
+        acc = false;
+      }
+    }
+    const uint64_t m = __ballot(acc);
+    if (FILL && acc) {
+      const int slot = count + __popcll(m & lt);
+      if (slot < kRowMax) key[slot] = entry_key(j, na, nb, nc);
+    }
+    count += __popcll(m);
+  };
   if (g.small) {
     const int K0 = g.nb[0], K1 = g.nb[1], K2 = g.nb[2];
-    for (int64_t j = atom_ptr[c]; j < atom_ptr[c + 1]; ++j) {
-      const double* xj = pos + 3 * j;
-      for (int na = -K0; na <= K0; ++na)
-        for (int nb = -K1; nb <= K1; ++nb)
-          for (int nc = -K2; nc <= K2; ++nc) {
-            if (j == i && na == 0 && nb == 0 && nc == 0) continue;
-            double d[3];
-            displacement64(xi, xj, g.h, na, nb, nc, d);
-            if (norm2_64(d) < r2max) emit((int32_t)j, na, nb, nc);
-          }
+    const int w1 = 2 * K1 + 1, w2 = 2 * K2 + 1;
+    const int64_t nimg = (int64_t)(2 * K0 + 1) * w1 * w2;
+    const int64_t a0 = atom_ptr[c];
+    const int64_t total = (atom_ptr[c + 1] - a0) * nimg;
+    for (int64_t t0 = 0; t0 < total; t0 += kWave) {
+      const int64_t t = t0 + lane;
+      const bool active = t < total;
+      const int64_t jj = active ? t / nimg : 0;
+      int im = active ? (int)(t - jj * nimg) : 0;
+      const int nc = im % w2 - K2;
+      im /= w2;
+      const int nb = im % w1 - K1;
+      const int na = im / w1 - K0;
+      test(active, (int32_t)(a0 + jj), na, nb, nc);
     }
-    return ok;
-  }
-  const uint8_t* p3 = pbc + 3 * c;
-  int bi[3], mi[3];
-  {
-    int32_t bin = atom_bin[4 * i];
-    int64_t local = bin - g.bin_base;
-    bi[2] = (int)(local % g.nb[2]);
-    local /= g.nb[2];
-    bi[1] = (int)(local % g.nb[1]);
-    bi[0] = (int)(local / g.nb[1]);
-    mi[0] = atom_bin[4 * i + 1];
-    mi[1] = atom_bin[4 * i + 2];
-    mi[2] = atom_bin[4 * i + 3];
-  }
-  for (int da = -1; da <= 1; ++da)
-    for (int db = -1; db <= 1; ++db)
-      for (int dc = -1; dc <= 1; ++dc) {
-        int dd[3] = {da, db, dc}, bb[3], wr[3];
-        bool skip = false;
-        for (int d = 0; d < 3; ++d) {
-          int k = bi[d] + dd[d];
-          wr[d] = 0;
-          if (k < 0 || k >= g.nb[d]) {
-            if (!p3[d]) {
-              skip = true;
-              break;
+  } else {
+    const uint8_t* p3 = pbc + 3 * c;
+    int bi[3], mi[3];
+    {
+      const int64_t bin = atom_bin[4 * i];
+      int64_t local = bin - g.bin_base;
+      bi[2] = (int)(local % g.nb[2]);
+      local /= g.nb[2];
+      bi[1] = (int)(local % g.nb[1]);
+      bi[0] = (int)(local / g.nb[1]);
+      mi[0] = atom_bin[4 * i + 1];
+      mi[1] = atom_bin[4 * i + 2];
+      mi[2] = atom_bin[4 * i + 3];
+    }
+    for (int da = -1; da <= 1; ++da)
+      for (int db = -1; db <= 1; ++db)
+        for (int dc = -1; dc <= 1; ++dc) {
+          const int dd[3] = {da, db, dc};
+          int bb[3], wr[3];
+          bool skip = false;
+          for (int d = 0; d < 3; ++d) {
+            int k = bi[d] + dd[d];
+            wr[d] = 0;
+            if (k < 0 || k >= g.nb[d]) {
+              if (!p3[d]) {
+                skip = true;
+                break;
+              }
+              wr[d] = k < 0 ? -1 : 1;
+              k -= wr[d] * g.nb[d];
             }
-            wr[d] = k < 0 ? -1 : 1;
-            k -= wr[d] * g.nb[d];
+            bb[d] = k;
           }
-          bb[d] = k;
+          if (skip) continue;
+          const int64_t bin = g.bin_base + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
+          const int64_t b0 = bin_start[bin], b1 = bin_start[bin + 1];
+          for (int64_t t0 = b0; t0 < b1; t0 += kWave) {
+            const int64_t t = t0 + lane;
+            const bool active = t < b1;
+            const int32_t j = active ? bin_atoms[t] : 0;
+            int n[3] = {0, 0, 0};
+            if (active)
+              for (int d = 0; d < 3; ++d) n[d] = p3[d] ? wr[d] + mi[d] - atom_bin[4 * (int64_t)j + 1 + d] : 0;
+            test(active, j, n[0], n[1], n[2]);
+          }
         }
-        if (skip) continue;
-        int64_t bin = g.bin_base + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
-        for (int64_t t = bin_start[bin]; t < bin_start[bin + 1]; ++t) {
-          int32_t j = bin_atoms[t];
-          int n[3];
-          for (int d = 0; d < 3; ++d) n[d] = p3[d] ? wr[d] + mi[d] - atom_bin[4 * j + 1 + d] : 0;
-          if (j == i && n[0] == 0 && n[1] == 0 && n[2] == 0) continue;
-          double dv[3];
-          displacement64(xi, pos + 3 * (int64_t)j, g.h, n[0], n[1], n[2], dv);
-          if (norm2_64(dv) < r2max) {
-            if (n[0] < -127 || n[0] > 127 || n[1] < -127 || n[1] > 127 || n[2] < -127 || n[2] > 127) ok = false;
-            emit(j, n[0], n[1], n[2]);
+  }
+  if (!FILL) {
+    if (lane == 0) {
+      row_count[i] = count;
+      if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+      atomicMax((unsigned long long*)&meta[kMetaMaxRow], (unsigned long long)count);
+    }
+    if (__any(shift_bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
+    return;
+  }
+  // FILL: sort the row's keys and write it out
+  const int len = count;
+  if (len > kRowMax) return;  // flagged by the counting pass; the fill does not run then
+  int P = 1;
+  while (P < len) P <<= 1;
+  for (int t = len + lane; t < P; t += kWave) key[t] = ~0ull;
+  __syncthreads();
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int jj = k >> 1; jj > 0; jj >>= 1) {
+      for (int t = lane; t < P; t += kWave) {
+        const int partner = t ^ jj;
+        if (partner > t) {
+          const uint64_t a = key[t], b = key[partner];
+          if ((a > b) == ((t & k) == 0)) {
+            key[t] = b;
+            key[partner] = a;
           }
         }
       }
-  return ok;
-}
-
-__global__ void k_nb_count(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
-                           const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
-                           const int64_t* __restrict__ bin_start, const int32_t* __restrict__ bin_atoms,
-                           const int32_t* __restrict__ atom_bin, double r2max, int64_t* __restrict__ row_count,
-                           int64_t* meta, const int32_t* flag) {
-  if (!*flag) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double* x = pos + 3 * i;
-  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
-    row_count[i] = 0;
-    atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
-    return;
+      __syncthreads();
+    }
   }
-  int64_t cnt = 0;
-  bool ok = enumerate_row(i, pos, atom_ptr, pbc, B, geom, bin_start, bin_atoms, atom_bin, r2max,
-                          [&](int32_t, int, int, int) { ++cnt; });
-  if (!ok) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
-  if (cnt > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
-  atomicMax((unsigned long long*)&meta[kMetaMaxRow], (unsigned long long)cnt);
-  row_count[i] = cnt;
+  const int64_t e0 = offsets[i];
+  const int64_t room = offsets[i + 1] - e0;
+  char4* sh4 = reinterpret_cast<char4*>(shift);
+  for (int t = lane; t < len && t < room; t += kWave) {
+    const uint64_t k = key[t];
+    nbr[e0 + t] = (int32_t)(k >> 24);
+    char4 sv;
+    sv.x = (signed char)((int)((k >> 16) & 255) - 128);
+    sv.y = (signed char)((int)((k >> 8) & 255) - 128);
+    sv.z = (signed char)((int)(k & 255) - 128);
+    sv.w = 0;
+    sh4[e0 + t] = sv;
+  }
 }
 
 // After the scan of row counts: record nnz, check the capacity, and decide
@@ -453,83 +524,6 @@ __global__ void k_nb_capacity(const int64_t* offsets, int64_t N, int64_t capacit
     flag[1] = 0;
   } else {
     flag[1] = 1;
-  }
-}
-
-__global__ void k_nb_fill(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
-                          const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
-                          const int64_t* __restrict__ bin_start, const int32_t* __restrict__ bin_atoms,
-                          const int32_t* __restrict__ atom_bin, double r2max, const int64_t* __restrict__ offsets,
-                          int32_t* __restrict__ nbr, int8_t* __restrict__ shift, const int32_t* flag) {
-  if (!flag[1]) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double* x = pos + 3 * i;
-  if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) return;
-  int64_t out = offsets[i];
-  const int64_t end = offsets[i + 1];
-  enumerate_row(i, pos, atom_ptr, pbc, B, geom, bin_start, bin_atoms, atom_bin, r2max,
-                [&](int32_t j, int na, int nb, int nc) {
-                  if (out < end) {
-                    nbr[out] = j;
-                    char4 s;
-                    s.x = (signed char)na;
-                    s.y = (signed char)nb;
-                    s.z = (signed char)nc;
-                    s.w = 0;
-                    reinterpret_cast<char4*>(shift)[out] = s;
-                  }
-                  ++out;
-                });
-}
-
-__device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) {
-  return ((uint64_t)(uint32_t)j << 24) | ((uint64_t)(uint8_t)(s.x + 128) << 16) |
-         ((uint64_t)(uint8_t)(s.y + 128) << 8) | (uint64_t)(uint8_t)(s.z + 128);
-}
-
-// Sort each row by (j, n_a, n_b, n_c): one 64-thread block per row, bitonic
-// sort in LDS (rows up to kRowMax entries).
-__global__ void __launch_bounds__(64) k_nb_sort_rows(int64_t N, const int64_t* __restrict__ offsets,
-                                                     int32_t* __restrict__ nbr, int8_t* __restrict__ shift,
-                                                     const int32_t* flag) {
-  if (!flag[1]) return;
-  __shared__ uint64_t key[kRowMax];
-  const int64_t i = blockIdx.x;
-  if (i >= N) return;
-  const int64_t e0 = offsets[i];
-  const int len = (int)(offsets[i + 1] - e0);
-  if (len <= 1 || len > kRowMax) return;
-  int P = 1;
-  while (P < len) P <<= 1;
-  char4* sh4 = reinterpret_cast<char4*>(shift);
-  for (int t = threadIdx.x; t < P; t += 64) key[t] = t < len ? entry_key(nbr[e0 + t], sh4[e0 + t]) : ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = threadIdx.x; t < P; t += 64) {
-        int partner = t ^ jj;
-        if (partner > t) {
-          uint64_t a = key[t], b = key[partner];
-          bool up = (t & k) == 0;
-          if ((a > b) == up) {
-            key[t] = b;
-            key[partner] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int t = threadIdx.x; t < len; t += 64) {
-    uint64_t k = key[t];
-    nbr[e0 + t] = (int32_t)(k >> 24);
-    char4 s;
-    s.x = (signed char)((int)((k >> 16) & 255) - 128);
-    s.y = (signed char)((int)((k >> 8) & 255) - 128);
-    s.z = (signed char)((int)(k & 255) - 128);
-    s.w = 0;
-    sh4[e0 + t] = s;
   }
 }
 
@@ -612,17 +606,18 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   if (N > 0) {
     hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, L.atom_bin, L.bin_start, L.bin_fill, L.bin_atoms,
                        L.flag);
-    hipLaunchKernelGGL(k_nb_count, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                       L.bin_start, L.bin_atoms, L.atom_bin, r2, L.counts, L.meta, L.flag);
+    hipLaunchKernelGGL(k_nb_rows<false>, dim3((unsigned)N), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N,
+                       L.geom, L.bin_start, L.bin_atoms, L.atom_bin, r2, L.counts, (const int64_t*)nullptr,
+                       (int32_t*)nullptr, (int8_t*)nullptr, L.meta, L.flag);
   }
   exclusive_scan_i64(L.counts, L.offsets, N, L.scan_tmp, s, L.flag);
   hipLaunchKernelGGL(k_nb_capacity, dim3(1), dim3(1), 0, s, L.offsets, N,
                      count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag);
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  hipLaunchKernelGGL(k_nb_fill, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                     L.bin_start, L.bin_atoms, L.atom_bin, r2, nl->offsets, nl->nbr, nl->shift, L.flag);
-  hipLaunchKernelGGL(k_nb_sort_rows, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, L.flag);
+  hipLaunchKernelGGL(k_nb_rows<true>, dim3((unsigned)N), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N,
+                     L.geom, L.bin_start, L.bin_atoms, L.atom_bin, r2, (int64_t*)nullptr, nl->offsets, nl->nbr,
+                     nl->shift, L.meta, L.flag);
   hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev, L.meta,
                      L.flag);
   hipLaunchKernelGGL(k_nb_finish, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, s, sys->pos, nl->ref_pos, N,

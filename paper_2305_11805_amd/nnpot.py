@@ -62,7 +62,8 @@ class nn_model(C.Structure):
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_check", "nn_last_error")
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_check", "nn_last_error", "nn_timing", "nn_timing_read")
+STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather")
 
 
 def lib():
@@ -91,6 +92,10 @@ def lib():
         L.nn_check.argtypes = [P, P, C.POINTER(I64)]
         L.nn_last_error.restype = C.c_char_p
         L.nn_last_error.argtypes = []
+        L.nn_timing.restype = I32
+        L.nn_timing.argtypes = [I32]
+        L.nn_timing_read.restype = I32
+        L.nn_timing_read.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -160,6 +165,18 @@ def nn_check(nl: nn_nlist, stream=None) -> int:
 
 def nn_last_error() -> str:
     return lib().nn_last_error().decode()
+
+
+def nn_timing(enable: bool):
+    _ok(lib().nn_timing(1 if enable else 0))
+
+
+def nn_timing_read() -> dict:
+    """{stage: (total ms, launches)} since the last nn_timing(True)."""
+    ms = (C.c_double * len(STAGES))()
+    n = (C.c_int64 * len(STAGES))()
+    _ok(lib().nn_timing_read(ms, n))
+    return {name: (ms[k], n[k]) for k, name in enumerate(STAGES)}
 
 
 # ---------------------------------------------------------------------------
