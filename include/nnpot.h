@@ -228,9 +228,13 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
  * workspace (it reuses G and lambda).
  *   dL_dpos [device] FP32 [N][3] (may be NULL): dL/dx_k = -dL_dE[c(k)] F_k;
  *            needs the F of that call.
- *   dW[s*NN_MAX_LAYERS + l], db[...] [device] FP32 (may be NULL): dL/dW^l and
- *            dL/db^l of species s, same layout as the weights, reduced over
- *            atoms in a fixed order.
+ *   dW, db [host] arrays of NN_MAX_SPECIES*NN_MAX_LAYERS device pointers
+ *            (either array may be NULL): dW[s*NN_MAX_LAYERS + l] receives
+ *            dL/dW^(l+1) of species s as FP32 in the layout of W[l], db the
+ *            same for b.  The MLP is re-run on the stored descriptors in the
+ *            same precision mode (flags) to recover dE_i/dz^l; the sums over
+ *            atoms use FP32 MFMA over fixed atom chunks reduced in chunk
+ *            order (bitwise reproducible).
  */
 nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
                                 const nn_model* model, int32_t flags, const double* dL_dE, const float* F,

@@ -107,6 +107,8 @@ struct Layout {
   int64_t *sp_cnt, *sp_off, *sp_start;
   __bf16* wb;  // BF16 weights, W then W^T per species and layer
   size_t wb_elems;
+  // weight gradient: per-atom stash, per-atom weights, chunk partials
+  float *st_a1, *st_d1, *st_a2, *st_d2, *w_atom, *partial;
   size_t bytes;
 };
 
@@ -150,6 +152,20 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
     L.sp_start = c.take<int64_t>(NN_MAX_SPECIES + 1);
     L.wb_elems = 4 * model_param_floats(model);
     L.wb = c.take<__bf16>(L.wb_elems);
+    if (model && model->n_species > 0 && model->mlp[0].n_layers == 3) {
+      const int H1 = model->mlp[0].width[1], H2 = model->mlp[0].width[2];
+      L.st_a1 = c.take<float>((size_t)N * H1);
+      L.st_d1 = c.take<float>((size_t)N * H1);
+      L.st_a2 = c.take<float>((size_t)N * H2);
+      L.st_d2 = c.take<float>((size_t)N * H2);
+      L.w_atom = c.take<float>(N);
+      ModelDev md{};
+      md.S = S;
+      md.m[0].width[0] = (int)D;
+      md.m[0].width[1] = H1;
+      md.m[0].width[2] = H2;
+      L.partial = c.take<float>(wgrad_partial_floats(N, S, md));
+    }
   }
   L.bytes = c.off + 256;
   return L;
@@ -273,6 +289,49 @@ static NbLaunch nb_launch(const nn_system* sys, const Layout& L, double radius, 
   n.meta = count_only ? L.count_meta : nl->meta;
   n.max_bins = L.max_bins;
   return n;
+}
+
+// Fill the kernels' view of the model; in BF16 modes also enqueue the BF16
+// hi/lo weight copies into the workspace.
+static void prepare_model(const nn_model* model, const DescConst& P, const Layout& L, bool bf16, MlpArgs& a,
+                          hipStream_t s) {
+  a.model.S = P.S;
+  ConvJob job{};
+  size_t wofs = 0;
+  for (int sp = 0; sp < P.S; ++sp) {
+    const nn_mlp& q = model->mlp[sp];
+    MlpDev& d = a.model.m[sp];
+    d.n_layers = q.n_layers;
+    for (int l = 0; l <= q.n_layers; ++l) d.width[l] = q.width[l];
+    for (int l = 0; l < q.n_layers; ++l) {
+      d.act[l] = q.act[l];
+      d.W[l] = q.W[l];
+      d.b[l] = q.b[l];
+    }
+    if (bf16) {
+      for (int l = 0; l < 2; ++l) {
+        const size_t n = ((size_t)q.width[l + 1] * q.width[l] + 127) / 128 * 128;
+        __bf16* w = L.wb + wofs;
+        wofs += 4 * n;
+        d.Wb[l] = w;
+        d.Wl[l] = w + n;
+        d.WbT[l] = w + 2 * n;
+        d.WlT[l] = w + 3 * n;
+        job.src[job.n] = q.W[l];
+        job.hi[job.n] = w;
+        job.lo[job.n] = w + n;
+        job.hiT[job.n] = w + 2 * n;
+        job.loT[job.n] = w + 3 * n;
+        job.rows[job.n] = q.width[l + 1];
+        job.cols[job.n] = q.width[l];
+        ++job.n;
+      }
+    }
+  }
+  if (bf16) {
+    StageTimer t(NN_STAGE_WEIGHTS, s);
+    launch_convert_bf16(job, s);
+  }
 }
 
 __global__ void k_zero_meta(int64_t* m) {
@@ -408,45 +467,8 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     StageTimer t(NN_STAGE_SPECIES, s);
     launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
   }
-  // model as seen by the kernels
   MlpArgs a{};
-  a.model.S = P.S;
-  ConvJob job{};
-  size_t wofs = 0;
-  for (int sp = 0; sp < P.S; ++sp) {
-    const nn_mlp& q = model->mlp[sp];
-    MlpDev& d = a.model.m[sp];
-    d.n_layers = q.n_layers;
-    for (int l = 0; l <= q.n_layers; ++l) d.width[l] = q.width[l];
-    for (int l = 0; l < q.n_layers; ++l) {
-      d.act[l] = q.act[l];
-      d.W[l] = q.W[l];
-      d.b[l] = q.b[l];
-    }
-    if (bf16) {
-      for (int l = 0; l < 2; ++l) {
-        const size_t n = ((size_t)q.width[l + 1] * q.width[l] + 127) / 128 * 128;
-        __bf16* w = L.wb + wofs;
-        wofs += 4 * n;
-        d.Wb[l] = w;
-        d.Wl[l] = w + n;
-        d.WbT[l] = w + 2 * n;
-        d.WlT[l] = w + 3 * n;
-        job.src[job.n] = q.W[l];
-        job.hi[job.n] = w;
-        job.lo[job.n] = w + n;
-        job.hiT[job.n] = w + 2 * n;
-        job.loT[job.n] = w + 3 * n;
-        job.rows[job.n] = q.width[l + 1];
-        job.cols[job.n] = q.width[l];
-        ++job.n;
-      }
-    }
-  }
-  if (bf16) {
-    StageTimer t(NN_STAGE_WEIGHTS, s);
-    launch_convert_bf16(job, s);
-  }
+  prepare_model(model, P, L, bf16, a, s);
   // descriptors
   {
     StageTimer t(NN_STAGE_DESC_FWD, s);
@@ -482,20 +504,49 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
                                 const nn_model* model, int32_t flags, const double* dL_dE, const float* F,
                                 float* dL_dpos, float* const* dW, float* const* db, void* ws, size_t ws_bytes,
                                 void* stream) {
-  (void)sys;
-  (void)nl;
-  (void)p;
-  (void)model;
-  (void)flags;
-  (void)dL_dE;
-  (void)F;
-  (void)dL_dpos;
-  (void)dW;
-  (void)db;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return fail(NN_E_UNSUPPORTED, "nn_energy_forces_grad is not available in this build");
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((st = check_model(model, P))) return st;
+  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN)) return fail(NN_E_INVALID, "unknown flags");
+  if (!dL_dE && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE is NULL");
+  if (dL_dpos && !F) return fail(NN_E_INVALID, "dL_dpos needs the forces F");
+  const int64_t N = sys->n_atoms;
+  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) return NN_OK;
+  if (dL_dpos) launch_pos_grad(dL_dE, sys->atom_ptr, sys->n_structs, N, F, dL_dpos, s);
+  if (dW || db) {
+    const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
+    launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+    MlpArgs a{};
+    prepare_model(model, P, L, mode != 0, a, s);
+    // re-run the MLP on the stored descriptors, keeping a1, a2, dE/dz1, dE/dz2
+    a.G = L.G;
+    a.perm = L.perm;
+    a.sp_start = L.sp_start;
+    a.E_atom = L.E_atom;
+    a.lambda = nullptr;
+    a.D = P.D;
+    a.st_a1 = L.st_a1;
+    a.st_d1 = L.st_d1;
+    a.st_a2 = L.st_a2;
+    a.st_d2 = L.st_d2;
+    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
+    launch_atom_weights(dL_dE, sys->atom_ptr, sys->n_structs, N, L.w_atom, s);
+    WgradArgs g{};
+    g.perm = L.perm;
+    g.sp_start = L.sp_start;
+    g.w = L.w_atom;
+    g.partial = L.partial;
+    g.S = P.S;
+    launch_wgrad(g, a.model, L.G, L.st_a1, L.st_d1, L.st_a2, L.st_d2, P.D, N, dW, db, s);
+  }
+  return check_launch("nn_energy_forces_grad");
 }
 
 nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {

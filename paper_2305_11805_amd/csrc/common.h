@@ -136,6 +136,9 @@ struct MlpArgs {
   float* E_atom;            // [N]
   float* lambda;            // [N][D] (null: energies only)
   int D;
+  // optional per-atom stash for the weight gradient (null: not written):
+  // a1 / delta1 = dE/dz1 [N][H1], a2 / delta2 = dE/dz2 [N][H2]
+  float *st_a1, *st_d1, *st_a2, *st_d2;
 };
 struct ConvJob {
   int n;
@@ -151,6 +154,21 @@ void launch_species_group(const int32_t* species, int64_t N, int S, int64_t* cnt
 bool mlp_supported(int h1, int h2);
 void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s);  // mode 0 FP32, 1 BF16, 2 split BF16
 void launch_convert_bf16(const ConvJob& job, hipStream_t s);
+// wgrad.hip
+struct WgradArgs {
+  const int32_t* perm;      // atoms grouped by species
+  const int64_t* sp_start;  // [S+1]
+  const float* w;           // [N] per-atom weight dL/dE of its structure
+  float* partial;           // chunk partial sums
+  int S;
+};
+size_t wgrad_partial_floats(int64_t N, int S, const ModelDev& m);
+void launch_wgrad(const WgradArgs& a, const ModelDev& m, const float* G, const float* a1, const float* d1,
+                  const float* a2, const float* d2, int D, int64_t N, float* const* dW, float* const* db,
+                  hipStream_t s);
+void launch_atom_weights(const double* dL_dE, const int64_t* atom_ptr, int32_t B, int64_t N, float* w, hipStream_t s);
+void launch_pos_grad(const double* dL_dE, const int64_t* atom_ptr, int32_t B, int64_t N, const float* F,
+                     float* dL_dpos, hipStream_t s);
 void launch_energy_reduce(const float* E_atom, const int64_t* atom_ptr, int32_t B, int64_t N, double* E_struct,
                           hipStream_t s);
 

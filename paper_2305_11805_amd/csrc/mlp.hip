@@ -209,6 +209,10 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
       const float a = act_f(act1, z);
       d1[n][j] = act_d(act1, z, a);
       buf[(4 * lk + j) * LD + n * 16 + lm] = a;
+      if (args.st_a1) {
+        const int r = rows[4 * lk + j];
+        if (r >= 0) args.st_a1[(int64_t)r * H1 + n * 16 + lm] = a;
+      }
     }
   }
   __syncthreads();
@@ -253,6 +257,13 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
       const float a = act_f(act2, z);
       e[j] = fmaf(a, w, e[j]);
       dl2[n][j] = w * act_d(act2, z, a);
+      if (args.st_a2) {
+        const int r = rows[4 * lk + j];
+        if (r >= 0) {
+          args.st_a2[(int64_t)r * H2 + n * 16 + lm] = a;
+          args.st_d2[(int64_t)r * H2 + n * 16 + lm] = dl2[n][j];
+        }
+      }
     }
   }
 #pragma unroll
@@ -272,7 +283,7 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
       if (r >= 0) args.E_atom[r] = e[j] + b3;
     }
   }
-  if (args.lambda == nullptr) return;
+  if (args.lambda == nullptr && args.st_d1 == nullptr) return;
   __syncthreads();
   // ---- delta1 = (delta2 W2) * act'(z1) ----
 #pragma unroll
@@ -308,7 +319,15 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
 #pragma unroll
   for (int n = 0; n < H1T; ++n)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) buf[(4 * lk + j) * LD + n * 16 + lm] = acc1[n][j] * d1[n][j];
+    for (int j = 0; j < 4; ++j) {
+      const float dd = acc1[n][j] * d1[n][j];
+      buf[(4 * lk + j) * LD + n * 16 + lm] = dd;
+      if (args.st_d1) {
+        const int r = rows[4 * lk + j];
+        if (r >= 0) args.st_d1[(int64_t)r * H1 + n * 16 + lm] = dd;
+      }
+    }
+  if (args.lambda == nullptr) return;
   __syncthreads();
   // ---- lambda = delta1 W1, D columns in chunks of 8 tiles ----
   constexpr int CH = 8;

@@ -150,9 +150,22 @@ def nn_energy_forces(sys, nl, params, model, flags, mem_budget, E_struct, E_atom
                                _p(E_struct), _p(E_atom), _p(F), _p(ws), ws.numel(), _stream(stream)))
 
 
+def _ptr_table(tensors):
+    """[species][layer] tensors (or None) -> C array of NN_MAX_SPECIES*NN_MAX_LAYERS device pointers."""
+    if tensors is None:
+        return None
+    arr = (C.c_void_p * (NN_MAX_SPECIES * NN_MAX_LAYERS))()
+    for s, layers in enumerate(tensors):
+        for l, t in enumerate(layers):
+            arr[s * NN_MAX_LAYERS + l] = None if t is None else t.data_ptr()
+    return arr
+
+
 def nn_energy_forces_grad(sys, nl, params, model, flags, dL_dE, F, dL_dpos, dW, db, ws, stream=None):
+    """dW, db: [species][layer] lists of FP32 device tensors (or None)."""
     _ok(lib().nn_energy_forces_grad(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, _p(dL_dE),
-                                    _p(F), _p(dL_dpos), dW, db, _p(ws), ws.numel(), _stream(stream)))
+                                    _p(F), _p(dL_dpos), _ptr_table(dW), _ptr_table(db), _p(ws), ws.numel(),
+                                    _stream(stream)))
 
 
 def nn_check(nl: nn_nlist, stream=None) -> int:
@@ -291,6 +304,30 @@ class Potential:
         nn_energy_forces(self.sys, self.nl, self.params, self.dmodel.struct, f, mem_budget, self.E_struct,
                          self.E_atom, self.F if forces else None, self.ws)
         return self.E_struct, self.E_atom, self.F
+
+    def grad(self, dL_dE, flags: Optional[int] = None, positions: bool = True, weights: bool = True):
+        """Backward of E_struct after energy_forces(): (dL/dpos [N,3] or None,
+        [species][layer] (dW, db) or None)."""
+        torch = self.torch
+        f = self.flags if flags is None else flags
+        dL_dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=self.dev).contiguous()
+        dpos = torch.zeros((self.N, 3), dtype=torch.float32, device=self.dev) if positions else None
+        dW = db = None
+        if weights:
+            dW, db = [], []
+            it = iter(self.dmodel.tensors)
+            for s in range(self.dmodel.struct.n_species):
+                L = self.dmodel.struct.mlp[s].n_layers
+                ws_, bs_ = [], []
+                for _ in range(L):
+                    W, b = next(it), next(it)
+                    ws_.append(torch.zeros_like(W))
+                    bs_.append(torch.zeros_like(b))
+                dW.append(ws_)
+                db.append(bs_)
+        nn_energy_forces_grad(self.sys, self.nl, self.params, self.dmodel.struct, f, dL_dE, self.F, dpos, dW, db,
+                              self.ws)
+        return dpos, ([list(zip(w_s, b_s)) for w_s, b_s in zip(dW, db)] if weights else None)
 
     def neighbor_list_host(self):
         """(offsets, nbr, shift[:, :3]) copied to the host (after a sync)."""
