@@ -52,11 +52,15 @@ enum { NN_ACT_LINEAR = 0, NN_ACT_GAUSSIAN = 1, NN_ACT_RELU = 2, NN_ACT_TANH = 3 
 enum {
   NN_BF16_MLP = 1,       /* MLP products on BF16 MFMA, operands rounded to BF16, FP32 sums     */
   NN_STORE_JACOBIAN = 2, /* store dG/dx during the descriptor pass if it fits mem_budget        */
-  NN_BF16X3_MLP = 4      /* MLP products on BF16 MFMA with every operand split into BF16 hi + lo
+  NN_BF16X3_MLP = 4,     /* MLP products on BF16 MFMA with every operand split into BF16 hi + lo
                             and three products (hi*hi + hi*lo + lo*hi), FP32 sums: about 16
                             significant bits per operand.  Exclusive with NN_BF16_MLP.
                             Neither flag: FP32 MFMA.                                           */
+  NN_REUSE_DESCRIPTORS = 8 /* skip the descriptor pass: use G and the Jacobian that an earlier
+                              NN_STORE_JACOBIAN call with the same positions and list left in
+                              this workspace (weights may have changed)                        */
 };
+
 
 /*
  * A batch of atomic configurations (Sec. II.A: positions, species, cell).
@@ -160,6 +164,16 @@ typedef struct nn_model {
 int64_t nn_descriptor_dim(const nn_mbp_params* p);
 
 /*
+ * Row length (floats) of the stored Jacobian: one row per list entry e =
+ * (i -> j), js = 4 * ceil((n_rad + 3 + 3 * S * n_theta * n_rs_ang) / 4):
+ *   [0, n_rad)   d/dr of the radial bins of species s_j (gradient = value * d/r);
+ *   [n_rad, +3)  the unit vector d/r;
+ *   then, for partner species b = 0 .. S-1, the angular block (s_j, b) as
+ *   [q][p] 3-vectors dG_i/dd_e.  Rows of entries at r >= rc are zero.
+ */
+int64_t nn_jacobian_stride(const nn_mbp_params* p);
+
+/*
  * Workspace bytes needed by every call below for a system of n_atoms atoms
  * and n_structs structures, a list of `capacity` entries, these descriptor
  * and model parameters (model may be NULL for list/descriptor-only use) and
@@ -195,10 +209,9 @@ nn_status nn_build_neighbors(const nn_system* sys, double rc, double skin, nn_nl
 /*
  * Descriptors of every atom: G [device] FP32 [N][D] (layout of
  * nn_mbp_params).  Neighbor entries at r >= rc (skin lists) contribute
- * nothing.  If jac != NULL, also the stored Jacobian
- * jac [device] FP32 [capacity][D][3] with jac[e][d][k] = dG_{i,d}/d(d_e)_k
- * for entry e of row i (the derivatives the paper's precomputed mode stores,
- * Sec. II.A).
+ * nothing.  If jac != NULL, also the stored Jacobian jac [device] FP32
+ * [capacity][nn_jacobian_stride] (rows as documented there): the
+ * derivatives the paper's precomputed-descriptor mode stores (Sec. II.A).
  */
 nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, float* G, float* jac,
                          void* ws, size_t ws_bytes, void* stream);
@@ -212,8 +225,10 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
  * Forces come from a hand-written adjoint: lambda_i = dE_i/dG_i by the MLP
  * backward pass, then per-pair vectors dE_i/dd_e by re-running the
  * descriptor's pair and triplet loops against lambda (or, with
- * NN_STORE_JACOBIAN and a Jacobian within mem_budget, by contracting the
- * Jacobian stored during the descriptor pass), then a deterministic gather
+ * NN_STORE_JACOBIAN and a Jacobian of capacity * nn_jacobian_stride * 4
+ * bytes <= mem_budget, by contracting the Jacobian stored during the
+ * descriptor pass, which later calls can reuse with NN_REUSE_DESCRIPTORS;
+ * over the budget the call silently recomputes), then a deterministic gather
  * F_k = sum_e dE_k/dd_e - sum_e dE_{j(e)}/dd_rev(e).  G and lambda stay in
  * the workspace for nn_energy_forces_grad.
  */
@@ -268,7 +283,9 @@ enum {
   NN_STAGE_ENERGY = 5,      /* per-structure FP64 energy                     */
   NN_STAGE_DESC_ADJ = 6,    /* descriptor adjoint: per-pair gradients        */
   NN_STAGE_FORCE_GATHER = 7,/* per-atom forces from per-pair gradients       */
-  NN_STAGE_COUNT = 8
+  NN_STAGE_DESC_JAC = 8,    /* stored Jacobian of the descriptors            */
+  NN_STAGE_JAC_CONTRACT = 9,/* per-pair gradients from the stored Jacobian   */
+  NN_STAGE_COUNT = 10
 };
 nn_status nn_timing(int32_t enable);
 nn_status nn_timing_read(double* ms, int64_t* launches);

@@ -109,6 +109,7 @@ struct Layout {
   size_t wb_elems;
   // weight gradient: per-atom stash, per-atom weights, chunk partials
   float *st_a1, *st_d1, *st_a2, *st_d2, *w_atom, *partial;
+  float* jac;  // stored Jacobian (NN_STORE_JACOBIAN within the memory budget)
   size_t bytes;
 };
 
@@ -121,7 +122,8 @@ static size_t model_param_floats(const nn_model* m) {
   return t;
 }
 
-static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D, int S, const nn_model* model) {
+static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D, int S, const nn_model* model,
+                    size_t jac_floats = 0) {
   Layout L{};
   Carver c{static_cast<char*>(ws)};
   L.max_bins = 8 * N + 64 * (int64_t)B + 1;
@@ -167,6 +169,7 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
       L.partial = c.take<float>(wgrad_partial_floats(N, S, md));
     }
   }
+  L.jac = jac_floats ? c.take<float>(jac_floats) : nullptr;
   L.bytes = c.off + 256;
   return L;
 }
@@ -264,6 +267,13 @@ static nn_status check_model(const nn_model* m, const DescConst& P) {
   return NN_OK;
 }
 
+// Floats of the stored Jacobian if these flags and budget ask for it, else 0.
+static size_t jac_request(const DescConst& P, int64_t capacity, int32_t flags, size_t mem_budget) {
+  if (!(flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))) return 0;
+  const size_t n = jacobian_floats(P.n_rad, P.S, P.n_theta, P.n_rs_ang, capacity);
+  return n * sizeof(float) <= mem_budget ? n : 0;
+}
+
 static int64_t dim_of(const nn_mbp_params* p) {
   return (int64_t)p->n_rad * p->n_species + (int64_t)p->n_theta * p->n_rs_ang * p->n_species * (p->n_species + 1) / 2;
 }
@@ -352,20 +362,20 @@ int64_t nn_descriptor_dim(const nn_mbp_params* p) {
 
 nn_status nn_workspace_size(int64_t n_atoms, int32_t n_structs, int64_t capacity, const nn_mbp_params* p,
                             const nn_model* model, int32_t flags, size_t mem_budget, size_t* bytes) {
-  (void)flags;
-  (void)mem_budget;
   if (!bytes) return fail(NN_E_INVALID, "bytes is NULL");
   if (n_atoms < 0 || n_structs < 0 || capacity < 0) return fail(NN_E_INVALID, "negative sizes");
   int64_t D = 0;
   int S = 1;
+  size_t jf = 0;
   if (p) {
     DescConst P;
     nn_status st = make_desc_const(p, &P);
     if (st) return st;
     D = P.D;
     S = P.S;
+    jf = jac_request(P, capacity, flags, mem_budget);
   }
-  Layout L = carve(nullptr, n_atoms, n_structs, capacity, D, S, model);
+  Layout L = carve(nullptr, n_atoms, n_structs, capacity, D, S, model, jf);
   *bytes = L.bytes;
   return NN_OK;
 }
@@ -424,7 +434,7 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if (!G && sys->n_atoms > 0) return fail(NN_E_INVALID, "G is NULL");
-  if (jac) return fail(NN_E_UNSUPPORTED, "stored Jacobian output is not available in this build");
+
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   (void)ws;
   (void)ws_bytes;
@@ -433,13 +443,16 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
     StageTimer t(NN_STAGE_DESC_FWD, s);
     launch_desc_fwd(*sys, *nl, P, G, s);
   }
+  if (jac) {
+    StageTimer t(NN_STAGE_DESC_JAC, s);
+    launch_desc_jac(*sys, *nl, P, jac, s);
+  }
   return check_launch("nn_descriptors");
 }
 
 nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
                            int32_t flags, size_t mem_budget, double* E_struct, float* E_atom, float* F, void* ws,
                            size_t ws_bytes, void* stream) {
-  (void)mem_budget;
   nn_status st = check_system(sys);
   if (st) return st;
   if ((st = check_nlist(nl, sys, true))) return st;
@@ -448,13 +461,19 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   if ((st = check_model(model, P))) return st;
   if (!E_struct && sys->n_structs > 0) return fail(NN_E_INVALID, "E_struct is NULL");
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
-  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN)) return fail(NN_E_INVALID, "unknown flags");
+  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
+    return fail(NN_E_INVALID, "unknown flags");
   if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
     return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
   const int64_t N = sys->n_atoms;
-  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  const size_t jf = jac_request(P, nl->capacity, flags, mem_budget);
+  if ((flags & NN_REUSE_DESCRIPTORS) && !jf)
+    return fail(NN_E_INVALID, "NN_REUSE_DESCRIPTORS needs the stored Jacobian within mem_budget");
+  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model, jf);
   if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
-  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model, jf);
+  const bool reuse = flags & NN_REUSE_DESCRIPTORS;
+  const bool stored = jf != 0;
   hipStream_t s = (hipStream_t)stream;
   const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
   const bool bf16 = mode != 0;
@@ -469,10 +488,14 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   }
   MlpArgs a{};
   prepare_model(model, P, L, bf16, a, s);
-  // descriptors
-  {
+  // descriptors (and the stored Jacobian)
+  if (!reuse) {
     StageTimer t(NN_STAGE_DESC_FWD, s);
     launch_desc_fwd(*sys, *nl, P, L.G, s);
+  }
+  if (stored && !reuse) {
+    StageTimer t(NN_STAGE_DESC_JAC, s);
+    launch_desc_jac(*sys, *nl, P, L.jac, s);
   }
   // MLP energies and lambda
   a.G = L.G;
@@ -490,7 +513,10 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
   }
   if (F) {
-    {
+    if (stored) {
+      StageTimer t(NN_STAGE_JAC_CONTRACT, s);
+      launch_jac_contract(*sys, *nl, P, L.lam, L.jac, L.pg, s);
+    } else {
       StageTimer t(NN_STAGE_DESC_ADJ, s);
       launch_desc_adj(*sys, *nl, P, L.lam, L.pg, s);
     }
@@ -514,6 +540,8 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   if (!dL_dE && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE is NULL");
   if (dL_dpos && !F) return fail(NN_E_INVALID, "dL_dpos needs the forces F");
   const int64_t N = sys->n_atoms;
+  // the stored Jacobian (if any) sits after every piece used here, so the
+  // layout without it matches the forward call's
   Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
   if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
   L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
@@ -575,6 +603,12 @@ nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {
 }
 
 const char* nn_last_error(void) { return g_err; }
+
+int64_t nn_jacobian_stride(const nn_mbp_params* p) {
+  DescConst P;
+  if (make_desc_const(p, &P) != NN_OK) return -1;
+  return (int64_t)jacobian_floats(P.n_rad, P.S, P.n_theta, P.n_rs_ang, 1);
+}
 
 nn_status nn_timing(int32_t enable) {
   std::lock_guard<std::mutex> g(g_tmu);

@@ -126,6 +126,10 @@ void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& 
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                      hipStream_t s);
 void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, hipStream_t s);
+size_t jacobian_floats(int n_rad, int S, int nt, int nra, int64_t capacity);
+void launch_desc_jac(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s);
+void launch_jac_contract(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam,
+                         const float* J, float4* pg, hipStream_t s);
 
 // mlp.hip
 struct MlpArgs {

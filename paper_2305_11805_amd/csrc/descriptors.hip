@@ -564,4 +564,209 @@ void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4*
                      nl.offsets, nl.rev, pg, F, nl.meta);
 }
 
+
+// ---------------------------------------------------------------------------
+// Stored Jacobian (the precomputed-derivative mode of Sec. II.A)
+//
+// Entry e = (i -> j) stores dG_i/dd_e in a compact row of
+// js = pad4(n_rad + 3 + 3 S NT NRA) floats:
+//   [0, n_rad)        d/dr [exp(-eta_rad (r - Rs_k)^2) fc(r)] of the radial
+//                     bins of species s_j (the gradient is that times d/r);
+//   [n_rad, n_rad+3)  d/r;
+//   then for each partner species b = 0..S-1 the block (s_j, b) as NRA x NT
+//   3-vectors dG[(s_j,b)][q][p] / dd_e.
+// Entries at r >= rc are all zero.  One lane per neighbor j walks every
+// partner k != j (both orders of each pair, so no lane writes another
+// lane's row); blocks are flushed when k enters the next species segment.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline int jac_stride(int n_rad, int S, int NB) { return (n_rad + 3 + 3 * S * NB + 3) / 4 * 4; }
+
+template <int NT, int NRA>
+__global__ void __launch_bounds__(64) k_desc_jac(nn_system sys, const int64_t* __restrict__ offsets,
+                                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
+                                                 DescConst P, float* __restrict__ J, int64_t* meta) {
+  constexpr int NB = NT * NRA;
+  __shared__ AtomNb nb;
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int S = P.S;
+  const int js = jac_stride(P.n_rad, S, NB);
+  if (meta[kMetaValid] != 1) return;
+  const int64_t e0 = offsets[i], e1 = offsets[i + 1];
+  {
+    // rows of entries outside rc (skin lists) are all zero; valid rows are
+    // written in full below, so no address is written twice
+    const int c = struct_of_atom(sys.atom_ptr, sys.n_structs, i);
+    double h[9];
+    for (int k = 0; k < 9; ++k) h[k] = sys.cell[9 * (int64_t)c + k];
+    const double xi[3] = {sys.pos[3 * i], sys.pos[3 * i + 1], sys.pos[3 * i + 2]};
+    const char4* sh4 = reinterpret_cast<const char4*>(shift);
+    for (int64_t e = e0 + lane; e < e1; e += kWave) {
+      const int32_t j = nbr[e];
+      const char4 s4 = sh4[e];
+      double d[3];
+      displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d);
+      const int sp = sys.species[j];
+      if (!(norm2_64(d) < P.rc64 * P.rc64) || sp < 0 || sp >= S)
+        for (int x = 0; x < js; ++x) J[e * js + x] = 0.f;
+    }
+  }
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr);
+  if (nb.bad) {
+    for (int64_t x = e0 * js + lane; x < e1 * js; x += kWave) J[x] = 0.f;
+    return;
+  }
+  const int n = nb.n;
+  const float eta_r2 = P.eta_rad * 1.4426950408889634f;
+  const float eta_a2 = P.eta_ang * 1.4426950408889634f;
+  const int zeta1 = P.zeta - 1;
+  const float zf = (float)P.zeta;
+  for (int j0 = 0; j0 < n; j0 += kWave) {
+    const int j = j0 + lane;
+    const bool active = j < n;
+    float4 u = make_float4(1.f, 0.f, 0.f, 1.f), fu = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (active) {
+      u = nb.d[j];
+      fu = nb.f[j];
+    }
+    float* row = J + (e0 + (active ? nb_entry(fu) : 0)) * js;
+    if (active) {
+      for (int k = 0; k < P.n_rad; ++k) {
+        const float dr = (u.w - P.rs_rad[k]) + (fu.z - P.rs_rad_lo[k]);
+        const float g = fexp2(-eta_r2 * dr * dr);
+        row[k] = g * fmaf(-2.0f * P.eta_rad * dr, fu.x, fu.y);
+      }
+      row[P.n_rad] = u.x;
+      row[P.n_rad + 1] = u.y;
+      row[P.n_rad + 2] = u.z;
+      for (int x = P.n_rad + 3 + 3 * S * NB; x < js; ++x) row[x] = 0.f;
+    }
+    const float iru = frcp(u.w);
+    for (int b = 0; b < S; ++b) {
+      float vx[NB], vy[NB], vz[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) vx[t] = vy[t] = vz[t] = 0.f;
+      for (int k = nb.seg[b]; k < nb.seg[b + 1]; ++k) {
+        if (!active || k == j) continue;
+        const float4 v = nb.d[k], fv = nb.f[k];
+        const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+        const float c = g.c;
+        const float F2 = 2.0f * fu.x * fv.x;
+        const float dF2 = 2.0f * fu.y * fv.x;  // dF2 / dr_u
+        float x[NT], P1[NT], A[NT], dA[NT];
+#pragma unroll
+        for (int p = 0; p < NT; ++p) x[p] = fmaf(c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
+        ipow_array<NT>(x, zeta1, P1);
+        const float issm = frcp(g.ssm);
+#pragma unroll
+        for (int p = 0; p < NT; ++p) {
+          A[p] = P1[p] * x[p];
+          // dA/dcos along the path cos -> (cos, ssm(cos)), ssm' = -cos/ssm
+          dA[p] = zf * P1[p] * (P.x_a[p] - P.x_b[p] * c * issm);
+        }
+        // d cos/dd_u = (v^ - cos u^) / r_u ; d r_u/dd_u = u^
+        const float ex = (v.x - c * u.x) * iru, ey = (v.y - c * u.y) * iru, ez = (v.z - c * u.z) * iru;
+#pragma unroll
+        for (int q = 0; q < NRA; ++q) {
+          const float dq = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
+          const float R = fexp2(-eta_a2 * dq * dq);
+          const float FR = F2 * R;
+          const float dFR = fmaf(F2 * R, -P.eta_ang * dq, dF2 * R);  // d(F2 R)/dr_u, with d rbar/dr_u = 1/2
+#pragma unroll
+          for (int p = 0; p < NT; ++p) {
+            const float a = FR * dA[p];
+            const float bcoef = A[p] * dFR;
+            const int t = q * NT + p;
+            vx[t] = fmaf(a, ex, fmaf(bcoef, u.x, vx[t]));
+            vy[t] = fmaf(a, ey, fmaf(bcoef, u.y, vy[t]));
+            vz[t] = fmaf(a, ez, fmaf(bcoef, u.z, vz[t]));
+          }
+        }
+      }
+      if (active) {
+        float* blk = row + P.n_rad + 3 + b * NB * 3;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+          blk[3 * t] = vx[t];
+          blk[3 * t + 1] = vy[t];
+          blk[3 * t + 2] = vz[t];
+        }
+      }
+    }
+  }
+}
+
+// pg[e] = sum_d lambda_i[d] dG_i[d]/dd_e from the stored rows: one wave per
+// atom, one lane per entry, lambda of the atom in LDS.
+template <int NT, int NRA>
+__global__ void __launch_bounds__(64) k_jac_contract(nn_system sys, const int64_t* __restrict__ offsets,
+                                                     const int32_t* __restrict__ nbr, DescConst P,
+                                                     const float* __restrict__ lambda, const float* __restrict__ J,
+                                                     float4* __restrict__ pg, const int64_t* meta) {
+  constexpr int NB = NT * NRA;
+  extern __shared__ float lam[];  // [D]
+  const int64_t i = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int S = P.S;
+  const int js = jac_stride(P.n_rad, S, NB);
+  if (meta[kMetaValid] != 1) return;
+  for (int d = lane; d < P.D; d += kWave) lam[d] = lambda[i * (int64_t)P.D + d];
+  __syncthreads();
+  const int64_t e0 = offsets[i], e1 = offsets[i + 1];
+  const int ang0 = P.n_rad * S;
+  for (int64_t e = e0 + lane; e < e1; e += kWave) {
+    const float* row = J + e * js;
+    const int sj = sys.species[nbr[e]];
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if (sj >= 0 && sj < S) {
+      float gr = 0.f;
+      for (int k = 0; k < P.n_rad; ++k) gr = fmaf(lam[sj * P.n_rad + k], row[k], gr);
+      gx = gr * row[P.n_rad];
+      gy = gr * row[P.n_rad + 1];
+      gz = gr * row[P.n_rad + 2];
+      for (int b = 0; b < S; ++b) {
+        const float* L = lam + ang0 + pair_block(S, sj, b) * NB;
+        const float* blk = row + P.n_rad + 3 + b * NB * 3;
+        for (int t = 0; t < NB; ++t) {
+          gx = fmaf(L[t], blk[3 * t], gx);
+          gy = fmaf(L[t], blk[3 * t + 1], gy);
+          gz = fmaf(L[t], blk[3 * t + 2], gz);
+        }
+      }
+    }
+    pg[e] = make_float4(gx, gy, gz, 0.f);
+  }
+}
+
+size_t jacobian_floats(int n_rad, int S, int nt, int nra, int64_t capacity) {
+  return (size_t)jac_stride(n_rad, S, nt * nra) * (size_t)capacity;
+}
+
+template <int NT, int NRA>
+static void launch_jac_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s) {
+  hipLaunchKernelGGL((k_desc_jac<NT, NRA>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets, nl.nbr,
+                     nl.shift, P, J, nl.meta);
+}
+
+template <int NT, int NRA>
+static void launch_contract_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam,
+                              const float* J, float4* pg, hipStream_t s) {
+  hipLaunchKernelGGL((k_jac_contract<NT, NRA>), dim3((unsigned)sys.n_atoms), dim3(64), sizeof(float) * P.D, s, sys,
+                     nl.offsets, nl.nbr, P, lam, J, pg, nl.meta);
+}
+
+void launch_desc_jac(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s) {
+  if (sys.n_atoms == 0) return;
+  const int nt = P.n_theta, nra = P.n_rs_ang;
+  NNP_DISPATCH(A, B, (launch_jac_t<A, B>(sys, nl, P, J, s)));
+}
+
+void launch_jac_contract(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam,
+                         const float* J, float4* pg, hipStream_t s) {
+  if (sys.n_atoms == 0) return;
+  const int nt = P.n_theta, nra = P.n_rs_ang;
+  NNP_DISPATCH(A, B, (launch_contract_t<A, B>(sys, nl, P, lam, J, pg, s)));
+}
+
 }  // namespace nnp

@@ -23,6 +23,7 @@ NN_MAX_LAYERS = 4
 NN_BF16_MLP = 1
 NN_STORE_JACOBIAN = 2
 NN_BF16X3_MLP = 4
+NN_REUSE_DESCRIPTORS = 8
 ACT = {"linear": 0, "gaussian": 1, "relu": 2, "tanh": 3}
 STATUS = {0: "NN_OK", 1: "NN_E_INVALID", 2: "NN_E_CAPACITY", 3: "NN_E_CELL", 4: "NN_E_WORKSPACE",
           5: "NN_E_UNSUPPORTED", 6: "NN_E_HIP", 7: "NN_E_DEVICE"}
@@ -62,8 +63,10 @@ class nn_model(C.Structure):
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_check", "nn_last_error", "nn_timing", "nn_timing_read")
-STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather")
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_check", "nn_last_error", "nn_timing", "nn_timing_read",
+           "nn_jacobian_stride")
+STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
+          "jac_contract")
 
 
 def lib():
@@ -92,6 +95,8 @@ def lib():
         L.nn_check.argtypes = [P, P, C.POINTER(I64)]
         L.nn_last_error.restype = C.c_char_p
         L.nn_last_error.argtypes = []
+        L.nn_jacobian_stride.restype = I64
+        L.nn_jacobian_stride.argtypes = [P]
         L.nn_timing.restype = I32
         L.nn_timing.argtypes = [I32]
         L.nn_timing_read.restype = I32
@@ -180,6 +185,10 @@ def nn_last_error() -> str:
     return lib().nn_last_error().decode()
 
 
+def nn_jacobian_stride(params: nn_mbp_params) -> int:
+    return int(lib().nn_jacobian_stride(C.byref(params)))
+
+
 def nn_timing(enable: bool):
     _ok(lib().nn_timing(1 if enable else 0))
 
@@ -241,7 +250,7 @@ class Potential:
     workspace and outputs.  All compute runs in libnnpot."""
 
     def __init__(self, system, params, model=None, capacity: Optional[int] = None, skin: float = 0.0,
-                 capacity_margin: float = 1.25, flags: int = 0, device="cuda"):
+                 capacity_margin: float = 1.25, flags: int = 0, mem_budget: int = 0, device="cuda"):
         import torch
         lib()
         self.torch = torch
@@ -252,7 +261,7 @@ class Potential:
         self.D = nn_descriptor_dim(self.params)
         if self.D < 0:
             raise NNError(1, nn_last_error())
-        self.rc, self.skin, self.flags = float(params.rc), float(skin), flags
+        self.rc, self.skin, self.flags, self.mem_budget = float(params.rc), float(skin), flags, int(mem_budget)
         t = lambda a, dt: torch.tensor(np.ascontiguousarray(a), dtype=dt, device=self.dev)
         self.pos = t(system.pos, torch.float64)
         self.species = t(system.species, torch.int32)
@@ -278,7 +287,7 @@ class Potential:
         self.nl = nn_nlist(self.capacity, self.offsets.data_ptr(), self.nbr.data_ptr(), self.shift.data_ptr(),
                            self.rev.data_ptr(), self.ref_pos.data_ptr(), self.meta.data_ptr(), 0.0)
         ws = nn_workspace_size(self.N, self.B, self.capacity, self.params,
-                               self.dmodel.struct if self.dmodel else None, flags, 0)
+                               self.dmodel.struct if self.dmodel else None, flags, self.mem_budget)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=self.dev)
         self.E_struct = z(self.B, torch.float64)
         self.E_atom = z(self.N, torch.float32)
@@ -299,11 +308,20 @@ class Potential:
         nn_descriptors(self.sys, self.nl, self.params, self.G, None, self.ws)
         return self.G
 
-    def energy_forces(self, flags: Optional[int] = None, forces: bool = True, mem_budget: int = 0):
+    def energy_forces(self, flags: Optional[int] = None, forces: bool = True, mem_budget: Optional[int] = None):
         f = self.flags if flags is None else flags
-        nn_energy_forces(self.sys, self.nl, self.params, self.dmodel.struct, f, mem_budget, self.E_struct,
+        b = self.mem_budget if mem_budget is None else int(mem_budget)
+        nn_energy_forces(self.sys, self.nl, self.params, self.dmodel.struct, f, b, self.E_struct,
                          self.E_atom, self.F if forces else None, self.ws)
         return self.E_struct, self.E_atom, self.F
+
+    def jacobian(self):
+        """(G [N, D], J [capacity, stride]) via nn_descriptors with a Jacobian buffer."""
+        js = nn_jacobian_stride(self.params)
+        J = self.torch.zeros((self.capacity, js), dtype=self.torch.float32, device=self.dev)
+        G = self.torch.zeros((self.N, self.D), dtype=self.torch.float32, device=self.dev)
+        nn_descriptors(self.sys, self.nl, self.params, G, J, self.ws)
+        return G, J
 
     def grad(self, dL_dE, flags: Optional[int] = None, positions: bool = True, weights: bool = True):
         """Backward of E_struct after energy_forces(): (dL/dpos [N,3] or None,

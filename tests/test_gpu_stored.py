@@ -1,0 +1,94 @@
+"""Stored-Jacobian mode (the paper's precomputed-derivative mode): the GPU's
+dG/dd against the oracle's analytic Jacobian, forces from the stored
+Jacobian against recompute mode and the oracle, reuse after a weight change,
+and the memory-budget fallback."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11805_amd import nnpot, synth
+
+from helpers import E_TOL, F_TOL
+
+pytestmark = pytest.mark.gpu
+
+BIG = 1 << 40
+
+
+def expand_jacobian(J, nl, species, p):
+    """Compact rows -> dense [nnz][D][3] (layout of nn_jacobian_stride)."""
+    S, nr, NB = p.n_species, p.n_rad, p.n_theta * p.n_rs_ang
+    blocks = [(a, b) for a in range(S) for b in range(a, S)]
+    ang0 = nr * S
+    nnz = len(nl["nbr"])
+    out = np.zeros((nnz, p.dim, 3))
+    for e in range(nnz):
+        sj = species[nl["nbr"][e]]
+        row = J[e]
+        unit = row[nr:nr + 3]
+        out[e, sj * nr:(sj + 1) * nr, :] = row[:nr, None] * unit[None, :]
+        for b in range(S):
+            blk = blocks.index((min(sj, b), max(sj, b)))
+            v = row[nr + 3 + b * NB * 3: nr + 3 + (b + 1) * NB * 3].reshape(NB, 3)
+            out[e, ang0 + blk * NB: ang0 + (blk + 1) * NB, :] += v
+    return out
+
+
+@pytest.mark.parametrize("cfg,scale", [(0, 1.0), (1, 0.05), (3, 0.01)])
+def test_jacobian_matches_oracle(cfg, scale):
+    w = synth.config(cfg, scale=scale)
+    s, p = w.system, w.params
+    pot = nnpot.Potential(s, p, w.model)
+    pot.build_neighbors()
+    G, J = pot.jacobian()
+    nnpot.nn_check(pot.nl)
+    nl = pot.neighbor_list_host()
+    ref_nl = oracle.neighbors_cells(s, p.rc)
+    _, dG = oracle.descriptors(p, s, ref_nl, jacobian=True)
+    got = expand_jacobian(J.cpu().numpy().astype(np.float64)[:len(nl["nbr"])], nl, s.species, p)
+    # per entry, relative to the entry's largest derivative
+    scale_e = np.maximum(np.abs(dG).max(axis=(1, 2)), 1e-12)
+    err = (np.abs(got - dG).max(axis=(1, 2)) / scale_e).max()
+    print(f"cfg{cfg}: max per-entry |dJ| / max |J| = {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("cfg,scale", [(1, 1.0), (3, 0.1), (2, 0.05)])
+def test_stored_mode_forces(cfg, scale):
+    w = synth.config(cfg, scale=scale)
+    s, p = w.system, w.params
+    pot = nnpot.Potential(s, p, w.model, mem_budget=BIG, flags=nnpot.NN_STORE_JACOBIAN)
+    pot.build_neighbors()
+    Es0, _, F0 = [t.cpu().numpy().copy() for t in pot.energy_forces(flags=0)]
+    Es1, _, F1 = [t.cpu().numpy().copy() for t in pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN)]
+    nnpot.nn_check(pot.nl)
+    assert np.array_equal(Es0, Es1)  # same descriptors and MLP
+    rel = np.abs(F1 - F0).max() / np.abs(F0).max()
+    print(f"cfg{cfg}: stored vs recompute max |dF| / max |F| = {rel:.2e}", flush=True)
+    assert rel <= 1e-5
+    if s.n_atoms <= 5000:
+        nl = oracle.neighbors_cells(s, p.rc)
+        Es_ref, _, F_ref = oracle.energy_forces(p, w.model, s, nl)
+        assert np.abs(F1 - F_ref).max() <= F_TOL
+        assert np.max(np.abs(Es1 - Es_ref) / np.diff(s.atom_ptr)) <= E_TOL
+
+
+def test_reuse_after_weight_change_and_budget_fallback():
+    import torch
+    w = synth.config(1, scale=0.25)
+    s, p = w.system, w.params
+    pot = nnpot.Potential(s, p, w.model, mem_budget=BIG, flags=nnpot.NN_STORE_JACOBIAN)
+    pot.build_neighbors()
+    pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN)
+    # change the weights in place: reuse must equal a fresh stored-mode call
+    with torch.no_grad():
+        pot.dmodel.tensors[0].mul_(1.1)
+    Er, _, Fr = [t.cpu().numpy().copy() for t in pot.energy_forces(flags=nnpot.NN_REUSE_DESCRIPTORS)]
+    Ef, _, Ff = [t.cpu().numpy().copy() for t in pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN)]
+    assert np.array_equal(Er, Ef) and np.array_equal(Fr, Ff)
+    # a budget below the Jacobian size silently recomputes: identical to flags=0
+    Eb, _, Fb = [t.cpu().numpy().copy() for t in pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN, mem_budget=1024)]
+    E0, _, F0 = [t.cpu().numpy().copy() for t in pot.energy_forces(flags=0)]
+    assert np.array_equal(Eb, E0) and np.array_equal(Fb, F0)
+    with pytest.raises(nnpot.NNError):
+        pot.energy_forces(flags=nnpot.NN_REUSE_DESCRIPTORS, mem_budget=1024)
