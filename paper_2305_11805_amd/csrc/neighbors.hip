@@ -123,8 +123,9 @@ __global__ void k_skin_check(const double* __restrict__ pos, const double* __res
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool move = false;
   if (i < n) {
+#pragma clang fp contract(off)
     double dx = pos[3 * i] - ref[3 * i], dy = pos[3 * i + 1] - ref[3 * i + 1], dz = pos[3 * i + 2] - ref[3 * i + 2];
-    double d2 = dx * dx + dy * dy + dz * dz;
+    double d2 = (dx * dx + dy * dy) + dz * dz;
     move = !(d2 <= half_skin2);  // also catches NaN
   }
   if (__any(move) && lane_id() == 0) flag[0] = 1;
