@@ -94,8 +94,11 @@ __device__ __forceinline__ double norm2_64(const double d[3]) {
 // ------------------------------------------------------------------------
 
 size_t scan_scratch_elems(int64_t n);
+// out[0..n] = exclusive prefix sums of in[0..n) (out[n] = total), skipped
+// when *predicate == 0; with n_dev, the small-n path scans only the first
+// *n_dev entries (the large-n path always scans n).
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s,
-                        const int32_t* predicate);
+                        const int32_t* predicate, const int64_t* n_dev = nullptr);
 
 // neighbors.hip
 struct NbLaunch {

@@ -60,7 +60,9 @@ __device__ __forceinline__ int struct_of_atom(const int64_t* atom_ptr, int32_t B
 __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, const int64_t* __restrict__ offsets,
                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
                                 const DescConst& P, int64_t* meta, float4* __restrict__ pg) {
-  const int lane = threadIdx.x;
+  // wave 0 does the work; every thread of the block passes the barriers
+  const int lane = threadIdx.x & 63;
+  const bool w0 = threadIdx.x < 64;
   const int c = struct_of_atom(sys.atom_ptr, sys.n_structs, i);
   double h[9];
   for (int k = 0; k < 9; ++k) h[k] = sys.cell[9 * (int64_t)c + k];
@@ -73,7 +75,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   for (int s = 0; s < NN_MAX_SPECIES; ++s) cnt[s] = 0;
   bool bad = false;
   // pass A: count neighbors inside rc per species
-  for (int64_t base = e0; base < e1; base += kWave) {
+  for (int64_t base = e0; w0 && base < e1; base += kWave) {
     int64_t e = base + lane;
     bool valid = false;
     int sp = 0;
@@ -91,9 +93,9 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
     }
     for (int s = 0; s < S; ++s) cnt[s] += __popcll(__ballot(valid && sp == s));
   }
-  if (__any(bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+  if (w0 && __any(bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
   int total = 0;
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     for (int s = 0; s < S; ++s) {
       nb.seg[s] = total;
       total += cnt[s];
@@ -109,7 +111,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   for (int s = 0; s < S; ++s) run[s] = nb.seg[s];
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   // pass B: pair geometry, scattered in species order
-  for (int64_t base = e0; base < e1; base += kWave) {
+  for (int64_t base = e0; w0 && base < e1; base += kWave) {
     int64_t e = base + lane;
     bool valid = false;
     int sp = 0;
@@ -166,6 +168,32 @@ __device__ __forceinline__ void ipow_array(const float (&x)[N], int e, float (&o
     if (e) {
 #pragma unroll
       for (int p = 0; p < N; ++p) base[p] *= base[p];
+    }
+  }
+}
+
+// x^E for a compile-time E (fully unrolled); E = 0 selects the runtime loop.
+template <int E, int N>
+__device__ __forceinline__ void ipow_sel(const float (&x)[N], int e_runtime, float (&out)[N]) {
+  if constexpr (E == 0) {
+    ipow_array<N>(x, e_runtime, out);
+  } else {
+    float base[N];
+    bool first = true;
+#pragma unroll
+    for (int p = 0; p < N; ++p) base[p] = x[p];
+#pragma unroll
+    for (int bit = 0; bit < 11; ++bit) {
+      if ((E >> bit) == 0) break;
+      if ((E >> bit) & 1) {
+#pragma unroll
+        for (int p = 0; p < N; ++p) out[p] = first ? base[p] : out[p] * base[p];
+        first = false;
+      }
+      if ((E >> (bit + 1)) != 0) {
+#pragma unroll
+        for (int p = 0; p < N; ++p) base[p] *= base[p];
+      }
     }
   }
 }
@@ -230,39 +258,57 @@ __device__ __forceinline__ void butterfly(float (&v)[NB]) {
   for (int m = 1 << S; m < 64; m <<= 1) v[0] += __shfl_xor(v[0], m);
 }
 
-template <int NT, int NRA>
-__global__ void __launch_bounds__(64) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
-                                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
-                                                 DescConst P, float* __restrict__ G, int64_t* meta) {
+template <int NT, int NRA, int WPA, int ZC>
+__global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const int8_t* __restrict__ shift, DescConst P,
+                                                       float* __restrict__ G, int64_t* meta) {
   constexpr int NB = NT * NRA;
   __shared__ AtomNb nb;
+  // per-wave partial sums (radial bins: S * n_rad <= 512; angular block: NB)
+  __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
   const int64_t i = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Gi = G + i * (int64_t)P.D;
   if (meta[kMetaValid] != 1) {  // no valid list: never read its entries
-    for (int d = lane; d < P.D; d += kWave) Gi[d] = 0.f;
+    for (int d = tid; d < P.D; d += 64 * WPA) Gi[d] = 0.f;
     return;
   }
   stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr);
   if (nb.bad) {
-    for (int d = lane; d < P.D; d += kWave) Gi[d] = 0.f;
+    for (int d = tid; d < P.D; d += 64 * WPA) Gi[d] = 0.f;
     return;
   }
   const int S = P.S;
   const float eta_r2 = P.eta_rad * 1.4426950408889634f;
   const float eta_a2 = P.eta_ang * 1.4426950408889634f;
-  // radial bins
+  // radial bins: lane k owns bin k; wave w sums the neighbors t = w mod WPA
   for (int k0 = 0; k0 < P.n_rad; k0 += kWave) {
     const int k = k0 + lane;
     const float rs = k < P.n_rad ? P.rs_rad[k] : 0.f;
     const float rs_lo = k < P.n_rad ? P.rs_rad_lo[k] : 0.f;
     for (int s = 0; s < S; ++s) {
       float acc = 0.f;
-      for (int t = nb.seg[s]; t < nb.seg[s + 1]; ++t) {
+      for (int t = nb.seg[s] + wv; t < nb.seg[s + 1]; t += WPA) {
         const float dr = (nb.d[t].w - rs) + (nb.f[t].z - rs_lo);
         acc = fmaf(fexp2(-eta_r2 * dr * dr), nb.f[t].x, acc);
       }
-      if (k < P.n_rad) Gi[s * P.n_rad + k] = acc;
+      if constexpr (WPA == 1) {
+        if (k < P.n_rad) Gi[s * P.n_rad + k] = acc;
+      } else {
+        if (k < P.n_rad) xch[wv * NN_MAX_SPECIES * kMaxRad + s * P.n_rad + k] = acc;
+      }
+    }
+    if constexpr (WPA > 1) {
+      __syncthreads();
+      for (int x = tid; x < S * P.n_rad; x += 64 * WPA) {
+        const int s = x / P.n_rad, kk = x - s * P.n_rad;
+        if (kk < k0 || kk >= k0 + kWave) continue;
+        float v = 0.f;
+        for (int w = 0; w < WPA; ++w) v += xch[w * NN_MAX_SPECIES * kMaxRad + x];
+        Gi[x] = v;
+      }
+      __syncthreads();
     }
   }
   // angular blocks
@@ -274,7 +320,7 @@ __global__ void __launch_bounds__(64) k_desc_fwd(nn_system sys, const int64_t* _
       float acc[NB];
 #pragma unroll
       for (int t = 0; t < NB; ++t) acc[t] = 0.f;
-      for (int t0 = 0; t0 < T; t0 += kWave) {
+      for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
         const int t = t0 + lane;
         if (t < T) {
           int j, k;
@@ -295,7 +341,7 @@ __global__ void __launch_bounds__(64) k_desc_fwd(nn_system sys, const int64_t* _
           float x[NT], A[NT];
 #pragma unroll
           for (int p = 0; p < NT; ++p) x[p] = fmaf(g.c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
-          ipow_array<NT>(x, P.zeta, A);
+          ipow_sel<ZC, NT>(x, P.zeta, A);
 #pragma unroll
           for (int q = 0; q < NRA; ++q) {
             const float dq = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
@@ -313,7 +359,19 @@ __global__ void __launch_bounds__(64) k_desc_fwd(nn_system sys, const int64_t* _
       if (lane < (1 << SS)) {
         const int base = bitrev(lane, SS) << (L - SS);
 #pragma unroll
-        for (int r = 0; r < PER; ++r) out[base + r] = acc[r];
+        for (int r = 0; r < PER; ++r) {
+          if constexpr (WPA == 1) out[base + r] = acc[r];
+          else xch[wv * NB + base + r] = acc[r];
+        }
+      }
+      if constexpr (WPA > 1) {
+        __syncthreads();
+        for (int x = tid; x < NB; x += 64 * WPA) {
+          float v = 0.f;
+          for (int w = 0; w < WPA; ++w) v += xch[w * NB + x];
+          out[x] = v;
+        }
+        __syncthreads();
       }
     }
   }
@@ -321,25 +379,26 @@ __global__ void __launch_bounds__(64) k_desc_fwd(nn_system sys, const int64_t* _
 
 // Per-pair energy gradients dE_i/dd_e (float4 per entry, w unused) from
 // lambda_i = dE_i/dG_i.
-template <int NT, int NRA, bool ONE_SPECIES>
-__global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* __restrict__ offsets,
-                                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
-                                                 DescConst P, const float* __restrict__ lambda,
-                                                 float4* __restrict__ pg, int64_t* meta) {
+template <int NT, int NRA, bool ONE_SPECIES, int WPA, int ZC>
+__global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int64_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const int8_t* __restrict__ shift, DescConst P,
+                                                       const float* __restrict__ lambda, float4* __restrict__ pg,
+                                                       int64_t* meta) {
   constexpr int NB = NT * NRA;
   constexpr int NBP = NB + 4;  // padded block stride in LDS (bank spread)
   __shared__ AtomNb nb;
-  __shared__ float gx[kMaxNb], gy[kMaxNb], gz[kMaxNb];
+  __shared__ float gx[WPA][kMaxNb], gy[WPA][kMaxNb], gz[WPA][kMaxNb];  // one accumulator set per wave
   extern __shared__ float dyn_lds[];  // [S * n_rad] radial lambda, then the angular blocks
   float* lam_r = dyn_lds;
   float* lam_a = dyn_lds + P.S * P.n_rad;
   const int64_t i = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
   const int64_t e0 = offsets[i];
   stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, pg);
   if (nb.bad) {
-    for (int64_t e = e0 + lane; e < offsets[i + 1]; e += kWave) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t e = e0 + tid; e < offsets[i + 1]; e += 64 * WPA) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
     return;
   }
   const int S = P.S;
@@ -347,18 +406,18 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
   const float* lam = lambda + i * (int64_t)P.D;
   const int ang0 = P.n_rad * S;
   const int nblk = S * (S + 1) / 2;
-  for (int d = lane; d < ang0; d += kWave) lam_r[d] = lam[d];
-  for (int d = lane; d < nblk * NB; d += kWave) lam_a[(d / NB) * NBP + d % NB] = lam[ang0 + d];
+  for (int d = tid; d < ang0; d += 64 * WPA) lam_r[d] = lam[d];
+  for (int d = tid; d < nblk * NB; d += 64 * WPA) lam_a[(d / NB) * NBP + d % NB] = lam[ang0 + d];
   for (int t = lane; t < n; t += kWave) {
-    gx[t] = 0.f;
-    gy[t] = 0.f;
-    gz[t] = 0.f;
+    gx[wv][t] = 0.f;
+    gy[wv][t] = 0.f;
+    gz[wv][t] = 0.f;
   }
   __syncthreads();
   const float eta_r2 = P.eta_rad * 1.4426950408889634f;
   const float eta_a2 = P.eta_ang * 1.4426950408889634f;
-  // radial: lane <-> neighbor; dE/dd = (dE/dr) d/r
-  for (int t0 = 0; t0 < n; t0 += kWave) {
+  // radial: lane <-> neighbor (waves take alternate chunks); dE/dd = (dE/dr) d/r
+  for (int t0 = wv * kWave; t0 < n; t0 += kWave * WPA) {
     const int t = t0 + lane;
     if (t < n) {
       const float4 u = nb.d[t], fu = nb.f[t];
@@ -369,12 +428,11 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
         const float g = fexp2(-eta_r2 * dr * dr);
         gr = fmaf(lr[k] * g, fmaf(-2.0f * P.eta_rad * dr, fu.x, fu.y), gr);
       }
-      atomicAdd(&gx[t], gr * u.x);
-      atomicAdd(&gy[t], gr * u.y);
-      atomicAdd(&gz[t], gr * u.z);
+      gx[wv][t] += gr * u.x;
+      gy[wv][t] += gr * u.y;
+      gz[wv][t] += gr * u.z;
     }
   }
-  __syncthreads();
   float Lr[ONE_SPECIES ? NB : 1];
   if constexpr (ONE_SPECIES) {
 #pragma unroll
@@ -382,7 +440,8 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
   }
   const int zeta1 = P.zeta - 1;
   const float zf = (float)P.zeta;
-  // angular: circular schedule over the species-sorted list
+  // angular: circular schedule over the species-sorted list; wave w takes
+  // the steps s = 1 + w, 1 + w + WPA, ...
   for (int j0 = 0; j0 < n; j0 += kWave) {
     const int j = j0 + lane;
     const bool active = j < n;
@@ -396,7 +455,7 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
     const float iru = frcp(u.w);
     float ax = 0.f, ay = 0.f, az = 0.f;
     const int smax = n / 2;  // s = n/2 only for j < n/2 when n is even
-    for (int s = 1; s <= smax; ++s) {
+    for (int s = 1 + wv; s <= smax; s += WPA) {
       const bool take = active && !((n % 2 == 0) && s == n / 2 && j >= n / 2);
       int k = j + s;
       if (k >= n) k -= n;
@@ -412,7 +471,7 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
         float x[NT], P1[NT], A[NT];
 #pragma unroll
         for (int p = 0; p < NT; ++p) x[p] = fmaf(c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
-        ipow_array<NT>(x, zeta1, P1);
+        ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
 #pragma unroll
         for (int p = 0; p < NT; ++p) A[p] = P1[p] * x[p];
         float R[NRA], dq[NRA];
@@ -463,19 +522,28 @@ __global__ void __launch_bounds__(64) k_desc_adj(nn_system sys, const int64_t* _
         ax += cu * (v.x - c * u.x) + dEdru * u.x;
         ay += cu * (v.y - c * u.y) + dEdru * u.y;
         az += cu * (v.z - c * u.z) + dEdru * u.z;
-        atomicAdd(&gx[k], cv * (u.x - c * v.x) + dEdrv * v.x);
-        atomicAdd(&gy[k], cv * (u.y - c * v.y) + dEdrv * v.y);
-        atomicAdd(&gz[k], cv * (u.z - c * v.z) + dEdrv * v.z);
+        atomicAdd(&gx[wv][k], cv * (u.x - c * v.x) + dEdrv * v.x);
+        atomicAdd(&gy[wv][k], cv * (u.y - c * v.y) + dEdrv * v.y);
+        atomicAdd(&gz[wv][k], cv * (u.z - c * v.z) + dEdrv * v.z);
       }
     }
     if (active) {
-      atomicAdd(&gx[j], ax);
-      atomicAdd(&gy[j], ay);
-      atomicAdd(&gz[j], az);
+      atomicAdd(&gx[wv][j], ax);
+      atomicAdd(&gy[wv][j], ay);
+      atomicAdd(&gz[wv][j], az);
     }
   }
   __syncthreads();
-  for (int t = lane; t < n; t += kWave) pg[e0 + nb_entry(nb.f[t])] = make_float4(gx[t], gy[t], gz[t], 0.f);
+  for (int t = tid; t < n; t += 64 * WPA) {
+    float x = 0.f, y = 0.f, z = 0.f;
+#pragma unroll
+    for (int w = 0; w < WPA; ++w) {
+      x += gx[w][t];
+      y += gy[w][t];
+      z += gz[w][t];
+    }
+    pg[e0 + nb_entry(nb.f[t])] = make_float4(x, y, z, 0.f);
+  }
 }
 
 // F_k = sum over entries e of row k of (pg[e] - pg[rev[e]]).  Sixteen lanes
@@ -513,22 +581,54 @@ __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* 
 // launchers
 // ---------------------------------------------------------------------------
 
+// Waves per atom: two when the atoms alone would leave the SIMDs with few
+// waves to switch between, one otherwise.
+static int waves_per_atom(int64_t n_atoms) { return n_atoms <= 16384 ? 2 : 1; }
+
+template <int NT, int NRA, int WPA, int ZC>
+static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
+  hipLaunchKernelGGL((k_desc_fwd<NT, NRA, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), 0, s, sys,
+                     nl.offsets, nl.nbr, nl.shift, P, G, nl.meta);
+}
+
 template <int NT, int NRA>
 static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
-  hipLaunchKernelGGL((k_desc_fwd<NT, NRA>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets, nl.nbr,
-                     nl.shift, P, G, nl.meta);
+  const int wpa = waves_per_atom(sys.n_atoms);
+  if (P.zeta == 50) {
+    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 50>(sys, nl, P, G, s);
+    else launch_fwd_w<NT, NRA, 1, 50>(sys, nl, P, G, s);
+  } else {
+    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 0>(sys, nl, P, G, s);
+    else launch_fwd_w<NT, NRA, 1, 0>(sys, nl, P, G, s);
+  }
+}
+
+template <int NT, int NRA, bool ONE, int WPA, int ZC>
+static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
+                         hipStream_t s) {
+  const size_t lds = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
+  hipLaunchKernelGGL((k_desc_adj<NT, NRA, ONE, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), lds, s, sys,
+                     nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta);
+}
+
+template <int NT, int NRA, bool ONE>
+static void launch_adj_o(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
+                         hipStream_t s) {
+  const int wpa = waves_per_atom(sys.n_atoms);
+  if (P.zeta == 50) {
+    if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 50>(sys, nl, P, lam, pg, s);
+    else launch_adj_w<NT, NRA, ONE, 1, 50>(sys, nl, P, lam, pg, s);
+  } else {
+    if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 0>(sys, nl, P, lam, pg, s);
+    else launch_adj_w<NT, NRA, ONE, 1, 0>(sys, nl, P, lam, pg, s);
+  }
 }
 
 template <int NT, int NRA>
 static void launch_adj_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                          hipStream_t s) {
-  const size_t lds = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
-  if (P.S == 1)
-    hipLaunchKernelGGL((k_desc_adj<NT, NRA, true>), dim3((unsigned)sys.n_atoms), dim3(64), lds, s, sys, nl.offsets,
-                       nl.nbr, nl.shift, P, lam, pg, nl.meta);
-  else
-    hipLaunchKernelGGL((k_desc_adj<NT, NRA, false>), dim3((unsigned)sys.n_atoms), dim3(64), lds, s, sys, nl.offsets,
-                       nl.nbr, nl.shift, P, lam, pg, nl.meta);
+  if (P.S == 1) launch_adj_o<NT, NRA, true>(sys, nl, P, lam, pg, s);
+  else launch_adj_o<NT, NRA, false>(sys, nl, P, lam, pg, s);
 }
 
 bool desc_supported(int nt, int nra) {

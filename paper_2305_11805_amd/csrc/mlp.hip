@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(64) k_sp_scatter(const int32_t* __restrict__ s
 
 // Row operand of a 16x16x4 FP32 MFMA from a row-major [16][ld] buffer.
 __device__ __forceinline__ float a_f32(const float* buf, int ld, int k0) {
-  const int l = threadIdx.x;
+  const int l = threadIdx.x & 63;  // lane within the wave
   return buf[(l & 15) * ld + k0 + (l >> 4)];
 }
 
@@ -132,14 +132,23 @@ __device__ __forceinline__ void b_frag(const __bf16* p, const __bf16* p_lo, int 
   }
 }
 
+// One 16-atom tile per block of kWaves waves.  Wave w owns the 16-column
+// output tiles n = w, w + kWaves, ... of every product, so act'(z) of its
+// layer-1 and layer-2 tiles stays in its registers; activations and deltas
+// are exchanged through two LDS buffers.
+constexpr int kWaves = 4;
+
 template <int H1T, int H2T, int MODE>
-__global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
+__global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
   constexpr int H1 = H1T * 16, H2 = H2T * 16;
   constexpr int HM = H1 > H2 ? H1 : H2;
   constexpr bool BF = MODE != kFp32;
-  __shared__ float buf[kTile * (HM + 4)];
+  constexpr int LD = HM + 4;
+  constexpr int T1 = (H1T + kWaves - 1) / kWaves, T2 = (H2T + kWaves - 1) / kWaves;
+  __shared__ float buf[2][kTile * LD];
+  __shared__ float epart[kWaves][kTile];
   __shared__ int32_t rows[kTile];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int S = args.model.S;
   // which species / tile
   int64_t t = blockIdx.x;
@@ -154,7 +163,7 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
   if (s >= S) return;
   r0 = args.sp_start[s] + t * kTile;
   const int nrows = (int)min<int64_t>(kTile, args.sp_start[s] + ns - r0);
-  if (lane < kTile) rows[lane] = lane < nrows ? args.perm[r0 + lane] : -1;
+  if (tid < kTile) rows[tid] = tid < nrows ? args.perm[r0 + tid] : -1;
   __syncthreads();
   const MlpDev& M = args.model.m[s];
   const int D = args.D;
@@ -163,13 +172,14 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
   const int arow = rows[lm];
   const float* Grow = args.G + (int64_t)(arow < 0 ? 0 : arow) * D;
   const int act1 = M.act[0], act2 = M.act[1];
-  constexpr int LD = HM + 4;
   bf16x8 ah{}, al{}, bh{}, bl{};
+  float* bufA = buf[0];
+  float* bufB = buf[1];
 
-  // ---- layer 1: z1 = G W1^T + b1 ----
-  floatx4 acc1[H1T];
+  // ---- layer 1: z1 = G W1^T + b1 (this wave's tiles n = wv + kWaves * u) ----
+  floatx4 acc1[T1];
 #pragma unroll
-  for (int n = 0; n < H1T; ++n) acc1[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < T1; ++u) acc1[u] = floatx4{0.f, 0.f, 0.f, 0.f};
   if constexpr (BF) {
     for (int k0 = 0; k0 < D; k0 += 32) {
       const int kb = k0 + 8 * lk;
@@ -181,10 +191,13 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) ah[q] = (__bf16)x[q];
 #pragma unroll
-      for (int n = 0; n < H1T; ++n) {
-        const int64_t off = (int64_t)(n * 16 + lm) * D + kb;
-        b_frag<MODE>(M.Wb[0] + off, M.Wl[0] + off, D - kb, bh, bl);
-        acc1[n] = mma_bf16<MODE>(acc1[n], ah, al, bh, bl);
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + kWaves * u;
+        if (n < H1T) {
+          const int64_t off = (int64_t)(n * 16 + lm) * D + kb;
+          b_frag<MODE>(M.Wb[0] + off, M.Wl[0] + off, D - kb, bh, bl);
+          acc1[u] = mma_bf16<MODE>(acc1[u], ah, al, bh, bl);
+        }
       }
     }
   } else {
@@ -193,22 +206,27 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
       const int k = k0 + lk;
       const float a = (arow >= 0 && k < D) ? Grow[k] : 0.f;
 #pragma unroll
-      for (int n = 0; n < H1T; ++n) {
-        const float b = k < D ? W1[(int64_t)(n * 16 + lm) * D + k] : 0.f;
-        acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[n], 0, 0, 0);
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + kWaves * u;
+        if (n < H1T) {
+          const float b = k < D ? W1[(int64_t)(n * 16 + lm) * D + k] : 0.f;
+          acc1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[u], 0, 0, 0);
+        }
       }
     }
   }
-  float d1[H1T][4];  // act'(z1) in C layout: row 4*lk + j, column n*16 + lm
+  float d1[T1][4];  // act'(z1) in C layout: row 4*lk + j, column n*16 + lm
 #pragma unroll
-  for (int n = 0; n < H1T; ++n) {
+  for (int u = 0; u < T1; ++u) {
+    const int n = wv + kWaves * u;
+    if (n >= H1T) continue;
     const float bias = M.b[0][n * 16 + lm];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float z = acc1[n][j] + bias;
+      const float z = acc1[u][j] + bias;
       const float a = act_f(act1, z);
-      d1[n][j] = act_d(act1, z, a);
-      buf[(4 * lk + j) * LD + n * 16 + lm] = a;
+      d1[u][j] = act_d(act1, z, a);
+      bufA[(4 * lk + j) * LD + n * 16 + lm] = a;
       if (args.st_a1) {
         const int r = rows[4 * lk + j];
         if (r >= 0) args.st_a1[(int64_t)r * H1 + n * 16 + lm] = a;
@@ -218,50 +236,58 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
   __syncthreads();
 
   // ---- layer 2: z2 = a1 W2^T + b2 ----
-  floatx4 acc2[H2T];
+  floatx4 acc2[T2];
 #pragma unroll
-  for (int n = 0; n < H2T; ++n) acc2[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < T2; ++u) acc2[u] = floatx4{0.f, 0.f, 0.f, 0.f};
   if constexpr (BF) {
     for (int k0 = 0; k0 < H1; k0 += 32) {
       const int kb = k0 + 8 * lk;
-      a_frag_lds<MODE>(buf, LD, lm, kb, ah, al);
+      a_frag_lds<MODE>(bufA, LD, lm, kb, ah, al);
 #pragma unroll
-      for (int n = 0; n < H2T; ++n) {
-        const int64_t off = (int64_t)(n * 16 + lm) * H1 + kb;
-        b_frag<MODE>(M.Wb[1] + off, M.Wl[1] + off, 8, bh, bl);
-        acc2[n] = mma_bf16<MODE>(acc2[n], ah, al, bh, bl);
+      for (int u = 0; u < T2; ++u) {
+        const int n = wv + kWaves * u;
+        if (n < H2T) {
+          const int64_t off = (int64_t)(n * 16 + lm) * H1 + kb;
+          b_frag<MODE>(M.Wb[1] + off, M.Wl[1] + off, 8, bh, bl);
+          acc2[u] = mma_bf16<MODE>(acc2[u], ah, al, bh, bl);
+        }
       }
     }
   } else {
     const float* W2 = M.W[1];
     for (int k0 = 0; k0 < H1; k0 += 4) {
-      const float a = a_f32(buf, LD, k0);
+      const float a = a_f32(bufA, LD, k0);
 #pragma unroll
-      for (int n = 0; n < H2T; ++n) {
-        const float b = W2[(int64_t)(n * 16 + lm) * H1 + k0 + lk];
-        acc2[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2[n], 0, 0, 0);
+      for (int u = 0; u < T2; ++u) {
+        const int n = wv + kWaves * u;
+        if (n < H2T) {
+          const float b = W2[(int64_t)(n * 16 + lm) * H1 + k0 + lk];
+          acc2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2[u], 0, 0, 0);
+        }
       }
     }
   }
   // ---- output E = w3 . a2 + b3, delta2 = w3 * act'(z2) ----
   const float* w3 = M.W[2];
   float e[4] = {0.f, 0.f, 0.f, 0.f};
-  float dl2[H2T][4];
 #pragma unroll
-  for (int n = 0; n < H2T; ++n) {
+  for (int u = 0; u < T2; ++u) {
+    const int n = wv + kWaves * u;
+    if (n >= H2T) continue;
     const float bias = M.b[1][n * 16 + lm];
     const float w = w3[n * 16 + lm];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float z = acc2[n][j] + bias;
+      const float z = acc2[u][j] + bias;
       const float a = act_f(act2, z);
       e[j] = fmaf(a, w, e[j]);
-      dl2[n][j] = w * act_d(act2, z, a);
+      const float dl2 = w * act_d(act2, z, a);
+      bufB[(4 * lk + j) * LD + n * 16 + lm] = dl2;
       if (args.st_a2) {
         const int r = rows[4 * lk + j];
         if (r >= 0) {
           args.st_a2[(int64_t)r * H2 + n * 16 + lm] = a;
-          args.st_d2[(int64_t)r * H2 + n * 16 + lm] = dl2[n][j];
+          args.st_d2[(int64_t)r * H2 + n * 16 + lm] = dl2;
         }
       }
     }
@@ -275,73 +301,81 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
     v += __shfl_xor(v, 8);
     e[j] = v;
   }
-  if (lm == 0) {
-    const float b3 = M.b[2][0];
+  if (lm == 0)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = rows[4 * lk + j];
-      if (r >= 0) args.E_atom[r] = e[j] + b3;
-    }
+    for (int j = 0; j < 4; ++j) epart[wv][4 * lk + j] = e[j];
+  __syncthreads();
+  if (tid < kTile) {
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) v += epart[w][tid];
+    const int r = rows[tid];
+    if (r >= 0) args.E_atom[r] = v + M.b[2][0];
   }
   if (args.lambda == nullptr && args.st_d1 == nullptr) return;
-  __syncthreads();
-  // ---- delta1 = (delta2 W2) * act'(z1) ----
+  // ---- delta1 = (delta2 W2) * act'(z1), this wave's layer-1 tiles ----
 #pragma unroll
-  for (int n = 0; n < H2T; ++n)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) buf[(4 * lk + j) * LD + n * 16 + lm] = dl2[n][j];
-  __syncthreads();
-#pragma unroll
-  for (int n = 0; n < H1T; ++n) acc1[n] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < T1; ++u) acc1[u] = floatx4{0.f, 0.f, 0.f, 0.f};
   if constexpr (BF) {
     for (int k0 = 0; k0 < H2; k0 += 32) {  // B = W2 [H2][H1] read through W2^T [H1][H2]
       const int kb = k0 + 8 * lk;
-      a_frag_lds<MODE>(buf, LD, lm, kb, ah, al);
+      a_frag_lds<MODE>(bufB, LD, lm, kb, ah, al);
 #pragma unroll
-      for (int n = 0; n < H1T; ++n) {
-        const int64_t off = (int64_t)(n * 16 + lm) * H2 + kb;
-        b_frag<MODE>(M.WbT[1] + off, M.WlT[1] + off, 8, bh, bl);
-        acc1[n] = mma_bf16<MODE>(acc1[n], ah, al, bh, bl);
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + kWaves * u;
+        if (n < H1T) {
+          const int64_t off = (int64_t)(n * 16 + lm) * H2 + kb;
+          b_frag<MODE>(M.WbT[1] + off, M.WlT[1] + off, 8, bh, bl);
+          acc1[u] = mma_bf16<MODE>(acc1[u], ah, al, bh, bl);
+        }
       }
     }
   } else {
     const float* W2 = M.W[1];  // [H2][H1]: B[k][n] = W2[k][n]
     for (int k0 = 0; k0 < H2; k0 += 4) {
-      const float a = a_f32(buf, LD, k0);
+      const float a = a_f32(bufB, LD, k0);
 #pragma unroll
-      for (int n = 0; n < H1T; ++n) {
-        const float b = W2[(int64_t)(k0 + lk) * H1 + n * 16 + lm];
-        acc1[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[n], 0, 0, 0);
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + kWaves * u;
+        if (n < H1T) {
+          const float b = W2[(int64_t)(k0 + lk) * H1 + n * 16 + lm];
+          acc1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[u], 0, 0, 0);
+        }
       }
     }
   }
-  __syncthreads();
+  // bufA (a1) is no longer read by anyone after the layer-2 products, which
+  // every wave finished before the barrier above
 #pragma unroll
-  for (int n = 0; n < H1T; ++n)
+  for (int u = 0; u < T1; ++u) {
+    const int n = wv + kWaves * u;
+    if (n >= H1T) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const float dd = acc1[n][j] * d1[n][j];
-      buf[(4 * lk + j) * LD + n * 16 + lm] = dd;
+      const float dd = acc1[u][j] * d1[u][j];
+      bufA[(4 * lk + j) * LD + n * 16 + lm] = dd;
       if (args.st_d1) {
         const int r = rows[4 * lk + j];
         if (r >= 0) args.st_d1[(int64_t)r * H1 + n * 16 + lm] = dd;
       }
     }
+  }
   if (args.lambda == nullptr) return;
   __syncthreads();
-  // ---- lambda = delta1 W1, D columns in chunks of 8 tiles ----
-  constexpr int CH = 8;
-  for (int c0 = 0; c0 < D; c0 += CH * 16) {
+  // ---- lambda = delta1 W1: D columns, 16-column tiles dealt to the waves ----
+  const int DT = (D + 15) / 16;
+  constexpr int CH = 4;
+  for (int c0 = wv; c0 < DT; c0 += kWaves * CH) {
     floatx4 acc[CH];
 #pragma unroll
     for (int n = 0; n < CH; ++n) acc[n] = floatx4{0.f, 0.f, 0.f, 0.f};
     if constexpr (BF) {
       for (int k0 = 0; k0 < H1; k0 += 32) {  // B = W1 [H1][D] read through W1^T [D][H1]
         const int kb = k0 + 8 * lk;
-        a_frag_lds<MODE>(buf, LD, lm, kb, ah, al);
+        a_frag_lds<MODE>(bufA, LD, lm, kb, ah, al);
 #pragma unroll
         for (int n = 0; n < CH; ++n) {
-          const int col = c0 + n * 16 + lm;
+          const int col = (c0 + n * kWaves) * 16 + lm;
           const int64_t off = (int64_t)(col < D ? col : 0) * H1 + kb;
           b_frag<MODE>(M.WbT[0] + off, M.WlT[0] + off, col < D ? 8 : 0, bh, bl);
           acc[n] = mma_bf16<MODE>(acc[n], ah, al, bh, bl);
@@ -350,10 +384,10 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
     } else {
       const float* W1 = M.W[0];  // [H1][D]: B[k][n] = W1[k][n]
       for (int k0 = 0; k0 < H1; k0 += 4) {
-        const float a = a_f32(buf, LD, k0);
+        const float a = a_f32(bufA, LD, k0);
 #pragma unroll
         for (int n = 0; n < CH; ++n) {
-          const int col = c0 + n * 16 + lm;
+          const int col = (c0 + n * kWaves) * 16 + lm;
           const float b = col < D ? W1[(int64_t)(k0 + lk) * D + col] : 0.f;
           acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[n], 0, 0, 0);
         }
@@ -361,7 +395,7 @@ __global__ void __launch_bounds__(64) k_mlp(MlpArgs args) {
     }
 #pragma unroll
     for (int n = 0; n < CH; ++n) {
-      const int col = c0 + n * 16 + lm;
+      const int col = (c0 + n * kWaves) * 16 + lm;
       if (col < D) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -435,9 +469,10 @@ bool mlp_supported(int h1, int h2) {
 
 template <int A, int B>
 static void launch_mlp_t(const MlpArgs& a, int mode, int64_t n_tiles, hipStream_t s) {
-  if (mode == kBf16x3) hipLaunchKernelGGL((k_mlp<A, B, kBf16x3>), dim3((unsigned)n_tiles), dim3(64), 0, s, a);
-  else if (mode == kBf16) hipLaunchKernelGGL((k_mlp<A, B, kBf16>), dim3((unsigned)n_tiles), dim3(64), 0, s, a);
-  else hipLaunchKernelGGL((k_mlp<A, B, kFp32>), dim3((unsigned)n_tiles), dim3(64), 0, s, a);
+  const dim3 g((unsigned)n_tiles), b(64 * kWaves);
+  if (mode == kBf16x3) hipLaunchKernelGGL((k_mlp<A, B, kBf16x3>), g, b, 0, s, a);
+  else if (mode == kBf16) hipLaunchKernelGGL((k_mlp<A, B, kBf16>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_mlp<A, B, kFp32>), g, b, 0, s, a);
 }
 
 void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s) {

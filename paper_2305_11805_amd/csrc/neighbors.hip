@@ -84,8 +84,55 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t n, const in
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
 }
 
+// Whole scan in one block of 1024 threads (n <= kScanSmall): each thread
+// sums a contiguous run, runs are scanned with wave shuffles and one step
+// across the 16 wave totals, then each thread writes its run.  If n_dev is
+// given, only its first min(*n_dev, n) entries are scanned.
+constexpr int kScanSmallThreads = 1024;
+constexpr int64_t kScanSmall = 64 * 1024;
+
+__global__ void __launch_bounds__(kScanSmallThreads) k_scan_small(const int64_t* __restrict__ in, int64_t n,
+                                                                  const int64_t* __restrict__ n_dev,
+                                                                  int64_t* __restrict__ out, const int32_t* pred) {
+  if (pred && !*pred) return;
+  __shared__ int64_t wsum[kScanSmallThreads / 64];
+  if (n_dev) n = min(n, max(*n_dev, (int64_t)0));
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t per = (n + kScanSmallThreads - 1) / kScanSmallThreads;
+  const int64_t b = (int64_t)t * per, e = min(b + per, n);
+  int64_t sum = 0;
+  for (int64_t k = b; k < e; ++k) sum += in[k];
+  int64_t incl = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    int64_t x = lane < kScanSmallThreads / 64 ? wsum[lane] : 0;
+    for (int off = 1; off < kScanSmallThreads / 64; off <<= 1) {
+      const int64_t v = __shfl_up(x, off);
+      if (lane >= off) x += v;
+    }
+    if (lane < kScanSmallThreads / 64) wsum[lane] = x;  // inclusive wave totals
+  }
+  __syncthreads();
+  int64_t run = incl - sum + (w > 0 ? wsum[w - 1] : 0);
+  for (int64_t k = b; k < e; ++k) {
+    const int64_t v = in[k];
+    out[k] = run;
+    run += v;
+  }
+  if (t == kScanSmallThreads - 1) out[n] = wsum[kScanSmallThreads / 64 - 1];
+}
+
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s,
-                        const int32_t* pred) {
+                        const int32_t* pred, const int64_t* n_dev) {
+  if (n <= kScanSmall) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanSmallThreads), 0, s, in, n, n_dev, out, pred);
+    return;
+  }
   int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 0) nb = 1;
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, n, scratch, pred);
@@ -97,23 +144,27 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scr
 // skin test and build predicate
 // ---------------------------------------------------------------------------
 
-// flag[0] = 1 if the list must be (re)built.
-__global__ void k_skin_init(int32_t* flag, const int64_t* meta, int use_skin) {
-  flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
-}
-
-// atom_ptr must run from 0 to N without decreasing; otherwise nothing is
-// built (and the list is marked invalid, so no later kernel reads it).
-__global__ void k_check_ptr(const int64_t* __restrict__ atom_ptr, int32_t B, int64_t N, int64_t* meta, int32_t* flag) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  bool bad = false;
-  if (c == 0) bad = atom_ptr[0] != 0 || atom_ptr[B] != N;
-  if (c < B) bad = bad || atom_ptr[c + 1] < atom_ptr[c];
+// flag[0] = 1 if the list must be (re)built (no valid list yet, or no
+// skin); the skin test below may raise it.  atom_ptr must run from 0 to N
+// without decreasing; otherwise nothing is built and the list is marked
+// invalid, so no later kernel reads it (the skin test only runs on a valid
+// list).  One block.
+__global__ void k_nb_prep(const int64_t* __restrict__ atom_ptr, int32_t B, int64_t N, int64_t* meta, int32_t* flag,
+                          int use_skin) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = (atom_ptr[0] != 0 || atom_ptr[B] != N);
+  __syncthreads();
+  for (int c = threadIdx.x; c < B; c += blockDim.x)
+    if (atom_ptr[c + 1] < atom_ptr[c]) bad = 1;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   if (bad) {
     atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrPtr);
     meta[kMetaValid] = 0;
     flag[0] = 0;
     flag[1] = 0;
+  } else {
+    flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
   }
 }
 
@@ -257,16 +308,14 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
   n_bins[c] = nbins;
 }
 
-__global__ void k_nb_set_base(StructGeom* geom, const int64_t* base, int32_t B, const int32_t* flag) {
-  if (!*flag) return;
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < B) geom[c].bin_base = base[c];
-}
 
-__global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v, const int32_t* flag) {
+__global__ void k_zero2_i64(int64_t* p, int64_t* q, int64_t n, const int32_t* flag) {
   if (flag && !*flag) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  if (i < n) {
+    p[i] = 0;
+    q[i] = 0;
+  }
 }
 
 __device__ __forceinline__ int struct_of(const int64_t* atom_ptr, int32_t B, int64_t i) {
@@ -300,8 +349,8 @@ __device__ __forceinline__ void bin_coords(const StructGeom& g, const uint8_t* p
 
 __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
                          const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
-                         int64_t* __restrict__ bin_count, int32_t* __restrict__ atom_bin, int64_t* meta,
-                         const int32_t* flag) {
+                         const int64_t* __restrict__ bin_base, int64_t* __restrict__ bin_count,
+                         int32_t* __restrict__ atom_bin, int64_t* meta, const int32_t* flag) {
   if (!*flag) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -319,7 +368,7 @@ __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restri
   }
   int b3[3], m[3];
   bin_coords(g, pbc + 3 * c, x, b3, m);
-  int64_t bin = g.bin_base + ((int64_t)b3[0] * g.nb[1] + b3[1]) * g.nb[2] + b3[2];
+  int64_t bin = bin_base[c] + ((int64_t)b3[0] * g.nb[1] + b3[1]) * g.nb[2] + b3[2];
   atom_bin[4 * i + 0] = (int32_t)bin;
   atom_bin[4 * i + 1] = m[0];
   atom_bin[4 * i + 2] = m[1];
@@ -356,6 +405,7 @@ template <bool FILL>
 __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
                                                 const uint8_t* __restrict__ pbc, int32_t B, int64_t N,
                                                 const StructGeom* __restrict__ geom,
+                                                const int64_t* __restrict__ bin_base,
                                                 const int64_t* __restrict__ bin_start,
                                                 const int32_t* __restrict__ bin_atoms,
                                                 const int32_t* __restrict__ atom_bin, double r2max,
@@ -416,51 +466,80 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
       test(active, (int32_t)(a0 + jj), na, nb, nc);
     }
   } else {
+    // the 27 bins around i's bin, flattened into one candidate index space:
+    // lane b < 27 describes bin b (first atom, atom count, lattice wrap), a
+    // prefix sum over the counts maps candidate t to (bin, atom)
+    __shared__ int64_t b_start[27];
+    __shared__ int32_t b_pre[28];
+    __shared__ int32_t b_img[27][3];
     const uint8_t* p3 = pbc + 3 * c;
-    int bi[3], mi[3];
-    {
-      const int64_t bin = atom_bin[4 * i];
-      int64_t local = bin - g.bin_base;
+    int mi[3];
+    mi[0] = atom_bin[4 * i + 1];
+    mi[1] = atom_bin[4 * i + 2];
+    mi[2] = atom_bin[4 * i + 3];
+    int cnt_b = 0;
+    if (lane < 27) {
+      const int64_t base_c = bin_base[c];
+      int64_t local = atom_bin[4 * i] - base_c;
+      int bi[3];
       bi[2] = (int)(local % g.nb[2]);
       local /= g.nb[2];
       bi[1] = (int)(local % g.nb[1]);
       bi[0] = (int)(local / g.nb[1]);
-      mi[0] = atom_bin[4 * i + 1];
-      mi[1] = atom_bin[4 * i + 2];
-      mi[2] = atom_bin[4 * i + 3];
-    }
-    for (int da = -1; da <= 1; ++da)
-      for (int db = -1; db <= 1; ++db)
-        for (int dc = -1; dc <= 1; ++dc) {
-          const int dd[3] = {da, db, dc};
-          int bb[3], wr[3];
-          bool skip = false;
-          for (int d = 0; d < 3; ++d) {
-            int k = bi[d] + dd[d];
-            wr[d] = 0;
-            if (k < 0 || k >= g.nb[d]) {
-              if (!p3[d]) {
-                skip = true;
-                break;
-              }
-              wr[d] = k < 0 ? -1 : 1;
-              k -= wr[d] * g.nb[d];
-            }
-            bb[d] = k;
+      const int dd[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
+      int bb[3], wr[3];
+      bool skip = false;
+      for (int d = 0; d < 3; ++d) {
+        int k = bi[d] + dd[d];
+        wr[d] = 0;
+        if (k < 0 || k >= g.nb[d]) {
+          if (!p3[d]) {
+            skip = true;
+            break;
           }
-          if (skip) continue;
-          const int64_t bin = g.bin_base + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
-          const int64_t b0 = bin_start[bin], b1 = bin_start[bin + 1];
-          for (int64_t t0 = b0; t0 < b1; t0 += kWave) {
-            const int64_t t = t0 + lane;
-            const bool active = t < b1;
-            const int32_t j = active ? bin_atoms[t] : 0;
-            int n[3] = {0, 0, 0};
-            if (active)
-              for (int d = 0; d < 3; ++d) n[d] = p3[d] ? wr[d] + mi[d] - atom_bin[4 * (int64_t)j + 1 + d] : 0;
-            test(active, j, n[0], n[1], n[2]);
-          }
+          wr[d] = k < 0 ? -1 : 1;
+          k -= wr[d] * g.nb[d];
         }
+        bb[d] = k;
+      }
+      int64_t b0 = 0;
+      if (!skip) {
+        const int64_t bin = base_c + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
+        b0 = bin_start[bin];
+        cnt_b = (int)(bin_start[bin + 1] - b0);
+      }
+      b_start[lane] = b0;
+      for (int d = 0; d < 3; ++d) b_img[lane][d] = p3[d] ? wr[d] + mi[d] : 0;
+    }
+    // inclusive prefix of the 27 counts (wave scan)
+    int pre = cnt_b;
+    for (int off = 1; off < 32; off <<= 1) {
+      const int v = __shfl_up(pre, off);
+      if (lane >= off) pre += v;
+    }
+    if (lane < 27) b_pre[lane + 1] = pre;
+    if (lane == 0) b_pre[0] = 0;
+    __syncthreads();
+    const int total = b_pre[27];
+    for (int t0 = 0; t0 < total; t0 += kWave) {
+      const int t = t0 + lane;
+      const bool active = t < total;
+      int b = 0;
+      if (active) {  // largest b with b_pre[b] <= t
+        int lo = 0, hi = 26;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (b_pre[mid] <= t) lo = mid;
+          else hi = mid - 1;
+        }
+        b = lo;
+      }
+      const int32_t j = active ? bin_atoms[b_start[b] + (t - b_pre[b])] : 0;
+      int n[3] = {0, 0, 0};
+      if (active)
+        for (int d = 0; d < 3; ++d) n[d] = p3[d] ? b_img[b][d] - atom_bin[4 * (int64_t)j + 1 + d] : 0;
+      test(active, j, n[0], n[1], n[2]);
+    }
   }
   if (!FILL) {
     if (lane == 0) {
@@ -531,12 +610,20 @@ __global__ void k_nb_capacity(const int64_t* offsets, int64_t N, int64_t capacit
 // Reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
 // found by binary search in the sorted row.  The list is exactly symmetric
 // because the FP64 displacement of the reverse entry is the exact negation.
+// Also records the positions of this build (skin reference) and marks the
+// list valid.
 __global__ void __launch_bounds__(64) k_nb_rev(int64_t N, const int64_t* __restrict__ offsets,
                                                const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
-                                               int32_t* __restrict__ rev, int64_t* meta, const int32_t* flag) {
+                                               int32_t* __restrict__ rev, const double* __restrict__ pos,
+                                               double* __restrict__ ref_pos, int64_t* meta, const int32_t* flag) {
   if (!flag[1]) return;
   const int64_t i = blockIdx.x;
   if (i >= N) return;
+  if (ref_pos && threadIdx.x < 3) ref_pos[3 * i + threadIdx.x] = pos[3 * i + threadIdx.x];
+  if (i == 0 && threadIdx.x == 0) {
+    meta[kMetaValid] = 1;
+    meta[kMetaBuilds] += 1;
+  }
   const char4* sh4 = reinterpret_cast<const char4*>(shift);
   for (int64_t e = offsets[i] + threadIdx.x; e < offsets[i + 1]; e += 64) {
     int32_t j = nbr[e];
@@ -565,17 +652,6 @@ __global__ void __launch_bounds__(64) k_nb_rev(int64_t N, const int64_t* __restr
   }
 }
 
-__global__ void k_nb_finish(const double* __restrict__ pos, double* __restrict__ ref_pos, int64_t N, int64_t* meta,
-                            const int32_t* flag) {
-  if (!flag[1]) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 3 * N && ref_pos) ref_pos[i] = pos[i];
-  if (i == 0) {
-    meta[kMetaValid] = 1;
-    meta[kMetaBuilds] += 1;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
@@ -585,31 +661,27 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const int64_t N = sys->n_atoms;
   const int32_t B = sys->n_structs;
   const unsigned gN = (unsigned)((N + 255) / 256 > 0 ? (N + 255) / 256 : 1);
-  hipLaunchKernelGGL(k_skin_init, dim3(1), dim3(1), 0, s, L.flag, L.meta, use_skin ? 1 : 0);
+  hipLaunchKernelGGL(k_nb_prep, dim3(1), dim3(256), 0, s, sys->atom_ptr, B, N, L.meta, L.flag, use_skin ? 1 : 0);
   if (use_skin && L.nl && L.nl->ref_pos && N > 0)
     hipLaunchKernelGGL(k_skin_check, dim3(gN), dim3(256), 0, s, sys->pos, L.nl->ref_pos, N, 0.25 * skin * skin,
                        L.meta, L.flag, 1);
-  hipLaunchKernelGGL(k_check_ptr, dim3((B + 256) / 256), dim3(256), 0, s, sys->atom_ptr, B, N, L.meta, L.flag);
   if (B > 0)
     hipLaunchKernelGGL(k_nb_geom, dim3(B), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B, L.radius,
                        L.geom, L.n_bins, L.meta, L.flag);
   exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
-  if (B > 0)
-    hipLaunchKernelGGL(k_nb_set_base, dim3((B + 255) / 256), dim3(256), 0, s, L.geom, L.bin_base, B, L.flag);
   const unsigned gB = (unsigned)((L.max_bins + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_fill_i64, dim3(gB), dim3(256), 0, s, L.bin_count, L.max_bins + 1, (int64_t)0, L.flag);
-  hipLaunchKernelGGL(k_fill_i64, dim3(gB), dim3(256), 0, s, L.bin_fill, L.max_bins + 1, (int64_t)0, L.flag);
+  hipLaunchKernelGGL(k_zero2_i64, dim3(gB), dim3(256), 0, s, L.bin_count, L.bin_fill, L.max_bins + 1, L.flag);
   const double r2 = L.radius * L.radius;
   if (N > 0)
     hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                       L.bin_count, L.atom_bin, L.meta, L.flag);
-  exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag);
+                       L.bin_base, L.bin_count, L.atom_bin, L.meta, L.flag);
+  exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag, L.bin_base + B);
   if (N > 0) {
     hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, L.atom_bin, L.bin_start, L.bin_fill, L.bin_atoms,
                        L.flag);
     hipLaunchKernelGGL(k_nb_rows<false>, dim3((unsigned)N), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N,
-                       L.geom, L.bin_start, L.bin_atoms, L.atom_bin, r2, L.counts, (const int64_t*)nullptr,
-                       (int32_t*)nullptr, (int8_t*)nullptr, L.meta, L.flag);
+                       L.geom, L.bin_base, L.bin_start, L.bin_atoms, L.atom_bin, r2, L.counts,
+                       (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, L.meta, L.flag);
   }
   exclusive_scan_i64(L.counts, L.offsets, N, L.scan_tmp, s, L.flag);
   hipLaunchKernelGGL(k_nb_capacity, dim3(1), dim3(1), 0, s, L.offsets, N,
@@ -617,12 +689,10 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
   hipLaunchKernelGGL(k_nb_rows<true>, dim3((unsigned)N), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N,
-                     L.geom, L.bin_start, L.bin_atoms, L.atom_bin, r2, (int64_t*)nullptr, nl->offsets, nl->nbr,
-                     nl->shift, L.meta, L.flag);
-  hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev, L.meta,
-                     L.flag);
-  hipLaunchKernelGGL(k_nb_finish, dim3((unsigned)((3 * N + 255) / 256)), dim3(256), 0, s, sys->pos, nl->ref_pos, N,
-                     L.meta, L.flag);
+                     L.geom, L.bin_base, L.bin_start, L.bin_atoms, L.atom_bin, r2, (int64_t*)nullptr, nl->offsets,
+                     nl->nbr, nl->shift, L.meta, L.flag);
+  hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev,
+                     sys->pos, nl->ref_pos, L.meta, L.flag);
 }
 
 }  // namespace nnp
