@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
+PEAK_FP32_PACKED_TFLOPS = 157.3  # the same with two-wide packed FP32 FMA
 PEAK_HBM_GBS = 8000.0
 METRIC = "energy+force atoms/sec at stated force error vs FP64 oracle; HBM GB/s"
 
@@ -72,27 +73,35 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The FP64 oracle as it stands, on the host cores: per-atom energy and
-    per-pair gradients (all of the E + F work) for a bounded sample of rows."""
+def oracle_leg(w, F, target_s=15.0):
+    """The FP64 oracle as it stands, on the host cores, and the force error of
+    the GPU run on a seeded sample of atoms.
+
+    Throughput: per-atom energies and per-pair gradients (all of the E + F
+    work) for the first rows of the workload; if the whole workload takes
+    less than target_s, it is evaluated repeatedly until about target_s."""
     import oracle
     oracle.build(force=False)
     s, p = w.system, w.params
-    n = 64
-    rows = np.arange(min(n, s.n_atoms))
+    n = min(64, s.n_atoms)
     t0 = time.perf_counter()
-    nl = oracle.neighbors_cells(s, p.rc, rows=rows)
+    nl = oracle.neighbors_cells(s, p.rc, rows=np.arange(n))
     oracle.atom_energies(p, w.model, s, nl, pair_grads=True)
     dt = time.perf_counter() - t0
     n2 = int(min(s.n_atoms, max(n, n * target_s / max(dt, 1e-3))))
+    reps = 1
+    if n2 == s.n_atoms:
+        reps = max(1, int(round(target_s / max(dt * s.n_atoms / n, 1e-3))))
     rows = np.arange(n2)
     t0 = time.perf_counter()
-    nl = oracle.neighbors_cells(s, p.rc, rows=rows)
-    oracle.atom_energies(p, w.model, s, nl, pair_grads=True)
+    for _ in range(reps):
+        nl = oracle.neighbors_cells(s, p.rc, rows=rows)
+        oracle.atom_energies(p, w.model, s, nl, pair_grads=True)
     dt = time.perf_counter() - t0
-    return {"value": n2 / dt, "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"E + per-pair dE/dd of the first {n2} of {s.n_atoms} atoms (FP64, OpenMP over atoms), "
-                      f"{dt:.1f} s"}
+    what = f"the first {n2} of {s.n_atoms} atoms" if n2 < s.n_atoms else f"all {s.n_atoms} atoms x {reps} passes"
+    base = {"value": n2 * reps / dt, "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"neighbor rows + E + per-pair dE/dd of {what} (FP64, OpenMP over atoms), {dt:.1f} s"}
+    return base, sampled_force_error(w, F)
 
 
 def sampled_force_error(w, F, n=16, seed=0):
@@ -106,6 +115,47 @@ def sampled_force_error(w, F, n=16, seed=0):
     return float(np.max(np.abs(F[t] - F_ref)))
 
 
+def read_pmc_csv(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 counter_collection
+    CSV: list of (kernel name, value)."""
+    import csv
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernel="k_desc_adj"):
+    """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the ratio of
+    the known size of a plain device copy to what the counter read for it."""
+    res = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = read_pmc_csv(path, name)
+        mine = [v for k, v in rows if f"nnp::{kernel}" in k]
+        copies = [v for k, v in rows if "copyBuffer" in k]
+        if not mine or not copies:
+            raise SystemExit(f"{path}: no {kernel} or copy dispatch with {name}")
+        known_kib = calib_mib * 1024.0
+        calib = max(copies)
+        res[name] = {"kib_per_launch_raw": sum(mine) / len(mine), "launches": len(mine),
+                     "copy_kib_raw": calib, "copy_kib_known": known_kib, "scale": known_kib / calib}
+    hbm = sum(1024.0 * r["kib_per_launch_raw"] * r["scale"] for r in res.values())
+    prof = os.path.join(ROOT, "profiles", "counters.json")
+    cnt = {}
+    if os.path.exists(prof):
+        with open(prof) as f:
+            cnt = json.load(f)
+    cnt[f"{kernel}:{workload}"] = {"source_hash": source_hash(), "hbm_bytes_per_launch": round(hbm),
+                                  "counters": res}
+    with open(prof, "w") as f:
+        json.dump(cnt, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(cnt[f"{kernel}:{workload}"]))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,16 +164,26 @@ def main():
     ap.add_argument("--config", type=int, default=1, help="workload index 0-4 (default: 1)")
     ap.add_argument("--mode", choices=["fp32", "bf16", "bf16x3"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the steady-state and graph-replay timings")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 --pmc CSVs of this workload into profiles/counters.json")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    from paper_2305_11805_amd import synth
+    if args.ingest_counters:
+        if args.calib_copy_mib <= 0:
+            raise SystemExit("--ingest-counters needs --calib-copy-mib of the profiled run")
+        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config).name)
+        return
+
     import torch
-    from paper_2305_11805_amd import nnpot, synth
+    from paper_2305_11805_amd import nnpot
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
@@ -134,10 +194,16 @@ def main():
     skin = float(w.extra.get("skin", 0.0))
     pot = nnpot.Potential(s, p, w.model, skin=skin, flags=flags)
 
-    def step():
+    def build():
         nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+
+    def energy_forces():
         nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, flags, 0, pot.E_struct,
                                pot.E_atom, pot.F, pot.ws)
+
+    def step():
+        build()
+        energy_forces()
 
     for _ in range(max(args.warmup, 1)):
         step()
@@ -145,18 +211,43 @@ def main():
     nnpot.nn_check(pot.nl)
 
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    # the timed region: K whole steps, per-stage HIP events on the library's stream
     nnpot.nn_timing(True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
+    total_ms = timed(step, args.steps)
     stages = nnpot.nn_timing_read()
     nnpot.nn_timing(False)
     nnpot.nn_check(pot.nl)
+    F = pot.F.cpu().numpy()
+
+    variants = {}
+    if not args.no_variants:
+        # E + F on the list already built (no rebuild), and the whole step
+        # replayed from a HIP graph
+        ms = timed(energy_forces, args.steps) / args.steps
+        variants["steady_state_no_rebuild"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1)}
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            step()
+        torch.cuda.synchronize()
+        graph.replay()
+        ms = timed(graph.replay, args.steps) / args.steps
+        variants["graph_replay"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1)}
+        torch.cuda.synchronize()
+        nnpot.nn_check(pot.nl)
+        assert np.array_equal(pot.F.cpu().numpy(), F), "graph replay differs from the eager step"
 
     if args.calib_copy_mib > 0:
         a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -172,14 +263,14 @@ def main():
     single_kernel = ["desc_adj", "desc_fwd", "mlp", "force_gather", "energy"]
     dom = max(single_kernel, key=lambda k: stages[k][0])
     dom_ms = stages[dom][0] / max(stages[dom][1], 1)
-    F = pot.F.cpu().numpy()
     if dom in ("desc_adj", "desc_fwd"):
         achieved = fm[dom] / (dom_ms / 1e3) / 1e12
         roof = {"kernel": {"desc_adj": "k_desc_adj", "desc_fwd": "k_desc_fwd"}[dom], "bound": "alu",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
                 "avg_launch_ms": round(dom_ms, 5), "algorithmic_flops_per_launch": fm[dom],
-                "flops_per_triplet": fm["per_triplet"][dom]}
+                "flops_per_triplet": fm["per_triplet"][dom],
+                "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4)}
     else:
         roof = {"kernel": dom, "bound": "mfma", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "avg_launch_ms": round(dom_ms, 5)}
@@ -190,6 +281,7 @@ def main():
         key = f"{roof['kernel']}:{w.name}"
         if key in cnt and cnt[key].get("source_hash") == source_hash():
             roof["traffic"] = cnt[key]["hbm_bytes_per_launch"]
+            roof["traffic_gbs"] = round(roof["traffic"] / (dom_ms / 1e3) / 1e9, 1)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -197,14 +289,14 @@ def main():
                                                         "bf16x3": "bf16x3-mlp/f32"}[args.mode],
         "data": "synthetic (seeded RSA positions, seeded N(0, 1/fan_in) weights)",
         "config": {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
-                   "neighbor_build_each_step": True, "seed": w.seed},
+                   "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
         "pairs_per_step": fm["pairs"], "triplets_per_step": fm["triplets"],
-        "force_err_max_sampled_eV_per_A": sampled_force_error(w, F),
+        "variants": variants,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"], out["force_err_max_sampled_eV_per_A"] = oracle_leg(w, F)
     print(json.dumps(out), flush=True)
 
 

@@ -94,7 +94,7 @@ typedef struct nn_system {
  *   (n_a, n_b, n_c, 0), rev [capacity] int32 (index of the reverse entry
  *   (j -> i, -n)), ref_pos [N][3] FP64 (positions at the last build),
  *   meta [8] int64 (nnz, valid, builds, rebuilt-last-call, error bits,
- *   longest row, -, -); zero meta once before the first build.
+ *   -, -, -); zero meta once before the first build.
  * radius is written by nn_build_neighbors (host field).
  */
 typedef struct nn_nlist {

@@ -29,7 +29,7 @@ enum : int64_t {
 };
 
 // Layout of the device metadata block of a neighbor list (nl->meta, int64[8]).
-enum { kMetaNnz = 0, kMetaValid = 1, kMetaBuilds = 2, kMetaRebuilt = 3, kMetaErr = 4, kMetaMaxRow = 5 };
+enum { kMetaNnz = 0, kMetaValid = 1, kMetaBuilds = 2, kMetaRebuilt = 3, kMetaErr = 4 };
 
 // Per-structure geometry computed on the device before binning.
 struct alignas(16) StructGeom {

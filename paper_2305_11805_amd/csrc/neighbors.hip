@@ -545,7 +545,6 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
     if (lane == 0) {
       row_count[i] = count;
       if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
-      atomicMax((unsigned long long*)&meta[kMetaMaxRow], (unsigned long long)count);
     }
     if (__any(shift_bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
     return;
