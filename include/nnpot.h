@@ -280,9 +280,10 @@ enum {
   NN_STAGE_WEIGHTS = 2,     /* BF16 weight copies                            */
   NN_STAGE_DESC_FWD = 3,    /* radial + angular descriptors                  */
   NN_STAGE_MLP = 4,         /* per-species MLP forward + backward            */
-  NN_STAGE_ENERGY = 5,      /* per-structure FP64 energy                     */
+  NN_STAGE_ENERGY = 5,      /* per-structure FP64 energy (energy-only calls)  */
   NN_STAGE_DESC_ADJ = 6,    /* descriptor adjoint: per-pair gradients        */
-  NN_STAGE_FORCE_GATHER = 7,/* per-atom forces from per-pair gradients       */
+  NN_STAGE_FORCE_GATHER = 7,/* per-atom forces from per-pair gradients, and
+                             * the FP64 energy sums when forces are asked for */
   NN_STAGE_DESC_JAC = 8,    /* stored Jacobian of the descriptors            */
   NN_STAGE_JAC_CONTRACT = 9,/* per-pair gradients from the stored Jacobian   */
   NN_STAGE_COUNT = 10

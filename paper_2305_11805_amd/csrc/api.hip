@@ -97,8 +97,10 @@ struct Carver {
 struct Layout {
   // neighbor build
   StructGeom* geom;
-  int64_t *n_bins, *bin_base, *bin_count, *bin_start, *bin_fill, *row_count, *count_off, *scan_tmp, *count_meta;
-  int32_t *bin_atoms, *atom_bin, *flag;
+  int64_t *n_bins, *bin_base, *bin_count, *bin_start, *row_count, *count_off, *scan_tmp, *count_meta;
+  int32_t *atom_bin, *bin_rank, *flag;
+  int4* bin_m;
+  double4* bin_x;
   int64_t max_bins;
   // energy / forces
   float *G, *lam, *E_atom;
@@ -134,8 +136,9 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
   L.bin_base = c.take<int64_t>(B + 1);
   L.bin_count = c.take<int64_t>(L.max_bins + 1);
   L.bin_start = c.take<int64_t>(L.max_bins + 1);
-  L.bin_fill = c.take<int64_t>(L.max_bins + 1);
-  L.bin_atoms = c.take<int32_t>(N);
+  L.bin_rank = c.take<int32_t>(N);
+  L.bin_m = c.take<int4>(N);
+  L.bin_x = c.take<double4>(N);
   L.atom_bin = c.take<int32_t>(4 * N);
   L.row_count = c.take<int64_t>(N + 1);
   L.count_off = c.take<int64_t>(N + 1);
@@ -291,8 +294,9 @@ static NbLaunch nb_launch(const nn_system* sys, const Layout& L, double radius, 
   n.bin_base = L.bin_base;
   n.bin_count = L.bin_count;
   n.bin_start = L.bin_start;
-  n.bin_fill = L.bin_fill;
-  n.bin_atoms = L.bin_atoms;
+  n.bin_rank = L.bin_rank;
+  n.bin_m = L.bin_m;
+  n.bin_x = L.bin_x;
   n.atom_bin = L.atom_bin;
   n.scan_tmp = L.scan_tmp;
   n.flag = L.flag;
@@ -508,11 +512,10 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     StageTimer t(NN_STAGE_MLP, s);
     launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
   }
-  {
+  if (!F) {
     StageTimer t(NN_STAGE_ENERGY, s);
     launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
-  }
-  if (F) {
+  } else {
     if (stored) {
       StageTimer t(NN_STAGE_JAC_CONTRACT, s);
       launch_jac_contract(*sys, *nl, P, L.lam, L.jac, L.pg, s);
@@ -520,8 +523,9 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
       StageTimer t(NN_STAGE_DESC_ADJ, s);
       launch_desc_adj(*sys, *nl, P, L.lam, L.pg, s);
     }
+    // the per-structure energy sums ride along in the gather's launch
     StageTimer t(NN_STAGE_FORCE_GATHER, s);
-    launch_force_gather(*sys, *nl, L.pg, F, s);
+    launch_force_gather(*sys, *nl, L.pg, F, EnergyJob{a.E_atom, sys->atom_ptr, sys->n_structs, E_struct}, s);
   }
   return check_launch("nn_energy_forces");
 }

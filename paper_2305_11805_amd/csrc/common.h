@@ -113,8 +113,9 @@ struct NbLaunch {
   int64_t* bin_base; // [B+1]
   int64_t* bin_count;
   int64_t* bin_start;
-  int64_t* bin_fill;
-  int32_t* bin_atoms;
+  int32_t* bin_rank;  // [N] rank of each atom inside its bin
+  int4* bin_m;       // [N] per binned slot: atom j and its whole-cell offsets
+  double4* bin_x;    // [N] per binned slot: the position of j (copied bit for bit)
   int32_t* atom_bin;
   int64_t* scan_tmp;
   int32_t* flag;
@@ -128,7 +129,30 @@ bool desc_supported(int nt, int nra);
 void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s);
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                      hipStream_t s);
-void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, hipStream_t s);
+// FP64 sum of E_atom over structure c by one block of 256 threads (a fixed
+// tree, so the result is the same on every run).
+__device__ __forceinline__ void energy_block_sum(const float* __restrict__ E_atom, const int64_t* __restrict__ atom_ptr,
+                                                 int64_t N, int c, double* __restrict__ E_struct) {
+  __shared__ double sh[256];
+  const int64_t a0 = min(max(atom_ptr[c], (int64_t)0), N), a1 = min(max(atom_ptr[c + 1], a0), N);
+  double acc = 0.0;
+  for (int64_t a = a0 + threadIdx.x; a < a1; a += 256) acc += (double)E_atom[a];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E_struct[c] = sh[0];
+}
+struct EnergyJob {  // per-structure energy sums run by extra blocks of the gather
+  const float* E_atom;
+  const int64_t* atom_ptr;
+  int32_t B;
+  double* E_struct;
+};
+void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, const EnergyJob& ej,
+                         hipStream_t s);
 size_t jacobian_floats(int n_rad, int S, int nt, int nra, int64_t capacity);
 void launch_desc_jac(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s);
 void launch_jac_contract(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam,

@@ -551,7 +551,12 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
 // by a fixed xor-shuffle tree, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ rev, const float4* __restrict__ pg,
-                                                      float* __restrict__ F, const int64_t* meta) {
+                                                      float* __restrict__ F, const int64_t* meta,
+                                                      unsigned n_gather_blocks, EnergyJob ej) {
+  if (blockIdx.x >= n_gather_blocks) {
+    energy_block_sum(ej.E_atom, ej.atom_ptr, N, (int)(blockIdx.x - n_gather_blocks), ej.E_struct);
+    return;
+  }
   const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
   float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -658,10 +663,14 @@ void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& 
   NNP_DISPATCH(A, B, (launch_adj_t<A, B>(sys, nl, P, lam, pg, s)));
 }
 
-void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, hipStream_t s) {
-  if (sys.n_atoms == 0) return;
-  hipLaunchKernelGGL(k_force_gather, dim3((unsigned)((sys.n_atoms * 16 + 255) / 256)), dim3(256), 0, s, sys.n_atoms,
-                     nl.offsets, nl.rev, pg, F, nl.meta);
+// F from the per-entry gradients; blocks past the gather's sum the
+// per-structure energies (ej.B of them) in the same launch.
+void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, const EnergyJob& ej,
+                         hipStream_t s) {
+  const unsigned ng = (unsigned)((sys.n_atoms * 16 + 255) / 256);
+  if (ng + (unsigned)ej.B == 0) return;
+  hipLaunchKernelGGL(k_force_gather, dim3(ng + (unsigned)ej.B), dim3(256), 0, s, sys.n_atoms, nl.offsets, nl.rev, pg,
+                     F, nl.meta, ng, ej);
 }
 
 

@@ -67,15 +67,92 @@ __global__ void __launch_bounds__(64) k_sp_scatter(const int32_t* __restrict__ s
   if (blockIdx.x == 0 && lane <= S) sp_start[lane] = off[(int64_t)lane * nblk];
 }
 
+// The same grouping in one block for N <= kSpSmall: each thread counts the
+// species of a contiguous run of atoms, the runs' counts are scanned per
+// species, and each thread then places its run.
+constexpr int kSpThreads = 1024;
+constexpr int64_t kSpSmall = 64 * 1024;
+
+__global__ void __launch_bounds__(kSpThreads) k_sp_group_small(const int32_t* __restrict__ species, int64_t N, int S,
+                                                               int32_t* __restrict__ perm,
+                                                               int64_t* __restrict__ sp_start) {
+  constexpr int NW = kSpThreads / 64;
+  __shared__ int wtot[NW][NN_MAX_SPECIES];
+  __shared__ int64_t start[NN_MAX_SPECIES + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t per = (N + kSpThreads - 1) / kSpThreads;
+  const int64_t b = (int64_t)t * per, e = min(b + per, N);
+  int cnt[NN_MAX_SPECIES], incl[NN_MAX_SPECIES];
+#pragma unroll
+  for (int q = 0; q < NN_MAX_SPECIES; ++q) cnt[q] = 0;
+  for (int64_t k = b; k < e; ++k) {
+    const int sp = species[k];
+#pragma unroll
+    for (int q = 0; q < NN_MAX_SPECIES; ++q) cnt[q] += (sp == q && q < S) ? 1 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < NN_MAX_SPECIES; ++q) {
+    int x = cnt[q];
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(x, off);
+      if (lane >= off) x += v;
+    }
+    incl[q] = x;
+    if (lane == 63) wtot[w][q] = x;
+  }
+  __syncthreads();
+  if (t < NN_MAX_SPECIES) {  // thread q: exclusive scan of species q over the waves
+    int run = 0;
+    for (int v = 0; v < NW; ++v) {
+      const int x = wtot[v][t];
+      wtot[v][t] = run;
+      run += x;
+    }
+    start[t + 1] = run;  // species total for now
+  }
+  __syncthreads();
+  if (t == 0) {
+    start[0] = 0;
+    for (int q = 0; q < NN_MAX_SPECIES; ++q) start[q + 1] = start[q] + (q < S ? start[q + 1] : 0);
+  }
+  __syncthreads();
+  int64_t at[NN_MAX_SPECIES];
+#pragma unroll
+  for (int q = 0; q < NN_MAX_SPECIES; ++q) at[q] = start[q] + wtot[w][q] + incl[q] - cnt[q];
+  for (int64_t k = b; k < e; ++k) {
+    const int sp = species[k];
+#pragma unroll
+    for (int q = 0; q < NN_MAX_SPECIES; ++q)
+      if (sp == q && q < S) perm[at[q]++] = (int32_t)k;
+  }
+  if (t <= S) sp_start[t] = start[t];
+}
+
 // ---------------------------------------------------------------------------
 // fused MLP tile kernel
 // ---------------------------------------------------------------------------
 
 
-// Row operand of a 16x16x4 FP32 MFMA from a row-major [16][ld] buffer.
-__device__ __forceinline__ float a_f32(const float* buf, int ld, int k0) {
-  const int l = threadIdx.x & 63;  // lane within the wave
-  return buf[(l & 15) * ld + k0 + (l >> 4)];
+// FP32 products use v_mfma_f32_16x16x4_f32 over 16-wide k blocks: lane
+// (lm, lk) holds the four k values kb + 4 lk + i (i = 0..3) of its A row and
+// B column, and the i-th of four MFMAs takes element i.  The four MFMAs
+// together cover the whole block (each product a_k b_k once), so every lane
+// fetches its operands as one 16-byte vector.
+__device__ __forceinline__ float4 ld4(const float* p, int k, int kmax, bool vec) {
+  if (vec && k + 3 < kmax) return *reinterpret_cast<const float4*>(p + k);
+  float4 v;
+  v.x = k < kmax ? p[k] : 0.f;
+  v.y = k + 1 < kmax ? p[k + 1] : 0.f;
+  v.z = k + 2 < kmax ? p[k + 2] : 0.f;
+  v.w = k + 3 < kmax ? p[k + 3] : 0.f;
+  return v;
+}
+
+__device__ __forceinline__ floatx4 mma4_f32(floatx4 acc, const float4& a, const float4& b) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
 }
 
 // Products in the MLP run in one of three modes:
@@ -145,7 +222,7 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
   constexpr bool BF = MODE != kFp32;
   constexpr int LD = HM + 4;
   constexpr int T1 = (H1T + kWaves - 1) / kWaves, T2 = (H2T + kWaves - 1) / kWaves;
-  __shared__ float buf[2][kTile * LD];
+  __shared__ __align__(16) float buf[2][kTile * LD];
   __shared__ float epart[kWaves][kTile];
   __shared__ int32_t rows[kTile];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -202,17 +279,24 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
     }
   } else {
     const float* W1 = M.W[0];
-    for (int k0 = 0; k0 < D; k0 += 4) {
-      const int k = k0 + lk;
-      const float a = (arow >= 0 && k < D) ? Grow[k] : 0.f;
+    const bool vec = ((((uintptr_t)W1) | ((uintptr_t)args.G)) & 15) == 0 && (D & 3) == 0;
+    for (int k0 = 0; k0 < D; k0 += 32) {
+      float4 a[2], b[2][T1];
 #pragma unroll
-      for (int u = 0; u < T1; ++u) {
-        const int n = wv + kWaves * u;
-        if (n < H1T) {
-          const float b = k < D ? W1[(int64_t)(n * 16 + lm) * D + k] : 0.f;
-          acc1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[u], 0, 0, 0);
+      for (int q = 0; q < 2; ++q) {
+        const int k = k0 + 16 * q + 4 * lk;
+        a[q] = ld4(Grow, k, arow >= 0 ? D : 0, vec);
+#pragma unroll
+        for (int u = 0; u < T1; ++u) {
+          const int n = wv + kWaves * u;
+          b[q][u] = ld4(W1 + (int64_t)(n < H1T ? n * 16 + lm : 0) * D, k, n < H1T ? D : 0, vec);
         }
       }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int u = 0; u < T1; ++u)
+          if (wv + kWaves * u < H1T) acc1[u] = mma4_f32(acc1[u], a[q], b[q][u]);
     }
   }
   float d1[T1][4];  // act'(z1) in C layout: row 4*lk + j, column n*16 + lm
@@ -255,15 +339,14 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
     }
   } else {
     const float* W2 = M.W[1];
-    for (int k0 = 0; k0 < H1; k0 += 4) {
-      const float a = a_f32(bufA, LD, k0);
+    const bool vec = (((uintptr_t)W2) & 15) == 0;
+#pragma unroll
+    for (int kb = 0; kb < H1; kb += 16) {
+      const float4 a = *reinterpret_cast<const float4*>(bufA + lm * LD + kb + 4 * lk);
 #pragma unroll
       for (int u = 0; u < T2; ++u) {
         const int n = wv + kWaves * u;
-        if (n < H2T) {
-          const float b = W2[(int64_t)(n * 16 + lm) * H1 + k0 + lk];
-          acc2[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc2[u], 0, 0, 0);
-        }
+        if (n < H2T) acc2[u] = mma4_f32(acc2[u], a, ld4(W2 + (int64_t)(n * 16 + lm) * H1, kb + 4 * lk, H1, vec));
       }
     }
   }
@@ -332,14 +415,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
     }
   } else {
     const float* W2 = M.W[1];  // [H2][H1]: B[k][n] = W2[k][n]
-    for (int k0 = 0; k0 < H2; k0 += 4) {
-      const float a = a_f32(bufB, LD, k0);
+#pragma unroll
+    for (int kb = 0; kb < H2; kb += 16) {
+      const float4 a = *reinterpret_cast<const float4*>(bufB + lm * LD + kb + 4 * lk);
+      const float* w = W2 + (int64_t)(kb + 4 * lk) * H1 + lm;
 #pragma unroll
       for (int u = 0; u < T1; ++u) {
         const int n = wv + kWaves * u;
         if (n < H1T) {
-          const float b = W2[(int64_t)(k0 + lk) * H1 + n * 16 + lm];
-          acc1[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc1[u], 0, 0, 0);
+          float4 b;
+          b.x = w[n * 16];
+          b.y = w[H1 + n * 16];
+          b.z = w[2 * H1 + n * 16];
+          b.w = w[3 * H1 + n * 16];
+          acc1[u] = mma4_f32(acc1[u], a, b);
         }
       }
     }
@@ -383,13 +472,21 @@ __global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
       }
     } else {
       const float* W1 = M.W[0];  // [H1][D]: B[k][n] = W1[k][n]
-      for (int k0 = 0; k0 < H1; k0 += 4) {
-        const float a = a_f32(bufA, LD, k0);
+#pragma unroll
+      for (int kb = 0; kb < H1; kb += 16) {
+        const float4 a = *reinterpret_cast<const float4*>(bufA + lm * LD + kb + 4 * lk);
+        const float* w = W1 + (int64_t)(kb + 4 * lk) * D;
 #pragma unroll
         for (int n = 0; n < CH; ++n) {
           const int col = (c0 + n * kWaves) * 16 + lm;
-          const float b = col < D ? W1[(int64_t)(k0 + lk) * D + col] : 0.f;
-          acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[n], 0, 0, 0);
+          float4 b = {0.f, 0.f, 0.f, 0.f};
+          if (col < D) {
+            b.x = w[col];
+            b.y = w[D + col];
+            b.z = w[2 * D + col];
+            b.w = w[3 * D + col];
+          }
+          acc[n] = mma4_f32(acc[n], a, b);
         }
       }
     }
@@ -437,18 +534,7 @@ __global__ void k_convert_bf16(ConvJob job) {
 __global__ void __launch_bounds__(256) k_energy_reduce(const float* __restrict__ E_atom,
                                                        const int64_t* __restrict__ atom_ptr, int64_t N,
                                                        double* __restrict__ E_struct) {
-  __shared__ double sh[256];
-  const int c = blockIdx.x;
-  const int64_t a0 = min(max(atom_ptr[c], (int64_t)0), N), a1 = min(max(atom_ptr[c + 1], a0), N);
-  double acc = 0.0;
-  for (int64_t a = a0 + threadIdx.x; a < a1; a += 256) acc += (double)E_atom[a];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) E_struct[c] = sh[0];
+  energy_block_sum(E_atom, atom_ptr, N, blockIdx.x, E_struct);
 }
 
 // ---------------------------------------------------------------------------
@@ -457,6 +543,10 @@ __global__ void __launch_bounds__(256) k_energy_reduce(const float* __restrict__
 
 void launch_species_group(const int32_t* species, int64_t N, int S, int64_t* cnt, int64_t* off, int64_t* scan_tmp,
                           int32_t* perm, int64_t* sp_start, hipStream_t s) {
+  if (N <= kSpSmall) {
+    hipLaunchKernelGGL(k_sp_group_small, dim3(1), dim3(kSpThreads), 0, s, species, N, S, perm, sp_start);
+    return;
+  }
   const int64_t nblk = (N + 63) / 64 > 0 ? (N + 63) / 64 : 1;
   hipLaunchKernelGGL(k_sp_count, dim3((unsigned)nblk), dim3(64), 0, s, species, N, S, nblk, cnt);
   exclusive_scan_i64(cnt, off, (int64_t)S * nblk, scan_tmp, s, nullptr);

@@ -7,6 +7,8 @@
 // build can sit in a captured graph without host decisions.
 #include <math.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace nnp {
@@ -91,10 +93,25 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t n, const in
 constexpr int kScanSmallThreads = 1024;
 constexpr int64_t kScanSmall = 64 * 1024;
 
+struct CapacityJob {  // decision taken after the scan of the row counts
+  int64_t capacity;
+  int64_t* meta;
+  int32_t* flag;
+};
+__device__ void capacity_decision(const CapacityJob& cj, int64_t nnz);
+
+template <bool CAP>
 __global__ void __launch_bounds__(kScanSmallThreads) k_scan_small(const int64_t* __restrict__ in, int64_t n,
                                                                   const int64_t* __restrict__ n_dev,
-                                                                  int64_t* __restrict__ out, const int32_t* pred) {
-  if (pred && !*pred) return;
+                                                                  int64_t* __restrict__ out, const int32_t* pred,
+                                                                  CapacityJob cj) {
+  if (pred && !*pred) {
+    if (CAP && threadIdx.x == 0) {
+      cj.flag[1] = 0;
+      cj.meta[kMetaRebuilt] = 0;
+    }
+    return;
+  }
   __shared__ int64_t wsum[kScanSmallThreads / 64];
   if (n_dev) n = min(n, max(*n_dev, (int64_t)0));
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -124,13 +141,17 @@ __global__ void __launch_bounds__(kScanSmallThreads) k_scan_small(const int64_t*
     out[k] = run;
     run += v;
   }
-  if (t == kScanSmallThreads - 1) out[n] = wsum[kScanSmallThreads / 64 - 1];
+  if (t == kScanSmallThreads - 1) {
+    out[n] = wsum[kScanSmallThreads / 64 - 1];
+    if (CAP) capacity_decision(cj, wsum[kScanSmallThreads / 64 - 1]);
+  }
 }
 
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s,
                         const int32_t* pred, const int64_t* n_dev) {
   if (n <= kScanSmall) {
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanSmallThreads), 0, s, in, n, n_dev, out, pred);
+    hipLaunchKernelGGL(k_scan_small<false>, dim3(1), dim3(kScanSmallThreads), 0, s, in, n, n_dev, out, pred,
+                       CapacityJob{});
     return;
   }
   int64_t nb = (n + kScanTile - 1) / kScanTile;
@@ -222,11 +243,16 @@ __device__ __forceinline__ void frac(const double* inv, const double* x, double 
 // take the all-pairs path with an image bound K_d = floor(radius/w_d +
 // spread_d) + 1 on periodic directions (spread of the fractional
 // coordinates); larger ones are binned with bins >= radius wide.
+// Every block of the grid (B or more) also clears its share of the bin
+// counts [0, n_zero).  With one structure, bin_base is written here too.
 __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
                           const double* __restrict__ cell, const uint8_t* __restrict__ pbc, int32_t B,
                           double radius, StructGeom* __restrict__ geom, int64_t* __restrict__ n_bins,
+                          int64_t* __restrict__ bin_count, int64_t n_zero, int64_t* __restrict__ bin_base_one,
                           int64_t* meta, const int32_t* flag) {
   if (!*flag) return;
+  for (int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x; k < n_zero; k += (int64_t)gridDim.x * 64)
+    bin_count[k] = 0;
   const int c = blockIdx.x;
   if (c >= B) return;
   __shared__ double h[9], inv[9];
@@ -306,17 +332,12 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
   g.bin_base = 0;
   geom[c] = g;
   n_bins[c] = nbins;
-}
-
-
-__global__ void k_zero2_i64(int64_t* p, int64_t* q, int64_t n, const int32_t* flag) {
-  if (flag && !*flag) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    p[i] = 0;
-    q[i] = 0;
+  if (bin_base_one) {
+    bin_base_one[0] = 0;
+    bin_base_one[1] = nbins;
   }
 }
+
 
 __device__ __forceinline__ int struct_of(const int64_t* atom_ptr, int32_t B, int64_t i) {
   int lo = 0, hi = B - 1;
@@ -350,7 +371,8 @@ __device__ __forceinline__ void bin_coords(const StructGeom& g, const uint8_t* p
 __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
                          const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
                          const int64_t* __restrict__ bin_base, int64_t* __restrict__ bin_count,
-                         int32_t* __restrict__ atom_bin, int64_t* meta, const int32_t* flag) {
+                         int32_t* __restrict__ atom_bin, int32_t* __restrict__ bin_rank, int64_t* meta,
+                         const int32_t* flag) {
   if (!*flag) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -373,18 +395,24 @@ __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restri
   atom_bin[4 * i + 1] = m[0];
   atom_bin[4 * i + 2] = m[1];
   atom_bin[4 * i + 3] = m[2];
-  atomicAdd((unsigned long long*)&bin_count[bin], 1ull);
+  bin_rank[i] = (int32_t)atomicAdd((unsigned long long*)&bin_count[bin], 1ull);
 }
 
-__global__ void k_nb_scatter(int64_t N, const int32_t* __restrict__ atom_bin, const int64_t* __restrict__ bin_start,
-                             int64_t* __restrict__ bin_fill, int32_t* __restrict__ bin_atoms, const int32_t* flag) {
+// Atoms into bin order, with a copy of each atom's position and whole-cell
+// offsets in the same order, so that the row passes read the candidates of
+// a bin as contiguous memory.  The order inside a bin is the order in which
+// the binning pass's atomics ran (rows are sorted afterwards).
+__global__ void k_nb_scatter(int64_t N, const double* __restrict__ pos, const int32_t* __restrict__ atom_bin,
+                             const int32_t* __restrict__ bin_rank, const int64_t* __restrict__ bin_start,
+                             int4* __restrict__ bin_m, double4* __restrict__ bin_x, const int32_t* flag) {
   if (!*flag) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   int32_t bin = atom_bin[4 * i];
   if (bin < 0) return;
-  unsigned long long k = atomicAdd((unsigned long long*)&bin_fill[bin], 1ull);
-  bin_atoms[bin_start[bin] + (int64_t)k] = (int32_t)i;
+  const int64_t k = bin_start[bin] + bin_rank[i];
+  bin_m[k] = make_int4((int)i, atom_bin[4 * i + 1], atom_bin[4 * i + 2], atom_bin[4 * i + 3]);
+  bin_x[k] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
 }
 
 __device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc) {
@@ -393,48 +421,61 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc)
 }
 __device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry_key(j, s.x, s.y, s.z); }
 
-// One wave per atom i enumerates its candidates, 64 at a time, and applies
-// the FP64 inclusion test; accepted entries are counted with ballots.
+// A block of kRowWaves waves per atom i enumerates its candidates,
+// kRowThreads at a time, and applies the FP64 inclusion test.  Each wave
+// counts its accepted entries with a ballot and reserves room for them with
+// one LDS atomic, so the slots are unique (their order is not: the fill
+// sorts the keys).
 //   COUNT: row_count[i] = number of entries.
 //   FILL : the entries' keys (j, n_a, n_b, n_c) are collected in LDS, sorted
 //          (bitonic) and written to the row at offsets[i].
 // Small structures: candidates are every (j, image) with |n_d| <= K_d.
 // Binned structures: the atoms of the 27 bins around i's bin, with the image
 // that the bin wrap and the whole-cell offsets of i and j imply.
+constexpr int kRowWaves = 4;
+constexpr int kRowThreads = 64 * kRowWaves;
+
 template <bool FILL>
-__global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
-                                                const uint8_t* __restrict__ pbc, int32_t B, int64_t N,
-                                                const StructGeom* __restrict__ geom,
-                                                const int64_t* __restrict__ bin_base,
-                                                const int64_t* __restrict__ bin_start,
-                                                const int32_t* __restrict__ bin_atoms,
-                                                const int32_t* __restrict__ atom_bin, double r2max,
-                                                int64_t* __restrict__ row_count, const int64_t* __restrict__ offsets,
-                                                int32_t* __restrict__ nbr, int8_t* __restrict__ shift, int64_t* meta,
-                                                const int32_t* flag) {
+__global__ void __launch_bounds__(kRowThreads) k_nb_rows(const double* __restrict__ pos,
+                                                         const int64_t* __restrict__ atom_ptr,
+                                                         const uint8_t* __restrict__ pbc, int32_t B, int64_t N,
+                                                         const StructGeom* __restrict__ geom,
+                                                         const int64_t* __restrict__ bin_base,
+                                                         const int64_t* __restrict__ bin_start,
+                                                         const int4* __restrict__ bin_m,
+                                                         const double4* __restrict__ bin_x,
+                                                         const int32_t* __restrict__ atom_bin, double r2max,
+                                                         int64_t* __restrict__ row_count,
+                                                         const int64_t* __restrict__ offsets,
+                                                         int32_t* __restrict__ nbr, int8_t* __restrict__ shift,
+                                                         int64_t* meta, const int32_t* flag) {
   if (FILL ? !flag[1] : !flag[0]) return;
   __shared__ uint64_t key[FILL ? kRowMax : 1];
+  __shared__ int n_acc, any_bad;
   const int64_t i = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   if (i >= N) return;
   const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   if (!(isfinite(xi[0]) && isfinite(xi[1]) && isfinite(xi[2]))) {
-    if (!FILL && lane == 0) {
+    if (!FILL && tid == 0) {
       row_count[i] = 0;
       atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
     }
     return;
   }
+  if (tid == 0) {
+    n_acc = 0;
+    any_bad = 0;
+  }
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int c = struct_of(atom_ptr, B, i);
   const StructGeom& g = geom[c];
-  int count = 0;
   bool shift_bad = false;
-  auto test = [&](bool active, int32_t j, int na, int nb, int nc) {
+  auto test = [&](bool active, int32_t j, const double* xj, int na, int nb, int nc) {
     bool acc = false;
     if (active && !(j == i && na == 0 && nb == 0 && nc == 0)) {
       double d[3];
-      displacement64(xi, pos + 3 * (int64_t)j, g.h, na, nb, nc, d);
+      displacement64(xi, xj, g.h, na, nb, nc, d);
       acc = norm2_64(d) < r2max;
       if (acc && (na < -127 || na > 127 || nb < -127 || nb > 127 || nc < -127 || nc > 127)) {
         shift_bad = true;
@@ -442,20 +483,24 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
       }
     }
     const uint64_t m = __ballot(acc);
+    if (m == 0) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&n_acc, __popcll(m));
+    base = __shfl(base, 0);
     if (FILL && acc) {
-      const int slot = count + __popcll(m & lt);
+      const int slot = base + __popcll(m & lt);
       if (slot < kRowMax) key[slot] = entry_key(j, na, nb, nc);
     }
-    count += __popcll(m);
   };
   if (g.small) {
+    __syncthreads();
     const int K0 = g.nb[0], K1 = g.nb[1], K2 = g.nb[2];
     const int w1 = 2 * K1 + 1, w2 = 2 * K2 + 1;
     const int64_t nimg = (int64_t)(2 * K0 + 1) * w1 * w2;
     const int64_t a0 = atom_ptr[c];
     const int64_t total = (atom_ptr[c + 1] - a0) * nimg;
-    for (int64_t t0 = 0; t0 < total; t0 += kWave) {
-      const int64_t t = t0 + lane;
+    for (int64_t t0 = 0; t0 < total; t0 += kRowThreads) {
+      const int64_t t = t0 + tid;
       const bool active = t < total;
       const int64_t jj = active ? t / nimg : 0;
       int im = active ? (int)(t - jj * nimg) : 0;
@@ -463,66 +508,68 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
       im /= w2;
       const int nb = im % w1 - K1;
       const int na = im / w1 - K0;
-      test(active, (int32_t)(a0 + jj), na, nb, nc);
+      test(active, (int32_t)(a0 + jj), pos + 3 * (a0 + jj), na, nb, nc);
     }
   } else {
     // the 27 bins around i's bin, flattened into one candidate index space:
-    // lane b < 27 describes bin b (first atom, atom count, lattice wrap), a
-    // prefix sum over the counts maps candidate t to (bin, atom)
+    // lane b < 27 of wave 0 describes bin b (first atom, atom count, lattice
+    // wrap), a prefix sum over the counts maps candidate t to (bin, atom)
     __shared__ int64_t b_start[27];
     __shared__ int32_t b_pre[28];
     __shared__ int32_t b_img[27][3];
     const uint8_t* p3 = pbc + 3 * c;
-    int mi[3];
-    mi[0] = atom_bin[4 * i + 1];
-    mi[1] = atom_bin[4 * i + 2];
-    mi[2] = atom_bin[4 * i + 3];
-    int cnt_b = 0;
-    if (lane < 27) {
-      const int64_t base_c = bin_base[c];
-      int64_t local = atom_bin[4 * i] - base_c;
-      int bi[3];
-      bi[2] = (int)(local % g.nb[2]);
-      local /= g.nb[2];
-      bi[1] = (int)(local % g.nb[1]);
-      bi[0] = (int)(local / g.nb[1]);
-      const int dd[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
-      int bb[3], wr[3];
-      bool skip = false;
-      for (int d = 0; d < 3; ++d) {
-        int k = bi[d] + dd[d];
-        wr[d] = 0;
-        if (k < 0 || k >= g.nb[d]) {
-          if (!p3[d]) {
-            skip = true;
-            break;
+    if (tid < 64) {
+      int cnt_b = 0;
+      if (lane < 27) {
+        int mi[3];
+        mi[0] = atom_bin[4 * i + 1];
+        mi[1] = atom_bin[4 * i + 2];
+        mi[2] = atom_bin[4 * i + 3];
+        const int64_t base_c = bin_base[c];
+        int64_t local = atom_bin[4 * i] - base_c;
+        int bi[3];
+        bi[2] = (int)(local % g.nb[2]);
+        local /= g.nb[2];
+        bi[1] = (int)(local % g.nb[1]);
+        bi[0] = (int)(local / g.nb[1]);
+        const int dd[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
+        int bb[3], wr[3];
+        bool skip = false;
+        for (int d = 0; d < 3; ++d) {
+          int k = bi[d] + dd[d];
+          wr[d] = 0;
+          if (k < 0 || k >= g.nb[d]) {
+            if (!p3[d]) {
+              skip = true;
+              break;
+            }
+            wr[d] = k < 0 ? -1 : 1;
+            k -= wr[d] * g.nb[d];
           }
-          wr[d] = k < 0 ? -1 : 1;
-          k -= wr[d] * g.nb[d];
+          bb[d] = k;
         }
-        bb[d] = k;
+        int64_t b0 = 0;
+        if (!skip) {
+          const int64_t bin = base_c + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
+          b0 = bin_start[bin];
+          cnt_b = (int)(bin_start[bin + 1] - b0);
+        }
+        b_start[lane] = b0;
+        for (int d = 0; d < 3; ++d) b_img[lane][d] = p3[d] ? wr[d] + mi[d] : 0;
       }
-      int64_t b0 = 0;
-      if (!skip) {
-        const int64_t bin = base_c + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
-        b0 = bin_start[bin];
-        cnt_b = (int)(bin_start[bin + 1] - b0);
+      // inclusive prefix of the 27 counts (wave scan)
+      int pre = cnt_b;
+      for (int off = 1; off < 32; off <<= 1) {
+        const int v = __shfl_up(pre, off);
+        if (lane >= off) pre += v;
       }
-      b_start[lane] = b0;
-      for (int d = 0; d < 3; ++d) b_img[lane][d] = p3[d] ? wr[d] + mi[d] : 0;
+      if (lane < 27) b_pre[lane + 1] = pre;
+      if (lane == 0) b_pre[0] = 0;
     }
-    // inclusive prefix of the 27 counts (wave scan)
-    int pre = cnt_b;
-    for (int off = 1; off < 32; off <<= 1) {
-      const int v = __shfl_up(pre, off);
-      if (lane >= off) pre += v;
-    }
-    if (lane < 27) b_pre[lane + 1] = pre;
-    if (lane == 0) b_pre[0] = 0;
     __syncthreads();
     const int total = b_pre[27];
-    for (int t0 = 0; t0 < total; t0 += kWave) {
-      const int t = t0 + lane;
+    for (int t0 = 0; t0 < total; t0 += kRowThreads) {
+      const int t = t0 + tid;
       const bool active = t < total;
       int b = 0;
       if (active) {  // largest b with b_pre[b] <= t
@@ -534,19 +581,32 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
         }
         b = lo;
       }
-      const int32_t j = active ? bin_atoms[b_start[b] + (t - b_pre[b])] : 0;
+      int4 mj = make_int4(0, 0, 0, 0);
+      double xj[3] = {0.0, 0.0, 0.0};
       int n[3] = {0, 0, 0};
-      if (active)
-        for (int d = 0; d < 3; ++d) n[d] = p3[d] ? b_img[b][d] - atom_bin[4 * (int64_t)j + 1 + d] : 0;
-      test(active, j, n[0], n[1], n[2]);
+      if (active) {
+        const int64_t k = b_start[b] + (t - b_pre[b]);
+        mj = bin_m[k];
+        const double4 x4 = bin_x[k];
+        xj[0] = x4.x;
+        xj[1] = x4.y;
+        xj[2] = x4.z;
+        n[0] = p3[0] ? b_img[b][0] - mj.y : 0;
+        n[1] = p3[1] ? b_img[b][1] - mj.z : 0;
+        n[2] = p3[2] ? b_img[b][2] - mj.w : 0;
+      }
+      test(active, mj.x, xj, n[0], n[1], n[2]);
     }
   }
+  if (!FILL && shift_bad) any_bad = 1;
+  __syncthreads();
+  const int count = n_acc;
   if (!FILL) {
-    if (lane == 0) {
+    if (tid == 0) {
       row_count[i] = count;
       if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+      if (any_bad) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
     }
-    if (__any(shift_bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
     return;
   }
   // FILL: sort the row's keys and write it out
@@ -554,11 +614,11 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
   if (len > kRowMax) return;  // flagged by the counting pass; the fill does not run then
   int P = 1;
   while (P < len) P <<= 1;
-  for (int t = len + lane; t < P; t += kWave) key[t] = ~0ull;
+  for (int t = len + tid; t < P; t += kRowThreads) key[t] = ~0ull;
   __syncthreads();
   for (int k = 2; k <= P; k <<= 1) {
     for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = lane; t < P; t += kWave) {
+      for (int t = tid; t < P; t += kRowThreads) {
         const int partner = t ^ jj;
         if (partner > t) {
           const uint64_t a = key[t], b = key[partner];
@@ -574,7 +634,7 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
   const int64_t e0 = offsets[i];
   const int64_t room = offsets[i + 1] - e0;
   char4* sh4 = reinterpret_cast<char4*>(shift);
-  for (int t = lane; t < len && t < room; t += kWave) {
+  for (int t = tid; t < len && t < room; t += kRowThreads) {
     const uint64_t k = key[t];
     nbr[e0 + t] = (int32_t)(k >> 24);
     char4 sv;
@@ -588,22 +648,26 @@ __global__ void __launch_bounds__(64) k_nb_rows(const double* __restrict__ pos, 
 
 // After the scan of row counts: record nnz, check the capacity, and decide
 // whether the fill runs (flag[1]).
-__global__ void k_nb_capacity(const int64_t* offsets, int64_t N, int64_t capacity, int64_t* meta, int32_t* flag) {
-  if (!flag[0]) {
-    flag[1] = 0;
-    meta[kMetaRebuilt] = 0;
-    return;
-  }
-  int64_t nnz = offsets[N];
+__device__ void capacity_decision(const CapacityJob& cj, int64_t nnz) {
+  int64_t* meta = cj.meta;
   meta[kMetaNnz] = nnz;
   meta[kMetaRebuilt] = 1;
-  if (nnz > capacity || (meta[kMetaErr] & (kErrShift | kErrTooMany | kErrNonFinite | kErrCell))) {
-    if (nnz > capacity) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrCapacity);
+  if (nnz > cj.capacity || (meta[kMetaErr] & (kErrShift | kErrTooMany | kErrNonFinite | kErrCell))) {
+    if (nnz > cj.capacity) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrCapacity);
     meta[kMetaValid] = 0;
-    flag[1] = 0;
+    cj.flag[1] = 0;
   } else {
-    flag[1] = 1;
+    cj.flag[1] = 1;
   }
+}
+
+__global__ void k_nb_capacity(const int64_t* offsets, int64_t N, CapacityJob cj) {
+  if (!cj.flag[0]) {
+    cj.flag[1] = 0;
+    cj.meta[kMetaRebuilt] = 0;
+    return;
+  }
+  capacity_decision(cj, offsets[N]);
 }
 
 // Reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
@@ -664,32 +728,38 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   if (use_skin && L.nl && L.nl->ref_pos && N > 0)
     hipLaunchKernelGGL(k_skin_check, dim3(gN), dim3(256), 0, s, sys->pos, L.nl->ref_pos, N, 0.25 * skin * skin,
                        L.meta, L.flag, 1);
+  const int64_t n_zero = L.max_bins + 1;
+  const unsigned gGeom = (unsigned)std::max<int64_t>(B, std::min<int64_t>((n_zero + 1023) / 1024, 4096));
   if (B > 0)
-    hipLaunchKernelGGL(k_nb_geom, dim3(B), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B, L.radius,
-                       L.geom, L.n_bins, L.meta, L.flag);
-  exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
-  const unsigned gB = (unsigned)((L.max_bins + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_zero2_i64, dim3(gB), dim3(256), 0, s, L.bin_count, L.bin_fill, L.max_bins + 1, L.flag);
+    hipLaunchKernelGGL(k_nb_geom, dim3(gGeom), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B,
+                       L.radius, L.geom, L.n_bins, L.bin_count, n_zero, B == 1 ? L.bin_base : (int64_t*)nullptr,
+                       L.meta, L.flag);
+  if (B != 1) exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
   const double r2 = L.radius * L.radius;
   if (N > 0)
     hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                       L.bin_base, L.bin_count, L.atom_bin, L.meta, L.flag);
+                       L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.meta, L.flag);
   exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag, L.bin_base + B);
   if (N > 0) {
-    hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, L.atom_bin, L.bin_start, L.bin_fill, L.bin_atoms,
-                       L.flag);
-    hipLaunchKernelGGL(k_nb_rows<false>, dim3((unsigned)N), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N,
-                       L.geom, L.bin_base, L.bin_start, L.bin_atoms, L.atom_bin, r2, L.counts,
+    hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, sys->pos, L.atom_bin, L.bin_rank, L.bin_start,
+                       L.bin_m, L.bin_x, L.flag);
+    hipLaunchKernelGGL(k_nb_rows<false>, dim3((unsigned)N), dim3(kRowThreads), 0, s, sys->pos, sys->atom_ptr,
+                       sys->pbc, B, N, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, L.atom_bin, r2, L.counts,
                        (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, L.meta, L.flag);
   }
-  exclusive_scan_i64(L.counts, L.offsets, N, L.scan_tmp, s, L.flag);
-  hipLaunchKernelGGL(k_nb_capacity, dim3(1), dim3(1), 0, s, L.offsets, N,
-                     count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag);
+  const CapacityJob cj{count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag};
+  if (N <= kScanSmall) {
+    hipLaunchKernelGGL(k_scan_small<true>, dim3(1), dim3(kScanSmallThreads), 0, s, L.counts, N,
+                       (const int64_t*)nullptr, L.offsets, L.flag, cj);
+  } else {
+    exclusive_scan_i64(L.counts, L.offsets, N, L.scan_tmp, s, L.flag);
+    hipLaunchKernelGGL(k_nb_capacity, dim3(1), dim3(1), 0, s, L.offsets, N, cj);
+  }
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  hipLaunchKernelGGL(k_nb_rows<true>, dim3((unsigned)N), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N,
-                     L.geom, L.bin_base, L.bin_start, L.bin_atoms, L.atom_bin, r2, (int64_t*)nullptr, nl->offsets,
-                     nl->nbr, nl->shift, L.meta, L.flag);
+  hipLaunchKernelGGL(k_nb_rows<true>, dim3((unsigned)N), dim3(kRowThreads), 0, s, sys->pos, sys->atom_ptr,
+                     sys->pbc, B, N, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, L.atom_bin, r2, (int64_t*)nullptr,
+                     nl->offsets, nl->nbr, nl->shift, L.meta, L.flag);
   hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev,
                      sys->pos, nl->ref_pos, L.meta, L.flag);
 }
