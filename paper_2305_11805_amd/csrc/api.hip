@@ -101,6 +101,8 @@ struct Layout {
   int32_t *atom_bin, *bin_rank, *flag;
   int4* bin_m;
   double4* bin_x;
+  uint64_t* row_keys;
+  int kslot;
   int64_t max_bins;
   // energy / forces
   float *G, *lam, *E_atom;
@@ -139,6 +141,8 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
   L.bin_rank = c.take<int32_t>(N);
   L.bin_m = c.take<int4>(N);
   L.bin_x = c.take<double4>(N);
+  L.kslot = row_key_slot(N, capacity);
+  L.row_keys = c.take<uint64_t>((size_t)N * L.kslot);
   L.atom_bin = c.take<int32_t>(4 * N);
   L.row_count = c.take<int64_t>(N + 1);
   L.count_off = c.take<int64_t>(N + 1);
@@ -297,6 +301,8 @@ static NbLaunch nb_launch(const nn_system* sys, const Layout& L, double radius, 
   n.bin_rank = L.bin_rank;
   n.bin_m = L.bin_m;
   n.bin_x = L.bin_x;
+  n.row_keys = L.row_keys;
+  n.kslot = L.kslot;
   n.atom_bin = L.atom_bin;
   n.scan_tmp = L.scan_tmp;
   n.flag = L.flag;

@@ -116,12 +116,17 @@ struct NbLaunch {
   int32_t* bin_rank;  // [N] rank of each atom inside its bin
   int4* bin_m;       // [N] per binned slot: atom j and its whole-cell offsets
   double4* bin_x;    // [N] per binned slot: the position of j (copied bit for bit)
+  uint64_t* row_keys; // [N][kslot] sorted keys of each row (counting pass)
+  int kslot;
   int32_t* atom_bin;
   int64_t* scan_tmp;
   int32_t* flag;
   int64_t* meta;
   int64_t max_bins;
 };
+// Keys per atom in the counting pass's slab for a list of `capacity` entries
+// over n_atoms atoms (0 when there is no list to fill).
+int row_key_slot(int64_t n_atoms, int64_t capacity);
 void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_only, hipStream_t s);
 
 // descriptors.hip

@@ -187,6 +187,7 @@ __global__ void k_nb_prep(const int64_t* __restrict__ atom_ptr, int32_t B, int64
   } else {
     flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
   }
+  flag[2] = 0;  // raised by the counting pass if a row does not fit its key slab
 }
 
 __global__ void k_skin_check(const double* __restrict__ pos, const double* __restrict__ ref, int64_t n,
@@ -242,7 +243,8 @@ __device__ __forceinline__ void frac(const double* inv, const double* x, double 
 // One 64-thread block per structure.  Small structures (<= kSmallMax atoms)
 // take the all-pairs path with an image bound K_d = floor(radius/w_d +
 // spread_d) + 1 on periodic directions (spread of the fractional
-// coordinates); larger ones are binned with bins >= radius wide.
+// coordinates) and form a single bin; larger ones are binned with bins >=
+// radius wide.
 // Every block of the grid (B or more) also clears its share of the bin
 // counts [0, n_zero).  With one structure, bin_base is written here too.
 __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
@@ -296,6 +298,7 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
   g.small = small ? 1 : 0;
   int64_t nbins = 0;
   if (small) {
+    nbins = nc > 0 ? 1 : 0;  // the whole structure is one group of the row passes
     for (int d = 0; d < 3; ++d) {
       double K = pbc[3 * c + d] && nc > 0 ? floor(radius / w[d] + (u[d] - l[d])) + 1.0 : 0.0;
       if (!(K <= 127.0)) {
@@ -368,11 +371,14 @@ __device__ __forceinline__ void bin_coords(const StructGeom& g, const uint8_t* p
   }
 }
 
+// Bin of every atom (the single bin of its structure for small ones) and
+// its rank inside the bin.  Atoms with non-finite coordinates are left out
+// (row count 0) and flagged.
 __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
                          const uint8_t* __restrict__ pbc, int32_t B, int64_t N, const StructGeom* __restrict__ geom,
                          const int64_t* __restrict__ bin_base, int64_t* __restrict__ bin_count,
-                         int32_t* __restrict__ atom_bin, int32_t* __restrict__ bin_rank, int64_t* meta,
-                         const int32_t* flag) {
+                         int32_t* __restrict__ atom_bin, int32_t* __restrict__ bin_rank,
+                         int64_t* __restrict__ row_count, int64_t* meta, const int32_t* flag) {
   if (!*flag) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -380,17 +386,15 @@ __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restri
   if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) {
     atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
     atom_bin[4 * i] = -1;
+    row_count[i] = 0;
     return;
   }
   int c = struct_of(atom_ptr, B, i);
   const StructGeom& g = geom[c];
-  if (g.small) {
-    atom_bin[4 * i] = -1;
-    return;
-  }
-  int b3[3], m[3];
-  bin_coords(g, pbc + 3 * c, x, b3, m);
+  int b3[3] = {0, 0, 0}, m[3] = {0, 0, 0};
+  if (!g.small) bin_coords(g, pbc + 3 * c, x, b3, m);
   int64_t bin = bin_base[c] + ((int64_t)b3[0] * g.nb[1] + b3[1]) * g.nb[2] + b3[2];
+  if (g.small) bin = bin_base[c];
   atom_bin[4 * i + 0] = (int32_t)bin;
   atom_bin[4 * i + 1] = m[0];
   atom_bin[4 * i + 2] = m[1];
@@ -421,228 +425,271 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc)
 }
 __device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry_key(j, s.x, s.y, s.z); }
 
-// A block of kRowWaves waves per atom i enumerates its candidates,
-// kRowThreads at a time, and applies the FP64 inclusion test.  Each wave
-// counts its accepted entries with a ballot and reserves room for them with
-// one LDS atomic, so the slots are unique (their order is not: the fill
-// sorts the keys).
-//   COUNT: row_count[i] = number of entries.
-//   FILL : the entries' keys (j, n_a, n_b, n_c) are collected in LDS, sorted
-//          (bitonic) and written to the row at offsets[i].
-// Small structures: candidates are every (j, image) with |n_d| <= K_d.
-// Binned structures: the atoms of the 27 bins around i's bin, with the image
-// that the bin wrap and the whole-cell offsets of i and j imply.
-constexpr int kRowWaves = 4;
-constexpr int kRowThreads = 64 * kRowWaves;
+// Row passes, one block per group of atoms that share their candidates: a
+// bin of a binned structure (candidates: the atoms of the 27 bins around
+// it, with the image implied by the bin wrap and the whole-cell offsets of
+// both atoms), or a whole small structure (candidates: every atom of the
+// structure in every image with |n_d| <= K_d).  The candidates are staged
+// in LDS once per group; each wave then takes the group's atoms one at a
+// time, 64 candidates per step, with the FP64 inclusion test.
+//   kRowsCount: row_count[i] = number of entries.
+//   kRowsKeys : also the row's keys (j, n_a, n_b, n_c), collected in LDS and
+//               put in order by each key's rank among them, go to a slab of
+//               kslot keys per atom; a longer row raises flag[2].
+//   kRowsFill : (only when flag[2] was raised) the row's keys, in order,
+//               are written straight to the list at offsets[i].
+constexpr int kGrpWaves = 4;
+constexpr int kGrpThreads = 64 * kGrpWaves;
+constexpr int kGrpSplit = 4;  // blocks sharing one group (blockIdx.y), each with every kGrpSplit-th set of atoms
+constexpr int kCandMax = 1024;  // binned groups with more candidates read them from HBM
 
-template <bool FILL>
-__global__ void __launch_bounds__(kRowThreads) k_nb_rows(const double* __restrict__ pos,
-                                                         const int64_t* __restrict__ atom_ptr,
-                                                         const uint8_t* __restrict__ pbc, int32_t B, int64_t N,
+// Orders this wave's LDS writes before its later LDS reads of other lanes'
+// data (and keeps the compiler from moving accesses across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+enum { kRowsCount = 0, kRowsKeys = 1, kRowsFill = 2 };
+
+template <int MODE>
+__global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restrict__ atom_ptr,
+                                                         const uint8_t* __restrict__ pbc, int32_t B,
                                                          const StructGeom* __restrict__ geom,
                                                          const int64_t* __restrict__ bin_base,
                                                          const int64_t* __restrict__ bin_start,
                                                          const int4* __restrict__ bin_m,
-                                                         const double4* __restrict__ bin_x,
-                                                         const int32_t* __restrict__ atom_bin, double r2max,
+                                                         const double4* __restrict__ bin_x, double r2max,
                                                          int64_t* __restrict__ row_count,
                                                          const int64_t* __restrict__ offsets,
                                                          int32_t* __restrict__ nbr, int8_t* __restrict__ shift,
-                                                         int64_t* meta, const int32_t* flag) {
-  if (FILL ? !flag[1] : !flag[0]) return;
-  __shared__ uint64_t key[FILL ? kRowMax : 1];
-  __shared__ int n_acc, any_bad;
-  const int64_t i = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63;
-  if (i >= N) return;
-  const double xi[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-  if (!(isfinite(xi[0]) && isfinite(xi[1]) && isfinite(xi[2]))) {
-    if (!FILL && tid == 0) {
-      row_count[i] = 0;
-      atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
-    }
-    return;
-  }
-  if (tid == 0) {
-    n_acc = 0;
-    any_bad = 0;
-  }
+                                                         uint64_t* __restrict__ row_keys, int kslot,
+                                                         int64_t* meta, int32_t* flag) {
+  constexpr bool FILL = MODE == kRowsFill;
+  constexpr bool KEYS = MODE != kRowsCount;
+  if (FILL ? !(flag[1] && flag[2]) : !flag[0]) return;
+  __shared__ double cx[kCandMax], cy[kCandMax], cz[kCandMax];
+  __shared__ int32_t cj[kCandMax];
+  __shared__ int32_t cw[3][kCandMax];  // image of a binned candidate minus the centre atom's cell offset
+  __shared__ uint64_t keyw[KEYS ? kGrpWaves : 1][KEYS ? kRowMax : 1];
+  __shared__ int64_t b_start[27];
+  __shared__ int32_t b_pre[28];
+  __shared__ int32_t b_wr[27][3];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int c = struct_of(atom_ptr, B, i);
-  const StructGeom& g = geom[c];
-  bool shift_bad = false;
-  auto test = [&](bool active, int32_t j, const double* xj, int na, int nb, int nc) {
-    bool acc = false;
-    if (active && !(j == i && na == 0 && nb == 0 && nc == 0)) {
-      double d[3];
-      displacement64(xi, xj, g.h, na, nb, nc, d);
-      acc = norm2_64(d) < r2max;
-      if (acc && (na < -127 || na > 127 || nb < -127 || nb > 127 || nc < -127 || nc > 127)) {
-        shift_bad = true;
-        acc = false;
+  const int64_t n_groups = B > 0 ? bin_base[B] : 0;
+  for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+    int c = 0;
+    {
+      int lo = 0, hi = B - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bin_base[mid] <= grp) lo = mid;
+        else hi = mid - 1;
       }
+      c = lo;
     }
-    const uint64_t m = __ballot(acc);
-    if (m == 0) return;
-    int base = 0;
-    if (lane == 0) base = atomicAdd(&n_acc, __popcll(m));
-    base = __shfl(base, 0);
-    if (FILL && acc) {
-      const int slot = base + __popcll(m & lt);
-      if (slot < kRowMax) key[slot] = entry_key(j, na, nb, nc);
-    }
-  };
-  if (g.small) {
-    __syncthreads();
-    const int K0 = g.nb[0], K1 = g.nb[1], K2 = g.nb[2];
+    // the structure's geometry in registers: stores to the list below are
+    // char-typed and would otherwise force reloads of it
+    double h[9];
+    for (int k = 0; k < 9; ++k) h[k] = geom[c].h[k];
+    const int gnb[3] = {geom[c].nb[0], geom[c].nb[1], geom[c].nb[2]};
+    const bool small = geom[c].small != 0;
+    const bool p3[3] = {pbc[3 * c] != 0, pbc[3 * c + 1] != 0, pbc[3 * c + 2] != 0};
+    const int64_t base_c = bin_base[c];
+    const int64_t a_lo = bin_start[grp], a_hi = bin_start[grp + 1];
+    if (a_lo + (int64_t)blockIdx.y * kGrpWaves >= a_hi) continue;  // no atoms of this group for this block
+    const int K0 = small ? gnb[0] : 0, K1 = small ? gnb[1] : 0, K2 = small ? gnb[2] : 0;
     const int w1 = 2 * K1 + 1, w2 = 2 * K2 + 1;
     const int64_t nimg = (int64_t)(2 * K0 + 1) * w1 * w2;
-    const int64_t a0 = atom_ptr[c];
-    const int64_t total = (atom_ptr[c + 1] - a0) * nimg;
-    for (int64_t t0 = 0; t0 < total; t0 += kRowThreads) {
-      const int64_t t = t0 + tid;
-      const bool active = t < total;
-      const int64_t jj = active ? t / nimg : 0;
-      int im = active ? (int)(t - jj * nimg) : 0;
-      const int nc = im % w2 - K2;
-      im /= w2;
-      const int nb = im % w1 - K1;
-      const int na = im / w1 - K0;
-      test(active, (int32_t)(a0 + jj), pos + 3 * (a0 + jj), na, nb, nc);
-    }
-  } else {
-    // the 27 bins around i's bin, flattened into one candidate index space:
-    // lane b < 27 of wave 0 describes bin b (first atom, atom count, lattice
-    // wrap), a prefix sum over the counts maps candidate t to (bin, atom)
-    __shared__ int64_t b_start[27];
-    __shared__ int32_t b_pre[28];
-    __shared__ int32_t b_img[27][3];
-    const uint8_t* p3 = pbc + 3 * c;
-    if (tid < 64) {
-      int cnt_b = 0;
-      if (lane < 27) {
-        int mi[3];
-        mi[0] = atom_bin[4 * i + 1];
-        mi[1] = atom_bin[4 * i + 2];
-        mi[2] = atom_bin[4 * i + 3];
-        const int64_t base_c = bin_base[c];
-        int64_t local = atom_bin[4 * i] - base_c;
-        int bi[3];
-        bi[2] = (int)(local % g.nb[2]);
-        local /= g.nb[2];
-        bi[1] = (int)(local % g.nb[1]);
-        bi[0] = (int)(local / g.nb[1]);
-        const int dd[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
-        int bb[3], wr[3];
-        bool skip = false;
-        for (int d = 0; d < 3; ++d) {
-          int k = bi[d] + dd[d];
-          wr[d] = 0;
-          if (k < 0 || k >= g.nb[d]) {
-            if (!p3[d]) {
-              skip = true;
-              break;
+    int64_t total;
+    bool staged = true;
+    if (small) {
+      const int n_at = (int)(a_hi - a_lo);  // <= kSmallMax <= kCandMax
+      for (int t = tid; t < n_at; t += kGrpThreads) {
+        const double4 x4 = bin_x[a_lo + t];
+        cx[t] = x4.x;
+        cy[t] = x4.y;
+        cz[t] = x4.z;
+        cj[t] = bin_m[a_lo + t].x;
+      }
+      total = (int64_t)n_at * nimg;
+    } else {
+      if (tid < 64) {
+        int cnt_b = 0;
+        if (lane < 27) {
+          int64_t local = grp - base_c;
+          int bi[3];
+          bi[2] = (int)(local % gnb[2]);
+          local /= gnb[2];
+          bi[1] = (int)(local % gnb[1]);
+          bi[0] = (int)(local / gnb[1]);
+          const int dd[3] = {lane / 9 - 1, (lane / 3) % 3 - 1, lane % 3 - 1};
+          int bb[3], wr[3] = {0, 0, 0};
+          bool skip = false;
+          for (int d = 0; d < 3; ++d) {
+            int k = bi[d] + dd[d];
+            if (k < 0 || k >= gnb[d]) {
+              if (!p3[d]) {
+                skip = true;
+                break;
+              }
+              wr[d] = k < 0 ? -1 : 1;
+              k -= wr[d] * gnb[d];
             }
-            wr[d] = k < 0 ? -1 : 1;
-            k -= wr[d] * g.nb[d];
+            bb[d] = k;
           }
-          bb[d] = k;
-        }
-        int64_t b0 = 0;
-        if (!skip) {
-          const int64_t bin = base_c + ((int64_t)bb[0] * g.nb[1] + bb[1]) * g.nb[2] + bb[2];
-          b0 = bin_start[bin];
-          cnt_b = (int)(bin_start[bin + 1] - b0);
-        }
-        b_start[lane] = b0;
-        for (int d = 0; d < 3; ++d) b_img[lane][d] = p3[d] ? wr[d] + mi[d] : 0;
-      }
-      // inclusive prefix of the 27 counts (wave scan)
-      int pre = cnt_b;
-      for (int off = 1; off < 32; off <<= 1) {
-        const int v = __shfl_up(pre, off);
-        if (lane >= off) pre += v;
-      }
-      if (lane < 27) b_pre[lane + 1] = pre;
-      if (lane == 0) b_pre[0] = 0;
-    }
-    __syncthreads();
-    const int total = b_pre[27];
-    for (int t0 = 0; t0 < total; t0 += kRowThreads) {
-      const int t = t0 + tid;
-      const bool active = t < total;
-      int b = 0;
-      if (active) {  // largest b with b_pre[b] <= t
-        int lo = 0, hi = 26;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (b_pre[mid] <= t) lo = mid;
-          else hi = mid - 1;
-        }
-        b = lo;
-      }
-      int4 mj = make_int4(0, 0, 0, 0);
-      double xj[3] = {0.0, 0.0, 0.0};
-      int n[3] = {0, 0, 0};
-      if (active) {
-        const int64_t k = b_start[b] + (t - b_pre[b]);
-        mj = bin_m[k];
-        const double4 x4 = bin_x[k];
-        xj[0] = x4.x;
-        xj[1] = x4.y;
-        xj[2] = x4.z;
-        n[0] = p3[0] ? b_img[b][0] - mj.y : 0;
-        n[1] = p3[1] ? b_img[b][1] - mj.z : 0;
-        n[2] = p3[2] ? b_img[b][2] - mj.w : 0;
-      }
-      test(active, mj.x, xj, n[0], n[1], n[2]);
-    }
-  }
-  if (!FILL && shift_bad) any_bad = 1;
-  __syncthreads();
-  const int count = n_acc;
-  if (!FILL) {
-    if (tid == 0) {
-      row_count[i] = count;
-      if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
-      if (any_bad) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
-    }
-    return;
-  }
-  // FILL: sort the row's keys and write it out
-  const int len = count;
-  if (len > kRowMax) return;  // flagged by the counting pass; the fill does not run then
-  int P = 1;
-  while (P < len) P <<= 1;
-  for (int t = len + tid; t < P; t += kRowThreads) key[t] = ~0ull;
-  __syncthreads();
-  for (int k = 2; k <= P; k <<= 1) {
-    for (int jj = k >> 1; jj > 0; jj >>= 1) {
-      for (int t = tid; t < P; t += kRowThreads) {
-        const int partner = t ^ jj;
-        if (partner > t) {
-          const uint64_t a = key[t], b = key[partner];
-          if ((a > b) == ((t & k) == 0)) {
-            key[t] = b;
-            key[partner] = a;
+          int64_t b0 = 0;
+          if (!skip) {
+            const int64_t bin = base_c + ((int64_t)bb[0] * gnb[1] + bb[1]) * gnb[2] + bb[2];
+            b0 = bin_start[bin];
+            cnt_b = (int)(bin_start[bin + 1] - b0);
           }
+          b_start[lane] = b0;
+          for (int d = 0; d < 3; ++d) b_wr[lane][d] = p3[d] ? wr[d] : 0;
         }
+        int pre = cnt_b;  // inclusive prefix of the 27 counts
+        for (int off = 1; off < 32; off <<= 1) {
+          const int v = __shfl_up(pre, off);
+          if (lane >= off) pre += v;
+        }
+        if (lane < 27) b_pre[lane + 1] = pre;
+        if (lane == 0) b_pre[0] = 0;
       }
       __syncthreads();
+      total = b_pre[27];
+      staged = total <= kCandMax;
+      if (staged)
+        for (int t = tid; t < total; t += kGrpThreads) {
+          int lo = 0, hi = 26;  // largest b with b_pre[b] <= t
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b_pre[mid] <= t) lo = mid;
+            else hi = mid - 1;
+          }
+          const int64_t k = b_start[lo] + (t - b_pre[lo]);
+          const int4 m4 = bin_m[k];
+          const double4 x4 = bin_x[k];
+          cx[t] = x4.x;
+          cy[t] = x4.y;
+          cz[t] = x4.z;
+          cj[t] = m4.x;
+          cw[0][t] = p3[0] ? b_wr[lo][0] - m4.y : 0;
+          cw[1][t] = p3[1] ? b_wr[lo][1] - m4.z : 0;
+          cw[2][t] = p3[2] ? b_wr[lo][2] - m4.w : 0;
+        }
     }
-  }
-  const int64_t e0 = offsets[i];
-  const int64_t room = offsets[i + 1] - e0;
-  char4* sh4 = reinterpret_cast<char4*>(shift);
-  for (int t = tid; t < len && t < room; t += kRowThreads) {
-    const uint64_t k = key[t];
-    nbr[e0 + t] = (int32_t)(k >> 24);
-    char4 sv;
-    sv.x = (signed char)((int)((k >> 16) & 255) - 128);
-    sv.y = (signed char)((int)((k >> 8) & 255) - 128);
-    sv.z = (signed char)((int)(k & 255) - 128);
-    sv.w = 0;
-    sh4[e0 + t] = sv;
+    __syncthreads();
+    for (int64_t a = a_lo + (int64_t)blockIdx.y * kGrpWaves + wv; a < a_hi; a += kGrpWaves * kGrpSplit) {
+      const int4 mi4 = bin_m[a];
+      const double4 xi4 = bin_x[a];
+      const int32_t i = mi4.x;
+      const double xi[3] = {xi4.x, xi4.y, xi4.z};
+      const int mi[3] = {mi4.y, mi4.z, mi4.w};
+      int count = 0;
+      bool shift_bad = false;
+      for (int64_t t0 = 0; t0 < total; t0 += kWave) {
+        const int64_t t = t0 + lane;
+        const bool active = t < total;
+        int32_t j = 0;
+        double xj[3] = {0.0, 0.0, 0.0};
+        int n[3] = {0, 0, 0};
+        if (active) {
+          if (small) {
+            const int jj = (int)(t / nimg);
+            int im = (int)(t - (int64_t)jj * nimg);
+            n[2] = im % w2 - K2;
+            im /= w2;
+            n[1] = im % w1 - K1;
+            n[0] = im / w1 - K0;
+            j = cj[jj];
+            xj[0] = cx[jj];
+            xj[1] = cy[jj];
+            xj[2] = cz[jj];
+          } else if (staged) {
+            j = cj[t];
+            xj[0] = cx[t];
+            xj[1] = cy[t];
+            xj[2] = cz[t];
+            for (int d = 0; d < 3; ++d) n[d] = p3[d] ? cw[d][t] + mi[d] : 0;
+          } else {
+            int lo = 0, hi = 26;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (b_pre[mid] <= t) lo = mid;
+              else hi = mid - 1;
+            }
+            const int64_t k = b_start[lo] + (t - b_pre[lo]);
+            const int4 m4 = bin_m[k];
+            const double4 x4 = bin_x[k];
+            j = m4.x;
+            xj[0] = x4.x;
+            xj[1] = x4.y;
+            xj[2] = x4.z;
+            const int mj[3] = {m4.y, m4.z, m4.w};
+            for (int d = 0; d < 3; ++d) n[d] = p3[d] ? b_wr[lo][d] - mj[d] + mi[d] : 0;
+          }
+        }
+        bool acc = false;
+        if (active && !(j == i && n[0] == 0 && n[1] == 0 && n[2] == 0)) {
+          double d[3];
+          displacement64(xi, xj, h, n[0], n[1], n[2], d);
+          acc = norm2_64(d) < r2max;
+          if (acc && (n[0] < -127 || n[0] > 127 || n[1] < -127 || n[1] > 127 || n[2] < -127 || n[2] > 127)) {
+            shift_bad = true;
+            acc = false;
+          }
+        }
+        const uint64_t m = __ballot(acc);
+        if (KEYS && acc) {
+          const int slot = count + __popcll(m & lt);
+          if (slot < kRowMax) keyw[wv][slot] = entry_key(j, n[0], n[1], n[2]);
+        }
+        count += __popcll(m);
+      }
+      if (!FILL) {
+        if (lane == 0) {
+          row_count[i] = count;
+          if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+          if (KEYS && count > kslot) flag[2] = 1;
+        }
+        if (__any(shift_bad) && lane == 0)
+          atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
+        if (KEYS && count <= kslot) {
+          wave_lds_sync();
+          uint64_t* dst = row_keys + (int64_t)i * kslot;
+          for (int t = lane; t < count; t += kWave) {
+            const uint64_t k = keyw[wv][t];
+            int rank = 0;
+            for (int u = 0; u < count; ++u) rank += keyw[wv][u] < k ? 1 : 0;
+            dst[rank] = k;
+          }
+          wave_lds_sync();
+        }
+      } else if (count <= kRowMax) {  // longer rows were flagged by the counting pass; no fill then
+        wave_lds_sync();
+        const int64_t e0 = offsets[i];
+        const int64_t room = offsets[i + 1] - e0;
+        char4* sh4 = reinterpret_cast<char4*>(shift);
+        for (int t = lane; t < count; t += kWave) {
+          const uint64_t k = keyw[wv][t];
+          int rank = 0;
+          for (int u = 0; u < count; ++u) rank += keyw[wv][u] < k ? 1 : 0;
+          if (rank < room) {
+            nbr[e0 + rank] = (int32_t)(k >> 24);
+            char4 sv;
+            sv.x = (signed char)((int)((k >> 16) & 255) - 128);
+            sv.y = (signed char)((int)((k >> 8) & 255) - 128);
+            sv.z = (signed char)((int)(k & 255) - 128);
+            sv.w = 0;
+            sh4[e0 + rank] = sv;
+          }
+        }
+        wave_lds_sync();
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -670,8 +717,99 @@ __global__ void k_nb_capacity(const int64_t* offsets, int64_t N, CapacityJob cj)
   capacity_decision(cj, offsets[N]);
 }
 
-// Reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
-// found by binary search in the sorted row.  The list is exactly symmetric
+__device__ __forceinline__ void decode_key(uint64_t k, int32_t& j, char4& sv) {
+  j = (int32_t)(k >> 24);
+  sv.x = (signed char)((int)((k >> 16) & 255) - 128);
+  sv.y = (signed char)((int)((k >> 8) & 255) - 128);
+  sv.z = (signed char)((int)(k & 255) - 128);
+  sv.w = 0;
+}
+
+// Number of keys below `want` in the sorted keys[0, len): rounds of seven
+// independent probes cut the range eightfold, then at most eight keys are
+// compared directly; `found` tells whether `want` itself is among them.
+__device__ __forceinline__ int lower_bound8(const uint64_t* __restrict__ keys, int len, uint64_t want,
+                                            bool& found) {
+  int lo = 0, hi = len;  // keys[< lo] < want <= keys[>= hi]
+  while (hi - lo > 8) {
+    const int step = (hi - lo + 7) >> 3;
+    uint64_t kq[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int p = lo + step * (q + 1);
+      kq[q] = p < hi ? keys[p] : ~0ull;
+    }
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) c += kq[q] < want ? 1 : 0;
+    const int nlo = c > 0 ? lo + step * c + 1 : lo;
+    const int nhi = min(hi, lo + step * (c + 1));
+    lo = nlo;
+    hi = nhi;
+  }
+  uint64_t kq[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) kq[q] = lo + q < hi ? keys[lo + q] : ~0ull;
+  int c = 0;
+  found = false;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    c += kq[q] < want ? 1 : 0;
+    found = found || kq[q] == want;
+  }
+  return lo + c;
+}
+
+// Writes the rows from the key slabs at their offsets, with the reverse
+// entry of every entry (i -> j, n): the entry (j -> i, -n) of row j, whose
+// position is the number of row j's keys below its key.  Also records the
+// positions of this build (skin reference) and marks the list valid.  One
+// wave per atom.
+__global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys, int kslot,
+                                                const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
+                                                int8_t* __restrict__ shift, int32_t* __restrict__ rev,
+                                                const double* __restrict__ pos, double* __restrict__ ref_pos,
+                                                int64_t* meta, const int32_t* flag) {
+  if (!flag[1] || flag[2]) return;
+  const int64_t i = blockIdx.x;
+  if (i >= N) return;
+  const int lane = threadIdx.x;
+  if (ref_pos && lane < 3) ref_pos[3 * i + lane] = pos[3 * i + lane];
+  if (i == 0 && lane == 0) {
+    meta[kMetaValid] = 1;
+    meta[kMetaBuilds] += 1;
+  }
+  const int64_t e0 = offsets[i];
+  const int len = (int)(offsets[i + 1] - e0);
+  const uint64_t* mine = row_keys + i * kslot;
+  char4* sh4 = reinterpret_cast<char4*>(shift);
+  for (int t = lane; t < len; t += kWave) {
+    const uint64_t k = mine[t];
+    int32_t j;
+    char4 sv;
+    decode_key(k, j, sv);
+    nbr[e0 + t] = j;
+    sh4[e0 + t] = sv;
+    char4 ns;
+    ns.x = (signed char)(-sv.x);
+    ns.y = (signed char)(-sv.y);
+    ns.z = (signed char)(-sv.z);
+    ns.w = 0;
+    const uint64_t want = entry_key((int32_t)i, ns);
+    const int64_t f0 = offsets[j];
+    const int lj = (int)(offsets[j + 1] - f0);
+    const uint64_t* theirs = row_keys + (int64_t)j * kslot;
+    bool found;
+    const int r = lower_bound8(theirs, lj, want, found);
+    // a missing reverse entry cannot happen for an exactly symmetric list;
+    // point at the entry itself (zero net force) and flag it
+    rev[e0 + t] = (int32_t)(found ? f0 + r : e0 + t);
+    if (!found) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+  }
+}
+
+// Fallback after a full fill (a row longer than its slab): the reverse entry
+// of every entry by binary search in the sorted rows of the list.  The list is exactly symmetric
 // because the FP64 displacement of the reverse entry is the exact negation.
 // Also records the positions of this build (skin reference) and marks the
 // list valid.
@@ -679,7 +817,7 @@ __global__ void __launch_bounds__(64) k_nb_rev(int64_t N, const int64_t* __restr
                                                const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
                                                int32_t* __restrict__ rev, const double* __restrict__ pos,
                                                double* __restrict__ ref_pos, int64_t* meta, const int32_t* flag) {
-  if (!flag[1]) return;
+  if (!(flag[1] && flag[2])) return;
   const int64_t i = blockIdx.x;
   if (i >= N) return;
   if (ref_pos && threadIdx.x < 3) ref_pos[3 * i + threadIdx.x] = pos[3 * i + threadIdx.x];
@@ -719,6 +857,14 @@ __global__ void __launch_bounds__(64) k_nb_rev(int64_t N, const int64_t* __restr
 // host driver
 // ---------------------------------------------------------------------------
 
+int row_key_slot(int64_t n_atoms, int64_t capacity) {
+  if (n_atoms <= 0 || capacity <= 0) return 0;
+  const int64_t want = (3 * ((capacity + n_atoms - 1) / n_atoms) + 1) / 2;
+  int k = 64;
+  while (k < want && k < kRowMax) k <<= 1;
+  return k;
+}
+
 void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_only, hipStream_t s) {
   const nn_system* sys = L.sys;
   const int64_t N = sys->n_atoms;
@@ -738,14 +884,23 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const double r2 = L.radius * L.radius;
   if (N > 0)
     hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                       L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.meta, L.flag);
+                       L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.counts, L.meta, L.flag);
   exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag, L.bin_base + B);
+  // groups (bins) are known on the device only: a grid-stride loop over them
+  const unsigned gRows = (unsigned)std::max<int64_t>(1, std::min<int64_t>(L.max_bins, 2048));
   if (N > 0) {
     hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, sys->pos, L.atom_bin, L.bin_rank, L.bin_start,
                        L.bin_m, L.bin_x, L.flag);
-    hipLaunchKernelGGL(k_nb_rows<false>, dim3((unsigned)N), dim3(kRowThreads), 0, s, sys->pos, sys->atom_ptr,
-                       sys->pbc, B, N, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, L.atom_bin, r2, L.counts,
-                       (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, L.meta, L.flag);
+    if (count_only)
+      hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
+                         sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts,
+                         (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, (uint64_t*)nullptr, 0,
+                         L.meta, L.flag);
+    else
+      hipLaunchKernelGGL(k_nb_rows<kRowsKeys>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
+                         sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts,
+                         (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, L.row_keys, L.kslot,
+                         L.meta, L.flag);
   }
   const CapacityJob cj{count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag};
   if (N <= kScanSmall) {
@@ -757,9 +912,13 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   }
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  hipLaunchKernelGGL(k_nb_rows<true>, dim3((unsigned)N), dim3(kRowThreads), 0, s, sys->pos, sys->atom_ptr,
-                     sys->pbc, B, N, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, L.atom_bin, r2, (int64_t*)nullptr,
-                     nl->offsets, nl->nbr, nl->shift, L.meta, L.flag);
+  hipLaunchKernelGGL(k_nb_emit, dim3((unsigned)N), dim3(64), 0, s, N, L.row_keys, L.kslot, nl->offsets, nl->nbr,
+                     nl->shift, nl->rev, sys->pos, nl->ref_pos, L.meta, L.flag);
+  // fallback when some row did not fit its slab: both kernels exit at once otherwise
+  const unsigned gFill = (unsigned)std::min<int64_t>(gRows, 256);
+  hipLaunchKernelGGL(k_nb_rows<kRowsFill>, dim3(gFill, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr, sys->pbc, B,
+                     L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, (int64_t*)nullptr, nl->offsets, nl->nbr,
+                     nl->shift, (uint64_t*)nullptr, 0, L.meta, L.flag);
   hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev,
                      sys->pos, nl->ref_pos, L.meta, L.flag);
 }

@@ -155,3 +155,41 @@ def test_force_sum_vanishes_periodic():
     _, _, F = pot.energy_forces()
     F = F.double().cpu().numpy()
     assert np.abs(F.sum(0)).max() < 1e-6 * np.abs(F).max() * F.shape[0]
+
+
+def dense_blob_system():
+    """A periodic box of dilute atoms around a dense blob: the blob's rows are
+    several times the mean row length, longer than the per-atom key slab the
+    counting pass keeps, so the build takes its full-fill fallback."""
+    rng = np.random.Generator(np.random.PCG64(91))
+    L = 30.0
+    g = (np.arange(11) + 0.5) * (L / 11)
+    dil = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    dil = dil + rng.uniform(-0.3, 0.3, dil.shape)
+    c = np.full(3, L / 2)
+    dil = dil[np.linalg.norm(dil - c, axis=1) > 4.3]
+    b = np.arange(-3, 4) * 1.0
+    blob = np.stack(np.meshgrid(b, b, b, indexing="ij"), -1).reshape(-1, 3)
+    blob = blob[np.linalg.norm(blob, axis=1) <= 3.0] + c + rng.uniform(-0.1, 0.1, (1, 3))
+    pos = np.concatenate([dil, blob])
+    sp = rng.integers(0, 2, len(pos))
+    return synth.single(pos, sp, cell=np.eye(3) * L, pbc=(1, 1, 1))
+
+
+def test_neighbor_list_long_rows_fallback():
+    s = dense_blob_system()
+    p = synth.mbp_params(2, 4.0, 8, 4, 4)
+    ref = oracle.neighbors_cells(s, p.rc)
+    rows = np.diff(ref["offsets"])
+    print(f"[neighbors] dense blob: {s.n_atoms} atoms, rows mean {rows.mean():.1f} max {rows.max()}", flush=True)
+    assert rows.max() > 2 * rows.mean()
+    pot = nnpot.Potential(s, p, None)
+    pot.build_neighbors()
+    got = pot.neighbor_list_host()
+    assert np.array_equal(got["offsets"], ref["offsets"])
+    ok, msg = list_rows_equal(got, ref)
+    assert ok, msg
+    off = got["offsets"]
+    row_of = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    assert np.array_equal(got["nbr"][got["rev"]], row_of)
+    assert np.array_equal(got["shift"][got["rev"]], -got["shift"])
