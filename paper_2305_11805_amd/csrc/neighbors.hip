@@ -725,12 +725,11 @@ __device__ __forceinline__ void decode_key(uint64_t k, int32_t& j, char4& sv) {
   sv.w = 0;
 }
 
-// Number of keys below `want` in the sorted keys[0, len): rounds of seven
+// Position of `want` in the sorted keys[0, len), or -1: rounds of seven
 // independent probes cut the range eightfold, then at most eight keys are
-// compared directly; `found` tells whether `want` itself is among them.
-__device__ __forceinline__ int lower_bound8(const uint64_t* __restrict__ keys, int len, uint64_t want,
-                                            bool& found) {
-  int lo = 0, hi = len;  // keys[< lo] < want <= keys[>= hi]
+// compared directly.
+__device__ __forceinline__ int find_key8(const uint64_t* __restrict__ keys, int len, uint64_t want) {
+  int lo = 0, hi = len;  // keys[< lo] < want < keys[>= hi]
   while (hi - lo > 8) {
     const int step = (hi - lo + 7) >> 3;
     uint64_t kq[7];
@@ -739,9 +738,10 @@ __device__ __forceinline__ int lower_bound8(const uint64_t* __restrict__ keys, i
       const int p = lo + step * (q + 1);
       kq[q] = p < hi ? keys[p] : ~0ull;
     }
-    int c = 0;
+    int c = 0;  // probes below want
 #pragma unroll
     for (int q = 0; q < 7; ++q) c += kq[q] < want ? 1 : 0;
+    if (c < 7 && kq[c] == want) return lo + step * (c + 1);
     const int nlo = c > 0 ? lo + step * c + 1 : lo;
     const int nhi = min(hi, lo + step * (c + 1));
     lo = nlo;
@@ -750,14 +750,11 @@ __device__ __forceinline__ int lower_bound8(const uint64_t* __restrict__ keys, i
   uint64_t kq[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) kq[q] = lo + q < hi ? keys[lo + q] : ~0ull;
-  int c = 0;
-  found = false;
+  int r = -1;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    c += kq[q] < want ? 1 : 0;
-    found = found || kq[q] == want;
-  }
-  return lo + c;
+  for (int q = 0; q < 8; ++q)
+    if (kq[q] == want) r = lo + q;
+  return r;
 }
 
 // Writes the rows from the key slabs at their offsets, with the reverse
@@ -799,8 +796,8 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
     const int64_t f0 = offsets[j];
     const int lj = (int)(offsets[j + 1] - f0);
     const uint64_t* theirs = row_keys + (int64_t)j * kslot;
-    bool found;
-    const int r = lower_bound8(theirs, lj, want, found);
+    const int r = find_key8(theirs, lj, want);
+    const bool found = r >= 0;
     // a missing reverse entry cannot happen for an exactly symmetric list;
     // point at the entry itself (zero net force) and flag it
     rev[e0 + t] = (int32_t)(found ? f0 + r : e0 + t);
