@@ -42,6 +42,13 @@ struct AtomNb {
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// Orders this wave's LDS accesses: writes before it are seen by reads after
+// it in every lane, and the compiler moves no LDS access across it.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 __device__ __forceinline__ int nb_species(const float4& f) { return __float_as_int(f.w) & 15; }
 __device__ __forceinline__ int nb_entry(const float4& f) { return __float_as_int(f.w) >> 4; }
 
@@ -440,97 +447,114 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   }
   const int zeta1 = P.zeta - 1;
   const float zf = (float)P.zeta;
-  // angular: circular schedule over the species-sorted list; wave w takes
-  // the steps s = 1 + w, 1 + w + WPA, ...
-  for (int j0 = 0; j0 < n; j0 += kWave) {
-    const int j = j0 + lane;
-    const bool active = j < n;
-    float4 u = make_float4(1.f, 0.f, 0.f, 1.f), fu = make_float4(0.f, 0.f, 0.f, 0.f);
-    int sj = 0;
-    if (active) {
-      u = nb.d[j];
-      fu = nb.f[j];
-      sj = nb_species(fu);
-    }
-    const float iru = frcp(u.w);
-    float ax = 0.f, ay = 0.f, az = 0.f;
-    const int smax = n / 2;  // s = n/2 only for j < n/2 when n is even
-    for (int s = 1 + wv; s <= smax; s += WPA) {
-      const bool take = active && !((n % 2 == 0) && s == n / 2 && j >= n / 2);
-      int k = j + s;
-      if (k >= n) k -= n;
-      if (take) {
-        const float4 v = nb.d[k];
-        const float4 fv = nb.f[k];
-        const float* La = lam_a;
-        if (!ONE_SPECIES) La = lam_a + pair_block(S, sj, nb_species(fv)) * NBP;
-        const float irv = frcp(v.w);
-        const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
-        const float c = g.c;
-        const float F2 = 2.0f * fu.x * fv.x;
-        float x[NT], P1[NT], A[NT];
+  // angular: the unordered pairs {j, (j + s) mod n} for s = 1 .. n/2 (for
+  // even n the step n/2 only for j < n/2), numbered t = (s - 1) n + j and
+  // taken 64 at a time (wave w: chunks w, w + WPA, ...), so every lane has a
+  // triplet whatever n is.  A chunk spans a few steps; the gradients are
+  // added to the per-neighbor LDS slots one step at a time, and within one
+  // step the lanes' j are distinct and so are their k = j + s: no two lanes
+  // of an add share a slot, and the order of all adds is fixed.
+  const int T = n * (n - 1) / 2;
+  int sj_step = 1, jj = 0;
+  if (n >= 2) {
+    const int t = wv * kWave + lane;
+    sj_step = t / n + 1;
+    jj = t - (sj_step - 1) * n;
+  }
+  for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
+    const bool take = t0 + lane < T;
+    const int j = jj;
+    int k = j + sj_step;
+    if (k >= n) k -= n;
+    float gjx = 0.f, gjy = 0.f, gjz = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
+    if (take) {
+      const float4 u = nb.d[j], fu = nb.f[j];
+      const float4 v = nb.d[k], fv = nb.f[k];
+      const float* La = lam_a;
+      if (!ONE_SPECIES) La = lam_a + pair_block(S, nb_species(fu), nb_species(fv)) * NBP;
+      const float iru = frcp(u.w), irv = frcp(v.w);
+      const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+      const float c = g.c;
+      const float F2 = 2.0f * fu.x * fv.x;
+      float x[NT], P1[NT], A[NT];
 #pragma unroll
-        for (int p = 0; p < NT; ++p) x[p] = fmaf(c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
-        ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
+      for (int p = 0; p < NT; ++p) x[p] = fmaf(c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
+      ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
 #pragma unroll
-        for (int p = 0; p < NT; ++p) A[p] = P1[p] * x[p];
-        float R[NRA], dq[NRA];
+      for (int p = 0; p < NT; ++p) A[p] = P1[p] * x[p];
+      float R[NRA], dq[NRA];
 #pragma unroll
-        for (int q = 0; q < NRA; ++q) {
-          dq[q] = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
-          R[q] = fexp2(-eta_a2 * dq[q] * dq[q]);
-        }
-        float T[NRA], U[NT];
+      for (int q = 0; q < NRA; ++q) {
+        dq[q] = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
+        R[q] = fexp2(-eta_a2 * dq[q] * dq[q]);
+      }
+      float Tq[NRA], U[NT];
 #pragma unroll
-        for (int p = 0; p < NT; ++p) U[p] = 0.f;
+      for (int p = 0; p < NT; ++p) U[p] = 0.f;
 #pragma unroll
-        for (int q = 0; q < NRA; ++q) {
-          float tq = 0.f;
-#pragma unroll
-          for (int p = 0; p < NT; ++p) {
-            float l;
-            if constexpr (ONE_SPECIES) l = Lr[q * NT + p];
-            else l = La[q * NT + p];
-            tq = fmaf(l, A[p], tq);
-            U[p] = fmaf(l, R[q], U[p]);
-          }
-          T[q] = tq;
-        }
-        // E_t = F2 sum_q R_q T_q, T_q = sum_p lambda_qp A_p
-        float dEdF2 = 0.f, dEdravg = 0.f;
-#pragma unroll
-        for (int q = 0; q < NRA; ++q) {
-          dEdF2 = fmaf(T[q], R[q], dEdF2);
-          dEdravg = fmaf(T[q] * R[q], dq[q], dEdravg);
-        }
-        dEdravg *= -2.0f * P.eta_ang * F2;
-        float dEdc = 0.f, dEdssm = 0.f;
+      for (int q = 0; q < NRA; ++q) {
+        float tq = 0.f;
 #pragma unroll
         for (int p = 0; p < NT; ++p) {
-          const float gp = U[p] * P1[p];
-          dEdc = fmaf(gp, P.x_a[p], dEdc);
-          dEdssm = fmaf(gp, P.x_b[p], dEdssm);
+          float l;
+          if constexpr (ONE_SPECIES) l = Lr[q * NT + p];
+          else l = La[q * NT + p];
+          tq = fmaf(l, A[p], tq);
+          U[p] = fmaf(l, R[q], U[p]);
         }
-        dEdc *= zf * F2;
-        dEdssm *= zf * F2;
-        // sin^2 = 1 - cos^2, so d ssm / d cos = -cos / ssm
-        const float coef = dEdc - dEdssm * c * frcp(g.ssm);
-        const float dEdru = 0.5f * dEdravg + dEdF2 * 2.0f * fu.y * fv.x;
-        const float dEdrv = 0.5f * dEdravg + dEdF2 * 2.0f * fu.x * fv.y;
-        // d cos / d d_u = (v^ - cos u^) / r_u
-        const float cu = coef * iru, cv = coef * irv;
-        ax += cu * (v.x - c * u.x) + dEdru * u.x;
-        ay += cu * (v.y - c * u.y) + dEdru * u.y;
-        az += cu * (v.z - c * u.z) + dEdru * u.z;
-        atomicAdd(&gx[wv][k], cv * (u.x - c * v.x) + dEdrv * v.x);
-        atomicAdd(&gy[wv][k], cv * (u.y - c * v.y) + dEdrv * v.y);
-        atomicAdd(&gz[wv][k], cv * (u.z - c * v.z) + dEdrv * v.z);
+        Tq[q] = tq;
       }
+      // E_t = F2 sum_q R_q T_q, T_q = sum_p lambda_qp A_p
+      float dEdF2 = 0.f, dEdravg = 0.f;
+#pragma unroll
+      for (int q = 0; q < NRA; ++q) {
+        dEdF2 = fmaf(Tq[q], R[q], dEdF2);
+        dEdravg = fmaf(Tq[q] * R[q], dq[q], dEdravg);
+      }
+      dEdravg *= -2.0f * P.eta_ang * F2;
+      float dEdc = 0.f, dEdssm = 0.f;
+#pragma unroll
+      for (int p = 0; p < NT; ++p) {
+        const float gp = U[p] * P1[p];
+        dEdc = fmaf(gp, P.x_a[p], dEdc);
+        dEdssm = fmaf(gp, P.x_b[p], dEdssm);
+      }
+      dEdc *= zf * F2;
+      dEdssm *= zf * F2;
+      // sin^2 = 1 - cos^2, so d ssm / d cos = -cos / ssm
+      const float coef = dEdc - dEdssm * c * frcp(g.ssm);
+      const float dEdru = 0.5f * dEdravg + dEdF2 * 2.0f * fu.y * fv.x;
+      const float dEdrv = 0.5f * dEdravg + dEdF2 * 2.0f * fu.x * fv.y;
+      // d cos / d d_u = (v^ - cos u^) / r_u
+      const float cu = coef * iru, cv = coef * irv;
+      gjx = cu * (v.x - c * u.x) + dEdru * u.x;
+      gjy = cu * (v.y - c * u.y) + dEdru * u.y;
+      gjz = cu * (v.z - c * u.z) + dEdru * u.z;
+      gkx = cv * (u.x - c * v.x) + dEdrv * v.x;
+      gky = cv * (u.y - c * v.y) + dEdrv * v.y;
+      gkz = cv * (u.z - c * v.z) + dEdrv * v.z;
     }
-    if (active) {
-      atomicAdd(&gx[wv][j], ax);
-      atomicAdd(&gy[wv][j], ay);
-      atomicAdd(&gz[wv][j], az);
+    // steps present in this chunk: from lane 0's to the last taking lane's
+    const int last = min(kWave - 1, T - 1 - t0);
+    const int s_lo = __shfl(sj_step, 0), s_hi = __shfl(sj_step, last);
+    for (int ss = s_lo; ss <= s_hi; ++ss) {
+      if (take && sj_step == ss) {  // plain read-add-write: no two lanes share a slot here
+        gx[wv][k] += gkx;
+        gy[wv][k] += gky;
+        gz[wv][k] += gkz;
+      }
+      wave_lds_sync();
+      if (take && sj_step == ss) {
+        gx[wv][j] += gjx;
+        gy[wv][j] += gjy;
+        gz[wv][j] += gjz;
+      }
+      wave_lds_sync();
+    }
+    jj += kWave * WPA;
+    while (n >= 2 && jj >= n) {
+      jj -= n;
+      ++sj_step;
     }
   }
   __syncthreads();
