@@ -102,6 +102,7 @@ struct Layout {
   int4* bin_m;
   double4* bin_x;
   uint64_t* row_keys;
+  int64_t *key_loc, *cursor;
   int kslot;
   int64_t max_bins;
   // energy / forces
@@ -142,7 +143,9 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
   L.bin_m = c.take<int4>(N);
   L.bin_x = c.take<double4>(N);
   L.kslot = row_key_slot(N, capacity);
-  L.row_keys = c.take<uint64_t>((size_t)N * L.kslot);
+  L.row_keys = c.take<uint64_t>((size_t)N * L.kslot + (L.kslot > 0 ? (size_t)capacity : 0));
+  L.key_loc = c.take<int64_t>(N);
+  L.cursor = c.take<int64_t>(1);
   L.atom_bin = c.take<int32_t>(4 * N);
   L.row_count = c.take<int64_t>(N + 1);
   L.count_off = c.take<int64_t>(N + 1);
@@ -302,6 +305,8 @@ static NbLaunch nb_launch(const nn_system* sys, const Layout& L, double radius, 
   n.bin_m = L.bin_m;
   n.bin_x = L.bin_x;
   n.row_keys = L.row_keys;
+  n.key_loc = L.key_loc;
+  n.cursor = L.cursor;
   n.kslot = L.kslot;
   n.atom_bin = L.atom_bin;
   n.scan_tmp = L.scan_tmp;

@@ -205,6 +205,20 @@ __device__ __forceinline__ void ipow_sel(const float (&x)[N], int e_runtime, flo
   }
 }
 
+// q = t / n, r = t mod n for 0 <= t < 2^24 and 0 < n < 2^12, through a
+// float reciprocal: the float quotient is off by at most one.
+__device__ __forceinline__ void divmod_small(int t, int n, float inv_n, int& q, int& r) {
+  q = (int)((float)t * inv_n);
+  r = t - q * n;
+  if (r < 0) {
+    --q;
+    r += n;
+  } else if (r >= n) {
+    ++q;
+    r -= n;
+  }
+}
+
 __device__ __forceinline__ int pair_block(int S, int a, int b) {
   if (a > b) {
     int t = a;
@@ -327,19 +341,24 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
       float acc[NB];
 #pragma unroll
       for (int t = 0; t < NB; ++t) acc[t] = 0.f;
+      // a == b: the unordered pairs {j, (j + s) mod na}, s = 1 .. na/2 (for
+      // even na the last step only for j < na/2), numbered t = (s - 1) na + j;
+      // a < b: every (j, k) of the two segments, t = j nbb + k
+      const int m = (a == b) ? na : nbb;
+      const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
       for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
         const int t = t0 + lane;
         if (t < T) {
-          int j, k;
+          int q, r, j, k;
+          divmod_small(t, m, inv_m, q, r);
           if (a == b) {
-            int kk = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)t)) * 0.5f);
-            while (kk * (kk - 1) / 2 > t) --kk;
-            while ((kk + 1) * kk / 2 <= t) ++kk;
-            j = nb.seg[a] + (t - kk * (kk - 1) / 2);
+            int kk = r + q + 1;
+            if (kk >= na) kk -= na;
+            j = nb.seg[a] + r;
             k = nb.seg[a] + kk;
           } else {
-            j = nb.seg[a] + t / nbb;
-            k = nb.seg[b] + t % nbb;
+            j = nb.seg[a] + q;
+            k = nb.seg[b] + r;
           }
           const float4 u = nb.d[j], v = nb.d[k];
           const float4 fu = nb.f[j], fv = nb.f[k];
@@ -455,15 +474,12 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   // step the lanes' j are distinct and so are their k = j + s: no two lanes
   // of an add share a slot, and the order of all adds is fixed.
   const int T = n * (n - 1) / 2;
-  int sj_step = 1, jj = 0;
-  if (n >= 2) {
-    const int t = wv * kWave + lane;
-    sj_step = t / n + 1;
-    jj = t - (sj_step - 1) * n;
-  }
+  const float inv_n = n > 0 ? 1.0f / (float)n : 0.f;
   for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
     const bool take = t0 + lane < T;
-    const int j = jj;
+    int q, j;
+    divmod_small(t0 + lane, n, inv_n, q, j);
+    const int sj_step = q + 1;
     int k = j + sj_step;
     if (k >= n) k -= n;
     float gjx = 0.f, gjy = 0.f, gjz = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
@@ -550,11 +566,6 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
         gz[wv][j] += gjz;
       }
       wave_lds_sync();
-    }
-    jj += kWave * WPA;
-    while (n >= 2 && jj >= n) {
-      jj -= n;
-      ++sj_step;
     }
   }
   __syncthreads();

@@ -169,9 +169,9 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scr
 // skin); the skin test below may raise it.  atom_ptr must run from 0 to N
 // without decreasing; otherwise nothing is built and the list is marked
 // invalid, so no later kernel reads it (the skin test only runs on a valid
-// list).  One block.
-__global__ void k_nb_prep(const int64_t* __restrict__ atom_ptr, int32_t B, int64_t N, int64_t* meta, int32_t* flag,
-                          int use_skin) {
+// list).  Run by every thread of one block.
+__device__ void prep_flags(const int64_t* __restrict__ atom_ptr, int32_t B, int64_t N, int64_t* meta, int32_t* flag,
+                           int64_t* cursor, int use_skin) {
   __shared__ int bad;
   if (threadIdx.x == 0) bad = (atom_ptr[0] != 0 || atom_ptr[B] != N);
   __syncthreads();
@@ -187,7 +187,12 @@ __global__ void k_nb_prep(const int64_t* __restrict__ atom_ptr, int32_t B, int64
   } else {
     flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
   }
-  flag[2] = 0;  // raised by the counting pass if a row does not fit its key slab
+  *cursor = 0;  // overflow area of the counting pass's row keys
+}
+
+__global__ void k_nb_prep(const int64_t* __restrict__ atom_ptr, int32_t B, int64_t N, int64_t* meta, int32_t* flag,
+                          int64_t* cursor, int use_skin) {
+  prep_flags(atom_ptr, B, N, meta, flag, cursor, use_skin);
 }
 
 __global__ void k_skin_check(const double* __restrict__ pos, const double* __restrict__ ref, int64_t n,
@@ -251,8 +256,15 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
                           const double* __restrict__ cell, const uint8_t* __restrict__ pbc, int32_t B,
                           double radius, StructGeom* __restrict__ geom, int64_t* __restrict__ n_bins,
                           int64_t* __restrict__ bin_count, int64_t n_zero, int64_t* __restrict__ bin_base_one,
-                          int64_t* meta, const int32_t* flag) {
-  if (!*flag) return;
+                          int64_t N, int64_t* meta, int32_t* flag, int64_t* cursor, int prep) {
+  // prep: no skin test, so this launch also checks atom_ptr and sets the
+  // build flags (block 0); the other blocks read atom_ptr clamped to [0, N],
+  // and nothing after this launch runs if it was invalid
+  if (prep) {
+    if (blockIdx.x == 0) prep_flags(atom_ptr, B, N, meta, flag, cursor, 0);
+  } else if (!*flag) {
+    return;
+  }
   for (int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x; k < n_zero; k += (int64_t)gridDim.x * 64)
     bin_count[k] = 0;
   const int c = blockIdx.x;
@@ -263,7 +275,7 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
   __syncthreads();
   if (threadIdx.x == 0) inverse3(h, inv);
   __syncthreads();
-  const int64_t a0 = atom_ptr[c], a1 = atom_ptr[c + 1];
+  const int64_t a0 = min(max(atom_ptr[c], (int64_t)0), N), a1 = min(max(atom_ptr[c + 1], a0), N);
   const int64_t nc = a1 - a0;
   const bool small = nc <= kSmallMax;
   double l[3] = {1e300, 1e300, 1e300}, u[3] = {-1e300, -1e300, -1e300};
@@ -434,10 +446,10 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry
 // time, 64 candidates per step, with the FP64 inclusion test.
 //   kRowsCount: row_count[i] = number of entries.
 //   kRowsKeys : also the row's keys (j, n_a, n_b, n_c), collected in LDS and
-//               put in order by each key's rank among them, go to a slab of
-//               kslot keys per atom; a longer row raises flag[2].
-//   kRowsFill : (only when flag[2] was raised) the row's keys, in order,
-//               are written straight to the list at offsets[i].
+//               put in order by each key's rank among them, go to the
+//               atom's slab of kslot keys, or (a longer row) to a range of
+//               the overflow area reserved with one atomic; key_loc[i] says
+//               where.
 constexpr int kGrpWaves = 4;
 constexpr int kGrpThreads = 64 * kGrpWaves;
 constexpr int kGrpSplit = 4;  // blocks sharing one group (blockIdx.y), each with every kGrpSplit-th set of atoms
@@ -451,7 +463,7 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-enum { kRowsCount = 0, kRowsKeys = 1, kRowsFill = 2 };
+enum { kRowsCount = 0, kRowsKeys = 1 };
 
 template <int MODE>
 __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restrict__ atom_ptr,
@@ -461,14 +473,13 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
                                                          const int64_t* __restrict__ bin_start,
                                                          const int4* __restrict__ bin_m,
                                                          const double4* __restrict__ bin_x, double r2max,
-                                                         int64_t* __restrict__ row_count,
-                                                         const int64_t* __restrict__ offsets,
-                                                         int32_t* __restrict__ nbr, int8_t* __restrict__ shift,
+                                                         int64_t* __restrict__ row_count, int64_t n_atoms,
                                                          uint64_t* __restrict__ row_keys, int kslot,
-                                                         int64_t* meta, int32_t* flag) {
-  constexpr bool FILL = MODE == kRowsFill;
-  constexpr bool KEYS = MODE != kRowsCount;
-  if (FILL ? !(flag[1] && flag[2]) : !flag[0]) return;
+                                                         int64_t over_len, int64_t* __restrict__ key_loc,
+                                                         int64_t* __restrict__ cursor, int64_t* meta,
+                                                         const int32_t* flag) {
+  constexpr bool KEYS = MODE == kRowsKeys;
+  if (!flag[0]) return;
   __shared__ double cx[kCandMax], cy[kCandMax], cz[kCandMax];
   __shared__ int32_t cj[kCandMax];
   __shared__ int32_t cw[3][kCandMax];  // image of a binned candidate minus the centre atom's cell offset
@@ -648,17 +659,27 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
         }
         count += __popcll(m);
       }
-      if (!FILL) {
-        if (lane == 0) {
-          row_count[i] = count;
-          if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
-          if (KEYS && count > kslot) flag[2] = 1;
+      if (lane == 0) {
+        row_count[i] = count;
+        if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+      }
+      if (__any(shift_bad) && lane == 0)
+        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
+      if (KEYS && count <= kRowMax) {
+        // where the row's keys go: its slab, or the overflow area after the
+        // N slabs (a range past the area's end means the list cannot hold
+        // the entries either; the capacity check then stops the build)
+        int64_t base = i * (int64_t)kslot;
+        if (count > kslot) {
+          int64_t off = 0;
+          if (lane == 0) off = (int64_t)atomicAdd((unsigned long long*)cursor, (unsigned long long)count);
+          off = __shfl(off, 0);
+          base = off + count <= over_len ? n_atoms * (int64_t)kslot + off : -1;
         }
-        if (__any(shift_bad) && lane == 0)
-          atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
-        if (KEYS && count <= kslot) {
+        if (lane == 0) key_loc[i] = base;
+        if (base >= 0) {
           wave_lds_sync();
-          uint64_t* dst = row_keys + (int64_t)i * kslot;
+          uint64_t* dst = row_keys + base;
           for (int t = lane; t < count; t += kWave) {
             const uint64_t k = keyw[wv][t];
             int rank = 0;
@@ -667,26 +688,6 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
           }
           wave_lds_sync();
         }
-      } else if (count <= kRowMax) {  // longer rows were flagged by the counting pass; no fill then
-        wave_lds_sync();
-        const int64_t e0 = offsets[i];
-        const int64_t room = offsets[i + 1] - e0;
-        char4* sh4 = reinterpret_cast<char4*>(shift);
-        for (int t = lane; t < count; t += kWave) {
-          const uint64_t k = keyw[wv][t];
-          int rank = 0;
-          for (int u = 0; u < count; ++u) rank += keyw[wv][u] < k ? 1 : 0;
-          if (rank < room) {
-            nbr[e0 + rank] = (int32_t)(k >> 24);
-            char4 sv;
-            sv.x = (signed char)((int)((k >> 16) & 255) - 128);
-            sv.y = (signed char)((int)((k >> 8) & 255) - 128);
-            sv.z = (signed char)((int)(k & 255) - 128);
-            sv.w = 0;
-            sh4[e0 + rank] = sv;
-          }
-        }
-        wave_lds_sync();
       }
     }
     __syncthreads();
@@ -728,7 +729,8 @@ __device__ __forceinline__ void decode_key(uint64_t k, int32_t& j, char4& sv) {
 // Position of `want` in the sorted keys[0, len), or -1: rounds of seven
 // independent probes cut the range eightfold, then at most eight keys are
 // compared directly.
-__device__ __forceinline__ int find_key8(const uint64_t* __restrict__ keys, int len, uint64_t want) {
+template <class KeyAt>
+__device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t want) {
   int lo = 0, hi = len;  // keys[< lo] < want < keys[>= hi]
   while (hi - lo > 8) {
     const int step = (hi - lo + 7) >> 3;
@@ -736,7 +738,7 @@ __device__ __forceinline__ int find_key8(const uint64_t* __restrict__ keys, int 
 #pragma unroll
     for (int q = 0; q < 7; ++q) {
       const int p = lo + step * (q + 1);
-      kq[q] = p < hi ? keys[p] : ~0ull;
+      kq[q] = p < hi ? keys(p) : ~0ull;
     }
     int c = 0;  // probes below want
 #pragma unroll
@@ -749,7 +751,7 @@ __device__ __forceinline__ int find_key8(const uint64_t* __restrict__ keys, int 
   }
   uint64_t kq[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) kq[q] = lo + q < hi ? keys[lo + q] : ~0ull;
+  for (int q = 0; q < 8; ++q) kq[q] = lo + q < hi ? keys(lo + q) : ~0ull;
   int r = -1;
 #pragma unroll
   for (int q = 0; q < 8; ++q)
@@ -757,17 +759,18 @@ __device__ __forceinline__ int find_key8(const uint64_t* __restrict__ keys, int 
   return r;
 }
 
-// Writes the rows from the key slabs at their offsets, with the reverse
-// entry of every entry (i -> j, n): the entry (j -> i, -n) of row j, whose
-// position is the number of row j's keys below its key.  Also records the
+// Writes the rows from the keys the counting pass left (key_loc), with the
+// reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
+// whose position is found among row j's sorted keys.  Also records the
 // positions of this build (skin reference) and marks the list valid.  One
 // wave per atom.
-__global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys, int kslot,
+__global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys,
+                                                const int64_t* __restrict__ key_loc,
                                                 const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
                                                 int8_t* __restrict__ shift, int32_t* __restrict__ rev,
                                                 const double* __restrict__ pos, double* __restrict__ ref_pos,
                                                 int64_t* meta, const int32_t* flag) {
-  if (!flag[1] || flag[2]) return;
+  if (!flag[1]) return;
   const int64_t i = blockIdx.x;
   if (i >= N) return;
   const int lane = threadIdx.x;
@@ -778,13 +781,12 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
   }
   const int64_t e0 = offsets[i];
   const int len = (int)(offsets[i + 1] - e0);
-  const uint64_t* mine = row_keys + i * kslot;
+  const uint64_t* mine = row_keys + key_loc[i];
   char4* sh4 = reinterpret_cast<char4*>(shift);
   for (int t = lane; t < len; t += kWave) {
-    const uint64_t k = mine[t];
     int32_t j;
     char4 sv;
-    decode_key(k, j, sv);
+    decode_key(mine[t], j, sv);
     nbr[e0 + t] = j;
     sh4[e0 + t] = sv;
     char4 ns;
@@ -795,58 +797,12 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
     const uint64_t want = entry_key((int32_t)i, ns);
     const int64_t f0 = offsets[j];
     const int lj = (int)(offsets[j + 1] - f0);
-    const uint64_t* theirs = row_keys + (int64_t)j * kslot;
-    const int r = find_key8(theirs, lj, want);
-    const bool found = r >= 0;
+    const uint64_t* theirs = row_keys + key_loc[j];
+    const int r = find_key8([&](int p) { return theirs[p]; }, lj, want);
     // a missing reverse entry cannot happen for an exactly symmetric list;
     // point at the entry itself (zero net force) and flag it
-    rev[e0 + t] = (int32_t)(found ? f0 + r : e0 + t);
-    if (!found) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
-  }
-}
-
-// Fallback after a full fill (a row longer than its slab): the reverse entry
-// of every entry by binary search in the sorted rows of the list.  The list is exactly symmetric
-// because the FP64 displacement of the reverse entry is the exact negation.
-// Also records the positions of this build (skin reference) and marks the
-// list valid.
-__global__ void __launch_bounds__(64) k_nb_rev(int64_t N, const int64_t* __restrict__ offsets,
-                                               const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
-                                               int32_t* __restrict__ rev, const double* __restrict__ pos,
-                                               double* __restrict__ ref_pos, int64_t* meta, const int32_t* flag) {
-  if (!(flag[1] && flag[2])) return;
-  const int64_t i = blockIdx.x;
-  if (i >= N) return;
-  if (ref_pos && threadIdx.x < 3) ref_pos[3 * i + threadIdx.x] = pos[3 * i + threadIdx.x];
-  if (i == 0 && threadIdx.x == 0) {
-    meta[kMetaValid] = 1;
-    meta[kMetaBuilds] += 1;
-  }
-  const char4* sh4 = reinterpret_cast<const char4*>(shift);
-  for (int64_t e = offsets[i] + threadIdx.x; e < offsets[i + 1]; e += 64) {
-    int32_t j = nbr[e];
-    char4 s = sh4[e];
-    char4 ns;
-    ns.x = (signed char)(-s.x);
-    ns.y = (signed char)(-s.y);
-    ns.z = (signed char)(-s.z);
-    ns.w = 0;
-    uint64_t want = entry_key((int32_t)i, ns);
-    int64_t lo = offsets[j], hi = offsets[j + 1] - 1, found = -1;
-    while (lo <= hi) {
-      int64_t mid = (lo + hi) >> 1;
-      uint64_t k = entry_key(nbr[mid], sh4[mid]);
-      if (k == want) {
-        found = mid;
-        break;
-      }
-      if (k < want) lo = mid + 1;
-      else hi = mid - 1;
-    }
-    // a missing reverse entry cannot happen for an exactly symmetric list;
-    // point at the entry itself (zero net force) and flag it
-    rev[e] = (int32_t)(found >= 0 ? found : e);
-    if (found < 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+    rev[e0 + t] = (int32_t)(r >= 0 ? f0 + r : e0 + t);
+    if (r < 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
   }
 }
 
@@ -867,7 +823,10 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const int64_t N = sys->n_atoms;
   const int32_t B = sys->n_structs;
   const unsigned gN = (unsigned)((N + 255) / 256 > 0 ? (N + 255) / 256 : 1);
-  hipLaunchKernelGGL(k_nb_prep, dim3(1), dim3(256), 0, s, sys->atom_ptr, B, N, L.meta, L.flag, use_skin ? 1 : 0);
+  const bool sep_prep = use_skin || B == 0;  // else the geometry launch does it
+  if (sep_prep)
+    hipLaunchKernelGGL(k_nb_prep, dim3(1), dim3(256), 0, s, sys->atom_ptr, B, N, L.meta, L.flag, L.cursor,
+                       use_skin ? 1 : 0);
   if (use_skin && L.nl && L.nl->ref_pos && N > 0)
     hipLaunchKernelGGL(k_skin_check, dim3(gN), dim3(256), 0, s, sys->pos, L.nl->ref_pos, N, 0.25 * skin * skin,
                        L.meta, L.flag, 1);
@@ -876,7 +835,7 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   if (B > 0)
     hipLaunchKernelGGL(k_nb_geom, dim3(gGeom), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B,
                        L.radius, L.geom, L.n_bins, L.bin_count, n_zero, B == 1 ? L.bin_base : (int64_t*)nullptr,
-                       L.meta, L.flag);
+                       N, L.meta, L.flag, L.cursor, sep_prep ? 0 : 1);
   if (B != 1) exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
   const double r2 = L.radius * L.radius;
   if (N > 0)
@@ -890,14 +849,12 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
                        L.bin_m, L.bin_x, L.flag);
     if (count_only)
       hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
-                         sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts,
-                         (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, (uint64_t*)nullptr, 0,
-                         L.meta, L.flag);
+                         sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N,
+                         (uint64_t*)nullptr, 0, (int64_t)0, (int64_t*)nullptr, L.cursor, L.meta, L.flag);
     else
       hipLaunchKernelGGL(k_nb_rows<kRowsKeys>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
-                         sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts,
-                         (const int64_t*)nullptr, (int32_t*)nullptr, (int8_t*)nullptr, L.row_keys, L.kslot,
-                         L.meta, L.flag);
+                         sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N, L.row_keys,
+                         L.kslot, L.capacity, L.key_loc, L.cursor, L.meta, L.flag);
   }
   const CapacityJob cj{count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag};
   if (N <= kScanSmall) {
@@ -909,15 +866,8 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   }
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  hipLaunchKernelGGL(k_nb_emit, dim3((unsigned)N), dim3(64), 0, s, N, L.row_keys, L.kslot, nl->offsets, nl->nbr,
+  hipLaunchKernelGGL(k_nb_emit, dim3((unsigned)N), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
                      nl->shift, nl->rev, sys->pos, nl->ref_pos, L.meta, L.flag);
-  // fallback when some row did not fit its slab: both kernels exit at once otherwise
-  const unsigned gFill = (unsigned)std::min<int64_t>(gRows, 256);
-  hipLaunchKernelGGL(k_nb_rows<kRowsFill>, dim3(gFill, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr, sys->pbc, B,
-                     L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, (int64_t*)nullptr, nl->offsets, nl->nbr,
-                     nl->shift, (uint64_t*)nullptr, 0, L.meta, L.flag);
-  hipLaunchKernelGGL(k_nb_rev, dim3((unsigned)N), dim3(64), 0, s, N, nl->offsets, nl->nbr, nl->shift, nl->rev,
-                     sys->pos, nl->ref_pos, L.meta, L.flag);
 }
 
 }  // namespace nnp

@@ -193,3 +193,30 @@ def test_neighbor_list_long_rows_fallback():
     row_of = np.repeat(np.arange(len(off) - 1), np.diff(off))
     assert np.array_equal(got["nbr"][got["rev"]], row_of)
     assert np.array_equal(got["shift"][got["rev"]], -got["shift"])
+
+
+@pytest.mark.parametrize("skin", [0.0, 0.3])
+def test_decreasing_atom_ptr_is_reported(skin):
+    """A structure pointer array that decreases is caught on the device: the
+    build leaves the list invalid and nn_check reports it; a good pointer
+    array afterwards builds the same list as before."""
+    import torch
+    w = synth.config(2, scale=0.01)
+    pot = nnpot.Potential(w.system, w.params, w.model, skin=skin)
+    pot.build_neighbors()
+    good = pot.neighbor_list_host()
+    ptr = pot.atom_ptr.clone()
+    bad = ptr.clone()
+    bad[1], bad[2] = ptr[2], ptr[1]  # structure 1 ends before it starts
+    pot.atom_ptr.copy_(bad)
+    pot.set_positions(w.system.pos + 0.2)  # a skin list must rebuild too
+    pot.build_neighbors(check=False)
+    torch.cuda.synchronize()
+    with pytest.raises(nnpot.NNError, match="atom_ptr"):
+        nnpot.nn_check(pot.nl)
+    pot.atom_ptr.copy_(ptr)
+    pot.set_positions(w.system.pos)
+    pot.build_neighbors()
+    again = pot.neighbor_list_host()
+    assert np.array_equal(again["offsets"], good["offsets"])
+    assert np.array_equal(again["nbr"], good["nbr"])
