@@ -456,7 +456,7 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   hipStream_t s = (hipStream_t)stream;
   {
     StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, G, s);
+    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, s);
   }
   if (jac) {
     StageTimer t(NN_STAGE_DESC_JAC, s);
@@ -496,8 +496,10 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     if (sys->n_structs > 0) launch_energy_reduce(L.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
     return check_launch("nn_energy_forces");
   }
-  // species grouping
-  {
+  // species grouping (with one species the descriptor launch writes the
+  // identity grouping)
+  const bool fold_species = P.S == 1 && !reuse;
+  if (!fold_species) {
     StageTimer t(NN_STAGE_SPECIES, s);
     launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
   }
@@ -506,7 +508,7 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   // descriptors (and the stored Jacobian)
   if (!reuse) {
     StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, L.G, s);
+    launch_desc_fwd(*sys, *nl, P, L.G, fold_species ? IdentityGroup{L.perm, L.sp_start} : IdentityGroup{}, s);
   }
   if (stored && !reuse) {
     StageTimer t(NN_STAGE_DESC_JAC, s);

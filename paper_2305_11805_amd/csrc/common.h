@@ -133,7 +133,15 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
 
 // descriptors.hip
 bool desc_supported(int nt, int nra);
-void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s);
+// With one species the grouping is the identity: the descriptor launch
+// writes perm[i] = i and sp_start = {0, N} itself (and flags atoms whose
+// species is not 0) when perm is set.
+struct IdentityGroup {
+  int32_t* perm;
+  int64_t* sp_start;
+};
+void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
+                     hipStream_t s);
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                      hipStream_t s);
 // FP64 sum of E_atom over structure c by one block of 256 threads (a fixed

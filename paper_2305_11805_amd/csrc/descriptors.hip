@@ -283,9 +283,18 @@ template <int NT, int NRA, int WPA, int ZC>
 __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ nbr,
                                                        const int8_t* __restrict__ shift, DescConst P,
-                                                       float* __restrict__ G, int64_t* meta) {
+                                                       float* __restrict__ G, int64_t* meta, IdentityGroup one) {
   constexpr int NB = NT * NRA;
   __shared__ AtomNb nb;
+  if (one.perm && threadIdx.x == 0) {
+    one.perm[blockIdx.x] = (int32_t)blockIdx.x;
+    if (sys.species[blockIdx.x] != 0)
+      atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+    if (blockIdx.x == 0) {
+      one.sp_start[0] = 0;
+      one.sp_start[1] = sys.n_atoms;
+    }
+  }
   // per-wave partial sums (radial bins: S * n_rad <= 512; angular block: NB)
   __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
   const int64_t i = blockIdx.x;
@@ -626,20 +635,22 @@ __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* 
 static int waves_per_atom(int64_t n_atoms) { return n_atoms <= 16384 ? 2 : 1; }
 
 template <int NT, int NRA, int WPA, int ZC>
-static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
+static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
+                         hipStream_t s) {
   hipLaunchKernelGGL((k_desc_fwd<NT, NRA, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), 0, s, sys,
-                     nl.offsets, nl.nbr, nl.shift, P, G, nl.meta);
+                     nl.offsets, nl.nbr, nl.shift, P, G, nl.meta, one);
 }
 
 template <int NT, int NRA>
-static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
+static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
+                         hipStream_t s) {
   const int wpa = waves_per_atom(sys.n_atoms);
   if (P.zeta == 50) {
-    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 50>(sys, nl, P, G, s);
-    else launch_fwd_w<NT, NRA, 1, 50>(sys, nl, P, G, s);
+    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 50>(sys, nl, P, G, one, s);
+    else launch_fwd_w<NT, NRA, 1, 50>(sys, nl, P, G, one, s);
   } else {
-    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 0>(sys, nl, P, G, s);
-    else launch_fwd_w<NT, NRA, 1, 0>(sys, nl, P, G, s);
+    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 0>(sys, nl, P, G, one, s);
+    else launch_fwd_w<NT, NRA, 1, 0>(sys, nl, P, G, one, s);
   }
 }
 
@@ -685,10 +696,11 @@ bool desc_supported(int nt, int nra) {
     else if (nt == 16 && nra == 8) { constexpr int NT_ = 16, NRA_ = 8; CALL; } \
   } while (0)
 
-void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, hipStream_t s) {
+void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
+                     hipStream_t s) {
   if (sys.n_atoms == 0) return;
   const int nt = P.n_theta, nra = P.n_rs_ang;
-  NNP_DISPATCH(A, B, (launch_fwd_t<A, B>(sys, nl, P, G, s)));
+  NNP_DISPATCH(A, B, (launch_fwd_t<A, B>(sys, nl, P, G, one, s)));
 }
 
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,

@@ -209,14 +209,19 @@ __device__ __forceinline__ void b_frag(const __bf16* p, const __bf16* p_lo, int 
   }
 }
 
-// One 16-atom tile per block of kWaves waves.  Wave w owns the 16-column
-// output tiles n = w, w + kWaves, ... of every product, so act'(z) of its
+// One 16-atom tile per block of NW waves.  Wave w owns the 16-column
+// output tiles n = w, w + NW, ... of every product, so act'(z) of its
 // layer-1 and layer-2 tiles stays in its registers; activations and deltas
 // are exchanged through two LDS buffers.
-constexpr int kWaves = 4;
+// Waves per tile: one per 16 hidden units of layer 1, at most 8.
+template <int H1T>
+constexpr int mlp_waves() {
+  return H1T < 8 ? H1T : 8;
+}
 
 template <int H1T, int H2T, int MODE>
-__global__ void __launch_bounds__(64 * kWaves) k_mlp(MlpArgs args) {
+__global__ void __launch_bounds__(64 * mlp_waves<H1T>()) k_mlp(MlpArgs args) {
+  constexpr int kWaves = mlp_waves<H1T>();
   constexpr int H1 = H1T * 16, H2 = H2T * 16;
   constexpr int HM = H1 > H2 ? H1 : H2;
   constexpr bool BF = MODE != kFp32;
@@ -559,7 +564,7 @@ bool mlp_supported(int h1, int h2) {
 
 template <int A, int B>
 static void launch_mlp_t(const MlpArgs& a, int mode, int64_t n_tiles, hipStream_t s) {
-  const dim3 g((unsigned)n_tiles), b(64 * kWaves);
+  const dim3 g((unsigned)n_tiles), b(64 * mlp_waves<A>());
   if (mode == kBf16x3) hipLaunchKernelGGL((k_mlp<A, B, kBf16x3>), g, b, 0, s, a);
   else if (mode == kBf16) hipLaunchKernelGGL((k_mlp<A, B, kBf16>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_mlp<A, B, kFp32>), g, b, 0, s, a);
