@@ -156,6 +156,190 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernel="k_desc_ad
     print(json.dumps(cnt[f"{kernel}:{workload}"]))
 
 
+def _timed(torch, stream, fn, k):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(k):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def suite_config(idx, modes, steps, out):
+    """Every workload at full size: throughput (eager step, graph replay,
+    standing list) per MLP mode, errors against the FP64 oracle, the oracle's
+    own throughput, and the workload-specific extras (batched vs per-structure
+    launches and the loss gradient for the cluster batch, the 100-step random
+    walk with skin rebuilds for the large bulk cell)."""
+    import torch
+    import oracle
+    from paper_2305_11805_amd import nnpot, synth
+    oracle.build(force=False)
+    w = synth.config(idx)
+    s, p = w.system, w.params
+    stream = torch.cuda.current_stream()
+    skin = float(w.extra.get("skin", 0.0))
+    res = {"config": idx, "workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "modes": {}}
+    md = idx == 4
+    if md:
+        nsteps = int(w.extra["steps"])
+        xi = torch.tensor(np.stack(list(synth.md_displacements(w.seed, s.n_atoms, nsteps, w.extra["step_sigma"]))),
+                          dtype=torch.float64, device="cuda")
+    # oracle reference (full for small workloads, seeded samples for the MD cell)
+    t0 = time.perf_counter()
+    if not md:
+        nl_ref = oracle.neighbors_cells(s, p.rc)
+        Es_ref, _, F_ref = oracle.energy_forces(p, w.model, s, nl_ref)
+        t_or = time.perf_counter() - t0
+        G_ref = oracle.descriptors(p, s, nl_ref)
+        res["oracle"] = {"atoms_per_s": s.n_atoms / t_or, "cores": oracle.num_threads(), "seconds": round(t_or, 2),
+                         "what": "full neighbor list + E + F"}
+    else:
+        rng = np.random.Generator(np.random.PCG64(5))
+        tgt = np.sort(rng.choice(s.n_atoms, 64, replace=False))
+        own = oracle.neighbors_cells(s, p.rc, rows=tgt)
+        rows = np.array(sorted(set(tgt.tolist()) | set(own["nbr"].tolist())), np.int64)
+        nl_s = oracle.neighbors_cells(s, p.rc, rows=rows)
+        _, F0_ref = oracle.forces(p, w.model, s, nl_s, tgt)
+        t_or = time.perf_counter() - t0
+        res["oracle"] = {"atoms_per_s": len(tgt) / t_or, "cores": oracle.num_threads(), "seconds": round(t_or, 2),
+                         "what": f"forces on 64 seeded atoms (rows of {len(rows)} atoms)"}
+    n_c = np.diff(s.atom_ptr)
+    for mode in modes:
+        flags = {"fp32": 0, "bf16": nnpot.NN_BF16_MLP, "bf16x3": nnpot.NN_BF16X3_MLP}[mode]
+        pot = nnpot.Potential(s, p, w.model, skin=skin, flags=flags, capacity_margin=1.3 if md else 1.25)
+        r = {}
+
+        def build():
+            nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+
+        def ef():
+            nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, flags, 0, pot.E_struct,
+                                   pot.E_atom, pot.F, pot.ws)
+
+        if not md:
+            def step():
+                build()
+                ef()
+            for _ in range(3):
+                step()
+            torch.cuda.synchronize()
+            nnpot.nn_check(pot.nl)
+            ms = _timed(torch, stream, step, steps) / steps
+            r["eager_step"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            ms = _timed(torch, stream, ef, steps) / steps
+            r["standing_list"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                step()
+            torch.cuda.synchronize()
+            ms = _timed(torch, stream, g.replay, steps) / steps
+            r["graph_replay"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            torch.cuda.synchronize()
+            nnpot.nn_check(pot.nl)
+            Es = pot.E_struct.cpu().numpy()
+            F = pot.F.cpu().numpy()
+            dE = np.abs(Es - Es_ref) / np.maximum(n_c, 1)
+            dF = np.abs(F - F_ref)
+            r["errors"] = {"E_per_atom_max": float(dE.max()), "E_per_atom_rms": float(np.sqrt(np.mean(dE ** 2))),
+                           "F_max": float(dF.max()), "F_rms": float(np.sqrt(np.mean(dF ** 2)))}
+            if mode == modes[0]:
+                G = pot.descriptors().cpu().numpy().astype(np.float64)
+                floor = 1e-6 * np.max(np.abs(G_ref), axis=1, keepdims=True)
+                den = np.maximum(np.abs(G_ref), floor)
+                err = np.abs(G - G_ref)
+                # rows with no neighbors are all zero on both sides
+                r["errors"]["G_max_rel"] = float(np.max(np.where(den > 0, err / np.where(den > 0, den, 1.0), err)))
+        else:
+            pos0 = pot.pos.clone()
+            build()
+            ef()
+            torch.cuda.synchronize()
+            nnpot.nn_check(pot.nl)
+            F0 = pot.F.cpu().numpy()
+            b0 = int(pot.meta[2].item())
+            k = [0]
+
+            def md_step():
+                pot.pos.add_(xi[k[0]])
+                k[0] += 1
+                build()
+                ef()
+            ms = _timed(torch, stream, md_step, nsteps) / nsteps
+            nnpot.nn_check(pot.nl)
+            r["md_walk"] = {"steps": nsteps, "ms_per_step": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1),
+                            "rebuilds": int(pot.meta[2].item()) - b0,
+                            "what": "x += N(0, 0.02 A) per component, skin 0.5 A, rebuild when an atom moved > skin/2"}
+            ms = _timed(torch, stream, ef, 20) / 20
+            r["standing_list"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            F_end = pot.F.cpu().numpy()
+            pos_end = pot.pos.cpu().numpy()
+            s_end = synth.System(pos_end, s.species, s.atom_ptr, s.cell, s.pbc)
+            own = oracle.neighbors_cells(s_end, p.rc, rows=tgt)
+            rows = np.array(sorted(set(tgt.tolist()) | set(own["nbr"].tolist())), np.int64)
+            _, F1_ref = oracle.forces(p, w.model, s_end, oracle.neighbors_cells(s_end, p.rc, rows=rows), tgt)
+            r["errors"] = {"F_max_step0_sampled": float(np.max(np.abs(F0[tgt] - F0_ref))),
+                           "F_max_last_step_sampled": float(np.max(np.abs(F_end[tgt] - F1_ref)))}
+            pot.pos.copy_(pos0)
+        res["modes"][mode] = r
+        if idx == 2 and mode == modes[0]:
+            # loss gradient step: E, F and dL/dW of L = mean_c (E_c - T_c)^2
+            T = torch.tensor(synth.energy_targets(w.seed, s.n_structs), dtype=torch.float64, device="cuda")
+
+            def grad_step():
+                build()
+                ef()
+                dL = (2.0 / s.n_structs) * (pot.E_struct - T)
+                pot.grad(dL, positions=False, weights=True)
+            grad_step()
+            ms = _timed(torch, stream, grad_step, steps) / steps
+            res["loss_gradient_step"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            # the same structures, one Potential and one launch sequence each
+            sub = 64
+            pots = [nnpot.Potential(synth.single(s.pos[s.atom_ptr[c]:s.atom_ptr[c + 1]],
+                                                 s.species[s.atom_ptr[c]:s.atom_ptr[c + 1]],
+                                                 cell=s.cell[c], pbc=s.pbc[c]), p, w.model)
+                    for c in range(sub)]
+            n_sub = int(s.atom_ptr[sub])
+
+            def per_structure():
+                for q in pots:
+                    q.build_neighbors(check=False)
+                    q.energy_forces()
+            per_structure()
+            ms = _timed(torch, stream, per_structure, 5) / 5
+            aps = n_sub / ms * 1e3
+            res["per_structure_launches"] = {"structures": sub, "atoms": n_sub, "ms": round(ms, 4),
+                                             "atoms_per_s": round(aps, 1),
+                                             "batched_over_per_structure": round(r["eager_step"]["atoms_per_s"] / aps, 2)}
+        del pot
+        torch.cuda.empty_cache()
+    if len(modes) > 1:
+        key = "eager_step" if not md else "md_walk"
+        base = res["modes"]["fp32"][key]["atoms_per_s"]
+        res["bf16_over_fp32"] = {m: round(res["modes"][m][key]["atoms_per_s"] / base, 3) for m in modes if m != "fp32"}
+    out.write(json.dumps(res) + "\n")
+    out.flush()
+    print(json.dumps(res), flush=True)
+
+
+def suite(args):
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    path = args.suite_out
+    with open(path, "w") as out:
+        for idx in args.suite_configs:
+            modes = ["fp32", "bf16x3", "bf16"] if idx in (3, 4) else ["fp32"]
+            print(f"[suite] config {idx}", file=sys.stderr, flush=True)
+            suite_config(idx, modes, args.steps, out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +353,10 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 --pmc CSVs of this workload into profiles/counters.json")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure every workload (one JSON line each) instead of the single bench line")
+    ap.add_argument("--suite-configs", type=int, nargs="*", default=[0, 1, 2, 3, 4])
+    ap.add_argument("--suite-out", default="suite.jsonl")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -176,6 +364,9 @@ def main():
         sys.exit(2)
 
     from paper_2305_11805_amd import synth
+    if args.suite:
+        suite(args)
+        return
     if args.ingest_counters:
         if args.calib_copy_mib <= 0:
             raise SystemExit("--ingest-counters needs --calib-copy-mib of the profiled run")

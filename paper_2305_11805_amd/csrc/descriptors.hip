@@ -468,13 +468,12 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
       gz[wv][t] += gr * u.z;
     }
   }
-  float Lr[ONE_SPECIES ? NB : 1];
-  if constexpr (ONE_SPECIES) {
-#pragma unroll
-    for (int t = 0; t < NB; ++t) Lr[t] = lam_a[t];
-  }
   const int zeta1 = P.zeta - 1;
   const float zf = (float)P.zeta;
+  const float sq_eta_a2 = sqrtf(eta_a2);
+  float rs_sc[NRA];
+#pragma unroll
+  for (int q = 0; q < NRA; ++q) rs_sc[q] = P.rs_ang[q] * sq_eta_a2;
   // angular: the unordered pairs {j, (j + s) mod n} for s = 1 .. n/2 (for
   // even n the step n/2 only for j < n/2), numbered t = (s - 1) n + j and
   // taken 64 at a time (wave w: chunks w, w + WPA, ...), so every lane has a
@@ -507,11 +506,15 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
       ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
 #pragma unroll
       for (int p = 0; p < NT; ++p) A[p] = P1[p] * x[p];
+      // R_q = 2^(-dq_q^2) with dq_q = sqrt(eta log2 e) (rbar - Rs'_q); the
+      // hi/lo split of rbar and Rs' that the forward pass keeps for the
+      // descriptor values is below what the gradient needs
       float R[NRA], dq[NRA];
+      const float rb = g.rbar * sq_eta_a2;
 #pragma unroll
       for (int q = 0; q < NRA; ++q) {
-        dq[q] = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
-        R[q] = fexp2(-eta_a2 * dq[q] * dq[q]);
+        dq[q] = rb - rs_sc[q];
+        R[q] = fexp2(-dq[q] * dq[q]);
       }
       float Tq[NRA], U[NT];
 #pragma unroll
@@ -521,9 +524,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
         float tq = 0.f;
 #pragma unroll
         for (int p = 0; p < NT; ++p) {
-          float l;
-          if constexpr (ONE_SPECIES) l = Lr[q * NT + p];
-          else l = La[q * NT + p];
+          const float l = La[q * NT + p];  // LDS (a broadcast with one species)
           tq = fmaf(l, A[p], tq);
           U[p] = fmaf(l, R[q], U[p]);
         }
@@ -536,7 +537,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
         dEdF2 = fmaf(Tq[q], R[q], dEdF2);
         dEdravg = fmaf(Tq[q] * R[q], dq[q], dEdravg);
       }
-      dEdravg *= -2.0f * P.eta_ang * F2;
+      dEdravg *= -2.0f * P.eta_ang / sq_eta_a2 * F2;
       float dEdc = 0.f, dEdssm = 0.f;
 #pragma unroll
       for (int p = 0; p < NT; ++p) {
