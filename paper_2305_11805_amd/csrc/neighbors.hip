@@ -680,10 +680,19 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
         if (base >= 0) {
           wave_lds_sync();
           uint64_t* dst = row_keys + base;
+          const uint64_t* kw = keyw[wv];
           for (int t = lane; t < count; t += kWave) {
-            const uint64_t k = keyw[wv][t];
+            const uint64_t k = kw[t];
             int rank = 0;
-            for (int u = 0; u < count; ++u) rank += keyw[wv][u] < k ? 1 : 0;
+            int u = 0;
+            for (; u + 8 <= count; u += 8) {  // eight independent LDS reads in flight
+              uint64_t v[8];
+#pragma unroll
+              for (int q = 0; q < 8; ++q) v[q] = kw[u + q];
+#pragma unroll
+              for (int q = 0; q < 8; ++q) rank += v[q] < k ? 1 : 0;
+            }
+            for (; u < count; ++u) rank += kw[u] < k ? 1 : 0;
             dst[rank] = k;
           }
           wave_lds_sync();
