@@ -94,7 +94,11 @@ typedef struct nn_system {
  *   (n_a, n_b, n_c, 0), rev [capacity] int32 (index of the reverse entry
  *   (j -> i, -n)), ref_pos [N][3] FP64 (positions at the last build),
  *   meta [8] int64 (nnz, valid, builds, rebuilt-last-call, error bits,
- *   -, -, -); zero meta once before the first build.
+ *   -, -, -); zero meta once before the first build;
+ *   order [N] int32, optional (NULL: not kept): the atoms in cell-bin order
+ *   at the last build.  When present, the force gather walks the atoms in
+ *   this order, each XCD taking a contiguous run of it, so that the rows
+ *   read together are those of nearby atoms and share that XCD's L2.
  * radius is written by nn_build_neighbors (host field).
  */
 typedef struct nn_nlist {
@@ -105,6 +109,7 @@ typedef struct nn_nlist {
   int32_t* rev;
   double* ref_pos;
   int64_t* meta;
+  int32_t* order;
   double radius;
 } nn_nlist;
 

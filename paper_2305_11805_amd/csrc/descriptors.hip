@@ -594,18 +594,30 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
 // F_k = sum over entries e of row k of (pg[e] - pg[rev[e]]).  Sixteen lanes
 // per atom take the row's entries round robin; the partial sums are combined
 // by a fixed xor-shuffle tree, so the result does not depend on scheduling.
+// With the list's bin order, block b takes the atoms of slot block
+// (b mod 8) * per + b / 8: consecutive blocks go to different XCDs, so each
+// XCD walks one contiguous stretch of the bin order and the neighbor rows
+// its atoms read back stay in its L2.
 __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ rev, const float4* __restrict__ pg,
-                                                      float* __restrict__ F, const int64_t* meta,
-                                                      unsigned n_gather_blocks, EnergyJob ej) {
+                                                      const int32_t* __restrict__ order, float* __restrict__ F,
+                                                      const int64_t* meta, unsigned n_gather_blocks, EnergyJob ej) {
   if (blockIdx.x >= n_gather_blocks) {
     energy_block_sum(ej.E_atom, ej.atom_ptr, N, (int)(blockIdx.x - n_gather_blocks), ej.E_struct);
     return;
   }
-  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const bool valid = meta[kMetaValid] == 1;
+  int64_t blk = blockIdx.x;
+  if (order) {
+    const unsigned per = (n_gather_blocks + 7) / 8;
+    blk = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  }
+  const int64_t slot = ((blk * blockDim.x) + threadIdx.x) >> 4;
   const int sub = threadIdx.x & 15;
+  int64_t k = slot;
+  if (order && valid && slot < N) k = order[slot];
   float fx = 0.f, fy = 0.f, fz = 0.f;
-  if (k < N && meta[kMetaValid] == 1) {
+  if (slot < N && valid) {
     const int64_t e1 = offsets[k + 1];
     for (int64_t e = offsets[k] + sub; e < e1; e += 16) {
       const float4 a = pg[e], b = pg[rev[e]];
@@ -620,7 +632,7 @@ __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* 
     fy += __shfl_xor(fy, m, 16);
     fz += __shfl_xor(fz, m, 16);
   }
-  if (sub == 0 && k < N) {
+  if (sub == 0 && slot < N) {
     F[3 * k] = fx;
     F[3 * k + 1] = fy;
     F[3 * k + 2] = fz;
@@ -715,10 +727,11 @@ void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& 
 // per-structure energies (ej.B of them) in the same launch.
 void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4* pg, float* F, const EnergyJob& ej,
                          hipStream_t s) {
-  const unsigned ng = (unsigned)((sys.n_atoms * 16 + 255) / 256);
+  unsigned ng = (unsigned)((sys.n_atoms * 16 + 255) / 256);
+  if (nl.order) ng = (ng + 7) / 8 * 8;  // whole rounds of the eight XCDs (the extra slots are past N)
   if (ng + (unsigned)ej.B == 0) return;
   hipLaunchKernelGGL(k_force_gather, dim3(ng + (unsigned)ej.B), dim3(256), 0, s, sys.n_atoms, nl.offsets, nl.rev, pg,
-                     F, nl.meta, ng, ej);
+                     nl.order, F, nl.meta, ng, ej);
 }
 
 

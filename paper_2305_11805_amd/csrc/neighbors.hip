@@ -420,7 +420,8 @@ __global__ void k_nb_bin(const double* __restrict__ pos, const int64_t* __restri
 // the binning pass's atomics ran (rows are sorted afterwards).
 __global__ void k_nb_scatter(int64_t N, const double* __restrict__ pos, const int32_t* __restrict__ atom_bin,
                              const int32_t* __restrict__ bin_rank, const int64_t* __restrict__ bin_start,
-                             int4* __restrict__ bin_m, double4* __restrict__ bin_x, const int32_t* flag) {
+                             int4* __restrict__ bin_m, double4* __restrict__ bin_x, int32_t* __restrict__ order,
+                             const int32_t* flag) {
   if (!*flag) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
@@ -429,6 +430,7 @@ __global__ void k_nb_scatter(int64_t N, const double* __restrict__ pos, const in
   const int64_t k = bin_start[bin] + bin_rank[i];
   bin_m[k] = make_int4((int)i, atom_bin[4 * i + 1], atom_bin[4 * i + 2], atom_bin[4 * i + 3]);
   bin_x[k] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
+  if (order) order[k] = (int32_t)i;
 }
 
 __device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc) {
@@ -855,7 +857,7 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const unsigned gRows = (unsigned)std::max<int64_t>(1, std::min<int64_t>(L.max_bins, 2048));
   if (N > 0) {
     hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, sys->pos, L.atom_bin, L.bin_rank, L.bin_start,
-                       L.bin_m, L.bin_x, L.flag);
+                       L.bin_m, L.bin_x, (count_only || !L.nl) ? (int32_t*)nullptr : L.nl->order, L.flag);
     if (count_only)
       hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N,

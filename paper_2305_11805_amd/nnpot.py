@@ -42,7 +42,8 @@ class nn_system(C.Structure):
 
 class nn_nlist(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("offsets", C.c_void_p), ("nbr", C.c_void_p), ("shift", C.c_void_p),
-                ("rev", C.c_void_p), ("ref_pos", C.c_void_p), ("meta", C.c_void_p), ("radius", C.c_double)]
+                ("rev", C.c_void_p), ("ref_pos", C.c_void_p), ("meta", C.c_void_p), ("order", C.c_void_p),
+                ("radius", C.c_double)]
 
 
 class nn_mbp_params(C.Structure):
@@ -284,8 +285,10 @@ class Potential:
         self.rev = z(self.capacity, torch.int32)
         self.ref_pos = z((self.N, 3), torch.float64)
         self.meta = z(8, torch.int64)
+        self.order = z(max(self.N, 1), torch.int32)
         self.nl = nn_nlist(self.capacity, self.offsets.data_ptr(), self.nbr.data_ptr(), self.shift.data_ptr(),
-                           self.rev.data_ptr(), self.ref_pos.data_ptr(), self.meta.data_ptr(), 0.0)
+                           self.rev.data_ptr(), self.ref_pos.data_ptr(), self.meta.data_ptr(),
+                           self.order.data_ptr(), 0.0)
         ws = nn_workspace_size(self.N, self.B, self.capacity, self.params,
                                self.dmodel.struct if self.dmodel else None, flags, self.mem_budget)
         self.ws = torch.empty(ws, dtype=torch.uint8, device=self.dev)
