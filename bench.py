@@ -227,6 +227,7 @@ def suite_config(idx, modes, steps, out):
                 step()
             torch.cuda.synchronize()
             nnpot.nn_check(pot.nl)
+            r["launch_plan"] = pot.autotune()
             ms = _timed(torch, stream, step, steps) / steps
             r["eager_step"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
             ms = _timed(torch, stream, ef, steps) / steps
@@ -260,6 +261,7 @@ def suite_config(idx, modes, steps, out):
             ef()
             torch.cuda.synchronize()
             nnpot.nn_check(pot.nl)
+            r["launch_plan"] = pot.autotune()
             F0 = pot.F.cpu().numpy()
             b0 = int(pot.meta[2].item())
             k = [0]
@@ -349,6 +351,7 @@ def main():
     ap.add_argument("--mode", choices=["fp32", "bf16", "bf16x3"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the steady-state and graph-replay timings")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch plan")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -400,6 +403,10 @@ def main():
         step()
     torch.cuda.synchronize()
     nnpot.nn_check(pot.nl)
+    plan = None if args.no_autotune else pot.autotune()  # launch plan for this shape class (untimed)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
 
@@ -485,7 +492,10 @@ def main():
                                                         "bf16x3": "bf16x3-mlp/f32"}[args.mode],
         "data": "synthetic (seeded RSA positions, seeded N(0, 1/fan_in) weights)",
         "config": {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
-                   "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed},
+                   "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed,
+                   "launch_plan": None if plan is None else {"waves_per_atom_fwd": plan[0],
+                                                             "waves_per_atom_adj": plan[1],
+                                                             "waves_per_mlp_tile": plan[2]}},
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
         "ms_per_step_with_stage_events": round(staged_ms / args.steps, 4),

@@ -242,6 +242,27 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
                            float* E_atom, float* F, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Launch tuning (the tiles of the batching step): times the launch variants
+ * of this workload's passes -- waves per atom of the descriptor forward and
+ * adjoint passes (1, 2, 4) and waves per MLP tile (4, 8) -- on `stream`,
+ * and keeps the fastest for workloads of the same shape class (atom count
+ * within a factor of two, list entries per atom, descriptor sizes, MLP
+ * widths and MLP mode) in a process-wide table that nn_energy_forces and
+ * nn_energy_forces_grad then use; without an entry they use fixed rules.
+ * Needs a valid list (nn_build_neighbors) and the nn_energy_forces
+ * workspace; overwrites the workspace's descriptors and lambda.  Blocks
+ * until the timings are done, so it must not be called while the stream is
+ * being captured into a graph.  A plan changes only the order of some sums:
+ * results stay bitwise reproducible for a fixed table.  plan_out [host]
+ * (nullable) receives {waves/atom forward, waves/atom adjoint, waves/MLP tile}.
+ */
+nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
+                      int32_t flags, void* ws, size_t ws_bytes, void* stream, int32_t* plan_out);
+
+/* Forgets every plan nn_autotune stored. */
+void nn_autotune_reset(void);
+
+/*
  * Backward of E_struct with respect to positions and weights, given
  * dL_dE [device] FP64 [B] (Sec. II.A: the loss is minimised over the MLP
  * parameters).  Must follow nn_energy_forces with the same arguments and

@@ -7,7 +7,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "common.h"
@@ -32,6 +34,45 @@ static nn_status check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(NN_E_HIP, "%s: %s", what, hipGetErrorString(e));
   return NN_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch plans: the defaults, or the ones nn_autotune measured for a shape
+// class (atom count within a factor of two, list entries per atom rounded
+// to a multiple of four, descriptor sizes, MLP widths and mode)
+// ---------------------------------------------------------------------------
+
+struct PlanKey {
+  int n_log2, row4, S, nt, nra, n_rad, h1, h2, mode;
+  bool operator<(const PlanKey& o) const {
+    return std::tie(n_log2, row4, S, nt, nra, n_rad, h1, h2, mode) <
+           std::tie(o.n_log2, o.row4, o.S, o.nt, o.nra, o.n_rad, o.h1, o.h2, o.mode);
+  }
+};
+static std::mutex g_pmu;
+static std::map<PlanKey, LaunchPlan> g_plans;
+
+static PlanKey plan_key(int64_t n_atoms, int64_t capacity, const DescConst& P, const nn_model* model, int mode) {
+  PlanKey k{};
+  int b = 0;
+  for (int64_t v = n_atoms; v > 0; v >>= 1) ++b;
+  k.n_log2 = b;
+  k.row4 = n_atoms > 0 ? (int)(((capacity + n_atoms - 1) / n_atoms + 2) / 4) : 0;
+  k.S = P.S;
+  k.nt = P.n_theta;
+  k.nra = P.n_rs_ang;
+  k.n_rad = P.n_rad;
+  k.h1 = model ? model->mlp[0].width[1] : 0;
+  k.h2 = model ? model->mlp[0].width[2] : 0;
+  k.mode = mode;
+  return k;
+}
+
+static LaunchPlan plan_for(int64_t n_atoms, int64_t capacity, const DescConst& P, const nn_model* model, int mode) {
+  const PlanKey k = plan_key(n_atoms, capacity, P, model, mode);
+  std::lock_guard<std::mutex> g(g_pmu);
+  auto it = g_plans.find(k);
+  return it != g_plans.end() ? it->second : plan_default(n_atoms);
 }
 
 // ---------------------------------------------------------------------------
@@ -456,7 +497,7 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   hipStream_t s = (hipStream_t)stream;
   {
     StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, s);
+    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, plan_default(sys->n_atoms).wpa_fwd, s);
   }
   if (jac) {
     StageTimer t(NN_STAGE_DESC_JAC, s);
@@ -496,6 +537,7 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     if (sys->n_structs > 0) launch_energy_reduce(L.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
     return check_launch("nn_energy_forces");
   }
+  const LaunchPlan plan = plan_for(N, nl->capacity, P, model, mode);
   // species grouping (with one species the descriptor launch writes the
   // identity grouping)
   const bool fold_species = P.S == 1 && !reuse;
@@ -508,7 +550,8 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   // descriptors (and the stored Jacobian)
   if (!reuse) {
     StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, L.G, fold_species ? IdentityGroup{L.perm, L.sp_start} : IdentityGroup{}, s);
+    launch_desc_fwd(*sys, *nl, P, L.G, fold_species ? IdentityGroup{L.perm, L.sp_start} : IdentityGroup{},
+                    plan.wpa_fwd, s);
   }
   if (stored && !reuse) {
     StageTimer t(NN_STAGE_DESC_JAC, s);
@@ -523,7 +566,7 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   a.D = P.D;
   {
     StageTimer t(NN_STAGE_MLP, s);
-    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
+    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
   }
   if (!F) {
     StageTimer t(NN_STAGE_ENERGY, s);
@@ -534,13 +577,92 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
       launch_jac_contract(*sys, *nl, P, L.lam, L.jac, L.pg, s);
     } else {
       StageTimer t(NN_STAGE_DESC_ADJ, s);
-      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, s);
+      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, plan.wpa_adj, s);
     }
     // the per-structure energy sums ride along in the gather's launch
     StageTimer t(NN_STAGE_FORCE_GATHER, s);
     launch_force_gather(*sys, *nl, L.pg, F, EnergyJob{a.E_atom, sys->atom_ptr, sys->n_structs, E_struct}, s);
   }
   return check_launch("nn_energy_forces");
+}
+
+nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
+                      int32_t flags, void* ws, size_t ws_bytes, void* stream, int32_t* plan_out) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((st = check_model(model, P))) return st;
+  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
+  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
+    return fail(NN_E_INVALID, "unknown flags");
+  if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
+    return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
+  const int64_t N = sys->n_atoms;
+  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
+  LaunchPlan best = plan_default(N);
+  if (N > 0) {
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+      return fail(NN_E_HIP, "nn_autotune: event creation failed");
+    // mean time of three launches after one untimed one; -1 on an error
+    auto time_of = [&](auto&& launch) -> float {
+      launch();
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r) launch();
+      hipEventRecord(e1, s);
+      float ms = -1.f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+      return ms / 3.f;
+    };
+    launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+    MlpArgs a{};
+    prepare_model(model, P, L, mode != 0, a, s);
+    a.G = L.G;
+    a.perm = L.perm;
+    a.sp_start = L.sp_start;
+    a.E_atom = L.E_atom;
+    a.lambda = L.lam;
+    a.D = P.D;
+    const int h1 = model->mlp[0].width[1], h2 = model->mlp[0].width[2];
+    float t_best = -1.f;
+    for (int w : {1, 2, 4}) {  // descriptor forward
+      const float t = time_of([&] { launch_desc_fwd(*sys, *nl, P, L.G, IdentityGroup{}, w, s); });
+      if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_fwd = w;
+    }
+    t_best = -1.f;
+    for (int w : {4, 8}) {  // MLP (lambda for the adjoint timings comes from here)
+      if (w == 8 && h1 < 128) continue;
+      const float t = time_of([&] { launch_mlp(a, h1, h2, mode, N, w, s); });
+      if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.mlp_waves = w;
+    }
+    t_best = -1.f;
+    for (int w : {1, 2, 4}) {  // adjoint
+      const float t = time_of([&] { launch_desc_adj(*sys, *nl, P, L.lam, L.pg, w, s); });
+      if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_adj = w;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if ((st = check_launch("nn_autotune"))) return st;
+    std::lock_guard<std::mutex> g(g_pmu);
+    g_plans[plan_key(N, nl->capacity, P, model, mode)] = best;
+  }
+  if (plan_out) {
+    plan_out[0] = best.wpa_fwd;
+    plan_out[1] = best.wpa_adj;
+    plan_out[2] = best.mlp_waves;
+  }
+  return NN_OK;
+}
+
+void nn_autotune_reset(void) {
+  std::lock_guard<std::mutex> g(g_pmu);
+  g_plans.clear();
 }
 
 nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
@@ -581,7 +703,8 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
     a.st_d1 = L.st_d1;
     a.st_a2 = L.st_a2;
     a.st_d2 = L.st_d2;
-    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, s);
+    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N,
+               plan_for(N, nl->capacity, P, model, mode).mlp_waves, s);
     launch_atom_weights(dL_dE, sys->atom_ptr, sys->n_structs, N, L.w_atom, s);
     WgradArgs g{};
     g.perm = L.perm;

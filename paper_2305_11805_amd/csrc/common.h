@@ -140,10 +140,19 @@ struct IdentityGroup {
   int32_t* perm;
   int64_t* sp_start;
 };
+// Launch choices that change the speed of a pass but not what it computes
+// (only the order of some sums): waves per atom of the descriptor forward
+// and adjoint passes (1, 2 or 4) and waves per MLP tile (4 or 8; 0 = the
+// default).  Defaults come from plan_default(); nn_autotune stores measured
+// ones per shape class.
+struct LaunchPlan {
+  int wpa_fwd, wpa_adj, mlp_waves;
+};
+LaunchPlan plan_default(int64_t n_atoms);
 void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
-                     hipStream_t s);
+                     int wpa, hipStream_t s);
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
-                     hipStream_t s);
+                     int wpa, hipStream_t s);
 // FP64 sum of E_atom over structure c by one block of 256 threads (a fixed
 // tree, so the result is the same on every run).
 __device__ __forceinline__ void energy_block_sum(const float* __restrict__ E_atom, const int64_t* __restrict__ atom_ptr,
@@ -198,7 +207,8 @@ struct ConvJob {
 void launch_species_group(const int32_t* species, int64_t N, int S, int64_t* cnt, int64_t* off, int64_t* scan_tmp,
                           int32_t* perm, int64_t* sp_start, hipStream_t s);
 bool mlp_supported(int h1, int h2);
-void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s);  // mode 0 FP32, 1 BF16, 2 split BF16
+// mode 0 FP32, 1 BF16, 2 split BF16; waves per tile 4 or 8 (0: default)
+void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, int waves, hipStream_t s);
 void launch_convert_bf16(const ConvJob& job, hipStream_t s);
 // wgrad.hip
 struct WgradArgs {

@@ -645,7 +645,10 @@ __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* 
 
 // Waves per atom: two when the atoms alone would leave the SIMDs with few
 // waves to switch between, one otherwise.
-static int waves_per_atom(int64_t n_atoms) { return n_atoms <= 16384 ? 2 : 1; }
+LaunchPlan plan_default(int64_t n_atoms) {
+  const int w = n_atoms <= 16384 ? 2 : 1;
+  return LaunchPlan{w, w, 0};
+}
 
 template <int NT, int NRA, int WPA, int ZC>
 static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
@@ -656,13 +659,14 @@ static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescCon
 
 template <int NT, int NRA>
 static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
-                         hipStream_t s) {
-  const int wpa = waves_per_atom(sys.n_atoms);
+                         int wpa, hipStream_t s) {
   if (P.zeta == 50) {
-    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 50>(sys, nl, P, G, one, s);
+    if (wpa == 4) launch_fwd_w<NT, NRA, 4, 50>(sys, nl, P, G, one, s);
+    else if (wpa == 2) launch_fwd_w<NT, NRA, 2, 50>(sys, nl, P, G, one, s);
     else launch_fwd_w<NT, NRA, 1, 50>(sys, nl, P, G, one, s);
   } else {
-    if (wpa == 2) launch_fwd_w<NT, NRA, 2, 0>(sys, nl, P, G, one, s);
+    if (wpa == 4) launch_fwd_w<NT, NRA, 4, 0>(sys, nl, P, G, one, s);
+    else if (wpa == 2) launch_fwd_w<NT, NRA, 2, 0>(sys, nl, P, G, one, s);
     else launch_fwd_w<NT, NRA, 1, 0>(sys, nl, P, G, one, s);
   }
 }
@@ -677,22 +681,23 @@ static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescCon
 
 template <int NT, int NRA, bool ONE>
 static void launch_adj_o(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
-                         hipStream_t s) {
-  const int wpa = waves_per_atom(sys.n_atoms);
+                         int wpa, hipStream_t s) {
   if (P.zeta == 50) {
-    if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 50>(sys, nl, P, lam, pg, s);
+    if (wpa == 4) launch_adj_w<NT, NRA, ONE, 4, 50>(sys, nl, P, lam, pg, s);
+    else if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 50>(sys, nl, P, lam, pg, s);
     else launch_adj_w<NT, NRA, ONE, 1, 50>(sys, nl, P, lam, pg, s);
   } else {
-    if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 0>(sys, nl, P, lam, pg, s);
+    if (wpa == 4) launch_adj_w<NT, NRA, ONE, 4, 0>(sys, nl, P, lam, pg, s);
+    else if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 0>(sys, nl, P, lam, pg, s);
     else launch_adj_w<NT, NRA, ONE, 1, 0>(sys, nl, P, lam, pg, s);
   }
 }
 
 template <int NT, int NRA>
 static void launch_adj_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
-                         hipStream_t s) {
-  if (P.S == 1) launch_adj_o<NT, NRA, true>(sys, nl, P, lam, pg, s);
-  else launch_adj_o<NT, NRA, false>(sys, nl, P, lam, pg, s);
+                         int wpa, hipStream_t s) {
+  if (P.S == 1) launch_adj_o<NT, NRA, true>(sys, nl, P, lam, pg, wpa, s);
+  else launch_adj_o<NT, NRA, false>(sys, nl, P, lam, pg, wpa, s);
 }
 
 bool desc_supported(int nt, int nra) {
@@ -710,17 +715,17 @@ bool desc_supported(int nt, int nra) {
   } while (0)
 
 void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
-                     hipStream_t s) {
+                     int wpa, hipStream_t s) {
   if (sys.n_atoms == 0) return;
   const int nt = P.n_theta, nra = P.n_rs_ang;
-  NNP_DISPATCH(A, B, (launch_fwd_t<A, B>(sys, nl, P, G, one, s)));
+  NNP_DISPATCH(A, B, (launch_fwd_t<A, B>(sys, nl, P, G, one, wpa, s)));
 }
 
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
-                     hipStream_t s) {
+                     int wpa, hipStream_t s) {
   if (sys.n_atoms == 0) return;
   const int nt = P.n_theta, nra = P.n_rs_ang;
-  NNP_DISPATCH(A, B, (launch_adj_t<A, B>(sys, nl, P, lam, pg, s)));
+  NNP_DISPATCH(A, B, (launch_adj_t<A, B>(sys, nl, P, lam, pg, wpa, s)));
 }
 
 // F from the per-entry gradients; blocks past the gather's sum the

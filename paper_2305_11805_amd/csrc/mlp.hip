@@ -213,15 +213,9 @@ __device__ __forceinline__ void b_frag(const __bf16* p, const __bf16* p_lo, int 
 // output tiles n = w, w + NW, ... of every product, so act'(z) of its
 // layer-1 and layer-2 tiles stays in its registers; activations and deltas
 // are exchanged through two LDS buffers.
-// Waves per tile: one per 16 hidden units of layer 1, at most 8.
-template <int H1T>
-constexpr int mlp_waves() {
-  return H1T < 8 ? H1T : 8;
-}
-
-template <int H1T, int H2T, int MODE>
-__global__ void __launch_bounds__(64 * mlp_waves<H1T>()) k_mlp(MlpArgs args) {
-  constexpr int kWaves = mlp_waves<H1T>();
+template <int H1T, int H2T, int MODE, int NW>
+__global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
+  constexpr int kWaves = NW;
   constexpr int H1 = H1T * 16, H2 = H2T * 16;
   constexpr int HM = H1 > H2 ? H1 : H2;
   constexpr bool BF = MODE != kFp32;
@@ -562,20 +556,33 @@ bool mlp_supported(int h1, int h2) {
   return (h1 == 64 && h2 == 32) || (h1 == 128 && h2 == 128) || (h1 == 256 && h2 == 128);
 }
 
-template <int A, int B>
-static void launch_mlp_t(const MlpArgs& a, int mode, int64_t n_tiles, hipStream_t s) {
-  const dim3 g((unsigned)n_tiles), b(64 * mlp_waves<A>());
-  if (mode == kBf16x3) hipLaunchKernelGGL((k_mlp<A, B, kBf16x3>), g, b, 0, s, a);
-  else if (mode == kBf16) hipLaunchKernelGGL((k_mlp<A, B, kBf16>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_mlp<A, B, kFp32>), g, b, 0, s, a);
+template <int A, int B, int NW>
+static void launch_mlp_w(const MlpArgs& a, int mode, int64_t n_tiles, hipStream_t s) {
+  const dim3 g((unsigned)n_tiles), b(64 * NW);
+  if (mode == kBf16x3) hipLaunchKernelGGL((k_mlp<A, B, kBf16x3, NW>), g, b, 0, s, a);
+  else if (mode == kBf16) hipLaunchKernelGGL((k_mlp<A, B, kBf16, NW>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_mlp<A, B, kFp32, NW>), g, b, 0, s, a);
 }
 
-void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s) {
+// waves per tile: 4, or 8 when layer 1 has at least 8 tiles of 16 units
+// (the default)
+template <int A, int B>
+static void launch_mlp_t(const MlpArgs& a, int mode, int64_t n_tiles, int waves, hipStream_t s) {
+  if constexpr (A >= 8) {
+    if (waves != 4) {
+      launch_mlp_w<A, B, 8>(a, mode, n_tiles, s);
+      return;
+    }
+  }
+  launch_mlp_w<A, B, 4>(a, mode, n_tiles, s);
+}
+
+void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, int waves, hipStream_t s) {
   const int64_t n_tiles = (N + kTile - 1) / kTile + a.model.S;
   if (N == 0) return;
-  if (h1 == 64 && h2 == 32) launch_mlp_t<4, 2>(a, mode, n_tiles, s);
-  else if (h1 == 128 && h2 == 128) launch_mlp_t<8, 8>(a, mode, n_tiles, s);
-  else if (h1 == 256 && h2 == 128) launch_mlp_t<16, 8>(a, mode, n_tiles, s);
+  if (h1 == 64 && h2 == 32) launch_mlp_t<4, 2>(a, mode, n_tiles, waves, s);
+  else if (h1 == 128 && h2 == 128) launch_mlp_t<8, 8>(a, mode, n_tiles, waves, s);
+  else if (h1 == 256 && h2 == 128) launch_mlp_t<16, 8>(a, mode, n_tiles, waves, s);
 }
 
 void launch_convert_bf16(const ConvJob& job, hipStream_t s) {

@@ -64,7 +64,8 @@ class nn_model(C.Structure):
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_check", "nn_last_error", "nn_timing", "nn_timing_read",
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
           "jac_contract")
@@ -92,6 +93,10 @@ def lib():
         L.nn_energy_forces.argtypes = [P, P, P, P, I32, SZ, P, P, P, P, SZ, P]
         L.nn_energy_forces_grad.restype = I32
         L.nn_energy_forces_grad.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, SZ, P]
+        L.nn_autotune.restype = I32
+        L.nn_autotune.argtypes = [P, P, P, P, I32, P, SZ, P, P]
+        L.nn_autotune_reset.restype = None
+        L.nn_autotune_reset.argtypes = []
         L.nn_check.restype = I32
         L.nn_check.argtypes = [P, P, C.POINTER(I64)]
         L.nn_last_error.restype = C.c_char_p
@@ -172,6 +177,19 @@ def nn_energy_forces_grad(sys, nl, params, model, flags, dL_dE, F, dL_dpos, dW, 
     _ok(lib().nn_energy_forces_grad(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, _p(dL_dE),
                                     _p(F), _p(dL_dpos), _ptr_table(dW), _ptr_table(db), _p(ws), ws.numel(),
                                     _stream(stream)))
+
+
+def nn_autotune(sys, nl, params, model, flags, ws, stream=None) -> tuple:
+    """Times the launch variants and stores the fastest plan for this shape
+    class; returns (waves/atom forward, waves/atom adjoint, waves/MLP tile)."""
+    plan = (C.c_int32 * 3)()
+    _ok(lib().nn_autotune(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, _p(ws), ws.numel(),
+                          _stream(stream), plan))
+    return tuple(int(v) for v in plan)
+
+
+def nn_autotune_reset():
+    lib().nn_autotune_reset()
 
 
 def nn_check(nl: nn_nlist, stream=None) -> int:
@@ -310,6 +328,11 @@ class Potential:
             self.G = self.torch.zeros((self.N, self.D), dtype=self.torch.float32, device=self.dev)
         nn_descriptors(self.sys, self.nl, self.params, self.G, None, self.ws)
         return self.G
+
+    def autotune(self, flags: Optional[int] = None):
+        """nn_autotune on the current list (build it first)."""
+        f = self.flags if flags is None else flags
+        return nn_autotune(self.sys, self.nl, self.params, self.dmodel.struct, f, self.ws)
 
     def energy_forces(self, flags: Optional[int] = None, forces: bool = True, mem_budget: Optional[int] = None):
         f = self.flags if flags is None else flags

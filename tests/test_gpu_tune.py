@@ -1,0 +1,43 @@
+"""Launch tuning: nn_autotune picks waves per atom / per MLP tile by timing;
+the tuned plan must keep every result within the oracle tolerances, be
+bitwise reproducible, and nn_autotune_reset must bring back the default
+plan's results bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11805_amd import nnpot, synth
+
+from helpers import E_TOL, F_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,flags", [("cfg1", 0), ("cfg3s", 0), ("cfg3s", nnpot.NN_BF16X3_MLP),
+                                        ("cfg2s", 0)])
+def test_autotuned_plan_matches_oracle(name, flags):
+    import torch
+    w = {"cfg1": lambda: synth.config(1), "cfg3s": lambda: synth.config(3, scale=0.1),
+         "cfg2s": lambda: synth.config(2, scale=0.05)}[name]()
+    s, p = w.system, w.params
+    print(f"[tune] {name} flags {flags}: {w.name}", flush=True)
+    nnpot.nn_autotune_reset()
+    pot = nnpot.Potential(s, p, w.model, flags=flags)
+    pot.build_neighbors()
+    Es0, _, F0 = (t.clone() for t in pot.energy_forces())
+    plan = pot.autotune()
+    print(f"  plan {plan}", flush=True)
+    assert plan[0] in (1, 2, 4) and plan[1] in (1, 2, 4) and plan[2] in (4, 8)
+    Es, _, F = (t.clone() for t in pot.energy_forces())
+    Es2, _, F2 = pot.energy_forces()
+    assert torch.equal(Es, Es2) and torch.equal(F, F2)
+    nl = oracle.neighbors_cells(s, p.rc)
+    Es_ref, _, F_ref = oracle.energy_forces(p, w.model, s, nl)
+    n_c = np.diff(s.atom_ptr)
+    e_err = float(np.max(np.abs(Es.cpu().numpy() - Es_ref) / np.maximum(n_c, 1)))
+    f_err = float(np.max(np.abs(F.cpu().numpy() - F_ref)))
+    print(f"  E/atom {e_err:.2e}  F {f_err:.2e}", flush=True)
+    assert e_err <= E_TOL and f_err <= F_TOL
+    nnpot.nn_autotune_reset()
+    Es3, _, F3 = pot.energy_forces()
+    assert torch.equal(Es3, Es0) and torch.equal(F3, F0)
