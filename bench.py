@@ -268,6 +268,10 @@ def suite_config(idx, modes, steps, out):
             torch.cuda.synchronize()
             nnpot.nn_check(pot.nl)
             r["launch_plan"] = pot.autotune()
+            pot.meta[1] = 0  # the walk starts from a fresh list
+            build()
+            ef()
+            torch.cuda.synchronize()
             F0 = pot.F.cpu().numpy()
             b0 = int(pot.meta[2].item())
             k = [0]
@@ -282,6 +286,35 @@ def suite_config(idx, modes, steps, out):
             r["md_walk"] = {"steps": nsteps, "ms_per_step": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1),
                             "rebuilds": int(pot.meta[2].item()) - b0,
                             "what": "x += N(0, 0.02 A) per component, skin 0.5 A, rebuild when an atom moved > skin/2"}
+            F_eager = pot.F.clone()
+            # the same walk with each step replayed from a captured graph
+            # (skin test, predicated rebuild, E, F); the displacement of the
+            # step is copied into the graph's input buffer before each replay
+            pot.pos.copy_(pos0)
+            pot.meta[1] = 0
+            build()
+            ef()
+            xi_buf = torch.zeros_like(pot.pos)
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                pot.pos.add_(xi_buf)
+                build()
+                ef()
+            torch.cuda.synchronize()
+            kg = [0]
+
+            def md_graph_step():
+                xi_buf.copy_(xi[kg[0]])
+                kg[0] += 1
+                g.replay()
+            ms = _timed(torch, stream, md_graph_step, nsteps) / nsteps
+            nnpot.nn_check(pot.nl)
+            r["md_walk_graph"] = {"steps": nsteps, "ms_per_step": round(ms, 4),
+                                  "atoms_per_s": round(s.n_atoms / ms * 1e3, 1),
+                                  "forces_equal_eager_bitwise": bool(torch.equal(pot.F, F_eager))}
+            del g
             ms = _timed(torch, stream, ef, 20) / 20
             r["standing_list"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
             F_end = pot.F.cpu().numpy()
@@ -306,6 +339,16 @@ def suite_config(idx, modes, steps, out):
             grad_step()
             ms = _timed(torch, stream, grad_step, steps) / steps
             res["loss_gradient_step"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                grad_step()
+            torch.cuda.synchronize()
+            g.replay()
+            ms = _timed(torch, stream, g.replay, steps) / steps
+            res["loss_gradient_step_graph"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            del g
             # the same structures, one Potential and one launch sequence each
             sub = 64
             pots = [nnpot.Potential(synth.single(s.pos[s.atom_ptr[c]:s.atom_ptr[c + 1]],
@@ -457,6 +500,18 @@ def main():
         torch.cuda.synchronize()
         nnpot.nn_check(pot.nl)
         assert np.array_equal(pot.F.cpu().numpy(), F), "graph replay differs from the eager step"
+        # the same step through torch.autograd.Function: E forward, dE/dpos
+        # (= -F, from the adjoint) by backward
+        from paper_2305_11805_amd import autograd
+        pos_t = pot.pos.clone().requires_grad_(True)
+
+        def ag_step():
+            E = autograd.energy(pot, pos_t, flags)
+            torch.autograd.grad(E.sum(), pos_t)
+        for _ in range(2):
+            ag_step()
+        ms = timed(ag_step, args.steps) / args.steps
+        variants["autograd_function"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1)}
 
     if args.calib_copy_mib > 0:
         a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
