@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
 PEAK_FP32_PACKED_TFLOPS = 157.3  # the same with two-wide packed FP32 FMA
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 METRIC = "energy+force atoms/sec at stated force error vs FP64 oracle; HBM GB/s"
 
 
@@ -53,6 +55,13 @@ def flop_model(p, n_valid):
             "per_triplet": {"desc_fwd": fwd_trip, "desc_adj": adj_trip}}
 
 
+def mlp_flops(w, n_atoms):
+    """Algorithmic flops of one MLP launch (forward and backward to dE/dG):
+    per atom 2 (D h1 + h1 h2 + h2) forward and 2 (h2 h1 + h1 D) backward."""
+    D, h1, h2 = w.model[0][0][:3]
+    return float(n_atoms) * (2 * (D * h1 + h1 * h2 + h2) + 2 * (h2 * h1 + h1 * D))
+
+
 def valid_neighbor_counts(pot, rc):
     nl = pot.neighbor_list_host()
     pos = pot.pos.cpu().numpy()
@@ -66,9 +75,15 @@ def valid_neighbor_counts(pot, rc):
     return np.bincount(rows[valid], minlength=len(off) - 1)
 
 
-def source_hash():
+SOURCES = {"k_desc": "descriptors.hip", "k_mlp": "mlp.hip", "k_nb": "neighbors.hip"}
+
+
+def source_hash(kernel="k_desc_adj"):
+    """Hash of the source file a kernel is built from (counter figures are
+    used only while it matches)."""
+    src = next(v for k, v in SOURCES.items() if kernel.startswith(k))
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2305_11805_amd", "csrc", "descriptors.hip"), "rb") as f:
+    with open(os.path.join(ROOT, "paper_2305_11805_amd", "csrc", src), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -127,7 +142,12 @@ def read_pmc_csv(path, counter):
     return out
 
 
-def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernel="k_desc_adj"):
+def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernels=("k_desc_adj", "k_desc_fwd", "k_mlp")):
+    for k in kernels:
+        ingest_kernel(fetch_csv, write_csv, calib_mib, workload, k)
+
+
+def ingest_kernel(fetch_csv, write_csv, calib_mib, workload, kernel):
     """HBM bytes per launch of `kernel` from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the ratio of
     the known size of a plain device copy to what the counter read for it."""
@@ -154,7 +174,7 @@ def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernel="k_desc_ad
     if os.path.exists(prof):
         with open(prof) as f:
             cnt = json.load(f)
-    cnt[f"{kernel}:{workload}"] = {"source_hash": source_hash(), "hbm_bytes_per_launch": round(hbm),
+    cnt[f"{kernel}:{workload}"] = {"source_hash": source_hash(kernel), "hbm_bytes_per_launch": round(hbm),
                                   "counters": res}
     with open(prof, "w") as f:
         json.dump(cnt, f, indent=1, sort_keys=True)
@@ -538,14 +558,46 @@ def main():
     else:
         roof = {"kernel": dom, "bound": "mfma", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "avg_launch_ms": round(dom_ms, 5)}
+    cnt = {}
     prof = os.path.join(ROOT, "profiles", "counters.json")
     if os.path.exists(prof):
         with open(prof) as f:
             cnt = json.load(f)
-        key = f"{roof['kernel']}:{w.name}"
-        if key in cnt and cnt[key].get("source_hash") == source_hash():
-            roof["traffic"] = cnt[key]["hbm_bytes_per_launch"]
-            roof["traffic_gbs"] = round(roof["traffic"] / (dom_ms / 1e3) / 1e9, 1)
+
+    def hbm_bytes(kernel):
+        e = cnt.get(f"{kernel}:{w.name}")
+        return e["hbm_bytes_per_launch"] if e and e.get("source_hash") == source_hash(kernel) else None
+
+    t = hbm_bytes(roof["kernel"])
+    if t is not None:
+        roof["traffic"] = t
+        roof["traffic_gbs"] = round(t / (dom_ms / 1e3) / 1e9, 1)
+    # every hot kernel against its own roof: the descriptor passes against
+    # FP32 VALU and HBM, the MLP against the MFMA peak of its operand type
+    kern = {}
+    for stage, name in (("desc_fwd", "k_desc_fwd"), ("desc_adj", "k_desc_adj")):
+        if stages[stage][1]:
+            ms_k = stages[stage][0] / stages[stage][1]
+            e = {"avg_launch_ms": round(ms_k, 5), "tflops": round(fm[stage] / (ms_k / 1e3) / 1e12, 3),
+                 "frac_fp32_valu": round(fm[stage] / (ms_k / 1e3) / 1e12 / PEAK_FP32_VALU_TFLOPS, 4)}
+            b = hbm_bytes(name)
+            if b is not None:
+                e["hbm_bytes_per_launch"] = b
+                e["hbm_gbs"] = round(b / (ms_k / 1e3) / 1e9, 1)
+                e["frac_hbm"] = round(b / (ms_k / 1e3) / 1e9 / PEAK_HBM_GBS, 4)
+            kern[name] = e
+    if stages["mlp"][1]:
+        ms_k = stages["mlp"][0] / stages["mlp"][1]
+        fl = mlp_flops(w, s.n_atoms)
+        peak = {"fp32": PEAK_FP32_MFMA_TFLOPS, "bf16": PEAK_BF16_MFMA_TFLOPS, "bf16x3": PEAK_BF16_MFMA_TFLOPS}[args.mode]
+        e = {"avg_launch_ms": round(ms_k, 5), "algorithmic_flops_per_launch": fl,
+             "tflops": round(fl / (ms_k / 1e3) / 1e12, 3), "peak_mfma_tflops": peak,
+             "frac_mfma": round(fl / (ms_k / 1e3) / 1e12 / peak, 4)}
+        b = hbm_bytes("k_mlp")
+        if b is not None:
+            e["hbm_bytes_per_launch"] = b
+            e["hbm_gbs"] = round(b / (ms_k / 1e3) / 1e9, 1)
+        kern["k_mlp"] = e
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -560,7 +612,7 @@ def main():
         "roofline": roof,
         "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
         "ms_per_step_with_stage_events": round(staged_ms / args.steps, 4),
-        "pairs_per_step": fm["pairs"], "triplets_per_step": fm["triplets"],
+        "pairs_per_step": fm["pairs"], "triplets_per_step": fm["triplets"], "kernels": kern,
         "variants": variants,
     }
     if not args.no_cpu_baseline:

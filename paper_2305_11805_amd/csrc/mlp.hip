@@ -463,6 +463,7 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
         a_frag_lds<MODE>(bufA, LD, lm, kb, ah, al);
 #pragma unroll
         for (int n = 0; n < CH; ++n) {
+          if (c0 + n * kWaves >= DT) continue;  // no column tile here (the same for the whole wave)
           const int col = (c0 + n * kWaves) * 16 + lm;
           const int64_t off = (int64_t)(col < D ? col : 0) * H1 + kb;
           b_frag<MODE>(M.WbT[0] + off, M.WlT[0] + off, col < D ? 8 : 0, bh, bl);
@@ -477,6 +478,7 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
         const float* w = W1 + (int64_t)(kb + 4 * lk) * D;
 #pragma unroll
         for (int n = 0; n < CH; ++n) {
+          if (c0 + n * kWaves >= DT) continue;  // no column tile here (the same for the whole wave)
           const int col = (c0 + n * kWaves) * 16 + lm;
           float4 b = {0.f, 0.f, 0.f, 0.f};
           if (col < D) {
