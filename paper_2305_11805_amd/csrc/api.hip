@@ -184,7 +184,7 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
   L.bin_m = c.take<int4>(N);
   L.bin_x = c.take<double4>(N);
   L.kslot = row_key_slot(N, capacity);
-  L.row_keys = c.take<uint64_t>((size_t)N * L.kslot + (L.kslot > 0 ? (size_t)capacity : 0));
+  L.row_keys = c.take<uint64_t>((size_t)N * L.kslot + (L.kslot > 0 ? 2 * (size_t)capacity : 0));
   L.key_loc = c.take<int64_t>(N);
   L.cursor = c.take<int64_t>(1);
   L.atom_bin = c.take<int32_t>(4 * N);
@@ -613,9 +613,9 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     // mean time of three launches after one untimed one; -1 on an error
     auto time_of = [&](auto&& launch) -> float {
       launch();
-      hipEventRecord(e0, s);
+      if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
       for (int r = 0; r < 3; ++r) launch();
-      hipEventRecord(e1, s);
+      if (hipEventRecord(e1, s) != hipSuccess) return -1.f;
       float ms = -1.f;
       if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
       return ms / 3.f;
@@ -646,9 +646,9 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
       const float t = time_of([&] { launch_desc_adj(*sys, *nl, P, L.lam, L.pg, w, s); });
       if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_adj = w;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    const bool destroyed = hipEventDestroy(e0) == hipSuccess && hipEventDestroy(e1) == hipSuccess;
     if ((st = check_launch("nn_autotune"))) return st;
+    if (!destroyed) return fail(NN_E_HIP, "nn_autotune: event release failed");
     std::lock_guard<std::mutex> g(g_pmu);
     g_plans[plan_key(N, nl->capacity, P, model, mode)] = best;
   }

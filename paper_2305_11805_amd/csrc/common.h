@@ -116,7 +116,7 @@ struct NbLaunch {
   int32_t* bin_rank;  // [N] rank of each atom inside its bin
   int4* bin_m;       // [N] per binned slot: atom j and its whole-cell offsets
   double4* bin_x;    // [N] per binned slot: the position of j (copied bit for bit)
-  uint64_t* row_keys; // N slabs of kslot keys, then an overflow area of `capacity` keys
+  uint64_t* row_keys; // N slabs of kslot keys, then an overflow area of 2 * capacity keys
   int64_t* key_loc;   // [N] start of each row's sorted keys in row_keys
   int64_t* cursor;    // overflow area use
   int kslot;

@@ -455,7 +455,8 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry
 constexpr int kGrpWaves = 4;
 constexpr int kGrpThreads = 64 * kGrpWaves;
 constexpr int kGrpSplit = 4;  // blocks sharing one group (blockIdx.y), each with every kGrpSplit-th set of atoms
-constexpr int kCandMax = 1024;  // binned groups with more candidates read them from HBM
+constexpr int kCandMax = 768;   // binned groups with more candidates read them from HBM
+constexpr int kKeyLds = 256;    // row keys kept in LDS; longer rows take a second pass through HBM
 
 // Orders this wave's LDS writes before its later LDS reads of other lanes'
 // data (and keeps the compiler from moving accesses across).
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
   __shared__ double cx[kCandMax], cy[kCandMax], cz[kCandMax];
   __shared__ int32_t cj[kCandMax];
   __shared__ int32_t cw[3][kCandMax];  // image of a binned candidate minus the centre atom's cell offset
-  __shared__ uint64_t keyw[KEYS ? kGrpWaves : 1][KEYS ? kRowMax : 1];
+  __shared__ uint64_t keyw[KEYS ? kGrpWaves : 1][KEYS ? kKeyLds : 1];
   __shared__ int64_t b_start[27];
   __shared__ int32_t b_pre[28];
   __shared__ int32_t b_wr[27][3];
@@ -600,67 +601,72 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
       const int32_t i = mi4.x;
       const double xi[3] = {xi4.x, xi4.y, xi4.z};
       const int mi[3] = {mi4.y, mi4.z, mi4.w};
-      int count = 0;
+      // one pass over the candidates; sink(slot, key) receives each entry's
+      // key with slot = its position in candidate order
       bool shift_bad = false;
-      for (int64_t t0 = 0; t0 < total; t0 += kWave) {
-        const int64_t t = t0 + lane;
-        const bool active = t < total;
-        int32_t j = 0;
-        double xj[3] = {0.0, 0.0, 0.0};
-        int n[3] = {0, 0, 0};
-        if (active) {
-          if (small) {
-            const int jj = (int)(t / nimg);
-            int im = (int)(t - (int64_t)jj * nimg);
-            n[2] = im % w2 - K2;
-            im /= w2;
-            n[1] = im % w1 - K1;
-            n[0] = im / w1 - K0;
-            j = cj[jj];
-            xj[0] = cx[jj];
-            xj[1] = cy[jj];
-            xj[2] = cz[jj];
-          } else if (staged) {
-            j = cj[t];
-            xj[0] = cx[t];
-            xj[1] = cy[t];
-            xj[2] = cz[t];
-            for (int d = 0; d < 3; ++d) n[d] = p3[d] ? cw[d][t] + mi[d] : 0;
-          } else {
-            int lo = 0, hi = 26;
-            while (lo < hi) {
-              const int mid = (lo + hi + 1) >> 1;
-              if (b_pre[mid] <= t) lo = mid;
-              else hi = mid - 1;
+      auto scan = [&](auto&& sink) -> int {
+        int count = 0;
+        for (int64_t t0 = 0; t0 < total; t0 += kWave) {
+          const int64_t t = t0 + lane;
+          const bool active = t < total;
+          int32_t j = 0;
+          double xj[3] = {0.0, 0.0, 0.0};
+          int n[3] = {0, 0, 0};
+          if (active) {
+            if (small) {
+              const int jj = (int)(t / nimg);
+              int im = (int)(t - (int64_t)jj * nimg);
+              n[2] = im % w2 - K2;
+              im /= w2;
+              n[1] = im % w1 - K1;
+              n[0] = im / w1 - K0;
+              j = cj[jj];
+              xj[0] = cx[jj];
+              xj[1] = cy[jj];
+              xj[2] = cz[jj];
+            } else if (staged) {
+              j = cj[t];
+              xj[0] = cx[t];
+              xj[1] = cy[t];
+              xj[2] = cz[t];
+              for (int d = 0; d < 3; ++d) n[d] = p3[d] ? cw[d][t] + mi[d] : 0;
+            } else {
+              int lo = 0, hi = 26;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (b_pre[mid] <= t) lo = mid;
+                else hi = mid - 1;
+              }
+              const int64_t k = b_start[lo] + (t - b_pre[lo]);
+              const int4 m4 = bin_m[k];
+              const double4 x4 = bin_x[k];
+              j = m4.x;
+              xj[0] = x4.x;
+              xj[1] = x4.y;
+              xj[2] = x4.z;
+              const int mj[3] = {m4.y, m4.z, m4.w};
+              for (int d = 0; d < 3; ++d) n[d] = p3[d] ? b_wr[lo][d] - mj[d] + mi[d] : 0;
             }
-            const int64_t k = b_start[lo] + (t - b_pre[lo]);
-            const int4 m4 = bin_m[k];
-            const double4 x4 = bin_x[k];
-            j = m4.x;
-            xj[0] = x4.x;
-            xj[1] = x4.y;
-            xj[2] = x4.z;
-            const int mj[3] = {m4.y, m4.z, m4.w};
-            for (int d = 0; d < 3; ++d) n[d] = p3[d] ? b_wr[lo][d] - mj[d] + mi[d] : 0;
           }
-        }
-        bool acc = false;
-        if (active && !(j == i && n[0] == 0 && n[1] == 0 && n[2] == 0)) {
-          double d[3];
-          displacement64(xi, xj, h, n[0], n[1], n[2], d);
-          acc = norm2_64(d) < r2max;
-          if (acc && (n[0] < -127 || n[0] > 127 || n[1] < -127 || n[1] > 127 || n[2] < -127 || n[2] > 127)) {
-            shift_bad = true;
-            acc = false;
+          bool acc = false;
+          if (active && !(j == i && n[0] == 0 && n[1] == 0 && n[2] == 0)) {
+            double d[3];
+            displacement64(xi, xj, h, n[0], n[1], n[2], d);
+            acc = norm2_64(d) < r2max;
+            if (acc && (n[0] < -127 || n[0] > 127 || n[1] < -127 || n[1] > 127 || n[2] < -127 || n[2] > 127)) {
+              shift_bad = true;
+              acc = false;
+            }
           }
+          const uint64_t m = __ballot(acc);
+          if (acc) sink(count + __popcll(m & lt), entry_key(j, n[0], n[1], n[2]));
+          count += __popcll(m);
         }
-        const uint64_t m = __ballot(acc);
-        if (KEYS && acc) {
-          const int slot = count + __popcll(m & lt);
-          if (slot < kRowMax) keyw[wv][slot] = entry_key(j, n[0], n[1], n[2]);
-        }
-        count += __popcll(m);
-      }
+        return count;
+      };
+      const int count = scan([&](int slot, uint64_t k) {
+        if (KEYS && slot < kKeyLds) keyw[wv][slot] = k;
+      });
       if (lane == 0) {
         row_count[i] = count;
         if (count > kRowMax) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
@@ -668,26 +674,41 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
       if (__any(shift_bad) && lane == 0)
         atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
       if (KEYS && count <= kRowMax) {
-        // where the row's keys go: its slab, or the overflow area after the
-        // N slabs (a range past the area's end means the list cannot hold
-        // the entries either; the capacity check then stops the build)
-        int64_t base = i * (int64_t)kslot;
-        if (count > kslot) {
+        // where the row's keys go: its slab, or a range of the overflow area
+        // after the N slabs, reserved with one atomic (a range past the
+        // area's end means the list cannot hold the entries either; the
+        // capacity check then stops the build).  A row longer than the LDS
+        // buffer also reserves room for its unsorted keys and is scanned a
+        // second time to write them there.
+        const bool in_lds = count <= kKeyLds;
+        int64_t base = i * (int64_t)kslot, raw = -1;
+        if (count > kslot || !in_lds) {
+          const int64_t need = in_lds ? count : 2 * (int64_t)count;
           int64_t off = 0;
-          if (lane == 0) off = (int64_t)atomicAdd((unsigned long long*)cursor, (unsigned long long)count);
+          if (lane == 0) off = (int64_t)atomicAdd((unsigned long long*)cursor, (unsigned long long)need);
           off = __shfl(off, 0);
-          base = off + count <= over_len ? n_atoms * (int64_t)kslot + off : -1;
+          base = off + need <= over_len ? n_atoms * (int64_t)kslot + off : -1;
+          if (!in_lds && base >= 0) raw = base + count;
         }
         if (lane == 0) key_loc[i] = base;
         if (base >= 0) {
-          wave_lds_sync();
-          uint64_t* dst = row_keys + base;
           const uint64_t* kw = keyw[wv];
+          if (!in_lds) {
+            uint64_t* rk = row_keys + raw;
+            scan([&](int slot, uint64_t k) { rk[slot] = k; });
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            kw = rk;
+          } else {
+            wave_lds_sync();
+          }
+          uint64_t* dst = row_keys + base;
           for (int t = lane; t < count; t += kWave) {
             const uint64_t k = kw[t];
             int rank = 0;
             int u = 0;
-            for (; u + 8 <= count; u += 8) {  // eight independent LDS reads in flight
+            for (; u + 8 <= count; u += 8) {  // eight independent reads in flight
               uint64_t v[8];
 #pragma unroll
               for (int q = 0; q < 8; ++q) v[q] = kw[u + q];
@@ -865,7 +886,7 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
     else
       hipLaunchKernelGGL(k_nb_rows<kRowsKeys>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N, L.row_keys,
-                         L.kslot, L.capacity, L.key_loc, L.cursor, L.meta, L.flag);
+                         L.kslot, 2 * L.capacity, L.key_loc, L.cursor, L.meta, L.flag);
   }
   const CapacityJob cj{count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag};
   if (N <= kScanSmall) {

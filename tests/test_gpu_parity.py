@@ -160,7 +160,7 @@ def test_force_sum_vanishes_periodic():
 def dense_blob_system():
     """A periodic box of dilute atoms around a dense blob: the blob's rows are
     several times the mean row length, longer than the per-atom key slab the
-    counting pass keeps, so the build takes its full-fill fallback."""
+    counting pass keeps, so their keys go to the overflow area."""
     rng = np.random.Generator(np.random.PCG64(91))
     L = 30.0
     g = (np.arange(11) + 0.5) * (L / 11)
@@ -176,7 +176,7 @@ def dense_blob_system():
     return synth.single(pos, sp, cell=np.eye(3) * L, pbc=(1, 1, 1))
 
 
-def test_neighbor_list_long_rows_fallback():
+def test_neighbor_list_long_rows_overflow_area():
     s = dense_blob_system()
     p = synth.mbp_params(2, 4.0, 8, 4, 4)
     ref = oracle.neighbors_cells(s, p.rc)
@@ -220,3 +220,35 @@ def test_decreasing_atom_ptr_is_reported(skin):
     again = pot.neighbor_list_host()
     assert np.array_equal(again["offsets"], good["offsets"])
     assert np.array_equal(again["nbr"], good["nbr"])
+
+
+def test_neighbor_list_rows_longer_than_lds_buffer():
+    """Rows of 300-400 entries (a dense blob, radius 4.5 A): longer than the
+    counting pass keeps in LDS, so their keys take the second pass through
+    HBM; the list must still equal the oracle's."""
+    rng = np.random.Generator(np.random.PCG64(93))
+    L = 30.0
+    g = (np.arange(10) + 0.5) * (L / 10)
+    dil = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3) + rng.uniform(-0.3, 0.3, (1000, 3))
+    c = np.full(3, L / 2)
+    dil = dil[np.linalg.norm(dil - c, axis=1) > 6.2]
+    b = np.arange(-5, 6) * 1.0
+    blob = np.stack(np.meshgrid(b, b, b, indexing="ij"), -1).reshape(-1, 3)
+    blob = blob[np.linalg.norm(blob, axis=1) <= 5.0] + c + rng.uniform(-0.05, 0.05, (1, 3))
+    pos = np.concatenate([dil, blob])
+    s = synth.single(pos, rng.integers(0, 2, len(pos)), cell=np.eye(3) * L, pbc=(1, 1, 1))
+    p = synth.mbp_params(2, 4.5, 8, 4, 4)
+    ref = oracle.neighbors_cells(s, p.rc)
+    rows = np.diff(ref["offsets"])
+    print(f"[neighbors] blob: {s.n_atoms} atoms, rows mean {rows.mean():.1f} max {rows.max()}", flush=True)
+    assert rows.max() > 300
+    pot = nnpot.Potential(s, p, None)
+    pot.build_neighbors()
+    got = pot.neighbor_list_host()
+    assert np.array_equal(got["offsets"], ref["offsets"])
+    ok, msg = list_rows_equal(got, ref)
+    assert ok, msg
+    off = got["offsets"]
+    row_of = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    assert np.array_equal(got["nbr"][got["rev"]], row_of)
+    assert np.array_equal(got["shift"][got["rev"]], -got["shift"])
