@@ -35,6 +35,7 @@ namespace nnp {
 struct AtomNb {
   float4 d[kMaxNb];   // unit vector d/r (x, y, z), r (hi)
   float4 f[kMaxNb];   // fc, dfc/dr, r (lo), (entry index << 4 | species) as bits
+  float ir[kMaxNb];   // 1/r
   int seg[NN_MAX_SPECIES + 1];
   int n;
   int bad;
@@ -152,6 +153,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       const float dfc = (float)(-0.5 * P.pi_over_rc64) * sinf((float)(P.pi_over_rc64 * u));
       nb.d[slot] = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
       nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
+      nb.ir[slot] = (float)ir;
     }
   }
   __syncthreads();
@@ -239,6 +241,9 @@ struct TripGeom {
   float c, ssm, rbar, rbar_lo;
 };
 
+// EXACT_SQRT: the correctly rounded square root (descriptor values); the
+// gradient passes take the hardware's 1-ulp one.
+template <bool EXACT_SQRT = true>
 __device__ __forceinline__ TripGeom triplet_geom(const float4& u, const float4& fu, const float4& v, const float4& fv,
                                                  float eps) {
   TripGeom t;
@@ -246,7 +251,8 @@ __device__ __forceinline__ TripGeom triplet_geom(const float4& u, const float4& 
   const float cx = fmaf(u.y, v.z, -u.z * v.y);
   const float cy = fmaf(u.z, v.x, -u.x * v.z);
   const float cz = fmaf(u.x, v.y, -u.y * v.x);
-  t.ssm = sqrtf(fmaf(cx, cx, fmaf(cy, cy, fmaf(cz, cz, eps))));
+  const float s2 = fmaf(cx, cx, fmaf(cy, cy, fmaf(cz, cz, eps)));
+  t.ssm = EXACT_SQRT ? sqrtf(s2) : __builtin_amdgcn_sqrtf(s2);
   const float s = u.w + v.w;  // TwoSum: s + err == u.w + v.w exactly
   const float bb = s - u.w;
   const float err = (u.w - (s - bb)) + (v.w - bb);
@@ -496,8 +502,8 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
       const float4 v = nb.d[k], fv = nb.f[k];
       const float* La = lam_a;
       if (!ONE_SPECIES) La = lam_a + pair_block(S, nb_species(fu), nb_species(fv)) * NBP;
-      const float iru = frcp(u.w), irv = frcp(v.w);
-      const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+      const float iru = nb.ir[j], irv = nb.ir[k];
+      const TripGeom g = triplet_geom<false>(u, fu, v, fv, P.eps_ang);
       const float c = g.c;
       const float F2 = 2.0f * fu.x * fv.x;
       float x[NT], P1[NT], A[NT];

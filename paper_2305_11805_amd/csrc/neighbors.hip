@@ -270,7 +270,6 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
   const int c = blockIdx.x;
   if (c >= B) return;
   __shared__ double h[9], inv[9];
-  __shared__ double lo[3][64], hi[3][64];
   if (threadIdx.x < 9) h[threadIdx.x] = cell[9 * (int64_t)c + threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) inverse3(h, inv);
@@ -289,17 +288,14 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
       }
     }
   }
-  for (int d = 0; d < 3; ++d) {
-    lo[d][threadIdx.x] = l[d];
-    hi[d][threadIdx.x] = u[d];
+  if (small) {  // range of the fractional coordinates (wave reduction)
+    for (int d = 0; d < 3; ++d)
+      for (int off = 32; off > 0; off >>= 1) {
+        l[d] = fmin(l[d], __shfl_xor(l[d], off));
+        u[d] = fmax(u[d], __shfl_xor(u[d], off));
+      }
   }
-  __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int t = 1; t < 64; ++t)
-    for (int d = 0; d < 3; ++d) {
-      l[d] = fmin(l[d], lo[d][t]);
-      u[d] = fmax(u[d], hi[d][t]);
-    }
   double w[3];
   perp_widths(h, w);
   StructGeom g;
@@ -795,19 +791,27 @@ __device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t wa
 // reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
 // whose position is found among row j's sorted keys.  Also records the
 // positions of this build (skin reference) and marks the list valid.  One
-// wave per atom.
+// wave per atom; with the bin order, block b takes the atom at slot
+// (b mod 8) * per + b / 8, so each XCD walks a contiguous stretch of space
+// and the neighbor rows it searches stay in its L2.
 __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys,
                                                 const int64_t* __restrict__ key_loc,
                                                 const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
                                                 int8_t* __restrict__ shift, int32_t* __restrict__ rev,
                                                 const double* __restrict__ pos, double* __restrict__ ref_pos,
-                                                int64_t* meta, const int32_t* flag) {
+                                                const int32_t* __restrict__ order, int64_t* meta, const int32_t* flag) {
   if (!flag[1]) return;
-  const int64_t i = blockIdx.x;
+  int64_t i = blockIdx.x;
+  if (order) {
+    const int64_t per = (gridDim.x + 7) / 8;
+    const int64_t slot = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (slot >= N) return;
+    i = order[slot];
+  }
   if (i >= N) return;
   const int lane = threadIdx.x;
   if (ref_pos && lane < 3) ref_pos[3 * i + lane] = pos[3 * i + lane];
-  if (i == 0 && lane == 0) {
+  if (blockIdx.x == 0 && lane == 0) {
     meta[kMetaValid] = 1;
     meta[kMetaBuilds] += 1;
   }
@@ -898,8 +902,9 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   }
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  hipLaunchKernelGGL(k_nb_emit, dim3((unsigned)N), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
-                     nl->shift, nl->rev, sys->pos, nl->ref_pos, L.meta, L.flag);
+  const unsigned gEmit = nl->order ? (unsigned)((N + 7) / 8 * 8) : (unsigned)N;  // whole rounds of the 8 XCDs
+  hipLaunchKernelGGL(k_nb_emit, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+                     nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
 }
 
 }  // namespace nnp
