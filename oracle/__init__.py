@@ -87,6 +87,10 @@ def lib():
         L.nnref_energy_forces.argtypes = [P, P, P, P, P, P, P]
         L.nnref_energy_loss_grad.restype = C.c_double
         L.nnref_energy_loss_grad.argtypes = [P, P, P, P, P, P, P, C.c_int64]
+        L.nnref_descriptor_tangent.restype = None
+        L.nnref_descriptor_tangent.argtypes = [P, P, P, P, P]
+        L.nnref_force_loss_grad.restype = None
+        L.nnref_force_loss_grad.argtypes = [P, P, P, P, P, P, P, C.c_int64]
         L.nnref_num_threads.restype = C.c_int
         L.nnref_num_threads.argtypes = []
         _lib = L
@@ -254,6 +258,32 @@ def energy_loss_grad(params, model, sys, nl, targets):
     L = lib().nnref_energy_loss_grad(C.byref(cp), C.byref(cm), C.byref(cs), C.byref(cn), _ptr(T), _ptr(Es),
                                      _ptr(dp), n_params)
     return L, Es, dp
+
+
+def descriptor_tangent(params, sys, nl, v):
+    """u[rows][D]: derivative of each row atom's descriptor along the
+    displacement field v [N][3] (sum over atoms k of dG_i/dx_k . v_k)."""
+    keep = _Keep()
+    cp, cs, cn = _c_params(params, keep), _c_system(sys, keep), _c_nlist(nl, keep)
+    V = keep(np.asarray(v, np.float64).reshape(-1, 3), np.float64)
+    D = descriptor_dim(params.n_species, params.n_rad, params.n_theta, params.n_rs_ang)
+    u = np.zeros((cn.n_rows, D))
+    lib().nnref_descriptor_tangent(C.byref(cp), C.byref(cs), C.byref(cn), _ptr(V), _ptr(u))
+    return u
+
+
+def force_loss_grad(params, model, sys, nl, gE=None, gF=None):
+    """Flat dL/dparams for upstream gradients gE [B] = dL/dE_c and gF [N][3] =
+    dL/dF_k (either may be None)."""
+    keep = _Keep()
+    cp, cs, cn = _c_params(params, keep), _c_system(sys, keep), _c_nlist(nl, keep)
+    cm, n_params = _c_model(model, keep)
+    E = None if gE is None else keep(np.asarray(gE, np.float64), np.float64)
+    Fv = None if gF is None else keep(np.asarray(gF, np.float64).reshape(-1, 3), np.float64)
+    dp = np.zeros(n_params)
+    lib().nnref_force_loss_grad(C.byref(cp), C.byref(cm), C.byref(cs), C.byref(cn), _ptr(E), _ptr(Fv), _ptr(dp),
+                                n_params)
+    return dp
 
 
 def unflatten_grads(model, flat):

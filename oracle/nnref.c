@@ -14,8 +14,9 @@
  *   - radial and angular mBP descriptors as direct sums over neighbors and
  *     unordered neighbor pairs, with analytic derivatives;
  *   - the dense per-species MLP of Eq. (1) and its backward pass;
- *   - forces F = -dE/dx by the chain rule, and the weight gradient of an
- *     energy loss.
+ *   - forces F = -dE/dx by the chain rule, and the weight gradient of a
+ *     loss on energies and forces (the force part by forward mode through
+ *     the MLP along the descriptor tangent, then reverse mode).
  *
  * Sources (PANNA 2.0 paper):
  *   - total energy as a sum of atomic terms, weights shared per species:
@@ -26,7 +27,8 @@
  *     radius and the angle, split by species: Sec. III.A, Sec. III.B;
  *   - MLP layer equation: Sec. II.A, Eq. (1); Gaussian / ReLU / tanh /
  *     linear activations: Sec. II.A;
- *   - loss on energies per configuration: Sec. II.A.
+ *   - loss on energies per configuration, and on forces with a relative
+ *     weight: Sec. II.A, Sec. III.A.
  * The paper does not print the mBP formulas (it defers to the first PANNA
  * paper).  The functional form used here is the reading stated in the
  * design notes: ANI-style radial Gaussians times a cosine cutoff, and an
@@ -638,6 +640,14 @@ static double act_deriv(int code, double z) {
     }
 }
 
+static double act_deriv2(int code, double z) {
+    switch (code) {
+    case ACT_GAUSSIAN: return (4.0 * z * z - 2.0) * exp(-z * z);
+    case ACT_TANH: { double t = tanh(z); return -2.0 * t * (1.0 - t * t); }
+    default: return 0.0; /* linear; ReLU away from 0 */
+    }
+}
+
 /* Atomic energy E = a^L (a scalar) of species s for input g:
  *   a^0 = g,  z^l = W^l a^(l-1) + b^l,  a^l = sigma_l(z^l).
  * If lambda != NULL, writes dE/dg.  If dparams != NULL, adds
@@ -710,6 +720,153 @@ void nnref_mlp(const ref_model *M, int64_t n, const int32_t *species, const doub
 #pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < n; ++r)
         E[r] = mlp_atom(M, species[r], G + r * D, lambda ? lambda + r * D : NULL, NULL, 0.0);
+}
+
+/* For species s, input g and a direction u in descriptor space: the
+ * derivative of the atomic energy along u, Et = dE/dg . u, evaluated in
+ * forward mode (tangents zt^l = W^l at^(l-1), at^l = sigma'(z^l) zt^l,
+ * at^0 = u, Et = at^L), and scale * dEt/dtheta added into dparams by
+ * reverse mode through that forward computation:
+ *   zbar^l  = abar^l sigma'(z^l) + atbar^l sigma''(z^l) zt^l   (via a^l)
+ *   ztbar^l = atbar^l sigma'(z^l)                              (via at^l)
+ *   dW^l += zbar^l a^(l-1)T + ztbar^l at^(l-1)T,  db^l += zbar^l,
+ *   abar^(l-1) = W^lT zbar^l,  atbar^(l-1) = W^lT ztbar^l,
+ * starting from abar^L = 0, atbar^L = 1.  Returns Et.                      */
+static double mlp_atom_tangent_grad(const ref_model *M, int s, const double *g, const double *u,
+                                    double *dparams, double scale) {
+    const int L = M->n_layers[s];
+    const int32_t *w = M->arch + (int64_t)s * (REF_MAX_LAYERS + 1);
+    const int32_t *act = M->act + (int64_t)s * REF_MAX_LAYERS;
+    const double *par = M->params + M->poff[s];
+    double *a[REF_MAX_LAYERS + 1], *at[REF_MAX_LAYERS + 1], *z[REF_MAX_LAYERS + 1], *zt[REF_MAX_LAYERS + 1];
+    const double *Wl[REF_MAX_LAYERS + 1], *bl[REF_MAX_LAYERS + 1];
+    int64_t woff[REF_MAX_LAYERS + 1], boff[REF_MAX_LAYERS + 1];
+    int64_t pos = 0;
+    for (int l = 1; l <= L; ++l) {
+        woff[l] = pos;
+        Wl[l] = par + pos;
+        pos += (int64_t)w[l] * w[l - 1];
+        boff[l] = pos;
+        bl[l] = par + pos;
+        pos += w[l];
+    }
+    a[0] = (double *)g;
+    at[0] = (double *)u;
+    for (int l = 1; l <= L; ++l) {
+        z[l] = malloc(sizeof(double) * (size_t)w[l]);
+        zt[l] = malloc(sizeof(double) * (size_t)w[l]);
+        a[l] = malloc(sizeof(double) * (size_t)w[l]);
+        at[l] = malloc(sizeof(double) * (size_t)w[l]);
+        for (int o = 0; o < w[l]; ++o) {
+            double acc = bl[l][o], acct = 0.0;
+            for (int k = 0; k < w[l - 1]; ++k) {
+                acc += Wl[l][(int64_t)o * w[l - 1] + k] * a[l - 1][k];
+                acct += Wl[l][(int64_t)o * w[l - 1] + k] * at[l - 1][k];
+            }
+            z[l][o] = acc;
+            zt[l][o] = acct;
+            a[l][o] = act_fn(act[l - 1], acc);
+            at[l][o] = act_deriv(act[l - 1], acc) * acct;
+        }
+    }
+    const double Et = at[L][0];
+    double *abar = calloc((size_t)w[L], sizeof(double));
+    double *atbar = calloc((size_t)w[L], sizeof(double));
+    atbar[0] = 1.0;
+    for (int l = L; l >= 1; --l) {
+        double *zbar = malloc(sizeof(double) * (size_t)w[l]);
+        double *ztbar = malloc(sizeof(double) * (size_t)w[l]);
+        for (int o = 0; o < w[l]; ++o) {
+            zbar[o] = abar[o] * act_deriv(act[l - 1], z[l][o]) + atbar[o] * act_deriv2(act[l - 1], z[l][o]) * zt[l][o];
+            ztbar[o] = atbar[o] * act_deriv(act[l - 1], z[l][o]);
+        }
+        for (int o = 0; o < w[l]; ++o) {
+            for (int k = 0; k < w[l - 1]; ++k)
+                dparams[M->poff[s] + woff[l] + (int64_t)o * w[l - 1] + k] +=
+                    scale * (zbar[o] * a[l - 1][k] + ztbar[o] * at[l - 1][k]);
+            dparams[M->poff[s] + boff[l] + o] += scale * zbar[o];
+        }
+        double *pa = calloc((size_t)w[l - 1], sizeof(double));
+        double *pat = calloc((size_t)w[l - 1], sizeof(double));
+        for (int k = 0; k < w[l - 1]; ++k)
+            for (int o = 0; o < w[l]; ++o) {
+                pa[k] += Wl[l][(int64_t)o * w[l - 1] + k] * zbar[o];
+                pat[k] += Wl[l][(int64_t)o * w[l - 1] + k] * ztbar[o];
+            }
+        free(zbar);
+        free(ztbar);
+        free(abar);
+        free(atbar);
+        abar = pa;
+        atbar = pat;
+    }
+    free(abar);
+    free(atbar);
+    for (int l = 1; l <= L; ++l) {
+        free(z[l]);
+        free(zt[l]);
+        free(a[l]);
+        free(at[l]);
+    }
+    return Et;
+}
+
+/* The descriptor tangent of every row atom i along a displacement field v
+ * (one 3-vector per atom): u_i = sum_k dG_i/dx_k . v_k
+ *                              = sum_{e in row i} dG_i/dd_e . (v_j(e) - v_i). */
+void nnref_descriptor_tangent(const ref_params *P, const ref_system *sys, const ref_nlist *nl, const double *v,
+                              double *u) {
+    const int64_t D = nnref_descriptor_dim(P->n_species, P->n_rad, P->n_theta, P->n_rs_ang);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t r = 0; r < nl->n_rows; ++r) {
+        int64_t i = nl->rows ? nl->rows[r] : r;
+        double (*d)[3];
+        int32_t *sp;
+        int64_t n_e = row_geometry(sys, nl, r, &d, &sp);
+        double *G = malloc(sizeof(double) * (size_t)D);
+        double *jac = malloc(sizeof(double) * (size_t)(D * n_e * 3 + 1));
+        atom_descriptor(P, n_e, (const double(*)[3])d, sp, G, jac);
+        for (int64_t dd = 0; dd < D; ++dd) {
+            double acc = 0.0;
+            for (int64_t e = 0; e < n_e; ++e) {
+                int64_t j = nl->nbr[nl->offsets[r] + e];
+                for (int k = 0; k < 3; ++k) acc += jac[(dd * n_e + e) * 3 + k] * (v[3 * j + k] - v[3 * i + k]);
+            }
+            u[r * D + dd] = acc;
+        }
+        free(jac);
+        free(G);
+        free(d);
+        free(sp);
+    }
+}
+
+/* Gradient of a loss on energies and forces with respect to every MLP
+ * parameter, given the upstream gradients gE[c] = dL/dE_c (NULL: none) and
+ * gF[k][3] = dL/dF_k (NULL: none):
+ *   dL/dtheta = sum_c gE_c sum_{i in c} dE_i/dtheta
+ *             + sum_k gF_k . dF_k/dtheta,
+ * and, with F_k = -sum_i dE_i/dx_k = -sum_i lambda_i . dG_i/dx_k,
+ *   sum_k gF_k . dF_k/dtheta = -sum_i d/dtheta [lambda_i . u_i],
+ * u_i the descriptor tangent along gF (theta-independent).  Needs a list
+ * holding every atom's row.  Writes dparams (overwritten).                 */
+void nnref_force_loss_grad(const ref_params *P, const ref_model *M, const ref_system *sys,
+                           const ref_nlist *nl, const double *gE, const double *gF, double *dparams,
+                           int64_t n_params) {
+    const int64_t D = nnref_descriptor_dim(P->n_species, P->n_rad, P->n_theta, P->n_rs_ang);
+    int64_t N = sys->n_atoms;
+    double *G = malloc(sizeof(double) * (size_t)(N * D + 1));
+    double *u = gF ? malloc(sizeof(double) * (size_t)(N * D + 1)) : NULL;
+    nnref_descriptors(P, sys, nl, G, NULL);
+    if (gF) nnref_descriptor_tangent(P, sys, nl, gF, u);
+    memset(dparams, 0, sizeof(double) * (size_t)n_params);
+    for (int c = 0; c < sys->n_structs; ++c)
+        for (int64_t a = sys->atom_ptr[c]; a < sys->atom_ptr[c + 1]; ++a) {
+            if (gE) (void)mlp_atom(M, sys->species[a], G + a * D, NULL, dparams, gE[c]);
+            if (gF) (void)mlp_atom_tangent_grad(M, sys->species[a], G + a * D, u + a * D, dparams, -1.0);
+        }
+    free(u);
+    free(G);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -436,3 +436,91 @@ def test_energy_loss_weight_gradient_fd(O):
         fd = (loss_with(h) - loss_with(-h)) / (2 * h)
         g = O.unflatten_grads(model, flat)[s][l][0][idx]
         assert abs(fd - g) < 1e-6 * max(1.0, abs(g))
+
+
+# ----------------------------------------------------------------------------
+# loss on forces: the descriptor tangent and the weight gradient
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["clusters", "periodic"])
+def test_descriptor_tangent_central_differences(O, kind):
+    """u_i = sum_k dG_i/dx_k . v_k against (G(x + h v) - G(x - h v)) / 2h."""
+    rng = np.random.Generator(np.random.PCG64(21))
+    p = small_params(S=2, rc=3.6)
+    if kind == "clusters":
+        sys = synth.concat([random_cluster(rng, n) for n in (7, 5)])
+    else:
+        sys = small_periodic(rng, n=9)
+    v = rng.normal(size=(sys.n_atoms, 3))
+    u = O.descriptor_tangent(p, sys, O.neighbors_brute(sys, p.rc), v)
+    h = 1e-5
+
+    def G_at(x):
+        s2 = synth.System(x, sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+        return O.descriptors(p, s2, O.neighbors_brute(s2, p.rc))
+    fd = (G_at(sys.pos + h * v) - G_at(sys.pos - h * v)) / (2 * h)
+    assert np.max(np.abs(fd - u)) < 1e-6 * max(1.0, np.max(np.abs(u)))
+
+
+def _loss_terms(O, p, model, sys, nl, gE, gF):
+    """sum_c gE_c E_c + sum_k gF_k . F_k from the oracle's energies and forces."""
+    Es, _, F = O.energy_forces(p, model, sys, nl)
+    return float(np.dot(gE, Es) + np.sum(gF * F))
+
+
+@pytest.mark.parametrize("act", ["gaussian", "tanh"])
+def test_force_loss_weight_gradient_fd(O, act):
+    """d/dtheta [sum_c gE_c E_c + sum_k gF_k . F_k] by central differences of
+    the oracle's own energies and forces, for weights and biases of every
+    layer (forces are pinned to energy differences separately)."""
+    rng = np.random.Generator(np.random.PCG64(22))
+    p = small_params(S=2, rc=3.8)
+    model = synth.random_model(2, p.dim, [6, 5], 7, act=act, in_scale=0.7)
+    sys = synth.concat([random_cluster(rng, n) for n in (6, 7)])
+    nl = O.neighbors_brute(sys, p.rc)
+    gE = rng.normal(size=sys.n_structs)
+    gF = rng.normal(size=(sys.n_atoms, 3))
+    flat = O.force_loss_grad(p, model, sys, nl, gE, gF)
+    grads = O.unflatten_grads(model, flat)
+    h = 1e-6
+    for (s, l, which, idx) in [(0, 0, 2, (1, 3)), (1, 0, 3, (2,)), (1, 1, 2, (2, 0)), (0, 1, 3, (4,)),
+                               (1, 2, 2, (0, 1)), (0, 2, 3, (0,))]:
+        def value(delta):
+            mm = [(m[0], m[1], [w.copy() for w in m[2]], [b.copy() for b in m[3]]) for m in model]
+            mm[s][which][l][idx] += delta
+            return _loss_terms(O, p, mm, sys, nl, gE, gF)
+        fd = (value(h) - value(-h)) / (2 * h)
+        g = grads[s][l][0 if which == 2 else 1][idx]
+        assert abs(fd - g) < 2e-6 * max(1.0, abs(g)), (s, l, which, idx, fd, g)
+
+
+def test_force_loss_weight_gradient_vs_torch_double_backward(O):
+    """The MLP part against torch float64: on the oracle's G and tangent u,
+    d/dtheta [sum_i gE_c(i) E_i - (dE_i/dG_i) . u_i] by double backward."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(23))
+    p = small_params(S=2, rc=3.8)
+    model = synth.random_model(2, p.dim, [7, 4], 9, in_scale=0.7)
+    sys = synth.concat([random_cluster(rng, n) for n in (5, 8, 6)])
+    nl = O.neighbors_brute(sys, p.rc)
+    gE = rng.normal(size=sys.n_structs)
+    gF = rng.normal(size=(sys.n_atoms, 3))
+    flat = O.force_loss_grad(p, model, sys, nl, gE, gF)
+    G = O.descriptors(p, sys, nl)
+    u = O.descriptor_tangent(p, sys, nl, gF)
+    struct = np.repeat(np.arange(sys.n_structs), np.diff(sys.atom_ptr))
+    tparams = [[(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True))
+                for W, b in zip(m[2], m[3])] for m in model]
+    total = torch.zeros((), dtype=torch.float64)
+    for s in range(2):
+        idx = np.nonzero(sys.species == s)[0]
+        g = torch.tensor(G[idx], requires_grad=True)
+        e = torch_mlp_energy(torch, tparams[s], model[s][1], g)
+        (lam,) = torch.autograd.grad(e.sum(), g, create_graph=True)
+        total = total + (torch.tensor(gE[struct[idx]]) * e).sum() - (lam * torch.tensor(u[idx])).sum()
+    total.backward()
+    grads = O.unflatten_grads(model, flat)
+    for s in range(2):
+        for (dW, db), (W, b) in zip(grads[s], tparams[s]):
+            np.testing.assert_allclose(dW, W.grad.numpy(), rtol=1e-10, atol=1e-13)
+            np.testing.assert_allclose(db, b.grad.numpy(), rtol=1e-10, atol=1e-13)
