@@ -179,6 +179,17 @@ int64_t nn_descriptor_dim(const nn_mbp_params* p);
 int64_t nn_jacobian_stride(const nn_mbp_params* p);
 
 /*
+ * Derivative of every atom's descriptors along a displacement field v
+ * [device] FP32 [N][3]:  U_i = sum_k (dG_i/dx_k) . v_k  [device] FP32 [N][D]
+ * (the forward-mode product behind the weight gradient of a loss on forces,
+ * Sec. II.A with forces as derivatives of the energy, Sec. II).  Computed in
+ * FP32 from the same neighbor staging as nn_descriptors; entries at r >= rc
+ * contribute nothing.  No workspace.  NN_E_INVALID for NULL buffers.
+ */
+nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const float* v,
+                                float* U, void* stream);
+
+/*
  * Workspace bytes needed by every call below for a system of n_atoms atoms
  * and n_structs structures, a list of `capacity` entries, these descriptor
  * and model parameters (model may be NULL for list/descriptor-only use) and
@@ -263,24 +274,37 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
 void nn_autotune_reset(void);
 
 /*
- * Backward of E_struct with respect to positions and weights, given
- * dL_dE [device] FP64 [B] (Sec. II.A: the loss is minimised over the MLP
- * parameters).  Must follow nn_energy_forces with the same arguments and
- * workspace (it reuses G and lambda).
+ * Backward of E_struct and F with respect to positions and weights, given
+ * the upstream gradients of a loss L (Sec. II.A: the loss is minimised over
+ * the MLP parameters; forces are derivatives of the energy, Sec. II, so a
+ * loss on forces reaches the weights through second derivatives).  Must
+ * follow nn_energy_forces with the same arguments and workspace (it reuses
+ * G and the list).
+ *   dL_dE   [device] FP64 [B] dL/dE_c (may be NULL if dL_dF is given: zero).
+ *   dL_dF   [device] FP32 [N][3] dL/dF_k (may be NULL: no force term).  With
+ *            it, sum_k dL_dF_k . F_k = -sum_i lambda_i . u_i, where u_i is
+ *            the derivative of G_i along the displacement field dL_dF; the
+ *            library computes u on the device (overwriting the workspace's
+ *            lambda), runs the MLP together with its tangent along u, and
+ *            adds the reverse pass of that tangent to the weight gradient.
+ *            This part runs in FP32 whatever the MLP flags.
  *   dL_dpos [device] FP32 [N][3] (may be NULL): dL/dx_k = -dL_dE[c(k)] F_k;
- *            needs the F of that call.
+ *            needs dL_dE and the F of that call.  Not provided together
+ *            with dL_dF (NN_E_UNSUPPORTED): that would need the Hessian.
  *   dW, db [host] arrays of NN_MAX_SPECIES*NN_MAX_LAYERS device pointers
  *            (either array may be NULL): dW[s*NN_MAX_LAYERS + l] receives
  *            dL/dW^(l+1) of species s as FP32 in the layout of W[l], db the
- *            same for b.  The MLP is re-run on the stored descriptors in the
- *            same precision mode (flags) to recover dE_i/dz^l; the sums over
- *            atoms use FP32 MFMA over fixed atom chunks reduced in chunk
- *            order (bitwise reproducible).
+ *            same for b.  Without dL_dF the MLP is re-run on the stored
+ *            descriptors in the same precision mode (flags) to recover
+ *            dE_i/dz^l; the sums over atoms use FP32 MFMA over fixed atom
+ *            chunks reduced in chunk order (bitwise reproducible).
+ * Errors: NN_E_INVALID for missing arguments, NN_E_WORKSPACE for a short
+ * workspace, NN_E_UNSUPPORTED as above; nothing is enqueued then.
  */
 nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
-                                const nn_model* model, int32_t flags, const double* dL_dE, const float* F,
-                                float* dL_dpos, float* const* dW, float* const* db, void* ws, size_t ws_bytes,
-                                void* stream);
+                                const nn_model* model, int32_t flags, const double* dL_dE, const float* dL_dF,
+                                const float* F, float* dL_dpos, float* const* dW, float* const* db, void* ws,
+                                size_t ws_bytes, void* stream);
 
 /*
  * Synchronize `stream` and report device-side errors recorded in the list's

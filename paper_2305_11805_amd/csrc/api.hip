@@ -155,6 +155,7 @@ struct Layout {
   size_t wb_elems;
   // weight gradient: per-atom stash, per-atom weights, chunk partials
   float *st_a1, *st_d1, *st_a2, *st_d2, *w_atom, *partial;
+  float *st_t1, *st_x1, *st_x2;  // the force term's extra stash (a1_dot, x1, x2)
   float* jac;  // stored Jacobian (NN_STORE_JACOBIAN within the memory budget)
   size_t bytes;
 };
@@ -211,6 +212,9 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
       L.st_d1 = c.take<float>((size_t)N * H1);
       L.st_a2 = c.take<float>((size_t)N * H2);
       L.st_d2 = c.take<float>((size_t)N * H2);
+      L.st_t1 = c.take<float>((size_t)N * H1);
+      L.st_x1 = c.take<float>((size_t)N * H1);
+      L.st_x2 = c.take<float>((size_t)N * H2);
       L.w_atom = c.take<float>(N);
       ModelDev md{};
       md.S = S;
@@ -506,6 +510,20 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   return check_launch("nn_descriptors");
 }
 
+nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const float* v,
+                                float* U, void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((!v || !U) && sys->n_atoms > 0) return fail(NN_E_INVALID, "v/U is NULL");
+  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
+  hipStream_t s = (hipStream_t)stream;
+  launch_desc_tan(*sys, *nl, P, v, U, plan_default(sys->n_atoms).wpa_fwd, s);
+  return check_launch("nn_descriptor_tangent");
+}
+
 nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
                            int32_t flags, size_t mem_budget, double* E_struct, float* E_atom, float* F, void* ws,
                            size_t ws_bytes, void* stream) {
@@ -666,9 +684,9 @@ void nn_autotune_reset(void) {
 }
 
 nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
-                                const nn_model* model, int32_t flags, const double* dL_dE, const float* F,
-                                float* dL_dpos, float* const* dW, float* const* db, void* ws, size_t ws_bytes,
-                                void* stream) {
+                                const nn_model* model, int32_t flags, const double* dL_dE, const float* dL_dF,
+                                const float* F, float* dL_dpos, float* const* dW, float* const* db, void* ws,
+                                size_t ws_bytes, void* stream) {
   nn_status st = check_system(sys);
   if (st) return st;
   if ((st = check_nlist(nl, sys, true))) return st;
@@ -676,7 +694,10 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   if ((st = make_desc_const(p, &P))) return st;
   if ((st = check_model(model, P))) return st;
   if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN)) return fail(NN_E_INVALID, "unknown flags");
-  if (!dL_dE && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE is NULL");
+  if (!dL_dE && !dL_dF && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE and dL_dF are both NULL");
+  if (dL_dpos && dL_dF)
+    return fail(NN_E_UNSUPPORTED, "the position gradient of a loss on forces (second derivatives) is not provided");
+  if (dL_dpos && !dL_dE) return fail(NN_E_INVALID, "dL_dpos needs dL_dE");
   if (dL_dpos && !F) return fail(NN_E_INVALID, "dL_dpos needs the forces F");
   const int64_t N = sys->n_atoms;
   // the stored Jacobian (if any) sits after every piece used here, so the
@@ -689,30 +710,63 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   if (dL_dpos) launch_pos_grad(dL_dE, sys->atom_ptr, sys->n_structs, N, F, dL_dpos, s);
   if (dW || db) {
     const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
+    const LaunchPlan plan = plan_for(N, nl->capacity, P, model, mode);
     launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
     MlpArgs a{};
-    prepare_model(model, P, L, mode != 0, a, s);
-    // re-run the MLP on the stored descriptors, keeping a1, a2, dE/dz1, dE/dz2
-    a.G = L.G;
-    a.perm = L.perm;
-    a.sp_start = L.sp_start;
-    a.E_atom = L.E_atom;
-    a.lambda = nullptr;
-    a.D = P.D;
-    a.st_a1 = L.st_a1;
-    a.st_d1 = L.st_d1;
-    a.st_a2 = L.st_a2;
-    a.st_d2 = L.st_d2;
-    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N,
-               plan_for(N, nl->capacity, P, model, mode).mlp_waves, s);
+    prepare_model(model, P, L, mode != 0 && !dL_dF, a, s);
     launch_atom_weights(dL_dE, sys->atom_ptr, sys->n_structs, N, L.w_atom, s);
+    WgradSrc src{};
+    src.G = L.G;
+    src.a1 = L.st_a1;
+    src.d1 = L.st_d1;
+    src.a2 = L.st_a2;
+    src.d2 = L.st_d2;
+    if (dL_dF) {
+      // descriptor tangent along dL/dF into the lambda buffer (not needed
+      // here), then the MLP with its tangent in FP32
+      launch_desc_tan(*sys, *nl, P, dL_dF, L.lam, plan.wpa_fwd, s);
+      MlpFmArgs f{};
+      f.model = a.model;
+      f.G = L.G;
+      f.U = L.lam;
+      f.perm = L.perm;
+      f.sp_start = L.sp_start;
+      f.w = L.w_atom;
+      f.E_atom = L.E_atom;
+      f.D = P.D;
+      f.a1 = L.st_a1;
+      f.t1 = L.st_t1;
+      f.d1 = L.st_d1;
+      f.x1 = L.st_x1;
+      f.d2 = L.st_d2;
+      f.x2 = L.st_x2;
+      f.c3 = L.st_a2;
+      launch_mlp_fm(f, model->mlp[0].width[1], model->mlp[0].width[2], N, plan.mlp_waves, s);
+      src.U = L.lam;
+      src.t1 = L.st_t1;
+      src.x1 = L.st_x1;
+      src.x2 = L.st_x2;
+    } else {
+      // re-run the MLP on the stored descriptors, keeping a1, a2, dE/dz1, dE/dz2
+      a.G = L.G;
+      a.perm = L.perm;
+      a.sp_start = L.sp_start;
+      a.E_atom = L.E_atom;
+      a.lambda = nullptr;
+      a.D = P.D;
+      a.st_a1 = L.st_a1;
+      a.st_d1 = L.st_d1;
+      a.st_a2 = L.st_a2;
+      a.st_d2 = L.st_d2;
+      launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
+    }
     WgradArgs g{};
     g.perm = L.perm;
     g.sp_start = L.sp_start;
     g.w = L.w_atom;
     g.partial = L.partial;
     g.S = P.S;
-    launch_wgrad(g, a.model, L.G, L.st_a1, L.st_d1, L.st_a2, L.st_d2, P.D, N, dW, db, s);
+    launch_wgrad(g, a.model, src, P.D, N, dW, db, s);
   }
   return check_launch("nn_energy_forces_grad");
 }

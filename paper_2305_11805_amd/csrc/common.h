@@ -153,6 +153,10 @@ void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& 
                      int wpa, hipStream_t s);
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                      int wpa, hipStream_t s);
+// U [N][D] = directional derivative of the descriptors along the
+// displacement field v [N][3] (FP32)
+void launch_desc_tan(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* v, float* U,
+                     int wpa, hipStream_t s);
 // FP64 sum of E_atom over structure c by one block of 256 threads (a fixed
 // tree, so the result is the same on every run).
 __device__ __forceinline__ void energy_block_sum(const float* __restrict__ E_atom, const int64_t* __restrict__ atom_ptr,
@@ -195,6 +199,21 @@ struct MlpArgs {
   // a1 / delta1 = dE/dz1 [N][H1], a2 / delta2 = dE/dz2 [N][H2]
   float *st_a1, *st_d1, *st_a2, *st_d2;
 };
+// The MLP and its tangent along the descriptor tangent U (FP32 MFMA), with
+// the per-atom terms of the weight gradient of sum_i (w_i E_i - E_dot_i).
+struct MlpFmArgs {
+  ModelDev model;
+  const float* G;           // [N][D]
+  const float* U;           // [N][D] descriptor tangent
+  const int32_t* perm;
+  const int64_t* sp_start;
+  const float* w;           // [N] dL/dE of each atom's structure
+  float* E_atom;            // [N]
+  int D;
+  // per-atom stash [N][H1]: a1, a1_dot (t1), delta1 (d1), x1 = w delta1 - eps1;
+  // [N][H2]: delta2 (d2), x2 = w delta2 - eps2, c3 = w a2 - a2_dot
+  float *a1, *t1, *d1, *x1, *d2, *x2, *c3;
+};
 struct ConvJob {
   int n;
   const float* src[NN_MAX_SPECIES * 2];
@@ -210,6 +229,7 @@ bool mlp_supported(int h1, int h2);
 // mode 0 FP32, 1 BF16, 2 split BF16; waves per tile 4 or 8 (0: default)
 void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, int waves, hipStream_t s);
 void launch_convert_bf16(const ConvJob& job, hipStream_t s);
+void launch_mlp_fm(const MlpFmArgs& a, int h1, int h2, int64_t N, int waves, hipStream_t s);
 // wgrad.hip
 struct WgradArgs {
   const int32_t* perm;      // atoms grouped by species
@@ -219,9 +239,15 @@ struct WgradArgs {
   int S;
 };
 size_t wgrad_partial_floats(int64_t N, int S, const ModelDev& m);
-void launch_wgrad(const WgradArgs& a, const ModelDev& m, const float* G, const float* a1, const float* d1,
-                  const float* a2, const float* d2, int D, int64_t N, float* const* dW, float* const* db,
-                  hipStream_t s);
+// Per-atom sources of the weight-gradient sums.  Energy term only: G, a1,
+// d1 = delta1, a2, d2 = delta2 (weighted by w inside).  With the force term
+// (x1 set): a2 holds c3, and x1, x2, U, t1 = a1_dot are used as well.
+struct WgradSrc {
+  const float *G, *a1, *d1, *a2, *d2;
+  const float *U, *t1, *x1, *x2;
+};
+void launch_wgrad(const WgradArgs& a, const ModelDev& m, const WgradSrc& src, int D, int64_t N, float* const* dW,
+                  float* const* db, hipStream_t s);
 void launch_atom_weights(const double* dL_dE, const int64_t* atom_ptr, int32_t B, int64_t N, float* w, hipStream_t s);
 void launch_pos_grad(const double* dL_dE, const int64_t* atom_ptr, int32_t B, int64_t N, const float* F,
                      float* dL_dpos, hipStream_t s);

@@ -418,6 +418,165 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   }
 }
 
+// Directional derivative of the descriptors along a displacement field v
+// [N][3] (the forward-mode product that the weight gradient of a loss on
+// forces needs, Sec. II.A with forces as derivatives of the energy):
+//   u_i = sum_k (dG_i/dx_k) v_k = sum over neighbors j of (dG_i/dd_ij) (v_j - v_i).
+// Same neighbor staging, work split and sums as k_desc_fwd, with each
+// radial or triplet term replaced by its derivative along the field:
+//   radial: d/de g(r) = g'(r) r_dot with r_dot = d^ . (v_j - v_i);
+//   angular: d/de [A_p R_q F2] = A_p_dot R_q F2 + A_p R_q (F2_dot + F2 R_q_dot / R_q),
+//   cos_dot = v^ . w_j + u^ . w_k - cos (r_dot_j / r_j + r_dot_k / r_k) with
+//   w = (v_j - v_i) / r, ssm_dot = -cos cos_dot / ssm.
+template <int NT, int NRA, int WPA, int ZC>
+__global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int64_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const int8_t* __restrict__ shift, DescConst P,
+                                                       const float* __restrict__ field, float* __restrict__ U,
+                                                       int64_t* meta) {
+  constexpr int NB = NT * NRA;
+  __shared__ AtomNb nb;
+  __shared__ float4 tw[kMaxNb];  // per neighbor: (v_j - v_i) / r, and r_dot
+  __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
+  const int64_t i = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  float* Ui = U + i * (int64_t)P.D;
+  if (meta[kMetaValid] != 1) {
+    for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
+    return;
+  }
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr);
+  if (nb.bad) {
+    for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
+    return;
+  }
+  {
+    const int64_t e0 = offsets[i];
+    const float vx = field[3 * i], vy = field[3 * i + 1], vz = field[3 * i + 2];
+    for (int t = tid; t < nb.n; t += 64 * WPA) {
+      const int64_t j = nbr[e0 + nb_entry(nb.f[t])];
+      const float dx = field[3 * j] - vx, dy = field[3 * j + 1] - vy, dz = field[3 * j + 2] - vz;
+      const float4 d = nb.d[t];
+      const float ir = nb.ir[t];
+      tw[t] = make_float4(dx * ir, dy * ir, dz * ir, fmaf(d.x, dx, fmaf(d.y, dy, d.z * dz)));
+    }
+  }
+  __syncthreads();
+  const int S = P.S;
+  const float eta_r2 = P.eta_rad * 1.4426950408889634f;
+  const float eta_a2 = P.eta_ang * 1.4426950408889634f;
+  for (int k0 = 0; k0 < P.n_rad; k0 += kWave) {
+    const int k = k0 + lane;
+    const float rs = k < P.n_rad ? P.rs_rad[k] : 0.f;
+    const float rs_lo = k < P.n_rad ? P.rs_rad_lo[k] : 0.f;
+    for (int s = 0; s < S; ++s) {
+      float acc = 0.f;
+      for (int t = nb.seg[s] + wv; t < nb.seg[s + 1]; t += WPA) {
+        const float4 f = nb.f[t];
+        const float dr = (nb.d[t].w - rs) + (f.z - rs_lo);
+        const float g = fexp2(-eta_r2 * dr * dr);
+        acc = fmaf(g * fmaf(-2.0f * P.eta_rad * dr, f.x, f.y), tw[t].w, acc);
+      }
+      if constexpr (WPA == 1) {
+        if (k < P.n_rad) Ui[s * P.n_rad + k] = acc;
+      } else {
+        if (k < P.n_rad) xch[wv * NN_MAX_SPECIES * kMaxRad + s * P.n_rad + k] = acc;
+      }
+    }
+    if constexpr (WPA > 1) {
+      __syncthreads();
+      for (int x = tid; x < S * P.n_rad; x += 64 * WPA) {
+        const int s = x / P.n_rad, kk = x - s * P.n_rad;
+        if (kk < k0 || kk >= k0 + kWave) continue;
+        float v = 0.f;
+        for (int w = 0; w < WPA; ++w) v += xch[w * NN_MAX_SPECIES * kMaxRad + x];
+        Ui[x] = v;
+      }
+      __syncthreads();
+    }
+  }
+  const int ang0 = P.n_rad * S;
+  const int zeta1 = P.zeta - 1;
+  const float zf = (float)P.zeta;
+  for (int a = 0; a < S; ++a) {
+    for (int b = a; b < S; ++b) {
+      const int na = nb.seg[a + 1] - nb.seg[a], nbb = nb.seg[b + 1] - nb.seg[b];
+      const int T = (a == b) ? na * (na - 1) / 2 : na * nbb;
+      float acc[NB];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) acc[t] = 0.f;
+      const int m = (a == b) ? na : nbb;
+      const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
+      for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
+        const int t = t0 + lane;
+        if (t < T) {
+          int q, r, j, k;
+          divmod_small(t, m, inv_m, q, r);
+          if (a == b) {
+            int kk = r + q + 1;
+            if (kk >= na) kk -= na;
+            j = nb.seg[a] + r;
+            k = nb.seg[a] + kk;
+          } else {
+            j = nb.seg[a] + q;
+            k = nb.seg[b] + r;
+          }
+          const float4 u = nb.d[j], v = nb.d[k];
+          const float4 fu = nb.f[j], fv = nb.f[k];
+          const float4 wj = tw[j], wk = tw[k];
+          const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+          const float cdot = fmaf(v.x, wj.x, fmaf(v.y, wj.y, v.z * wj.z)) + fmaf(u.x, wk.x, fmaf(u.y, wk.y, u.z * wk.z)) -
+                             g.c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
+          const float sdot = -g.c * cdot * frcp(g.ssm);
+          const float F2 = 2.0f * fu.x * fv.x;
+          const float F2dot = 2.0f * fmaf(fu.y * wj.w, fv.x, fu.x * fv.y * wk.w);
+          const float rbdot = 0.5f * (wj.w + wk.w);
+          float x[NT], P1[NT], A[NT], Ad[NT];
+#pragma unroll
+          for (int p = 0; p < NT; ++p) x[p] = fmaf(g.c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
+          ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
+#pragma unroll
+          for (int p = 0; p < NT; ++p) {
+            A[p] = P1[p] * x[p];
+            Ad[p] = zf * P1[p] * fmaf(P.x_a[p], cdot, P.x_b[p] * sdot);
+          }
+#pragma unroll
+          for (int q = 0; q < NRA; ++q) {
+            const float dq = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
+            const float R = fexp2(-eta_a2 * dq * dq);
+            const float RF = R * F2;
+            const float RT = R * fmaf(-2.0f * P.eta_ang * dq * rbdot, F2, F2dot);
+#pragma unroll
+            for (int p = 0; p < NT; ++p) acc[q * NT + p] = fmaf(Ad[p], RF, fmaf(A[p], RT, acc[q * NT + p]));
+          }
+        }
+      }
+      butterfly<NB>(acc);
+      constexpr int L = __builtin_ctz(NB);
+      constexpr int SS = L < 6 ? L : 6;
+      constexpr int PER = NB >> SS;
+      float* out = Ui + ang0 + pair_block(S, a, b) * NB;
+      if (lane < (1 << SS)) {
+        const int base = bitrev(lane, SS) << (L - SS);
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+          if constexpr (WPA == 1) out[base + r] = acc[r];
+          else xch[wv * NB + base + r] = acc[r];
+        }
+      }
+      if constexpr (WPA > 1) {
+        __syncthreads();
+        for (int x = tid; x < NB; x += 64 * WPA) {
+          float v = 0.f;
+          for (int w = 0; w < WPA; ++w) v += xch[w * NB + x];
+          out[x] = v;
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // Per-pair energy gradients dE_i/dd_e (float4 per entry, w unused) from
 // lambda_i = dE_i/dG_i.
 template <int NT, int NRA, bool ONE_SPECIES, int WPA, int ZC>
@@ -677,6 +836,27 @@ static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescCon
   }
 }
 
+template <int NT, int NRA, int WPA, int ZC>
+static void launch_tan_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* v, float* U,
+                         hipStream_t s) {
+  hipLaunchKernelGGL((k_desc_tan<NT, NRA, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), 0, s, sys,
+                     nl.offsets, nl.nbr, nl.shift, P, v, U, nl.meta);
+}
+
+template <int NT, int NRA>
+static void launch_tan_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* v, float* U,
+                         int wpa, hipStream_t s) {
+  if (P.zeta == 50) {
+    if (wpa == 4) launch_tan_w<NT, NRA, 4, 50>(sys, nl, P, v, U, s);
+    else if (wpa == 2) launch_tan_w<NT, NRA, 2, 50>(sys, nl, P, v, U, s);
+    else launch_tan_w<NT, NRA, 1, 50>(sys, nl, P, v, U, s);
+  } else {
+    if (wpa == 4) launch_tan_w<NT, NRA, 4, 0>(sys, nl, P, v, U, s);
+    else if (wpa == 2) launch_tan_w<NT, NRA, 2, 0>(sys, nl, P, v, U, s);
+    else launch_tan_w<NT, NRA, 1, 0>(sys, nl, P, v, U, s);
+  }
+}
+
 template <int NT, int NRA, bool ONE, int WPA, int ZC>
 static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                          hipStream_t s) {
@@ -732,6 +912,13 @@ void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& 
   if (sys.n_atoms == 0) return;
   const int nt = P.n_theta, nra = P.n_rs_ang;
   NNP_DISPATCH(A, B, (launch_adj_t<A, B>(sys, nl, P, lam, pg, wpa, s)));
+}
+
+void launch_desc_tan(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* v, float* U,
+                     int wpa, hipStream_t s) {
+  if (sys.n_atoms == 0) return;
+  const int nt = P.n_theta, nra = P.n_rs_ang;
+  NNP_DISPATCH(A, B, (launch_tan_t<A, B>(sys, nl, P, v, U, wpa, s)));
 }
 
 // F from the per-entry gradients; blocks past the gather's sum the

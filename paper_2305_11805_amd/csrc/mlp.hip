@@ -506,6 +506,250 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
 }
 
 // ---------------------------------------------------------------------------
+// MLP with its tangent, for the weight gradient of a loss on forces
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float act_d2(int code, float z, float a) {
+  switch (code) {
+    case NN_ACT_GAUSSIAN: return fmaf(4.0f * z, z, -2.0f) * a;
+    case NN_ACT_TANH: return -2.0f * a * (1.0f - a * a);
+    default: return 0.0f;
+  }
+}
+
+// With the per-atom weight w = dL/dE of the atom's structure and the
+// descriptor tangent u (the derivative of G along dL/dF), the loss is
+// L = sum_i (w_i E_i - E_dot_i) where E_dot = lambda . u is the forward-mode
+// derivative of the MLP along u.  One 16-atom tile per block of NW waves
+// (FP32 MFMA) computes
+//   z1 = W1 G + b1, z1_dot = W1 u, a1 = act(z1), a1_dot = act'(z1) z1_dot,
+//   z2 = W2 a1 + b2, z2_dot = W2 a1_dot, a2, a2_dot likewise, E = w3 . a2 + b3,
+// then the reverse pass of w E - E_dot:
+//   delta2 = w3 act'(z2),  eps2 = w3 act''(z2) z2_dot,
+//   delta1 = act'(z1) (W2^T delta2),
+//   eps1 = act''(z1) z1_dot (W2^T delta2) + act'(z1) (W2^T eps2),
+// and stashes per atom what the weight-gradient sums contract:
+//   x1 = w delta1 - eps1 (with G), delta1 (with -u), a1 and a1_dot,
+//   x2 = w delta2 - eps2 (with a1), delta2 (with -a1_dot),
+//   c3 = w a2 - a2_dot (the output-layer column).
+template <int H1T, int H2T, int NW>
+__global__ void __launch_bounds__(64 * NW) k_mlp_fm(MlpFmArgs args) {
+  constexpr int H1 = H1T * 16, H2 = H2T * 16;
+  constexpr int HM = H1 > H2 ? H1 : H2;
+  constexpr int LD = HM + 4;
+  constexpr int T1 = (H1T + NW - 1) / NW, T2 = (H2T + NW - 1) / NW;
+  __shared__ __align__(16) float buf[2][kTile * LD];
+  __shared__ float epart[NW][kTile];
+  __shared__ int32_t rows[kTile];
+  __shared__ float wrow[kTile];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int S = args.model.S;
+  int64_t t = blockIdx.x;
+  int s = 0;
+  int64_t ns = 0;
+  for (; s < S; ++s) {
+    ns = args.sp_start[s + 1] - args.sp_start[s];
+    const int64_t nt = (ns + kTile - 1) / kTile;
+    if (t < nt) break;
+    t -= nt;
+  }
+  if (s >= S) return;
+  const int64_t r0 = args.sp_start[s] + t * kTile;
+  const int nrows = (int)min<int64_t>(kTile, args.sp_start[s] + ns - r0);
+  if (tid < kTile) {
+    const int r = tid < nrows ? args.perm[r0 + tid] : -1;
+    rows[tid] = r;
+    wrow[tid] = r >= 0 ? args.w[r] : 0.f;
+  }
+  __syncthreads();
+  const MlpDev& M = args.model.m[s];
+  const int D = args.D;
+  const int lm = lane & 15, lk = lane >> 4;
+  const int arow = rows[lm];
+  const float* Grow = args.G + (int64_t)(arow < 0 ? 0 : arow) * D;
+  const float* Urow = args.U + (int64_t)(arow < 0 ? 0 : arow) * D;
+  const int act1 = M.act[0], act2 = M.act[1];
+  float* bufA = buf[0];
+  float* bufB = buf[1];
+  auto stash = [&](float* dst, int ld, int col, int j, float v) {
+    const int r = rows[4 * lk + j];
+    if (r >= 0) dst[(int64_t)r * ld + col] = v;
+  };
+
+  // ---- layer 1: z1 = G W1^T, z1_dot = u W1^T (shared B fragments) ----
+  floatx4 acc[T1], acct[T1];
+#pragma unroll
+  for (int u = 0; u < T1; ++u) acc[u] = acct[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const float* W1 = M.W[0];
+    const bool vec = ((((uintptr_t)W1) | ((uintptr_t)args.G) | ((uintptr_t)args.U)) & 15) == 0 && (D & 3) == 0;
+    for (int k0 = 0; k0 < D; k0 += 16) {
+      const int k = k0 + 4 * lk;
+      const float4 a = ld4(Grow, k, arow >= 0 ? D : 0, vec);
+      const float4 at = ld4(Urow, k, arow >= 0 ? D : 0, vec);
+#pragma unroll
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + NW * u;
+        if (n < H1T) {
+          const float4 b = ld4(W1 + (int64_t)(n * 16 + lm) * D, k, D, vec);
+          acc[u] = mma4_f32(acc[u], a, b);
+          acct[u] = mma4_f32(acct[u], at, b);
+        }
+      }
+    }
+  }
+  float p1[T1][4], q1[T1][4];  // act'(z1) and act''(z1) z1_dot in C layout
+#pragma unroll
+  for (int u = 0; u < T1; ++u) {
+    const int n = wv + NW * u;
+    if (n >= H1T) continue;
+    const int col = n * 16 + lm;
+    const float bias = M.b[0][col];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = acc[u][j] + bias, zt = acct[u][j];
+      const float a = act_f(act1, z);
+      const float d = act_d(act1, z, a);
+      p1[u][j] = d;
+      q1[u][j] = act_d2(act1, z, a) * zt;
+      bufA[(4 * lk + j) * LD + col] = a;
+      bufB[(4 * lk + j) * LD + col] = d * zt;
+      stash(args.a1, H1, col, j, a);
+      stash(args.t1, H1, col, j, d * zt);
+    }
+  }
+  __syncthreads();
+
+  // ---- layer 2: z2 = a1 W2^T, z2_dot = a1_dot W2^T ----
+  floatx4 acc2[T2], acc2t[T2];
+#pragma unroll
+  for (int u = 0; u < T2; ++u) acc2[u] = acc2t[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const float* W2 = M.W[1];
+    const bool vec = (((uintptr_t)W2) & 15) == 0;
+#pragma unroll
+    for (int kb = 0; kb < H1; kb += 16) {
+      const float4 a = *reinterpret_cast<const float4*>(bufA + lm * LD + kb + 4 * lk);
+      const float4 at = *reinterpret_cast<const float4*>(bufB + lm * LD + kb + 4 * lk);
+#pragma unroll
+      for (int u = 0; u < T2; ++u) {
+        const int n = wv + NW * u;
+        if (n < H2T) {
+          const float4 b = ld4(W2 + (int64_t)(n * 16 + lm) * H1, kb + 4 * lk, H1, vec);
+          acc2[u] = mma4_f32(acc2[u], a, b);
+          acc2t[u] = mma4_f32(acc2t[u], at, b);
+        }
+      }
+    }
+  }
+  __syncthreads();  // every wave is done reading a1 and a1_dot
+  const float* w3 = M.W[2];
+  float e[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < T2; ++u) {
+    const int n = wv + NW * u;
+    if (n >= H2T) continue;
+    const int col = n * 16 + lm;
+    const float bias = M.b[1][col];
+    const float w = w3[col];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float z = acc2[u][j] + bias, zt = acc2t[u][j];
+      const float a = act_f(act2, z);
+      const float d = act_d(act2, z, a);
+      const float wi = wrow[4 * lk + j];
+      e[j] = fmaf(a, w, e[j]);
+      const float dl2 = w * d;
+      const float ep2 = w * act_d2(act2, z, a) * zt;
+      bufA[(4 * lk + j) * LD + col] = dl2;
+      bufB[(4 * lk + j) * LD + col] = ep2;
+      stash(args.d2, H2, col, j, dl2);
+      stash(args.x2, H2, col, j, fmaf(wi, dl2, -ep2));
+      stash(args.c3, H2, col, j, fmaf(wi, a, -d * zt));
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    float v = e[j];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    e[j] = v;
+  }
+  if (lm == 0)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) epart[wv][4 * lk + j] = e[j];
+  __syncthreads();
+  if (tid < kTile) {
+    float v = 0.f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += epart[w][tid];
+    const int r = rows[tid];
+    if (r >= 0) args.E_atom[r] = v + M.b[2][0];
+  }
+
+  // ---- W2^T delta2 and W2^T eps2 (shared B fragments) ----
+#pragma unroll
+  for (int u = 0; u < T1; ++u) acc[u] = acct[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  {
+    const float* W2 = M.W[1];  // [H2][H1]: B[k][n] = W2[k][n]
+#pragma unroll
+    for (int kb = 0; kb < H2; kb += 16) {
+      const float4 a = *reinterpret_cast<const float4*>(bufA + lm * LD + kb + 4 * lk);
+      const float4 at = *reinterpret_cast<const float4*>(bufB + lm * LD + kb + 4 * lk);
+      const float* w = W2 + (int64_t)(kb + 4 * lk) * H1 + lm;
+#pragma unroll
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + NW * u;
+        if (n < H1T) {
+          float4 b;
+          b.x = w[n * 16];
+          b.y = w[H1 + n * 16];
+          b.z = w[2 * H1 + n * 16];
+          b.w = w[3 * H1 + n * 16];
+          acc[u] = mma4_f32(acc[u], a, b);
+          acct[u] = mma4_f32(acct[u], at, b);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < T1; ++u) {
+    const int n = wv + NW * u;
+    if (n >= H1T) continue;
+    const int col = n * 16 + lm;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float tv = acc[u][j];
+      const float dl1 = p1[u][j] * tv;
+      const float ep1 = fmaf(q1[u][j], tv, p1[u][j] * acct[u][j]);
+      stash(args.d1, H1, col, j, dl1);
+      stash(args.x1, H1, col, j, fmaf(wrow[4 * lk + j], dl1, -ep1));
+    }
+  }
+}
+
+template <int A, int B>
+static void launch_mlp_fm_t(const MlpFmArgs& a, int64_t n_tiles, int waves, hipStream_t s) {
+  if constexpr (A >= 8) {
+    if (waves != 4) {
+      hipLaunchKernelGGL((k_mlp_fm<A, B, 8>), dim3((unsigned)n_tiles), dim3(512), 0, s, a);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_mlp_fm<A, B, 4>), dim3((unsigned)n_tiles), dim3(256), 0, s, a);
+}
+
+void launch_mlp_fm(const MlpFmArgs& a, int h1, int h2, int64_t N, int waves, hipStream_t s) {
+  const int64_t n_tiles = (N + kTile - 1) / kTile + a.model.S;
+  if (N == 0) return;
+  if (h1 == 64 && h2 == 32) launch_mlp_fm_t<4, 2>(a, n_tiles, waves, s);
+  else if (h1 == 128 && h2 == 128) launch_mlp_fm_t<8, 8>(a, n_tiles, waves, s);
+  else if (h1 == 256 && h2 == 128) launch_mlp_fm_t<16, 8>(a, n_tiles, waves, s);
+}
+
+// ---------------------------------------------------------------------------
 // BF16 weight copies: hi = bf16(W), lo = bf16(W - hi), each also transposed;
 // one launch for all species and layers
 // ---------------------------------------------------------------------------

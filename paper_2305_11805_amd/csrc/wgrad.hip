@@ -5,6 +5,12 @@
 // With w_i = dL/dE of atom i's structure, delta_l,i = dE_i/dz^l and a^0 = G:
 //   dL/dW^l = sum_i w_i delta_l,i a_{l-1,i}^T,   dL/db^l = sum_i w_i delta_l,i,
 //   dL/dW^3 = sum_i w_i a_2,i,  dL/db^3 = sum_i w_i.
+// With a loss on forces as well (L = sum_i (w_i E_i - E_dot_i), E_dot the
+// derivative of the MLP along the descriptor tangent u), each hidden layer
+// gets a second product, with x_l = w delta_l - eps_l from the tangent pass:
+//   dL/dW^1 = sum_i x_1,i G_i^T - delta_1,i u_i^T,
+//   dL/dW^2 = sum_i x_2,i a_1,i^T - delta_2,i a1_dot_i^T,
+//   dL/db^l = sum_i x_l,i,  dL/dW^3 = sum_i (w_i a_2,i - a2_dot_i).
 // The atoms of each species are cut into chunks of kChunk in species order.
 // For each chunk, one wave computes one 16 x 64 tile of a weight gradient on
 // FP32 MFMA (the atoms are the contraction index), and a second kernel adds
@@ -64,6 +70,10 @@ __global__ void k_atom_weights(const double* __restrict__ dL_dE, const int64_t* 
                                int64_t N, float* __restrict__ w) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
+  if (!dL_dE) {
+    w[i] = 0.f;
+    return;
+  }
   int lo = 0, hi = B - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -92,12 +102,15 @@ __global__ void k_pos_grad(const double* __restrict__ dL_dE, const int64_t* __re
 // out[m][n] (chunk partial) = sum over the chunk's atoms k of w_k X_k[m] Y_k[n]
 // job 0: X = delta1 [N][H1], Y = G  [N][D]   -> dW1 [H1][D]
 // job 1: X = delta2 [N][H2], Y = a1 [N][H1]  -> dW2 [H2][H1]
-__global__ void __launch_bounds__(64) k_wgrad_mm(WgradArgs a, WgradLayout L, const float* __restrict__ G,
-                                                 const float* __restrict__ a1, const float* __restrict__ d1,
-                                                 const float* __restrict__ d2) {
+// With the force term (src.x1 set) the sum is X'_k[m] Y_k[n] - X_k[m] Y'_k[n]
+// instead, X' = x1 / x2 and Y' = u / a1_dot, with no weight w_k.
+__global__ void __launch_bounds__(64) k_wgrad_mm(WgradArgs a, WgradLayout L, WgradSrc src) {
   const int job = blockIdx.z;
-  const float* X = job == 0 ? d1 : d2;
-  const float* Y = job == 0 ? G : a1;
+  const bool fm = src.x1 != nullptr;
+  const float* X = job == 0 ? src.d1 : src.d2;
+  const float* Y = job == 0 ? src.G : src.a1;
+  const float* Xf = job == 0 ? src.x1 : src.x2;
+  const float* Yf = job == 0 ? src.U : src.t1;
   const int M = job == 0 ? L.H1 : L.H2;
   const int Nc = job == 0 ? L.D : L.H1;
   const int ldx = M, ldy = Nc;
@@ -116,12 +129,24 @@ __global__ void __launch_bounds__(64) k_wgrad_mm(WgradArgs a, WgradLayout L, con
     const int64_t kk = k0 + lk;
     const bool valid = kk < r1;
     const int64_t atom = valid ? a.perm[kk] : 0;
-    const float av = valid ? a.w[atom] * X[atom * ldx + m0 + lm] : 0.f;
+    if (fm) {
+      const float av = valid ? Xf[atom * ldx + m0 + lm] : 0.f;
+      const float avn = valid ? -X[atom * ldx + m0 + lm] : 0.f;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int col = n0 + 16 * t + lm;
-      const float bv = (valid && col < Nc) ? Y[atom * ldy + col] : 0.f;
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      for (int t = 0; t < 4; ++t) {
+        const int col = n0 + 16 * t + lm;
+        const bool in = valid && col < Nc;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, in ? Y[atom * ldy + col] : 0.f, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(avn, in ? Yf[atom * ldy + col] : 0.f, acc[t], 0, 0, 0);
+      }
+    } else {
+      const float av = valid ? a.w[atom] * X[atom * ldx + m0 + lm] : 0.f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = n0 + 16 * t + lm;
+        const float bv = (valid && col < Nc) ? Y[atom * ldy + col] : 0.f;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      }
     }
   }
   float* out = a.partial + (int64_t)blockIdx.x * L.per_chunk + (job == 0 ? L.off_w1 : L.off_w2);
@@ -135,31 +160,35 @@ __global__ void __launch_bounds__(64) k_wgrad_mm(WgradArgs a, WgradLayout L, con
 }
 
 // Bias columns and the output layer: sums over the chunk's atoms, one
-// thread per output element, atoms in order.
-__global__ void __launch_bounds__(256) k_wgrad_cols(WgradArgs a, WgradLayout L, const float* __restrict__ d1,
-                                                    const float* __restrict__ a2, const float* __restrict__ d2) {
+// thread per output element, atoms in order.  With the force term the
+// sources already hold the weighted values (x1, x2, c3 = w a2 - a2_dot).
+__global__ void __launch_bounds__(256) k_wgrad_cols(WgradArgs a, WgradLayout L, WgradSrc src) {
   int s;
   int64_t r0, r1;
   if (!chunk_range(a.sp_start, a.S, blockIdx.x, s, r0, r1)) return;
+  const bool fm = src.x1 != nullptr;
   float* out = a.partial + (int64_t)blockIdx.x * L.per_chunk;
   const int ncol = L.H1 + 2 * L.H2 + 1;
   for (int t = threadIdx.x; t < ncol; t += blockDim.x) {
-    const float* src;
+    const float* p;
     int ld, col;
     int64_t dst;
     if (t < L.H1) {
-      src = d1, ld = L.H1, col = t, dst = L.off_b1 + t;
+      p = fm ? src.x1 : src.d1, ld = L.H1, col = t, dst = L.off_b1 + t;
     } else if (t < L.H1 + L.H2) {
-      src = d2, ld = L.H2, col = t - L.H1, dst = L.off_b2 + col;
+      col = t - L.H1;
+      p = fm ? src.x2 : src.d2, ld = L.H2, dst = L.off_b2 + col;
     } else if (t < L.H1 + 2 * L.H2) {
-      src = a2, ld = L.H2, col = t - L.H1 - L.H2, dst = L.off_w3 + col;
+      p = src.a2, ld = L.H2, col = t - L.H1 - L.H2, dst = L.off_w3 + col;
     } else {
-      src = nullptr, ld = 0, col = 0, dst = L.off_b3;
+      p = nullptr, ld = 0, col = 0, dst = L.off_b3;
     }
     float acc = 0.f;
     for (int64_t k = r0; k < r1; ++k) {
       const int64_t atom = a.perm[k];
-      acc = fmaf(a.w[atom], src ? src[atom * ld + col] : 1.0f, acc);
+      if (!p) acc += a.w[atom];
+      else if (fm) acc += p[atom * ld + col];
+      else acc = fmaf(a.w[atom], p[atom * ld + col], acc);
     }
     out[dst] = acc;
   }
@@ -205,15 +234,14 @@ void launch_pos_grad(const double* dL_dE, const int64_t* atom_ptr, int32_t B, in
                      dL_dpos);
 }
 
-void launch_wgrad(const WgradArgs& a, const ModelDev& m, const float* G, const float* a1, const float* d1,
-                  const float* a2, const float* d2, int D, int64_t N, float* const* dW, float* const* db,
-                  hipStream_t s) {
+void launch_wgrad(const WgradArgs& a, const ModelDev& m, const WgradSrc& src, int D, int64_t N, float* const* dW,
+                  float* const* db, hipStream_t s) {
   const WgradLayout L = wgrad_layout(D, m.m[0].width[1], m.m[0].width[2]);
   const int64_t chunks = N / kChunk + a.S + 1;
   const int tiles1 = (L.H1 / 16) * ((L.D + 63) / 64), tiles2 = (L.H2 / 16) * ((L.H1 + 63) / 64);
   const int tiles = tiles1 > tiles2 ? tiles1 : tiles2;
-  hipLaunchKernelGGL(k_wgrad_mm, dim3((unsigned)chunks, (unsigned)tiles, 2), dim3(64), 0, s, a, L, G, a1, d1, d2);
-  hipLaunchKernelGGL(k_wgrad_cols, dim3((unsigned)chunks), dim3(256), 0, s, a, L, d1, a2, d2);
+  hipLaunchKernelGGL(k_wgrad_mm, dim3((unsigned)chunks, (unsigned)tiles, 2), dim3(64), 0, s, a, L, src);
+  hipLaunchKernelGGL(k_wgrad_cols, dim3((unsigned)chunks), dim3(256), 0, s, a, L, src);
   GradOut out{};
   for (int sp = 0; sp < a.S; ++sp)
     for (int l = 0; l < 3; ++l) {

@@ -64,7 +64,7 @@ class nn_model(C.Structure):
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_autotune", "nn_autotune_reset", "nn_check",
            "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
@@ -91,8 +91,10 @@ def lib():
         L.nn_descriptors.argtypes = [P, P, P, P, P, P, SZ, P]
         L.nn_energy_forces.restype = I32
         L.nn_energy_forces.argtypes = [P, P, P, P, I32, SZ, P, P, P, P, SZ, P]
+        L.nn_descriptor_tangent.restype = I32
+        L.nn_descriptor_tangent.argtypes = [P, P, P, P, P, P]
         L.nn_energy_forces_grad.restype = I32
-        L.nn_energy_forces_grad.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, SZ, P]
+        L.nn_energy_forces_grad.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, SZ, P]
         L.nn_autotune.restype = I32
         L.nn_autotune.argtypes = [P, P, P, P, I32, P, SZ, P, P]
         L.nn_autotune_reset.restype = None
@@ -156,6 +158,10 @@ def nn_descriptors(sys, nl, params, G, jac, ws, stream=None):
                              0 if ws is None else ws.numel(), _stream(stream)))
 
 
+def nn_descriptor_tangent(sys, nl, params, v, U, stream=None):
+    _ok(lib().nn_descriptor_tangent(C.byref(sys), C.byref(nl), C.byref(params), _p(v), _p(U), _stream(stream)))
+
+
 def nn_energy_forces(sys, nl, params, model, flags, mem_budget, E_struct, E_atom, F, ws, stream=None):
     _ok(lib().nn_energy_forces(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, mem_budget,
                                _p(E_struct), _p(E_atom), _p(F), _p(ws), ws.numel(), _stream(stream)))
@@ -172,11 +178,12 @@ def _ptr_table(tensors):
     return arr
 
 
-def nn_energy_forces_grad(sys, nl, params, model, flags, dL_dE, F, dL_dpos, dW, db, ws, stream=None):
-    """dW, db: [species][layer] lists of FP32 device tensors (or None)."""
+def nn_energy_forces_grad(sys, nl, params, model, flags, dL_dE, dL_dF, F, dL_dpos, dW, db, ws, stream=None):
+    """dW, db: [species][layer] lists of FP32 device tensors (or None);
+    dL_dE [B] FP64, dL_dF [N, 3] FP32 (either may be None)."""
     _ok(lib().nn_energy_forces_grad(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, _p(dL_dE),
-                                    _p(F), _p(dL_dpos), _ptr_table(dW), _ptr_table(db), _p(ws), ws.numel(),
-                                    _stream(stream)))
+                                    _p(dL_dF), _p(F), _p(dL_dpos), _ptr_table(dW), _ptr_table(db), _p(ws),
+                                    ws.numel(), _stream(stream)))
 
 
 def nn_autotune(sys, nl, params, model, flags, ws, stream=None) -> tuple:
@@ -329,6 +336,14 @@ class Potential:
         nn_descriptors(self.sys, self.nl, self.params, self.G, None, self.ws)
         return self.G
 
+    def descriptor_tangent(self, v):
+        """U [N, D]: derivative of the descriptors along the displacement field v [N, 3]."""
+        torch = self.torch
+        v = torch.as_tensor(v, dtype=torch.float32, device=self.dev).reshape(self.N, 3).contiguous()
+        U = torch.zeros((self.N, self.D), dtype=torch.float32, device=self.dev)
+        nn_descriptor_tangent(self.sys, self.nl, self.params, v, U)
+        return U
+
     def autotune(self, flags: Optional[int] = None):
         """nn_autotune on the current list (build it first)."""
         f = self.flags if flags is None else flags
@@ -349,12 +364,17 @@ class Potential:
         nn_descriptors(self.sys, self.nl, self.params, G, J, self.ws)
         return G, J
 
-    def grad(self, dL_dE, flags: Optional[int] = None, positions: bool = True, weights: bool = True):
-        """Backward of E_struct after energy_forces(): (dL/dpos [N,3] or None,
-        [species][layer] (dW, db) or None)."""
+    def grad(self, dL_dE=None, flags: Optional[int] = None, positions: bool = True, weights: bool = True,
+             dL_dF=None):
+        """Backward of E_struct (dL_dE [B]) and F (dL_dF [N, 3]) after
+        energy_forces(): (dL/dpos [N,3] or None, [species][layer] (dW, db) or
+        None).  The position gradient is only available without dL_dF."""
         torch = self.torch
         f = self.flags if flags is None else flags
-        dL_dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=self.dev).contiguous()
+        if dL_dE is not None:
+            dL_dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=self.dev).contiguous()
+        if dL_dF is not None:
+            dL_dF = torch.as_tensor(dL_dF, dtype=torch.float32, device=self.dev).reshape(self.N, 3).contiguous()
         dpos = torch.zeros((self.N, 3), dtype=torch.float32, device=self.dev) if positions else None
         dW = db = None
         if weights:
@@ -369,8 +389,8 @@ class Potential:
                     bs_.append(torch.zeros_like(b))
                 dW.append(ws_)
                 db.append(bs_)
-        nn_energy_forces_grad(self.sys, self.nl, self.params, self.dmodel.struct, f, dL_dE, self.F, dpos, dW, db,
-                              self.ws)
+        nn_energy_forces_grad(self.sys, self.nl, self.params, self.dmodel.struct, f, dL_dE, dL_dF, self.F, dpos, dW,
+                              db, self.ws)
         return dpos, ([list(zip(w_s, b_s)) for w_s, b_s in zip(dW, db)] if weights else None)
 
     def neighbor_list_host(self):

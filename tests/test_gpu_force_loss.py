@@ -1,0 +1,191 @@
+"""Weight gradient of a loss on forces (force matching) through the C ABI.
+
+The descriptor tangent along a displacement field (nn_descriptor_tangent)
+and the weight gradient of sum_c gE_c E_c + sum_k gF_k . F_k
+(nn_energy_forces_grad with dL_dF) against the FP64 oracle on the same
+seeded inputs.  Tolerances: the tangent within 1e-4 of the largest entry of
+its descriptor block (radial block of a species, angular block of a species
+pair) in the same row, and the weight gradient within 1e-4 of the largest
+entry of each parameter tensor.  FP32 terms of either sign are summed over
+up to a few thousand triplets (rounding ~6e-8 relative each): a random walk
+of that many roundings is ~1e-5 of the block scale at the largest rows,
+and the bar allows a few times that.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11805_amd import nnpot, synth
+
+pytestmark = pytest.mark.gpu
+
+TAN_REL = 1e-4
+WG_REL = 1e-4
+
+
+def small_periodic_batch():
+    rng = np.random.Generator(np.random.PCG64(91))
+    p = synth.mbp_params(2, 4.0, 16, 8, 4)
+    systems = []
+    for L, n in [(3.4, 7), (6.1, 30)]:
+        cell = np.array([[L, 0, 0], [0.4, L * 0.96, 0], [-0.2, 0.5, L * 1.05]])
+        pos = rng.uniform(0, 1, (n, 3)) @ cell
+        systems.append(synth.single(pos, rng.integers(0, 2, n), cell=cell, pbc=(1, 1, 1)))
+    cl = synth.clusters_system(rng, [11, 2, 17], lambda n: 5.0, 0.9, 2)
+    model = synth.random_model(2, p.dim, [64, 32], 5, in_scale=3.0)
+    return synth.Workload("small periodic cells + clusters", synth.concat(systems + [cl]), p, model, 91)
+
+
+CASES = {
+    "cfg0": lambda: synth.config(0),
+    "cfg1s": lambda: synth.config(1, scale=0.25),
+    "cfg2s": lambda: synth.config(2, scale=0.03),
+    "cfg3s": lambda: synth.config(3, scale=0.05),
+    "smallcells": small_periodic_batch,
+}
+
+
+def field(seed, n):
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal((n, 3))
+
+
+def block_bounds(p):
+    """Column ranges of the descriptor blocks (radial per species, angular per pair)."""
+    S, nr, nb = p.n_species, p.n_rad, p.n_theta * p.n_rs_ang
+    out = [(s * nr, (s + 1) * nr) for s in range(S)]
+    a0 = S * nr
+    for k in range(S * (S + 1) // 2):
+        out.append((a0 + k * nb, a0 + (k + 1) * nb))
+    return out
+
+
+def tangent_error(U, U_ref, p):
+    worst = 0.0
+    for c0, c1 in block_bounds(p):
+        ref = U_ref[:, c0:c1]
+        scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-30)
+        worst = max(worst, float((np.abs(U[:, c0:c1] - ref) / scale).max()))
+    return worst
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_descriptor_tangent_matches_oracle(name):
+    w = CASES[name]()
+    s, p = w.system, w.params
+    print(f"[tangent] {name}: {s.n_atoms} atoms", flush=True)
+    v = field(w.seed + 5, s.n_atoms)
+    nl = oracle.neighbors_cells(s, p.rc)
+    U_ref = oracle.descriptor_tangent(p, s, nl, v)
+    pot = nnpot.Potential(s, p, w.model)
+    pot.build_neighbors()
+    U = pot.descriptor_tangent(v.astype(np.float32)).double().cpu().numpy()
+    nnpot.nn_check(pot.nl)
+    # the oracle takes v in FP64, the GPU the FP32 rounding of it
+    U_ref32 = oracle.descriptor_tangent(p, s, nl, v.astype(np.float32).astype(np.float64))
+    err = tangent_error(U, U_ref32, p)
+    print(f"  max |dU| / block scale = {err:.2e}", flush=True)
+    assert err <= TAN_REL
+    assert np.abs(U_ref - U_ref32).max() <= 1e-5 * max(np.abs(U_ref).max(), 1e-30)
+
+
+def weight_grad_error(got, ref):
+    worst = 0.0
+    for sp in range(len(ref)):
+        for (dW_r, db_r), (dW_g, db_g) in zip(ref[sp], got[sp]):
+            for r_, g_ in ((dW_r, dW_g), (db_r, db_g)):
+                g_ = g_.double().cpu().numpy().reshape(r_.shape)
+                scale_ = max(np.abs(r_).max(), 1e-30)
+                worst = max(worst, float(np.abs(g_ - r_).max() / scale_))
+    return worst
+
+
+def run_force_loss(w, gE, gF):
+    s, p = w.system, w.params
+    nl = oracle.neighbors_cells(s, p.rc)
+    gF32 = None if gF is None else gF.astype(np.float32)
+    ref = oracle.unflatten_grads(w.model, oracle.force_loss_grad(
+        p, w.model, s, nl, gE, None if gF32 is None else gF32.astype(np.float64)))
+    pot = nnpot.Potential(s, p, w.model)
+    pot.build_neighbors()
+    pot.energy_forces()
+    _, got = pot.grad(gE, positions=False, dL_dF=gF32)
+    nnpot.nn_check(pot.nl)
+    return weight_grad_error(got, ref), pot
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_force_loss_weight_gradient_matches_oracle(name):
+    w = CASES[name]()
+    s = w.system
+    print(f"[force-loss wgrad] {name}: {s.n_atoms} atoms", flush=True)
+    rng = np.random.Generator(np.random.PCG64(w.seed + 9))
+    gE = rng.standard_normal(s.n_structs)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    err, _ = run_force_loss(w, gE, gF)
+    print(f"  max |d dW| / max |dW| = {err:.2e}", flush=True)
+    assert err <= WG_REL
+
+
+def test_force_term_alone_and_energy_term_alone():
+    w = CASES["cfg0"]()
+    s = w.system
+    rng = np.random.Generator(np.random.PCG64(3))
+    gE = rng.standard_normal(s.n_structs)
+    gF = rng.standard_normal((s.n_atoms, 3))
+    err_f, _ = run_force_loss(w, None, gF)
+    err_e, _ = run_force_loss(w, gE, None)
+    print(f"  force only {err_f:.2e}, energy only {err_e:.2e}", flush=True)
+    assert err_f <= WG_REL and err_e <= WG_REL
+
+
+def test_force_loss_gradient_deterministic_and_position_gradient_refused():
+    import torch
+    w = CASES["cfg2s"]()
+    s = w.system
+    rng = np.random.Generator(np.random.PCG64(4))
+    gE = rng.standard_normal(s.n_structs)
+    gF = rng.standard_normal((s.n_atoms, 3)).astype(np.float32)
+    pot = nnpot.Potential(s, w.params, w.model)
+    pot.build_neighbors()
+    pot.energy_forces()
+    outs = []
+    for _ in range(2):
+        _, got = pot.grad(gE, positions=False, dL_dF=gF)
+        outs.append([t.cpu().numpy().copy() for layers in got for pair in layers for t in pair])
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    with pytest.raises(nnpot.NNError):
+        pot.grad(gE, positions=True, dL_dF=gF)
+    torch.cuda.synchronize()
+
+
+def test_autograd_force_matching_loss_matches_oracle():
+    """L = sum_c (E_c - T_c)^2 / B + sum_k |F_k - F*_k|^2 / (3N) through the
+    autograd.Function; the weight gradient against the oracle at the
+    upstream gradients that L gives."""
+    import torch
+    from paper_2305_11805_amd.autograd import energy_forces
+    w = CASES["cfg0"]()
+    s, p = w.system, w.params
+    pot = nnpot.Potential(s, p, w.model)
+    rng = np.random.Generator(np.random.PCG64(12))
+    T = torch.tensor(rng.standard_normal(s.n_structs), dtype=torch.float64, device=pot.dev)
+    Ft = torch.tensor(rng.standard_normal((s.n_atoms, 3)), dtype=torch.float32, device=pot.dev)
+    weights = list(pot.dmodel.tensors)
+    for t in weights:
+        t.requires_grad_(True)
+    E, F = energy_forces(pot, pot.pos.clone())
+    L = ((E - T) ** 2).mean() + ((F - Ft) ** 2).sum() / (3 * s.n_atoms)
+    L.backward()
+    gE = (2.0 * (E.detach() - T) / s.n_structs).cpu().numpy()
+    gF = (2.0 * (F.detach() - Ft) / (3 * s.n_atoms)).cpu().numpy()
+    nl = oracle.neighbors_cells(s, p.rc)
+    flat = oracle.force_loss_grad(p, w.model, s, nl, gE, gF.astype(np.float64))
+    ref = oracle.unflatten_grads(w.model, flat)
+    got = [[(weights[2 * (3 * sp + l)].grad, weights[2 * (3 * sp + l) + 1].grad) for l in range(3)]
+           for sp in range(len(ref))]
+    for t in weights:
+        t.requires_grad_(False)
+    err = weight_grad_error(got, ref)
+    print(f"  autograd force matching: max |d dW| / max |dW| = {err:.2e}", flush=True)
+    assert err <= WG_REL
