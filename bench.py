@@ -369,6 +369,29 @@ def suite_config(idx, modes, steps, out):
             ms = _timed(torch, stream, g.replay, steps) / steps
             res["loss_gradient_step_graph"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
             del g
+            # force-matching step: E, F and dL/dW of
+            # L = mean_c (E_c - T_c)^2 + sum_k |F_k - F*_k|^2 / (3N)
+            Ft = torch.tensor(synth.force_targets(w.seed, s.n_atoms), dtype=torch.float32, device="cuda")
+
+            def fm_step():
+                build()
+                ef()
+                dL = (2.0 / s.n_structs) * (pot.E_struct - T)
+                dF = (2.0 / (3 * s.n_atoms)) * (pot.F - Ft)
+                pot.grad(dL, positions=False, weights=True, dL_dF=dF)
+            fm_step()
+            ms = _timed(torch, stream, fm_step, steps) / steps
+            res["force_matching_step"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            side = torch.cuda.Stream()
+            side.wait_stream(stream)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=side):
+                fm_step()
+            torch.cuda.synchronize()
+            g.replay()
+            ms = _timed(torch, stream, g.replay, steps) / steps
+            res["force_matching_step_graph"] = {"ms": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1)}
+            del g
             # the same structures, one Potential and one launch sequence each
             sub = 64
             pots = [nnpot.Potential(synth.single(s.pos[s.atom_ptr[c]:s.atom_ptr[c + 1]],

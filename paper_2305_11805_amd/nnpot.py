@@ -385,8 +385,8 @@ class Potential:
                 ws_, bs_ = [], []
                 for _ in range(L):
                     W, b = next(it), next(it)
-                    ws_.append(torch.zeros_like(W))
-                    bs_.append(torch.zeros_like(b))
+                    ws_.append(torch.empty_like(W))  # every element is written
+                    bs_.append(torch.empty_like(b))
                 dW.append(ws_)
                 db.append(bs_)
         nn_energy_forces_grad(self.sys, self.nl, self.params, self.dmodel.struct, f, dL_dE, dL_dF, self.F, dpos, dW,

@@ -263,6 +263,11 @@ def energy_targets(seed: int, n_structs: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64([seed, 11])).normal(size=n_structs)
 
 
+def force_targets(seed: int, n_atoms: int) -> np.ndarray:
+    """Seeded force targets F*_k ~ N(0, 1) eV/A per component for a force-matching loss."""
+    return np.random.Generator(np.random.PCG64([seed, 12])).normal(size=(n_atoms, 3))
+
+
 def single(pos, species, cell=None, pbc=(0, 0, 0)) -> System:
     """One structure from explicit arrays (tests and small examples)."""
     pos = np.asarray(pos, np.float64).reshape(-1, 3)
