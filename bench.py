@@ -49,10 +49,15 @@ def flop_model(p, n_valid):
     geom = 33
     fwd_trip = geom + 4 * NT + NT * ipow_mults(z) + 7 * NR + 2 * NT * NR
     adj_trip = geom + 4 * NT + NT * ipow_mults(z - 1) + NT + 6 * NR + 4 * NT * NR + 5 * NR + 5 * NT + 35
+    # tangent along a displacement field: the forward terms, their derivatives
+    # (A_dot 5 per angle bin, R_dot 5 per radius bin, cos/ssm/F2/rbar dots 26)
+    # and two FMAs per bin
+    tan_trip = geom + 4 * NT + NT * ipow_mults(z - 1) + NT + 5 * NT + 26 + 12 * NR + 4 * NT * NR
     fwd = T * fwd_trip + P * p.n_rad * 8
     adj = T * adj_trip + P * (p.n_rad * 12 + 6)
-    return {"pairs": P, "triplets": T, "desc_fwd": fwd, "desc_adj": adj,
-            "per_triplet": {"desc_fwd": fwd_trip, "desc_adj": adj_trip}}
+    tan = T * tan_trip + P * (p.n_rad * 12 + 11)
+    return {"pairs": P, "triplets": T, "desc_fwd": fwd, "desc_adj": adj, "desc_tan": tan,
+            "per_triplet": {"desc_fwd": fwd_trip, "desc_adj": adj_trip, "desc_tan": tan_trip}}
 
 
 def mlp_flops(w, n_atoms):
@@ -421,6 +426,43 @@ def suite_config(idx, modes, steps, out):
     print(json.dumps(res), flush=True)
 
 
+def force_matching(args):
+    """One force-matching training step per iteration on --config: list
+    (re)build, E and F, then dL/dW of L = mean_c (E_c - T_c)^2 +
+    sum_k |F_k - F*_k|^2 / (3N) (the force term through the descriptor
+    tangent and the MLP's forward-mode tangent).  Prints one JSON line."""
+    import torch
+    from paper_2305_11805_amd import nnpot, synth
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    w = synth.config(args.config)
+    s = w.system
+    pot = nnpot.Potential(s, w.params, w.model, skin=float(w.extra.get("skin", 0.0)))
+    T = torch.tensor(synth.energy_targets(w.seed, s.n_structs), dtype=torch.float64, device="cuda")
+    Ft = torch.tensor(synth.force_targets(w.seed, s.n_atoms), dtype=torch.float32, device="cuda")
+
+    def step():
+        pot.build_neighbors(check=False)
+        pot.energy_forces()
+        dL = (2.0 / s.n_structs) * (pot.E_struct - T)
+        dF = (2.0 / (3 * s.n_atoms)) * (pot.F - Ft)
+        pot.grad(dL, positions=False, weights=True, dL_dF=dF)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    nnpot.nn_check(pot.nl)
+    stream = torch.cuda.current_stream()
+    ms = _timed(torch, stream, step, args.steps) / args.steps
+    nnpot.nn_check(pot.nl)
+    n_valid = valid_neighbor_counts(pot, w.params.rc)
+    fm = flop_model(w.params, n_valid)
+    res = {"workload": w.name, "step": "force_matching", "n_atoms": s.n_atoms, "steps": args.steps,
+           "ms_per_step": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1),
+           "desc_tan_flops_per_launch": fm["desc_tan"], "desc_tan_flops_per_triplet": fm["per_triplet"]["desc_tan"]}
+    print(json.dumps(res), flush=True)
+
+
 def suite(args):
     import torch
     if not torch.cuda.is_available():
@@ -452,6 +494,8 @@ def main():
                     help="measure every workload (one JSON line each) instead of the single bench line")
     ap.add_argument("--suite-configs", type=int, nargs="*", default=[0, 1, 2, 3, 4])
     ap.add_argument("--suite-out", default="suite.jsonl")
+    ap.add_argument("--force-matching", action="store_true",
+                    help="time the force-matching training step on --config instead of the bench line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
@@ -461,6 +505,9 @@ def main():
     from paper_2305_11805_amd import synth
     if args.suite:
         suite(args)
+        return
+    if args.force_matching:
+        force_matching(args)
         return
     if args.ingest_counters:
         if args.calib_copy_mib <= 0:
