@@ -7,7 +7,8 @@ library.  Inputs are plain arrays (any object with the attributes named
 below); nothing here imports the product package.
 
 What each function computes, and the passage of the PANNA 2.0 paper it
-follows, is stated in ``nnref.c``.
+follows, is stated in ``nnref.c``; the Langevin integrator written here in
+numpy (``md_langevin``) states it in its docstring.
 """
 from __future__ import annotations
 
@@ -299,6 +300,51 @@ def unflatten_grads(model, flat):
             layers.append((dW, db))
         out.append(layers)
     return out
+
+
+# (eV / Angstrom) / amu in Angstrom / fs^2: eV = 1.602176634e-19 J,
+# amu = 1.66053906660e-27 kg, Angstrom^2 / fs^2 = 1e10 m^2 / s^2
+ACCEL = 1.602176634e-19 / 1.66053906660e-27 / 1e10
+
+
+class _Sys:
+    def __init__(self, pos, species, atom_ptr, cell, pbc):
+        self.pos, self.species, self.atom_ptr, self.cell, self.pbc = pos, species, atom_ptr, cell, pbc
+
+
+def md_langevin(params, model, sys, vel, inv_mass, dt, friction, kT, noise, n_steps, cutoff=None):
+    """Langevin dynamics on the potential, as in the repeated evaluation of
+    Table II (Sec. III.B), by the BAOAB splitting (Leimkuhler and Matthews,
+    2013): per step
+        v += dt/2 F/m;  x += dt/2 v;  v = c1 v + c2 sqrt(kT/m) xi;  x += dt/2 v;
+        F = F(x) (fresh cell list at `cutoff`, default rc);  v += dt/2 F/m,
+    with c1 = exp(-friction dt), c2 = sqrt(1 - c1^2), xi = noise[step].
+    Units: Angstrom, fs, eV, amu.  Returns (x, v, F, E_pot [n_steps][B])."""
+    x = np.array(sys.pos, np.float64, copy=True).reshape(-1, 3)
+    v = np.array(vel, np.float64, copy=True).reshape(-1, 3)
+    a = (np.asarray(inv_mass, np.float64) * ACCEL)[:, None]
+    rc = params.rc if cutoff is None else cutoff
+
+    def eval_at(xx):
+        s = _Sys(xx, sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+        E, _, F = energy_forces(params, model, s, neighbors_cells(s, rc))
+        return E, F
+
+    _, F = eval_at(x)
+    c1 = np.exp(-friction * dt)
+    c2 = np.sqrt(max(0.0, 1.0 - c1 * c1))
+    sigma = np.sqrt(kT * a)
+    E_pot = []
+    for n in range(n_steps):
+        v = v + 0.5 * dt * a * F
+        x = x + 0.5 * dt * v
+        xi = np.asarray(noise[n], np.float64).reshape(-1, 3) if friction > 0 else 0.0
+        v = c1 * v + c2 * sigma * xi
+        x = x + 0.5 * dt * v
+        E, F = eval_at(x)
+        v = v + 0.5 * dt * a * F
+        E_pot.append(E)
+    return x, v, F, np.array(E_pot).reshape(n_steps, -1)
 
 
 def num_threads() -> int:

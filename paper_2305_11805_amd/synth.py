@@ -251,6 +251,35 @@ def config(idx: int, scale: float = 1.0) -> Workload:
     return Workload(name, sys, p, model, seed, extra)
 
 
+# Atomic masses (amu) of the four species the molecular workloads draw
+# ({H, C, N, O}); the bulk workloads are carbon.
+SPECIES_MASS = (1.008, 12.011, 14.007, 15.999)
+CARBON_MASS = 12.011
+
+
+def md_cells(n_cells: int = 1) -> Workload:
+    """The repeated-evaluation shape of Table II: 16-atom periodic carbon
+    cells at the config-1 density and minimum distance (cube side 5.43 A,
+    narrower than 2 Rc, so several images of each atom are neighbors), with
+    the config-1 descriptor and MLP; n_cells independent cells are batched as
+    structures."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 5))
+    cells = [bulk_system(rng, 16, 0.1, 1.2, [16]) for _ in range(n_cells)]
+    p = mbp_params(1, 5.0, 32, 8, 8)
+    model = random_model(1, p.dim, [128, 128], SEED_BASE + 1, in_scale=IN_SCALE[1])
+    name = f"{n_cells} periodic carbon cell(s) of 16 atoms, rho 0.1, Rc 5.0, 32 + 8x8 bins, MLP D-128-128-1"
+    return Workload(name, concat(cells), p, model, SEED_BASE + 5, {"mass": CARBON_MASS})
+
+
+def md_inputs(seed: int, n_atoms: int, n_steps: int, v_sigma: float):
+    """Initial velocities N(0, v_sigma) (Angstrom/fs, FP64 [N, 3]) and the
+    Langevin noise: standard normal FP32 [n_steps, N, 3]."""
+    rng = np.random.Generator(np.random.PCG64([seed, 13]))
+    v0 = rng.normal(0.0, v_sigma, size=(n_atoms, 3))
+    noise = rng.standard_normal(size=(n_steps, n_atoms, 3), dtype=np.float32)
+    return v0, noise
+
+
 def md_displacements(seed: int, n_atoms: int, steps: int, sigma: float):
     """Generator of per-step Gaussian displacements (cumulative random walk)."""
     rng = np.random.Generator(np.random.PCG64([seed, 7]))

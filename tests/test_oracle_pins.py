@@ -524,3 +524,71 @@ def test_force_loss_weight_gradient_vs_torch_double_backward(O):
         for (dW, db), (W, b) in zip(grads[s], tparams[s]):
             np.testing.assert_allclose(dW, W.grad.numpy(), rtol=1e-10, atol=1e-13)
             np.testing.assert_allclose(db, b.grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# Langevin dynamics (the repeated evaluation of Table II), BAOAB splitting
+# ---------------------------------------------------------------------------
+
+def test_md_unit_conversion_textbook_value(O):
+    """1 amu A^2 / fs^2 = 103.6427 eV (CODATA-based tabulated value)."""
+    assert abs(1.0 / O.ACCEL - 103.6427) < 5e-4
+
+
+def test_md_free_atoms_closed_form(O):
+    """Isolated atoms (one per structure, nothing within rc) feel no force, so
+    the splitting reduces to the exact Ornstein-Uhlenbeck velocity update and a
+    trapezoid position update:
+        v_m = c1^m v_0 + c2 s sum_{k<m} c1^(m-1-k) xi_k,  s = sqrt(kT / m),
+        x_n = x_0 + dt/2 sum_{m=1..n} (v_{m-1} + v_m)."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    p = synth.mbp_params(2, 4.0, 8, 4, 4)
+    model = synth.random_model(2, p.dim, [64, 32], 3)
+    n = 5
+    pos = rng.uniform(0, 3, (n, 3))
+    sys = synth.System(pos, np.array([0, 1, 1, 0, 1], np.int32), np.arange(n + 1, dtype=np.int64),
+                       np.stack([np.eye(3) * 10] * n), np.zeros((n, 3), np.uint8))
+    m = np.array([1.008, 12.011, 14.007, 15.999, 12.011])
+    dt, gamma, kT, steps = 0.7, 0.05, 0.03, 30
+    v0, noise = synth.md_inputs(4, n, steps, 0.01)
+    x, v, F, E = O.md_langevin(p, model, sys, v0, 1.0 / m, dt, gamma, kT, noise, steps)
+    c1 = np.exp(-gamma * dt)
+    c2 = np.sqrt(1 - c1 * c1)
+    s = np.sqrt(kT / (103.6427 * m))[:, None]  # velocity scale in A/fs
+    xi = noise.astype(np.float64)
+    vs = [v0]
+    for mm in range(1, steps + 1):
+        k = np.arange(mm)
+        vs.append(c1 ** mm * v0 + c2 * s * np.tensordot(c1 ** (mm - 1 - k), xi[:mm], axes=(0, 0)))
+    x_ref = pos + 0.5 * dt * sum(vs[mm - 1] + vs[mm] for mm in range(1, steps + 1))
+    assert np.all(F == 0) and np.all(E == E[0])
+    assert np.allclose(v, vs[-1], rtol=1e-6, atol=1e-12)
+    assert np.allclose(x, x_ref, rtol=1e-6, atol=1e-9)
+
+
+def test_md_velocity_verlet_energy_error_is_second_order(O):
+    """Without friction the splitting is velocity Verlet: the largest
+    deviation of E_pot + E_kin along an 8 fs path shrinks four-fold when dt
+    halves (two molecular clusters of the 4-species workload)."""
+    w = synth.config(0)
+    s = w.system
+    n2 = int(s.atom_ptr[2])
+    sub = synth.System(s.pos[:n2], s.species[:n2], s.atom_ptr[:3], s.cell[:2], s.pbc[:2])
+    inv_m = 1.0 / np.asarray(synth.SPECIES_MASS)[sub.species]
+    v0, _ = synth.md_inputs(5, n2, 1, 0.005)
+
+    def ke(v):
+        return 0.5 * np.sum(np.sum(v * v, axis=1) / inv_m) / O.ACCEL
+
+    def worst(dt):
+        E0, _, _ = O.energy_forces(w.params, w.model, sub, O.neighbors_cells(sub, w.params.rc))
+        Et0 = E0.sum() + ke(v0)
+        cur, v, dev = sub, v0, 0.0
+        for _ in range(int(round(8.0 / dt))):
+            x, v, _, E = O.md_langevin(w.params, w.model, cur, v, inv_m, dt, 0.0, 0.0, None, 1)
+            cur = synth.System(x, sub.species, sub.atom_ptr, sub.cell, sub.pbc)
+            dev = max(dev, abs(E.sum() + ke(v) - Et0))
+        return dev
+
+    d1, d2 = worst(0.4), worst(0.2)
+    assert 3.0 < d1 / d2 < 5.0, (d1, d2)
