@@ -463,6 +463,56 @@ def force_matching(args):
     print(json.dumps(res), flush=True)
 
 
+def md_table2(args):
+    """The repeated-evaluation shape of Table II: Langevin dynamics (300 K,
+    0.5 fs, friction 0.01 / fs) of 16-atom periodic carbon cells through
+    nn_md_langevin, one cell and a batch of independent cells, eager and
+    replayed from a HIP graph.  Prints one JSON line; the paper's figure
+    (0.78 ms per step per atom, A100 through ASE) is context only."""
+    import torch
+    from paper_2305_11805_amd import nnpot, synth
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    dt, gamma, kT = 0.5, 0.01, 0.025852
+    out = {"step": "langevin_md", "dt_fs": dt, "friction_per_fs": gamma, "kT_eV": kT,
+           "paper_context": {"ms_per_step_per_atom": 0.78, "hardware": "A100, ASE driver"}, "runs": []}
+    for n_cells, steps in ((1, 1000), (args.md_cells, 200)):
+        w = synth.md_cells(n_cells)
+        s = w.system
+        pot = nnpot.Potential(s, w.params, w.model, skin=1.0)
+        pot.build_neighbors()
+        pot.energy_forces()
+        v0, _ = synth.md_inputs(w.seed, s.n_atoms, 1, 0.005)
+        vel = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        im = torch.full((s.n_atoms,), 1.0 / synth.CARBON_MASS, dtype=torch.float64, device="cuda")
+        chunk = 100
+        xi = torch.randn((chunk, s.n_atoms, 3), dtype=torch.float32, device="cuda")
+        E = torch.empty((chunk, s.n_structs), dtype=torch.float64, device="cuda")
+
+        def run_chunk():
+            pot.md_langevin(chunk, vel, im, dt, gamma, kT, noise=xi, E_pot=E)
+        run_chunk()
+        torch.cuda.synchronize()
+        ms = _timed(torch, stream, run_chunk, steps // chunk) / (steps // chunk * chunk)
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            run_chunk()
+        torch.cuda.synchronize()
+        g.replay()
+        ms_g = _timed(torch, stream, g.replay, steps // chunk) / (steps // chunk * chunk)
+        nnpot.nn_check(pot.nl)
+        del g
+        out["runs"].append({"cells": n_cells, "atoms": s.n_atoms, "steps": steps,
+                            "ms_per_step": round(ms, 5), "ms_per_step_graph": round(ms_g, 5),
+                            "us_per_step_per_atom_graph": round(ms_g * 1e3 / s.n_atoms, 4),
+                            "list_builds": int(pot.meta[2].item())})
+    print(json.dumps(out), flush=True)
+
+
 def suite(args):
     import torch
     if not torch.cuda.is_available():
@@ -494,6 +544,9 @@ def main():
                     help="measure every workload (one JSON line each) instead of the single bench line")
     ap.add_argument("--suite-configs", type=int, nargs="*", default=[0, 1, 2, 3, 4])
     ap.add_argument("--suite-out", default="suite.jsonl")
+    ap.add_argument("--md", action="store_true",
+                    help="Langevin dynamics of 16-atom cells (the Table II shape) instead of the bench line")
+    ap.add_argument("--md-cells", type=int, default=1024, help="cells in the batched --md run")
     ap.add_argument("--force-matching", action="store_true",
                     help="time the force-matching training step on --config instead of the bench line")
     args = ap.parse_args()
@@ -508,6 +561,9 @@ def main():
         return
     if args.force_matching:
         force_matching(args)
+        return
+    if args.md:
+        md_table2(args)
         return
     if args.ingest_counters:
         if args.calib_copy_mib <= 0:

@@ -306,6 +306,43 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
                                 const float* F, float* dL_dpos, float* const* dW, float* const* db, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* Langevin dynamics parameters (units: Angstrom, fs, eV, amu). */
+typedef struct {
+  double dt;       /* time step, fs (> 0)                                   */
+  double friction; /* gamma, 1/fs (>= 0); 0 gives velocity Verlet (constant energy) */
+  double kT;       /* thermal energy, eV (>= 0)                             */
+} nn_langevin;
+
+/*
+ * n_steps steps of Langevin dynamics on the potential: the repeated
+ * evaluation of Table II (Sec. III.B), integrated with the BAOAB splitting
+ * (Leimkuhler and Matthews 2013):  B v += dt/2 F/m;  A x += dt/2 v;
+ * O v = c1 v + c2 sqrt(kT/m) xi with c1 = exp(-gamma dt), c2 = sqrt(1 - c1^2);
+ * A x += dt/2 v;  list update (nn_build_neighbors with rc, skin: rebuilt on
+ * the device only when an atom moved farther than skin/2) and
+ * nn_energy_forces at the new x;  B v += dt/2 F/m.
+ *   pos      [device] FP64 [N][3], the buffer sys->pos points at (advanced in
+ *            place; NN_E_INVALID if pos != sys->pos).
+ *   vel      [device] FP64 [N][3] in/out, Angstrom/fs.
+ *   inv_mass [device] FP64 [N], 1/amu.
+ *   noise    [device] FP32 [n_steps][N][3] standard normal draws xi (the
+ *            caller's generator); may be NULL when friction == 0.
+ *   E_pot    [device] FP64 [n_steps][B]: the energies after each step.
+ *   F        [device] FP32 [N][3] in/out: on entry the forces at pos (as
+ *            left by nn_energy_forces or the previous call), on exit those
+ *            at the final positions.
+ *   flags    MLP precision flags of nn_energy_forces (no stored Jacobian).
+ * nl, ws as for nn_build_neighbors / nn_energy_forces (a skin > 0 needs
+ * nl->ref_pos).  Everything is enqueued on `stream` with no host round
+ * trip, so a whole call can be captured in a HIP graph.  Device-side errors
+ * (list capacity, ...) are reported by nn_check; after a capacity overflow
+ * the forces of the following steps are zero.
+ */
+nn_status nn_md_langevin(const nn_system* sys, double* pos, double* vel, const double* inv_mass, nn_nlist* nl,
+                         double rc, double skin, const nn_mbp_params* p, const nn_model* model, int32_t flags,
+                         const nn_langevin* lp, const float* noise, int32_t n_steps, double* E_pot, float* F,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /*
  * Synchronize `stream` and report device-side errors recorded in the list's
  * metadata since the last check (then clear them).  *info (may be NULL)

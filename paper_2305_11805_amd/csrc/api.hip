@@ -771,6 +771,42 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   return check_launch("nn_energy_forces_grad");
 }
 
+nn_status nn_md_langevin(const nn_system* sys, double* pos, double* vel, const double* inv_mass, nn_nlist* nl,
+                         double rc, double skin, const nn_mbp_params* p, const nn_model* model, int32_t flags,
+                         const nn_langevin* lp, const float* noise, int32_t n_steps, double* E_pot, float* F,
+                         void* ws, size_t ws_bytes, void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if (!lp) return fail(NN_E_INVALID, "langevin parameters are NULL");
+  if (!(lp->dt > 0.0) || !isfinite(lp->dt) || !(lp->friction >= 0.0) || !isfinite(lp->friction) ||
+      !(lp->kT >= 0.0) || !isfinite(lp->kT))
+    return fail(NN_E_INVALID, "need dt > 0, friction >= 0 and kT >= 0 (finite)");
+  if (n_steps < 0) return fail(NN_E_INVALID, "n_steps < 0");
+  if (flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
+    return fail(NN_E_INVALID, "dynamics takes only the MLP precision flags");
+  const int64_t N = sys->n_atoms;
+  if (N > 0 && pos != sys->pos) return fail(NN_E_INVALID, "pos must be the buffer sys->pos points at");
+  if (N > 0 && (!vel || !inv_mass || !F)) return fail(NN_E_INVALID, "vel/inv_mass/F is NULL");
+  if (n_steps > 0 && sys->n_structs > 0 && !E_pot) return fail(NN_E_INVALID, "E_pot is NULL");
+  if (N > 0 && n_steps > 0 && lp->friction > 0.0 && !noise) return fail(NN_E_INVALID, "noise is NULL");
+  if (n_steps == 0 || N == 0) return NN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const double c1 = exp(-lp->friction * lp->dt);
+  const double c2 = sqrt(std::max(0.0, 1.0 - c1 * c1));
+  const double c2_sqrt_kT = c2 * sqrt(lp->kT);
+  const float* xi = lp->friction > 0.0 ? noise : nullptr;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    launch_md_update(N, k == 0 ? kMdHalfKickDrift : kMdKickDrift, pos, vel, inv_mass, F,
+                     xi ? xi + (size_t)k * 3 * (size_t)N : nullptr, lp->dt, c1, c2_sqrt_kT, s);
+    if ((st = nn_build_neighbors(sys, rc, skin, nl, ws, ws_bytes, stream))) return st;
+    if ((st = nn_energy_forces(sys, nl, p, model, flags, 0, E_pot + (size_t)k * sys->n_structs, nullptr, F, ws,
+                               ws_bytes, stream)))
+      return st;
+  }
+  launch_md_update(N, kMdKick, pos, vel, inv_mass, F, nullptr, lp->dt, c1, c2_sqrt_kT, s);
+  return check_launch("nn_md_langevin");
+}
+
 nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {
   if (!nl || !nl->meta) return fail(NN_E_INVALID, "nl/meta is NULL");
   hipStream_t s = (hipStream_t)stream;

@@ -253,5 +253,13 @@ void launch_pos_grad(const double* dL_dE, const int64_t* atom_ptr, int32_t B, in
                      float* dL_dpos, hipStream_t s);
 void launch_energy_reduce(const float* E_atom, const int64_t* atom_ptr, int32_t B, int64_t N, double* E_struct,
                           hipStream_t s);
+// md.hip: one integrator update of the BAOAB Langevin splitting per atom.
+//   kMdHalfKickDrift: B A O A (the first step);
+//   kMdKickDrift:     a kick of dt (the previous step's last B and this
+//                     step's first B), then A O A;
+//   kMdKick:          the last B only.
+enum { kMdHalfKickDrift = 0, kMdKickDrift = 1, kMdKick = 2 };
+void launch_md_update(int64_t N, int mode, double* pos, double* vel, const double* inv_mass, const float* F,
+                      const float* noise, double dt, double c1, double c2_sqrt_kT, hipStream_t s);
 
 }  // namespace nnp

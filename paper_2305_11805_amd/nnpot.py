@@ -62,9 +62,13 @@ class nn_model(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("mlp", nn_mlp * NN_MAX_SPECIES)]
 
 
+class nn_langevin(C.Structure):
+    _fields_ = [("dt", C.c_double), ("friction", C.c_double), ("kT", C.c_double)]
+
+
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_autotune", "nn_autotune_reset", "nn_check",
            "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
@@ -93,6 +97,8 @@ def lib():
         L.nn_energy_forces.argtypes = [P, P, P, P, I32, SZ, P, P, P, P, SZ, P]
         L.nn_descriptor_tangent.restype = I32
         L.nn_descriptor_tangent.argtypes = [P, P, P, P, P, P]
+        L.nn_md_langevin.restype = I32
+        L.nn_md_langevin.argtypes = [P, P, P, P, P, C.c_double, C.c_double, P, P, I32, P, P, I32, P, P, P, SZ, P]
         L.nn_energy_forces_grad.restype = I32
         L.nn_energy_forces_grad.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, SZ, P]
         L.nn_autotune.restype = I32
@@ -184,6 +190,13 @@ def nn_energy_forces_grad(sys, nl, params, model, flags, dL_dE, dL_dF, F, dL_dpo
     _ok(lib().nn_energy_forces_grad(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, _p(dL_dE),
                                     _p(dL_dF), _p(F), _p(dL_dpos), _ptr_table(dW), _ptr_table(db), _p(ws),
                                     ws.numel(), _stream(stream)))
+
+
+def nn_md_langevin(sys, pos, vel, inv_mass, nl, rc, skin, params, model, flags, lp, noise, n_steps, E_pot, F, ws,
+                   stream=None):
+    _ok(lib().nn_md_langevin(C.byref(sys), _p(pos), _p(vel), _p(inv_mass), C.byref(nl), float(rc), float(skin),
+                             C.byref(params), C.byref(model), flags, C.byref(lp), _p(noise), int(n_steps), _p(E_pot),
+                             _p(F), _p(ws), ws.numel(), _stream(stream)))
 
 
 def nn_autotune(sys, nl, params, model, flags, ws, stream=None) -> tuple:
@@ -343,6 +356,23 @@ class Potential:
         U = torch.zeros((self.N, self.D), dtype=torch.float32, device=self.dev)
         nn_descriptor_tangent(self.sys, self.nl, self.params, v, U)
         return U
+
+    def md_langevin(self, n_steps, vel, inv_mass, dt, friction, kT, noise=None, E_pot=None,
+                    flags: Optional[int] = None):
+        """n_steps of BAOAB Langevin dynamics in place on self.pos / vel
+        (FP64 [N, 3], Angstrom/fs), with inv_mass FP64 [N] (1/amu), dt in fs,
+        friction in 1/fs, kT in eV and noise FP32 [n_steps, N, 3] standard
+        normal draws.  self.F must hold the forces at the current positions
+        (energy_forces() or the previous call) and holds those at the new
+        ones on return.  Returns E_pot [n_steps, B] (FP64)."""
+        torch = self.torch
+        f = self.flags if flags is None else flags
+        if E_pot is None:
+            E_pot = torch.empty((max(int(n_steps), 1), self.B), dtype=torch.float64, device=self.dev)
+        lp = nn_langevin(float(dt), float(friction), float(kT))
+        nn_md_langevin(self.sys, self.pos, vel, inv_mass, self.nl, self.rc, self.skin, self.params,
+                       self.dmodel.struct, f, lp, noise, n_steps, E_pot, self.F, self.ws)
+        return E_pot
 
     def autotune(self, flags: Optional[int] = None):
         """nn_autotune on the current list (build it first)."""

@@ -62,3 +62,25 @@ def test_host_side_errors(L):
     sysd = nnpot.nn_system(10, 1, None, None, None, None, None)
     n = C.c_int64(0)
     assert L.nn_count_neighbors(C.byref(sysd), 5.0, C.byref(n), None, 0, None) == 1
+
+
+def test_md_host_side_errors(L):
+    """nn_md_langevin rejects bad arguments before any device work."""
+    a = [C.c_void_p(0x1000 * k) for k in range(1, 8)]
+    sysd = nnpot.nn_system(10, 1, a[0].value, a[1].value, a[2].value, a[3].value, a[4].value)
+    pos, vel, im, F, E = a[0], a[5], a[6], a[1], a[2]
+
+    def call(lp, pos_=pos, noise=None, n_steps=3, flags=0):
+        return L.nn_md_langevin(C.byref(sysd), pos_, vel, im, None, 5.0, 0.0, None, None, flags,
+                                None if lp is None else C.byref(lp), noise, n_steps, E, F, None, 0, None)
+
+    assert call(None) == 1 and "NULL" in nnpot.nn_last_error()
+    assert call(nnpot.nn_langevin(0.0, 0.0, 0.0)) == 1           # dt must be > 0
+    assert call(nnpot.nn_langevin(0.5, -1.0, 0.0)) == 1          # negative friction
+    assert call(nnpot.nn_langevin(0.5, 0.0, 0.0), n_steps=-1) == 1
+    assert call(nnpot.nn_langevin(0.5, 0.0, 0.0), flags=nnpot.NN_STORE_JACOBIAN) == 1
+    assert call(nnpot.nn_langevin(0.5, 0.0, 0.0), pos_=a[3]) == 1  # not the buffer sys->pos points at
+    assert "sys->pos" in nnpot.nn_last_error()
+    assert call(nnpot.nn_langevin(0.5, 0.01, 0.025)) == 1       # friction > 0 needs noise
+    assert "noise" in nnpot.nn_last_error()
+    assert call(nnpot.nn_langevin(0.5, 0.01, 0.025), n_steps=0, noise=a[4]) == 0  # nothing to do
