@@ -11,10 +11,10 @@
 //   radial: lane k owns radial bin k and sums over the neighbors of each
 //   species segment;
 //   angular: for every unordered species pair block (a <= b) the block's
-//   triplets are dealt to lanes 64 at a time; each lane accumulates the
-//   separable product  A_p(theta) * R_q(r_avg) * 2 fc fc  into n_theta x
-//   n_rs_ang registers, and a transposing butterfly over the wave leaves one
-//   summed bin per lane.
+//   triplets are taken 64 at a time; the bins are the sum over triplets of
+//   the separable outer product  A_p(theta) * R_q(r_avg) * 2 fc fc, which
+//   runs on the 4x4x1 FP32 MFMA (each lane forms one triplet's geometry, then
+//   four lanes share a triplet and supply its angle and radius factors).
 //
 // Adjoint (forces, Sec. II: forces are derivatives of the energy): given
 // lambda_i = dE_i/dG_i, produce dE_i/dd_e for every neighbor entry e.
@@ -31,6 +31,8 @@
 #include "common.h"
 
 namespace nnp {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 struct AtomNb {
   float4 d[kMaxNb];   // unit vector d/r (x, y, z), r (hi)
@@ -230,10 +232,6 @@ __device__ __forceinline__ int pair_block(int S, int a, int b) {
   return a * S - a * (a - 1) / 2 + (b - a);
 }
 
-__device__ __forceinline__ int bitrev(int v, int bits) {
-  return bits == 0 ? 0 : (int)(__builtin_bitreverse32((unsigned)v) >> (32 - bits));
-}
-
 // Angle terms of one triplet from the two unit vectors: cos(theta), the
 // smoothed sine sqrt(sin^2 + eps), and the average radius as hi (exact half
 // of a rounded sum) + lo (the rounding error of that sum plus the lo parts).
@@ -261,30 +259,6 @@ __device__ __forceinline__ TripGeom triplet_geom(const float4& u, const float4& 
   return t;
 }
 
-// Transposing butterfly: on entry every lane holds NB partial sums; on exit
-// lane l holds, in v[r] (r < max(1, NB/64)), the wave-wide sum of bin
-// (bitrev_S(l mod 2^S) << (L - S)) + r, with L = log2 NB and S = min(L, 6).
-template <int NB>
-__device__ __forceinline__ void butterfly(float (&v)[NB]) {
-  constexpr int L = __builtin_ctz(NB);
-  constexpr int S = L < 6 ? L : 6;
-  const int lane = threadIdx.x;
-#pragma unroll
-  for (int st = 0; st < S; ++st) {
-    const int half = NB >> (st + 1);
-    const bool up = (lane >> st) & 1;
-#pragma unroll
-    for (int t = 0; t < half; ++t) {
-      float lo = v[t], hi = v[t + half];
-      float send = up ? lo : hi;
-      float keep = up ? hi : lo;
-      v[t] = keep + __shfl_xor(send, 1 << st);
-    }
-  }
-#pragma unroll
-  for (int m = 1 << S; m < 64; m <<= 1) v[0] += __shfl_xor(v[0], m);
-}
-
 template <int NT, int NRA, int WPA, int ZC>
 __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ nbr,
@@ -303,6 +277,8 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   }
   // per-wave partial sums (radial bins: S * n_rad <= 512; angular block: NB)
   __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
+  __shared__ float4 tgeo[WPA][kWave];  // per chunk: cos, smoothed sine, average radius (hi, lo)
+  __shared__ float tf2[WPA][kWave];    // and 2 fc fc
   const int64_t i = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Gi = G + i * (int64_t)P.D;
@@ -347,15 +323,36 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
       __syncthreads();
     }
   }
-  // angular blocks
+  // angular blocks: the bins are a sum over triplets of the outer product
+  // A_p R_q F2, taken on the 4x4x1 FP32 MFMA (16 blocks of 4 lanes, block b
+  // = lanes 4b..4b+3; lane 4b+i gives row i of A and column i of B, and
+  // register r of lane 4b+j accumulates C_b[r][j]).  Per chunk of 64 triplets
+  // each lane first forms one triplet's geometry into LDS; then each 4-lane
+  // block takes one triplet of every group of 16 and its lane i supplies
+  // A_(4P+i) and R_(4Q+i) F2.  The 16 blocks' sums are added at the end.
   const int ang0 = P.n_rad * S;
+  constexpr int NP = NT / 4, NQ = NRA / 4;
+  const int li = lane & 3, blk = lane >> 2;
+  float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    xa[u] = P.x_a[4 * u + li];
+    xb[u] = P.x_b[4 * u + li];
+  }
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    rsq[u] = P.rs_ang[4 * u + li];
+    rsq_lo[u] = P.rs_ang_lo[4 * u + li];
+  }
   for (int a = 0; a < S; ++a) {
     for (int b = a; b < S; ++b) {
       const int na = nb.seg[a + 1] - nb.seg[a], nbb = nb.seg[b + 1] - nb.seg[b];
       const int T = (a == b) ? na * (na - 1) / 2 : na * nbb;
-      float acc[NB];
+      floatx4 acc[NP][NQ];
 #pragma unroll
-      for (int t = 0; t < NB; ++t) acc[t] = 0.f;
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
       // a == b: the unordered pairs {j, (j + s) mod na}, s = 1 .. na/2 (for
       // even na the last step only for j < na/2), numbered t = (s - 1) na + j;
       // a < b: every (j, k) of the two segments, t = j nbb + k
@@ -363,6 +360,8 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
       const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
       for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
         const int t = t0 + lane;
+        float4 geo = make_float4(1.f, 0.f, 0.f, 0.f);
+        float F2 = 0.f;  // zero past the block's triplets: such rows add nothing
         if (t < T) {
           int q, r, j, k;
           divmod_small(t, m, inv_m, q, r);
@@ -375,35 +374,61 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
             j = nb.seg[a] + q;
             k = nb.seg[b] + r;
           }
-          const float4 u = nb.d[j], v = nb.d[k];
           const float4 fu = nb.f[j], fv = nb.f[k];
-          const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
-          const float F2 = 2.0f * fu.x * fv.x;
-          float x[NT], A[NT];
+          const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
+          geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
+          F2 = 2.0f * fu.x * fv.x;
+        }
+        tgeo[wv][lane] = geo;
+        tf2[wv][lane] = F2;
+        wave_lds_sync();
+        const int ng = (min(T - t0, kWave) + 15) >> 4;  // groups of 16 triplets holding any of the block's
+        for (int gi = 0; gi < ng; ++gi) {
+          const float4 q4 = tgeo[wv][16 * gi + blk];
+          const float f2 = tf2[wv][16 * gi + blk];
+          float x[NP], A[NP], R[NQ];
 #pragma unroll
-          for (int p = 0; p < NT; ++p) x[p] = fmaf(g.c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
-          ipow_sel<ZC, NT>(x, P.zeta, A);
+          for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+          ipow_sel<ZC, NP>(x, P.zeta, A);
 #pragma unroll
-          for (int q = 0; q < NRA; ++q) {
-            const float dq = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
-            const float R = fexp2(-eta_a2 * dq * dq) * F2;
-#pragma unroll
-            for (int p = 0; p < NT; ++p) acc[q * NT + p] = fmaf(A[p], R, acc[q * NT + p]);
+          for (int v = 0; v < NQ; ++v) {
+            const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
+            R[v] = fexp2(-eta_a2 * dq * dq) * f2;
           }
-        }
-      }
-      butterfly<NB>(acc);
-      constexpr int L = __builtin_ctz(NB);
-      constexpr int SS = L < 6 ? L : 6;
-      constexpr int PER = NB >> SS;
-      float* out = Gi + ang0 + pair_block(S, a, b) * NB;
-      if (lane < (1 << SS)) {
-        const int base = bitrev(lane, SS) << (L - SS);
 #pragma unroll
-        for (int r = 0; r < PER; ++r) {
-          if constexpr (WPA == 1) out[base + r] = acc[r];
-          else xch[wv * NB + base + r] = acc[r];
+          for (int u = 0; u < NP; ++u)
+#pragma unroll
+            for (int v = 0; v < NQ; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[u], R[v], acc[u][v], 0, 0, 0);
         }
+        wave_lds_sync();  // this chunk's reads are done before the next chunk's writes
+      }
+      // sum over the 16 blocks (lanes of equal lane mod 4); lanes 0..3 then
+      // hold bin (p = 4u + r, q = 4v + lane)
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float y = acc[u][v][r];
+            y += __shfl_xor(y, 4);
+            y += __shfl_xor(y, 8);
+            y += __shfl_xor(y, 16);
+            y += __shfl_xor(y, 32);
+            acc[u][v][r] = y;
+          }
+      float* out = Gi + ang0 + pair_block(S, a, b) * NB;
+      if (lane < 4) {
+#pragma unroll
+        for (int u = 0; u < NP; ++u)
+#pragma unroll
+          for (int v = 0; v < NQ; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int bin = (4 * v + lane) * NT + 4 * u + r;
+              if constexpr (WPA == 1) out[bin] = acc[u][v][r];
+              else xch[wv * NB + bin] = acc[u][v][r];
+            }
       }
       if constexpr (WPA > 1) {
         __syncthreads();
@@ -438,6 +463,8 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
   __shared__ AtomNb nb;
   __shared__ float4 tw[kMaxNb];  // per neighbor: (v_j - v_i) / r, and r_dot
   __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
+  __shared__ float4 tgeo[WPA][kWave], tdot[WPA][kWave];  // per chunk: geometry; F2, zeta cos_dot, zeta ssm_dot, F2_dot
+  __shared__ float tg2[WPA][kWave];                      // and -2 eta r_dot F2
   const int64_t i = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Ui = U + i * (int64_t)P.D;
@@ -495,20 +522,42 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
       __syncthreads();
     }
   }
+  // angular blocks: the tangent bins are the sum over triplets of
+  // A_dot_p (R_q F2) + A_p R_q (F2_dot - 2 eta dq r_dot F2), two outer
+  // products per triplet on the 4x4x1 FP32 MFMA, with the same lane roles as
+  // the forward pass (one triplet's geometry and tangents per lane into LDS,
+  // then four lanes per triplet supply its factors)
   const int ang0 = P.n_rad * S;
   const int zeta1 = P.zeta - 1;
   const float zf = (float)P.zeta;
+  constexpr int NP = NT / 4, NQ = NRA / 4;
+  const int li = lane & 3, blk = lane >> 2;
+  float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    xa[u] = P.x_a[4 * u + li];
+    xb[u] = P.x_b[4 * u + li];
+  }
+#pragma unroll
+  for (int u = 0; u < NQ; ++u) {
+    rsq[u] = P.rs_ang[4 * u + li];
+    rsq_lo[u] = P.rs_ang_lo[4 * u + li];
+  }
   for (int a = 0; a < S; ++a) {
     for (int b = a; b < S; ++b) {
       const int na = nb.seg[a + 1] - nb.seg[a], nbb = nb.seg[b + 1] - nb.seg[b];
       const int T = (a == b) ? na * (na - 1) / 2 : na * nbb;
-      float acc[NB];
+      floatx4 acc[NP][NQ];
 #pragma unroll
-      for (int t = 0; t < NB; ++t) acc[t] = 0.f;
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
       const int m = (a == b) ? na : nbb;
       const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
       for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
         const int t = t0 + lane;
+        float4 geo = make_float4(1.f, 0.f, 0.f, 0.f), dot = make_float4(0.f, 0.f, 0.f, 0.f);
+        float g2 = 0.f;  // all zero past the block's triplets: such rows add nothing
         if (t < T) {
           int q, r, j, k;
           divmod_small(t, m, inv_m, q, r);
@@ -531,38 +580,70 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
           const float F2 = 2.0f * fu.x * fv.x;
           const float F2dot = 2.0f * fmaf(fu.y * wj.w, fv.x, fu.x * fv.y * wk.w);
           const float rbdot = 0.5f * (wj.w + wk.w);
-          float x[NT], P1[NT], A[NT], Ad[NT];
+          geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
+          dot = make_float4(F2, zf * cdot, zf * sdot, F2dot);
+          g2 = -2.0f * P.eta_ang * rbdot * F2;
+        }
+        tgeo[wv][lane] = geo;
+        tdot[wv][lane] = dot;
+        tg2[wv][lane] = g2;
+        wave_lds_sync();
+        const int ng = (min(T - t0, kWave) + 15) >> 4;
+        for (int gi = 0; gi < ng; ++gi) {
+          const float4 q4 = tgeo[wv][16 * gi + blk];
+          const float4 d4 = tdot[wv][16 * gi + blk];
+          const float h2 = tg2[wv][16 * gi + blk];
+          float x[NP], P1[NP], A[NP], Ad[NP], RF[NQ], RT[NQ];
 #pragma unroll
-          for (int p = 0; p < NT; ++p) x[p] = fmaf(g.c, P.x_a[p], fmaf(g.ssm, P.x_b[p], P.x_c));
-          ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
+          for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+          ipow_sel<(ZC > 0 ? ZC - 1 : 0), NP>(x, zeta1, P1);
 #pragma unroll
-          for (int p = 0; p < NT; ++p) {
-            A[p] = P1[p] * x[p];
-            Ad[p] = zf * P1[p] * fmaf(P.x_a[p], cdot, P.x_b[p] * sdot);
+          for (int u = 0; u < NP; ++u) {
+            A[u] = P1[u] * x[u];
+            Ad[u] = P1[u] * fmaf(xa[u], d4.y, xb[u] * d4.z);
           }
 #pragma unroll
-          for (int q = 0; q < NRA; ++q) {
-            const float dq = (g.rbar - P.rs_ang[q]) + (g.rbar_lo - P.rs_ang_lo[q]);
+          for (int v = 0; v < NQ; ++v) {
+            const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
             const float R = fexp2(-eta_a2 * dq * dq);
-            const float RF = R * F2;
-            const float RT = R * fmaf(-2.0f * P.eta_ang * dq * rbdot, F2, F2dot);
-#pragma unroll
-            for (int p = 0; p < NT; ++p) acc[q * NT + p] = fmaf(Ad[p], RF, fmaf(A[p], RT, acc[q * NT + p]));
+            RF[v] = R * d4.x;
+            RT[v] = R * fmaf(h2, dq, d4.w);
           }
-        }
-      }
-      butterfly<NB>(acc);
-      constexpr int L = __builtin_ctz(NB);
-      constexpr int SS = L < 6 ? L : 6;
-      constexpr int PER = NB >> SS;
-      float* out = Ui + ang0 + pair_block(S, a, b) * NB;
-      if (lane < (1 << SS)) {
-        const int base = bitrev(lane, SS) << (L - SS);
 #pragma unroll
-        for (int r = 0; r < PER; ++r) {
-          if constexpr (WPA == 1) out[base + r] = acc[r];
-          else xch[wv * NB + base + r] = acc[r];
+          for (int u = 0; u < NP; ++u)
+#pragma unroll
+            for (int v = 0; v < NQ; ++v) {
+              acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ad[u], RF[v], acc[u][v], 0, 0, 0);
+              acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[u], RT[v], acc[u][v], 0, 0, 0);
+            }
         }
+        wave_lds_sync();
+      }
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float y = acc[u][v][r];
+            y += __shfl_xor(y, 4);
+            y += __shfl_xor(y, 8);
+            y += __shfl_xor(y, 16);
+            y += __shfl_xor(y, 32);
+            acc[u][v][r] = y;
+          }
+      float* out = Ui + ang0 + pair_block(S, a, b) * NB;
+      if (lane < 4) {
+#pragma unroll
+        for (int u = 0; u < NP; ++u)
+#pragma unroll
+          for (int v = 0; v < NQ; ++v)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int bin = (4 * v + lane) * NT + 4 * u + r;
+              if constexpr (WPA == 1) out[bin] = acc[u][v][r];
+              else xch[wv * NB + bin] = acc[u][v][r];
+            }
       }
       if constexpr (WPA > 1) {
         __syncthreads();
