@@ -52,7 +52,8 @@ class _Params(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("rc", C.c_double), ("n_rad", C.c_int32),
                 ("eta_rad", C.c_double), ("rs_rad", C.c_void_p), ("n_theta", C.c_int32),
                 ("theta_s", C.c_void_p), ("n_rs_ang", C.c_int32), ("eta_ang", C.c_double),
-                ("rs_ang", C.c_void_p), ("zeta", C.c_double), ("eps", C.c_double)]
+                ("rs_ang", C.c_void_p), ("zeta", C.c_double), ("eps", C.c_double),
+                ("kind", C.c_int32), ("bp_zeta", C.c_void_p), ("bp_lambda", C.c_void_p), ("bp_eta", C.c_void_p)]
 
 
 class _Model(C.Structure):
@@ -124,11 +125,19 @@ def _c_system(sys, keep):
 
 
 def _c_params(p, keep):
+    """Descriptor parameters; p.kind = 1 selects the standard BP angular term
+    with per-term p.bp_zeta, p.bp_lambda (n_theta of them) and p.bp_eta
+    (n_rs_ang of them)."""
     rs_rad = keep(p.rs_rad, np.float64)
+    kind = int(getattr(p, "kind", 0))
+    if kind == 1:
+        bz, bl, be = keep(p.bp_zeta, np.float64), keep(p.bp_lambda, np.float64), keep(p.bp_eta, np.float64)
+        return _Params(p.n_species, p.rc, rs_rad.size, p.eta_rad, _ptr(rs_rad), bz.size, None, be.size, 0.0, None,
+                       0.0, 0.0, 1, _ptr(bz), _ptr(bl), _ptr(be))
     th = keep(p.theta_s, np.float64)
     rs_ang = keep(p.rs_ang, np.float64)
     return _Params(p.n_species, p.rc, rs_rad.size, p.eta_rad, _ptr(rs_rad), th.size, _ptr(th),
-                   rs_ang.size, p.eta_ang, _ptr(rs_ang), p.zeta, p.eps)
+                   rs_ang.size, p.eta_ang, _ptr(rs_ang), p.zeta, p.eps, 0, None, None, None)
 
 
 def _c_model(model, keep):
@@ -197,7 +206,7 @@ def descriptors(params, sys, nl, jacobian=False):
     """G[n_rows][D] (and dG[nnz][D][3] = dG_row/d(d_e) if jacobian)."""
     keep = _Keep()
     cp, cs, cn = _c_params(params, keep), _c_system(sys, keep), _c_nlist(nl, keep)
-    D = descriptor_dim(params.n_species, len(params.rs_rad), len(params.theta_s), len(params.rs_ang))
+    D = descriptor_dim(params.n_species, params.n_rad, params.n_theta, params.n_rs_ang)
     n_rows = len(nl["offsets"]) - 1
     G = np.zeros((n_rows, D))
     dG = np.zeros((len(nl["nbr"]), D, 3)) if jacobian else None

@@ -37,6 +37,10 @@
  *     / (1 + sqrt(1 + eps)),
  * summed over unordered neighbor pairs.  At eps = 0 this is the published
  * ANI modified angular function 2^(1-zeta) (1 + cos(theta - theta_s))^zeta.
+ * The standard BP angular term (Sec. II.A names both; Behler and Parrinello's
+ * definition) is also provided: for every ordered pair of neighbors (j, k),
+ * 2^(1-zeta_p) (1 + lambda_p cos(theta))^zeta_p
+ *   exp(-eta_q (r_ij^2 + r_ik^2 + r_jk^2)) fc(r_ij) fc(r_ik) fc(r_jk).
  * Numerical identity with PANNA's own code is parity unpinned (no PANNA
  * code or data is available); every other function below is pinned by the
  * CPU tests (closed forms, invariances, finite differences, brute force,
@@ -89,6 +93,10 @@ typedef struct {
     const double *rs_ang;    /* [n_rs_ang] */
     double zeta;
     double eps;
+    int32_t kind;            /* 0: mBP angular term; 1: standard BP angular term */
+    const double *bp_zeta;   /* [n_theta]  BP: exponent of angle term p        */
+    const double *bp_lambda; /* [n_theta]  BP: +1 or -1                        */
+    const double *bp_eta;    /* [n_rs_ang] BP: width of radius term q, 1/A^2   */
 } ref_params;
 
 /* Per-species dense MLP.  arch[s*(REF_MAX_LAYERS+1) + l] = width of layer l
@@ -474,6 +482,68 @@ static double cutoff_deriv(double r, double rc) {
     return -0.5 * M_PI / rc * sin(M_PI * r / rc);
 }
 
+/* Standard BP angular part of one atom (kind 1), added to G (and dG, same
+ * layout as atom_descriptor): bin (q, p) of the species pair block of (e, f)
+ * sums, over every ordered pair of distinct neighbors e, f inside rc,
+ *   T = 2^(1 - zeta_p) (1 + lambda_p cos(theta))^zeta_p
+ *       exp(-eta_q (r_e^2 + r_f^2 + r_ef^2)) fc(r_e) fc(r_f) fc(r_ef),
+ * with r_ef = |d_f - d_e|.                                                   */
+static void bp_angular(const ref_params *P, int64_t n_e, const double (*d)[3], const int32_t *sp,
+                       const double *r, double *G, double *dG) {
+    const int S = P->n_species;
+    const int64_t ang0 = (int64_t)P->n_rad * S;
+    const int64_t nbins = (int64_t)P->n_theta * P->n_rs_ang;
+    const double rc = P->rc;
+    for (int64_t e = 0; e < n_e; ++e) {
+        if (!(r[e] < rc)) continue;
+        for (int64_t f = 0; f < n_e; ++f) {
+            if (f == e || !(r[f] < rc)) continue;
+            const double *u = d[e], *v = d[f];
+            const double ru = r[e], rv = r[f];
+            const double w[3] = {v[0] - u[0], v[1] - u[1], v[2] - u[2]};  /* d_f - d_e */
+            const double rw = sqrt(norm2(w));
+            double uv = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+            double cos_t = uv / (ru * rv);
+            double s2 = ru * ru + rv * rv + rw * rw;
+            double fu = cutoff_fn(ru, rc), fv = cutoff_fn(rv, rc), fw = cutoff_fn(rw, rc);
+            double dfu = cutoff_deriv(ru, rc), dfv = cutoff_deriv(rv, rc), dfw = cutoff_deriv(rw, rc);
+            double F = fu * fv * fw;
+            int64_t blk = ang0 + pair_block(S, sp[e], sp[f]) * nbins;
+            /* gradients of cos(theta), s2 and F with respect to d_e and d_f */
+            double dcos_du[3], dcos_dv[3], ds2_du[3], ds2_dv[3], dF_du[3], dF_dv[3];
+            for (int c = 0; c < 3; ++c) {
+                dcos_du[c] = v[c] / (ru * rv) - cos_t * u[c] / (ru * ru);
+                dcos_dv[c] = u[c] / (ru * rv) - cos_t * v[c] / (rv * rv);
+                ds2_du[c] = 2.0 * u[c] - 2.0 * w[c];
+                ds2_dv[c] = 2.0 * v[c] + 2.0 * w[c];
+                double dw_term = (rw > 0.0) ? fu * fv * dfw * w[c] / rw : 0.0;
+                dF_du[c] = dfu * u[c] / ru * fv * fw - dw_term;
+                dF_dv[c] = fu * dfv * v[c] / rv * fw + dw_term;
+            }
+            for (int q = 0; q < P->n_rs_ang; ++q) {
+                double R = exp(-P->bp_eta[q] * s2);
+                double dR_ds2 = -P->bp_eta[q] * R;
+                for (int p = 0; p < P->n_theta; ++p) {
+                    double z = P->bp_zeta[p], lam = P->bp_lambda[p];
+                    double base = 1.0 + lam * cos_t;
+                    double A = pow(2.0, 1.0 - z) * pow(base, z);
+                    int64_t idx = blk + (int64_t)q * P->n_theta + p;
+                    G[idx] += A * R * F;
+                    if (dG) {
+                        double dA_dcos = pow(2.0, 1.0 - z) * z * lam * pow(base, z - 1.0);
+                        for (int c = 0; c < 3; ++c) {
+                            dG[(idx * n_e + e) * 3 + c] +=
+                                dA_dcos * dcos_du[c] * R * F + A * dR_ds2 * ds2_du[c] * F + A * R * dF_du[c];
+                            dG[(idx * n_e + f) * 3 + c] +=
+                                dA_dcos * dcos_dv[c] * R * F + A * dR_ds2 * ds2_dv[c] * F + A * R * dF_dv[c];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
 /* Descriptor of one atom from its neighbor displacements d[e] (only entries
  * with r < rc contribute) and neighbor species sp[e].  Writes G[D]; when
  * dG != NULL also writes dG[(d * n_e + e) * 3 + k] = dG_d / d(d_e)_k.
@@ -515,6 +585,12 @@ static void atom_descriptor(const ref_params *P, int64_t n_e, const double (*d)[
                 for (int c = 0; c < 3; ++c) dG[(idx * n_e + e) * 3 + c] += dval_dr * d[e][c] / r[e];
             }
         }
+    }
+
+    if (P->kind == 1) {
+        bp_angular(P, n_e, d, sp, r, G, dG);
+        free(r);
+        return;
     }
 
     /* angular part */

@@ -53,6 +53,14 @@ class MBPParams:
     rs_ang: np.ndarray
     zeta: float = 50.0
     eps: float = 1e-3
+    # kind 1: the standard BP angular term instead of mBP, with per angle
+    # term p an integer exponent bp_zeta[p] and sign bp_lambda[p], and per
+    # radius term q a width bp_eta[q] (theta_s, rs_ang, eta_ang, zeta, eps
+    # are then unused)
+    kind: int = 0
+    bp_zeta: np.ndarray = None
+    bp_lambda: np.ndarray = None
+    bp_eta: np.ndarray = None
 
     @property
     def n_rad(self) -> int:
@@ -60,11 +68,11 @@ class MBPParams:
 
     @property
     def n_theta(self) -> int:
-        return int(len(self.theta_s))
+        return int(len(self.bp_zeta) if self.kind == 1 else len(self.theta_s))
 
     @property
     def n_rs_ang(self) -> int:
-        return int(len(self.rs_ang))
+        return int(len(self.bp_eta) if self.kind == 1 else len(self.rs_ang))
 
     @property
     def dim(self) -> int:
@@ -95,6 +103,19 @@ def mbp_params(n_species, rc, n_rad, n_theta, n_rs_ang, eta_rad=16.0, eta_ang=12
         n_species=n_species, rc=float(rc), eta_rad=float(eta_rad),
         rs_rad=np.linspace(r_min, rc, n_rad), theta_s=(np.arange(n_theta) + 0.5) * np.pi / n_theta,
         eta_ang=float(eta_ang), rs_ang=np.linspace(r_min, rc, n_rs_ang), zeta=float(zeta), eps=float(eps))
+
+
+def bp_params(n_species, rc, n_rad, zetas=(1, 2, 4, 16), etas=(0.005, 0.02, 0.06, 0.15), eta_rad=16.0,
+              r_min=0.5) -> MBPParams:
+    """Standard BP descriptor: the mBP radial part (same grid rule) and angular
+    terms for every zeta in `zetas` with lambda = +1 and -1 (p = 2 z + l) and
+    every radius width in `etas` (1/A^2)."""
+    zl = [(float(z), lam) for z in zetas for lam in (1.0, -1.0)]
+    return MBPParams(
+        n_species=n_species, rc=float(rc), eta_rad=float(eta_rad), rs_rad=np.linspace(r_min, rc, n_rad),
+        theta_s=np.zeros(0), eta_ang=0.0, rs_ang=np.zeros(0), zeta=0.0, eps=0.0, kind=1,
+        bp_zeta=np.array([z for z, _ in zl]), bp_lambda=np.array([l for _, l in zl]),
+        bp_eta=np.asarray(etas, np.float64))
 
 
 def random_model(n_species, D, hidden: Sequence[int], seed, act="gaussian", in_scale=1.0) -> Model:

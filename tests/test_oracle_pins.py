@@ -592,3 +592,85 @@ def test_md_velocity_verlet_energy_error_is_second_order(O):
 
     d1, d2 = worst(0.4), worst(0.2)
     assert 3.0 < d1 / d2 < 5.0, (d1, d2)
+
+
+# ---------------------------------------------------------------------------
+# the standard BP angular term (Sec. II.A names BP beside mBP)
+# ---------------------------------------------------------------------------
+
+def small_bp(S=2, rc=3.8):
+    return synth.bp_params(S, rc, 6, zetas=(1, 2, 5), etas=(0.05, 0.3), eta_rad=4.0)
+
+
+@pytest.mark.parametrize("theta,r2", [(np.pi / 2, 2.6), (2.2, 2.6), (0.6, 1.9), (2.9, 3.2)])
+def test_bp_angular_three_atoms_textbook_form(O, theta, r2):
+    """Behler's angular function summed over ordered neighbor pairs:
+    G = 2^(1-zeta) sum_(j != k) (1 + lambda cos)^zeta exp(-eta (r_ij^2 + r_ik^2 + r_jk^2)) fc fc fc,
+    with the textbook cutoff 0.5 (1 + cos(pi r / rc)); for three atoms the two
+    orders of (j, k) give equal terms.  The last case has r_jk > rc (no term)."""
+    p = small_bp(S=3)
+    r1 = 1.7
+    pos = np.array([[0, 0, 0], [r1, 0, 0], [r2 * np.cos(theta), r2 * np.sin(theta), 0]])
+    sys = synth.single(pos, [1, 2, 0])           # neighbor species 2 and 0 -> pair block (0, 2)
+    G = O.descriptors(p, sys, O.neighbors_brute(sys, p.rc))[0]
+    S, nb = 3, p.n_theta * p.n_rs_ang
+    blocks = [(a, b) for a in range(S) for b in range(a, S)]
+    off = p.n_rad * S + blocks.index((0, 2)) * nb
+    rjk = np.linalg.norm(pos[2] - pos[1])
+    cos_t = np.cos(theta)
+    ang = 2.0 ** (1 - p.bp_zeta) * (1 + p.bp_lambda * cos_t) ** p.bp_zeta
+    rad = np.exp(-p.bp_eta * (r1 ** 2 + r2 ** 2 + rjk ** 2))
+    fcs = fc_textbook(r1, p.rc) * fc_textbook(r2, p.rc) * fc_textbook(rjk, p.rc)
+    expect = 2.0 * (rad[:, None] * ang[None, :]).ravel() * fcs
+    np.testing.assert_allclose(G[off:off + nb], expect, rtol=1e-12, atol=1e-15)
+    other = np.delete(G[p.n_rad * S:], np.arange(off - p.n_rad * S, off - p.n_rad * S + nb))
+    assert np.all(other == 0.0)
+    if rjk >= p.rc:
+        assert np.all(G[off:off + nb] == 0.0)
+
+
+def test_bp_invariances_and_forces_central_differences(O):
+    rng = np.random.Generator(np.random.PCG64(21))
+    p = small_bp(S=2)
+    m = small_model(p, hidden=(10, 6))
+    for sys in (random_cluster(rng, 9), small_periodic(rng, 8, tric=True, L=4.1)):
+        G0 = O.descriptors(p, sys, O.neighbors_brute(sys, p.rc))
+        scale = np.max(np.abs(G0))
+        R = random_rotation(rng)
+        rsys = synth.System(sys.pos @ R.T + 1.3, sys.species, sys.atom_ptr, sys.cell @ R.T, sys.pbc)
+        np.testing.assert_allclose(O.descriptors(p, rsys, O.neighbors_brute(rsys, p.rc)), G0, rtol=1e-12,
+                                   atol=1e-12 * scale)
+        perm = rng.permutation(sys.n_atoms)
+        psys = synth.System(sys.pos[perm], sys.species[perm], sys.atom_ptr, sys.cell, sys.pbc)
+        np.testing.assert_allclose(O.descriptors(p, psys, O.neighbors_brute(psys, p.rc)), G0[perm], rtol=1e-12,
+                                   atol=1e-12 * scale)
+        _, _, F = O.energy_forces(p, m, sys, O.neighbors_brute(sys, p.rc))
+        h = 1e-5
+        for k in range(sys.n_atoms):
+            for a in range(3):
+                pp = sys.pos.copy(); pp[k, a] += h
+                pm = sys.pos.copy(); pm[k, a] -= h
+                sp = synth.System(pp, sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+                sm = synth.System(pm, sys.species, sys.atom_ptr, sys.cell, sys.pbc)
+                fd = -(total_energy(O, p, m, sp) - total_energy(O, p, m, sm)) / (2 * h)
+                assert abs(fd - F[k, a]) < 1e-6 * max(1.0, abs(F[k, a])), (k, a, fd, F[k, a])
+
+
+def test_bp_jacobian_central_differences(O):
+    rng = np.random.Generator(np.random.PCG64(22))
+    p = small_bp(S=2)
+    sys = random_cluster(rng, 7)
+    nl = O.neighbors_brute(sys, p.rc)
+    G, dG = O.descriptors(p, sys, nl, jacobian=True)
+    assert np.abs(G[:, p.n_rad * 2:]).max() > 0
+    h = 1e-6
+    for r in range(sys.n_atoms):
+        for e in range(nl["offsets"][r], nl["offsets"][r + 1]):
+            j = nl["nbr"][e]
+            for a in range(3):
+                pp = sys.pos.copy(); pp[j, a] += h
+                pm = sys.pos.copy(); pm[j, a] -= h
+                Gp = O.descriptors(p, synth.System(pp, sys.species, sys.atom_ptr, sys.cell, sys.pbc), nl)
+                Gm = O.descriptors(p, synth.System(pm, sys.species, sys.atom_ptr, sys.cell, sys.pbc), nl)
+                fd = (Gp[r] - Gm[r]) / (2 * h)
+                np.testing.assert_allclose(dG[e, :, a], fd, rtol=1e-6, atol=1e-8 * max(1.0, np.abs(G[r]).max()))
