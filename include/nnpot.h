@@ -127,7 +127,19 @@ typedef struct nn_nlist {
  * fastest: D = n_rad*S + n_theta*n_rs_ang*S*(S+1)/2.
  * Limits: S <= 8, n_rad <= 64, (n_theta, n_rs_ang) in {4,8,16} x {4,8} with
  * n_theta*n_rs_ang <= 128, zeta a positive integer <= 1024.
+ *
+ * kind = NN_DESC_BP selects the standard Behler-Parrinello angular term
+ * instead (Sec. II.A names both descriptors):
+ *   angular G[(a,b)][q][p] = sum_{ordered (j,k), j != k: {s_j,s_k}={a,b}}
+ *       2^(1-bp_zeta[p]) (1 + bp_lambda[p] cos(t))^bp_zeta[p]
+ *       exp(-bp_eta[q] (r_ij^2 + r_ik^2 + r_jk^2)) fc(r_ij) fc(r_ik) fc(r_jk),
+ * with n_theta angle terms (bp_zeta integer in [1, 64], bp_lambda +1 or -1)
+ * and n_rs_ang radius terms (bp_eta >= 0, 1/A^2); theta_s, eta_ang, rs_ang,
+ * zeta and eps are then not read.  The radial part, layout and limits are
+ * those above.  With BP the stored Jacobian, nn_descriptor_tangent and the
+ * force term of nn_energy_forces_grad return NN_E_UNSUPPORTED.
  */
+enum { NN_DESC_MBP = 0, NN_DESC_BP = 1 };
 typedef struct nn_mbp_params {
   int32_t n_species;
   double rc;
@@ -141,6 +153,10 @@ typedef struct nn_mbp_params {
   const double* rs_ang;
   double zeta;
   double eps;
+  int32_t kind;             /* NN_DESC_MBP (0) or NN_DESC_BP (1)          */
+  const double* bp_zeta;    /* [n_theta]  BP angle-term exponents          */
+  const double* bp_lambda;  /* [n_theta]  BP angle-term signs              */
+  const double* bp_eta;     /* [n_rs_ang] BP radius-term widths            */
 } nn_mbp_params;
 
 /*

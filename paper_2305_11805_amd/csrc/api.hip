@@ -261,35 +261,60 @@ static nn_status make_desc_const(const nn_mbp_params* p, DescConst* out) {
   if (!desc_supported(p->n_theta, p->n_rs_ang))
     return fail(NN_E_UNSUPPORTED, "angular bins %d x %d not compiled (n_theta in {4,8,16}, n_rs_ang in {4,8})",
                 p->n_theta, p->n_rs_ang);
-  if (!p->rs_rad || !p->theta_s || !p->rs_ang) return fail(NN_E_INVALID, "grid arrays are NULL");
-  if (!(p->zeta >= 1.0 && p->zeta <= 1024.0 && floor(p->zeta) == p->zeta))
-    return fail(NN_E_UNSUPPORTED, "zeta must be an integer in [1, 1024]");
-  if (!(p->eps >= 0.0) || !(p->eta_rad >= 0.0) || !(p->eta_ang >= 0.0))
-    return fail(NN_E_INVALID, "eps and eta must be >= 0");
+  if (p->kind != NN_DESC_MBP && p->kind != NN_DESC_BP) return fail(NN_E_INVALID, "unknown descriptor kind");
+  const bool bp = p->kind == NN_DESC_BP;
+  if (!p->rs_rad) return fail(NN_E_INVALID, "grid arrays are NULL");
+  if (bp) {
+    if (!p->bp_zeta || !p->bp_lambda || !p->bp_eta) return fail(NN_E_INVALID, "BP term arrays are NULL");
+    for (int t = 0; t < p->n_theta; ++t) {
+      const double z = p->bp_zeta[t];
+      if (!(z >= 1.0 && z <= 64.0 && floor(z) == z)) return fail(NN_E_UNSUPPORTED, "BP zeta must be an integer in [1, 64]");
+      if (p->bp_lambda[t] != 1.0 && p->bp_lambda[t] != -1.0) return fail(NN_E_INVALID, "BP lambda must be +1 or -1");
+    }
+    for (int q = 0; q < p->n_rs_ang; ++q)
+      if (!(p->bp_eta[q] >= 0.0) || !isfinite(p->bp_eta[q])) return fail(NN_E_INVALID, "BP eta must be >= 0");
+    if (!(p->eta_rad >= 0.0)) return fail(NN_E_INVALID, "eta must be >= 0");
+  } else {
+    if (!p->theta_s || !p->rs_ang) return fail(NN_E_INVALID, "grid arrays are NULL");
+    if (!(p->zeta >= 1.0 && p->zeta <= 1024.0 && floor(p->zeta) == p->zeta))
+      return fail(NN_E_UNSUPPORTED, "zeta must be an integer in [1, 1024]");
+    if (!(p->eps >= 0.0) || !(p->eta_rad >= 0.0) || !(p->eta_ang >= 0.0))
+      return fail(NN_E_INVALID, "eps and eta must be >= 0");
+  }
   DescConst P{};
   P.S = p->n_species;
   P.n_rad = p->n_rad;
   P.n_theta = p->n_theta;
   P.n_rs_ang = p->n_rs_ang;
   P.D = (int)(p->n_rad * p->n_species + p->n_theta * p->n_rs_ang * p->n_species * (p->n_species + 1) / 2);
-  P.zeta = (int)p->zeta;
+  P.zeta = bp ? 1 : (int)p->zeta;
+  P.kind = p->kind;
   P.rc = (float)p->rc;
   P.eta_rad = (float)p->eta_rad;
   P.eta_ang = (float)p->eta_ang;
   P.eps_ang = (float)p->eps;
   P.pi_over_rc = (float)(M_PI / p->rc);
   P.half_pi_over_rc = (float)(0.5 * M_PI / p->rc);
-  const double norm = 1.0 + sqrt(1.0 + p->eps);
-  for (int t = 0; t < p->n_theta; ++t) {
-    P.x_a[t] = (float)(cos(p->theta_s[t]) / norm);
-    P.x_b[t] = (float)(sin(p->theta_s[t]) / norm);
+  if (bp) {
+    for (int t = 0; t < p->n_theta; ++t) {
+      P.bp_zeta[t] = (int)p->bp_zeta[t];
+      P.bp_lam[t] = (float)p->bp_lambda[t];
+      P.bp_pref[t] = (float)ldexp(1.0, 2 - (int)p->bp_zeta[t]);  // 2 * 2^(1 - zeta): both orders of a pair
+    }
+    for (int q = 0; q < p->n_rs_ang; ++q) P.bp_eta[q] = (float)p->bp_eta[q];
+  } else {
+    const double norm = 1.0 + sqrt(1.0 + p->eps);
+    for (int t = 0; t < p->n_theta; ++t) {
+      P.x_a[t] = (float)(cos(p->theta_s[t]) / norm);
+      P.x_b[t] = (float)(sin(p->theta_s[t]) / norm);
+    }
+    P.x_c = (float)(1.0 / norm);
   }
-  P.x_c = (float)(1.0 / norm);
   for (int k = 0; k < p->n_rad; ++k) {
     P.rs_rad[k] = (float)p->rs_rad[k];
     P.rs_rad_lo[k] = (float)(p->rs_rad[k] - (double)P.rs_rad[k]);
   }
-  for (int q = 0; q < p->n_rs_ang; ++q) {
+  for (int q = 0; q < p->n_rs_ang && !bp; ++q) {
     P.rs_ang[q] = (float)p->rs_ang[q];
     P.rs_ang_lo[q] = (float)(p->rs_ang[q] - (double)P.rs_ang[q]);
   }
@@ -324,7 +349,7 @@ static nn_status check_model(const nn_model* m, const DescConst& P) {
 
 // Floats of the stored Jacobian if these flags and budget ask for it, else 0.
 static size_t jac_request(const DescConst& P, int64_t capacity, int32_t flags, size_t mem_budget) {
-  if (!(flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))) return 0;
+  if (!(flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS)) || P.kind == NN_DESC_BP) return 0;
   const size_t n = jacobian_floats(P.n_rad, P.S, P.n_theta, P.n_rs_ang, capacity);
   return n * sizeof(float) <= mem_budget ? n : 0;
 }
@@ -494,6 +519,7 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if (!G && sys->n_atoms > 0) return fail(NN_E_INVALID, "G is NULL");
+  if (jac && P.kind == NN_DESC_BP) return fail(NN_E_UNSUPPORTED, "no stored Jacobian for the BP angular term");
 
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   (void)ws;
@@ -518,6 +544,7 @@ nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const 
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if ((!v || !U) && sys->n_atoms > 0) return fail(NN_E_INVALID, "v/U is NULL");
+  if (P.kind == NN_DESC_BP) return fail(NN_E_UNSUPPORTED, "no descriptor tangent for the BP angular term");
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   hipStream_t s = (hipStream_t)stream;
   launch_desc_tan(*sys, *nl, P, v, U, plan_default(sys->n_atoms).wpa_fwd, s);
@@ -539,6 +566,8 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     return fail(NN_E_INVALID, "unknown flags");
   if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
     return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
+  if ((flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS)) && P.kind == NN_DESC_BP)
+    return fail(NN_E_UNSUPPORTED, "no stored Jacobian for the BP angular term");
   const int64_t N = sys->n_atoms;
   const size_t jf = jac_request(P, nl->capacity, flags, mem_budget);
   if ((flags & NN_REUSE_DESCRIPTORS) && !jf)
@@ -697,6 +726,7 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   if (!dL_dE && !dL_dF && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE and dL_dF are both NULL");
   if (dL_dpos && dL_dF)
     return fail(NN_E_UNSUPPORTED, "the position gradient of a loss on forces (second derivatives) is not provided");
+  if (dL_dF && P.kind == NN_DESC_BP) return fail(NN_E_UNSUPPORTED, "no force-loss gradient for the BP angular term");
   if (dL_dpos && !dL_dE) return fail(NN_E_INVALID, "dL_dpos needs dL_dE");
   if (dL_dpos && !F) return fail(NN_E_INVALID, "dL_dpos needs the forces F");
   const int64_t N = sys->n_atoms;

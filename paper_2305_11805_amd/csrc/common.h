@@ -50,6 +50,12 @@ struct DescConst {
   float rs_rad[kMaxRad], rs_rad_lo[kMaxRad];   // centre = hi + lo (double-float)
   float rs_ang[kMaxRsAng], rs_ang_lo[kMaxRsAng];
   double rc64, half_pi_over_rc64, pi_over_rc64;
+  // standard BP angular term (kind 1): per angle term p the prefactor
+  // 2 * 2^(1 - zeta_p) (both orders of each neighbor pair), lambda_p and the
+  // integer exponent; per radius term q its width eta_q
+  int32_t kind;
+  float bp_pref[kMaxTheta], bp_lam[kMaxTheta], bp_eta[kMaxRsAng];
+  int32_t bp_zeta[kMaxTheta];
 };
 
 // One species' MLP as seen by the kernels.

@@ -66,10 +66,12 @@ __device__ __forceinline__ int struct_of_atom(const int64_t* atom_ptr, int32_t B
 }
 
 // Stage the neighbors of atom i inside rc into LDS, sorted by species.
-// Entries at r >= rc get a zero pair gradient if pg != nullptr.
+// Entries at r >= rc get a zero pair gradient if pg != nullptr; with d64
+// the FP64 displacements are staged too ([slot][3]).
 __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, const int64_t* __restrict__ offsets,
                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
-                                const DescConst& P, int64_t* meta, float4* __restrict__ pg) {
+                                const DescConst& P, int64_t* meta, float4* __restrict__ pg,
+                                double* d64 = nullptr) {
   // wave 0 does the work; every thread of the block passes the barriers
   const int lane = threadIdx.x & 63;
   const bool w0 = threadIdx.x < 64;
@@ -156,6 +158,11 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       nb.d[slot] = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
       nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
       nb.ir[slot] = (float)ir;
+      if (d64) {
+        d64[3 * slot] = d[0];
+        d64[3 * slot + 1] = d[1];
+        d64[3 * slot + 2] = d[2];
+      }
     }
   }
   __syncthreads();
@@ -259,6 +266,48 @@ __device__ __forceinline__ TripGeom triplet_geom(const float4& u, const float4& 
   return t;
 }
 
+// ZC selects the angular term: a compile-time mBP exponent (50), 0 for a
+// run-time mBP exponent, or kZcBP for the standard BP term.
+constexpr int kZcBP = -1;
+
+// x^e for a run-time e >= 0 (binary exponentiation).
+__device__ __forceinline__ float ipow_rt(float x, int e) {
+  float r = 1.0f;
+  while (e) {
+    if (e & 1) r *= x;
+    x *= x;
+    e >>= 1;
+  }
+  return r;
+}
+
+// Standard BP triplet terms from the two staged neighbors (unit vector,
+// r): cos(theta), s2 = r_ij^2 + r_ik^2 + r_jk^2, the third side w = d_k -
+// d_j and its cutoff fc(r_jk) (with the derivative when DERIV).
+struct BpGeom {
+  float c, s2, wx, wy, wz, rw, fw, dfw;
+};
+template <bool DERIV>
+__device__ __forceinline__ BpGeom bp_geom(const float4& u, const float4& v, const DescConst& P) {
+  BpGeom g;
+  g.c = fmaf(u.x, v.x, fmaf(u.y, v.y, u.z * v.z));
+  g.wx = fmaf(v.w, v.x, -u.w * u.x);
+  g.wy = fmaf(v.w, v.y, -u.w * u.y);
+  g.wz = fmaf(v.w, v.z, -u.w * u.z);
+  const float rw2 = fmaf(g.wx, g.wx, fmaf(g.wy, g.wy, g.wz * g.wz));
+  g.rw = sqrtf(rw2);
+  g.s2 = fmaf(u.w, u.w, fmaf(v.w, v.w, rw2));
+  g.fw = 0.f;
+  g.dfw = 0.f;
+  if (g.rw < P.rc) {
+    float sn, cs;
+    sincosf(P.half_pi_over_rc * (P.rc - g.rw), &sn, &cs);
+    g.fw = sn * sn;  // sin^2(pi (rc - r) / (2 rc))
+    if (DERIV) g.dfw = -2.0f * P.half_pi_over_rc * sn * cs;
+  }
+  return g;
+}
+
 template <int NT, int NRA, int WPA, int ZC>
 __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ nbr,
@@ -279,6 +328,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
   __shared__ float4 tgeo[WPA][kWave];  // per chunk: cos, smoothed sine, average radius (hi, lo)
   __shared__ float tf2[WPA][kWave];    // and 2 fc fc
+  __shared__ double d64[ZC == kZcBP ? 3 * kMaxNb : 1];  // BP: FP64 displacements for the third side
   const int64_t i = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Gi = G + i * (int64_t)P.D;
@@ -286,7 +336,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
     for (int d = tid; d < P.D; d += 64 * WPA) Gi[d] = 0.f;
     return;
   }
-  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr);
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr, ZC == kZcBP ? d64 : nullptr);
   if (nb.bad) {
     for (int d = tid; d < P.D; d += 64 * WPA) Gi[d] = 0.f;
     return;
@@ -333,16 +383,30 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   const int ang0 = P.n_rad * S;
   constexpr int NP = NT / 4, NQ = NRA / 4;
   const int li = lane & 3, blk = lane >> 2;
+  // this lane's angle terms p = 4u + li and radius terms q = 4v + li
   float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
+  int zexp[NP];
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
-    xa[u] = P.x_a[4 * u + li];
-    xb[u] = P.x_b[4 * u + li];
+    if constexpr (ZC == kZcBP) {
+      xa[u] = P.bp_pref[4 * u + li];
+      xb[u] = P.bp_lam[4 * u + li];
+      zexp[u] = P.bp_zeta[4 * u + li];
+    } else {
+      xa[u] = P.x_a[4 * u + li];
+      xb[u] = P.x_b[4 * u + li];
+      zexp[u] = 0;
+    }
   }
 #pragma unroll
   for (int u = 0; u < NQ; ++u) {
-    rsq[u] = P.rs_ang[4 * u + li];
-    rsq_lo[u] = P.rs_ang_lo[4 * u + li];
+    if constexpr (ZC == kZcBP) {
+      rsq[u] = P.bp_eta[4 * u + li] * 1.4426950408889634f;
+      rsq_lo[u] = 0.f;
+    } else {
+      rsq[u] = P.rs_ang[4 * u + li];
+      rsq_lo[u] = P.rs_ang_lo[4 * u + li];
+    }
   }
   for (int a = 0; a < S; ++a) {
     for (int b = a; b < S; ++b) {
@@ -375,9 +439,31 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
             k = nb.seg[b] + r;
           }
           const float4 fu = nb.f[j], fv = nb.f[k];
-          const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
-          geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
-          F2 = 2.0f * fu.x * fv.x;
+          if constexpr (ZC == kZcBP) {
+            // 1 + cos and 1 - cos as |u^ +- v^|^2 / 2 (no cancellation near
+            // cos = -+1); the third side from the FP64 displacements, with
+            // rc - r_jk = (rc^2 - r_jk^2) / (rc + r_jk), so that its cutoff
+            // keeps its relative precision up to rc
+            const float4 u = nb.d[j], v = nb.d[k];
+            const float px = u.x + v.x, py = u.y + v.y, pz = u.z + v.z;
+            const float mx = u.x - v.x, my = u.y - v.y, mz = u.z - v.z;
+            const double wx = d64[3 * k] - d64[3 * j], wy = d64[3 * k + 1] - d64[3 * j + 1],
+                         wz = d64[3 * k + 2] - d64[3 * j + 2];
+            const double rw2 = fma(wx, wx, fma(wy, wy, wz * wz));
+            float fw = 0.f;
+            if (rw2 < P.rc64 * P.rc64) {
+              const float rw = sqrtf((float)rw2);
+              const float sn = sinf(P.half_pi_over_rc * ((float)(fma(P.rc64, P.rc64, -rw2)) / (P.rc + rw)));
+              fw = sn * sn;
+            }
+            geo = make_float4(0.5f * fmaf(px, px, fmaf(py, py, pz * pz)), 0.5f * fmaf(mx, mx, fmaf(my, my, mz * mz)),
+                              fmaf(u.w, u.w, fmaf(v.w, v.w, (float)rw2)), 0.f);
+            F2 = fu.x * fv.x * fw;  // three cutoffs
+          } else {
+            const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
+            geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
+            F2 = 2.0f * fu.x * fv.x;
+          }
         }
         tgeo[wv][lane] = geo;
         tf2[wv][lane] = F2;
@@ -386,14 +472,23 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
         for (int gi = 0; gi < ng; ++gi) {
           const float4 q4 = tgeo[wv][16 * gi + blk];
           const float f2 = tf2[wv][16 * gi + blk];
-          float x[NP], A[NP], R[NQ];
+          float A[NP], R[NQ];
+          if constexpr (ZC == kZcBP) {
+            // 2^(2 - zeta) (1 + lambda cos)^zeta and exp(-eta s2) fc fc fc
 #pragma unroll
-          for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
-          ipow_sel<ZC, NP>(x, P.zeta, A);
+            for (int u = 0; u < NP; ++u) A[u] = xa[u] * ipow_rt(xb[u] > 0.f ? q4.x : q4.y, zexp[u]);
 #pragma unroll
-          for (int v = 0; v < NQ; ++v) {
-            const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
-            R[v] = fexp2(-eta_a2 * dq * dq) * f2;
+            for (int v = 0; v < NQ; ++v) R[v] = fexp2(-rsq[v] * q4.z) * f2;
+          } else {
+            float x[NP];
+#pragma unroll
+            for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+            ipow_sel<(ZC > 0 ? ZC : 0), NP>(x, P.zeta, A);
+#pragma unroll
+            for (int v = 0; v < NQ; ++v) {
+              const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
+              R[v] = fexp2(-eta_a2 * dq * dq) * f2;
+            }
           }
 #pragma unroll
           for (int u = 0; u < NP; ++u)
@@ -737,7 +832,61 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
     int k = j + sj_step;
     if (k >= n) k -= n;
     float gjx = 0.f, gjy = 0.f, gjz = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
-    if (take) {
+    if (take && ZC == kZcBP) {
+      // standard BP: E_t = F3 sum_q R_q T_q with R_q = exp(-eta_q s2),
+      // T_q = sum_p lambda_qp A_p, A_p = pref_p (1 + lam_p cos)^zeta_p
+      const float4 u = nb.d[j], fu = nb.f[j];
+      const float4 v = nb.d[k], fv = nb.f[k];
+      const float* La = lam_a;
+      if (!ONE_SPECIES) La = lam_a + pair_block(S, nb_species(fu), nb_species(fv)) * NBP;
+      const BpGeom g = bp_geom<true>(u, v, P);
+      float P1[NT], A[NT], R[NRA];
+#pragma unroll
+      for (int p = 0; p < NT; ++p) {
+        const float base = fmaf(P.bp_lam[p], g.c, 1.0f);
+        P1[p] = ipow_rt(base, P.bp_zeta[p] - 1);
+        A[p] = P.bp_pref[p] * P1[p] * base;
+      }
+#pragma unroll
+      for (int q = 0; q < NRA; ++q) R[q] = fexp2(-P.bp_eta[q] * 1.4426950408889634f * g.s2);
+      float Tq[NRA], U[NT];
+#pragma unroll
+      for (int p = 0; p < NT; ++p) U[p] = 0.f;
+#pragma unroll
+      for (int q = 0; q < NRA; ++q) {
+        float tq = 0.f;
+#pragma unroll
+        for (int p = 0; p < NT; ++p) {
+          const float l = La[q * NT + p];
+          tq = fmaf(l, A[p], tq);
+          U[p] = fmaf(l, R[q], U[p]);
+        }
+        Tq[q] = tq;
+      }
+      float sRT = 0.f, sERT = 0.f;
+#pragma unroll
+      for (int q = 0; q < NRA; ++q) {
+        sRT = fmaf(Tq[q], R[q], sRT);
+        sERT = fmaf(Tq[q] * R[q], P.bp_eta[q], sERT);
+      }
+      float dEdc = 0.f;
+#pragma unroll
+      for (int p = 0; p < NT; ++p) dEdc = fmaf(U[p] * P1[p], P.bp_pref[p] * (float)P.bp_zeta[p] * P.bp_lam[p], dEdc);
+      const float F3 = fu.x * fv.x * g.fw;
+      dEdc *= F3;
+      const float two_ds2 = -2.0f * F3 * sERT;  // 2 dE/ds2
+      // d cos / d d_j = (v^ - cos u^) / r_j;  d s2 / d d_j = 2 d_j - 2 w, d s2 / d d_k = 2 d_k + 2 w;
+      // d F3 / d d_j = fc'_j u^ fc_k fc_w - fc_j fc_k fc'_w w^, d F3 / d d_k = fc_j fc'_k v^ fc_w + fc_j fc_k fc'_w w^
+      const float cu = dEdc * nb.ir[j], cv = dEdc * nb.ir[k];
+      const float fj = sRT * fu.y * fv.x * g.fw, fk = sRT * fu.x * fv.y * g.fw;
+      const float fwv = g.rw > 0.f ? sRT * fu.x * fv.x * g.dfw * frcp(g.rw) : 0.f;
+      gjx = cu * (v.x - g.c * u.x) + two_ds2 * fmaf(u.w, u.x, -g.wx) + fj * u.x - fwv * g.wx;
+      gjy = cu * (v.y - g.c * u.y) + two_ds2 * fmaf(u.w, u.y, -g.wy) + fj * u.y - fwv * g.wy;
+      gjz = cu * (v.z - g.c * u.z) + two_ds2 * fmaf(u.w, u.z, -g.wz) + fj * u.z - fwv * g.wz;
+      gkx = cv * (u.x - g.c * v.x) + two_ds2 * fmaf(v.w, v.x, g.wx) + fk * v.x + fwv * g.wx;
+      gky = cv * (u.y - g.c * v.y) + two_ds2 * fmaf(v.w, v.y, g.wy) + fk * v.y + fwv * g.wy;
+      gkz = cv * (u.z - g.c * v.z) + two_ds2 * fmaf(v.w, v.z, g.wz) + fk * v.z + fwv * g.wz;
+    } else if (take) {
       const float4 u = nb.d[j], fu = nb.f[j];
       const float4 v = nb.d[k], fv = nb.f[k];
       const float* La = lam_a;
@@ -906,7 +1055,11 @@ static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescCon
 template <int NT, int NRA>
 static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
                          int wpa, hipStream_t s) {
-  if (P.zeta == 50) {
+  if (P.kind == NN_DESC_BP) {
+    if (wpa == 4) launch_fwd_w<NT, NRA, 4, kZcBP>(sys, nl, P, G, one, s);
+    else if (wpa == 2) launch_fwd_w<NT, NRA, 2, kZcBP>(sys, nl, P, G, one, s);
+    else launch_fwd_w<NT, NRA, 1, kZcBP>(sys, nl, P, G, one, s);
+  } else if (P.zeta == 50) {
     if (wpa == 4) launch_fwd_w<NT, NRA, 4, 50>(sys, nl, P, G, one, s);
     else if (wpa == 2) launch_fwd_w<NT, NRA, 2, 50>(sys, nl, P, G, one, s);
     else launch_fwd_w<NT, NRA, 1, 50>(sys, nl, P, G, one, s);
@@ -949,7 +1102,11 @@ static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescCon
 template <int NT, int NRA, bool ONE>
 static void launch_adj_o(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                          int wpa, hipStream_t s) {
-  if (P.zeta == 50) {
+  if (P.kind == NN_DESC_BP) {
+    if (wpa == 4) launch_adj_w<NT, NRA, ONE, 4, kZcBP>(sys, nl, P, lam, pg, s);
+    else if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, kZcBP>(sys, nl, P, lam, pg, s);
+    else launch_adj_w<NT, NRA, ONE, 1, kZcBP>(sys, nl, P, lam, pg, s);
+  } else if (P.zeta == 50) {
     if (wpa == 4) launch_adj_w<NT, NRA, ONE, 4, 50>(sys, nl, P, lam, pg, s);
     else if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, 50>(sys, nl, P, lam, pg, s);
     else launch_adj_w<NT, NRA, ONE, 1, 50>(sys, nl, P, lam, pg, s);

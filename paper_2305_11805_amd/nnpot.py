@@ -24,6 +24,8 @@ NN_BF16_MLP = 1
 NN_STORE_JACOBIAN = 2
 NN_BF16X3_MLP = 4
 NN_REUSE_DESCRIPTORS = 8
+NN_DESC_MBP = 0
+NN_DESC_BP = 1
 ACT = {"linear": 0, "gaussian": 1, "relu": 2, "tanh": 3}
 STATUS = {0: "NN_OK", 1: "NN_E_INVALID", 2: "NN_E_CAPACITY", 3: "NN_E_CELL", 4: "NN_E_WORKSPACE",
           5: "NN_E_UNSUPPORTED", 6: "NN_E_HIP", 7: "NN_E_DEVICE"}
@@ -49,7 +51,8 @@ class nn_nlist(C.Structure):
 class nn_mbp_params(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("rc", C.c_double), ("n_rad", C.c_int32), ("eta_rad", C.c_double),
                 ("rs_rad", C.c_void_p), ("n_theta", C.c_int32), ("theta_s", C.c_void_p), ("n_rs_ang", C.c_int32),
-                ("eta_ang", C.c_double), ("rs_ang", C.c_void_p), ("zeta", C.c_double), ("eps", C.c_double)]
+                ("eta_ang", C.c_double), ("rs_ang", C.c_void_p), ("zeta", C.c_double), ("eps", C.c_double),
+                ("kind", C.c_int32), ("bp_zeta", C.c_void_p), ("bp_lambda", C.c_void_p), ("bp_eta", C.c_void_p)]
 
 
 class nn_mlp(C.Structure):
@@ -253,12 +256,20 @@ class DeviceModel:
 
 def make_params(p) -> tuple:
     """nn_mbp_params from an object with the descriptor hyperparameters
-    (host arrays are kept alive in the returned tuple)."""
+    (host arrays are kept alive in the returned tuple); p.kind = 1 selects
+    the standard BP angular term with p.bp_zeta, p.bp_lambda, p.bp_eta."""
     rs_rad = np.ascontiguousarray(p.rs_rad, np.float64)
+    if int(getattr(p, "kind", 0)) == NN_DESC_BP:
+        bz = np.ascontiguousarray(p.bp_zeta, np.float64)
+        bl = np.ascontiguousarray(p.bp_lambda, np.float64)
+        be = np.ascontiguousarray(p.bp_eta, np.float64)
+        s = nn_mbp_params(p.n_species, p.rc, rs_rad.size, p.eta_rad, rs_rad.ctypes.data, bz.size, None, be.size,
+                          0.0, None, 0.0, 0.0, NN_DESC_BP, bz.ctypes.data, bl.ctypes.data, be.ctypes.data)
+        return s, (rs_rad, bz, bl, be)
     th = np.ascontiguousarray(p.theta_s, np.float64)
     rs_ang = np.ascontiguousarray(p.rs_ang, np.float64)
     s = nn_mbp_params(p.n_species, p.rc, rs_rad.size, p.eta_rad, rs_rad.ctypes.data, th.size, th.ctypes.data,
-                      rs_ang.size, p.eta_ang, rs_ang.ctypes.data, p.zeta, p.eps)
+                      rs_ang.size, p.eta_ang, rs_ang.ctypes.data, p.zeta, p.eps, NN_DESC_MBP, None, None, None)
     return s, (rs_rad, th, rs_ang)
 
 

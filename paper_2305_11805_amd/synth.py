@@ -229,9 +229,37 @@ def bulk_system(rng, n, density, d_min, species_counts) -> System:
 IN_SCALE = {0: 14.0, 1: 0.45, 2: 12.0, 3: 3.3, 4: 0.6}
 
 
-def config(idx: int, scale: float = 1.0) -> Workload:
+# The standard BP descriptor on the geometries of configs 0-2 (desc="bp"):
+# radial grid as for mBP, angular terms zeta in {1, 2, 4, 8} (molecules) or
+# {1, 2, 4, 16} (bulk) with lambda = +-1, and 4 or 8 radius widths; the
+# first-layer scale follows the same rule as IN_SCALE.
+BP_ANGULAR = {0: ((1, 2, 4, 8), (0.01, 0.05, 0.15, 0.4)),
+              1: ((1, 2, 4, 16), (0.001, 0.01, 0.03, 0.06, 0.1, 0.2, 0.4, 0.8)),
+              2: ((1, 2, 4, 8), (0.01, 0.05, 0.15, 0.4))}
+BP_IN_SCALE = {0: 7.0, 1: 0.14, 2: 6.0}
+
+
+def config(idx: int, scale: float = 1.0, desc: str = "mbp") -> Workload:
     """Workload `idx` (0..4).  `scale` < 1 shrinks bulk systems (same density
-    and hyperparameters) for fast tests; it does not apply to clusters."""
+    and hyperparameters) for fast tests; it does not apply to clusters.
+    desc="bp" (configs 0-2) keeps the system and swaps the mBP angular term
+    for the standard BP one (same radial grid and MLP widths)."""
+    w = _config_mbp(idx, scale)
+    if desc == "mbp":
+        return w
+    if desc != "bp" or idx not in BP_ANGULAR:
+        raise ValueError(f"descriptor {desc!r} for config {idx}")
+    zetas, etas = BP_ANGULAR[idx]
+    p0 = w.params
+    p = bp_params(p0.n_species, p0.rc, p0.n_rad, zetas=zetas, etas=etas, eta_rad=p0.eta_rad)
+    hidden = list(w.model[0][0][1:-1])
+    model = random_model(p.n_species, p.dim, hidden, w.seed, in_scale=BP_IN_SCALE[idx])
+    name = w.name.replace(f"{p0.n_theta}x{p0.n_rs_ang} bins", f"BP {p.n_theta}x{p.n_rs_ang} terms")
+    name = name.replace(f" + {p0.n_theta}x{p0.n_rs_ang} ", f" + BP {p.n_theta}x{p.n_rs_ang} ")
+    return Workload(name, w.system, p, model, w.seed, w.extra)
+
+
+def _config_mbp(idx: int, scale: float = 1.0) -> Workload:
     seed = SEED_BASE + idx
     rng = np.random.Generator(np.random.PCG64(seed))
     if idx == 0:

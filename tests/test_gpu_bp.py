@@ -1,0 +1,122 @@
+"""The standard BP angular term (nn_mbp_params.kind = NN_DESC_BP) against the
+FP64 oracle: descriptors within 1e-5 relative, energies within 1e-4 eV/atom
+and forces within 1e-3 eV/A (FP32 and split-BF16 MLP), the energy-loss
+weight gradient within 1e-4 of each tensor's scale; and the calls that have
+no BP kernel report NN_E_UNSUPPORTED."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2305_11805_amd import nnpot, synth
+
+from helpers import E_TOL, F_TOL, descriptor_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def bp_small_cells():
+    rng = np.random.Generator(np.random.PCG64(44))
+    p = synth.bp_params(2, 4.0, 16, zetas=(1, 3, 4, 9), etas=(0.02, 0.1, 0.3, 0.7))
+    systems = []
+    for L, n in [(3.4, 7), (5.8, 26)]:
+        cell = np.array([[L, 0, 0], [0.4, L * 0.96, 0], [-0.3, 0.5, L * 1.04]])
+        systems.append(synth.single(rng.uniform(0, 1, (n, 3)) @ cell, rng.integers(0, 2, n), cell=cell,
+                                    pbc=(1, 1, 1)))
+    cl = synth.clusters_system(rng, [10, 1, 15], lambda n: 5.0, 0.9, 2)
+    model = synth.random_model(2, p.dim, [64, 32], 44, in_scale=2.0)
+    return synth.Workload("BP small periodic cells + clusters", synth.concat(systems + [cl]), p, model, 44)
+
+
+CASES = {
+    "bp0": lambda: synth.config(0, desc="bp"),
+    "bp1s": lambda: synth.config(1, scale=0.25, desc="bp"),
+    "bp2s": lambda: synth.config(2, scale=0.04, desc="bp"),
+    "bp_cells": bp_small_cells,
+}
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        w = CASES[name]()
+        nl = oracle.neighbors_cells(w.system, w.params.rc)
+        G = oracle.descriptors(w.params, w.system, nl)
+        Es, Ea, F = oracle.energy_forces(w.params, w.model, w.system, nl)
+        _cache[name] = (w, nl, G, Es, F)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bp_descriptors_match_oracle(name):
+    w, nl, G_ref, _, _ = case(name)
+    print(f"[bp descriptors] {w.name}", flush=True)
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    G = pot.descriptors().cpu().numpy()
+    nnpot.nn_check(pot.nl)
+    assert np.abs(G_ref[:, w.params.n_rad * w.params.n_species:]).max() > 0
+    err = descriptor_errors(G, G_ref)
+    print(f"  max |dG| / tol = {err:.3f}", flush=True)
+    assert err <= 1.0
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_bp_energy_forces_match_oracle(name, mode):
+    w, nl, _, Es_ref, F_ref = case(name)
+    print(f"[bp energy/forces] {w.name} {mode}", flush=True)
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    Es, _, F = pot.energy_forces(flags={"fp32": 0, "bf16x3": nnpot.NN_BF16X3_MLP}[mode])
+    nnpot.nn_check(pot.nl)
+    n_c = np.maximum(np.diff(w.system.atom_ptr), 1)
+    e_err = float(np.max(np.abs(Es.cpu().numpy() - Es_ref) / n_c))
+    f_err = float(np.max(np.abs(F.cpu().numpy() - F_ref)))
+    print(f"  E/atom {e_err:.2e} eV  F {f_err:.2e} eV/A (scale {np.abs(F_ref).max():.2f})", flush=True)
+    assert np.abs(F_ref).max() > 0.05
+    assert e_err <= E_TOL and f_err <= F_TOL
+
+
+def test_bp_autotuned_plan_and_weight_gradient():
+    w, nl, _, Es_ref, F_ref = case("bp1s")
+    s = w.system
+    pot = nnpot.Potential(s, w.params, w.model)
+    pot.build_neighbors()
+    plan = pot.autotune()
+    _, _, F = pot.energy_forces()
+    nnpot.nn_check(pot.nl)
+    f_err = float(np.max(np.abs(F.cpu().numpy() - F_ref)))
+    print(f"  plan {plan}: F {f_err:.2e}", flush=True)
+    assert f_err <= F_TOL
+    T = synth.energy_targets(w.seed, s.n_structs)
+    _, Es_o, flat = oracle.energy_loss_grad(w.params, w.model, s, nl, T)
+    ref = oracle.unflatten_grads(w.model, flat)
+    _, got = pot.grad(2.0 * (Es_o - T) / s.n_structs, positions=False)
+    worst = 0.0
+    for sp in range(len(ref)):
+        for (dW_r, db_r), (dW_g, db_g) in zip(ref[sp], got[sp]):
+            for r_, g_ in ((dW_r, dW_g), (db_r, db_g)):
+                g_ = g_.double().cpu().numpy().reshape(r_.shape)
+                worst = max(worst, np.abs(g_ - r_).max() / max(np.abs(r_).max(), 1e-30))
+    print(f"  weight gradient: max |d dW| / max |dW| = {worst:.2e}", flush=True)
+    assert worst <= 1e-4
+    nnpot.nn_autotune_reset()
+
+
+def test_bp_calls_without_kernel_are_refused():
+    w, _, _, _, _ = case("bp0")
+    pot = nnpot.Potential(w.system, w.params, w.model)
+    pot.build_neighbors()
+    pot.energy_forces()
+    with pytest.raises(nnpot.NNError) as e:
+        pot.descriptor_tangent(np.zeros((w.system.n_atoms, 3), np.float32))
+    assert e.value.status == 5
+    with pytest.raises(nnpot.NNError) as e:
+        pot.jacobian()
+    assert e.value.status == 5
+    with pytest.raises(nnpot.NNError) as e:
+        pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN, mem_budget=1 << 30)
+    assert e.value.status == 5
+    with pytest.raises(nnpot.NNError) as e:
+        pot.grad(np.zeros(w.system.n_structs), positions=False, dL_dF=np.zeros((w.system.n_atoms, 3)))
+    assert e.value.status == 5
