@@ -43,9 +43,20 @@ def flop_model(p, n_valid):
     each exp2 / sqrt / reciprocal = 1): per (pair, radial bin), per triplet
     (separable angular form) and per pair."""
     NT, NR = p.n_theta, p.n_rs_ang
-    z = int(p.zeta)
     P = float(np.sum(n_valid))
     T = float(np.sum(n_valid * (n_valid - 1) / 2))
+    if int(getattr(p, "kind", 0)) == 1:
+        # standard BP: 1 +- cos, the third side (FP64), its cutoff (sin as 15),
+        # s2 and fc fc fc; per angle term (1 + lambda cos)^zeta and the
+        # prefactor, per radius term exp(-eta s2) fc fc fc, two flops per bin
+        zs = [int(z) for z in p.bp_zeta]
+        fwd_trip = 50 + sum(ipow_mults(z) + 1 for z in zs) + 3 * NR + 2 * NT * NR
+        adj_trip = 45 + sum(ipow_mults(z - 1) + 4 for z in zs) + 3 * NR + 4 * NT * NR + 4 * NR + 4 * NT + 60
+        fwd = T * fwd_trip + P * p.n_rad * 8
+        adj = T * adj_trip + P * (p.n_rad * 12 + 6)
+        return {"pairs": P, "triplets": T, "desc_fwd": fwd, "desc_adj": adj, "desc_tan": 0.0,
+                "per_triplet": {"desc_fwd": fwd_trip, "desc_adj": adj_trip, "desc_tan": 0}}
+    z = int(p.zeta)
     geom = 33
     fwd_trip = geom + 4 * NT + NT * ipow_mults(z) + 7 * NR + 2 * NT * NR
     adj_trip = geom + 4 * NT + NT * ipow_mults(z - 1) + NT + 6 * NR + 4 * NT * NR + 5 * NR + 5 * NT + 35
@@ -483,6 +494,7 @@ def md_table2(args):
         s = w.system
         pot = nnpot.Potential(s, w.params, w.model, skin=1.0)
         pot.build_neighbors()
+        plan = pot.autotune()  # launch plan for this shape class (untimed)
         pot.energy_forces()
         v0, _ = synth.md_inputs(w.seed, s.n_atoms, 1, 0.005)
         vel = torch.tensor(v0, dtype=torch.float64, device="cuda")
@@ -509,7 +521,7 @@ def md_table2(args):
         out["runs"].append({"cells": n_cells, "atoms": s.n_atoms, "steps": steps,
                             "ms_per_step": round(ms, 5), "ms_per_step_graph": round(ms_g, 5),
                             "us_per_step_per_atom_graph": round(ms_g * 1e3 / s.n_atoms, 4),
-                            "list_builds": int(pot.meta[2].item())})
+                            "list_builds": int(pot.meta[2].item()), "launch_plan": list(plan)})
     print(json.dumps(out), flush=True)
 
 
@@ -533,6 +545,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=1, help="workload index 0-4 (default: 1)")
     ap.add_argument("--mode", choices=["fp32", "bf16", "bf16x3"], default="fp32")
+    ap.add_argument("--desc", choices=["mbp", "bp"], default="mbp",
+                    help="angular descriptor term: mBP (the headline) or standard BP (configs 0-2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the steady-state and graph-replay timings")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch plan")
@@ -568,7 +582,7 @@ def main():
     if args.ingest_counters:
         if args.calib_copy_mib <= 0:
             raise SystemExit("--ingest-counters needs --calib-copy-mib of the profiled run")
-        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config).name)
+        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config, desc=args.desc).name)
         return
 
     import torch
@@ -577,7 +591,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
-    w = synth.config(args.config)
+    w = synth.config(args.config, desc=args.desc)
     s, p = w.system, w.params
     flags = {"fp32": 0, "bf16": nnpot.NN_BF16_MLP, "bf16x3": nnpot.NN_BF16X3_MLP}[args.mode]
     skin = float(w.extra.get("skin", 0.0))

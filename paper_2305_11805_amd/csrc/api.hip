@@ -302,6 +302,9 @@ static nn_status make_desc_const(const nn_mbp_params* p, DescConst* out) {
       P.bp_pref[t] = (float)ldexp(1.0, 2 - (int)p->bp_zeta[t]);  // 2 * 2^(1 - zeta): both orders of a pair
     }
     for (int q = 0; q < p->n_rs_ang; ++q) P.bp_eta[q] = (float)p->bp_eta[q];
+    P.bp_zbits = 0;
+    for (int t = 0; t < p->n_theta; ++t)
+      while ((P.bp_zeta[t] >> P.bp_zbits) != 0) ++P.bp_zbits;
   } else {
     const double norm = 1.0 + sqrt(1.0 + p->eps);
     for (int t = 0; t < p->n_theta; ++t) {
@@ -544,7 +547,6 @@ nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const 
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if ((!v || !U) && sys->n_atoms > 0) return fail(NN_E_INVALID, "v/U is NULL");
-  if (P.kind == NN_DESC_BP) return fail(NN_E_UNSUPPORTED, "no descriptor tangent for the BP angular term");
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   hipStream_t s = (hipStream_t)stream;
   launch_desc_tan(*sys, *nl, P, v, U, plan_default(sys->n_atoms).wpa_fwd, s);
@@ -726,7 +728,6 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   if (!dL_dE && !dL_dF && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE and dL_dF are both NULL");
   if (dL_dpos && dL_dF)
     return fail(NN_E_UNSUPPORTED, "the position gradient of a loss on forces (second derivatives) is not provided");
-  if (dL_dF && P.kind == NN_DESC_BP) return fail(NN_E_UNSUPPORTED, "no force-loss gradient for the BP angular term");
   if (dL_dpos && !dL_dE) return fail(NN_E_INVALID, "dL_dpos needs dL_dE");
   if (dL_dpos && !F) return fail(NN_E_INVALID, "dL_dpos needs the forces F");
   const int64_t N = sys->n_atoms;

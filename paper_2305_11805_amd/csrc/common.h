@@ -56,6 +56,7 @@ struct DescConst {
   int32_t kind;
   float bp_pref[kMaxTheta], bp_lam[kMaxTheta], bp_eta[kMaxRsAng];
   int32_t bp_zeta[kMaxTheta];
+  int32_t bp_zbits;  // bit length of the largest exponent
 };
 
 // One species' MLP as seen by the kernels.

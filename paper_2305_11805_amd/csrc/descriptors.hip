@@ -270,8 +270,19 @@ __device__ __forceinline__ TripGeom triplet_geom(const float4& u, const float4& 
 // run-time mBP exponent, or kZcBP for the standard BP term.
 constexpr int kZcBP = -1;
 
-// x^e for a run-time e >= 0 (binary exponentiation).
-__device__ __forceinline__ float ipow_rt(float x, int e) {
+// x^e for a run-time 0 <= e < 2^nbits (binary exponentiation over a
+// wave-uniform number of bits, so lanes with different e do not diverge).
+__device__ __forceinline__ float ipow_rt(float x, int e, int nbits) {
+  float r = 1.0f;
+  for (int b = 0; b < nbits; ++b) {
+    r = ((e >> b) & 1) ? r * x : r;
+    x *= x;
+  }
+  return r;
+}
+
+// x^e for a run-time e >= 0 that is the same in every lane.
+__device__ __forceinline__ float ipow_uniform(float x, int e) {
   float r = 1.0f;
   while (e) {
     if (e & 1) r *= x;
@@ -279,6 +290,16 @@ __device__ __forceinline__ float ipow_rt(float x, int e) {
     e >>= 1;
   }
   return r;
+}
+
+// sin and cos of x in [0, pi/2] by their Taylor series to x^11 and x^12
+// (truncation below 6e-8 at pi/2), without range reduction.
+__device__ __forceinline__ void sincos_quarter(float x, float& sn, float& cs) {
+  const float z = x * x;
+  sn = x * fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, -2.5052108e-8f, 2.7557319e-6f), -1.9841270e-4f), 8.3333333e-3f),
+                        -1.6666667e-1f), 1.0f);
+  cs = fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, 2.0876757e-9f, -2.7557319e-7f), 2.4801587e-5f), -1.3888889e-3f),
+                        4.1666667e-2f), -0.5f), 1.0f);
 }
 
 // Standard BP triplet terms from the two staged neighbors (unit vector,
@@ -301,11 +322,39 @@ __device__ __forceinline__ BpGeom bp_geom(const float4& u, const float4& v, cons
   g.dfw = 0.f;
   if (g.rw < P.rc) {
     float sn, cs;
-    sincosf(P.half_pi_over_rc * (P.rc - g.rw), &sn, &cs);
+    sincos_quarter(P.half_pi_over_rc * (P.rc - g.rw), sn, cs);
     g.fw = sn * sn;  // sin^2(pi (rc - r) / (2 rc))
     if (DERIV) g.dfw = -2.0f * P.half_pi_over_rc * sn * cs;
   }
   return g;
+}
+
+// The third side w = d_k - d_j from the FP64 displacements of the two
+// neighbors, and its cutoff with rc - r_jk = (rc^2 - r_jk^2) / (rc + r_jk),
+// so that fc(r_jk) and its derivative keep their relative precision up to
+// rc (r_jk itself only enters that denominator).
+struct BpSide {
+  float wx, wy, wz, rw2, rw, fw, dfw;
+};
+__device__ __forceinline__ BpSide bp_side64(const double* __restrict__ dj, const double* __restrict__ dk,
+                                            const DescConst& P) {
+  BpSide b;
+  const double wx = dk[0] - dj[0], wy = dk[1] - dj[1], wz = dk[2] - dj[2];
+  const double rw2 = fma(wx, wx, fma(wy, wy, wz * wz));
+  b.wx = (float)wx;
+  b.wy = (float)wy;
+  b.wz = (float)wz;
+  b.rw2 = (float)rw2;
+  b.rw = __builtin_amdgcn_sqrtf(b.rw2);
+  b.fw = 0.f;
+  b.dfw = 0.f;
+  if (rw2 < P.rc64 * P.rc64) {
+    float sn, cs;
+    sincos_quarter(P.half_pi_over_rc * (float)(fma(P.rc64, P.rc64, -rw2)) * frcp(P.rc + b.rw), sn, cs);
+    b.fw = sn * sn;
+    b.dfw = -2.0f * P.half_pi_over_rc * sn * cs;
+  }
+  return b;
 }
 
 template <int NT, int NRA, int WPA, int ZC>
@@ -447,18 +496,10 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
             const float4 u = nb.d[j], v = nb.d[k];
             const float px = u.x + v.x, py = u.y + v.y, pz = u.z + v.z;
             const float mx = u.x - v.x, my = u.y - v.y, mz = u.z - v.z;
-            const double wx = d64[3 * k] - d64[3 * j], wy = d64[3 * k + 1] - d64[3 * j + 1],
-                         wz = d64[3 * k + 2] - d64[3 * j + 2];
-            const double rw2 = fma(wx, wx, fma(wy, wy, wz * wz));
-            float fw = 0.f;
-            if (rw2 < P.rc64 * P.rc64) {
-              const float rw = sqrtf((float)rw2);
-              const float sn = sinf(P.half_pi_over_rc * ((float)(fma(P.rc64, P.rc64, -rw2)) / (P.rc + rw)));
-              fw = sn * sn;
-            }
+            const BpSide w3 = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
             geo = make_float4(0.5f * fmaf(px, px, fmaf(py, py, pz * pz)), 0.5f * fmaf(mx, mx, fmaf(my, my, mz * mz)),
-                              fmaf(u.w, u.w, fmaf(v.w, v.w, (float)rw2)), 0.f);
-            F2 = fu.x * fv.x * fw;  // three cutoffs
+                              fmaf(u.w, u.w, fmaf(v.w, v.w, w3.rw2)), 0.f);
+            F2 = fu.x * fv.x * w3.fw;  // three cutoffs
           } else {
             const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
             geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
@@ -476,7 +517,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
           if constexpr (ZC == kZcBP) {
             // 2^(2 - zeta) (1 + lambda cos)^zeta and exp(-eta s2) fc fc fc
 #pragma unroll
-            for (int u = 0; u < NP; ++u) A[u] = xa[u] * ipow_rt(xb[u] > 0.f ? q4.x : q4.y, zexp[u]);
+            for (int u = 0; u < NP; ++u) A[u] = xa[u] * ipow_rt(xb[u] > 0.f ? q4.x : q4.y, zexp[u], P.bp_zbits);
 #pragma unroll
             for (int v = 0; v < NQ; ++v) R[v] = fexp2(-rsq[v] * q4.z) * f2;
           } else {
@@ -560,6 +601,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
   __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
   __shared__ float4 tgeo[WPA][kWave], tdot[WPA][kWave];  // per chunk: geometry; F2, zeta cos_dot, zeta ssm_dot, F2_dot
   __shared__ float tg2[WPA][kWave];                      // and -2 eta r_dot F2
+  __shared__ double d64[ZC == kZcBP ? 3 * kMaxNb : 1];  // BP: FP64 displacements for the third side
   const int64_t i = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Ui = U + i * (int64_t)P.D;
@@ -567,7 +609,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
     for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
     return;
   }
-  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr);
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr, ZC == kZcBP ? d64 : nullptr);
   if (nb.bad) {
     for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
     return;
@@ -628,15 +670,28 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
   constexpr int NP = NT / 4, NQ = NRA / 4;
   const int li = lane & 3, blk = lane >> 2;
   float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
+  int zexp[NP];
 #pragma unroll
   for (int u = 0; u < NP; ++u) {
-    xa[u] = P.x_a[4 * u + li];
-    xb[u] = P.x_b[4 * u + li];
+    if constexpr (ZC == kZcBP) {  // prefactor, lambda, zeta of angle term 4u + li
+      xa[u] = P.bp_pref[4 * u + li];
+      xb[u] = P.bp_lam[4 * u + li];
+      zexp[u] = P.bp_zeta[4 * u + li];
+    } else {
+      xa[u] = P.x_a[4 * u + li];
+      xb[u] = P.x_b[4 * u + li];
+      zexp[u] = 0;
+    }
   }
 #pragma unroll
   for (int u = 0; u < NQ; ++u) {
-    rsq[u] = P.rs_ang[4 * u + li];
-    rsq_lo[u] = P.rs_ang_lo[4 * u + li];
+    if constexpr (ZC == kZcBP) {  // eta log2(e) and eta of radius term 4u + li
+      rsq[u] = P.bp_eta[4 * u + li] * 1.4426950408889634f;
+      rsq_lo[u] = P.bp_eta[4 * u + li];
+    } else {
+      rsq[u] = P.rs_ang[4 * u + li];
+      rsq_lo[u] = P.rs_ang_lo[4 * u + li];
+    }
   }
   for (int a = 0; a < S; ++a) {
     for (int b = a; b < S; ++b) {
@@ -668,16 +723,34 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
           const float4 u = nb.d[j], v = nb.d[k];
           const float4 fu = nb.f[j], fv = nb.f[k];
           const float4 wj = tw[j], wk = tw[k];
-          const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
-          const float cdot = fmaf(v.x, wj.x, fmaf(v.y, wj.y, v.z * wj.z)) + fmaf(u.x, wk.x, fmaf(u.y, wk.y, u.z * wk.z)) -
-                             g.c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
-          const float sdot = -g.c * cdot * frcp(g.ssm);
-          const float F2 = 2.0f * fu.x * fv.x;
-          const float F2dot = 2.0f * fmaf(fu.y * wj.w, fv.x, fu.x * fv.y * wk.w);
-          const float rbdot = 0.5f * (wj.w + wk.w);
-          geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
-          dot = make_float4(F2, zf * cdot, zf * sdot, F2dot);
-          g2 = -2.0f * P.eta_ang * rbdot * F2;
+          const float cdot0 = fmaf(v.x, wj.x, fmaf(v.y, wj.y, v.z * wj.z)) + fmaf(u.x, wk.x, fmaf(u.y, wk.y, u.z * wk.z));
+          if constexpr (ZC == kZcBP) {
+            // s2_dot = 2 (r_j r_j_dot + r_k r_k_dot + w . (delta_k - delta_j)),
+            // F3_dot = fc'_j r_j_dot fc_k fc_w + fc_j fc'_k r_k_dot fc_w + fc_j fc_k fc'_w (w^ . (delta_k - delta_j))
+            const BpSide g = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
+            const float c = fmaf(u.x, v.x, fmaf(u.y, v.y, u.z * v.z));
+            const float cdot = cdot0 - c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
+            const float ddx = fmaf(wk.x, v.w, -wj.x * u.w), ddy = fmaf(wk.y, v.w, -wj.y * u.w),
+                        ddz = fmaf(wk.z, v.w, -wj.z * u.w);
+            const float wdd = fmaf(g.wx, ddx, fmaf(g.wy, ddy, g.wz * ddz));
+            const float s2dot = 2.0f * fmaf(u.w, wj.w, fmaf(v.w, wk.w, wdd));
+            const float F3 = fu.x * fv.x * g.fw;
+            const float F3dot = fmaf(fu.y * wj.w, fv.x * g.fw, fu.x * fv.y * wk.w * g.fw) +
+                                (g.rw > 0.f ? fu.x * fv.x * g.dfw * wdd * frcp(g.rw) : 0.f);
+            geo = make_float4(c, fmaf(u.w, u.w, fmaf(v.w, v.w, g.rw2)), 0.f, 0.f);
+            dot = make_float4(F3, cdot, F3dot, 0.f);
+            g2 = s2dot * F3;
+          } else {
+            const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+            const float cdot = cdot0 - g.c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
+            const float sdot = -g.c * cdot * frcp(g.ssm);
+            const float F2 = 2.0f * fu.x * fv.x;
+            const float F2dot = 2.0f * fmaf(fu.y * wj.w, fv.x, fu.x * fv.y * wk.w);
+            const float rbdot = 0.5f * (wj.w + wk.w);
+            geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
+            dot = make_float4(F2, zf * cdot, zf * sdot, F2dot);
+            g2 = -2.0f * P.eta_ang * rbdot * F2;
+          }
         }
         tgeo[wv][lane] = geo;
         tdot[wv][lane] = dot;
@@ -688,21 +761,40 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
           const float4 q4 = tgeo[wv][16 * gi + blk];
           const float4 d4 = tdot[wv][16 * gi + blk];
           const float h2 = tg2[wv][16 * gi + blk];
-          float x[NP], P1[NP], A[NP], Ad[NP], RF[NQ], RT[NQ];
+          float A[NP], Ad[NP], RF[NQ], RT[NQ];
+          if constexpr (ZC == kZcBP) {
+            // A = pref base^zeta, A_dot = pref zeta lambda base^(zeta-1) cos_dot;
+            // R F3 and R (F3_dot - eta s2_dot F3)
 #pragma unroll
-          for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
-          ipow_sel<(ZC > 0 ? ZC - 1 : 0), NP>(x, zeta1, P1);
+            for (int u = 0; u < NP; ++u) {
+              const float base = fmaf(xb[u], q4.x, 1.0f);
+              const float P1 = ipow_rt(base, zexp[u] - 1, P.bp_zbits);
+              A[u] = xa[u] * P1 * base;
+              Ad[u] = xa[u] * (float)zexp[u] * xb[u] * P1 * d4.y;
+            }
 #pragma unroll
-          for (int u = 0; u < NP; ++u) {
-            A[u] = P1[u] * x[u];
-            Ad[u] = P1[u] * fmaf(xa[u], d4.y, xb[u] * d4.z);
-          }
+            for (int v = 0; v < NQ; ++v) {
+              const float R = fexp2(-rsq[v] * q4.y);
+              RF[v] = R * d4.x;
+              RT[v] = R * fmaf(-rsq_lo[v], h2, d4.z);
+            }
+          } else {
+            float x[NP], P1[NP];
 #pragma unroll
-          for (int v = 0; v < NQ; ++v) {
-            const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
-            const float R = fexp2(-eta_a2 * dq * dq);
-            RF[v] = R * d4.x;
-            RT[v] = R * fmaf(h2, dq, d4.w);
+            for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+            ipow_sel<(ZC > 0 ? ZC - 1 : 0), NP>(x, zeta1, P1);
+#pragma unroll
+            for (int u = 0; u < NP; ++u) {
+              A[u] = P1[u] * x[u];
+              Ad[u] = P1[u] * fmaf(xa[u], d4.y, xb[u] * d4.z);
+            }
+#pragma unroll
+            for (int v = 0; v < NQ; ++v) {
+              const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
+              const float R = fexp2(-eta_a2 * dq * dq);
+              RF[v] = R * d4.x;
+              RT[v] = R * fmaf(h2, dq, d4.w);
+            }
           }
 #pragma unroll
           for (int u = 0; u < NP; ++u)
@@ -844,7 +936,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
 #pragma unroll
       for (int p = 0; p < NT; ++p) {
         const float base = fmaf(P.bp_lam[p], g.c, 1.0f);
-        P1[p] = ipow_rt(base, P.bp_zeta[p] - 1);
+        P1[p] = ipow_uniform(base, P.bp_zeta[p] - 1);
         A[p] = P.bp_pref[p] * P1[p] * base;
       }
 #pragma unroll
@@ -1080,7 +1172,11 @@ static void launch_tan_w(const nn_system& sys, const nn_nlist& nl, const DescCon
 template <int NT, int NRA>
 static void launch_tan_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* v, float* U,
                          int wpa, hipStream_t s) {
-  if (P.zeta == 50) {
+  if (P.kind == NN_DESC_BP) {
+    if (wpa == 4) launch_tan_w<NT, NRA, 4, kZcBP>(sys, nl, P, v, U, s);
+    else if (wpa == 2) launch_tan_w<NT, NRA, 2, kZcBP>(sys, nl, P, v, U, s);
+    else launch_tan_w<NT, NRA, 1, kZcBP>(sys, nl, P, v, U, s);
+  } else if (P.zeta == 50) {
     if (wpa == 4) launch_tan_w<NT, NRA, 4, 50>(sys, nl, P, v, U, s);
     else if (wpa == 2) launch_tan_w<NT, NRA, 2, 50>(sys, nl, P, v, U, s);
     else launch_tan_w<NT, NRA, 1, 50>(sys, nl, P, v, U, s);

@@ -1,8 +1,9 @@
 """The standard BP angular term (nn_mbp_params.kind = NN_DESC_BP) against the
 FP64 oracle: descriptors within 1e-5 relative, energies within 1e-4 eV/atom
 and forces within 1e-3 eV/A (FP32 and split-BF16 MLP), the energy-loss
-weight gradient within 1e-4 of each tensor's scale; and the calls that have
-no BP kernel report NN_E_UNSUPPORTED."""
+weight gradient within 1e-4 of each tensor's scale, the descriptor tangent
+and the force-loss weight gradient at the bars of the mBP tests; the stored
+Jacobian, which has no BP kernel, reports NN_E_UNSUPPORTED."""
 import numpy as np
 import pytest
 
@@ -103,20 +104,35 @@ def test_bp_autotuned_plan_and_weight_gradient():
     nnpot.nn_autotune_reset()
 
 
-def test_bp_calls_without_kernel_are_refused():
+@pytest.mark.parametrize("name", ["bp0", "bp_cells"])
+def test_bp_descriptor_tangent_and_force_loss_gradient_match_oracle(name):
+    from test_gpu_force_loss import tangent_error, weight_grad_error, TAN_REL, WG_REL
+    w, nl, _, _, _ = case(name)
+    s, p = w.system, w.params
+    rng = np.random.Generator(np.random.PCG64(w.seed + 17))
+    v = rng.standard_normal((s.n_atoms, 3)).astype(np.float32)
+    gE = rng.standard_normal(s.n_structs)
+    pot = nnpot.Potential(s, p, w.model)
+    pot.build_neighbors()
+    U = pot.descriptor_tangent(v).double().cpu().numpy()
+    U_ref = oracle.descriptor_tangent(p, s, nl, v.astype(np.float64))
+    t_err = tangent_error(U, U_ref, p)
+    pot.energy_forces()
+    _, got = pot.grad(gE, positions=False, dL_dF=v)
+    nnpot.nn_check(pot.nl)
+    ref = oracle.unflatten_grads(w.model, oracle.force_loss_grad(p, w.model, s, nl, gE, v.astype(np.float64)))
+    g_err = weight_grad_error(got, ref)
+    print(f"  {name}: tangent {t_err:.2e}, force-loss weight gradient {g_err:.2e}", flush=True)
+    assert t_err <= TAN_REL and g_err <= WG_REL
+
+
+def test_bp_stored_jacobian_is_refused():
     w, _, _, _, _ = case("bp0")
     pot = nnpot.Potential(w.system, w.params, w.model)
     pot.build_neighbors()
-    pot.energy_forces()
-    with pytest.raises(nnpot.NNError) as e:
-        pot.descriptor_tangent(np.zeros((w.system.n_atoms, 3), np.float32))
-    assert e.value.status == 5
     with pytest.raises(nnpot.NNError) as e:
         pot.jacobian()
     assert e.value.status == 5
     with pytest.raises(nnpot.NNError) as e:
         pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN, mem_budget=1 << 30)
-    assert e.value.status == 5
-    with pytest.raises(nnpot.NNError) as e:
-        pot.grad(np.zeros(w.system.n_structs), positions=False, dL_dF=np.zeros((w.system.n_atoms, 3)))
     assert e.value.status == 5
