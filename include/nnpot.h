@@ -136,8 +136,7 @@ typedef struct nn_nlist {
  * with n_theta angle terms (bp_zeta integer in [1, 64], bp_lambda +1 or -1)
  * and n_rs_ang radius terms (bp_eta >= 0, 1/A^2); theta_s, eta_ang, rs_ang,
  * zeta and eps are then not read.  The radial part, layout and limits are
- * those above.  With BP the stored Jacobian (nn_descriptors with jac,
- * NN_STORE_JACOBIAN, NN_REUSE_DESCRIPTORS) returns NN_E_UNSUPPORTED.
+ * those above.  Every call below accepts either kind.
  */
 enum { NN_DESC_MBP = 0, NN_DESC_BP = 1 };
 typedef struct nn_mbp_params {

@@ -352,7 +352,7 @@ static nn_status check_model(const nn_model* m, const DescConst& P) {
 
 // Floats of the stored Jacobian if these flags and budget ask for it, else 0.
 static size_t jac_request(const DescConst& P, int64_t capacity, int32_t flags, size_t mem_budget) {
-  if (!(flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS)) || P.kind == NN_DESC_BP) return 0;
+  if (!(flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))) return 0;
   const size_t n = jacobian_floats(P.n_rad, P.S, P.n_theta, P.n_rs_ang, capacity);
   return n * sizeof(float) <= mem_budget ? n : 0;
 }
@@ -522,7 +522,6 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if (!G && sys->n_atoms > 0) return fail(NN_E_INVALID, "G is NULL");
-  if (jac && P.kind == NN_DESC_BP) return fail(NN_E_UNSUPPORTED, "no stored Jacobian for the BP angular term");
 
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   (void)ws;
@@ -568,8 +567,6 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
     return fail(NN_E_INVALID, "unknown flags");
   if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
     return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
-  if ((flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS)) && P.kind == NN_DESC_BP)
-    return fail(NN_E_UNSUPPORTED, "no stored Jacobian for the BP angular term");
   const int64_t N = sys->n_atoms;
   const size_t jf = jac_request(P, nl->capacity, flags, mem_budget);
   if ((flags & NN_REUSE_DESCRIPTORS) && !jf)

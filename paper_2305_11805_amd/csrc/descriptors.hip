@@ -1284,7 +1284,7 @@ void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4*
 
 __host__ __device__ inline int jac_stride(int n_rad, int S, int NB) { return (n_rad + 3 + 3 * S * NB + 3) / 4 * 4; }
 
-template <int NT, int NRA>
+template <int NT, int NRA, bool BP>
 __global__ void __launch_bounds__(64) k_desc_jac(nn_system sys, const int64_t* __restrict__ offsets,
                                                  const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
                                                  DescConst P, float* __restrict__ J, int64_t* meta) {
@@ -1352,6 +1352,45 @@ __global__ void __launch_bounds__(64) k_desc_jac(nn_system sys, const int64_t* _
       for (int k = nb.seg[b]; k < nb.seg[b + 1]; ++k) {
         if (!active || k == j) continue;
         const float4 v = nb.d[k], fv = nb.f[k];
+        if constexpr (BP) {
+          // standard BP term T = A_p(cos) R_q(s2) F3: dT/dd_u = A_p' R_q F3 e + A_p G_q with
+          // e = d cos / dd_u and G_q = R_q (-eta_q F3 d s2/dd_u + d F3/dd_u),
+          // d s2/dd_u = 2 (d_u - w), d F3/dd_u = fc'_u u^ fc_v fc_w - fc_u fc_v fc'_w w^
+          const BpGeom g = bp_geom<true>(u, v, P);
+          const float c = g.c;
+          const float F3 = fu.x * fv.x * g.fw;
+          const float irw = g.rw > 0.f ? frcp(g.rw) : 0.f;
+          const float fuw = fu.y * fv.x * g.fw, fww = fu.x * fv.x * g.dfw * irw;
+          const float dfx = fmaf(fuw, u.x, -fww * g.wx), dfy = fmaf(fuw, u.y, -fww * g.wy),
+                      dfz = fmaf(fuw, u.z, -fww * g.wz);
+          const float sx = 2.0f * fmaf(u.w, u.x, -g.wx), sy = 2.0f * fmaf(u.w, u.y, -g.wy),
+                      sz = 2.0f * fmaf(u.w, u.z, -g.wz);
+          float A[NT], dA[NT];
+#pragma unroll
+          for (int p = 0; p < NT; ++p) {
+            const float base = fmaf(P.bp_lam[p], c, 1.0f);
+            const float P1 = ipow_uniform(base, P.bp_zeta[p] - 1);
+            A[p] = P.bp_pref[p] * P1 * base;
+            dA[p] = P.bp_pref[p] * (float)P.bp_zeta[p] * P.bp_lam[p] * P1;
+          }
+          const float ex = (v.x - c * u.x) * iru, ey = (v.y - c * u.y) * iru, ez = (v.z - c * u.z) * iru;
+#pragma unroll
+          for (int q = 0; q < NRA; ++q) {
+            const float R = fexp2(-P.bp_eta[q] * 1.4426950408889634f * g.s2);
+            const float FR = F3 * R;
+            const float ef = -P.bp_eta[q] * FR;
+            const float gx = R * dfx + ef * sx, gy = R * dfy + ef * sy, gz = R * dfz + ef * sz;
+#pragma unroll
+            for (int p = 0; p < NT; ++p) {
+              const float a = FR * dA[p];
+              const int t = q * NT + p;
+              vx[t] = fmaf(a, ex, fmaf(A[p], gx, vx[t]));
+              vy[t] = fmaf(a, ey, fmaf(A[p], gy, vy[t]));
+              vz[t] = fmaf(a, ez, fmaf(A[p], gz, vz[t]));
+            }
+          }
+          continue;
+        }
         const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
         const float c = g.c;
         const float F2 = 2.0f * fu.x * fv.x;
@@ -1447,8 +1486,12 @@ size_t jacobian_floats(int n_rad, int S, int nt, int nra, int64_t capacity) {
 
 template <int NT, int NRA>
 static void launch_jac_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s) {
-  hipLaunchKernelGGL((k_desc_jac<NT, NRA>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets, nl.nbr,
-                     nl.shift, P, J, nl.meta);
+  if (P.kind == NN_DESC_BP)
+    hipLaunchKernelGGL((k_desc_jac<NT, NRA, true>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets,
+                       nl.nbr, nl.shift, P, J, nl.meta);
+  else
+    hipLaunchKernelGGL((k_desc_jac<NT, NRA, false>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets,
+                       nl.nbr, nl.shift, P, J, nl.meta);
 }
 
 template <int NT, int NRA>

@@ -2,8 +2,8 @@
 FP64 oracle: descriptors within 1e-5 relative, energies within 1e-4 eV/atom
 and forces within 1e-3 eV/A (FP32 and split-BF16 MLP), the energy-loss
 weight gradient within 1e-4 of each tensor's scale, the descriptor tangent
-and the force-loss weight gradient at the bars of the mBP tests; the stored
-Jacobian, which has no BP kernel, reports NN_E_UNSUPPORTED."""
+and the force-loss weight gradient at the bars of the mBP tests (the stored
+Jacobian of BP is tested with the mBP one)."""
 import numpy as np
 import pytest
 
@@ -124,15 +124,3 @@ def test_bp_descriptor_tangent_and_force_loss_gradient_match_oracle(name):
     g_err = weight_grad_error(got, ref)
     print(f"  {name}: tangent {t_err:.2e}, force-loss weight gradient {g_err:.2e}", flush=True)
     assert t_err <= TAN_REL and g_err <= WG_REL
-
-
-def test_bp_stored_jacobian_is_refused():
-    w, _, _, _, _ = case("bp0")
-    pot = nnpot.Potential(w.system, w.params, w.model)
-    pot.build_neighbors()
-    with pytest.raises(nnpot.NNError) as e:
-        pot.jacobian()
-    assert e.value.status == 5
-    with pytest.raises(nnpot.NNError) as e:
-        pot.energy_forces(flags=nnpot.NN_STORE_JACOBIAN, mem_budget=1 << 30)
-    assert e.value.status == 5

@@ -34,9 +34,10 @@ def expand_jacobian(J, nl, species, p):
     return out
 
 
-@pytest.mark.parametrize("cfg,scale", [(0, 1.0), (1, 0.05), (3, 0.01)])
-def test_jacobian_matches_oracle(cfg, scale):
-    w = synth.config(cfg, scale=scale)
+@pytest.mark.parametrize("cfg,scale,desc", [(0, 1.0, "mbp"), (1, 0.05, "mbp"), (3, 0.01, "mbp"), (0, 1.0, "bp"),
+                                            (1, 0.05, "bp")])
+def test_jacobian_matches_oracle(cfg, scale, desc):
+    w = synth.config(cfg, scale=scale, desc=desc)
     s, p = w.system, w.params
     pot = nnpot.Potential(s, p, w.model)
     pot.build_neighbors()
@@ -49,13 +50,14 @@ def test_jacobian_matches_oracle(cfg, scale):
     # per entry, relative to the entry's largest derivative
     scale_e = np.maximum(np.abs(dG).max(axis=(1, 2)), 1e-12)
     err = (np.abs(got - dG).max(axis=(1, 2)) / scale_e).max()
-    print(f"cfg{cfg}: max per-entry |dJ| / max |J| = {err:.2e}", flush=True)
+    print(f"cfg{cfg} {desc}: max per-entry |dJ| / max |J| = {err:.2e}", flush=True)
     assert err <= 1e-4
 
 
-@pytest.mark.parametrize("cfg,scale", [(1, 1.0), (3, 0.1), (2, 0.05)])
-def test_stored_mode_forces(cfg, scale):
-    w = synth.config(cfg, scale=scale)
+@pytest.mark.parametrize("cfg,scale,desc", [(1, 1.0, "mbp"), (3, 0.1, "mbp"), (2, 0.05, "mbp"), (1, 0.25, "bp"),
+                                            (2, 0.05, "bp")])
+def test_stored_mode_forces(cfg, scale, desc):
+    w = synth.config(cfg, scale=scale, desc=desc)
     s, p = w.system, w.params
     pot = nnpot.Potential(s, p, w.model, mem_budget=BIG, flags=nnpot.NN_STORE_JACOBIAN)
     pot.build_neighbors()
@@ -64,7 +66,7 @@ def test_stored_mode_forces(cfg, scale):
     nnpot.nn_check(pot.nl)
     assert np.array_equal(Es0, Es1)  # same descriptors and MLP
     rel = np.abs(F1 - F0).max() / np.abs(F0).max()
-    print(f"cfg{cfg}: stored vs recompute max |dF| / max |F| = {rel:.2e}", flush=True)
+    print(f"cfg{cfg} {desc}: stored vs recompute max |dF| / max |F| = {rel:.2e}", flush=True)
     assert rel <= 1e-5
     if s.n_atoms <= 5000:
         nl = oracle.neighbors_cells(s, p.rc)
