@@ -311,6 +311,34 @@ def unflatten_grads(model, flat):
     return out
 
 
+def loss(atom_ptr, E, E_ref, F=None, F_ref=None, energy_kind="quad", force_kind="quad", per_atom=False,
+         energy_weight=1.0, force_weight=1.0):
+    """Loss of Sec. II.A (energy and force errors with a relative weight, each
+    a quadratic or exponential function of the difference, energies per
+    configuration or per atom), with its derivatives:
+        L = w_E mean_c l_E(dE_c) + w_F mean_(k,a) l_F(F_ka - F*_ka),
+        dE_c = E_c - T_c  or  (E_c - T_c) / N_c,  l(x) = x^2 or exp(x^2) - 1.
+    Returns (L, dL/dE [B], dL/dF [N][3] or None)."""
+    def term(kind, x):
+        if kind == "exp":
+            return np.exp(x * x) - 1.0, 2.0 * x * np.exp(x * x)
+        return x * x, 2.0 * x
+    E = np.asarray(E, np.float64)
+    n = np.diff(np.asarray(atom_ptr, np.int64)).astype(np.float64)
+    scale = 1.0 / np.maximum(n, 1.0) if per_atom else np.ones_like(E)
+    B = E.size
+    lE, dE = term(energy_kind, (E - np.asarray(E_ref, np.float64)) * scale)
+    L = energy_weight / B * lE.sum()
+    dL_dE = energy_weight / B * dE * scale
+    dL_dF = None
+    if F is not None:
+        d = np.asarray(F, np.float64) - np.asarray(F_ref, np.float64)
+        lF, dF = term(force_kind, d)
+        L += force_weight / d.size * lF.sum()
+        dL_dF = force_weight / d.size * dF
+    return L, dL_dE, dL_dF
+
+
 # (eV / Angstrom) / amu in Angstrom / fs^2: eV = 1.602176634e-19 J,
 # amu = 1.66053906660e-27 kg, Angstrom^2 / fs^2 = 1e10 m^2 / s^2
 ACCEL = 1.602176634e-19 / 1.66053906660e-27 / 1e10

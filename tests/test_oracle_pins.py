@@ -674,3 +674,45 @@ def test_bp_jacobian_central_differences(O):
                 Gm = O.descriptors(p, synth.System(pm, sys.species, sys.atom_ptr, sys.cell, sys.pbc), nl)
                 fd = (Gp[r] - Gm[r]) / (2 * h)
                 np.testing.assert_allclose(dG[e, :, a], fd, rtol=1e-6, atol=1e-8 * max(1.0, np.abs(G[r]).max()))
+
+
+# ---------------------------------------------------------------------------
+# the training loss of Sec. II.A
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ek,fk,per_atom", [("quad", "quad", False), ("exp", "quad", True), ("quad", "exp", True),
+                                           ("exp", "exp", False)])
+def test_loss_derivatives_central_differences(O, ek, fk, per_atom):
+    rng = np.random.Generator(np.random.PCG64(31))
+    ptr = np.array([0, 3, 4, 9])
+    E, T = rng.normal(size=3), rng.normal(size=3)
+    F, Fr = rng.normal(size=(9, 3)) * 0.5, rng.normal(size=(9, 3)) * 0.5
+    args = dict(energy_kind=ek, force_kind=fk, per_atom=per_atom, energy_weight=0.7, force_weight=1.9)
+    L, dE, dF = O.loss(ptr, E, T, F, Fr, **args)
+    h = 1e-6
+    for c in range(3):
+        Ep, Em = E.copy(), E.copy(); Ep[c] += h; Em[c] -= h
+        fd = (O.loss(ptr, Ep, T, F, Fr, **args)[0] - O.loss(ptr, Em, T, F, Fr, **args)[0]) / (2 * h)
+        assert abs(fd - dE[c]) < 1e-7 * max(1.0, abs(dE[c]))
+    for k in range(9):
+        for a in range(3):
+            Fp, Fm = F.copy(), F.copy(); Fp[k, a] += h; Fm[k, a] -= h
+            fd = (O.loss(ptr, E, T, Fp, Fr, **args)[0] - O.loss(ptr, E, T, Fm, Fr, **args)[0]) / (2 * h)
+            assert abs(fd - dF[k, a]) < 1e-7 * max(1.0, abs(dF[k, a]))
+
+
+def test_loss_special_values(O):
+    """Zero differences give zero loss in every form; the exponential form
+    exp(x^2) - 1 agrees with x^2 to second order; a per-atom energy term is
+    unchanged when a structure of n atoms carries n times the difference."""
+    ptr = np.array([0, 1, 5])
+    E = np.array([1.0, -2.0])
+    for ek in ("quad", "exp"):
+        assert O.loss(ptr, E, E, energy_kind=ek)[0] == 0.0
+    x = 1e-3
+    Lq = O.loss(np.array([0, 1]), np.array([x]), np.array([0.0]))[0]
+    Le = O.loss(np.array([0, 1]), np.array([x]), np.array([0.0]), energy_kind="exp")[0]
+    assert abs(Le - Lq) < x ** 4
+    a = O.loss(np.array([0, 4]), np.array([4 * 0.3]), np.array([0.0]), per_atom=True)[0]
+    b = O.loss(np.array([0, 1]), np.array([0.3]), np.array([0.0]), per_atom=True)[0]
+    assert abs(a - b) < 1e-15
