@@ -392,8 +392,7 @@ def suite_config(idx, modes, steps, out):
             def fm_step():
                 build()
                 ef()
-                dL = (2.0 / s.n_structs) * (pot.E_struct - T)
-                dF = (2.0 / (3 * s.n_atoms)) * (pot.F - Ft)
+                _, dL, dF = pot.loss(T, Ft)
                 pot.grad(dL, positions=False, weights=True, dL_dF=dF)
             fm_step()
             ms = _timed(torch, stream, fm_step, steps) / steps
@@ -439,9 +438,10 @@ def suite_config(idx, modes, steps, out):
 
 def force_matching(args):
     """One force-matching training step per iteration on --config: list
-    (re)build, E and F, then dL/dW of L = mean_c (E_c - T_c)^2 +
-    sum_k |F_k - F*_k|^2 / (3N) (the force term through the descriptor
-    tangent and the MLP's forward-mode tangent).  Prints one JSON line."""
+    (re)build, E and F, the loss L = mean_c (E_c - T_c)^2 + sum_k |F_k - F*_k|^2
+    / (3N) with its derivatives (nn_loss), then dL/dW (the force term through
+    the descriptor tangent and the MLP's forward-mode tangent).  Every step
+    runs in the library's kernels.  Prints one JSON line."""
     import torch
     from paper_2305_11805_amd import nnpot, synth
     if not torch.cuda.is_available():
@@ -456,8 +456,7 @@ def force_matching(args):
     def step():
         pot.build_neighbors(check=False)
         pot.energy_forces()
-        dL = (2.0 / s.n_structs) * (pot.E_struct - T)
-        dF = (2.0 / (3 * s.n_atoms)) * (pot.F - Ft)
+        _, dL, dF = pot.loss(T, Ft)  # nn_loss: L, dL/dE, dL/dF on the device
         pot.grad(dL, positions=False, weights=True, dL_dF=dF)
     for _ in range(max(args.warmup, 1)):
         step()

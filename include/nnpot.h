@@ -321,6 +321,31 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
                                 const float* F, float* dL_dpos, float* const* dW, float* const* db, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* Loss of Sec. II.A: energy and force terms with a relative weight. */
+enum { NN_LOSS_QUAD = 0, NN_LOSS_EXP = 1 };
+typedef struct {
+  int32_t energy_kind;  /* NN_LOSS_QUAD: x^2;  NN_LOSS_EXP: exp(x^2) - 1    */
+  int32_t force_kind;   /* the same choice for the force components         */
+  int32_t per_atom;     /* 1: the energy difference of a structure divided by
+                           its atom count (per-atom energies), 0: per structure */
+  double energy_weight; /* w_E                                               */
+  double force_weight;  /* w_F (the relative factor of the force term)        */
+} nn_loss_params;
+
+/*
+ * L = w_E / B sum_c l_E(dE_c) + w_F / (3N) sum_{k,a} l_F(F_ka - F_ref_ka), with
+ * dE_c = E_c - E_ref_c (per structure) or (E_c - E_ref_c) / N_c (per atom),
+ * and its derivatives, the inputs of nn_energy_forces_grad.
+ *   E, E_ref [device] FP64 [B];  F, F_ref [device] FP32 [N][3] (both NULL: no
+ *   force term, dL_dF not written);  L [device] FP64 [1];  dL_dE [device] FP64
+ *   [B];  dL_dF [device] FP32 [N][3].
+ * Sums are FP64 over fixed blocks added in block order (bitwise
+ * reproducible).  Uses the workspace of nn_energy_forces.
+ */
+nn_status nn_loss(const nn_system* sys, const nn_loss_params* lp, const double* E, const double* E_ref,
+                  const float* F, const float* F_ref, double* L, double* dL_dE, float* dL_dF, void* ws,
+                  size_t ws_bytes, void* stream);
+
 /* Langevin dynamics parameters (units: Angstrom, fs, eV, amu). */
 typedef struct {
   double dt;       /* time step, fs (> 0)                                   */

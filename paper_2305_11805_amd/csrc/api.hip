@@ -156,6 +156,7 @@ struct Layout {
   // weight gradient: per-atom stash, per-atom weights, chunk partials
   float *st_a1, *st_d1, *st_a2, *st_d2, *w_atom, *partial;
   float *st_t1, *st_x1, *st_x2;  // the force term's extra stash (a1_dot, x1, x2)
+  double* loss_partial;          // block sums of nn_loss
   float* jac;  // stored Jacobian (NN_STORE_JACOBIAN within the memory budget)
   size_t bytes;
 };
@@ -176,6 +177,8 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
   L.max_bins = 8 * N + 64 * (int64_t)B + 1;
   const int64_t scan_n = std::max<int64_t>(std::max<int64_t>(N, L.max_bins),
                                            std::max<int64_t>((int64_t)B, (int64_t)NN_MAX_SPECIES * ((N + 63) / 64 + 1)));
+  // first, so that every call's layout puts it at the same place
+  L.loss_partial = c.take<double>(loss_partial_elems(N, B));
   L.geom = c.take<StructGeom>(B);
   L.n_bins = c.take<int64_t>(B + 1);
   L.bin_base = c.take<int64_t>(B + 1);
@@ -833,6 +836,28 @@ nn_status nn_md_langevin(const nn_system* sys, double* pos, double* vel, const d
   }
   launch_md_update(N, kMdKick, pos, vel, inv_mass, F, nullptr, lp->dt, c1, c2_sqrt_kT, s);
   return check_launch("nn_md_langevin");
+}
+
+nn_status nn_loss(const nn_system* sys, const nn_loss_params* lp, const double* E, const double* E_ref,
+                  const float* F, const float* F_ref, double* L, double* dL_dE, float* dL_dF, void* ws,
+                  size_t ws_bytes, void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if (!lp) return fail(NN_E_INVALID, "loss parameters are NULL");
+  if ((lp->energy_kind != NN_LOSS_QUAD && lp->energy_kind != NN_LOSS_EXP) ||
+      (lp->force_kind != NN_LOSS_QUAD && lp->force_kind != NN_LOSS_EXP))
+    return fail(NN_E_INVALID, "unknown loss kind");
+  if (!isfinite(lp->energy_weight) || !isfinite(lp->force_weight)) return fail(NN_E_INVALID, "weights must be finite");
+  if (!L) return fail(NN_E_INVALID, "L is NULL");
+  if (sys->n_structs > 0 && (!E || !E_ref || !dL_dE)) return fail(NN_E_INVALID, "E/E_ref/dL_dE is NULL");
+  if ((F == nullptr) != (F_ref == nullptr)) return fail(NN_E_INVALID, "F and F_ref must both be given or both NULL");
+  if (F && sys->n_atoms > 0 && !dL_dF) return fail(NN_E_INVALID, "dL_dF is NULL");
+  Layout Lw = carve(nullptr, sys->n_atoms, sys->n_structs, 0, 0, 1, nullptr);
+  if (!ws || ws_bytes < Lw.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, Lw.bytes);
+  Lw = carve(ws, sys->n_atoms, sys->n_structs, 0, 0, 1, nullptr);
+  launch_loss(*lp, sys->atom_ptr, sys->n_structs, sys->n_atoms, E, E_ref, sys->n_atoms > 0 ? F : nullptr, F_ref, L,
+              dL_dE, dL_dF, Lw.loss_partial, (hipStream_t)stream);
+  return check_launch("nn_loss");
 }
 
 nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {

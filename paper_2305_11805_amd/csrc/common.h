@@ -260,6 +260,11 @@ void launch_pos_grad(const double* dL_dE, const int64_t* atom_ptr, int32_t B, in
                      float* dL_dpos, hipStream_t s);
 void launch_energy_reduce(const float* E_atom, const int64_t* atom_ptr, int32_t B, int64_t N, double* E_struct,
                           hipStream_t s);
+// loss.hip
+size_t loss_partial_elems(int64_t N, int32_t B);
+void launch_loss(const nn_loss_params& lp, const int64_t* atom_ptr, int32_t B, int64_t N, const double* E,
+                 const double* T, const float* F, const float* Fr, double* L, double* dL_dE, float* dL_dF,
+                 double* partial, hipStream_t s);
 // md.hip: one integrator update of the BAOAB Langevin splitting per atom.
 //   kMdHalfKickDrift: B A O A (the first step);
 //   kMdKickDrift:     a kick of dt (the previous step's last B and this

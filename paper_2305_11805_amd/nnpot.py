@@ -26,6 +26,8 @@ NN_BF16X3_MLP = 4
 NN_REUSE_DESCRIPTORS = 8
 NN_DESC_MBP = 0
 NN_DESC_BP = 1
+NN_LOSS_QUAD = 0
+NN_LOSS_EXP = 1
 ACT = {"linear": 0, "gaussian": 1, "relu": 2, "tanh": 3}
 STATUS = {0: "NN_OK", 1: "NN_E_INVALID", 2: "NN_E_CAPACITY", 3: "NN_E_CELL", 4: "NN_E_WORKSPACE",
           5: "NN_E_UNSUPPORTED", 6: "NN_E_HIP", 7: "NN_E_DEVICE"}
@@ -65,13 +67,18 @@ class nn_model(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("mlp", nn_mlp * NN_MAX_SPECIES)]
 
 
+class nn_loss_params(C.Structure):
+    _fields_ = [("energy_kind", C.c_int32), ("force_kind", C.c_int32), ("per_atom", C.c_int32),
+                ("energy_weight", C.c_double), ("force_weight", C.c_double)]
+
+
 class nn_langevin(C.Structure):
     _fields_ = [("dt", C.c_double), ("friction", C.c_double), ("kT", C.c_double)]
 
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_energy_forces", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset", "nn_check",
            "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
@@ -102,6 +109,8 @@ def lib():
         L.nn_descriptor_tangent.argtypes = [P, P, P, P, P, P]
         L.nn_md_langevin.restype = I32
         L.nn_md_langevin.argtypes = [P, P, P, P, P, C.c_double, C.c_double, P, P, I32, P, P, I32, P, P, P, SZ, P]
+        L.nn_loss.restype = I32
+        L.nn_loss.argtypes = [P, P, P, P, P, P, P, P, P, P, SZ, P]
         L.nn_energy_forces_grad.restype = I32
         L.nn_energy_forces_grad.argtypes = [P, P, P, P, I32, P, P, P, P, P, P, P, SZ, P]
         L.nn_autotune.restype = I32
@@ -200,6 +209,11 @@ def nn_md_langevin(sys, pos, vel, inv_mass, nl, rc, skin, params, model, flags, 
     _ok(lib().nn_md_langevin(C.byref(sys), _p(pos), _p(vel), _p(inv_mass), C.byref(nl), float(rc), float(skin),
                              C.byref(params), C.byref(model), flags, C.byref(lp), _p(noise), int(n_steps), _p(E_pot),
                              _p(F), _p(ws), ws.numel(), _stream(stream)))
+
+
+def nn_loss(sys, lp, E, E_ref, F, F_ref, L, dL_dE, dL_dF, ws, stream=None):
+    _ok(lib().nn_loss(C.byref(sys), C.byref(lp), _p(E), _p(E_ref), _p(F), _p(F_ref), _p(L), _p(dL_dE), _p(dL_dF),
+                      _p(ws), ws.numel(), _stream(stream)))
 
 
 def nn_autotune(sys, nl, params, model, flags, ws, stream=None) -> tuple:
@@ -384,6 +398,26 @@ class Potential:
         nn_md_langevin(self.sys, self.pos, vel, inv_mass, self.nl, self.rc, self.skin, self.params,
                        self.dmodel.struct, f, lp, noise, n_steps, E_pot, self.F, self.ws)
         return E_pot
+
+    def loss(self, E_ref, F_ref=None, energy_kind=NN_LOSS_QUAD, force_kind=NN_LOSS_QUAD, per_atom=False,
+             energy_weight=1.0, force_weight=1.0, E=None, F=None):
+        """(L [1], dL/dE [B], dL/dF [N, 3] or None) of the loss of Sec. II.A on
+        E (default self.E_struct) and F (default self.F) against the targets."""
+        torch = self.torch
+        E = self.E_struct if E is None else E
+        E_ref = torch.as_tensor(E_ref, dtype=torch.float64, device=self.dev).contiguous()
+        if F_ref is not None:
+            F = self.F if F is None else F
+            F_ref = torch.as_tensor(F_ref, dtype=torch.float32, device=self.dev).reshape(self.N, 3).contiguous()
+        else:
+            F = None
+        L = torch.empty(1, dtype=torch.float64, device=self.dev)
+        dE = torch.empty(self.B, dtype=torch.float64, device=self.dev)
+        dF = torch.empty((self.N, 3), dtype=torch.float32, device=self.dev) if F_ref is not None else None
+        lp = nn_loss_params(int(energy_kind), int(force_kind), int(bool(per_atom)), float(energy_weight),
+                            float(force_weight))
+        nn_loss(self.sys, lp, E, E_ref, F, F_ref, L, dE, dF, self.ws)
+        return L, dE, dF
 
     def autotune(self, flags: Optional[int] = None):
         """nn_autotune on the current list (build it first)."""
