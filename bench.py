@@ -91,7 +91,7 @@ def valid_neighbor_counts(pot, rc):
     return np.bincount(rows[valid], minlength=len(off) - 1)
 
 
-SOURCES = {"k_desc": "descriptors.hip", "k_mlp": "mlp.hip", "k_nb": "neighbors.hip"}
+SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp": "mlp.hip", "k_nb": "neighbors.hip"}
 
 
 def source_hash(kernel="k_desc_adj"):
@@ -524,6 +524,84 @@ def md_table2(args):
     print(json.dumps(out), flush=True)
 
 
+def stored_mode(args):
+    """The stored-Jacobian (precomputed-derivative) mode of Sec. II.A on
+    --config: a store step (list, descriptors with the Jacobian, MLP,
+    contraction, gather) and a reuse step (MLP, contraction and gather on the
+    stored descriptors and Jacobian: training over a fixed set), with the
+    achieved HBM GB/s of the two Jacobian kernels against 8 TB/s.  Prints one
+    JSON line."""
+    import torch
+    from paper_2305_11805_amd import nnpot, synth
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    w = synth.config(args.config, desc=args.desc)
+    s, p = w.system, w.params
+    big = 1 << 42
+    pot = nnpot.Potential(s, p, w.model, flags=nnpot.NN_STORE_JACOBIAN, mem_budget=big)
+    store_flags = nnpot.NN_STORE_JACOBIAN
+    reuse_flags = nnpot.NN_STORE_JACOBIAN | nnpot.NN_REUSE_DESCRIPTORS
+
+    def store():
+        nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+        nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, store_flags, big, pot.E_struct,
+                               pot.E_atom, pot.F, pot.ws)
+
+    def reuse():
+        nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, reuse_flags, big, pot.E_struct,
+                               pot.E_atom, pot.F, pot.ws)
+    for _ in range(max(args.warmup, 1)):
+        store()
+        reuse()
+    torch.cuda.synchronize()
+    nnpot.nn_check(pot.nl)
+    stream = torch.cuda.current_stream()
+    ms_store = _timed(torch, stream, store, args.steps) / args.steps
+    ms_reuse = _timed(torch, stream, reuse, args.steps) / args.steps
+    nnpot.nn_timing(True)
+    store()
+    reuse()
+    st = nnpot.nn_timing_read()
+    nnpot.nn_timing(False)
+    nnpot.nn_check(pot.nl)
+    entries = int(pot.offsets[-1].item())
+    js = nnpot.nn_jacobian_stride(pot.params)
+    # algorithmic bytes: the Jacobian rows written once and read once; the
+    # contraction also reads lambda and writes a 16-B pair gradient per entry
+    jac_bytes = 4.0 * js * entries
+    con_bytes = jac_bytes + 4.0 * s.n_atoms * p.dim + 16.0 * entries + 4.0 * entries
+    cnt = {}
+    prof = os.path.join(ROOT, "profiles", "counters.json")
+    if os.path.exists(prof):
+        with open(prof) as f:
+            cnt = json.load(f)
+
+    def kern(stage, name, alg):
+        ms_k = st[stage][0] / max(st[stage][1], 1)
+        e = {"avg_launch_ms": round(ms_k, 5), "algorithmic_bytes_per_launch": alg,
+             "gbs": round(alg / (ms_k / 1e3) / 1e9, 1), "frac_hbm": round(alg / (ms_k / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+        c = cnt.get(f"{name}:{w.name}")
+        if c and c.get("source_hash") == source_hash(name):
+            e["hbm_bytes_per_launch"] = c["hbm_bytes_per_launch"]
+            e["traffic_gbs"] = round(c["hbm_bytes_per_launch"] / (ms_k / 1e3) / 1e9, 1)
+        return e
+    res = {"workload": w.name, "step": "stored_jacobian", "n_atoms": s.n_atoms, "list_entries": entries,
+           "jacobian_floats_per_entry": js, "jacobian_gb": round(jac_bytes / 1e9, 3),
+           "store_step": {"ms": round(ms_store, 4), "atoms_per_s": round(s.n_atoms / ms_store * 1e3, 1)},
+           "reuse_step": {"ms": round(ms_reuse, 4), "atoms_per_s": round(s.n_atoms / ms_reuse * 1e3, 1)},
+           "kernels": {"k_desc_jac": kern("desc_jac", "k_desc_jac", jac_bytes),
+                       "k_jac_contract": kern("jac_contract", "k_jac_contract", con_bytes)},
+           "peak_hbm_gbs": PEAK_HBM_GBS}
+    if args.calib_copy_mib > 0:
+        a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+    print(json.dumps(res), flush=True)
+
+
 def suite(args):
     import torch
     if not torch.cuda.is_available():
@@ -557,6 +635,10 @@ def main():
                     help="measure every workload (one JSON line each) instead of the single bench line")
     ap.add_argument("--suite-configs", type=int, nargs="*", default=[0, 1, 2, 3, 4])
     ap.add_argument("--suite-out", default="suite.jsonl")
+    ap.add_argument("--stored", action="store_true",
+                    help="time the stored-Jacobian mode (store and reuse steps) on --config instead of the bench line")
+    ap.add_argument("--ingest-kernels", nargs="*", default=["k_desc_adj", "k_desc_fwd", "k_mlp"],
+                    help="kernels whose counters --ingest-counters keeps")
     ap.add_argument("--md", action="store_true",
                     help="Langevin dynamics of 16-atom cells (the Table II shape) instead of the bench line")
     ap.add_argument("--md-cells", type=int, default=1024, help="cells in the batched --md run")
@@ -578,10 +660,14 @@ def main():
     if args.md:
         md_table2(args)
         return
+    if args.stored:
+        stored_mode(args)
+        return
     if args.ingest_counters:
         if args.calib_copy_mib <= 0:
             raise SystemExit("--ingest-counters needs --calib-copy-mib of the profiled run")
-        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config, desc=args.desc).name)
+        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config, desc=args.desc).name,
+                        kernels=tuple(args.ingest_kernels))
         return
 
     import torch

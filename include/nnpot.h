@@ -189,7 +189,8 @@ int64_t nn_descriptor_dim(const nn_mbp_params* p);
  *   [0, n_rad)   d/dr of the radial bins of species s_j (gradient = value * d/r);
  *   [n_rad, +3)  the unit vector d/r;
  *   then, for partner species b = 0 .. S-1, the angular block (s_j, b) as
- *   [q][p] 3-vectors dG_i/dd_e.  Rows of entries at r >= rc are zero.
+ *   three component arrays x, y, z of dG_i/dd_e, each over the bins [q][p].
+ *   Rows of entries at r >= rc are zero.
  */
 int64_t nn_jacobian_stride(const nn_mbp_params* p);
 

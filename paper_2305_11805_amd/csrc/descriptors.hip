@@ -1275,8 +1275,8 @@ void launch_force_gather(const nn_system& sys, const nn_nlist& nl, const float4*
 //   [0, n_rad)        d/dr [exp(-eta_rad (r - Rs_k)^2) fc(r)] of the radial
 //                     bins of species s_j (the gradient is that times d/r);
 //   [n_rad, n_rad+3)  d/r;
-//   then for each partner species b = 0..S-1 the block (s_j, b) as NRA x NT
-//   3-vectors dG[(s_j,b)][q][p] / dd_e.
+//   then for each partner species b = 0..S-1 the block (s_j, b) as three
+//   component arrays (x, y, z), each of the NRA x NT bins dG[(s_j,b)][q][p] / dd_e.
 // Entries at r >= rc are all zero.  One lane per neighbor j walks every
 // partner k != j (both orders of each pair, so no lane writes another
 // lane's row); blocks are flushed when k enters the next species segment.
@@ -1426,12 +1426,12 @@ __global__ void __launch_bounds__(64) k_desc_jac(nn_system sys, const int64_t* _
         }
       }
       if (active) {
-        float* blk = row + P.n_rad + 3 + b * NB * 3;
+        float* blk = row + P.n_rad + 3 + b * NB * 3;  // x, y, z component arrays of NB bins each
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
-          blk[3 * t] = vx[t];
-          blk[3 * t + 1] = vy[t];
-          blk[3 * t + 2] = vz[t];
+          blk[t] = vx[t];
+          blk[NB + t] = vy[t];
+          blk[2 * NB + t] = vz[t];
         }
       }
     }
@@ -1439,7 +1439,11 @@ __global__ void __launch_bounds__(64) k_desc_jac(nn_system sys, const int64_t* _
 }
 
 // pg[e] = sum_d lambda_i[d] dG_i[d]/dd_e from the stored rows: one wave per
-// atom, one lane per entry, lambda of the atom in LDS.
+// atom, lambda of the atom in LDS, 16 lanes per entry (four entries at a
+// time).  The lanes of an entry stride over its row 16 floats at a time, so
+// every load is 64 contiguous bytes per entry; the component-major angular
+// blocks give bin t = 16 m + lane of each component without any division.
+// The 16 partial sums are combined by a fixed shuffle tree.
 template <int NT, int NRA>
 __global__ void __launch_bounds__(64) k_jac_contract(nn_system sys, const int64_t* __restrict__ offsets,
                                                      const int32_t* __restrict__ nbr, DescConst P,
@@ -1448,7 +1452,7 @@ __global__ void __launch_bounds__(64) k_jac_contract(nn_system sys, const int64_
   constexpr int NB = NT * NRA;
   extern __shared__ float lam[];  // [D]
   const int64_t i = blockIdx.x;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, sub = lane & 15, grp = lane >> 4;
   const int S = P.S;
   const int js = jac_stride(P.n_rad, S, NB);
   if (meta[kMetaValid] != 1) return;
@@ -1456,27 +1460,44 @@ __global__ void __launch_bounds__(64) k_jac_contract(nn_system sys, const int64_
   __syncthreads();
   const int64_t e0 = offsets[i], e1 = offsets[i + 1];
   const int ang0 = P.n_rad * S;
-  for (int64_t e = e0 + lane; e < e1; e += kWave) {
-    const float* row = J + e * js;
-    const int sj = sys.species[nbr[e]];
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    if (sj >= 0 && sj < S) {
-      float gr = 0.f;
-      for (int k = 0; k < P.n_rad; ++k) gr = fmaf(lam[sj * P.n_rad + k], row[k], gr);
-      gx = gr * row[P.n_rad];
-      gy = gr * row[P.n_rad + 1];
-      gz = gr * row[P.n_rad + 2];
-      for (int b = 0; b < S; ++b) {
-        const float* L = lam + ang0 + pair_block(S, sj, b) * NB;
-        const float* blk = row + P.n_rad + 3 + b * NB * 3;
-        for (int t = 0; t < NB; ++t) {
-          gx = fmaf(L[t], blk[3 * t], gx);
-          gy = fmaf(L[t], blk[3 * t + 1], gy);
-          gz = fmaf(L[t], blk[3 * t + 2], gz);
+  for (int64_t base = e0; base < e1; base += 4) {  // the same trip count in every lane
+    const int64_t e = base + grp;
+    float gr = 0.f, ax = 0.f, ay = 0.f, az = 0.f;
+    int sj = -1;
+    if (e < e1) {
+      sj = sys.species[nbr[e]];
+      if (sj >= 0 && sj < S) {
+        const float* row = J + e * js;
+        for (int k = sub; k < P.n_rad; k += 16) gr = fmaf(lam[sj * P.n_rad + k], row[k], gr);
+        for (int b = 0; b < S; ++b) {
+          const float* L = lam + ang0 + pair_block(S, sj, b) * NB;
+          const float* blk = row + P.n_rad + 3 + b * NB * 3;
+#pragma unroll
+          for (int m = 0; m < NB / 16; ++m) {
+            const int t = 16 * m + sub;
+            const float l = L[t];
+            ax = fmaf(l, blk[t], ax);
+            ay = fmaf(l, blk[NB + t], ay);
+            az = fmaf(l, blk[2 * NB + t], az);
+          }
         }
       }
     }
-    pg[e] = make_float4(gx, gy, gz, 0.f);
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      gr += __shfl_xor(gr, o, 16);
+      ax += __shfl_xor(ax, o, 16);
+      ay += __shfl_xor(ay, o, 16);
+      az += __shfl_xor(az, o, 16);
+    }
+    if (e < e1 && sub == 0) {
+      float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (sj >= 0 && sj < S) {
+        const float* u = J + e * js + P.n_rad;  // the unit vector d/r
+        g = make_float4(fmaf(gr, u[0], ax), fmaf(gr, u[1], ay), fmaf(gr, u[2], az), 0.f);
+      }
+      pg[e] = g;
+    }
   }
 }
 

@@ -29,7 +29,7 @@ def expand_jacobian(J, nl, species, p):
         out[e, sj * nr:(sj + 1) * nr, :] = row[:nr, None] * unit[None, :]
         for b in range(S):
             blk = blocks.index((min(sj, b), max(sj, b)))
-            v = row[nr + 3 + b * NB * 3: nr + 3 + (b + 1) * NB * 3].reshape(NB, 3)
+            v = row[nr + 3 + b * NB * 3: nr + 3 + (b + 1) * NB * 3].reshape(3, NB).T  # component-major
             out[e, ang0 + blk * NB: ang0 + (blk + 1) * NB, :] += v
     return out
 
