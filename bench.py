@@ -95,12 +95,14 @@ SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp": "ml
 
 
 def source_hash(kernel="k_desc_adj"):
-    """Hash of the source file a kernel is built from (counter figures are
-    used only while it matches)."""
+    """Hash of the source file a kernel is built from and of the compiler
+    flags (counter figures are used only while it matches)."""
+    from paper_2305_11805_amd import build as nnbuild
     src = next(v for k, v in SOURCES.items() if kernel.startswith(k))
     h = hashlib.sha256()
     with open(os.path.join(ROOT, "paper_2305_11805_amd", "csrc", src), "rb") as f:
         h.update(f.read())
+    h.update(" ".join(a for a in nnbuild.CFLAGS if not a.startswith("/")).encode())
     return h.hexdigest()[:16]
 
 
@@ -168,14 +170,17 @@ def ingest_kernel(fetch_csv, write_csv, calib_mib, workload, kernel):
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by the ratio of
     the known size of a plain device copy to what the counter read for it."""
     res = {}
+    runs = {name: read_pmc_csv(path, name) for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv))}
+    # one instantiation for both counters: of those both runs dispatched, the
+    # most frequent (the timed steps run one; the launch tuner also runs the
+    # others a few times each)
+    names = {name: [k for k, _ in rows if f"nnp::{kernel}" in k] for name, rows in runs.items()}
+    both = set(names["FETCH_SIZE"]) & set(names["WRITE_SIZE"])
+    if not both:
+        raise SystemExit(f"no {kernel} instantiation in both counter runs")
+    full = max(sorted(both), key=lambda k: names["FETCH_SIZE"].count(k) + names["WRITE_SIZE"].count(k))
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        rows = read_pmc_csv(path, name)
-        # the instantiation the timed steps ran is the most frequent one (the
-        # launch tuner also runs the others a few times each)
-        names = [k for k, _ in rows if f"nnp::{kernel}" in k]
-        if not names:
-            raise SystemExit(f"{path}: no {kernel} dispatch with {name}")
-        full = max(set(names), key=names.count)
+        rows = runs[name]
         mine = [v for k, v in rows if k == full]
         copies = [v for k, v in rows if "copyBuffer" in k]
         if not copies:

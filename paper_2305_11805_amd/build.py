@@ -23,6 +23,9 @@ ARCH = os.environ.get("NNPOT_ARCH", "gfx950")
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: no AGPR copies, and the unified
+    # register file then holds more waves of the MFMA kernels
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

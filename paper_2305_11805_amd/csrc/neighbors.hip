@@ -86,12 +86,18 @@ __global__ void k_scan_apply(const int64_t* __restrict__ in, int64_t n, const in
   if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = partial[nb];
 }
 
-// Whole scan in one block of 1024 threads (n <= kScanSmall): each thread
-// sums a contiguous run, runs are scanned with wave shuffles and one step
-// across the 16 wave totals, then each thread writes its run.  If n_dev is
+// Whole scan in one block of 1024 threads (n <= kScanSmall).  Up to
+// kScanRun elements per thread, thread t sums its own contiguous run.
+// Beyond that, wave w owns the contiguous chunk [w c, (w + 1) c) of the
+// input (c a multiple of 512) and takes it 512 elements at a time, lane l
+// the kScanRun consecutive elements from 8 l, so that every load of the
+// wave covers one contiguous stretch.  Either way: a pass for the run (or
+// chunk) sums, wave shuffles and one step across the 16 wave totals, then
+// a pass that writes the outputs on top of the running carry.  If n_dev is
 // given, only its first min(*n_dev, n) entries are scanned.
 constexpr int kScanSmallThreads = 1024;
 constexpr int64_t kScanSmall = 64 * 1024;
+constexpr int kScanRun = 8;
 
 struct CapacityJob {  // decision taken after the scan of the row counts
   int64_t capacity;
@@ -112,38 +118,83 @@ __global__ void __launch_bounds__(kScanSmallThreads) k_scan_small(const int64_t*
     }
     return;
   }
-  __shared__ int64_t wsum[kScanSmallThreads / 64];
+  constexpr int kW = kScanSmallThreads / 64;
+  constexpr int kGroup = 64 * kScanRun;
+  __shared__ int64_t wsum[kW];
   if (n_dev) n = min(n, max(*n_dev, (int64_t)0));
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int64_t per = (n + kScanSmallThreads - 1) / kScanSmallThreads;
-  const int64_t b = (int64_t)t * per, e = min(b + per, n);
-  int64_t sum = 0;
-  for (int64_t k = b; k < e; ++k) sum += in[k];
-  int64_t incl = sum;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int64_t v = __shfl_up(incl, off);
-    if (lane >= off) incl += v;
-  }
-  if (lane == 63) wsum[w] = incl;
-  __syncthreads();
-  if (w == 0) {
-    int64_t x = lane < kScanSmallThreads / 64 ? wsum[lane] : 0;
-    for (int off = 1; off < kScanSmallThreads / 64; off <<= 1) {
-      const int64_t v = __shfl_up(x, off);
-      if (lane >= off) x += v;
+  if (n <= (int64_t)kScanSmallThreads * kScanRun) {
+    const int64_t per = (n + kScanSmallThreads - 1) / kScanSmallThreads;
+    const int64_t b = min((int64_t)t * per, n), e = min(b + per, n);
+    int64_t sum = 0;
+    for (int64_t k = b; k < e; ++k) sum += in[k];
+    int64_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
     }
-    if (lane < kScanSmallThreads / 64) wsum[lane] = x;  // inclusive wave totals
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+      int64_t x = lane < kW ? wsum[lane] : 0;
+      for (int off = 1; off < kW; off <<= 1) {
+        const int64_t v = __shfl_up(x, off);
+        if (lane >= off) x += v;
+      }
+      if (lane < kW) wsum[lane] = x;  // inclusive wave totals
+    }
+    __syncthreads();
+    int64_t run = incl - sum + (w > 0 ? wsum[w - 1] : 0);
+    for (int64_t k = b; k < e; ++k) {
+      const int64_t v = in[k];
+      out[k] = run;
+      run += v;
+    }
+    if (t == kScanSmallThreads - 1) {
+      out[n] = wsum[kW - 1];
+      if (CAP) capacity_decision(cj, wsum[kW - 1]);
+    }
+    return;
   }
+  const int64_t chunk = ((n + kW - 1) / kW + kGroup - 1) / kGroup * kGroup;
+  const int64_t b = min((int64_t)w * chunk, n), e = min(b + chunk, n);
+  int64_t sum = 0;
+  for (int64_t k0 = b + kScanRun * lane; k0 < e; k0 += kGroup) {
+#pragma unroll
+    for (int r = 0; r < kScanRun; ++r) sum += k0 + r < e ? in[k0 + r] : 0;
+  }
+  for (int off = 32; off >= 1; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane == 0) wsum[w] = sum;
   __syncthreads();
-  int64_t run = incl - sum + (w > 0 ? wsum[w - 1] : 0);
-  for (int64_t k = b; k < e; ++k) {
-    const int64_t v = in[k];
-    out[k] = run;
-    run += v;
+  int64_t carry = 0;
+  for (int u = 0; u < w; ++u) carry += wsum[u];
+  for (int64_t g0 = b; g0 < e; g0 += kGroup) {
+    const int64_t k0 = g0 + kScanRun * lane;
+    int64_t v[kScanRun];
+    int64_t ls = 0;
+#pragma unroll
+    for (int r = 0; r < kScanRun; ++r) {
+      v[r] = k0 + r < e ? in[k0 + r] : 0;
+      ls += v[r];
+    }
+    int64_t incl = ls;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t x = __shfl_up(incl, off);
+      if (lane >= off) incl += x;
+    }
+    int64_t run = carry + incl - ls;
+#pragma unroll
+    for (int r = 0; r < kScanRun; ++r) {
+      if (k0 + r < e) out[k0 + r] = run;
+      run += v[r];
+    }
+    carry += __shfl(incl, 63);
   }
   if (t == kScanSmallThreads - 1) {
-    out[n] = wsum[kScanSmallThreads / 64 - 1];
-    if (CAP) capacity_decision(cj, wsum[kScanSmallThreads / 64 - 1]);
+    int64_t total = 0;
+    for (int u = 0; u < kW; ++u) total += wsum[u];
+    out[n] = total;
+    if (CAP) capacity_decision(cj, total);
   }
 }
 
