@@ -224,7 +224,8 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
   __shared__ __align__(16) float buf[2][kTile * LD];
   __shared__ float epart[kWaves][kTile];
   __shared__ int32_t rows[kTile];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile tests become scalar branches
   const int S = args.model.S;
   // which species / tile
   int64_t t = blockIdx.x;
@@ -251,6 +252,49 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
   bf16x8 ah{}, al{}, bh{}, bl{};
   float* bufA = buf[0];
   float* bufB = buf[1];
+  // FP32 with 16-byte aligned G and weights and D a multiple of 32: every
+  // operand load is an unguarded vector or scalar load, so each product
+  // can issue all of its weight loads before its first MFMA
+  // (shapes whose prefetch buffers fit in 192 registers per lane)
+  constexpr int kPre = (H1 / 16) * T2 * 4 + (H2 / 16) * T1 * 4 + 2 * (H1 / 16) * 4;
+  constexpr bool kFastOK = !BF && kPre <= 192;
+  const bool fast = kFastOK && D % 32 == 0 &&
+                    ((((uintptr_t)args.G) | ((uintptr_t)M.W[0]) | ((uintptr_t)M.W[1])) & 15) == 0;
+  constexpr int KB1 = kFastOK ? H1 / 16 : 1, KB2 = kFastOK ? H2 / 16 : 1;
+  float4 w2f[KB1][T2];     // layer 2: B fragments of W2 [H2][H1] (rows n, 4 consecutive k)
+  float w2t[KB2][T1][4];   // delta1: B fragments of W2 read by columns
+  float w1t[2][KB1][4];    // lambda: B fragments of W1 read by columns, two column tiles
+  auto prefetch_w2 = [&]() {
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb)
+#pragma unroll
+      for (int u = 0; u < T2; ++u) {
+        const int n = wv + kWaves * u;
+        w2f[kb][u] = *reinterpret_cast<const float4*>(M.W[1] + (int64_t)((n < H2T ? n : 0) * 16 + lm) * H1 +
+                                                      16 * kb + 4 * lk);
+      }
+  };
+  auto prefetch_w2t = [&]() {
+#pragma unroll
+    for (int kb = 0; kb < KB2; ++kb) {
+      const float* w = M.W[1] + (int64_t)(16 * kb + 4 * lk) * H1 + lm;
+#pragma unroll
+      for (int u = 0; u < T1; ++u) {
+        const int n = wv + kWaves * u;
+        const int c = (n < H1T ? n : 0) * 16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w2t[kb][u][i] = w[i * H1 + c];
+      }
+    }
+  };
+  auto prefetch_w1t = [&](int tile, int slot) {  // column tile `tile` of lambda (tile < D / 16)
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) {
+      const float* w = M.W[0] + (int64_t)(16 * kb + 4 * lk) * D + tile * 16 + lm;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w1t[slot][kb][i] = w[i * D];
+    }
+  };
 
   // ---- layer 1: z1 = G W1^T + b1 (this wave's tiles n = wv + kWaves * u) ----
   floatx4 acc1[T1];
@@ -275,6 +319,43 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
           acc1[u] = mma_bf16<MODE>(acc1[u], ah, al, bh, bl);
         }
       }
+    }
+  } else if (fast) {
+    // weights of the next two products are requested now and arrive while
+    // this one runs; the k steps of this one are double-buffered
+    prefetch_w2();
+    // rows past the tile's atoms read row 0 of G (Grow): every product is
+    // row by row and such rows are never stored, so their values do not matter
+    const float* w1row[T1];
+#pragma unroll
+    for (int u = 0; u < T1; ++u) {
+      const int n = wv + kWaves * u;
+      w1row[u] = M.W[0] + (int64_t)((n < H1T ? n : 0) * 16 + lm) * D;
+    }
+    float4 xa[2], xb[2][T1], ya[2], yb[2][T1];  // two k steps in flight
+    auto fetch = [&](int k0, float4(&a)[2], float4(&b)[2][T1]) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = k0 + 16 * q + 4 * lk;
+        a[q] = *reinterpret_cast<const float4*>(Grow + k);
+#pragma unroll
+        for (int u = 0; u < T1; ++u) b[q][u] = *reinterpret_cast<const float4*>(w1row[u] + k);
+      }
+    };
+    auto step = [&](const float4(&a)[2], const float4(&b)[2][T1]) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int u = 0; u < T1; ++u)
+          if (H1T % kWaves == 0 || wv + kWaves * u < H1T) acc1[u] = mma4_f32(acc1[u], a[q], b[q][u]);
+    };
+    fetch(0, xa, xb);
+    for (int k0 = 0; k0 < D; k0 += 64) {
+      if (k0 + 32 < D) fetch(k0 + 32, ya, yb);
+      step(xa, xb);
+      if (k0 + 32 >= D) break;
+      if (k0 + 64 < D) fetch(k0 + 64, xa, xb);
+      step(ya, yb);
     }
   } else {
     const float* W1 = M.W[0];
@@ -335,6 +416,15 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
           acc2[u] = mma_bf16<MODE>(acc2[u], ah, al, bh, bl);
         }
       }
+    }
+  } else if (fast) {
+    if (args.lambda != nullptr || args.st_d1 != nullptr) prefetch_w2t();
+#pragma unroll
+    for (int kb = 0; kb < KB1; ++kb) {
+      const float4 a = *reinterpret_cast<const float4*>(bufA + lm * LD + 16 * kb + 4 * lk);
+#pragma unroll
+      for (int u = 0; u < T2; ++u)
+        if (H2T % kWaves == 0 || wv + kWaves * u < H2T) acc2[u] = mma4_f32(acc2[u], a, w2f[kb][u]);
     }
   } else {
     const float* W2 = M.W[1];
@@ -412,6 +502,16 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
         }
       }
     }
+  } else if (fast) {
+    if (args.lambda != nullptr && wv < D / 16) prefetch_w1t(wv, 0);
+#pragma unroll
+    for (int kb = 0; kb < KB2; ++kb) {
+      const float4 a = *reinterpret_cast<const float4*>(bufB + lm * LD + 16 * kb + 4 * lk);
+#pragma unroll
+      for (int u = 0; u < T1; ++u)
+        if (H1T % kWaves == 0 || wv + kWaves * u < H1T)
+          acc1[u] = mma4_f32(acc1[u], a, make_float4(w2t[kb][u][0], w2t[kb][u][1], w2t[kb][u][2], w2t[kb][u][3]));
+    }
   } else {
     const float* W2 = M.W[1];  // [H2][H1]: B[k][n] = W2[k][n]
 #pragma unroll
@@ -452,6 +552,34 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
   __syncthreads();
   // ---- lambda = delta1 W1: D columns, 16-column tiles dealt to the waves ----
   const int DT = (D + 15) / 16;
+  if constexpr (!BF) {
+    if (fast) {
+      // tile wv was requested before the delta1 products; each tile's
+      // loads are issued before the previous tile's products
+      for (int tile = wv; tile < DT; tile += kWaves) {
+        const bool more = tile + kWaves < DT;
+        if (more) prefetch_w1t(tile + kWaves, 1);
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KB1; ++kb) {
+          const float4 a = *reinterpret_cast<const float4*>(bufA + lm * LD + 16 * kb + 4 * lk);
+          acc = mma4_f32(acc, a, make_float4(w1t[0][kb][0], w1t[0][kb][1], w1t[0][kb][2], w1t[0][kb][3]));
+        }
+        const int col = tile * 16 + lm;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = rows[4 * lk + j];
+          if (r >= 0) args.lambda[(int64_t)r * D + col] = acc[j];
+        }
+        if (more)
+#pragma unroll
+          for (int kb = 0; kb < KB1; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w1t[0][kb][i] = w1t[1][kb][i];
+      }
+      return;
+    }
+  }
   constexpr int CH = 4;
   for (int c0 = wv; c0 < DT; c0 += kWaves * CH) {
     floatx4 acc[CH];
