@@ -357,6 +357,8 @@ __device__ __forceinline__ BpSide bp_side64(const double* __restrict__ dj, const
   return b;
 }
 
+constexpr int kFuseTriplets = 256;  // triplets per atom for the pair-block-per-MFMA-block forward
+
 template <int NT, int NRA, int WPA, int ZC>
 __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ nbr,
@@ -422,6 +424,97 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
       __syncthreads();
     }
   }
+  const int ang0 = P.n_rad * S;
+  constexpr int NP = NT / 4, NQ = NRA / 4;
+  const int li = lane & 3, blk = lane >> 2;
+  // Few triplets (a small molecule with several species): one chunk of 64
+  // triplets, a reduction and the stores per species-pair block would
+  // mostly idle.  Instead 4-lane MFMA block b of the (single) wave takes
+  // species-pair block b (S(S+1)/2 <= 16) and walks its triplets, its lane
+  // i supplying A_(4u+i) and R_(4v+i) F2 of each, so that the block's
+  // accumulators end up holding exactly that pair block's bins: no
+  // reduction across lanes, no LDS beyond the neighbor staging.
+  const int nblk = S * (S + 1) / 2;
+  if (WPA == 1 && nblk > 1 && nblk <= 16 && nb.n * (nb.n - 1) / 2 <= kFuseTriplets) {
+    int pa = 0, rem = blk < nblk ? blk : 0;
+    while (rem >= S - pa) {
+      rem -= S - pa;
+      ++pa;
+    }
+    const int pb = pa + rem;
+    const int na = nb.seg[pa + 1] - nb.seg[pa], nbb = nb.seg[pb + 1] - nb.seg[pb];
+    const int Tb = blk < nblk ? (pa == pb ? na * (na - 1) / 2 : na * nbb) : 0;
+    int Tmax = Tb;
+    for (int o = 32; o >= 1; o >>= 1) Tmax = max(Tmax, __shfl_xor(Tmax, o));
+    const int m = pa == pb ? na : nbb;
+    const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
+    floatx4 acc[NP][NQ];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < Tmax; ++t) {
+      int j = 0, k = 0;  // past the block's triplets: any neighbor, with F2 = 0
+      if (t < Tb) {
+        int q, r;
+        divmod_small(t, m, inv_m, q, r);
+        if (pa == pb) {  // the unordered pairs {j, (j + s) mod na}, numbered (s - 1) na + j
+          int kk = r + q + 1;
+          if (kk >= na) kk -= na;
+          j = nb.seg[pa] + r;
+          k = nb.seg[pa] + kk;
+        } else {
+          j = nb.seg[pa] + q;
+          k = nb.seg[pb] + r;
+        }
+      }
+      const float4 fu = nb.f[j], fv = nb.f[k];
+      float A[NP], R[NQ];
+      if constexpr (ZC == kZcBP) {
+        const float4 u = nb.d[j], v = nb.d[k];
+        const float px = u.x + v.x, py = u.y + v.y, pz = u.z + v.z;
+        const float mx = u.x - v.x, my = u.y - v.y, mz = u.z - v.z;
+        const BpSide w3 = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
+        const float gp = 0.5f * fmaf(px, px, fmaf(py, py, pz * pz));
+        const float gm = 0.5f * fmaf(mx, mx, fmaf(my, my, mz * mz));
+        const float s2 = fmaf(u.w, u.w, fmaf(v.w, v.w, w3.rw2));
+        const float F2 = t < Tb ? fu.x * fv.x * w3.fw : 0.f;
+#pragma unroll
+        for (int uu = 0; uu < NP; ++uu)
+          A[uu] = P.bp_pref[4 * uu + li] *
+                  ipow_rt(P.bp_lam[4 * uu + li] > 0.f ? gp : gm, P.bp_zeta[4 * uu + li], P.bp_zbits);
+#pragma unroll
+        for (int vv = 0; vv < NQ; ++vv) R[vv] = fexp2(-(P.bp_eta[4 * vv + li] * 1.4426950408889634f) * s2) * F2;
+      } else {
+        const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
+        const float F2 = t < Tb ? 2.0f * fu.x * fv.x : 0.f;
+        float x[NP];
+#pragma unroll
+        for (int uu = 0; uu < NP; ++uu)
+          x[uu] = fmaf(g.c, P.x_a[4 * uu + li], fmaf(g.ssm, P.x_b[4 * uu + li], P.x_c));
+        ipow_sel<(ZC > 0 ? ZC : 0), NP>(x, P.zeta, A);
+#pragma unroll
+        for (int vv = 0; vv < NQ; ++vv) {
+          const float dq = (g.rbar - P.rs_ang[4 * vv + li]) + (g.rbar_lo - P.rs_ang_lo[4 * vv + li]);
+          R[vv] = fexp2(-eta_a2 * dq * dq) * F2;
+        }
+      }
+#pragma unroll
+      for (int uu = 0; uu < NP; ++uu)
+#pragma unroll
+        for (int vv = 0; vv < NQ; ++vv) acc[uu][vv] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[uu], R[vv], acc[uu][vv], 0, 0, 0);
+    }
+    if (blk < nblk) {
+      float* out = Gi + ang0 + blk * NB;  // blk is the pair block's index in the layout order
+#pragma unroll
+      for (int uu = 0; uu < NP; ++uu)
+#pragma unroll
+        for (int vv = 0; vv < NQ; ++vv)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[(4 * vv + li) * NT + 4 * uu + r] = acc[uu][vv][r];
+    }
+    return;
+  }
   // angular blocks: the bins are a sum over triplets of the outer product
   // A_p R_q F2, taken on the 4x4x1 FP32 MFMA (16 blocks of 4 lanes, block b
   // = lanes 4b..4b+3; lane 4b+i gives row i of A and column i of B, and
@@ -429,9 +522,6 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   // each lane first forms one triplet's geometry into LDS; then each 4-lane
   // block takes one triplet of every group of 16 and its lane i supplies
   // A_(4P+i) and R_(4Q+i) F2.  The 16 blocks' sums are added at the end.
-  const int ang0 = P.n_rad * S;
-  constexpr int NP = NT / 4, NQ = NRA / 4;
-  const int li = lane & 3, blk = lane >> 2;
   // this lane's angle terms p = 4u + li and radius terms q = 4v + li
   float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
   int zexp[NP];
@@ -693,6 +783,139 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
       rsq_lo[u] = P.rs_ang_lo[4 * u + li];
     }
   }
+  // one triplet's geometry and tangents: (cos, ...) in geo, the factors'
+  // tangents in dot and g2 (the layout the factor step below reads)
+  auto trip_terms = [&](int j, int k, float4& geo, float4& dot, float& g2) {
+    const float4 u = nb.d[j], v = nb.d[k];
+    const float4 fu = nb.f[j], fv = nb.f[k];
+    const float4 wj = tw[j], wk = tw[k];
+    const float cdot0 = fmaf(v.x, wj.x, fmaf(v.y, wj.y, v.z * wj.z)) + fmaf(u.x, wk.x, fmaf(u.y, wk.y, u.z * wk.z));
+    if constexpr (ZC == kZcBP) {
+      // s2_dot = 2 (r_j r_j_dot + r_k r_k_dot + w . (delta_k - delta_j)),
+      // F3_dot = fc'_j r_j_dot fc_k fc_w + fc_j fc'_k r_k_dot fc_w + fc_j fc_k fc'_w (w^ . (delta_k - delta_j))
+      const BpSide g = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
+      const float c = fmaf(u.x, v.x, fmaf(u.y, v.y, u.z * v.z));
+      const float cdot = cdot0 - c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
+      const float ddx = fmaf(wk.x, v.w, -wj.x * u.w), ddy = fmaf(wk.y, v.w, -wj.y * u.w),
+                  ddz = fmaf(wk.z, v.w, -wj.z * u.w);
+      const float wdd = fmaf(g.wx, ddx, fmaf(g.wy, ddy, g.wz * ddz));
+      const float s2dot = 2.0f * fmaf(u.w, wj.w, fmaf(v.w, wk.w, wdd));
+      const float F3 = fu.x * fv.x * g.fw;
+      const float F3dot = fmaf(fu.y * wj.w, fv.x * g.fw, fu.x * fv.y * wk.w * g.fw) +
+                          (g.rw > 0.f ? fu.x * fv.x * g.dfw * wdd * frcp(g.rw) : 0.f);
+      geo = make_float4(c, fmaf(u.w, u.w, fmaf(v.w, v.w, g.rw2)), 0.f, 0.f);
+      dot = make_float4(F3, cdot, F3dot, 0.f);
+      g2 = s2dot * F3;
+    } else {
+      const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
+      const float cdot = cdot0 - g.c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
+      const float sdot = -g.c * cdot * frcp(g.ssm);
+      const float F2 = 2.0f * fu.x * fv.x;
+      const float F2dot = 2.0f * fmaf(fu.y * wj.w, fv.x, fu.x * fv.y * wk.w);
+      const float rbdot = 0.5f * (wj.w + wk.w);
+      geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
+      dot = make_float4(F2, zf * cdot, zf * sdot, F2dot);
+      g2 = -2.0f * P.eta_ang * rbdot * F2;
+    }
+  };
+  // this lane's factors of one triplet: angle terms 4u + li and radius terms
+  // 4v + li with their tangents
+  auto lane_factors = [&](const float4& q4, const float4& d4, float h2, float (&A)[NP], float (&Ad)[NP],
+                          float (&RF)[NQ], float (&RT)[NQ]) {
+    if constexpr (ZC == kZcBP) {
+      // A = pref base^zeta, A_dot = pref zeta lambda base^(zeta-1) cos_dot;
+      // R F3 and R (F3_dot - eta s2_dot F3)
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        const float base = fmaf(xb[u], q4.x, 1.0f);
+        const float P1 = ipow_rt(base, zexp[u] - 1, P.bp_zbits);
+        A[u] = xa[u] * P1 * base;
+        Ad[u] = xa[u] * (float)zexp[u] * xb[u] * P1 * d4.y;
+      }
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        const float R = fexp2(-rsq[v] * q4.y);
+        RF[v] = R * d4.x;
+        RT[v] = R * fmaf(-rsq_lo[v], h2, d4.z);
+      }
+    } else {
+      float x[NP], P1[NP];
+#pragma unroll
+      for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+      ipow_sel<(ZC > 0 ? ZC - 1 : 0), NP>(x, zeta1, P1);
+#pragma unroll
+      for (int u = 0; u < NP; ++u) {
+        A[u] = P1[u] * x[u];
+        Ad[u] = P1[u] * fmaf(xa[u], d4.y, xb[u] * d4.z);
+      }
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
+        const float R = fexp2(-eta_a2 * dq * dq);
+        RF[v] = R * d4.x;
+        RT[v] = R * fmaf(h2, dq, d4.w);
+      }
+    }
+  };
+  // few triplets with several species: 4-lane block b walks the triplets of
+  // species-pair block b (as in the forward pass)
+  const int nblk = S * (S + 1) / 2;
+  if (WPA == 1 && nblk > 1 && nblk <= 16 && nb.n * (nb.n - 1) / 2 <= kFuseTriplets) {
+    int pa = 0, rem = blk < nblk ? blk : 0;
+    while (rem >= S - pa) {
+      rem -= S - pa;
+      ++pa;
+    }
+    const int pb = pa + rem;
+    const int na = nb.seg[pa + 1] - nb.seg[pa], nbb = nb.seg[pb + 1] - nb.seg[pb];
+    const int Tb = blk < nblk ? (pa == pb ? na * (na - 1) / 2 : na * nbb) : 0;
+    int Tmax = Tb;
+    for (int o = 32; o >= 1; o >>= 1) Tmax = max(Tmax, __shfl_xor(Tmax, o));
+    const int m = pa == pb ? na : nbb;
+    const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
+    floatx4 acc[NP][NQ];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < Tmax; ++t) {
+      float4 geo = make_float4(1.f, 0.f, 0.f, 0.f), dot = make_float4(0.f, 0.f, 0.f, 0.f);
+      float g2 = 0.f;  // all zero past the block's triplets: such terms add nothing
+      if (t < Tb) {
+        int q, r, j, k;
+        divmod_small(t, m, inv_m, q, r);
+        if (pa == pb) {
+          int kk = r + q + 1;
+          if (kk >= na) kk -= na;
+          j = nb.seg[pa] + r;
+          k = nb.seg[pa] + kk;
+        } else {
+          j = nb.seg[pa] + q;
+          k = nb.seg[pb] + r;
+        }
+        trip_terms(j, k, geo, dot, g2);
+      }
+      float A[NP], Ad[NP], RF[NQ], RT[NQ];
+      lane_factors(geo, dot, g2, A, Ad, RF, RT);
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) {
+          acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ad[u], RF[v], acc[u][v], 0, 0, 0);
+          acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[u], RT[v], acc[u][v], 0, 0, 0);
+        }
+    }
+    if (blk < nblk) {
+      float* out = Ui + ang0 + blk * NB;
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[(4 * v + li) * NT + 4 * u + r] = acc[u][v][r];
+    }
+    return;
+  }
   for (int a = 0; a < S; ++a) {
     for (int b = a; b < S; ++b) {
       const int na = nb.seg[a + 1] - nb.seg[a], nbb = nb.seg[b + 1] - nb.seg[b];
@@ -720,37 +943,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
             j = nb.seg[a] + q;
             k = nb.seg[b] + r;
           }
-          const float4 u = nb.d[j], v = nb.d[k];
-          const float4 fu = nb.f[j], fv = nb.f[k];
-          const float4 wj = tw[j], wk = tw[k];
-          const float cdot0 = fmaf(v.x, wj.x, fmaf(v.y, wj.y, v.z * wj.z)) + fmaf(u.x, wk.x, fmaf(u.y, wk.y, u.z * wk.z));
-          if constexpr (ZC == kZcBP) {
-            // s2_dot = 2 (r_j r_j_dot + r_k r_k_dot + w . (delta_k - delta_j)),
-            // F3_dot = fc'_j r_j_dot fc_k fc_w + fc_j fc'_k r_k_dot fc_w + fc_j fc_k fc'_w (w^ . (delta_k - delta_j))
-            const BpSide g = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
-            const float c = fmaf(u.x, v.x, fmaf(u.y, v.y, u.z * v.z));
-            const float cdot = cdot0 - c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
-            const float ddx = fmaf(wk.x, v.w, -wj.x * u.w), ddy = fmaf(wk.y, v.w, -wj.y * u.w),
-                        ddz = fmaf(wk.z, v.w, -wj.z * u.w);
-            const float wdd = fmaf(g.wx, ddx, fmaf(g.wy, ddy, g.wz * ddz));
-            const float s2dot = 2.0f * fmaf(u.w, wj.w, fmaf(v.w, wk.w, wdd));
-            const float F3 = fu.x * fv.x * g.fw;
-            const float F3dot = fmaf(fu.y * wj.w, fv.x * g.fw, fu.x * fv.y * wk.w * g.fw) +
-                                (g.rw > 0.f ? fu.x * fv.x * g.dfw * wdd * frcp(g.rw) : 0.f);
-            geo = make_float4(c, fmaf(u.w, u.w, fmaf(v.w, v.w, g.rw2)), 0.f, 0.f);
-            dot = make_float4(F3, cdot, F3dot, 0.f);
-            g2 = s2dot * F3;
-          } else {
-            const TripGeom g = triplet_geom(u, fu, v, fv, P.eps_ang);
-            const float cdot = cdot0 - g.c * fmaf(wj.w, nb.ir[j], wk.w * nb.ir[k]);
-            const float sdot = -g.c * cdot * frcp(g.ssm);
-            const float F2 = 2.0f * fu.x * fv.x;
-            const float F2dot = 2.0f * fmaf(fu.y * wj.w, fv.x, fu.x * fv.y * wk.w);
-            const float rbdot = 0.5f * (wj.w + wk.w);
-            geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
-            dot = make_float4(F2, zf * cdot, zf * sdot, F2dot);
-            g2 = -2.0f * P.eta_ang * rbdot * F2;
-          }
+          trip_terms(j, k, geo, dot, g2);
         }
         tgeo[wv][lane] = geo;
         tdot[wv][lane] = dot;
@@ -762,40 +955,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
           const float4 d4 = tdot[wv][16 * gi + blk];
           const float h2 = tg2[wv][16 * gi + blk];
           float A[NP], Ad[NP], RF[NQ], RT[NQ];
-          if constexpr (ZC == kZcBP) {
-            // A = pref base^zeta, A_dot = pref zeta lambda base^(zeta-1) cos_dot;
-            // R F3 and R (F3_dot - eta s2_dot F3)
-#pragma unroll
-            for (int u = 0; u < NP; ++u) {
-              const float base = fmaf(xb[u], q4.x, 1.0f);
-              const float P1 = ipow_rt(base, zexp[u] - 1, P.bp_zbits);
-              A[u] = xa[u] * P1 * base;
-              Ad[u] = xa[u] * (float)zexp[u] * xb[u] * P1 * d4.y;
-            }
-#pragma unroll
-            for (int v = 0; v < NQ; ++v) {
-              const float R = fexp2(-rsq[v] * q4.y);
-              RF[v] = R * d4.x;
-              RT[v] = R * fmaf(-rsq_lo[v], h2, d4.z);
-            }
-          } else {
-            float x[NP], P1[NP];
-#pragma unroll
-            for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
-            ipow_sel<(ZC > 0 ? ZC - 1 : 0), NP>(x, zeta1, P1);
-#pragma unroll
-            for (int u = 0; u < NP; ++u) {
-              A[u] = P1[u] * x[u];
-              Ad[u] = P1[u] * fmaf(xa[u], d4.y, xb[u] * d4.z);
-            }
-#pragma unroll
-            for (int v = 0; v < NQ; ++v) {
-              const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
-              const float R = fexp2(-eta_a2 * dq * dq);
-              RF[v] = R * d4.x;
-              RT[v] = R * fmaf(h2, dq, d4.w);
-            }
-          }
+          lane_factors(q4, d4, h2, A, Ad, RF, RT);
 #pragma unroll
           for (int u = 0; u < NP; ++u)
 #pragma unroll
