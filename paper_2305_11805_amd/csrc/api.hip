@@ -72,7 +72,7 @@ static LaunchPlan plan_for(int64_t n_atoms, int64_t capacity, const DescConst& P
   const PlanKey k = plan_key(n_atoms, capacity, P, model, mode);
   std::lock_guard<std::mutex> g(g_pmu);
   auto it = g_plans.find(k);
-  return it != g_plans.end() ? it->second : plan_default(n_atoms);
+  return it != g_plans.end() ? it->second : plan_default(n_atoms, P.S, capacity);
 }
 
 // ---------------------------------------------------------------------------
@@ -532,7 +532,7 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   hipStream_t s = (hipStream_t)stream;
   {
     StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, plan_default(sys->n_atoms).wpa_fwd, s);
+    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, plan_default(sys->n_atoms, P.S, nl->capacity).wpa_fwd, s);
   }
   if (jac) {
     StageTimer t(NN_STAGE_DESC_JAC, s);
@@ -551,7 +551,7 @@ nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const 
   if ((!v || !U) && sys->n_atoms > 0) return fail(NN_E_INVALID, "v/U is NULL");
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   hipStream_t s = (hipStream_t)stream;
-  launch_desc_tan(*sys, *nl, P, v, U, plan_default(sys->n_atoms).wpa_fwd, s);
+  launch_desc_tan(*sys, *nl, P, v, U, plan_default(sys->n_atoms, P.S, nl->capacity).wpa_fwd, s);
   return check_launch("nn_descriptor_tangent");
 }
 
@@ -653,7 +653,7 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
   if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
   L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
   const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
-  LaunchPlan best = plan_default(N);
+  LaunchPlan best = plan_default(N, P.S, nl->capacity);
   if (N > 0) {
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -155,7 +155,7 @@ struct IdentityGroup {
 struct LaunchPlan {
   int wpa_fwd, wpa_adj, mlp_waves;
 };
-LaunchPlan plan_default(int64_t n_atoms);
+LaunchPlan plan_default(int64_t n_atoms, int n_species, int64_t capacity);
 void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
                      int wpa, hipStream_t s);
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,

@@ -1292,9 +1292,13 @@ __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* 
 
 // Waves per atom: two when the atoms alone would leave the SIMDs with few
 // waves to switch between, one otherwise.
-LaunchPlan plan_default(int64_t n_atoms) {
+LaunchPlan plan_default(int64_t n_atoms, int n_species, int64_t capacity) {
   const int w = n_atoms <= 16384 ? 2 : 1;
-  return LaunchPlan{w, w, 0};
+  LaunchPlan plan{w, w, 0};
+  // several species and short rows (small molecules): one wave per atom, so
+  // that the forward and tangent passes take one MFMA block per species pair
+  if (n_species > 1 && n_atoms > 0 && capacity <= 24 * n_atoms) plan.wpa_fwd = 1;
+  return plan;
 }
 
 template <int NT, int NRA, int WPA, int ZC>

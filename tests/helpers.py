@@ -51,3 +51,23 @@ def oracle_sampled_forces(w, targets):
     nl = oracle.neighbors_cells(s, p.rc, rows=rows)
     E_rows, F = oracle.forces(p, w.model, s, nl, np.asarray(targets, np.int64))
     return rows, E_rows, F
+
+
+def block_bounds(p):
+    """Column ranges of the descriptor blocks (radial per species, angular per pair)."""
+    S, nr, nb = p.n_species, p.n_rad, p.n_theta * p.n_rs_ang
+    out = [(s * nr, (s + 1) * nr) for s in range(S)]
+    a0 = S * nr
+    for k in range(S * (S + 1) // 2):
+        out.append((a0 + k * nb, a0 + (k + 1) * nb))
+    return out
+
+
+def tangent_error(U, U_ref, p):
+    """Max over rows and blocks of |dU| / (largest |U_ref| of that block in that row)."""
+    worst = 0.0
+    for c0, c1 in block_bounds(p):
+        ref = U_ref[:, c0:c1]
+        scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-30)
+        worst = max(worst, float((np.abs(U[:, c0:c1] - ref) / scale).max()))
+    return worst
