@@ -427,101 +427,6 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   const int ang0 = P.n_rad * S;
   constexpr int NP = NT / 4, NQ = NRA / 4;
   const int li = lane & 3, blk = lane >> 2;
-  // Few triplets (a small molecule with several species): one chunk of 64
-  // triplets, a reduction and the stores per species-pair block would
-  // mostly idle.  Instead 4-lane MFMA block b of the (single) wave takes
-  // species-pair block b (S(S+1)/2 <= 16) and walks its triplets, its lane
-  // i supplying A_(4u+i) and R_(4v+i) F2 of each, so that the block's
-  // accumulators end up holding exactly that pair block's bins: no
-  // reduction across lanes, no LDS beyond the neighbor staging.
-  const int nblk = S * (S + 1) / 2;
-  if (WPA == 1 && nblk > 1 && nblk <= 16 && nb.n * (nb.n - 1) / 2 <= kFuseTriplets) {
-    int pa = 0, rem = blk < nblk ? blk : 0;
-    while (rem >= S - pa) {
-      rem -= S - pa;
-      ++pa;
-    }
-    const int pb = pa + rem;
-    const int na = nb.seg[pa + 1] - nb.seg[pa], nbb = nb.seg[pb + 1] - nb.seg[pb];
-    const int Tb = blk < nblk ? (pa == pb ? na * (na - 1) / 2 : na * nbb) : 0;
-    int Tmax = Tb;
-    for (int o = 32; o >= 1; o >>= 1) Tmax = max(Tmax, __shfl_xor(Tmax, o));
-    const int m = pa == pb ? na : nbb;
-    const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
-    floatx4 acc[NP][NQ];
-#pragma unroll
-    for (int u = 0; u < NP; ++u)
-#pragma unroll
-      for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int t = 0; t < Tmax; ++t) {
-      int j = 0, k = 0;  // past the block's triplets: any neighbor, with F2 = 0
-      if (t < Tb) {
-        int q, r;
-        divmod_small(t, m, inv_m, q, r);
-        if (pa == pb) {  // the unordered pairs {j, (j + s) mod na}, numbered (s - 1) na + j
-          int kk = r + q + 1;
-          if (kk >= na) kk -= na;
-          j = nb.seg[pa] + r;
-          k = nb.seg[pa] + kk;
-        } else {
-          j = nb.seg[pa] + q;
-          k = nb.seg[pb] + r;
-        }
-      }
-      const float4 fu = nb.f[j], fv = nb.f[k];
-      float A[NP], R[NQ];
-      if constexpr (ZC == kZcBP) {
-        const float4 u = nb.d[j], v = nb.d[k];
-        const float px = u.x + v.x, py = u.y + v.y, pz = u.z + v.z;
-        const float mx = u.x - v.x, my = u.y - v.y, mz = u.z - v.z;
-        const BpSide w3 = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
-        const float gp = 0.5f * fmaf(px, px, fmaf(py, py, pz * pz));
-        const float gm = 0.5f * fmaf(mx, mx, fmaf(my, my, mz * mz));
-        const float s2 = fmaf(u.w, u.w, fmaf(v.w, v.w, w3.rw2));
-        const float F2 = t < Tb ? fu.x * fv.x * w3.fw : 0.f;
-#pragma unroll
-        for (int uu = 0; uu < NP; ++uu)
-          A[uu] = P.bp_pref[4 * uu + li] *
-                  ipow_rt(P.bp_lam[4 * uu + li] > 0.f ? gp : gm, P.bp_zeta[4 * uu + li], P.bp_zbits);
-#pragma unroll
-        for (int vv = 0; vv < NQ; ++vv) R[vv] = fexp2(-(P.bp_eta[4 * vv + li] * 1.4426950408889634f) * s2) * F2;
-      } else {
-        const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
-        const float F2 = t < Tb ? 2.0f * fu.x * fv.x : 0.f;
-        float x[NP];
-#pragma unroll
-        for (int uu = 0; uu < NP; ++uu)
-          x[uu] = fmaf(g.c, P.x_a[4 * uu + li], fmaf(g.ssm, P.x_b[4 * uu + li], P.x_c));
-        ipow_sel<(ZC > 0 ? ZC : 0), NP>(x, P.zeta, A);
-#pragma unroll
-        for (int vv = 0; vv < NQ; ++vv) {
-          const float dq = (g.rbar - P.rs_ang[4 * vv + li]) + (g.rbar_lo - P.rs_ang_lo[4 * vv + li]);
-          R[vv] = fexp2(-eta_a2 * dq * dq) * F2;
-        }
-      }
-#pragma unroll
-      for (int uu = 0; uu < NP; ++uu)
-#pragma unroll
-        for (int vv = 0; vv < NQ; ++vv) acc[uu][vv] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[uu], R[vv], acc[uu][vv], 0, 0, 0);
-    }
-    if (blk < nblk) {
-      float* out = Gi + ang0 + blk * NB;  // blk is the pair block's index in the layout order
-#pragma unroll
-      for (int uu = 0; uu < NP; ++uu)
-#pragma unroll
-        for (int vv = 0; vv < NQ; ++vv)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) out[(4 * vv + li) * NT + 4 * uu + r] = acc[uu][vv][r];
-    }
-    return;
-  }
-  // angular blocks: the bins are a sum over triplets of the outer product
-  // A_p R_q F2, taken on the 4x4x1 FP32 MFMA (16 blocks of 4 lanes, block b
-  // = lanes 4b..4b+3; lane 4b+i gives row i of A and column i of B, and
-  // register r of lane 4b+j accumulates C_b[r][j]).  Per chunk of 64 triplets
-  // each lane first forms one triplet's geometry into LDS; then each 4-lane
-  // block takes one triplet of every group of 16 and its lane i supplies
-  // A_(4P+i) and R_(4Q+i) F2.  The 16 blocks' sums are added at the end.
   // this lane's angle terms p = 4u + li and radius terms q = 4v + li
   float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
   int zexp[NP];
@@ -547,6 +452,151 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
       rsq_lo[u] = P.rs_ang_lo[4 * u + li];
     }
   }
+  // one triplet's geometry: (cos, smoothed sine, average radius hi, lo)
+  // and 2 fc fc for mBP; (1 + cos, 1 - cos, sum of the squared sides) and
+  // the three cutoffs for BP
+  auto trip_geom = [&](int j, int k, float4& geo, float& F2) {
+    const float4 fu = nb.f[j], fv = nb.f[k];
+    if constexpr (ZC == kZcBP) {
+      // 1 + cos and 1 - cos as |u^ +- v^|^2 / 2 (no cancellation near
+      // cos = -+1); the third side from the FP64 displacements, with
+      // rc - r_jk = (rc^2 - r_jk^2) / (rc + r_jk), so that its cutoff
+      // keeps its relative precision up to rc
+      const float4 u = nb.d[j], v = nb.d[k];
+      const float px = u.x + v.x, py = u.y + v.y, pz = u.z + v.z;
+      const float mx = u.x - v.x, my = u.y - v.y, mz = u.z - v.z;
+      const BpSide w3 = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
+      geo = make_float4(0.5f * fmaf(px, px, fmaf(py, py, pz * pz)), 0.5f * fmaf(mx, mx, fmaf(my, my, mz * mz)),
+                        fmaf(u.w, u.w, fmaf(v.w, v.w, w3.rw2)), 0.f);
+      F2 = fu.x * fv.x * w3.fw;  // three cutoffs
+    } else {
+      const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
+      geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
+      F2 = 2.0f * fu.x * fv.x;
+    }
+  };
+  // this lane's factors of one triplet: angle terms A_(4u+li) and radius
+  // terms R_(4v+li) F2
+  auto lane_factors = [&](const float4& q4, float f2, float (&A)[NP], float (&R)[NQ]) {
+    if constexpr (ZC == kZcBP) {
+      // 2^(2 - zeta) (1 + lambda cos)^zeta and exp(-eta s2) fc fc fc
+#pragma unroll
+      for (int u = 0; u < NP; ++u) A[u] = xa[u] * ipow_rt(xb[u] > 0.f ? q4.x : q4.y, zexp[u], P.bp_zbits);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) R[v] = fexp2(-rsq[v] * q4.z) * f2;
+    } else {
+      float x[NP];
+#pragma unroll
+      for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+      ipow_sel<(ZC > 0 ? ZC : 0), NP>(x, P.zeta, A);
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) {
+        const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
+        R[v] = fexp2(-eta_a2 * dq * dq) * f2;
+      }
+    }
+  };
+  // triplet t of species-pair block (a, b), m = na (a == b) or nbb (a < b):
+  // a == b numbers the unordered pairs {j, (j + s) mod na} as (s - 1) na + j,
+  // a < b every (j, k) of the two segments as j nbb + k
+  auto decode = [&](int t, int a, int b, int m, float inv_m, int& j, int& k) {
+    int q, r;
+    divmod_small(t, m, inv_m, q, r);
+    if (a == b) {
+      int kk = r + q + 1;
+      if (kk >= m) kk -= m;
+      j = nb.seg[a] + r;
+      k = nb.seg[a] + kk;
+    } else {
+      j = nb.seg[a] + q;
+      k = nb.seg[b] + r;
+    }
+  };
+  // Few triplets (a small molecule with several species): one chunk of 64
+  // triplets, a reduction and the stores per species-pair block would
+  // mostly idle.  Instead 4-lane MFMA block b of the (single) wave takes
+  // species-pair block b (S(S+1)/2 <= 16) and walks its triplets, its lane
+  // i supplying A_(4u+i) and R_(4v+i) F2 of each, so that the block's
+  // accumulators end up holding exactly that pair block's bins: no
+  // reduction across lanes.  The four lanes of a block form each of its
+  // triplets' geometry themselves, except for the BP term (whose third side
+  // is an FP64 computation) with at most 64 triplets: then each lane first
+  // forms one triplet's geometry (numbered block after block) into LDS and
+  // the blocks read it back.
+  const int nblk = S * (S + 1) / 2;
+  const int Tall = nb.n * (nb.n - 1) / 2;
+  if (WPA == 1 && nblk > 1 && nblk <= 16 && Tall <= kFuseTriplets) {
+    int pa = 0, rem = blk < nblk ? blk : 0;
+    while (rem >= S - pa) {
+      rem -= S - pa;
+      ++pa;
+    }
+    const int pb = pa + rem;
+    const int na = nb.seg[pa + 1] - nb.seg[pa], nbb = nb.seg[pb + 1] - nb.seg[pb];
+    const int Tb = blk < nblk ? (pa == pb ? na * (na - 1) / 2 : na * nbb) : 0;
+    int Tmax = Tb;
+    for (int o = 32; o >= 1; o >>= 1) Tmax = max(Tmax, __shfl_xor(Tmax, o));
+    const int m = pa == pb ? na : nbb;
+    const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
+    const bool staged = ZC == kZcBP && Tall <= kWave;
+    int base = 0;  // first triplet of this lane's block in the block-after-block numbering
+    if (staged) {
+      float4 geo = make_float4(1.f, 0.f, 0.f, 0.f);
+      float F2 = 0.f;
+      int c = 0, acc_t = 0;
+      for (int a = 0; a < S; ++a)
+        for (int b = a; b < S; ++b, ++c) {
+          const int ma = nb.seg[a + 1] - nb.seg[a], mb = nb.seg[b + 1] - nb.seg[b];
+          const int Tc = a == b ? ma * (ma - 1) / 2 : ma * mb;
+          if (c < blk) base += Tc;
+          if (lane >= acc_t && lane < acc_t + Tc) {
+            const int mm = a == b ? ma : mb;
+            int j, k;
+            decode(lane - acc_t, a, b, mm, 1.0f / (float)mm, j, k);
+            trip_geom(j, k, geo, F2);
+          }
+          acc_t += Tc;
+        }
+      tgeo[0][lane] = geo;
+      tf2[0][lane] = F2;
+      wave_lds_sync();
+    }
+    floatx4 acc[NP][NQ];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < Tmax; ++t) {
+      float4 q4 = make_float4(1.f, 0.f, 0.f, 0.f);  // past the block's triplets: F2 = 0 adds nothing
+      float f2 = 0.f;
+      if (t < Tb) {
+        if (staged) {
+          q4 = tgeo[0][base + t];
+          f2 = tf2[0][base + t];
+        } else {
+          int j, k;
+          decode(t, pa, pb, m, inv_m, j, k);
+          trip_geom(j, k, q4, f2);
+        }
+      }
+      float A[NP], R[NQ];
+      lane_factors(q4, f2, A, R);
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[u], R[v], acc[u][v], 0, 0, 0);
+    }
+    if (blk < nblk) {
+      float* out = Gi + ang0 + blk * NB;  // blk is the pair block's index in the layout order
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) out[(4 * v + li) * NT + 4 * u + r] = acc[u][v][r];
+    }
+    return;
+  }
   for (int a = 0; a < S; ++a) {
     for (int b = a; b < S; ++b) {
       const int na = nb.seg[a + 1] - nb.seg[a], nbb = nb.seg[b + 1] - nb.seg[b];
@@ -556,9 +606,6 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
       for (int u = 0; u < NP; ++u)
 #pragma unroll
         for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
-      // a == b: the unordered pairs {j, (j + s) mod na}, s = 1 .. na/2 (for
-      // even na the last step only for j < na/2), numbered t = (s - 1) na + j;
-      // a < b: every (j, k) of the two segments, t = j nbb + k
       const int m = (a == b) ? na : nbb;
       const float inv_m = m > 0 ? 1.0f / (float)m : 0.f;
       for (int t0 = wv * kWave; t0 < T; t0 += kWave * WPA) {
@@ -566,35 +613,9 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
         float4 geo = make_float4(1.f, 0.f, 0.f, 0.f);
         float F2 = 0.f;  // zero past the block's triplets: such rows add nothing
         if (t < T) {
-          int q, r, j, k;
-          divmod_small(t, m, inv_m, q, r);
-          if (a == b) {
-            int kk = r + q + 1;
-            if (kk >= na) kk -= na;
-            j = nb.seg[a] + r;
-            k = nb.seg[a] + kk;
-          } else {
-            j = nb.seg[a] + q;
-            k = nb.seg[b] + r;
-          }
-          const float4 fu = nb.f[j], fv = nb.f[k];
-          if constexpr (ZC == kZcBP) {
-            // 1 + cos and 1 - cos as |u^ +- v^|^2 / 2 (no cancellation near
-            // cos = -+1); the third side from the FP64 displacements, with
-            // rc - r_jk = (rc^2 - r_jk^2) / (rc + r_jk), so that its cutoff
-            // keeps its relative precision up to rc
-            const float4 u = nb.d[j], v = nb.d[k];
-            const float px = u.x + v.x, py = u.y + v.y, pz = u.z + v.z;
-            const float mx = u.x - v.x, my = u.y - v.y, mz = u.z - v.z;
-            const BpSide w3 = bp_side64(d64 + 3 * j, d64 + 3 * k, P);
-            geo = make_float4(0.5f * fmaf(px, px, fmaf(py, py, pz * pz)), 0.5f * fmaf(mx, mx, fmaf(my, my, mz * mz)),
-                              fmaf(u.w, u.w, fmaf(v.w, v.w, w3.rw2)), 0.f);
-            F2 = fu.x * fv.x * w3.fw;  // three cutoffs
-          } else {
-            const TripGeom g = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
-            geo = make_float4(g.c, g.ssm, g.rbar, g.rbar_lo);
-            F2 = 2.0f * fu.x * fv.x;
-          }
+          int j, k;
+          decode(t, a, b, m, inv_m, j, k);
+          trip_geom(j, k, geo, F2);
         }
         tgeo[wv][lane] = geo;
         tf2[wv][lane] = F2;
@@ -604,23 +625,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
           const float4 q4 = tgeo[wv][16 * gi + blk];
           const float f2 = tf2[wv][16 * gi + blk];
           float A[NP], R[NQ];
-          if constexpr (ZC == kZcBP) {
-            // 2^(2 - zeta) (1 + lambda cos)^zeta and exp(-eta s2) fc fc fc
-#pragma unroll
-            for (int u = 0; u < NP; ++u) A[u] = xa[u] * ipow_rt(xb[u] > 0.f ? q4.x : q4.y, zexp[u], P.bp_zbits);
-#pragma unroll
-            for (int v = 0; v < NQ; ++v) R[v] = fexp2(-rsq[v] * q4.z) * f2;
-          } else {
-            float x[NP];
-#pragma unroll
-            for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
-            ipow_sel<(ZC > 0 ? ZC : 0), NP>(x, P.zeta, A);
-#pragma unroll
-            for (int v = 0; v < NQ; ++v) {
-              const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
-              R[v] = fexp2(-eta_a2 * dq * dq) * f2;
-            }
-          }
+          lane_factors(q4, f2, A, R);
 #pragma unroll
           for (int u = 0; u < NP; ++u)
 #pragma unroll
