@@ -55,12 +55,20 @@ __device__ __forceinline__ void wave_lds_sync() {
 __device__ __forceinline__ int nb_species(const float4& f) { return __float_as_int(f.w) & 15; }
 __device__ __forceinline__ int nb_entry(const float4& f) { return __float_as_int(f.w) >> 4; }
 
+// The structure of atom i: the largest c < B with atom_ptr[c] <= i.  Each
+// round the 64 lanes probe 64 evenly spaced positions of the remaining range
+// and one ballot keeps the stretch after the last probe at or below i, so
+// 2048 structures take two dependent rounds of loads instead of eleven.
+// Every lane of the wave must call it (with the same i).
 __device__ __forceinline__ int struct_of_atom(const int64_t* atom_ptr, int32_t B, int64_t i) {
-  int lo = 0, hi = B - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (atom_ptr[mid] <= i) lo = mid;
-    else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = B;  // atom_ptr[lo] <= i; the answer lies in [lo, hi)
+  while (hi - lo > 1) {
+    const int step = (hi - lo + 63) / 64;
+    const int p = lo + lane * step;
+    const uint64_t le = __ballot(p < hi && atom_ptr[p] <= i);  // a prefix of the lanes: atom_ptr does not decrease
+    lo += (__popcll(le) - 1) * step;
+    hi = min(hi, lo + step);
   }
   return lo;
 }

@@ -401,6 +401,24 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
 }
 
 
+// The largest c < n with a[c] <= x, for a non-decreasing a with a[0] <= x,
+// found by the whole wave: each round its 64 lanes probe 64 evenly spaced
+// positions of the remaining range and one ballot keeps the stretch after the
+// last probe at or below x (two dependent rounds for 4096 entries instead
+// of twelve).  Every lane of the wave must call it with the same x.
+__device__ __forceinline__ int wave_search_le(const int64_t* a, int n, int64_t x) {
+  const int lane = threadIdx.x & 63;
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int step = (hi - lo + 63) / 64;
+    const int p = lo + lane * step;
+    const uint64_t le = __ballot(p < hi && a[p] <= x);
+    lo += (__popcll(le) - 1) * step;
+    hi = min(hi, lo + step);
+  }
+  return lo;
+}
+
 __device__ __forceinline__ int struct_of(const int64_t* atom_ptr, int32_t B, int64_t i) {
   int lo = 0, hi = B - 1;
   while (lo < hi) {
@@ -541,16 +559,7 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const int64_t n_groups = B > 0 ? bin_base[B] : 0;
   for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-    int c = 0;
-    {
-      int lo = 0, hi = B - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bin_base[mid] <= grp) lo = mid;
-        else hi = mid - 1;
-      }
-      c = lo;
-    }
+    const int c = B > 0 ? wave_search_le(bin_base, B, grp) : 0;  // the group's structure
     // the structure's geometry in registers: stores to the list below are
     // char-typed and would otherwise force reloads of it
     double h[9];
