@@ -91,6 +91,70 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   const double rc2 = P.rc64 * P.rc64;
   const int S = P.S;
   const char4* sh4 = reinterpret_cast<const char4*>(shift);
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // entry e (neighbor species sp, FP64 displacement d, |d|^2 = r2 < rc^2)
+  // into staging slot `slot`
+  auto put = [&](int64_t e, int slot, const double (&d)[3], double r2, int sp) {
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    const double u = P.rc64 - r;  // formed in FP64: no cancellation near rc
+    const float r_hi = (float)r;
+    const float r_lo = (float)(r - (double)r_hi);
+    const float sa = sinf((float)(P.half_pi_over_rc64 * u));
+    const float fc = sa * sa;  // sin^2(pi (rc - r) / (2 rc))
+    // dfc/dr = -(pi / 2rc) sin(pi r / rc), and sin(pi r / rc) = sin(pi (rc - r) / rc)
+    const float dfc = (float)(-0.5 * P.pi_over_rc64) * sinf((float)(P.pi_over_rc64 * u));
+    nb.d[slot] = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
+    nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
+    nb.ir[slot] = (float)ir;
+    if (d64) {
+      d64[3 * slot] = d[0];
+      d64[3 * slot + 1] = d[1];
+      d64[3 * slot + 2] = d[2];
+    }
+  };
+  if (e1 - e0 <= kWave) {
+    // at most 64 entries: one pass, an entry per lane of wave 0; the ballots
+    // give every lane the per-species counts, so each knows its slot (the
+    // same slots as the two passes below)
+    if (w0) {
+      const int64_t e = e0 + lane;
+      bool valid = false, bad = false;
+      int sp = 0;
+      double d[3] = {0, 0, 0};
+      double r2 = 0;
+      if (e < e1) {
+        const int32_t j = nbr[e];
+        const char4 s4 = sh4[e];
+        displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d);
+        r2 = norm2_64(d);
+        valid = r2 < rc2;
+        sp = sys.species[j];
+        if (sp < 0 || sp >= S) {
+          bad = valid;
+          valid = false;
+        }
+        if (!valid && pg) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      if (__any(bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+      int before = 0, rank = 0, total = 0;
+      for (int s2 = 0; s2 < S; ++s2) {
+        const uint64_t m = __ballot(valid && sp == s2);
+        if (s2 < sp) before += __popcll(m);
+        if (valid && sp == s2) rank = __popcll(m & lt_mask);
+        if (lane == 0) nb.seg[s2] = total;
+        total += __popcll(m);
+      }
+      if (lane == 0) {
+        nb.seg[S] = total;
+        nb.n = total;
+        nb.bad = 0;
+      }
+      if (valid) put(e, before + rank, d, r2, sp);
+    }
+    __syncthreads();
+    return;
+  }
   int cnt[NN_MAX_SPECIES];
   for (int s = 0; s < NN_MAX_SPECIES; ++s) cnt[s] = 0;
   bool bad = false;
@@ -129,7 +193,6 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   if (nb.bad) return;
   int run[NN_MAX_SPECIES];
   for (int s = 0; s < S; ++s) run[s] = nb.seg[s];
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   // pass B: pair geometry, scattered in species order
   for (int64_t base = e0; w0 && base < e1; base += kWave) {
     int64_t e = base + lane;
@@ -153,25 +216,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       if (valid && sp == s) slot = run[s] + __popcll(m & lt_mask);
       run[s] += __popcll(m);
     }
-    if (valid) {
-      const double r = sqrt(r2);
-      const double ir = 1.0 / r;
-      const double u = P.rc64 - r;  // formed in FP64: no cancellation near rc
-      const float r_hi = (float)r;
-      const float r_lo = (float)(r - (double)r_hi);
-      const float sa = sinf((float)(P.half_pi_over_rc64 * u));
-      const float fc = sa * sa;  // sin^2(pi (rc - r) / (2 rc))
-      // dfc/dr = -(pi / 2rc) sin(pi r / rc), and sin(pi r / rc) = sin(pi (rc - r) / rc)
-      const float dfc = (float)(-0.5 * P.pi_over_rc64) * sinf((float)(P.pi_over_rc64 * u));
-      nb.d[slot] = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
-      nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
-      nb.ir[slot] = (float)ir;
-      if (d64) {
-        d64[3 * slot] = d[0];
-        d64[3 * slot + 1] = d[1];
-        d64[3 * slot + 2] = d[2];
-      }
-    }
+    if (valid) put(e, slot, d, r2, sp);
   }
   __syncthreads();
 }
