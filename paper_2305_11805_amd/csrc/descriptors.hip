@@ -73,6 +73,8 @@ __device__ __forceinline__ int struct_of_atom(const int64_t* atom_ptr, int32_t B
   return lo;
 }
 
+constexpr int kStageRounds = 2;  // rows up to 128 entries are staged in one pass
+
 // Stage the neighbors of atom i inside rc into LDS, sorted by species.
 // Entries at r >= rc get a zero pair gradient if pg != nullptr; with d64
 // the FP64 displacements are staged too ([slot][3]).
@@ -113,44 +115,56 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       d64[3 * slot + 2] = d[2];
     }
   };
-  if (e1 - e0 <= kWave) {
-    // at most 64 entries: one pass, an entry per lane of wave 0; the ballots
-    // give every lane the per-species counts, so each knows its slot (the
-    // same slots as the two passes below)
+  if (e1 - e0 <= kStageRounds * kWave) {
+    // at most 128 entries: one pass, entry e0 + 64 r + lane in round r of
+    // wave 0, held in registers; the ballots give every lane the per-species
+    // counts, so each knows its slots (the same slots as the two passes below)
     if (w0) {
-      const int64_t e = e0 + lane;
-      bool valid = false, bad = false;
-      int sp = 0;
-      double d[3] = {0, 0, 0};
-      double r2 = 0;
-      if (e < e1) {
-        const int32_t j = nbr[e];
-        const char4 s4 = sh4[e];
-        displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d);
-        r2 = norm2_64(d);
-        valid = r2 < rc2;
-        sp = sys.species[j];
-        if (sp < 0 || sp >= S) {
-          bad = valid;
-          valid = false;
+      bool valid[kStageRounds];
+      int sp[kStageRounds];
+      double d[kStageRounds][3], r2[kStageRounds];
+      bool bad = false;
+#pragma unroll
+      for (int r = 0; r < kStageRounds; ++r) {
+        const int64_t e = e0 + r * kWave + lane;
+        valid[r] = false;
+        sp[r] = 0;
+        d[r][0] = d[r][1] = d[r][2] = 0.0;
+        r2[r] = 0.0;
+        if (e < e1) {
+          const int32_t j = nbr[e];
+          const char4 s4 = sh4[e];
+          displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d[r]);
+          r2[r] = norm2_64(d[r]);
+          valid[r] = r2[r] < rc2;
+          sp[r] = sys.species[j];
+          if (sp[r] < 0 || sp[r] >= S) {
+            bad = bad || valid[r];
+            valid[r] = false;
+          }
+          if (!valid[r] && pg) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        if (!valid && pg) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
       if (__any(bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
-      int before = 0, rank = 0, total = 0;
+      int slot[kStageRounds] = {};
+      int total = 0;
       for (int s2 = 0; s2 < S; ++s2) {
-        const uint64_t m = __ballot(valid && sp == s2);
-        if (s2 < sp) before += __popcll(m);
-        if (valid && sp == s2) rank = __popcll(m & lt_mask);
         if (lane == 0) nb.seg[s2] = total;
-        total += __popcll(m);
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) {
+          const uint64_t m = __ballot(valid[r] && sp[r] == s2);
+          if (valid[r] && sp[r] == s2) slot[r] = total + __popcll(m & lt_mask);
+          total += __popcll(m);
+        }
       }
       if (lane == 0) {
         nb.seg[S] = total;
         nb.n = total;
         nb.bad = 0;
       }
-      if (valid) put(e, before + rank, d, r2, sp);
+#pragma unroll
+      for (int r = 0; r < kStageRounds; ++r)
+        if (valid[r]) put(e0 + r * kWave + lane, slot[r], d[r], r2[r], sp[r]);
     }
     __syncthreads();
     return;
