@@ -1096,6 +1096,16 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
   const int64_t e0 = offsets[i];
+  // this atom's lambda is requested before the neighbor staging (whose
+  // loads it then overlaps) and put into LDS after it
+  const float* lam = lambda + i * (int64_t)P.D;
+  constexpr int kLamPre = 8;
+  float lpre[kLamPre];
+#pragma unroll
+  for (int q = 0; q < kLamPre; ++q) {
+    const int d = tid + q * 64 * WPA;
+    lpre[q] = d < P.D ? lam[d] : 0.f;
+  }
   stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, pg);
   if (nb.bad) {
     for (int64_t e = e0 + tid; e < offsets[i + 1]; e += 64 * WPA) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1103,11 +1113,21 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   }
   const int S = P.S;
   const int n = nb.n;
-  const float* lam = lambda + i * (int64_t)P.D;
   const int ang0 = P.n_rad * S;
-  const int nblk = S * (S + 1) / 2;
-  for (int d = tid; d < ang0; d += 64 * WPA) lam_r[d] = lam[d];
-  for (int d = tid; d < nblk * NB; d += 64 * WPA) lam_a[(d / NB) * NBP + d % NB] = lam[ang0 + d];
+  auto put_lam = [&](int d, float x) {
+    if (d < ang0) {
+      lam_r[d] = x;
+    } else {
+      const int da = d - ang0;
+      lam_a[(da / NB) * NBP + da % NB] = x;
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < kLamPre; ++q) {
+    const int d = tid + q * 64 * WPA;
+    if (d < P.D) put_lam(d, lpre[q]);
+  }
+  for (int d = tid + kLamPre * 64 * WPA; d < P.D; d += 64 * WPA) put_lam(d, lam[d]);
   for (int t = lane; t < n; t += kWave) {
     gx[wv][t] = 0.f;
     gy[wv][t] = 0.f;
