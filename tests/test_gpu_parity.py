@@ -252,3 +252,32 @@ def test_neighbor_list_rows_longer_than_lds_buffer():
     row_of = np.repeat(np.arange(len(off) - 1), np.diff(off))
     assert np.array_equal(got["nbr"][got["rev"]], row_of)
     assert np.array_equal(got["shift"][got["rev"]], -got["shift"])
+
+
+def test_batch_with_empty_structures():
+    """Several hundred clusters, about 40 % of them with no atoms (repeated
+    atom_ptr entries, also at both ends): the owning structure of each atom
+    (found by the whole wave, 64 probes per round) and every structure's
+    energy (exactly 0 for the empty ones) against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(613))
+    sizes = [int(n) if rng.uniform() > 0.4 else 0 for n in rng.integers(1, 24, 300)]
+    sizes = [0, 0] + sizes + [0, 0, 0]
+    s = synth.clusters_system(rng, sizes, lambda n: 4.0 + 0.15 * n, 0.9, 4)
+    p = synth.mbp_params(4, 4.6, 16, 8, 4)
+    model = synth.random_model(4, p.dim, [64, 32], 613, in_scale=2.0)
+    print(f"[empty structures] {len(sizes)} structures, {sizes.count(0)} empty, {s.n_atoms} atoms", flush=True)
+    nl = oracle.neighbors_cells(s, p.rc)
+    G_ref = oracle.descriptors(p, s, nl)
+    Es_ref, _, F_ref = oracle.energy_forces(p, model, s, nl)
+    pot = nnpot.Potential(s, p, model)
+    pot.build_neighbors()
+    G = pot.descriptors().cpu().numpy()
+    Es, _, F = pot.energy_forces()
+    nnpot.nn_check(pot.nl)
+    Es, F = Es.cpu().numpy(), F.cpu().numpy()
+    empty = np.diff(s.atom_ptr) == 0
+    assert np.all(Es[empty] == 0.0)
+    n_c = np.maximum(np.diff(s.atom_ptr), 1).astype(np.float64)
+    assert descriptor_errors(G, G_ref) <= 1.0
+    assert np.max(np.abs(Es - Es_ref) / n_c) <= E_TOL
+    assert np.abs(F - F_ref).max() <= F_TOL
