@@ -81,7 +81,8 @@ constexpr int kStageRounds = 2;  // rows up to 128 entries are staged in one pas
 __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, const int64_t* __restrict__ offsets,
                                 const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
                                 const DescConst& P, int64_t* meta, float4* __restrict__ pg,
-                                double* d64 = nullptr) {
+                                double* d64 = nullptr, const float* __restrict__ field = nullptr,
+                                float4* tw = nullptr) {
   // wave 0 does the work; every thread of the block passes the barriers
   const int lane = threadIdx.x & 63;
   const bool w0 = threadIdx.x < 64;
@@ -94,9 +95,17 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   const int S = P.S;
   const char4* sh4 = reinterpret_cast<const char4*>(shift);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  // entry e (neighbor species sp, FP64 displacement d, |d|^2 = r2 < rc^2)
-  // into staging slot `slot`
-  auto put = [&](int64_t e, int slot, const double (&d)[3], double r2, int sp) {
+  // with a displacement field: v_i now, and per neighbor ((v_j - v_i) / r,
+  // r_dot = d^ . (v_j - v_i)) into tw[slot] as the neighbor is placed
+  float vx = 0.f, vy = 0.f, vz = 0.f;
+  if (tw) {
+    vx = field[3 * i];
+    vy = field[3 * i + 1];
+    vz = field[3 * i + 2];
+  }
+  // entry e (neighbor j of species sp, FP64 displacement d, |d|^2 = r2 <
+  // rc^2) into staging slot `slot`
+  auto put = [&](int64_t e, int32_t j, int slot, const double (&d)[3], double r2, int sp) {
     const double r = sqrt(r2);
     const double ir = 1.0 / r;
     const double u = P.rc64 - r;  // formed in FP64: no cancellation near rc
@@ -106,9 +115,15 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
     const float fc = sa * sa;  // sin^2(pi (rc - r) / (2 rc))
     // dfc/dr = -(pi / 2rc) sin(pi r / rc), and sin(pi r / rc) = sin(pi (rc - r) / rc)
     const float dfc = (float)(-0.5 * P.pi_over_rc64) * sinf((float)(P.pi_over_rc64 * u));
-    nb.d[slot] = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
+    const float ux = (float)(d[0] * ir), uy = (float)(d[1] * ir), uz = (float)(d[2] * ir), irf = (float)ir;
+    nb.d[slot] = make_float4(ux, uy, uz, r_hi);
     nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
-    nb.ir[slot] = (float)ir;
+    nb.ir[slot] = irf;
+    if (tw) {
+      const float dx = field[3 * (int64_t)j] - vx, dy = field[3 * (int64_t)j + 1] - vy,
+                  dz = field[3 * (int64_t)j + 2] - vz;
+      tw[slot] = make_float4(dx * irf, dy * irf, dz * irf, fmaf(ux, dx, fmaf(uy, dy, uz * dz)));
+    }
     if (d64) {
       d64[3 * slot] = d[0];
       d64[3 * slot + 1] = d[1];
@@ -122,6 +137,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
     if (w0) {
       bool valid[kStageRounds];
       int sp[kStageRounds];
+      int32_t jr[kStageRounds];
       double d[kStageRounds][3], r2[kStageRounds];
       bool bad = false;
 #pragma unroll
@@ -129,10 +145,12 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
         const int64_t e = e0 + r * kWave + lane;
         valid[r] = false;
         sp[r] = 0;
+        jr[r] = 0;
         d[r][0] = d[r][1] = d[r][2] = 0.0;
         r2[r] = 0.0;
         if (e < e1) {
           const int32_t j = nbr[e];
+          jr[r] = j;
           const char4 s4 = sh4[e];
           displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d[r]);
           r2[r] = norm2_64(d[r]);
@@ -164,7 +182,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       }
 #pragma unroll
       for (int r = 0; r < kStageRounds; ++r)
-        if (valid[r]) put(e0 + r * kWave + lane, slot[r], d[r], r2[r], sp[r]);
+        if (valid[r]) put(e0 + r * kWave + lane, jr[r], slot[r], d[r], r2[r], sp[r]);
     }
     __syncthreads();
     return;
@@ -212,10 +230,11 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
     int64_t e = base + lane;
     bool valid = false;
     int sp = 0;
+    int32_t j = 0;
     double d[3] = {0, 0, 0};
     double r2 = 0;
     if (e < e1) {
-      int32_t j = nbr[e];
+      j = nbr[e];
       char4 s4 = sh4[e];
       displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d);
       r2 = norm2_64(d);
@@ -230,7 +249,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       if (valid && sp == s) slot = run[s] + __popcll(m & lt_mask);
       run[s] += __popcll(m);
     }
-    if (valid) put(e, slot, d, r2, sp);
+    if (valid) put(e, j, slot, d, r2, sp);
   }
   __syncthreads();
 }
@@ -771,23 +790,11 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
     for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
     return;
   }
-  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr, ZC == kZcBP ? d64 : nullptr);
+  stage_neighbors(nb, i, sys, offsets, nbr, shift, P, meta, nullptr, ZC == kZcBP ? d64 : nullptr, field, tw);
   if (nb.bad) {
     for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
     return;
   }
-  {
-    const int64_t e0 = offsets[i];
-    const float vx = field[3 * i], vy = field[3 * i + 1], vz = field[3 * i + 2];
-    for (int t = tid; t < nb.n; t += 64 * WPA) {
-      const int64_t j = nbr[e0 + nb_entry(nb.f[t])];
-      const float dx = field[3 * j] - vx, dy = field[3 * j + 1] - vy, dz = field[3 * j + 2] - vz;
-      const float4 d = nb.d[t];
-      const float ir = nb.ir[t];
-      tw[t] = make_float4(dx * ir, dy * ir, dz * ir, fmaf(d.x, dx, fmaf(d.y, dy, d.z * dz)));
-    }
-  }
-  __syncthreads();
   const int S = P.S;
   const float eta_r2 = P.eta_rad * 1.4426950408889634f;
   const float eta_a2 = P.eta_ang * 1.4426950408889634f;
