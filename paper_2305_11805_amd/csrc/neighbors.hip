@@ -296,6 +296,71 @@ __device__ __forceinline__ void frac(const double* inv, const double* x, double 
   for (int d = 0; d < 3; ++d) s[d] = x[0] * inv[d] + x[1] * inv[3 + d] + x[2] * inv[6 + d];
 }
 
+// Geometry of one structure of nc atoms with cell h (inverse inv): the
+// all-pairs path with image bounds K_d = floor(radius/w_d + spread_d) + 1
+// on periodic directions (l, u: range of the fractional coordinates) for
+// small structures, else bins at least radius wide, merged while there are
+// more than 8 nc + 64 of them.  Errors go to meta.
+__device__ __forceinline__ StructGeom make_geom(const double h[9], const double inv[9], const uint8_t* pbc3, int64_t nc,
+                                                const double l[3], const double u[3], double radius, int64_t* meta) {
+  double w[3];
+  perp_widths(h, w);
+  StructGeom g;
+  for (int k = 0; k < 9; ++k) {
+    g.h[k] = h[k];
+    g.inv[k] = inv[k];
+  }
+  const bool small = nc <= kSmallMax;
+  g.small = small ? 1 : 0;
+  int64_t nbins = 0;
+  if (small) {
+    nbins = nc > 0 ? 1 : 0;  // the whole structure is one group of the row passes
+    for (int d = 0; d < 3; ++d) {
+      double K = pbc3[d] && nc > 0 ? floor(radius / w[d] + (u[d] - l[d])) + 1.0 : 0.0;
+      if (!(K <= 127.0)) {
+        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
+        K = 0.0;
+      }
+      g.nb[d] = (int)K;
+    }
+  } else {
+    int minb[3];
+    for (int d = 0; d < 3; ++d) {
+      double k = floor(w[d] / (radius * (1.0 + 1e-6)));
+      if (!(k >= 1.0)) k = 1.0;
+      if (k > 1024.0) k = 1024.0;
+      g.nb[d] = (int)k;
+      minb[d] = pbc3[d] ? 3 : 1;
+      if (g.nb[d] < minb[d]) {
+        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrCell);
+        g.nb[d] = minb[d];
+      }
+    }
+    // keep the bin count near the atom count (dilute boxes): halve the
+    // direction with the most bins above its minimum (the first on ties)
+    // while there are too many
+    const int64_t cap = 8 * nc + 64;
+    int n0 = g.nb[0], n1 = g.nb[1], n2 = g.nb[2];
+    for (int it = 0; it < 64 && (int64_t)n0 * n1 * n2 > cap; ++it) {
+      const int e0 = n0 - minb[0], e1 = n1 - minb[1], e2 = n2 - minb[2];
+      const int d = e1 > e0 ? (e2 > e1 ? 2 : 1) : (e2 > e0 ? 2 : 0);
+      const int nd = d == 0 ? n0 : (d == 1 ? n1 : n2), md = d == 0 ? minb[0] : (d == 1 ? minb[1] : minb[2]);
+      if (nd <= md) break;
+      const int half = max(md, (nd + 1) / 2);
+      n0 = d == 0 ? half : n0;
+      n1 = d == 1 ? half : n1;
+      n2 = d == 2 ? half : n2;
+    }
+    g.nb[0] = n0;
+    g.nb[1] = n1;
+    g.nb[2] = n2;
+    nbins = (int64_t)n0 * n1 * n2;
+  }
+  g.n_bins = nbins;
+  g.bin_base = 0;
+  return g;
+}
+
 // One 64-thread block per structure.  Small structures (<= kSmallMax atoms)
 // take the all-pairs path with an image bound K_d = floor(radius/w_d +
 // spread_d) + 1 on periodic directions (spread of the fractional
@@ -347,51 +412,8 @@ __global__ void k_nb_geom(const double* __restrict__ pos, const int64_t* __restr
       }
   }
   if (threadIdx.x != 0) return;
-  double w[3];
-  perp_widths(h, w);
-  StructGeom g;
-  for (int k = 0; k < 9; ++k) {
-    g.h[k] = h[k];
-    g.inv[k] = inv[k];
-  }
-  g.small = small ? 1 : 0;
-  int64_t nbins = 0;
-  if (small) {
-    nbins = nc > 0 ? 1 : 0;  // the whole structure is one group of the row passes
-    for (int d = 0; d < 3; ++d) {
-      double K = pbc[3 * c + d] && nc > 0 ? floor(radius / w[d] + (u[d] - l[d])) + 1.0 : 0.0;
-      if (!(K <= 127.0)) {
-        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrShift);
-        K = 0.0;
-      }
-      g.nb[d] = (int)K;
-    }
-  } else {
-    int minb[3];
-    for (int d = 0; d < 3; ++d) {
-      double k = floor(w[d] / (radius * (1.0 + 1e-6)));
-      if (!(k >= 1.0)) k = 1.0;
-      if (k > 1024.0) k = 1024.0;
-      g.nb[d] = (int)k;
-      minb[d] = pbc[3 * c + d] ? 3 : 1;
-      if (g.nb[d] < minb[d]) {
-        atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrCell);
-        g.nb[d] = minb[d];
-      }
-    }
-    // keep the bin count near the atom count (dilute boxes): merge bins
-    const int64_t cap = 8 * nc + 64;
-    for (int it = 0; it < 64 && (int64_t)g.nb[0] * g.nb[1] * g.nb[2] > cap; ++it) {
-      int d = 0;
-      for (int e = 1; e < 3; ++e)
-        if (g.nb[e] - minb[e] > g.nb[d] - minb[d]) d = e;
-      if (g.nb[d] <= minb[d]) break;
-      g.nb[d] = max(minb[d], (g.nb[d] + 1) / 2);
-    }
-    nbins = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
-  }
-  g.n_bins = nbins;
-  g.bin_base = 0;
+  const StructGeom g = make_geom(h, inv, pbc + 3 * c, nc, l, u, radius, meta);
+  const int64_t nbins = g.n_bins;
   geom[c] = g;
   n_bins[c] = nbins;
   if (bin_base_one) {
@@ -496,6 +518,169 @@ __global__ void k_nb_scatter(int64_t N, const double* __restrict__ pos, const in
   bin_m[k] = make_int4((int)i, atom_bin[4 * i + 1], atom_bin[4 * i + 2], atom_bin[4 * i + 3]);
   bin_x[k] = make_double4(pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], 0.0);
   if (order) order[k] = (int32_t)i;
+}
+
+// The geometry, binning, bin-start scan and scatter passes of a single
+// structure of at most kOneAtoms atoms in one block of 1024 threads (one
+// launch in place of four).  Bin counts and starts never exceed the atom
+// count, so they are kept in LDS as the two 16-bit halves of 32-bit words;
+// the geometry allows at most 8 N + 64 bins, which kOneWords covers.  The
+// positions are loaded before the geometry is known; each atom's place in
+// bin order goes to LDS, and the bin-ordered outputs are then written
+// k = t, t + 1024, ... so that the stores of a wave are contiguous.  The
+// outputs are those of the four passes: geom[0], n_bins[0], bin_base[0..1],
+// bin_start[0..n_bins], bin_m / bin_x / order in bin order, and a zero row
+// count for atoms with non-finite coordinates.
+constexpr int kOneThreads = 1024;
+constexpr int kOnePer = 4;
+constexpr int64_t kOneAtoms = (int64_t)kOneThreads * kOnePer;
+constexpr int kOneWords = (int)((8 * kOneAtoms + 64 + 1) / 2);
+
+__global__ void __launch_bounds__(kOneThreads) k_nb_one(const double* __restrict__ pos,
+                                                        const int64_t* __restrict__ atom_ptr,
+                                                        const double* __restrict__ cell,
+                                                        const uint8_t* __restrict__ pbc, double radius,
+                                                        StructGeom* __restrict__ geom, int64_t* __restrict__ n_bins,
+                                                        int64_t* __restrict__ bin_base, int64_t* __restrict__ bin_start,
+                                                        int4* __restrict__ bin_m, double4* __restrict__ bin_x,
+                                                        int32_t* __restrict__ order, int64_t* __restrict__ row_count,
+                                                        int64_t N, int64_t* meta, int32_t* flag, int64_t* cursor,
+                                                        int prep) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const double hc = t < 9 ? cell[t] : 0.0;
+  // prep: no skin test ran, so this launch checks atom_ptr (for one
+  // structure: atom_ptr = {0, N}) and sets the build flags itself
+  if (prep) prep_flags(atom_ptr, 1, N, meta, flag, cursor, 0);
+  const bool go = prep ? (atom_ptr[0] == 0 && atom_ptr[1] == N) : (*flag != 0);
+  if (!go) return;
+  // this thread's atoms i = t + 1024 r, in flight while the geometry is formed
+  double x[kOnePer][3];
+#pragma unroll
+  for (int r = 0; r < kOnePer; ++r) {
+    const int64_t i = t + (int64_t)kOneThreads * r;
+    for (int d = 0; d < 3; ++d) x[r][d] = i < N ? pos[3 * i + d] : 0.0;
+  }
+  constexpr int kW = kOneThreads / 64;
+  __shared__ uint32_t cnt[kOneWords];
+  __shared__ int32_t slot_atom[kOneAtoms];
+  __shared__ double h[9], inv[9];
+  __shared__ double ext[2][3][kW];
+  __shared__ int64_t wsum[kW];
+  __shared__ StructGeom gs;
+  if (t < 9) h[t] = hc;
+  __syncthreads();
+  if (t == 0) inverse3(h, inv);
+  __syncthreads();
+  const bool small = N <= kSmallMax;
+  double l[3] = {1e300, 1e300, 1e300}, u[3] = {-1e300, -1e300, -1e300};
+  if (small) {  // range of the fractional coordinates (block reduction; N <= 1024: one atom per thread)
+    if (t < N) {
+      double f[3];
+      frac(inv, x[0], f);
+      for (int d = 0; d < 3; ++d) {
+        l[d] = f[d];
+        u[d] = f[d];
+      }
+    }
+    for (int d = 0; d < 3; ++d) {
+      for (int off = 32; off > 0; off >>= 1) {
+        l[d] = fmin(l[d], __shfl_xor(l[d], off));
+        u[d] = fmax(u[d], __shfl_xor(u[d], off));
+      }
+      if (lane == 0) {
+        ext[0][d][w] = l[d];
+        ext[1][d][w] = u[d];
+      }
+    }
+    __syncthreads();
+    if (t == 0)
+      for (int d = 0; d < 3; ++d)
+        for (int v = 1; v < kW; ++v) {
+          l[d] = fmin(l[d], ext[0][d][v]);
+          u[d] = fmax(u[d], ext[1][d][v]);
+        }
+  }
+  if (t == 0) {
+    gs = make_geom(h, inv, pbc, N, l, u, radius, meta);
+    geom[0] = gs;
+    n_bins[0] = gs.n_bins;
+    bin_base[0] = 0;
+    bin_base[1] = gs.n_bins;
+  }
+  __syncthreads();
+  const StructGeom& g = gs;
+  const int64_t nbins = g.n_bins;
+  const int nw = (int)((nbins + 1) / 2);
+  for (int k = t; k < nw; k += kOneThreads) cnt[k] = 0;
+  __syncthreads();
+  // bin and rank of each of this thread's atoms (i = t + 1024 r)
+  int bin[kOnePer], rank[kOnePer];
+#pragma unroll
+  for (int r = 0; r < kOnePer; ++r) {
+    const int64_t i = t + (int64_t)kOneThreads * r;
+    bin[r] = -1;
+    if (i >= N) continue;
+    if (!(isfinite(x[r][0]) && isfinite(x[r][1]) && isfinite(x[r][2]))) {
+      atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
+      row_count[i] = 0;
+      continue;
+    }
+    int b3[3] = {0, 0, 0}, m[3];
+    if (!g.small) bin_coords(g, pbc, x[r], b3, m);
+    bin[r] = g.small ? 0 : (b3[0] * g.nb[1] + b3[1]) * g.nb[2] + b3[2];
+    const int sh = 16 * (bin[r] & 1);
+    rank[r] = (int)((atomicAdd(&cnt[bin[r] >> 1], 1u << sh) >> sh) & 0xffffu);
+  }
+  __syncthreads();
+  // exclusive scan of the counts: thread t takes a contiguous run of words
+  const int per = (nw + kOneThreads - 1) / kOneThreads;
+  const int w0 = min(t * per, nw), w1 = min(w0 + per, nw);
+  int64_t sum = 0;
+  for (int k = w0; k < w1; ++k) sum += (cnt[k] & 0xffffu) + (cnt[k] >> 16);
+  int64_t incl = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  if (w == 0) {
+    int64_t v = lane < kW ? wsum[lane] : 0;
+    for (int off = 1; off < kW; off <<= 1) {
+      const int64_t y = __shfl_up(v, off);
+      if (lane >= off) v += y;
+    }
+    if (lane < kW) wsum[lane] = v;  // inclusive wave totals
+  }
+  __syncthreads();
+  int64_t run = incl - sum + (w > 0 ? wsum[w - 1] : 0);
+  for (int k = w0; k < w1; ++k) {
+    const uint32_t v = cnt[k];
+    const int64_t s0 = run, s1 = run + (v & 0xffffu);
+    run = s1 + (v >> 16);
+    bin_start[2 * k] = s0;
+    if (2 * k + 1 < nbins) bin_start[2 * k + 1] = s1;
+    cnt[k] = (uint32_t)s0 | ((uint32_t)s1 << 16);
+  }
+  const int total = (int)wsum[kW - 1];  // atoms with finite coordinates
+  if (t == kOneThreads - 1) bin_start[nbins] = total;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kOnePer; ++r) {
+    if (bin[r] < 0) continue;
+    const int sh = 16 * (bin[r] & 1);
+    slot_atom[((cnt[bin[r] >> 1] >> sh) & 0xffffu) + rank[r]] = t + kOneThreads * r;
+  }
+  __syncthreads();
+  for (int k = t; k < total; k += kOneThreads) {
+    const int i = slot_atom[k];
+    const double y[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    int b3[3], m[3] = {0, 0, 0};
+    if (!g.small) bin_coords(g, pbc, y, b3, m);
+    bin_m[k] = make_int4(i, m[0], m[1], m[2]);
+    bin_x[k] = make_double4(y[0], y[1], y[2], 0.0);
+    if (order) order[k] = i;
+  }
 }
 
 __device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc) {
@@ -926,23 +1111,31 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   if (use_skin && L.nl && L.nl->ref_pos && N > 0)
     hipLaunchKernelGGL(k_skin_check, dim3(gN), dim3(256), 0, s, sys->pos, L.nl->ref_pos, N, 0.25 * skin * skin,
                        L.meta, L.flag, 1);
-  const int64_t n_zero = L.max_bins + 1;
-  const unsigned gGeom = (unsigned)std::max<int64_t>(B, std::min<int64_t>((n_zero + 1023) / 1024, 4096));
-  if (B > 0)
-    hipLaunchKernelGGL(k_nb_geom, dim3(gGeom), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B,
-                       L.radius, L.geom, L.n_bins, L.bin_count, n_zero, B == 1 ? L.bin_base : (int64_t*)nullptr,
-                       N, L.meta, L.flag, L.cursor, sep_prep ? 0 : 1);
-  if (B != 1) exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
+  int32_t* order = (count_only || !L.nl) ? (int32_t*)nullptr : L.nl->order;
+  if (B == 1 && N <= kOneAtoms) {
+    hipLaunchKernelGGL(k_nb_one, dim3(1), dim3(kOneThreads), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc,
+                       L.radius, L.geom, L.n_bins, L.bin_base, L.bin_start, L.bin_m, L.bin_x, order, L.counts, N,
+                       L.meta, L.flag, L.cursor, sep_prep ? 0 : 1);
+  } else {
+    const int64_t n_zero = L.max_bins + 1;
+    const unsigned gGeom = (unsigned)std::max<int64_t>(B, std::min<int64_t>((n_zero + 1023) / 1024, 4096));
+    if (B > 0)
+      hipLaunchKernelGGL(k_nb_geom, dim3(gGeom), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B,
+                         L.radius, L.geom, L.n_bins, L.bin_count, n_zero, B == 1 ? L.bin_base : (int64_t*)nullptr,
+                         N, L.meta, L.flag, L.cursor, sep_prep ? 0 : 1);
+    if (B != 1) exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
+    if (N > 0)
+      hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
+                         L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.counts, L.meta, L.flag);
+    exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag, L.bin_base + B);
+    if (N > 0)
+      hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, sys->pos, L.atom_bin, L.bin_rank, L.bin_start,
+                         L.bin_m, L.bin_x, order, L.flag);
+  }
   const double r2 = L.radius * L.radius;
-  if (N > 0)
-    hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                       L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.counts, L.meta, L.flag);
-  exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag, L.bin_base + B);
   // groups (bins) are known on the device only: a grid-stride loop over them
   const unsigned gRows = (unsigned)std::max<int64_t>(1, std::min<int64_t>(L.max_bins, 2048));
   if (N > 0) {
-    hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, sys->pos, L.atom_bin, L.bin_rank, L.bin_start,
-                       L.bin_m, L.bin_x, (count_only || !L.nl) ? (int32_t*)nullptr : L.nl->order, L.flag);
     if (count_only)
       hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N,
