@@ -1035,10 +1035,13 @@ __device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t wa
 // Writes the rows from the keys the counting pass left (key_loc), with the
 // reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
 // whose position is found among row j's sorted keys.  Also records the
-// positions of this build (skin reference) and marks the list valid.  One
-// wave per atom; with the bin order, block b takes the atom at slot
-// (b mod 8) * per + b / 8, so each XCD walks a contiguous stretch of space
-// and the neighbor rows it searches stay in its L2.
+// positions of this build (skin reference) and marks the list valid.  LPA
+// lanes per atom (64 / LPA atoms per one-wave block; 16 for short rows, so
+// that rows of about ten entries do not leave most of a wave idle); with
+// the bin order, block b takes the atoms at slots ((b mod 8) * per + b / 8)
+// * 64 / LPA + (0 .. 64 / LPA - 1), so each XCD walks a contiguous stretch
+// of space and the neighbor rows it searches stay in its L2.
+template <int LPA>
 __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys,
                                                 const int64_t* __restrict__ key_loc,
                                                 const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
@@ -1046,16 +1049,16 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
                                                 const double* __restrict__ pos, double* __restrict__ ref_pos,
                                                 const int32_t* __restrict__ order, int64_t* meta, const int32_t* flag) {
   if (!flag[1]) return;
-  int64_t i = blockIdx.x;
+  constexpr int kApw = kWave / LPA;  // atoms per wave
+  const int lane = threadIdx.x, sl = lane % LPA;
+  int64_t slot = (int64_t)blockIdx.x * kApw + lane / LPA;
   if (order) {
     const int64_t per = (gridDim.x + 7) / 8;
-    const int64_t slot = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (slot >= N) return;
-    i = order[slot];
+    slot = ((int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8) * kApw + lane / LPA;
   }
-  if (i >= N) return;
-  const int lane = threadIdx.x;
-  if (ref_pos && lane < 3) ref_pos[3 * i + lane] = pos[3 * i + lane];
+  if (slot >= N) return;  // no cross-lane operations below
+  const int64_t i = order ? (int64_t)order[slot] : slot;
+  if (ref_pos && sl < 3) ref_pos[3 * i + sl] = pos[3 * i + sl];
   if (blockIdx.x == 0 && lane == 0) {
     meta[kMetaValid] = 1;
     meta[kMetaBuilds] += 1;
@@ -1064,7 +1067,7 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
   const int len = (int)(offsets[i + 1] - e0);
   const uint64_t* mine = row_keys + key_loc[i];
   char4* sh4 = reinterpret_cast<char4*>(shift);
-  for (int t = lane; t < len; t += kWave) {
+  for (int t = sl; t < len; t += LPA) {
     int32_t j;
     char4 sv;
     decode_key(mine[t], j, sv);
@@ -1155,9 +1158,17 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   }
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  const unsigned gEmit = nl->order ? (unsigned)((N + 7) / 8 * 8) : (unsigned)N;  // whole rounds of the 8 XCDs
-  hipLaunchKernelGGL(k_nb_emit, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
-                     nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
+  // lanes per atom from the list's capacity per atom (about 1.25 times the
+  // mean row length when it was sized by a counting pass)
+  const int lpa = L.capacity <= 16 * N ? 16 : 64;
+  const int64_t nw = (N + kWave / lpa - 1) / (kWave / lpa);
+  const unsigned gEmit = nl->order ? (unsigned)((nw + 7) / 8 * 8) : (unsigned)nw;  // whole rounds of the 8 XCDs
+  if (lpa == 16)
+    hipLaunchKernelGGL(k_nb_emit<16>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
+  else
+    hipLaunchKernelGGL(k_nb_emit<64>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
 }
 
 }  // namespace nnp
