@@ -704,7 +704,12 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry
 //               where.
 constexpr int kGrpWaves = 4;
 constexpr int kGrpThreads = 64 * kGrpWaves;
-constexpr int kGrpSplit = 4;  // blocks sharing one group (blockIdx.y), each with every kGrpSplit-th set of atoms
+// Blocks sharing one group (blockIdx.y), each with every gridDim.y-th set of
+// kGrpWaves atoms: four while the groups are few (up to a few hundred bins
+// of a cell of some thousand atoms), so that the grid still fills the chip;
+// two from 16384 atoms on, where the groups alone are enough and each block
+// stages its candidates for more atoms.
+static int grp_split(int64_t n_atoms) { return n_atoms >= 16384 ? 2 : 4; }
 constexpr int kCandMax = 768;   // binned groups with more candidates read them from HBM
 constexpr int kKeyLds = 256;    // row keys kept in LDS; longer rows take a second pass through HBM
 
@@ -836,7 +841,7 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
         }
     }
     __syncthreads();
-    for (int64_t a = a_lo + (int64_t)blockIdx.y * kGrpWaves + wv; a < a_hi; a += kGrpWaves * kGrpSplit) {
+    for (int64_t a = a_lo + (int64_t)blockIdx.y * kGrpWaves + wv; a < a_hi; a += (int64_t)kGrpWaves * gridDim.y) {
       const int4 mi4 = bin_m[a];
       const double4 xi4 = bin_x[a];
       const int32_t i = mi4.x;
@@ -1140,11 +1145,11 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const unsigned gRows = (unsigned)std::max<int64_t>(1, std::min<int64_t>(L.max_bins, 2048));
   if (N > 0) {
     if (count_only)
-      hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
+      hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, grp_split(N)), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N,
                          (uint64_t*)nullptr, 0, (int64_t)0, (int64_t*)nullptr, L.cursor, L.meta, L.flag);
     else
-      hipLaunchKernelGGL(k_nb_rows<kRowsKeys>, dim3(gRows, kGrpSplit), dim3(kGrpThreads), 0, s, sys->atom_ptr,
+      hipLaunchKernelGGL(k_nb_rows<kRowsKeys>, dim3(gRows, grp_split(N)), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N, L.row_keys,
                          L.kslot, 2 * L.capacity, L.key_loc, L.cursor, L.meta, L.flag);
   }
