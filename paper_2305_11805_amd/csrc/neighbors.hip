@@ -1041,8 +1041,8 @@ __device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t wa
 // reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
 // whose position is found among row j's sorted keys.  Also records the
 // positions of this build (skin reference) and marks the list valid.  LPA
-// lanes per atom (64 / LPA atoms per one-wave block; 16 for short rows, so
-// that rows of about ten entries do not leave most of a wave idle); with
+// lanes per atom (64 / LPA atoms per one-wave block), each lane taking
+// every LPA-th entry of the row; with
 // the bin order, block b takes the atoms at slots ((b mod 8) * per + b / 8)
 // * 64 / LPA + (0 .. 64 / LPA - 1), so each XCD walks a contiguous stretch
 // of space and the neighbor rows it searches stay in its L2.
@@ -1163,16 +1163,18 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   }
   if (count_only || N == 0) return;
   nn_nlist* nl = L.nl;
-  // lanes per atom from the list's capacity per atom (about 1.25 times the
-  // mean row length when it was sized by a counting pass)
-  const int lpa = L.capacity <= 16 * N ? 16 : 64;
+  // lanes per atom: 16 for short rows (capacity per atom, about 1.25 times
+  // the mean row length when a counting pass sized the list, at most 16) and
+  // for lists of 16384 atoms or more, where fewer waves with longer loops
+  // serve better; 32 otherwise
+  const int lpa = (L.capacity <= 16 * N || N >= 16384) ? 16 : 32;
   const int64_t nw = (N + kWave / lpa - 1) / (kWave / lpa);
   const unsigned gEmit = nl->order ? (unsigned)((nw + 7) / 8 * 8) : (unsigned)nw;  // whole rounds of the 8 XCDs
   if (lpa == 16)
     hipLaunchKernelGGL(k_nb_emit<16>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
                        nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
   else
-    hipLaunchKernelGGL(k_nb_emit<64>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+    hipLaunchKernelGGL(k_nb_emit<32>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
                        nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
 }
 
