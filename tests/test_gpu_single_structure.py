@@ -6,14 +6,15 @@ whose bins are merged, an open molecule, a small periodic cell with lattice
 images and unwrapped positions must give the oracle's list entry for entry,
 with a consistent reverse index.  Bad inputs of a single structure (a
 non-finite position, an atom pointer array that does not end at N) are
-reported by nn_check."""
+reported by nn_check.  Structures of no, one and two atoms give the oracle's
+(empty or one-pair) list, energy and forces."""
 import numpy as np
 import pytest
 
 import oracle
 from paper_2305_11805_amd import nnpot, synth
 
-from helpers import list_rows_equal
+from helpers import E_TOL, F_TOL, list_rows_equal
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +112,27 @@ def test_single_structure_bad_atom_ptr_is_reported(skin):
     again = pot.neighbor_list_host()
     for k in ("offsets", "nbr", "shift", "rev"):
         assert np.array_equal(again[k], good[k]), k
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_tiny_single_structure_energy_forces_match_oracle(n):
+    """No atoms, one isolated atom (energy of a zero descriptor) and a pair:
+    the single-block binning launch, an empty list and the energy sums."""
+    rng = np.random.Generator(np.random.PCG64(40 + n))
+    s = synth.single(rng.uniform(0, 3, (n, 3)), rng.integers(0, 2, n))
+    p = synth.mbp_params(2, RC, 8, 4, 4)
+    model = synth.random_model(2, p.dim, [64, 32], 7, in_scale=2.0)
+    ref = oracle.neighbors_cells(s, p.rc)
+    Es_ref, _, F_ref = oracle.energy_forces(p, model, s, ref)
+    print(f"[single structure] {n} atoms", flush=True)
+    pot = nnpot.Potential(s, p, model)
+    pot.build_neighbors()
+    got = pot.neighbor_list_host()
+    assert np.array_equal(got["offsets"], ref["offsets"])
+    ok, msg = list_rows_equal(got, ref)
+    assert ok, msg
+    Es, _, F = pot.energy_forces()
+    nnpot.nn_check(pot.nl)
+    assert abs(float(Es.cpu().numpy()[0]) - Es_ref[0]) <= E_TOL * max(n, 1)
+    if n:
+        assert float(np.abs(F.cpu().numpy() - F_ref).max()) <= F_TOL
