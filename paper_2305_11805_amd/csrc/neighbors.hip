@@ -525,9 +525,10 @@ __global__ void k_nb_scatter(int64_t N, const double* __restrict__ pos, const in
 // launch in place of four).  Bin counts and starts never exceed the atom
 // count, so they are kept in LDS as the two 16-bit halves of 32-bit words;
 // the geometry allows at most 8 N + 64 bins, which kOneWords covers.  The
-// positions are loaded before the geometry is known; each atom's place in
-// bin order goes to LDS, and the bin-ordered outputs are then written
-// k = t, t + 1024, ... so that the stores of a wave are contiguous.  The
+// positions are loaded before the geometry is known; each atom's index and
+// position go to LDS at its place in bin order (the positions over the bin
+// counts, which are no longer needed), and the bin-ordered outputs are then
+// written k = t, t + 1024, ... so that the stores of a wave are contiguous.  The
 // outputs are those of the four passes: geom[0], n_bins[0], bin_base[0..1],
 // bin_start[0..n_bins], bin_m / bin_x / order in bin order, and a zero row
 // count for atoms with non-finite coordinates.
@@ -561,7 +562,11 @@ __global__ void __launch_bounds__(kOneThreads) k_nb_one(const double* __restrict
     for (int d = 0; d < 3; ++d) x[r][d] = i < N ? pos[3 * i + d] : 0.0;
   }
   constexpr int kW = kOneThreads / 64;
-  __shared__ uint32_t cnt[kOneWords];
+  __shared__ union {
+    uint32_t cnt[kOneWords];    // bin counts, then bin starts
+    double px[3][kOneAtoms];    // then the positions in bin order
+  } lds;
+  uint32_t* cnt = lds.cnt;
   __shared__ int32_t slot_atom[kOneAtoms];
   __shared__ double h[9], inv[9];
   __shared__ double ext[2][3][kW];
@@ -665,16 +670,23 @@ __global__ void __launch_bounds__(kOneThreads) k_nb_one(const double* __restrict
   const int total = (int)wsum[kW - 1];  // atoms with finite coordinates
   if (t == kOneThreads - 1) bin_start[nbins] = total;
   __syncthreads();
+  int slot[kOnePer];
 #pragma unroll
   for (int r = 0; r < kOnePer; ++r) {
-    if (bin[r] < 0) continue;
     const int sh = 16 * (bin[r] & 1);
-    slot_atom[((cnt[bin[r] >> 1] >> sh) & 0xffffu) + rank[r]] = t + kOneThreads * r;
+    slot[r] = bin[r] < 0 ? -1 : (int)((cnt[bin[r] >> 1] >> sh) & 0xffffu) + rank[r];
+  }
+  __syncthreads();  // every start is read before the positions take the counts' place
+#pragma unroll
+  for (int r = 0; r < kOnePer; ++r) {
+    if (slot[r] < 0) continue;
+    slot_atom[slot[r]] = t + kOneThreads * r;
+    for (int d = 0; d < 3; ++d) lds.px[d][slot[r]] = x[r][d];
   }
   __syncthreads();
   for (int k = t; k < total; k += kOneThreads) {
     const int i = slot_atom[k];
-    const double y[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    const double y[3] = {lds.px[0][k], lds.px[1][k], lds.px[2][k]};
     int b3[3], m[3] = {0, 0, 0};
     if (!g.small) bin_coords(g, pbc, y, b3, m);
     bin_m[k] = make_int4(i, m[0], m[1], m[2]);
