@@ -716,3 +716,36 @@ def test_loss_special_values(O):
     a = O.loss(np.array([0, 4]), np.array([4 * 0.3]), np.array([0.0]), per_atom=True)[0]
     b = O.loss(np.array([0, 1]), np.array([0.3]), np.array([0.0]), per_atom=True)[0]
     assert abs(a - b) < 1e-15
+
+
+def test_loss_hand_evaluated_normalisation(O):
+    """Hand-evaluated values of the loss of Sec. II.A on 3 structures of 1, 2
+    and 1 atoms (B = 3, N = 4, 12 force components), so that the energy mean
+    over structures (1/B) and the force mean over components (1/(3N)) cannot
+    be confused with each other or with 1/N:
+      dE = (1, 2, -1); quadratic: sum l_E = 6, L_E = w_E 6 / 3 = 2 w_E;
+      per atom: dE/N_c = (1, 1, -1), sum l_E = 3, L_E = w_E;
+      dF: one component +3, one -1, sum l_F = 10, L_F = w_F 10 / 12."""
+    ptr = np.array([0, 1, 3, 4])
+    E = np.array([1.0, 3.0, -2.0])
+    T = np.array([0.0, 1.0, -1.0])
+    F = np.zeros((4, 3))
+    Fr = np.zeros((4, 3))
+    F[1, 2] = 3.0
+    Fr[3, 0] = 1.0
+    wE, wF = 2.0, 0.6
+    L, dE, dF = O.loss(ptr, E, T, F, Fr, energy_weight=wE, force_weight=wF)
+    assert abs(L - (4.0 + 0.5)) < 1e-14
+    np.testing.assert_allclose(dE, [4.0 / 3.0, 8.0 / 3.0, -4.0 / 3.0], rtol=1e-15)
+    ref_dF = np.zeros((4, 3))
+    ref_dF[1, 2] = 0.3   # w_F / 12 * 2 * 3
+    ref_dF[3, 0] = -0.1  # w_F / 12 * 2 * (0 - 1)
+    np.testing.assert_allclose(dF, ref_dF, rtol=1e-14, atol=1e-16)
+    # per-atom energies: dE_c / N_c = (1, 1, -1); dL/dE_c = w_E / B * 2 (dE_c / N_c) / N_c
+    L, dE, _ = O.loss(ptr, E, T, per_atom=True, energy_weight=wE)
+    assert abs(L - 2.0) < 1e-14
+    np.testing.assert_allclose(dE, [4.0 / 3.0, 2.0 / 3.0, -4.0 / 3.0], rtol=1e-15)
+    # the exponential form at |x| = 1 for every structure: 3 (e - 1) w_E / 3
+    L, dE, _ = O.loss(ptr, E, T, per_atom=True, energy_weight=wE, energy_kind="exp")
+    assert abs(L - wE * (np.e - 1.0)) < 1e-14
+    np.testing.assert_allclose(dE, [wE / 3 * 2 * np.e, wE / 3 * 2 * np.e / 2, -wE / 3 * 2 * np.e], rtol=1e-14)
