@@ -1,13 +1,18 @@
 #!/usr/bin/env python3
 """Energy + force throughput of the mBP / per-species MLP path on one MI355X.
 
-One step = one pass of the whole path over the resident input: neighbor-list
-build (cell binning, FP64 inclusion test, row sort, reverse index), species
+One step = one pass of the whole path over the resident input.  The default
+workload is the repeated evaluation at scale: a 262144-atom periodic cell
+with 2 species (rho = 0.09 A^-3, Rc = 6 A, 48 radial + 8x8 angular bins, MLP
+288-128-128-1) whose atoms take a random walk of N(0, 0.02 A) per component
+and step.  Each step moves the atoms, tests the 0.5 A skin on the device and
+rebuilds the list (cell binning, FP64 inclusion test, row sort, reverse
+index) only when an atom moved farther than skin/2, then computes species
 grouping, radial + angular descriptors, per-species MLP forward + backward,
-FP64 per-structure energies, descriptor adjoint and force gather.  Inputs are
-synthetic (seeded RSA bulk cell: 4096 atoms, rho = 0.1 A^-3, Rc = 5 A,
-32 radial + 8x8 angular bins, MLP 96-128-128-1) and sit in HBM before the
-timed region.
+FP64 per-structure energies, the descriptor adjoint and the force gather.
+Inputs are synthetic and seeded and sit in HBM before the timed region;
+--config k selects another workload (those without a walk rebuild the list
+every step).
 
 Prints one JSON line: atoms/s, the roofline position of the dominant kernel
 (timed live with HIP events on the stream it runs on) and the FP64 oracle's
@@ -31,6 +36,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 METRIC = "energy+force atoms/sec at stated force error vs FP64 oracle; HBM GB/s"
+MODE_FLAGS = {"fp32": 0, "bf16": 1, "bf16x3": 4}  # NN_BF16_MLP, NN_BF16X3_MLP
 
 
 def ipow_mults(e: int) -> int:
@@ -106,13 +112,11 @@ def source_hash(kernel="k_desc_adj"):
     return h.hexdigest()[:16]
 
 
-def oracle_leg(w, F, target_s=15.0):
-    """The FP64 oracle as it stands, on the host cores, and the force error of
-    the GPU run on a seeded sample of atoms.
-
-    Throughput: per-atom energies and per-pair gradients (all of the E + F
-    work) for the first rows of the workload; if the whole workload takes
-    less than target_s, it is evaluated repeatedly until about target_s."""
+def oracle_leg(w, target_s=15.0):
+    """The FP64 oracle as it stands, on the host cores: per-atom energies and
+    per-pair gradients (all of the E + F work) for the first rows of the
+    workload at its input positions; if the whole workload takes less than
+    target_s, it is evaluated repeatedly until about target_s."""
     import oracle
     oracle.build(force=False)
     s, p = w.system, w.params
@@ -132,19 +136,23 @@ def oracle_leg(w, F, target_s=15.0):
         oracle.atom_energies(p, w.model, s, nl, pair_grads=True)
     dt = time.perf_counter() - t0
     what = f"the first {n2} of {s.n_atoms} atoms" if n2 < s.n_atoms else f"all {s.n_atoms} atoms x {reps} passes"
-    base = {"value": n2 * reps / dt, "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": n2 * reps / dt, "unit": "atoms/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"neighbor rows + E + per-pair dE/dd of {what} (FP64, OpenMP over atoms), {dt:.1f} s"}
-    return base, sampled_force_error(w, F)
 
 
-def sampled_force_error(w, F, n=16, seed=0):
+def sampled_force_error(w, F, n=16, seed=0, pos=None):
+    """Max |F - F_oracle| over n seeded atoms, at positions pos (default:
+    the workload's input positions)."""
     import oracle
+    from paper_2305_11805_amd import synth
+    s = w.system if pos is None else synth.System(np.asarray(pos, np.float64), w.system.species,
+                                                  w.system.atom_ptr, w.system.cell, w.system.pbc)
     rng = np.random.Generator(np.random.PCG64(seed))
-    t = np.sort(rng.choice(w.system.n_atoms, size=min(n, w.system.n_atoms), replace=False))
-    own = oracle.neighbors_cells(w.system, w.params.rc, rows=t)
+    t = np.sort(rng.choice(s.n_atoms, size=min(n, s.n_atoms), replace=False))
+    own = oracle.neighbors_cells(s, w.params.rc, rows=t)
     rows = np.array(sorted(set(t.tolist()) | set(own["nbr"].tolist())), np.int64)
-    nl = oracle.neighbors_cells(w.system, w.params.rc, rows=rows)
-    _, F_ref = oracle.forces(w.params, w.model, w.system, nl, t)
+    nl = oracle.neighbors_cells(s, w.params.rc, rows=rows)
+    _, F_ref = oracle.forces(w.params, w.model, s, nl, t)
     return float(np.max(np.abs(F[t] - F_ref)))
 
 
@@ -620,138 +628,162 @@ def suite(args):
             suite_config(idx, modes, args.steps, out)
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=1, help="workload index 0-4 (default: 1)")
-    ap.add_argument("--mode", choices=["fp32", "bf16", "bf16x3"], default="fp32")
-    ap.add_argument("--desc", choices=["mbp", "bp"], default="mbp",
-                    help="angular descriptor term: mBP (the headline) or standard BP (configs 0-2)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-variants", action="store_true", help="skip the steady-state and graph-replay timings")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch plan")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="also run one plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="no GPU run: turn two rocprofv3 --pmc CSVs of this workload into profiles/counters.json")
-    ap.add_argument("--suite", action="store_true",
-                    help="measure every workload (one JSON line each) instead of the single bench line")
-    ap.add_argument("--suite-configs", type=int, nargs="*", default=[0, 1, 2, 3, 4])
-    ap.add_argument("--suite-out", default="suite.jsonl")
-    ap.add_argument("--stored", action="store_true",
-                    help="time the stored-Jacobian mode (store and reuse steps) on --config instead of the bench line")
-    ap.add_argument("--ingest-kernels", nargs="*", default=["k_desc_adj", "k_desc_fwd", "k_mlp"],
-                    help="kernels whose counters --ingest-counters keeps")
-    ap.add_argument("--md", action="store_true",
-                    help="Langevin dynamics of 16-atom cells (the Table II shape) instead of the bench line")
-    ap.add_argument("--md-cells", type=int, default=1024, help="cells in the batched --md run")
-    ap.add_argument("--force-matching", action="store_true",
-                    help="time the force-matching training step on --config instead of the bench line")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
-    from paper_2305_11805_amd import synth
-    if args.suite:
-        suite(args)
-        return
-    if args.force_matching:
-        force_matching(args)
-        return
-    if args.md:
-        md_table2(args)
-        return
-    if args.stored:
-        stored_mode(args)
-        return
-    if args.ingest_counters:
-        if args.calib_copy_mib <= 0:
-            raise SystemExit("--ingest-counters needs --calib-copy-mib of the profiled run")
-        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config, desc=args.desc).name,
-                        kernels=tuple(args.ingest_kernels))
-        return
-
+def valid_neighbor_counts_gpu(pot, rc):
+    """Entries of each row inside rc (the skin list holds rc + skin), from
+    the list and positions on the device."""
     import torch
-    from paper_2305_11805_amd import nnpot
+    nnz = int(pot.offsets[-1].item())
+    off = pot.offsets
+    rows = torch.repeat_interleave(torch.arange(pot.N, device=pot.dev), off[1:] - off[:-1])
+    ptr = pot.atom_ptr
+    struct = torch.searchsorted(ptr, rows, right=True) - 1
+    cell = pot.cell.view(-1, 3, 3)
+    sh = pot.shift[:nnz, :3].to(torch.float64)
+    img = sh @ cell[0] if pot.B == 1 else torch.einsum("ek,ekl->el", sh, cell[struct])
+    d = pot.pos[pot.nbr[:nnz].long()] - pot.pos[rows] + img
+    valid = (d * d).sum(1) < rc * rc
+    return torch.bincount(rows[valid], minlength=pot.N).cpu().numpy()
 
+
+def headline(args):
+    """The bench line.  Workloads with a random walk (the 262144-atom cell)
+    time K steps of the walk from the input positions: per step x += xi_k,
+    the device skin test with a predicated list rebuild, then energies and
+    forces.  Other workloads rebuild the list every step."""
+    import torch
+    from paper_2305_11805_amd import nnpot, synth
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
     w = synth.config(args.config, desc=args.desc)
     s, p = w.system, w.params
-    flags = {"fp32": 0, "bf16": nnpot.NN_BF16_MLP, "bf16x3": nnpot.NN_BF16X3_MLP}[args.mode]
+    flags = MODE_FLAGS[args.mode]
     skin = float(w.extra.get("skin", 0.0))
-    pot = nnpot.Potential(s, p, w.model, skin=skin, flags=flags)
+    walk = "steps" in w.extra
+    pot = nnpot.Potential(s, p, w.model, skin=skin, flags=flags, capacity_margin=1.3 if walk else 1.25)
+    stream = torch.cuda.current_stream()
+    pos0 = pot.pos.clone()
+    n_disp = max(args.steps, args.warmup, 1)
+    xi = None
+    if walk:
+        xi = torch.tensor(np.stack(list(synth.md_displacements(w.seed, s.n_atoms, n_disp, w.extra["step_sigma"]))),
+                          dtype=torch.float64, device="cuda")
+    k = [0]
 
     def build():
         nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
 
-    def energy_forces():
-        nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, flags, 0, pot.E_struct,
+    def energy_forces(f=flags):
+        nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, f, 0, pot.E_struct,
                                pot.E_atom, pot.F, pot.ws)
 
-    def step():
+    def step(f=flags):
+        if walk:
+            pot.pos.add_(xi[k[0]])
+            k[0] += 1
         build()
-        energy_forces()
+        energy_forces(f)
 
-    for _ in range(max(args.warmup, 1)):
-        step()
-    torch.cuda.synchronize()
-    nnpot.nn_check(pot.nl)
-    plan = None if args.no_autotune else pot.autotune()  # launch plan for this shape class (untimed)
-    for _ in range(max(args.warmup, 1)):
-        step()
-    torch.cuda.synchronize()
+    def restart():
+        # the walk starts again from the input positions with a fresh list
+        torch.cuda.synchronize()
+        if walk:
+            pot.pos.copy_(pos0)
+            pot.meta[1] = 0
+            k[0] = 0
 
-    stream = torch.cuda.current_stream()
-
-    def timed(fn, k):
+    def timed(fn, n):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(k):
+        for _ in range(n):
             fn()
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
+    def builds():
+        return int(pot.meta[2].item())
+
+    restart()
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    nnpot.nn_check(pot.nl)
+    plan = None if args.no_autotune else pot.autotune()  # launch plan for this shape class (untimed)
+    restart()
+    for _ in range(max(args.warmup, 1)):
+        step()
+    restart()
+
     # the timed region: K whole steps
+    b0 = builds()
     total_ms = timed(step, args.steps)
+    n_builds = builds() - b0
     nnpot.nn_check(pot.nl)
     F = pot.F.cpu().numpy()
+    pos_end = pot.pos.cpu().numpy()
     # K more steps with the library's per-stage HIP events (on its launch
     # stream): per-kernel launch times for the roofline; the events add a
     # little time to these steps, so they are reported apart
+    restart()
     nnpot.nn_timing(True)
     staged_ms = timed(step, args.steps)
     stages = nnpot.nn_timing_read()
     nnpot.nn_timing(False)
     nnpot.nn_check(pot.nl)
+    assert np.array_equal(pot.F.cpu().numpy(), F), "the staged pass differs from the timed one"
+    n_valid = valid_neighbor_counts_gpu(pot, p.rc)
 
     variants = {}
     if not args.no_variants:
-        # E + F on the list already built (no rebuild), and the whole step
-        # replayed from a HIP graph
+        # E + F on the list already built (no rebuild)
         ms = timed(energy_forces, args.steps) / args.steps
         variants["steady_state_no_rebuild"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1)}
+        # the whole step replayed from a HIP graph; the walk's displacement is
+        # copied into the graph's input buffer before each replay
+        restart()
+        xi_buf = torch.zeros_like(pot.pos)
         side = torch.cuda.Stream()
         side.wait_stream(stream)
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=side):
-            step()
-        torch.cuda.synchronize()
-        graph.replay()
-        ms = timed(graph.replay, args.steps) / args.steps
-        variants["graph_replay"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1)}
-        torch.cuda.synchronize()
+            if walk:
+                pot.pos.add_(xi_buf)
+            build()
+            energy_forces()
+        restart()
+        kg = [0]
+
+        def replay():
+            if walk:
+                xi_buf.copy_(xi[kg[0]])
+                kg[0] += 1
+            graph.replay()
+        ms = timed(replay, args.steps) / args.steps
         nnpot.nn_check(pot.nl)
-        assert np.array_equal(pot.F.cpu().numpy(), F), "graph replay differs from the eager step"
+        same = bool(np.array_equal(pot.F.cpu().numpy(), F))
+        assert same, "graph replay differs from the eager steps"
+        variants["graph_replay"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1),
+                                    "forces_equal_eager_bitwise": same}
+        del graph
+        # the other MLP precision modes on the same walk, with their sampled
+        # force error against the oracle at the final positions
+        for mode in ("fp32", "bf16x3", "bf16"):
+            if mode == args.mode:
+                continue
+            restart()
+            for _ in range(max(args.warmup, 1)):
+                step(MODE_FLAGS[mode])
+            restart()
+            ms = timed(lambda: step(MODE_FLAGS[mode]), args.steps) / args.steps
+            nnpot.nn_check(pot.nl)
+            variants[f"mlp_{mode}"] = {
+                "ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1),
+                "force_err_max_sampled_eV_per_A": sampled_force_error(w, pot.F.cpu().numpy(),
+                                                                      pos=pot.pos.cpu().numpy())}
         # the same step through torch.autograd.Function: E forward, dE/dpos
-        # (= -F, from the adjoint) by backward
+        # (= -F, from the adjoint) by backward, at the walk's end positions
         from paper_2305_11805_amd import autograd
         pos_t = pot.pos.clone().requires_grad_(True)
 
@@ -762,6 +794,8 @@ def main():
             ag_step()
         ms = timed(ag_step, args.steps) / args.steps
         variants["autograd_function"] = {"ms_per_step": round(ms, 4), "value": round(s.n_atoms / ms * 1e3, 1)}
+        if args.config != 1:
+            variants["bulk4096_rebuild_every_step"] = small_bulk_line(args, flags)
 
     if args.calib_copy_mib > 0:
         a = torch.empty(args.calib_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -772,10 +806,9 @@ def main():
 
     ms_per_step = total_ms / args.steps
     value = s.n_atoms * args.steps / (total_ms / 1e3)
-    n_valid = valid_neighbor_counts(pot, p.rc)
     fm = flop_model(p, n_valid)
     single_kernel = ["desc_adj", "desc_fwd", "mlp", "force_gather", "energy"]
-    dom = max(single_kernel, key=lambda k: stages[k][0])
+    dom = max(single_kernel, key=lambda kk: stages[kk][0])
     dom_ms = stages[dom][0] / max(stages[dom][1], 1)
     if dom in ("desc_adj", "desc_fwd"):
         achieved = fm[dom] / (dom_ms / 1e3) / 1e12
@@ -828,26 +861,113 @@ def main():
             e["hbm_bytes_per_launch"] = b
             e["hbm_gbs"] = round(b / (ms_k / 1e3) / 1e9, 1)
         kern["k_mlp"] = e
+    cfg = {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
+           "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed,
+           "launch_plan": None if plan is None else {"waves_per_atom_fwd": plan[0], "waves_per_atom_adj": plan[1],
+                                                     "waves_per_mlp_tile": plan[2]}}
+    if walk:
+        cfg["walk"] = {"steps_timed": args.steps, "sigma_A": w.extra["step_sigma"], "list_builds_timed": n_builds,
+                       "rule": "rebuild on the device when an atom moved farther than skin/2 since the last build"}
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "bf16": "bf16-mlp/f32",
                                                         "bf16x3": "bf16x3-mlp/f32"}[args.mode],
-        "data": "synthetic (seeded RSA positions, seeded N(0, 1/fan_in) weights)",
-        "config": {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
-                   "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed,
-                   "launch_plan": None if plan is None else {"waves_per_atom_fwd": plan[0],
-                                                             "waves_per_atom_adj": plan[1],
-                                                             "waves_per_mlp_tile": plan[2]}},
+        "data": ("synthetic (seeded RSA positions; seeded W, b ~ N(0, 1/fan_in) with the first layer scaled by a "
+                 "fixed per-workload constant)"),
+        "config": cfg,
         "roofline": roof,
-        "stages_ms_per_step": {k: round(v[0] / args.steps, 5) for k, v in stages.items()},
+        "stages_ms_per_step": {kk: round(v[0] / args.steps, 5) for kk, v in stages.items()},
+        "stage_launches": {kk: int(v[1]) for kk, v in stages.items()},
         "ms_per_step_with_stage_events": round(staged_ms / args.steps, 4),
-        "pairs_per_step": fm["pairs"], "triplets_per_step": fm["triplets"], "kernels": kern,
+        "pairs_last_step": fm["pairs"], "triplets_last_step": fm["triplets"], "kernels": kern,
         "variants": variants,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["force_err_max_sampled_eV_per_A"] = oracle_leg(w, F)
+        out["cpu_baseline"] = oracle_leg(w)
+        out["force_err_max_sampled_eV_per_A"] = sampled_force_error(w, F, pos=pos_end)
     print(json.dumps(out), flush=True)
+
+
+def small_bulk_line(args, flags):
+    """The 4096-atom bulk cell with the list rebuilt every step (K steps)."""
+    import torch
+    from paper_2305_11805_amd import nnpot, synth
+    w = synth.config(1)
+    pot = nnpot.Potential(w.system, w.params, w.model, flags=flags)
+
+    def step():
+        nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+        nnpot.nn_energy_forces(pot.sys, pot.nl, pot.params, pot.dmodel.struct, flags, 0, pot.E_struct,
+                               pot.E_atom, pot.F, pot.ws)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    nnpot.nn_check(pot.nl)
+    plan = pot.autotune()
+    ms = _timed(torch, torch.cuda.current_stream(), step, args.steps) / args.steps
+    nnpot.nn_check(pot.nl)
+    return {"workload": w.name, "ms_per_step": round(ms, 4), "value": round(w.system.n_atoms / ms * 1e3, 1),
+            "launch_plan": list(plan)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=4,
+                    help="workload index 0-4 (default: 4, the 262144-atom cell's 100-step walk)")
+    ap.add_argument("--mode", choices=["fp32", "bf16", "bf16x3"], default="fp32")
+    ap.add_argument("--desc", choices=["mbp", "bp"], default="mbp",
+                    help="angular descriptor term: mBP (the headline) or standard BP (configs 0-2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the steady-state and graph-replay timings")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch plan")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 --pmc CSVs of this workload into profiles/counters.json")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure every workload (one JSON line each) instead of the single bench line")
+    ap.add_argument("--suite-configs", type=int, nargs="*", default=[0, 1, 2, 3, 4])
+    ap.add_argument("--suite-out", default="suite.jsonl")
+    ap.add_argument("--stored", action="store_true",
+                    help="time the stored-Jacobian mode (store and reuse steps) on --config instead of the bench line")
+    ap.add_argument("--ingest-kernels", nargs="*", default=["k_desc_adj", "k_desc_fwd", "k_mlp"],
+                    help="kernels whose counters --ingest-counters keeps")
+    ap.add_argument("--md", action="store_true",
+                    help="Langevin dynamics of 16-atom cells (the Table II shape) instead of the bench line")
+    ap.add_argument("--md-cells", type=int, default=1024, help="cells in the batched --md run")
+    ap.add_argument("--force-matching", action="store_true",
+                    help="time the force-matching training step on --config instead of the bench line")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    from paper_2305_11805_amd import synth
+    if args.suite:
+        suite(args)
+        return
+    if args.force_matching:
+        force_matching(args)
+        return
+    if args.md:
+        md_table2(args)
+        return
+    if args.stored:
+        stored_mode(args)
+        return
+    if args.ingest_counters:
+        if args.calib_copy_mib <= 0:
+            raise SystemExit("--ingest-counters needs --calib-copy-mib of the profiled run")
+        ingest_counters(*args.ingest_counters, args.calib_copy_mib, synth.config(args.config, desc=args.desc).name,
+                        kernels=tuple(args.ingest_kernels))
+        return
+
+    headline(args)
 
 
 if __name__ == "__main__":

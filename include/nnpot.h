@@ -50,7 +50,13 @@ enum { NN_ACT_LINEAR = 0, NN_ACT_GAUSSIAN = 1, NN_ACT_RELU = 2, NN_ACT_TANH = 3 
 
 /* Flags of nn_energy_forces. */
 enum {
-  NN_BF16_MLP = 1,       /* MLP products on BF16 MFMA, operands rounded to BF16, FP32 sums     */
+  NN_BF16_MLP = 1,       /* MLP products on BF16 MFMA, operands rounded to BF16, FP32 sums.
+                            Rounding G, W and the activations to 8 significant bits costs
+                            force accuracy: measured max |dF| against the FP64 reference is
+                            2.7e-2 eV/A on a 32768-atom 4-species bulk cell and 1.3e-2 on a
+                            262144-atom one, 13-27x over a 1e-3 eV/A force tolerance (energies
+                            stay within 1e-4 eV/atom).  Use NN_BF16X3_MLP where forces must
+                            meet 1e-3 eV/A.                                                   */
   NN_STORE_JACOBIAN = 2, /* store dG/dx during the descriptor pass if it fits mem_budget        */
   NN_BF16X3_MLP = 4,     /* MLP products on BF16 MFMA with every operand split into BF16 hi + lo
                             and three products (hi*hi + hi*lo + lo*hi), FP32 sums: about 16
@@ -58,7 +64,10 @@ enum {
                             Neither flag: FP32 MFMA.                                           */
   NN_REUSE_DESCRIPTORS = 8 /* skip the descriptor pass: use G and the Jacobian that an earlier
                               NN_STORE_JACOBIAN call with the same positions and list left in
-                              this workspace (weights may have changed)                        */
+                              this workspace (weights may have changed).  A list rebuilt since
+                              that call is detected on the device: the forces are then zero
+                              and nn_check reports NN_E_DEVICE.  Positions moved without a
+                              rebuild are not detected.                                        */
 };
 
 
@@ -94,7 +103,8 @@ typedef struct nn_system {
  *   (n_a, n_b, n_c, 0), rev [capacity] int32 (index of the reverse entry
  *   (j -> i, -n)), ref_pos [N][3] FP64 (positions at the last build),
  *   meta [8] int64 (nnz, valid, builds, rebuilt-last-call, error bits,
- *   -, -, -); zero meta once before the first build;
+ *   1 + builds at the last NN_STORE_JACOBIAN call, -, -); zero meta once
+ *   before the first build;
  *   order [N] int32, optional (NULL: not kept): the atoms in cell-bin order
  *   at the last build.  When present, the force gather walks the atoms in
  *   this order, each XCD taking a contiguous run of it, so that the rows
@@ -282,6 +292,9 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
  * being captured into a graph.  A plan changes only the order of some sums:
  * results stay bitwise reproducible for a fixed table.  plan_out [host]
  * (nullable) receives {waves/atom forward, waves/atom adjoint, waves/MLP tile}.
+ * The environment variable NNPOT_PLAN="f,a,m" (f, a in {1, 2, 4}; m in
+ * {4, 8}) overrides every plan, tuned or default, while it is set: a way to
+ * run each launch variant in tests.
  */
 nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
                       int32_t flags, void* ws, size_t ws_bytes, void* stream, int32_t* plan_out);

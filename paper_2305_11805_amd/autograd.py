@@ -16,6 +16,14 @@ import torch
 from . import nnpot
 
 
+def _check_current(ctx):
+    """The backward pass reads the Potential's list, descriptors and forces:
+    refuse it if another evaluation replaced them after this forward."""
+    if ctx.pot.evals != ctx.token:
+        raise RuntimeError("the Potential was evaluated again after this forward pass; run backward before the "
+                           "next evaluation on the same Potential (or use one Potential per graph)")
+
+
 def _weight_grads(wg, n):
     if wg is None:
         return [None] * n
@@ -31,19 +39,20 @@ class NNPotFn(torch.autograd.Function):
 
     The weights must be the Potential's own device tensors (pot.dmodel.tensors,
     species-major, W then b per layer): the library reads them by address.
-    A Potential holds the forces of its last forward, so run backward before
-    the next forward on the same Potential."""
+    A Potential holds the forces of its last forward, so backward must run
+    before the next evaluation on the same Potential; it raises otherwise."""
 
     @staticmethod
     def forward(ctx, pos, pot, flags, *weights):
         pot.pos.copy_(pos.detach())
-        nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+        pot.build_neighbors(check=False)
         E, _, _ = pot.energy_forces(flags=flags)
-        ctx.pot, ctx.flags = pot, flags
+        ctx.pot, ctx.flags, ctx.token = pot, flags, pot.evals
         return E.clone()
 
     @staticmethod
     def backward(ctx, gE):
+        _check_current(ctx)
         pot = ctx.pot
         need_pos = ctx.needs_input_grad[0]
         need_w = any(ctx.needs_input_grad[3:])
@@ -63,13 +72,14 @@ class NNPotEFFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, pos, pot, flags, *weights):
         pot.pos.copy_(pos.detach())
-        nnpot.nn_build_neighbors(pot.sys, pot.rc, pot.skin, pot.nl, pot.ws)
+        pot.build_neighbors(check=False)
         E, _, F = pot.energy_forces(flags=flags)
-        ctx.pot, ctx.flags = pot, flags
+        ctx.pot, ctx.flags, ctx.token = pot, flags, pot.evals
         return E.clone(), F.clone()
 
     @staticmethod
     def backward(ctx, gE, gF):
+        _check_current(ctx)
         pot = ctx.pot
         need_pos = ctx.needs_input_grad[0]
         need_w = any(ctx.needs_input_grad[3:])

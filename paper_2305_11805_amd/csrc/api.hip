@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -68,7 +69,23 @@ static PlanKey plan_key(int64_t n_atoms, int64_t capacity, const DescConst& P, c
   return k;
 }
 
+// NNPOT_PLAN="f,a,m" in the environment forces a plan on every call (waves
+// per atom of the forward and adjoint passes in {1, 2, 4}, waves per MLP
+// tile in {4, 8}): lets tests run each launch variant against the oracle.
+static bool forced_plan(LaunchPlan* out) {
+  const char* e = getenv("NNPOT_PLAN");
+  if (!e || !*e) return false;
+  int f = 0, a = 0, m = 0;
+  if (sscanf(e, "%d,%d,%d", &f, &a, &m) != 3) return false;
+  auto ok = [](int w) { return w == 1 || w == 2 || w == 4; };
+  if (!ok(f) || !ok(a) || (m != 4 && m != 8)) return false;
+  *out = LaunchPlan{f, a, m};
+  return true;
+}
+
 static LaunchPlan plan_for(int64_t n_atoms, int64_t capacity, const DescConst& P, const nn_model* model, int mode) {
+  LaunchPlan forced;
+  if (forced_plan(&forced)) return forced;
   const PlanKey k = plan_key(n_atoms, capacity, P, model, mode);
   std::lock_guard<std::mutex> g(g_pmu);
   auto it = g_plans.find(k);
@@ -439,6 +456,91 @@ __global__ void k_zero_meta(int64_t* m) {
   if (threadIdx.x < 8) m[threadIdx.x] = 0;
 }
 
+// Records which build of the list the workspace's stored Jacobian belongs to.
+__global__ void k_mark_jac(int64_t* meta) {
+  if (threadIdx.x == 0) meta[kMetaJac] = meta[kMetaBuilds] + 1;
+}
+
+// Checks shared by the energy/force entry points; fills the kernels'
+// descriptor constants.
+static nn_status check_ef_args(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
+                               int32_t flags, const double* E_struct, DescConst* P) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  if ((st = make_desc_const(p, P))) return st;
+  if ((st = check_model(model, *P))) return st;
+  if (!E_struct && sys->n_structs > 0) return fail(NN_E_INVALID, "E_struct is NULL");
+  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
+  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
+    return fail(NN_E_INVALID, "unknown flags");
+  if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
+    return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
+  return NN_OK;
+}
+
+// The launches of one energy/force evaluation on the workspace layout L
+// (stored: the layout holds a Jacobian within the caller's budget).
+static void ef_enqueue(const nn_system* sys, const nn_nlist* nl, const DescConst& P, const nn_model* model,
+                       int32_t flags, const Layout& L, bool stored, double* E_struct, float* E_atom, float* F,
+                       hipStream_t s) {
+  const bool reuse = flags & NN_REUSE_DESCRIPTORS;
+  const int64_t N = sys->n_atoms;
+  const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
+  const bool bf16 = mode != 0;
+  if (N == 0) {
+    if (sys->n_structs > 0) launch_energy_reduce(L.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+    return;
+  }
+  const LaunchPlan plan = plan_for(N, nl->capacity, P, model, mode);
+  // species grouping (with one species the descriptor launch writes the
+  // identity grouping)
+  const bool fold_species = P.S == 1 && !reuse;
+  if (!fold_species) {
+    StageTimer t(NN_STAGE_SPECIES, s);
+    launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+  }
+  MlpArgs a{};
+  prepare_model(model, P, L, bf16, a, s);
+  // descriptors (and the stored Jacobian)
+  if (!reuse) {
+    StageTimer t(NN_STAGE_DESC_FWD, s);
+    launch_desc_fwd(*sys, *nl, P, L.G, fold_species ? IdentityGroup{L.perm, L.sp_start} : IdentityGroup{},
+                    plan.wpa_fwd, s);
+  }
+  if (stored && !reuse) {
+    StageTimer t(NN_STAGE_DESC_JAC, s);
+    launch_desc_jac(*sys, *nl, P, L.jac, s);
+    hipLaunchKernelGGL(k_mark_jac, dim3(1), dim3(64), 0, s, nl->meta);
+  }
+  // MLP energies and lambda
+  a.G = L.G;
+  a.perm = L.perm;
+  a.sp_start = L.sp_start;
+  a.E_atom = E_atom ? E_atom : L.E_atom;
+  a.lambda = F ? L.lam : nullptr;
+  a.D = P.D;
+  {
+    StageTimer t(NN_STAGE_MLP, s);
+    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
+  }
+  if (!F) {
+    StageTimer t(NN_STAGE_ENERGY, s);
+    launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+  } else {
+    if (stored) {
+      StageTimer t(NN_STAGE_JAC_CONTRACT, s);
+      launch_jac_contract(*sys, *nl, P, L.lam, L.jac, L.pg, s);
+    } else {
+      StageTimer t(NN_STAGE_DESC_ADJ, s);
+      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, plan.wpa_adj, s);
+    }
+    // the per-structure energy sums ride along in the gather's launch
+    StageTimer t(NN_STAGE_FORCE_GATHER, s);
+    launch_force_gather(*sys, *nl, L.pg, F, EnergyJob{a.E_atom, sys->atom_ptr, sys->n_structs, E_struct}, s);
+  }
+}
+
 }  // namespace nnp
 
 using namespace nnp;
@@ -558,18 +660,9 @@ nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const 
 nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
                            int32_t flags, size_t mem_budget, double* E_struct, float* E_atom, float* F, void* ws,
                            size_t ws_bytes, void* stream) {
-  nn_status st = check_system(sys);
-  if (st) return st;
-  if ((st = check_nlist(nl, sys, true))) return st;
   DescConst P;
-  if ((st = make_desc_const(p, &P))) return st;
-  if ((st = check_model(model, P))) return st;
-  if (!E_struct && sys->n_structs > 0) return fail(NN_E_INVALID, "E_struct is NULL");
-  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
-  if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
-    return fail(NN_E_INVALID, "unknown flags");
-  if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
-    return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
+  nn_status st = check_ef_args(sys, nl, p, model, flags, E_struct, &P);
+  if (st) return st;
   const int64_t N = sys->n_atoms;
   const size_t jf = jac_request(P, nl->capacity, flags, mem_budget);
   if ((flags & NN_REUSE_DESCRIPTORS) && !jf)
@@ -577,61 +670,7 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model, jf);
   if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
   L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model, jf);
-  const bool reuse = flags & NN_REUSE_DESCRIPTORS;
-  const bool stored = jf != 0;
-  hipStream_t s = (hipStream_t)stream;
-  const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
-  const bool bf16 = mode != 0;
-  if (N == 0) {
-    if (sys->n_structs > 0) launch_energy_reduce(L.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
-    return check_launch("nn_energy_forces");
-  }
-  const LaunchPlan plan = plan_for(N, nl->capacity, P, model, mode);
-  // species grouping (with one species the descriptor launch writes the
-  // identity grouping)
-  const bool fold_species = P.S == 1 && !reuse;
-  if (!fold_species) {
-    StageTimer t(NN_STAGE_SPECIES, s);
-    launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
-  }
-  MlpArgs a{};
-  prepare_model(model, P, L, bf16, a, s);
-  // descriptors (and the stored Jacobian)
-  if (!reuse) {
-    StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, L.G, fold_species ? IdentityGroup{L.perm, L.sp_start} : IdentityGroup{},
-                    plan.wpa_fwd, s);
-  }
-  if (stored && !reuse) {
-    StageTimer t(NN_STAGE_DESC_JAC, s);
-    launch_desc_jac(*sys, *nl, P, L.jac, s);
-  }
-  // MLP energies and lambda
-  a.G = L.G;
-  a.perm = L.perm;
-  a.sp_start = L.sp_start;
-  a.E_atom = E_atom ? E_atom : L.E_atom;
-  a.lambda = F ? L.lam : nullptr;
-  a.D = P.D;
-  {
-    StageTimer t(NN_STAGE_MLP, s);
-    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
-  }
-  if (!F) {
-    StageTimer t(NN_STAGE_ENERGY, s);
-    launch_energy_reduce(a.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
-  } else {
-    if (stored) {
-      StageTimer t(NN_STAGE_JAC_CONTRACT, s);
-      launch_jac_contract(*sys, *nl, P, L.lam, L.jac, L.pg, s);
-    } else {
-      StageTimer t(NN_STAGE_DESC_ADJ, s);
-      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, plan.wpa_adj, s);
-    }
-    // the per-structure energy sums ride along in the gather's launch
-    StageTimer t(NN_STAGE_FORCE_GATHER, s);
-    launch_force_gather(*sys, *nl, L.pg, F, EnergyJob{a.E_atom, sys->atom_ptr, sys->n_structs, E_struct}, s);
-  }
+  ef_enqueue(sys, nl, P, model, flags, L, jf != 0, E_struct, E_atom, F, (hipStream_t)stream);
   return check_launch("nn_energy_forces");
 }
 
@@ -882,6 +921,8 @@ nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {
   if (err & kErrNonFinite) return fail(NN_E_DEVICE, "non-finite position");
   if (err & kErrShift) return fail(NN_E_DEVICE, "lattice image index beyond int8");
   if (err & kErrTooMany) return fail(NN_E_DEVICE, "too many neighbors (> %d inside rc or > %d per row)", kMaxNb, kRowMax);
+  if (err & kErrStale)
+    return fail(NN_E_DEVICE, "NN_REUSE_DESCRIPTORS after a list rebuild: the stored Jacobian is stale (forces zeroed)");
   return NN_OK;
 }
 

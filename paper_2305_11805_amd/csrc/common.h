@@ -26,10 +26,13 @@ enum : int64_t {
   kErrTooMany = 16,   // more than kMaxNb neighbors inside rc, or a row over kRowMax
   kErrShift = 32,     // lattice image index does not fit in int8
   kErrPtr = 64,       // atom_ptr not 0 .. N nondecreasing
+  kErrStale = 128,    // stored descriptors reused after the list was rebuilt
 };
 
 // Layout of the device metadata block of a neighbor list (nl->meta, int64[8]).
-enum { kMetaNnz = 0, kMetaValid = 1, kMetaBuilds = 2, kMetaRebuilt = 3, kMetaErr = 4 };
+// kMetaJac: 1 + the build count of the list when the workspace's Jacobian
+// was last stored (0: never), checked by the reuse path.
+enum { kMetaNnz = 0, kMetaValid = 1, kMetaBuilds = 2, kMetaRebuilt = 3, kMetaErr = 4, kMetaJac = 5 };
 
 // Per-structure geometry computed on the device before binning.
 struct alignas(16) StructGeom {

@@ -73,6 +73,25 @@ __device__ __forceinline__ int struct_of_atom(const int64_t* atom_ptr, int32_t B
   return lo;
 }
 
+// The atom a one-atom-per-block descriptor launch works on.  With the
+// list's bin order (kept by the list build) the grid is whole rounds of the
+// eight XCDs and block b takes slot (b mod 8) * per + b / 8 of that order:
+// consecutive blocks go to different XCDs, so each XCD walks one contiguous
+// stretch of space and the neighbor positions its atoms gather stay in its
+// L2.  Without the order, or while the list is not valid (the order is then
+// not a permutation), the slot is the atom.  -1 for slots past the atoms.
+__device__ __forceinline__ int64_t atom_of_block(const int32_t* __restrict__ order, int64_t N, bool valid) {
+  int64_t slot = blockIdx.x;
+  if (order) slot = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  if (slot >= N) return -1;
+  return (order && valid) ? (int64_t)order[slot] : slot;
+}
+
+// Blocks of such a launch: whole rounds of the eight XCDs with the order.
+static inline unsigned atom_grid(int64_t N, const int32_t* order) {
+  return (unsigned)(order ? (N + 7) / 8 * 8 : N);
+}
+
 constexpr int kStageRounds = 2;  // rows up to 128 entries are staged in one pass
 
 // Stage the neighbors of atom i inside rc into LDS, sorted by species.
@@ -449,14 +468,17 @@ template <int NT, int NRA, int WPA, int ZC>
 __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ nbr,
                                                        const int8_t* __restrict__ shift, DescConst P,
-                                                       float* __restrict__ G, int64_t* meta, IdentityGroup one) {
+                                                       float* __restrict__ G, int64_t* meta, IdentityGroup one,
+                                                       const int32_t* __restrict__ order) {
   constexpr int NB = NT * NRA;
   __shared__ AtomNb nb;
+  const bool list_ok = meta[kMetaValid] == 1;
+  const int64_t i = atom_of_block(order, sys.n_atoms, list_ok);
+  if (i < 0) return;
   if (one.perm && threadIdx.x == 0) {
-    one.perm[blockIdx.x] = (int32_t)blockIdx.x;
-    if (sys.species[blockIdx.x] != 0)
-      atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
-    if (blockIdx.x == 0) {
+    one.perm[i] = (int32_t)i;
+    if (sys.species[i] != 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+    if (i == 0) {
       one.sp_start[0] = 0;
       one.sp_start[1] = sys.n_atoms;
     }
@@ -466,10 +488,9 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
   __shared__ float4 tgeo[WPA][kWave];  // per chunk: cos, smoothed sine, average radius (hi, lo)
   __shared__ float tf2[WPA][kWave];    // and 2 fc fc
   __shared__ double d64[ZC == kZcBP ? 3 * kMaxNb : 1];  // BP: FP64 displacements for the third side
-  const int64_t i = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Gi = G + i * (int64_t)P.D;
-  if (meta[kMetaValid] != 1) {  // no valid list: never read its entries
+  if (!list_ok) {  // no valid list: never read its entries
     for (int d = tid; d < P.D; d += 64 * WPA) Gi[d] = 0.f;
     return;
   }
@@ -775,7 +796,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
                                                        const int32_t* __restrict__ nbr,
                                                        const int8_t* __restrict__ shift, DescConst P,
                                                        const float* __restrict__ field, float* __restrict__ U,
-                                                       int64_t* meta) {
+                                                       int64_t* meta, const int32_t* __restrict__ order) {
   constexpr int NB = NT * NRA;
   __shared__ AtomNb nb;
   __shared__ float4 tw[kMaxNb];  // per neighbor: (v_j - v_i) / r, and r_dot
@@ -783,10 +804,12 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
   __shared__ float4 tgeo[WPA][kWave], tdot[WPA][kWave];  // per chunk: geometry; F2, zeta cos_dot, zeta ssm_dot, F2_dot
   __shared__ float tg2[WPA][kWave];                      // and -2 eta r_dot F2
   __shared__ double d64[ZC == kZcBP ? 3 * kMaxNb : 1];  // BP: FP64 displacements for the third side
-  const int64_t i = blockIdx.x;
+  const bool list_ok = meta[kMetaValid] == 1;
+  const int64_t i = atom_of_block(order, sys.n_atoms, list_ok);
+  if (i < 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   float* Ui = U + i * (int64_t)P.D;
-  if (meta[kMetaValid] != 1) {
+  if (!list_ok) {
     for (int d = tid; d < P.D; d += 64 * WPA) Ui[d] = 0.f;
     return;
   }
@@ -1091,7 +1114,7 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
                                                        const int32_t* __restrict__ nbr,
                                                        const int8_t* __restrict__ shift, DescConst P,
                                                        const float* __restrict__ lambda, float4* __restrict__ pg,
-                                                       int64_t* meta) {
+                                                       int64_t* meta, const int32_t* __restrict__ order) {
   constexpr int NB = NT * NRA;
   constexpr int NBP = NB + 4;  // padded block stride in LDS (bank spread)
   __shared__ AtomNb nb;
@@ -1099,9 +1122,10 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   extern __shared__ float dyn_lds[];  // [S * n_rad] radial lambda, then the angular blocks
   float* lam_r = dyn_lds;
   float* lam_a = dyn_lds + P.S * P.n_rad;
-  const int64_t i = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
+  const int64_t i = atom_of_block(order, sys.n_atoms, true);
+  if (i < 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t e0 = offsets[i];
   // this atom's lambda is requested before the neighbor staging (whose
   // loads it then overlaps) and put into LDS after it
@@ -1403,8 +1427,8 @@ LaunchPlan plan_default(int64_t n_atoms, int n_species, int64_t capacity) {
 template <int NT, int NRA, int WPA, int ZC>
 static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
                          hipStream_t s) {
-  hipLaunchKernelGGL((k_desc_fwd<NT, NRA, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), 0, s, sys,
-                     nl.offsets, nl.nbr, nl.shift, P, G, nl.meta, one);
+  hipLaunchKernelGGL((k_desc_fwd<NT, NRA, WPA, ZC>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64 * WPA), 0, s,
+                     sys, nl.offsets, nl.nbr, nl.shift, P, G, nl.meta, one, nl.order);
 }
 
 template <int NT, int NRA>
@@ -1428,8 +1452,8 @@ static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescCon
 template <int NT, int NRA, int WPA, int ZC>
 static void launch_tan_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* v, float* U,
                          hipStream_t s) {
-  hipLaunchKernelGGL((k_desc_tan<NT, NRA, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), 0, s, sys,
-                     nl.offsets, nl.nbr, nl.shift, P, v, U, nl.meta);
+  hipLaunchKernelGGL((k_desc_tan<NT, NRA, WPA, ZC>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64 * WPA), 0, s,
+                     sys, nl.offsets, nl.nbr, nl.shift, P, v, U, nl.meta, nl.order);
 }
 
 template <int NT, int NRA>
@@ -1454,8 +1478,8 @@ template <int NT, int NRA, bool ONE, int WPA, int ZC>
 static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                          hipStream_t s) {
   const size_t lds = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
-  hipLaunchKernelGGL((k_desc_adj<NT, NRA, ONE, WPA, ZC>), dim3((unsigned)sys.n_atoms), dim3(64 * WPA), lds, s, sys,
-                     nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta);
+  hipLaunchKernelGGL((k_desc_adj<NT, NRA, ONE, WPA, ZC>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64 * WPA), lds,
+                     s, sys, nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta, nl.order);
 }
 
 template <int NT, int NRA, bool ONE>
@@ -1550,14 +1574,16 @@ __host__ __device__ inline int jac_stride(int n_rad, int S, int NB) { return (n_
 template <int NT, int NRA, bool BP>
 __global__ void __launch_bounds__(64) k_desc_jac(nn_system sys, const int64_t* __restrict__ offsets,
                                                  const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
-                                                 DescConst P, float* __restrict__ J, int64_t* meta) {
+                                                 DescConst P, float* __restrict__ J, int64_t* meta,
+                                                 const int32_t* __restrict__ order) {
   constexpr int NB = NT * NRA;
   __shared__ AtomNb nb;
-  const int64_t i = blockIdx.x;
   const int lane = threadIdx.x;
   const int S = P.S;
   const int js = jac_stride(P.n_rad, S, NB);
   if (meta[kMetaValid] != 1) return;
+  const int64_t i = atom_of_block(order, sys.n_atoms, true);
+  if (i < 0) return;
   const int64_t e0 = offsets[i], e1 = offsets[i + 1];
   {
     // rows of entries outside rc (skin lists) are all zero; valid rows are
@@ -1711,14 +1737,23 @@ template <int NT, int NRA>
 __global__ void __launch_bounds__(64) k_jac_contract(nn_system sys, const int64_t* __restrict__ offsets,
                                                      const int32_t* __restrict__ nbr, DescConst P,
                                                      const float* __restrict__ lambda, const float* __restrict__ J,
-                                                     float4* __restrict__ pg, const int64_t* meta) {
+                                                     float4* __restrict__ pg, int64_t* meta,
+                                                     const int32_t* __restrict__ order) {
   constexpr int NB = NT * NRA;
   extern __shared__ float lam[];  // [D]
-  const int64_t i = blockIdx.x;
   const int lane = threadIdx.x, sub = lane & 15, grp = lane >> 4;
   const int S = P.S;
   const int js = jac_stride(P.n_rad, S, NB);
   if (meta[kMetaValid] != 1) return;
+  const int64_t i = atom_of_block(order, sys.n_atoms, true);
+  if (i < 0) return;
+  if (meta[kMetaJac] != meta[kMetaBuilds] + 1) {
+    // the list was rebuilt since the Jacobian was stored: its rows refer to
+    // other entries, so the pair gradients are zero and the call is flagged
+    for (int64_t e = offsets[i] + lane; e < offsets[i + 1]; e += kWave) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrStale);
+    return;
+  }
   for (int d = lane; d < P.D; d += kWave) lam[d] = lambda[i * (int64_t)P.D + d];
   __syncthreads();
   const int64_t e0 = offsets[i], e1 = offsets[i + 1];
@@ -1771,18 +1806,18 @@ size_t jacobian_floats(int n_rad, int S, int nt, int nra, int64_t capacity) {
 template <int NT, int NRA>
 static void launch_jac_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s) {
   if (P.kind == NN_DESC_BP)
-    hipLaunchKernelGGL((k_desc_jac<NT, NRA, true>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets,
-                       nl.nbr, nl.shift, P, J, nl.meta);
+    hipLaunchKernelGGL((k_desc_jac<NT, NRA, true>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64), 0, s, sys,
+                       nl.offsets, nl.nbr, nl.shift, P, J, nl.meta, nl.order);
   else
-    hipLaunchKernelGGL((k_desc_jac<NT, NRA, false>), dim3((unsigned)sys.n_atoms), dim3(64), 0, s, sys, nl.offsets,
-                       nl.nbr, nl.shift, P, J, nl.meta);
+    hipLaunchKernelGGL((k_desc_jac<NT, NRA, false>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64), 0, s, sys,
+                       nl.offsets, nl.nbr, nl.shift, P, J, nl.meta, nl.order);
 }
 
 template <int NT, int NRA>
 static void launch_contract_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam,
                               const float* J, float4* pg, hipStream_t s) {
-  hipLaunchKernelGGL((k_jac_contract<NT, NRA>), dim3((unsigned)sys.n_atoms), dim3(64), sizeof(float) * P.D, s, sys,
-                     nl.offsets, nl.nbr, P, lam, J, pg, nl.meta);
+  hipLaunchKernelGGL((k_jac_contract<NT, NRA>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64), sizeof(float) * P.D,
+                     s, sys, nl.offsets, nl.nbr, P, lam, J, pg, nl.meta, nl.order);
 }
 
 void launch_desc_jac(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* J, hipStream_t s) {

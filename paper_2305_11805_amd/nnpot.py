@@ -31,6 +31,7 @@ NN_LOSS_EXP = 1
 ACT = {"linear": 0, "gaussian": 1, "relu": 2, "tanh": 3}
 STATUS = {0: "NN_OK", 1: "NN_E_INVALID", 2: "NN_E_CAPACITY", 3: "NN_E_CELL", 4: "NN_E_WORKSPACE",
           5: "NN_E_UNSUPPORTED", 6: "NN_E_HIP", 7: "NN_E_DEVICE"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 
 
 class NNError(RuntimeError):
@@ -359,11 +360,15 @@ class Potential:
         self.E_atom = z(self.N, torch.float32)
         self.F = z((self.N, 3), torch.float32)
         self.G = None
+        # calls through this object that replace the state a backward pass
+        # reads (list, workspace descriptors, forces); autograd checks it
+        self.evals = 0
 
     def set_positions(self, pos):
         self.pos.copy_(self.torch.as_tensor(pos, dtype=self.torch.float64))
 
     def build_neighbors(self, check: bool = True):
+        self.evals += 1
         nn_build_neighbors(self.sys, self.rc, self.skin, self.nl, self.ws)
         if check:
             nn_check(self.nl)
@@ -395,6 +400,7 @@ class Potential:
         if E_pot is None:
             E_pot = torch.empty((max(int(n_steps), 1), self.B), dtype=torch.float64, device=self.dev)
         lp = nn_langevin(float(dt), float(friction), float(kT))
+        self.evals += 1
         nn_md_langevin(self.sys, self.pos, vel, inv_mass, self.nl, self.rc, self.skin, self.params,
                        self.dmodel.struct, f, lp, noise, n_steps, E_pot, self.F, self.ws)
         return E_pot
@@ -422,11 +428,13 @@ class Potential:
     def autotune(self, flags: Optional[int] = None):
         """nn_autotune on the current list (build it first)."""
         f = self.flags if flags is None else flags
+        self.evals += 1
         return nn_autotune(self.sys, self.nl, self.params, self.dmodel.struct, f, self.ws)
 
     def energy_forces(self, flags: Optional[int] = None, forces: bool = True, mem_budget: Optional[int] = None):
         f = self.flags if flags is None else flags
         b = self.mem_budget if mem_budget is None else int(mem_budget)
+        self.evals += 1
         nn_energy_forces(self.sys, self.nl, self.params, self.dmodel.struct, f, b, self.E_struct,
                          self.E_atom, self.F if forces else None, self.ws)
         return self.E_struct, self.E_atom, self.F

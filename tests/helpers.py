@@ -71,3 +71,32 @@ def tangent_error(U, U_ref, p):
         scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-30)
         worst = max(worst, float((np.abs(U[:, c0:c1] - ref) / scale).max()))
     return worst
+
+
+def tangent_noise_floor(p, s, nl, v, trials=3, h=1e-7, seed=0):
+    """Per-element spread of the oracle's descriptor tangent when every
+    position moves by up to h (about one FP32 rounding of a displacement of
+    a few A): the GPU rounds each displacement to FP32 before forming the
+    tangent, so where the terms of an element cancel (for instance a
+    neighbor moving nearly perpendicular to its bond) its result cannot be
+    closer to the FP64 value than this spread."""
+    U0 = oracle.descriptor_tangent(p, s, nl, v)
+    out = np.zeros_like(U0)
+    for t in range(trials):
+        rng = np.random.Generator(np.random.PCG64(seed + t))
+        s2 = synth.System(s.pos + rng.uniform(-h, h, s.pos.shape), s.species, s.atom_ptr, s.cell, s.pbc)
+        out = np.maximum(out, np.abs(oracle.descriptor_tangent(p, s2, nl, v) - U0))
+    return out
+
+
+def tangent_error_with_floor(U, U_ref, p, floor, rel=1e-4, k=4.0):
+    """Max over elements of |dU| / (rel * block scale + k * noise floor):
+    pass if <= 1."""
+    worst = 0.0
+    for c0, c1 in block_bounds(p):
+        ref = U_ref[:, c0:c1]
+        scale = np.abs(ref).max(axis=1, keepdims=True)
+        bar = rel * scale + k * floor[:, c0:c1]
+        bar = np.maximum(bar, 1e-30)
+        worst = max(worst, float((np.abs(U[:, c0:c1] - ref) / bar).max()))
+    return worst

@@ -84,3 +84,40 @@ def test_md_host_side_errors(L):
     assert call(nnpot.nn_langevin(0.5, 0.01, 0.025)) == 1       # friction > 0 needs noise
     assert "noise" in nnpot.nn_last_error()
     assert call(nnpot.nn_langevin(0.5, 0.01, 0.025), n_steps=0, noise=a[4]) == 0  # nothing to do
+
+
+def test_short_workspace_rejected_before_any_launch(L):
+    """Every call that takes a workspace returns NN_E_WORKSPACE, with the
+    size it needs in the message, when ws_bytes is below nn_workspace_size
+    (host-side check: nothing is enqueued, so no GPU is needed)."""
+    w = synth.config(0)
+    p, model = w.params, w.model
+    s, keep = nnpot.make_params(p)
+    a = [C.c_void_p(0x10000 * k) for k in range(1, 16)]
+    sysd = nnpot.nn_system(192, 16, a[0].value, a[1].value, a[2].value, a[3].value, a[4].value)
+    cap = 4000
+    nl = nnpot.nn_nlist(cap, a[5].value, a[6].value, a[7].value, a[8].value, a[9].value, a[10].value, None, 4.6)
+    m = nnpot.nn_model()
+    m.n_species = len(model)
+    for sp, (widths, acts, Ws, bs) in enumerate(model):
+        q = m.mlp[sp]
+        q.n_layers = len(Ws)
+        for l, wd in enumerate(widths):
+            q.width[l] = wd
+        for l, act in enumerate(acts):
+            q.act[l] = nnpot.ACT[act]
+        for l in range(len(Ws)):
+            q.W[l] = a[11].value
+            q.b[l] = a[12].value
+    need = nnpot.nn_workspace_size(192, 16, cap, s, m)
+    ws, E, F = a[13], a[14], a[1]
+    st = L.nn_energy_forces(C.byref(sysd), C.byref(nl), C.byref(s), C.byref(m), 0, 0, E, None, F, ws, need - 1,
+                            None)
+    assert st == 4 and f"< {need} bytes" in nnpot.nn_last_error()
+    assert L.nn_build_neighbors(C.byref(sysd), 4.6, 0.0, C.byref(nl), ws, 16, None) == 4
+    assert L.nn_energy_forces_grad(C.byref(sysd), C.byref(nl), C.byref(s), C.byref(m), 0, E, None, None, None,
+                                   None, None, ws, need - 1, None) == 4
+    n = C.c_int64(0)
+    assert L.nn_count_neighbors(C.byref(sysd), 4.6, C.byref(n), ws, 8, None) == 4
+    lp = nnpot.nn_loss_params(0, 0, 0, 1.0, 1.0)
+    assert L.nn_loss(C.byref(sysd), C.byref(lp), E, E, None, None, E, E, None, ws, 8, None) == 4

@@ -122,10 +122,13 @@ def test_energy_forces_match_oracle(name, mode):
 
 
 # Plain BF16 operands (unit roundoff u = 2^-9 on G, weights, activations and
-# deltas): errors scale with u times the magnitudes; bound 16 u of the
-# largest atomic energy / force component.
+# deltas) do NOT meet the 1e-3 eV/A force tolerance: errors scale with u
+# times the magnitudes (measured 1e-2 to 3e-2 eV/A on the bulk workloads).
+# This test only holds the mode to its rounding model, 16 u of the largest
+# atomic energy / force component; NN_BF16X3_MLP is the mode that meets the
+# stated tolerances (test_energy_forces_match_oracle).
 @pytest.mark.parametrize("name", list(CASES))
-def test_energy_forces_plain_bf16_within_rounding_bound(name):
+def test_plain_bf16_error_follows_its_rounding_model_not_the_force_tolerance(name):
     print(f"[energy/forces] {name} bf16", flush=True)
     err = run_energy_forces(name, nnpot.NN_BF16_MLP)
     u = 2.0 ** -9
