@@ -141,6 +141,18 @@ def random_model(n_species, D, hidden: Sequence[int], seed, act="gaussian", in_s
     return model
 
 
+def random_model_per_species(D, hidden_per_species: Sequence[Sequence[int]], seed, act="gaussian",
+                             in_scale=1.0) -> Model:
+    """Per-species networks of different depths and widths (Sec. II.A lets
+    each species have its own architecture): species s gets
+    D -> hidden_per_species[s]... -> 1, drawn as in random_model."""
+    model = []
+    for s, hidden in enumerate(hidden_per_species):
+        one = random_model(len(hidden_per_species), D, list(hidden), seed, act=act, in_scale=in_scale)
+        model.append(one[s])
+    return model
+
+
 # ----------------------------------------------------------------------------
 # placement
 # ----------------------------------------------------------------------------

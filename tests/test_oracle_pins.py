@@ -749,3 +749,41 @@ def test_loss_hand_evaluated_normalisation(O):
     L, dE, _ = O.loss(ptr, E, T, per_atom=True, energy_weight=wE, energy_kind="exp")
     assert abs(L - wE * (np.e - 1.0)) < 1e-14
     np.testing.assert_allclose(dE, [wE / 3 * 2 * np.e, wE / 3 * 2 * np.e / 2, -wE / 3 * 2 * np.e], rtol=1e-14)
+
+
+def test_mlp_per_species_architectures_vs_torch(O):
+    """Species with different depths and widths (one to three hidden layers,
+    Sec. II.A): energies, dE/dG and the force-loss weight gradient against
+    torch float64 autograd (double backward for the tangent term)."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.Generator(np.random.PCG64(41))
+    p = small_params(S=3, rc=3.8)
+    hid = [[12, 9, 5], [7], [10, 6]]
+    model = synth.random_model_per_species(p.dim, hid, 19, act="tanh", in_scale=0.7)
+    assert [len(m[2]) for m in model] == [4, 2, 3]
+    sys = synth.concat([random_cluster(rng, n, S=3) for n in (6, 9, 7)])
+    nl = O.neighbors_brute(sys, p.rc)
+    G = O.descriptors(p, sys, nl)
+    E, lam = O.mlp(model, sys.species, G)
+    gE = rng.normal(size=sys.n_structs)
+    gF = rng.normal(size=(sys.n_atoms, 3))
+    flat = O.force_loss_grad(p, model, sys, nl, gE, gF)
+    u = O.descriptor_tangent(p, sys, nl, gF)
+    struct = np.repeat(np.arange(sys.n_structs), np.diff(sys.atom_ptr))
+    tparams = [[(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True))
+                for W, b in zip(m[2], m[3])] for m in model]
+    total = torch.zeros((), dtype=torch.float64)
+    for s in range(3):
+        idx = np.nonzero(sys.species == s)[0]
+        g = torch.tensor(G[idx], requires_grad=True)
+        e = torch_mlp_energy(torch, tparams[s], model[s][1], g)
+        (lam_t,) = torch.autograd.grad(e.sum(), g, create_graph=True)
+        np.testing.assert_allclose(E[idx], e.detach().numpy(), rtol=1e-13, atol=1e-14)
+        np.testing.assert_allclose(lam[idx], lam_t.detach().numpy(), rtol=1e-12, atol=1e-14)
+        total = total + (torch.tensor(gE[struct[idx]]) * e).sum() - (lam_t * torch.tensor(u[idx])).sum()
+    total.backward()
+    grads = O.unflatten_grads(model, flat)
+    for s in range(3):
+        for (dW, db), (W, b) in zip(grads[s], tparams[s]):
+            np.testing.assert_allclose(dW, W.grad.numpy(), rtol=1e-10, atol=1e-13)
+            np.testing.assert_allclose(db, b.grad.numpy(), rtol=1e-10, atol=1e-13)
