@@ -279,6 +279,27 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
                            float* E_atom, float* F, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * nn_energy_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same computation and results (bitwise, for the same
+ * flags and launch plan) without a caller workspace.  Its scratch (the
+ * descriptors, dE/dG, per-pair gradients and species grouping of one call)
+ * lives in a 64 MiB device array inside the library, one per GPU, held from
+ * the library's load until the process ends.  Needs, in bytes, about
+ * N * (8 D + 20) + 16 * nl->capacity + BF16 weight copies; inputs beyond
+ * 64 MiB are rejected with NN_E_WORKSPACE before anything is enqueued (the
+ * 4096-atom bulk cell of D = 96 takes about 8 MiB).  Every call on a GPU
+ * shares that GPU's array and leaves its contents there; calls that overlap
+ * on one GPU (several streams or threads at once) race and must be
+ * serialized by the caller.  Nothing in the array needs to start at zero.
+ * flags: MLP precision flags only (NN_STORE_JACOBIAN / NN_REUSE_DESCRIPTORS
+ * give NN_E_INVALID).  Calls no allocating routine.
+ */
+nn_status nn_energy_forces_noalloc(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                                   const nn_model* model, int32_t flags, double* E_struct, float* E_atom, float* F,
+                                   void* stream);
+
+/*
  * Launch tuning (the tiles of the batching step): times the launch variants
  * of this workload's passes -- waves per atom of the descriptor forward and
  * adjoint passes (1, 2, 4) and waves per MLP tile (4, 8) -- on `stream`,

@@ -249,6 +249,62 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
   return L;
 }
 
+// The part of the workspace an energy/force evaluation without a stored
+// Jacobian uses, and nothing else (no list-build or weight-gradient pieces):
+// the layout of nn_energy_forces_noalloc in the library's own scratch.
+static Layout carve_lean(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D, int S, const nn_model* model) {
+  Layout L{};
+  Carver c{static_cast<char*>(ws)};
+  const int64_t nblk = (N + 63) / 64 > 0 ? (N + 63) / 64 : 1;
+  L.scan_tmp = c.take<int64_t>(scan_scratch_elems((int64_t)S * nblk + 1));
+  L.G = c.take<float>((size_t)N * D);
+  L.lam = c.take<float>((size_t)N * D);
+  L.E_atom = c.take<float>(N);
+  L.pg = c.take<float4>(capacity);
+  L.perm = c.take<int32_t>(N);
+  L.sp_cnt = c.take<int64_t>((size_t)S * nblk + 1);
+  L.sp_off = c.take<int64_t>((size_t)S * nblk + 1);
+  L.sp_start = c.take<int64_t>(NN_MAX_SPECIES + 1);
+  L.wb_elems = 4 * model_param_floats(model);
+  L.wb = c.take<__bf16>(L.wb_elems);
+  L.bytes = c.off + 256;
+  (void)B;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// the library's own scratch, for callers that cannot allocate
+// (nn_energy_forces_noalloc).  A file-scope device array: every GPU the
+// library runs on holds one copy of it from the library's load until the
+// process ends.  In host code `scratch` is only a stand-in for the symbol;
+// the device address of each GPU's copy comes from hipGetSymbolAddress on
+// that GPU and is the only handle host code passes on.
+// ---------------------------------------------------------------------------
+
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_smu;
+static void* g_scratch_dev[kMaxDevices];
+
+// The address of the current device's copy of `scratch` (looked up once per
+// device, on the first call there).
+static nn_status static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(NN_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(NN_E_HIP, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+  std::lock_guard<std::mutex> g(g_smu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return fail(NN_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return NN_OK;
+}
+
 // ---------------------------------------------------------------------------
 // argument checks
 // ---------------------------------------------------------------------------
@@ -672,6 +728,26 @@ nn_status nn_energy_forces(const nn_system* sys, const nn_nlist* nl, const nn_mb
   L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model, jf);
   ef_enqueue(sys, nl, P, model, flags, L, jf != 0, E_struct, E_atom, F, (hipStream_t)stream);
   return check_launch("nn_energy_forces");
+}
+
+nn_status nn_energy_forces_noalloc(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                                   const nn_model* model, int32_t flags, double* E_struct, float* E_atom, float* F,
+                                   void* stream) {
+  DescConst P;
+  nn_status st = check_ef_args(sys, nl, p, model, flags, E_struct, &P);
+  if (st) return st;
+  if (flags & (NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
+    return fail(NN_E_INVALID, "nn_energy_forces_noalloc takes only the MLP precision flags");
+  const int64_t N = sys->n_atoms;
+  Layout L = carve_lean(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  if (L.bytes > kStaticScratchBytes)
+    return fail(NN_E_WORKSPACE, "nn_energy_forces_noalloc: needs %zu bytes of scratch, the library holds %zu", L.bytes,
+                kStaticScratchBytes);
+  void* ws = nullptr;
+  if ((st = static_scratch(&ws))) return st;
+  L = carve_lean(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  ef_enqueue(sys, nl, P, model, flags, L, false, E_struct, E_atom, F, (hipStream_t)stream);
+  return check_launch("nn_energy_forces_noalloc");
 }
 
 nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,

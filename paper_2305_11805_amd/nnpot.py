@@ -79,7 +79,7 @@ class nn_langevin(C.Structure):
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_energy_forces", "nn_energy_forces_noalloc", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset", "nn_check",
            "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
@@ -106,6 +106,8 @@ def lib():
         L.nn_descriptors.argtypes = [P, P, P, P, P, P, SZ, P]
         L.nn_energy_forces.restype = I32
         L.nn_energy_forces.argtypes = [P, P, P, P, I32, SZ, P, P, P, P, SZ, P]
+        L.nn_energy_forces_noalloc.restype = I32
+        L.nn_energy_forces_noalloc.argtypes = [P, P, P, P, I32, P, P, P, P]
         L.nn_descriptor_tangent.restype = I32
         L.nn_descriptor_tangent.argtypes = [P, P, P, P, P, P]
         L.nn_md_langevin.restype = I32
@@ -184,6 +186,11 @@ def nn_descriptor_tangent(sys, nl, params, v, U, stream=None):
 def nn_energy_forces(sys, nl, params, model, flags, mem_budget, E_struct, E_atom, F, ws, stream=None):
     _ok(lib().nn_energy_forces(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, mem_budget,
                                _p(E_struct), _p(E_atom), _p(F), _p(ws), ws.numel(), _stream(stream)))
+
+
+def nn_energy_forces_noalloc(sys, nl, params, model, flags, E_struct, E_atom, F, stream=None):
+    _ok(lib().nn_energy_forces_noalloc(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags,
+                                       _p(E_struct), _p(E_atom), _p(F), _stream(stream)))
 
 
 def _ptr_table(tensors):
