@@ -490,8 +490,10 @@ def md_table2(args):
     """The repeated-evaluation shape of Table II: Langevin dynamics (300 K,
     0.5 fs, friction 0.01 / fs) of 16-atom periodic carbon cells through
     nn_md_langevin, one cell and a batch of independent cells, eager and
-    replayed from a HIP graph.  Prints one JSON line; the paper's figure
-    (0.78 ms per step per atom, A100 through ASE) is context only."""
+    replayed from a HIP graph: the config-1 model, then the Carbon descriptor
+    of Sec. III.B (D = 152) with each of the three Table II networks (64-32,
+    256-128, 1024-512-256).  Prints one JSON line; the paper's figures
+    (0.78-0.79 ms per step per atom, A100 through ASE) are context only."""
     import torch
     from paper_2305_11805_amd import nnpot, synth
     if not torch.cuda.is_available():
@@ -500,9 +502,13 @@ def md_table2(args):
     stream = torch.cuda.current_stream()
     dt, gamma, kT = 0.5, 0.01, 0.025852
     out = {"step": "langevin_md", "dt_fs": dt, "friction_per_fs": gamma, "kT_eV": kT,
-           "paper_context": {"ms_per_step_per_atom": 0.78, "hardware": "A100, ASE driver"}, "runs": []}
-    for n_cells, steps in ((1, 1000), (args.md_cells, 200)):
-        w = synth.md_cells(n_cells)
+           "paper_context": {"ms_per_step_per_atom": {"small": 0.78, "middle": 0.79, "big": 0.79},
+                             "hardware": "A100, ASE driver"}, "runs": []}
+    runs = [(None, 1, 1000), (None, args.md_cells, 200)]
+    for net in ("small", "middle", "big"):  # the networks of Table II on the Sec. III.B descriptor
+        runs += [(net, 1, 1000), (net, args.md_cells, 200)]
+    for net, n_cells, steps in runs:
+        w = synth.md_cells(n_cells, network=net)
         s = w.system
         pot = nnpot.Potential(s, w.params, w.model, skin=1.0)
         pot.build_neighbors()
@@ -530,7 +536,7 @@ def md_table2(args):
         ms_g = _timed(torch, stream, g.replay, steps // chunk) / (steps // chunk * chunk)
         nnpot.nn_check(pot.nl)
         del g
-        out["runs"].append({"cells": n_cells, "atoms": s.n_atoms, "steps": steps,
+        out["runs"].append({"model": w.name.split(", ", 4)[-1], "cells": n_cells, "atoms": s.n_atoms, "steps": steps,
                             "ms_per_step": round(ms, 5), "ms_per_step_graph": round(ms_g, 5),
                             "us_per_step_per_atom_graph": round(ms_g * 1e3 / s.n_atoms, 4),
                             "list_builds": int(pot.meta[2].item()), "launch_plan": list(plan)})

@@ -173,6 +173,7 @@ struct Layout {
   // weight gradient: per-atom stash, per-atom weights, chunk partials
   float *st_a1, *st_d1, *st_a2, *st_d2, *w_atom, *partial;
   float *st_t1, *st_x1, *st_x2;  // the force term's extra stash (a1_dot, x1, x2)
+  LayBuf lay;                    // stashes of the layer-by-layer MLP (other architectures)
   double* loss_partial;          // block sums of nn_loss
   float* jac;  // stored Jacobian (NN_STORE_JACOBIAN within the memory budget)
   size_t bytes;
@@ -185,6 +186,51 @@ static size_t model_param_floats(const nn_model* m) {
     for (int l = 0; l < m->mlp[s].n_layers; ++l)
       t += ((size_t)m->mlp[s].width[l + 1] * m->mlp[s].width[l] + 127) / 128 * 128;
   return t;
+}
+
+// Depths and widths of the model as the kernels see them (no weights).
+static ModelDev model_shape(const nn_model* m) {
+  ModelDev d{};
+  if (!m) return d;
+  d.S = m->n_species;
+  for (int s = 0; s < m->n_species && s < NN_MAX_SPECIES; ++s) {
+    d.m[s].n_layers = m->mlp[s].n_layers;
+    for (int l = 0; l <= NN_MAX_LAYERS; ++l) d.m[s].width[l] = m->mlp[s].width[l];
+  }
+  return d;
+}
+
+// True when the fused two-hidden-layer kernels take this model: every
+// species has two hidden layers of the same compiled widths.
+static bool model_fused(const nn_model* m) {
+  if (!m || m->n_species < 1) return false;
+  const nn_mlp& q0 = m->mlp[0];
+  if (q0.n_layers != 3 || !mlp_supported(q0.width[1], q0.width[2])) return false;
+  for (int s = 1; s < m->n_species; ++s) {
+    const nn_mlp& q = m->mlp[s];
+    if (q.n_layers != 3 || q.width[1] != q0.width[1] || q.width[2] != q0.width[2]) return false;
+  }
+  return true;
+}
+
+// Stashes of the layer-by-layer MLP: activations, act' and the adjoint of
+// each hidden layer, and with `tangent` the tangent activations, act'' z_dot
+// and the tangent adjoint.
+static void carve_layers(Carver& c, int64_t N, const nn_model* model, bool tangent, LayBuf& b) {
+  const ModelDev shape = model_shape(model);
+  lay_stash_widths(shape, b.ld);
+  for (int h = 1; h < NN_MAX_LAYERS; ++h) {
+    if (!b.ld[h]) continue;
+    const size_t n = (size_t)N * b.ld[h];
+    b.a[h] = c.take<float>(n);
+    b.s[h] = c.take<float>(n);
+    b.d[h] = c.take<float>(n);
+    if (tangent) {
+      b.at[h] = c.take<float>(n);
+      b.q[h] = c.take<float>(n);
+      b.dt[h] = c.take<float>(n);
+    }
+  }
 }
 
 static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D, int S, const nn_model* model,
@@ -226,7 +272,11 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
     L.sp_start = c.take<int64_t>(NN_MAX_SPECIES + 1);
     L.wb_elems = 4 * model_param_floats(model);
     L.wb = c.take<__bf16>(L.wb_elems);
-    if (model && model->n_species > 0 && model->mlp[0].n_layers == 3) {
+    if (model && !model_fused(model) && model->n_species > 0) {
+      carve_layers(c, N, model, true, L.lay);
+      L.w_atom = c.take<float>(N);
+      L.partial = c.take<float>(lay_partial_floats(N, model_shape(model)));
+    } else if (model && model->n_species > 0 && model->mlp[0].n_layers == 3) {
       const int H1 = model->mlp[0].width[1], H2 = model->mlp[0].width[2];
       L.st_a1 = c.take<float>((size_t)N * H1);
       L.st_d1 = c.take<float>((size_t)N * H1);
@@ -267,6 +317,7 @@ static Layout carve_lean(void* ws, int64_t N, int32_t B, int64_t capacity, int64
   L.sp_start = c.take<int64_t>(NN_MAX_SPECIES + 1);
   L.wb_elems = 4 * model_param_floats(model);
   L.wb = c.take<__bf16>(L.wb_elems);
+  if (!model_fused(model)) carve_layers(c, N, model, false, L.lay);
   L.bytes = c.off + 256;
   (void)B;
   return L;
@@ -407,22 +458,31 @@ static nn_status make_desc_const(const nn_mbp_params* p, DescConst* out) {
 static nn_status check_model(const nn_model* m, const DescConst& P) {
   if (!m) return fail(NN_E_INVALID, "model is NULL");
   if (m->n_species != P.S) return fail(NN_E_INVALID, "model has %d species, descriptor %d", m->n_species, P.S);
-  const nn_mlp& m0 = m->mlp[0];
   for (int s = 0; s < m->n_species; ++s) {
     const nn_mlp& q = m->mlp[s];
-    if (q.n_layers != 3) return fail(NN_E_UNSUPPORTED, "species %d: only two hidden layers are compiled", s);
+    const int L = q.n_layers;
+    if (L < 2 || L > NN_MAX_LAYERS)
+      return fail(NN_E_UNSUPPORTED, "species %d: %d weight layers (1 to %d hidden layers are supported)", s, L,
+                  NN_MAX_LAYERS - 1);
     if (q.width[0] != P.D) return fail(NN_E_INVALID, "species %d: input width %d != D %d", s, q.width[0], P.D);
-    if (q.width[3] != 1) return fail(NN_E_INVALID, "species %d: output width must be 1", s);
-    if (!mlp_supported(q.width[1], q.width[2]))
-      return fail(NN_E_UNSUPPORTED, "species %d: hidden widths (%d, %d) not compiled", s, q.width[1], q.width[2]);
-    if (q.width[1] != m0.width[1] || q.width[2] != m0.width[2])
-      return fail(NN_E_UNSUPPORTED, "all species must share the hidden widths in the fused kernel");
-    for (int l = 0; l < 3; ++l) {
+    if (q.width[L] != 1) return fail(NN_E_INVALID, "species %d: output width must be 1", s);
+    for (int l = 1; l < L; ++l)
+      if (q.width[l] < 1 || q.width[l] > 4096)
+        return fail(NN_E_UNSUPPORTED, "species %d: hidden width %d outside 1..4096", s, q.width[l]);
+    for (int l = 0; l < L; ++l) {
       if (!q.W[l] || !q.b[l]) return fail(NN_E_INVALID, "species %d layer %d: NULL weights", s, l);
       if (q.act[l] < 0 || q.act[l] > 3) return fail(NN_E_INVALID, "bad activation code");
     }
-    if (q.act[2] != NN_ACT_LINEAR) return fail(NN_E_UNSUPPORTED, "output layer must be linear");
+    if (q.act[L - 1] != NN_ACT_LINEAR) return fail(NN_E_UNSUPPORTED, "output layer must be linear");
   }
+  return NN_OK;
+}
+
+// BF16 MLP modes exist only for the fused kernels' shapes.
+static nn_status check_mode(const nn_model* m, int32_t flags) {
+  if ((flags & (NN_BF16_MLP | NN_BF16X3_MLP)) && !model_fused(m))
+    return fail(NN_E_UNSUPPORTED, "BF16 MLP modes need two hidden layers of widths (64,32), (128,128) or (256,128) "
+                                  "shared by all species; other networks run in FP32");
   return NN_OK;
 }
 
@@ -532,7 +592,23 @@ static nn_status check_ef_args(const nn_system* sys, const nn_nlist* nl, const n
     return fail(NN_E_INVALID, "unknown flags");
   if ((flags & NN_BF16_MLP) && (flags & NN_BF16X3_MLP))
     return fail(NN_E_INVALID, "NN_BF16_MLP and NN_BF16X3_MLP are exclusive");
-  return NN_OK;
+  return check_mode(model, flags);
+}
+
+// The layer-by-layer MLP's view of a fused-kernel argument block and the
+// workspace.
+static LayArgs lay_args(const MlpArgs& a, const Layout& L) {
+  LayArgs la{};
+  la.model = a.model;
+  la.perm = a.perm;
+  la.sp_start = a.sp_start;
+  la.G = a.G;
+  la.D = a.D;
+  la.w_atom = L.w_atom;
+  la.E_atom = a.E_atom;
+  la.lambda = a.lambda ? a.lambda : L.lam;
+  la.buf = L.lay;
+  return la;
 }
 
 // The launches of one energy/force evaluation on the workspace layout L
@@ -578,7 +654,8 @@ static void ef_enqueue(const nn_system* sys, const nn_nlist* nl, const DescConst
   a.D = P.D;
   {
     StageTimer t(NN_STAGE_MLP, s);
-    launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
+    if (model_fused(model)) launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
+    else launch_mlp_layers(lay_args(a, L), N, F != nullptr, s);
   }
   if (!F) {
     StageTimer t(NN_STAGE_ENERGY, s);
@@ -758,6 +835,7 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if ((st = check_model(model, P))) return st;
+  if ((st = check_mode(model, flags))) return st;
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN | NN_REUSE_DESCRIPTORS))
     return fail(NN_E_INVALID, "unknown flags");
@@ -800,10 +878,14 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
       if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_fwd = w;
     }
     t_best = -1.f;
-    for (int w : {4, 8}) {  // MLP (lambda for the adjoint timings comes from here)
-      if (w == 8 && h1 < 128) continue;
-      const float t = time_of([&] { launch_mlp(a, h1, h2, mode, N, w, s); });
-      if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.mlp_waves = w;
+    if (model_fused(model)) {
+      for (int w : {4, 8}) {  // MLP (lambda for the adjoint timings comes from here)
+        if (w == 8 && h1 < 128) continue;
+        const float t = time_of([&] { launch_mlp(a, h1, h2, mode, N, w, s); });
+        if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.mlp_waves = w;
+      }
+    } else {
+      launch_mlp_layers(lay_args(a, L), N, true, s);  // no launch choice to tune; lambda for the adjoint
     }
     t_best = -1.f;
     for (int w : {1, 2, 4}) {  // adjoint
@@ -839,6 +921,7 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   DescConst P;
   if ((st = make_desc_const(p, &P))) return st;
   if ((st = check_model(model, P))) return st;
+  if (!dL_dF && (st = check_mode(model, flags))) return st;
   if (flags & ~(NN_BF16_MLP | NN_BF16X3_MLP | NN_STORE_JACOBIAN)) return fail(NN_E_INVALID, "unknown flags");
   if (!dL_dE && !dL_dF && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE and dL_dF are both NULL");
   if (dL_dpos && dL_dF)
@@ -861,6 +944,31 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
     MlpArgs a{};
     prepare_model(model, P, L, mode != 0 && !dL_dF, a, s);
     launch_atom_weights(dL_dE, sys->atom_ptr, sys->n_structs, N, L.w_atom, s);
+    if (!model_fused(model)) {
+      // layer-by-layer MLP: the stashes of the energy path (deltas) or, with
+      // a loss on forces, of the tangent and its reverse pass, then the sums
+      a.G = L.G;
+      a.perm = L.perm;
+      a.sp_start = L.sp_start;
+      a.E_atom = L.E_atom;
+      a.lambda = L.lam;
+      a.D = P.D;
+      LayArgs la = lay_args(a, L);
+      if (dL_dF) {
+        launch_desc_tan(*sys, *nl, P, dL_dF, L.lam, plan.wpa_fwd, s);
+        la.U = L.lam;
+        launch_mlp_layers_tangent(la, N, s);
+      } else {
+        launch_mlp_layers(la, N, true, s);
+      }
+      LayGradOut out{};
+      for (int k = 0; k < NN_MAX_SPECIES * NN_MAX_LAYERS; ++k) {
+        out.dW[k] = dW ? dW[k] : nullptr;
+        out.db[k] = db ? db[k] : nullptr;
+      }
+      launch_lay_wgrad(la, N, dL_dF != nullptr, L.partial, out, s);
+      return check_launch("nn_energy_forces_grad");
+    }
     WgradSrc src{};
     src.G = L.G;
     src.a1 = L.st_a1;

@@ -240,6 +240,47 @@ bool mlp_supported(int h1, int h2);
 void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, int waves, hipStream_t s);
 void launch_convert_bf16(const ConvJob& job, hipStream_t s);
 void launch_mlp_fm(const MlpFmArgs& a, int h1, int h2, int64_t N, int waves, hipStream_t s);
+// mlp_layers.hip: per-species networks of any depth (up to NN_MAX_LAYERS
+// weight layers) and widths, layer by layer.  Stashes of hidden layer h
+// (1 .. NN_MAX_LAYERS - 1) are [rows in species order][ld[h]]: activations a,
+// act' (s), and for the passes that need them the adjoint d (delta, or z_bar
+// with a loss on forces), the tangent activations at, act'' z_dot (q) and the
+// tangent adjoint dt.
+struct LayBuf {
+  float* a[NN_MAX_LAYERS];
+  float* s[NN_MAX_LAYERS];
+  float* d[NN_MAX_LAYERS];
+  float* at[NN_MAX_LAYERS];
+  float* q[NN_MAX_LAYERS];
+  float* dt[NN_MAX_LAYERS];
+  int ld[NN_MAX_LAYERS];
+};
+struct LayArgs {
+  ModelDev model;
+  const int32_t* perm;
+  const int64_t* sp_start;
+  const float* G;       // [N][D] descriptors (atom order)
+  const float* U;       // [N][D] descriptor tangent (loss on forces)
+  int D;
+  const float* w_atom;  // [N] dL/dE of each atom's structure (gradient passes)
+  float* E_atom;        // [N]
+  float* lambda;        // [N][D] dE/dG
+  LayBuf buf;
+};
+struct LayGradOut {
+  float* dW[NN_MAX_SPECIES * NN_MAX_LAYERS];
+  float* db[NN_MAX_SPECIES * NN_MAX_LAYERS];
+};
+// ld[h] of the stashes (widest hidden layer h over the species, rounded up to 16)
+void lay_stash_widths(const ModelDev& m, int ld[NN_MAX_LAYERS]);
+size_t lay_partial_floats(int64_t N, const ModelDev& m);
+// E_atom, and with lambda the stashed deltas and dE/dG
+void launch_mlp_layers(const LayArgs& a, int64_t N, bool lambda, hipStream_t s);
+// forward with the tangent along U and the reverse pass of w E - E_dot
+void launch_mlp_layers_tangent(const LayArgs& a, int64_t N, hipStream_t s);
+// dL/dW, dL/db from the stashes (energy path or, with tangent, both terms)
+void launch_lay_wgrad(const LayArgs& a, int64_t N, bool tangent, float* partial, const LayGradOut& out, hipStream_t s);
+
 // wgrad.hip
 struct WgradArgs {
   const int32_t* perm;      // atoms grouped by species

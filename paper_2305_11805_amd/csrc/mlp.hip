@@ -14,30 +14,13 @@
 #include <math.h>
 
 #include "common.h"
+#include "mlp_ops.h"
 
 namespace nnp {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTile = 16;
-
-__device__ __forceinline__ float act_f(int code, float z) {
-  switch (code) {
-    case NN_ACT_GAUSSIAN: return __builtin_amdgcn_exp2f(-1.4426950408889634f * z * z);
-    case NN_ACT_RELU: return z > 0.f ? z : 0.f;
-    case NN_ACT_TANH: return tanhf(z);
-    default: return z;
-  }
-}
-__device__ __forceinline__ float act_d(int code, float z, float a) {
-  switch (code) {
-    case NN_ACT_GAUSSIAN: return -2.0f * z * a;
-    case NN_ACT_RELU: return z > 0.f ? 1.f : 0.f;
-    case NN_ACT_TANH: return 1.0f - a * a;
-    default: return 1.0f;
-  }
-}
 
 // ---------------------------------------------------------------------------
 // species grouping: perm lists atoms species by species, in atom order
@@ -132,28 +115,6 @@ __global__ void __launch_bounds__(kSpThreads) k_sp_group_small(const int32_t* __
 // fused MLP tile kernel
 // ---------------------------------------------------------------------------
 
-
-// FP32 products use v_mfma_f32_16x16x4_f32 over 16-wide k blocks: lane
-// (lm, lk) holds the four k values kb + 4 lk + i (i = 0..3) of its A row and
-// B column, and the i-th of four MFMAs takes element i.  The four MFMAs
-// together cover the whole block (each product a_k b_k once), so every lane
-// fetches its operands as one 16-byte vector.
-__device__ __forceinline__ float4 ld4(const float* p, int k, int kmax, bool vec) {
-  if (vec && k + 3 < kmax) return *reinterpret_cast<const float4*>(p + k);
-  float4 v;
-  v.x = k < kmax ? p[k] : 0.f;
-  v.y = k + 1 < kmax ? p[k + 1] : 0.f;
-  v.z = k + 2 < kmax ? p[k + 2] : 0.f;
-  v.w = k + 3 < kmax ? p[k + 3] : 0.f;
-  return v;
-}
-
-__device__ __forceinline__ floatx4 mma4_f32(floatx4 acc, const float4& a, const float4& b) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
-}
 
 // Products in the MLP run in one of three modes:
 //   kFp32  - FP32 operands, v_mfma_f32_16x16x4_f32;
@@ -636,14 +597,6 @@ __global__ void __launch_bounds__(64 * NW) k_mlp(MlpArgs args) {
 // ---------------------------------------------------------------------------
 // MLP with its tangent, for the weight gradient of a loss on forces
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ float act_d2(int code, float z, float a) {
-  switch (code) {
-    case NN_ACT_GAUSSIAN: return fmaf(4.0f * z, z, -2.0f) * a;
-    case NN_ACT_TANH: return -2.0f * a * (1.0f - a * a);
-    default: return 0.0f;
-  }
-}
 
 // With the per-atom weight w = dL/dE of the atom's structure and the
 // descriptor tangent u (the derivative of G along dL/dF), the loss is

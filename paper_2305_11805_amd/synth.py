@@ -318,17 +318,33 @@ SPECIES_MASS = (1.008, 12.011, 14.007, 15.999)
 CARBON_MASS = 12.011
 
 
-def md_cells(n_cells: int = 1) -> Workload:
+# The three networks of Table II (hidden widths), on the Carbon descriptor
+# of Sec. III.B: one species, Rc 5 A, 24 radial bins and 8 radius x 16 angle
+# bins (D = 152).  First-layer scale 0.45: sqrt(D) over the RMS descriptor
+# row norm of these 16-atom cells (27.2), a fixed constant like IN_SCALE.
+TABLE2_HIDDEN = {"small": [64, 32], "middle": [256, 128], "big": [1024, 512, 256]}
+TABLE2_IN_SCALE = 0.45
+
+
+def md_cells(n_cells: int = 1, network: str = None) -> Workload:
     """The repeated-evaluation shape of Table II: 16-atom periodic carbon
     cells at the config-1 density and minimum distance (cube side 5.43 A,
-    narrower than 2 Rc, so several images of each atom are neighbors), with
-    the config-1 descriptor and MLP; n_cells independent cells are batched as
-    structures."""
+    narrower than 2 Rc, so several images of each atom are neighbors);
+    n_cells independent cells are batched as structures.  network=None: the
+    config-1 descriptor and MLP; "small" / "middle" / "big": the Carbon
+    descriptor of Sec. III.B (D = 152) with that Table II network."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 5))
     cells = [bulk_system(rng, 16, 0.1, 1.2, [16]) for _ in range(n_cells)]
-    p = mbp_params(1, 5.0, 32, 8, 8)
-    model = random_model(1, p.dim, [128, 128], SEED_BASE + 1, in_scale=IN_SCALE[1])
-    name = f"{n_cells} periodic carbon cell(s) of 16 atoms, rho 0.1, Rc 5.0, 32 + 8x8 bins, MLP D-128-128-1"
+    if network is None:
+        p = mbp_params(1, 5.0, 32, 8, 8)
+        model = random_model(1, p.dim, [128, 128], SEED_BASE + 1, in_scale=IN_SCALE[1])
+        name = f"{n_cells} periodic carbon cell(s) of 16 atoms, rho 0.1, Rc 5.0, 32 + 8x8 bins, MLP D-128-128-1"
+    else:
+        hidden = TABLE2_HIDDEN[network]
+        p = mbp_params(1, 5.0, 24, 16, 8)
+        model = random_model(1, p.dim, hidden, SEED_BASE + 6, in_scale=TABLE2_IN_SCALE)
+        name = (f"{n_cells} periodic carbon cell(s) of 16 atoms, rho 0.1, Rc 5.0, 24 + 8x16 bins (D = 152), "
+                f"Table II {network} MLP D-{'-'.join(map(str, hidden))}-1")
     return Workload(name, concat(cells), p, model, SEED_BASE + 5, {"mass": CARBON_MASS})
 
 

@@ -164,3 +164,16 @@ def test_constant_energy_16_atom_cell():
     nnpot.nn_check(pot.nl)
     print(f"  max |dE_tot|: gpu {dev_gpu:.2e} eV, oracle {dev_ref:.2e} eV", flush=True)
     assert dev_gpu <= 2 * dev_ref + 1e-4
+
+
+@pytest.mark.parametrize("network", ["small", "middle", "big"])
+def test_langevin_table2_networks_match_oracle(network):
+    """The like-for-like Table II shape: 16-atom periodic carbon cells (four of
+    them batched) with the Carbon descriptor of Sec. III.B (D = 152) and each
+    Table II network, 300 K, 0.5 fs, skin 1 A (the bench's setting)."""
+    w = synth.md_cells(4, network=network)
+    masses = np.full(w.system.n_atoms, synth.CARBON_MASS)
+    steps, dt = 20, 0.5
+    print(f"[langevin] {w.name}: {w.system.n_atoms} atoms, {steps} steps", flush=True)
+    got, ref, inv_m, _ = run_both(w, masses, steps, dt, 0.01, 0.025852, skin=1.0)
+    check_trajectory(got, ref, inv_m, steps, dt, np.diff(w.system.atom_ptr))
