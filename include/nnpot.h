@@ -170,11 +170,15 @@ typedef struct nn_mbp_params {
 
 /*
  * Per-species MLP, Eq. (1): a^0 = G_i, z^l = W^l a^(l-1) + b^l,
- * a^l = act[l-1](z^l); the atomic energy is a^L (width[L] = 1).  Weights are
- * shared by all atoms of a species (Sec. II).
+ * a^l = act[l-1](z^l); the atomic energy is a^L (width[L] = 1, linear
+ * output).  Weights are shared by all atoms of a species (Sec. II); each
+ * species has its own depth and widths (Sec. II.A).
  *   W[l] [device] FP32 [width[l+1]][width[l]] row-major, b[l] [device] FP32.
- * Limits of the fused kernel: L = 3 (two hidden layers), hidden widths
- * multiples of 16 with (h1, h2) in {(64,32), (128,128), (256,128)}.
+ * Limits: 2 <= n_layers <= NN_MAX_LAYERS (one to three hidden layers),
+ * hidden widths 1 .. 4096.  Models whose species all have two hidden layers
+ * of the same widths (64,32), (128,128) or (256,128) run in a fused kernel
+ * (FP32, or BF16 / split-BF16 with the MLP flags); every other model runs
+ * layer by layer in FP32 (the BF16 flags then give NN_E_UNSUPPORTED).
  */
 typedef struct nn_mlp {
   int32_t n_layers;
