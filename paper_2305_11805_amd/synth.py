@@ -118,13 +118,13 @@ def bp_params(n_species, rc, n_rad, zetas=(1, 2, 4, 16), etas=(0.005, 0.02, 0.06
         bp_eta=np.asarray(etas, np.float64))
 
 
-def random_model(n_species, D, hidden: Sequence[int], seed, act="gaussian", in_scale=1.0) -> Model:
-    """Per-species MLP D -> hidden... -> 1 with W, b ~ N(0, 1/fan_in), seeded
-    per species and layer.  The first layer's draws are multiplied by
+def random_model(n_species, D, hidden: Sequence[int], seed, act="gaussian", in_scale=1.0, n_out=1) -> Model:
+    """Per-species MLP D -> hidden... -> n_out with W, b ~ N(0, 1/fan_in),
+    seeded per species and layer.  The first layer's draws are multiplied by
     in_scale (the inverse of a typical descriptor magnitude) so that the
     Gaussian units are neither saturated nor flat."""
     model = []
-    widths = [D] + list(hidden) + [1]
+    widths = [D] + list(hidden) + [n_out]
     acts = [act] * len(hidden) + ["linear"]
     for s in range(n_species):
         Ws, bs = [], []
@@ -312,6 +312,49 @@ def _config_mbp(idx: int, scale: float = 1.0) -> Workload:
     return Workload(name, sys, p, model, seed, extra)
 
 
+# Charge equilibration (Sec. II.B) on charged two-species clusters shaped like
+# the paper's Na9Cl8+ / Na8Cl8+ test (17 and 16 atoms, total charge +1).
+# The paper's descriptor length 45 has no (n_theta, n_rs_ang) among the
+# compiled angular shapes, so the stand-in uses 16 radial + 4 x 4 angular
+# bins (D = 80) with the paper's network: two hidden layers of 15 units and
+# an output layer of 3 (local energy, electronegativity, hardness).  The
+# output biases start from per-species references (eV, eV/e, eV/e^2: the
+# Mulliken electronegativity and hardness of Na and Cl); Gaussian charge
+# widths 1.0 and 1.2 A.  Atoms are placed by RSA in a 9 A cube with a 2.2 A
+# minimum distance.
+QEQ_SIGMA = (1.0, 1.2)
+QEQ_REF = ((0.0, 2.85, 4.6), (0.0, 8.3, 9.4))
+
+
+def qeq_model(D, seed, hidden=(15, 15), in_scale=1.0) -> Model:
+    model = random_model(2, D, list(hidden), seed, in_scale=in_scale, n_out=3)
+    for s, (widths, acts, Ws, bs) in enumerate(model):
+        bs[-1] = bs[-1] + np.asarray(QEQ_REF[s])
+    return model
+
+
+def qeq_clusters(n_clusters: int, seed: int = SEED_BASE + 7):
+    """(Workload, total charges [B]): n_clusters charged NaCl-like clusters,
+    alternately 9 Na + 8 Cl and 8 Na + 8 Cl, each of total charge +1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos, sp, ptr, cell = [], [], [0], []
+    for c in range(n_clusters):
+        n_na = 9 if c % 2 == 0 else 8
+        n = n_na + 8
+        pos.append(rsa_cluster(rng, n, 9.0, 2.2))
+        s = np.array([0] * n_na + [1] * 8, np.int32)
+        rng.shuffle(s)
+        sp.append(s)
+        ptr.append(ptr[-1] + n)
+        cell.append(_cube(9.0))
+    system = System(np.concatenate(pos), np.concatenate(sp), np.asarray(ptr, np.int64), np.stack(cell),
+                    np.zeros((n_clusters, 3), np.uint8))
+    p = mbp_params(2, 6.0, 16, 4, 4, eta_rad=4.0, eta_ang=3.0, zeta=8.0)
+    model = qeq_model(p.dim, seed, in_scale=QEQ_IN_SCALE)
+    name = f"{n_clusters} charged clusters Na9Cl8+ / Na8Cl8+ (Q = +1), Rc 6.0, 16 + 4x4 bins, MLP D-15-15-3"
+    return Workload(name, system, p, model, seed, {"sigma": QEQ_SIGMA}), np.ones(n_clusters)
+
+
 # Atomic masses (amu) of the four species the molecular workloads draw
 # ({H, C, N, O}); the bulk workloads are carbon.
 SPECIES_MASS = (1.008, 12.011, 14.007, 15.999)
@@ -324,6 +367,7 @@ CARBON_MASS = 12.011
 # row norm of these 16-atom cells (27.2), a fixed constant like IN_SCALE.
 TABLE2_HIDDEN = {"small": [64, 32], "middle": [256, 128], "big": [1024, 512, 256]}
 TABLE2_IN_SCALE = 0.45
+QEQ_IN_SCALE = 5.4  # sqrt(D) over the RMS descriptor row norm of these clusters
 
 
 def md_cells(n_cells: int = 1, network: str = None) -> Workload:
