@@ -360,6 +360,59 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
                                 const float* F, float* dL_dpos, float* const* dW, float* const* db, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/*
+ * Long-range charge equilibration (Sec. II.B).  The paper describes one
+ * network per species with three outputs per atom -- the coefficients of a
+ * second-order expansion of the atom's energy in its charge: local energy
+ * E0, electronegativity chi and hardness J -- feeding a layer that returns
+ * the charges and the total energy from a linear system, and defers the
+ * theory to another work.  The reading computed here uses Gaussian charges
+ * of a per-species width sigma:
+ *   E(q) = sum_i [E0_i + chi_i q_i + J_i q_i^2 / 2]
+ *          + coulomb [ sum_i q_i^2 / (2 sigma_i sqrt(pi))
+ *                      + sum_{i<j} q_i q_j erf(r_ij / (sqrt(2) gamma_ij)) / r_ij ],
+ *   gamma_ij^2 = sigma_i^2 + sigma_j^2,
+ * minimised over the charges of each structure subject to sum_i q_i = Q_c:
+ * every atom ends at the same chemical potential, and the energy is
+ * sum E0 + chi.q / 2 + mu Q_c / 2 (mu the chemical potential).  Forces are the
+ * derivatives at fixed charges (the minimum makes the derivative of the solve
+ * vanish): the network part through the descriptor adjoint with output seeds
+ * (1, q_i, q_i^2 / 2), plus the Coulomb pair forces.
+ */
+typedef struct nn_qeq_params {
+  const double* sigma; /* [host] [S] Gaussian charge width of each species (> 0), Angstrom */
+  double coulomb;      /* e^2 / (4 pi eps0) in the energy and length units used: 14.399645 eV A */
+} nn_qeq_params;
+
+/*
+ * Energies, charges and forces with charge equilibration.  Every species'
+ * network must have output width 3 (E0, chi, J in that order; FP32, layer by
+ * layer).  Structures must be non-periodic with at most 64 atoms each (the
+ * per-structure FP64 Cholesky solve runs on chip); a structure outside that,
+ * or whose matrix is not positive definite, is reported by nn_check
+ * (NN_E_DEVICE) and gets zero charges and energy.
+ *   total_charge [device] FP64 [B]  total charge Q_c of each structure (e);
+ *   E_struct     [device] FP64 [B]  total energies;
+ *   charges      [device] FP64 [N]  equilibrated charges (may be NULL);
+ *   F            [device] FP32 [N][3] forces (may be NULL).
+ * The workspace is that of nn_workspace_size with this model.
+ */
+nn_status nn_energy_forces_qeq(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                               const nn_model* model, const nn_qeq_params* qp, const double* total_charge,
+                               double* E_struct, double* charges, float* F, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/*
+ * Weight gradient of a loss on the energies of nn_energy_forces_qeq (which it
+ * must follow with the same arguments and workspace): with dL_dE [device]
+ * FP64 [B], dL/dtheta = sum_c dL_dE_c sum_{i in c} d(E0_i + chi_i q_i +
+ * J_i q_i^2 / 2)/dtheta at the equilibrated charges (the derivative of the
+ * charges drops out at the minimum).  dW, db as for nn_energy_forces_grad.
+ */
+nn_status nn_energy_forces_qeq_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                                    const nn_model* model, const double* dL_dE, float* const* dW,
+                                    float* const* db, void* ws, size_t ws_bytes, void* stream);
+
 /* Loss of Sec. II.A: energy and force terms with a relative weight. */
 enum { NN_LOSS_QUAD = 0, NN_LOSS_EXP = 1 };
 typedef struct {

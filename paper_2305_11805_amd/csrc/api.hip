@@ -174,6 +174,8 @@ struct Layout {
   float *st_a1, *st_d1, *st_a2, *st_d2, *w_atom, *partial;
   float *st_t1, *st_x1, *st_x2;  // the force term's extra stash (a1_dot, x1, x2)
   LayBuf lay;                    // stashes of the layer-by-layer MLP (other architectures)
+  float *qeq_out, *qeq_seed;     // charge equilibration: network outputs and seeds [N][3]
+  double* qeq_q;                 // and the charges [N]
   double* loss_partial;          // block sums of nn_loss
   float* jac;  // stored Jacobian (NN_STORE_JACOBIAN within the memory budget)
   size_t bytes;
@@ -205,10 +207,10 @@ static ModelDev model_shape(const nn_model* m) {
 static bool model_fused(const nn_model* m) {
   if (!m || m->n_species < 1) return false;
   const nn_mlp& q0 = m->mlp[0];
-  if (q0.n_layers != 3 || !mlp_supported(q0.width[1], q0.width[2])) return false;
+  if (q0.n_layers != 3 || q0.width[3] != 1 || !mlp_supported(q0.width[1], q0.width[2])) return false;
   for (int s = 1; s < m->n_species; ++s) {
     const nn_mlp& q = m->mlp[s];
-    if (q.n_layers != 3 || q.width[1] != q0.width[1] || q.width[2] != q0.width[2]) return false;
+    if (q.n_layers != 3 || q.width[1] != q0.width[1] || q.width[2] != q0.width[2] || q.width[3] != 1) return false;
   }
   return true;
 }
@@ -276,6 +278,11 @@ static Layout carve(void* ws, int64_t N, int32_t B, int64_t capacity, int64_t D,
       carve_layers(c, N, model, true, L.lay);
       L.w_atom = c.take<float>(N);
       L.partial = c.take<float>(lay_partial_floats(N, model_shape(model)));
+      if (model->mlp[0].width[model->mlp[0].n_layers] == 3) {
+        L.qeq_out = c.take<float>((size_t)3 * N);
+        L.qeq_seed = c.take<float>((size_t)3 * N);
+        L.qeq_q = c.take<double>(N);
+      }
     } else if (model && model->n_species > 0 && model->mlp[0].n_layers == 3) {
       const int H1 = model->mlp[0].width[1], H2 = model->mlp[0].width[2];
       L.st_a1 = c.take<float>((size_t)N * H1);
@@ -455,7 +462,7 @@ static nn_status make_desc_const(const nn_mbp_params* p, DescConst* out) {
   return NN_OK;
 }
 
-static nn_status check_model(const nn_model* m, const DescConst& P) {
+static nn_status check_model(const nn_model* m, const DescConst& P, int n_out = 1) {
   if (!m) return fail(NN_E_INVALID, "model is NULL");
   if (m->n_species != P.S) return fail(NN_E_INVALID, "model has %d species, descriptor %d", m->n_species, P.S);
   for (int s = 0; s < m->n_species; ++s) {
@@ -465,7 +472,7 @@ static nn_status check_model(const nn_model* m, const DescConst& P) {
       return fail(NN_E_UNSUPPORTED, "species %d: %d weight layers (1 to %d hidden layers are supported)", s, L,
                   NN_MAX_LAYERS - 1);
     if (q.width[0] != P.D) return fail(NN_E_INVALID, "species %d: input width %d != D %d", s, q.width[0], P.D);
-    if (q.width[L] != 1) return fail(NN_E_INVALID, "species %d: output width must be 1", s);
+    if (q.width[L] != n_out) return fail(NN_E_INVALID, "species %d: output width must be %d", s, n_out);
     for (int l = 1; l < L; ++l)
       if (q.width[l] < 1 || q.width[l] > 4096)
         return fail(NN_E_UNSUPPORTED, "species %d: hidden width %d outside 1..4096", s, q.width[l]);
@@ -608,6 +615,7 @@ static LayArgs lay_args(const MlpArgs& a, const Layout& L) {
   la.E_atom = a.E_atom;
   la.lambda = a.lambda ? a.lambda : L.lam;
   la.buf = L.lay;
+  la.n_out = 1;
   return la;
 }
 
@@ -672,6 +680,35 @@ static void ef_enqueue(const nn_system* sys, const nn_nlist* nl, const DescConst
     StageTimer t(NN_STAGE_FORCE_GATHER, s);
     launch_force_gather(*sys, *nl, L.pg, F, EnergyJob{a.E_atom, sys->atom_ptr, sys->n_structs, E_struct}, s);
   }
+}
+
+// Charge equilibration: the argument block of the solve and Coulomb kernels.
+static nn_status make_qeq_args(const nn_system* sys, const nn_nlist* nl, const nn_qeq_params* qp, const DescConst& P,
+                               const double* total_charge, double* E_struct, double* charges, const Layout& L,
+                               QeqArgs* out) {
+  if (!qp || !qp->sigma) return fail(NN_E_INVALID, "charge equilibration parameters are NULL");
+  if (!(qp->coulomb > 0.0) || !isfinite(qp->coulomb)) return fail(NN_E_INVALID, "coulomb must be > 0");
+  QeqArgs a{};
+  for (int s = 0; s < P.S; ++s) {
+    if (!(qp->sigma[s] > 0.0) || !isfinite(qp->sigma[s])) return fail(NN_E_INVALID, "sigma must be > 0");
+    a.sigma[s] = qp->sigma[s];
+  }
+  if (sys->n_structs > 0 && (!total_charge || !E_struct)) return fail(NN_E_INVALID, "total_charge/E_struct is NULL");
+  a.pos = sys->pos;
+  a.species = sys->species;
+  a.atom_ptr = sys->atom_ptr;
+  a.pbc = sys->pbc;
+  a.B = sys->n_structs;
+  a.N = sys->n_atoms;
+  a.out = L.qeq_out;
+  a.total = total_charge;
+  a.ke = qp->coulomb;
+  a.E_struct = E_struct;
+  a.q = charges ? charges : L.qeq_q;
+  a.seed = L.qeq_seed;
+  a.meta = nl->meta;
+  *out = a;
+  return NN_OK;
 }
 
 }  // namespace nnp
@@ -1025,6 +1062,113 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
   return check_launch("nn_energy_forces_grad");
 }
 
+nn_status nn_energy_forces_qeq(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                               const nn_model* model, const nn_qeq_params* qp, const double* total_charge,
+                               double* E_struct, double* charges, float* F, void* ws, size_t ws_bytes, void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((st = check_model(model, P, 3))) return st;
+  if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
+  const int64_t N = sys->n_atoms;
+  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  QeqArgs qa;
+  if ((st = make_qeq_args(sys, nl, qp, P, total_charge, E_struct, charges, L, &qa))) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0) {
+    if (sys->n_structs > 0) launch_energy_reduce(L.E_atom, sys->atom_ptr, sys->n_structs, N, E_struct, s);
+    return check_launch("nn_energy_forces_qeq");
+  }
+  const LaunchPlan plan = plan_for(N, nl->capacity, P, model, 0);
+  const bool fold_species = P.S == 1;
+  if (!fold_species) {
+    StageTimer t(NN_STAGE_SPECIES, s);
+    launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+  }
+  MlpArgs a{};
+  prepare_model(model, P, L, false, a, s);
+  {
+    StageTimer t(NN_STAGE_DESC_FWD, s);
+    launch_desc_fwd(*sys, *nl, P, L.G, fold_species ? IdentityGroup{L.perm, L.sp_start} : IdentityGroup{},
+                    plan.wpa_fwd, s);
+  }
+  a.G = L.G;
+  a.perm = L.perm;
+  a.sp_start = L.sp_start;
+  a.E_atom = L.E_atom;
+  a.lambda = L.lam;
+  a.D = P.D;
+  LayArgs la = lay_args(a, L);
+  la.n_out = 3;
+  la.out = L.qeq_out;
+  la.seed = L.qeq_seed;
+  {
+    StageTimer t(NN_STAGE_MLP, s);
+    launch_mlp_layers_outputs(la, N, s);
+  }
+  launch_qeq_solve(qa, s);
+  if (F) {
+    {
+      StageTimer t(NN_STAGE_MLP, s);
+      launch_mlp_layers_seeded_backward(la, N, true, s);
+    }
+    {
+      StageTimer t(NN_STAGE_DESC_ADJ, s);
+      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, plan.wpa_adj, s);
+    }
+    StageTimer t(NN_STAGE_FORCE_GATHER, s);
+    launch_force_gather(*sys, *nl, L.pg, F, EnergyJob{nullptr, sys->atom_ptr, 0, nullptr}, s);
+    launch_qeq_coulomb(qa, F, s);
+  }
+  return check_launch("nn_energy_forces_qeq");
+}
+
+nn_status nn_energy_forces_qeq_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,
+                                    const nn_model* model, const double* dL_dE, float* const* dW, float* const* db,
+                                    void* ws, size_t ws_bytes, void* stream) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, true))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((st = check_model(model, P, 3))) return st;
+  if (!dL_dE && sys->n_structs > 0) return fail(NN_E_INVALID, "dL_dE is NULL");
+  const int64_t N = sys->n_atoms;
+  Layout L = carve(nullptr, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
+  L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
+  hipStream_t s = (hipStream_t)stream;
+  if (N == 0 || (!dW && !db)) return check_launch("nn_energy_forces_qeq_grad");
+  launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
+  MlpArgs a{};
+  prepare_model(model, P, L, false, a, s);
+  launch_atom_weights(dL_dE, sys->atom_ptr, sys->n_structs, N, L.w_atom, s);
+  a.G = L.G;
+  a.perm = L.perm;
+  a.sp_start = L.sp_start;
+  a.E_atom = L.E_atom;
+  a.lambda = L.lam;
+  a.D = P.D;
+  LayArgs la = lay_args(a, L);
+  la.n_out = 3;
+  la.out = L.qeq_out;
+  la.seed = L.qeq_seed;
+  // the stashes at the stored descriptors, then the deltas of the seeded outputs
+  launch_mlp_layers_outputs(la, N, s);
+  launch_mlp_layers_seeded_backward(la, N, false, s);
+  LayGradOut out{};
+  for (int k = 0; k < NN_MAX_SPECIES * NN_MAX_LAYERS; ++k) {
+    out.dW[k] = dW ? dW[k] : nullptr;
+    out.db[k] = db ? db[k] : nullptr;
+  }
+  launch_lay_wgrad(la, N, false, L.partial, out, s);
+  return check_launch("nn_energy_forces_qeq_grad");
+}
+
 nn_status nn_md_langevin(const nn_system* sys, double* pos, double* vel, const double* inv_mass, nn_nlist* nl,
                          double rc, double skin, const nn_mbp_params* p, const nn_model* model, int32_t flags,
                          const nn_langevin* lp, const float* noise, int32_t n_steps, double* E_pot, float* F,
@@ -1105,6 +1249,10 @@ nn_status nn_check(const nn_nlist* nl, void* stream, int64_t* info) {
   if (err & kErrNonFinite) return fail(NN_E_DEVICE, "non-finite position");
   if (err & kErrShift) return fail(NN_E_DEVICE, "lattice image index beyond int8");
   if (err & kErrTooMany) return fail(NN_E_DEVICE, "too many neighbors (> %d inside rc or > %d per row)", kMaxNb, kRowMax);
+  if (err & kErrQeq)
+    return fail(NN_E_DEVICE, "charge equilibration failed: a structure is periodic, has more than %d atoms, or its "
+                             "matrix is not positive definite (its charges, energy and Coulomb forces are zero)",
+                kQeqMax);
   if (err & kErrStale)
     return fail(NN_E_DEVICE, "NN_REUSE_DESCRIPTORS after a list rebuild: the stored Jacobian is stale (forces zeroed)");
   return NN_OK;

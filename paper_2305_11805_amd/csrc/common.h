@@ -27,6 +27,7 @@ enum : int64_t {
   kErrShift = 32,     // lattice image index does not fit in int8
   kErrPtr = 64,       // atom_ptr not 0 .. N nondecreasing
   kErrStale = 128,    // stored descriptors reused after the list was rebuilt
+  kErrQeq = 256,      // charge equilibration: structure periodic, over kQeqMax atoms, or not positive definite
 };
 
 // Layout of the device metadata block of a neighbor list (nl->meta, int64[8]).
@@ -266,6 +267,13 @@ struct LayArgs {
   float* E_atom;        // [N]
   float* lambda;        // [N][D] dE/dG
   LayBuf buf;
+  // networks with n_out outputs per atom (charge equilibration: local energy,
+  // electronegativity, hardness): out [N][n_out] receives them, and seed
+  // [N][n_out] holds the per-atom weights of the outputs that the backward
+  // pass and the weight gradient differentiate (null: one output, seed 1)
+  int n_out;
+  float* out;
+  const float* seed;
 };
 struct LayGradOut {
   float* dW[NN_MAX_SPECIES * NN_MAX_LAYERS];
@@ -276,10 +284,37 @@ void lay_stash_widths(const ModelDev& m, int ld[NN_MAX_LAYERS]);
 size_t lay_partial_floats(int64_t N, const ModelDev& m);
 // E_atom, and with lambda the stashed deltas and dE/dG
 void launch_mlp_layers(const LayArgs& a, int64_t N, bool lambda, hipStream_t s);
+// networks with several outputs: the forward pass writing a.out [N][n_out];
+// then, once a.seed is known, the stashed deltas of sum_o seed_o out_o and
+// (with lambda) its derivative with respect to G
+void launch_mlp_layers_outputs(const LayArgs& a, int64_t N, hipStream_t s);
+void launch_mlp_layers_seeded_backward(const LayArgs& a, int64_t N, bool lambda, hipStream_t s);
 // forward with the tangent along U and the reverse pass of w E - E_dot
 void launch_mlp_layers_tangent(const LayArgs& a, int64_t N, hipStream_t s);
 // dL/dW, dL/db from the stashes (energy path or, with tangent, both terms)
 void launch_lay_wgrad(const LayArgs& a, int64_t N, bool tangent, float* partial, const LayGradOut& out, hipStream_t s);
+
+// qeq.hip: charge equilibration per structure (Sec. II.B)
+constexpr int kQeqMax = 64;  // atoms per structure the on-chip solve takes
+struct QeqArgs {
+  const double* pos;        // [N][3]
+  const int32_t* species;   // [N]
+  const int64_t* atom_ptr;  // [B+1]
+  const uint8_t* pbc;       // [B][3]
+  int32_t B;
+  int64_t N;
+  const float* out;         // [N][3] network outputs E0, chi, J
+  const double* total;      // [B] total charge of each structure
+  double sigma[NN_MAX_SPECIES];
+  double ke;                // e^2 / (4 pi eps0)
+  double* E_struct;         // [B]
+  double* q;                // [N] charges
+  float* seed;              // [N][3] (1, q, q^2 / 2)
+  int64_t* meta;            // error bits
+};
+void launch_qeq_solve(const QeqArgs& a, hipStream_t s);
+// F [N][3] += the Coulomb pair forces at the charges a.q
+void launch_qeq_coulomb(const QeqArgs& a, float* F, hipStream_t s);
 
 // wgrad.hip
 struct WgradArgs {

@@ -149,11 +149,14 @@ __global__ void __launch_bounds__(64 * kLayWaves) k_lay_fwd(LayArgs A, int h) {
 }
 
 // ---------------------------------------------------------------------------
-// linear output layer: E_i, and the adjoints of the last hidden layer
+// linear output layer: the atom's outputs, and the adjoints of the last
+// hidden layer
 //   mode 0: E only;  1: delta = w_out * act';
 //   2 (loss on forces, per-atom weight w): z_bar = w_out (w act' - act'' z_dot),
-//     z_dot_bar = -w_out act'.
-// 16 lanes per row; fixed shuffle tree, so E is the same on every run.
+//     z_dot_bar = -w_out act';
+//   3: the n_out outputs into out [N][n_out] (no adjoint);
+//   4: delta = (sum_o seed_o w_out[o]) * act'  (seeded outputs, no output write).
+// 16 lanes per row; fixed shuffle tree, so the outputs are the same on every run.
 // ---------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(256) k_lay_out(LayArgs A, int mode) {
@@ -167,23 +170,36 @@ __global__ void __launch_bounds__(256) k_lay_out(LayArgs A, int mode) {
   const MlpDev& M = A.model.m[s];
   const int L = M.n_layers, hl = L - 1;  // the last hidden layer
   const int K = M.width[hl];
-  const float* w = M.W[L - 1];
+  const float* w = M.W[L - 1];           // [n_out][K]
   const int ld = A.buf.ld[hl];
-  float e = 0.f;
-  if (valid) {
-    const float* ar = A.buf.a[hl] + r * ld;
-    for (int k = sub; k < K; k += 16) e = fmaf(w[k], ar[k], e);
-  }
+  const int64_t atom = valid ? A.perm[r] : 0;
+  if (mode != 4) {
+    for (int o = 0; o < A.n_out; ++o) {
+      float e = 0.f;
+      if (valid) {
+        const float* ar = A.buf.a[hl] + r * ld;
+        for (int k = sub; k < K; k += 16) e = fmaf(w[(int64_t)o * K + k], ar[k], e);
+      }
 #pragma unroll
-  for (int o = 8; o > 0; o >>= 1) e += __shfl_xor(e, o, 16);
-  if (!valid) return;
-  const int64_t atom = A.perm[r];
-  if (sub == 0) A.E_atom[atom] = e + M.b[L - 1][0];
-  if (mode == 0) return;
+      for (int x = 8; x > 0; x >>= 1) e += __shfl_xor(e, x, 16);
+      if (valid && sub == 0) {
+        if (mode == 3) A.out[atom * A.n_out + o] = e + M.b[L - 1][o];
+        else A.E_atom[atom] = e + M.b[L - 1][0];
+      }
+    }
+  }
+  if (!valid || mode == 0 || mode == 3) return;
   const float* sr = A.buf.s[hl] + r * ld;
   float* dr = A.buf.d[hl] + r * ld;
   if (mode == 1) {
     for (int k = sub; k < K; k += 16) dr[k] = w[k] * sr[k];
+  } else if (mode == 4) {
+    const float* sd = A.seed + atom * A.n_out;
+    for (int k = sub; k < K; k += 16) {
+      float g = 0.f;
+      for (int o = 0; o < A.n_out; ++o) g = fmaf(sd[o], w[(int64_t)o * K + k], g);
+      dr[k] = g * sr[k];
+    }
   } else {
     const float wa = A.w_atom[atom];
     const float* qr = A.buf.q[hl] + r * ld;
@@ -352,7 +368,7 @@ __global__ void __launch_bounds__(64 * kLayWaves) k_lay_wgrad(LayArgs A, int64_t
       float zb = 0.f, zq = 0.f;
       if (rv && o < Nout) {
         if (out_layer) {
-          zb = A.w_atom[atom];
+          zb = A.seed ? A.w_atom[atom] * A.seed[(int64_t)atom * A.n_out + o] : A.w_atom[atom];
           zq = -1.f;
         } else if constexpr (TAN) {
           zb = A.buf.d[h][rr * ldh + o];
@@ -504,6 +520,28 @@ void launch_mlp_layers(const LayArgs& a, int64_t N, bool lambda, hipStream_t s) 
   hipLaunchKernelGGL(k_lay_out, dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s, a, lambda ? 1 : 0);
   if (!lambda) return;
   for (int h = H; h >= 1; --h) {
+    const unsigned ct = (unsigned)((max_width(a.model, h - 1) + 63) / 64);
+    hipLaunchKernelGGL(k_lay_bwd<false>, dim3(rt, ct), dim3(64 * kLayWaves), 0, s, a, h);
+  }
+}
+
+void launch_mlp_layers_outputs(const LayArgs& a, int64_t N, hipStream_t s) {
+  if (N == 0) return;
+  const int H = max_hidden(a.model);
+  const unsigned rt = lay_row_tiles(N, a.model.S);
+  for (int h = 1; h <= H; ++h) {
+    const unsigned ct = (unsigned)((max_width(a.model, h) + 63) / 64);
+    hipLaunchKernelGGL(k_lay_fwd<false>, dim3(rt, ct), dim3(64 * kLayWaves), 0, s, a, h);
+  }
+  hipLaunchKernelGGL(k_lay_out, dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s, a, 3);
+}
+
+void launch_mlp_layers_seeded_backward(const LayArgs& a, int64_t N, bool lambda, hipStream_t s) {
+  if (N == 0) return;
+  const int H = max_hidden(a.model);
+  const unsigned rt = lay_row_tiles(N, a.model.S);
+  hipLaunchKernelGGL(k_lay_out, dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s, a, 4);
+  for (int h = H; h >= (lambda ? 1 : 2); --h) {
     const unsigned ct = (unsigned)((max_width(a.model, h - 1) + 63) / 64);
     hipLaunchKernelGGL(k_lay_bwd<false>, dim3(rt, ct), dim3(64 * kLayWaves), 0, s, a, h);
   }

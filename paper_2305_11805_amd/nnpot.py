@@ -73,13 +73,18 @@ class nn_loss_params(C.Structure):
                 ("energy_weight", C.c_double), ("force_weight", C.c_double)]
 
 
+class nn_qeq_params(C.Structure):
+    _fields_ = [("sigma", C.c_void_p), ("coulomb", C.c_double)]
+
+
 class nn_langevin(C.Structure):
     _fields_ = [("dt", C.c_double), ("friction", C.c_double), ("kT", C.c_double)]
 
 
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
-           "nn_energy_forces", "nn_energy_forces_noalloc", "nn_energy_forces_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_energy_forces", "nn_energy_forces_noalloc", "nn_energy_forces_grad", "nn_energy_forces_qeq",
+           "nn_energy_forces_qeq_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset", "nn_check",
            "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
@@ -108,6 +113,10 @@ def lib():
         L.nn_energy_forces.argtypes = [P, P, P, P, I32, SZ, P, P, P, P, SZ, P]
         L.nn_energy_forces_noalloc.restype = I32
         L.nn_energy_forces_noalloc.argtypes = [P, P, P, P, I32, P, P, P, P]
+        L.nn_energy_forces_qeq.restype = I32
+        L.nn_energy_forces_qeq.argtypes = [P, P, P, P, P, P, P, P, P, P, SZ, P]
+        L.nn_energy_forces_qeq_grad.restype = I32
+        L.nn_energy_forces_qeq_grad.argtypes = [P, P, P, P, P, P, P, P, SZ, P]
         L.nn_descriptor_tangent.restype = I32
         L.nn_descriptor_tangent.argtypes = [P, P, P, P, P, P]
         L.nn_md_langevin.restype = I32
@@ -191,6 +200,17 @@ def nn_energy_forces(sys, nl, params, model, flags, mem_budget, E_struct, E_atom
 def nn_energy_forces_noalloc(sys, nl, params, model, flags, E_struct, E_atom, F, stream=None):
     _ok(lib().nn_energy_forces_noalloc(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags,
                                        _p(E_struct), _p(E_atom), _p(F), _stream(stream)))
+
+
+def nn_energy_forces_qeq(sys, nl, params, model, qp, total_charge, E_struct, charges, F, ws, stream=None):
+    _ok(lib().nn_energy_forces_qeq(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), C.byref(qp),
+                                   _p(total_charge), _p(E_struct), _p(charges), _p(F), _p(ws), ws.numel(),
+                                   _stream(stream)))
+
+
+def nn_energy_forces_qeq_grad(sys, nl, params, model, dL_dE, dW, db, ws, stream=None):
+    _ok(lib().nn_energy_forces_qeq_grad(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), _p(dL_dE),
+                                        _ptr_table(dW), _ptr_table(db), _p(ws), ws.numel(), _stream(stream)))
 
 
 def _ptr_table(tensors):
@@ -445,6 +465,39 @@ class Potential:
         nn_energy_forces(self.sys, self.nl, self.params, self.dmodel.struct, f, b, self.E_struct,
                          self.E_atom, self.F if forces else None, self.ws)
         return self.E_struct, self.E_atom, self.F
+
+    def energy_forces_qeq(self, total_charge, sigma, coulomb=14.399645, forces: bool = True):
+        """(E_struct [B] FP64, charges [N] FP64, F [N, 3] FP32) with charge
+        equilibration (Sec. II.B): the model's networks have three outputs per
+        atom; sigma [S] are the species' Gaussian charge widths."""
+        torch = self.torch
+        Qt = torch.as_tensor(total_charge, dtype=torch.float64, device=self.dev).contiguous()
+        sig = np.ascontiguousarray(sigma, np.float64)
+        qp = nn_qeq_params(sig.ctypes.data, float(coulomb))
+        q = torch.empty(self.N, dtype=torch.float64, device=self.dev)
+        self.evals += 1
+        nn_energy_forces_qeq(self.sys, self.nl, self.params, self.dmodel.struct, qp, Qt, self.E_struct, q,
+                             self.F if forces else None, self.ws)
+        return self.E_struct, q, self.F
+
+    def grad_qeq(self, dL_dE):
+        """[species][layer] (dW, db) of a loss on the energies of the last
+        energy_forces_qeq() call."""
+        torch = self.torch
+        dL_dE = torch.as_tensor(dL_dE, dtype=torch.float64, device=self.dev).contiguous()
+        dW, db = [], []
+        it = iter(self.dmodel.tensors)
+        for s in range(self.dmodel.struct.n_species):
+            L = self.dmodel.struct.mlp[s].n_layers
+            ws_, bs_ = [], []
+            for _ in range(L):
+                W, b = next(it), next(it)
+                ws_.append(torch.empty_like(W))
+                bs_.append(torch.empty_like(b))
+            dW.append(ws_)
+            db.append(bs_)
+        nn_energy_forces_qeq_grad(self.sys, self.nl, self.params, self.dmodel.struct, dL_dE, dW, db, self.ws)
+        return [list(zip(w_s, b_s)) for w_s, b_s in zip(dW, db)]
 
     def jacobian(self):
         """(G [N, D], J [capacity, stride]) via nn_descriptors with a Jacobian buffer."""
