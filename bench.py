@@ -543,6 +543,63 @@ def md_table2(args):
     print(json.dumps(out), flush=True)
 
 
+def qeq_bench(args):
+    """Charge equilibration (Sec. II.B) on a batch of charged NaCl-like
+    clusters (--qeq-clusters of 16/17 atoms, total charge +1): per step the
+    list build, descriptors, the 3-output networks, the per-structure FP64
+    solve, the seeded backward pass, the adjoint, the gather and the Coulomb
+    forces.  Reports atoms/s, the stage times, the errors against the FP64
+    oracle on the first 64 clusters and the oracle's own throughput there.
+    Prints one JSON line."""
+    import torch
+    from oracle import qeq as oqeq
+    import oracle
+    from paper_2305_11805_amd import nnpot, synth
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    oracle.build(force=False)
+    w, Qc = synth.qeq_clusters(args.qeq_clusters)
+    s = w.system
+    pot = nnpot.Potential(s, w.params, w.model)
+    Qt = torch.tensor(Qc, dtype=torch.float64, device="cuda")
+    sig = w.extra["sigma"]
+
+    def step():
+        pot.build_neighbors(check=False)
+        pot.energy_forces_qeq(Qt, sig)
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    nnpot.nn_check(pot.nl)
+    stream = torch.cuda.current_stream()
+    ms = _timed(torch, stream, step, args.steps) / args.steps
+    nnpot.nn_timing(True)
+    step()
+    st = nnpot.nn_timing_read()
+    nnpot.nn_timing(False)
+    nnpot.nn_check(pot.nl)
+    E = pot.E_struct.cpu().numpy()
+    _, q, F = pot.energy_forces_qeq(Qt, sig)
+    q, F = q.cpu().numpy(), F.cpu().numpy()
+    # the oracle on the first 64 clusters (timed: its own throughput)
+    m = min(64, s.n_structs)
+    a1 = int(s.atom_ptr[m])
+    sub = synth.System(s.pos[:a1], s.species[:a1], s.atom_ptr[:m + 1], s.cell[:m], s.pbc[:m])
+    t0 = time.perf_counter()
+    Es_r, q_r, F_r, _ = oqeq.energy_forces_qeq(w.params, w.model, sub, Qc[:m], sig)
+    t_or = time.perf_counter() - t0
+    out = {"step": "charge_equilibration", "workload": w.name, "n_atoms": s.n_atoms, "steps": args.steps,
+           "ms_per_step": round(ms, 4), "atoms_per_s": round(s.n_atoms / ms * 1e3, 1),
+           "stages_ms": {k: round(v[0], 5) for k, v in st.items() if v[1]},
+           "errors_first_64_clusters": {
+               "E_per_atom_max": float(np.max(np.abs(E[:m] - Es_r) / np.diff(sub.atom_ptr))),
+               "q_max": float(np.abs(q[:a1] - q_r).max()), "F_max": float(np.abs(F[:a1] - F_r).max())},
+           "oracle": {"atoms_per_s": round(a1 / t_or, 1), "what": "numpy FP64 oracle, first 64 clusters",
+                      "seconds": round(t_or, 2)}}
+    print(json.dumps(out), flush=True)
+
+
 def stored_mode(args):
     """The stored-Jacobian (precomputed-derivative) mode of Sec. II.A on
     --config: a store step (list, descriptors with the Jacobian, MLP,
@@ -945,6 +1002,9 @@ def main():
     ap.add_argument("--md", action="store_true",
                     help="Langevin dynamics of 16-atom cells (the Table II shape) instead of the bench line")
     ap.add_argument("--md-cells", type=int, default=1024, help="cells in the batched --md run")
+    ap.add_argument("--qeq", action="store_true",
+                    help="time charge equilibration (Sec. II.B) on charged clusters instead of the bench line")
+    ap.add_argument("--qeq-clusters", type=int, default=4096, help="clusters in the --qeq run")
     ap.add_argument("--force-matching", action="store_true",
                     help="time the force-matching training step on --config instead of the bench line")
     args = ap.parse_args()
@@ -962,6 +1022,9 @@ def main():
         return
     if args.md:
         md_table2(args)
+        return
+    if args.qeq:
+        qeq_bench(args)
         return
     if args.stored:
         stored_mode(args)
