@@ -70,14 +70,15 @@ static PlanKey plan_key(int64_t n_atoms, int64_t capacity, const DescConst& P, c
 }
 
 // NNPOT_PLAN="f,a,m" in the environment forces a plan on every call (waves
-// per atom of the forward and adjoint passes in {1, 2, 4}, waves per MLP
-// tile in {4, 8}): lets tests run each launch variant against the oracle.
+// per atom of the forward and adjoint passes in {0 (packed), 1, 2, 4},
+// waves per MLP tile in {4, 8}): lets tests run each launch variant against
+// the oracle.
 static bool forced_plan(LaunchPlan* out) {
   const char* e = getenv("NNPOT_PLAN");
   if (!e || !*e) return false;
   int f = 0, a = 0, m = 0;
   if (sscanf(e, "%d,%d,%d", &f, &a, &m) != 3) return false;
-  auto ok = [](int w) { return w == 1 || w == 2 || w == 4; };
+  auto ok = [](int w) { return w == 0 || w == 1 || w == 2 || w == 4; };
   if (!ok(f) || !ok(a) || (m != 4 && m != 8)) return false;
   *out = LaunchPlan{f, a, m};
   return true;
@@ -89,7 +90,7 @@ static LaunchPlan plan_for(int64_t n_atoms, int64_t capacity, const DescConst& P
   const PlanKey k = plan_key(n_atoms, capacity, P, model, mode);
   std::lock_guard<std::mutex> g(g_pmu);
   auto it = g_plans.find(k);
-  return it != g_plans.end() ? it->second : plan_default(n_atoms, P.S, capacity);
+  return it != g_plans.end() ? it->second : plan_default(n_atoms, P, capacity);
 }
 
 // ---------------------------------------------------------------------------
@@ -804,7 +805,7 @@ nn_status nn_descriptors(const nn_system* sys, const nn_nlist* nl, const nn_mbp_
   hipStream_t s = (hipStream_t)stream;
   {
     StageTimer t(NN_STAGE_DESC_FWD, s);
-    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, plan_default(sys->n_atoms, P.S, nl->capacity).wpa_fwd, s);
+    launch_desc_fwd(*sys, *nl, P, G, IdentityGroup{}, plan_for(sys->n_atoms, nl->capacity, P, nullptr, 0).wpa_fwd, s);
   }
   if (jac) {
     StageTimer t(NN_STAGE_DESC_JAC, s);
@@ -823,7 +824,7 @@ nn_status nn_descriptor_tangent(const nn_system* sys, const nn_nlist* nl, const 
   if ((!v || !U) && sys->n_atoms > 0) return fail(NN_E_INVALID, "v/U is NULL");
   if (nl->radius < p->rc) return fail(NN_E_INVALID, "list radius %g < rc %g", nl->radius, p->rc);
   hipStream_t s = (hipStream_t)stream;
-  launch_desc_tan(*sys, *nl, P, v, U, plan_default(sys->n_atoms, P.S, nl->capacity).wpa_fwd, s);
+  launch_desc_tan(*sys, *nl, P, v, U, plan_for(sys->n_atoms, nl->capacity, P, nullptr, 0).wpa_fwd, s);
   return check_launch("nn_descriptor_tangent");
 }
 
@@ -883,7 +884,7 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
   if (!ws || ws_bytes < L.bytes) return fail(NN_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.bytes);
   L = carve(ws, N, sys->n_structs, nl->capacity, P.D, P.S, model);
   const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
-  LaunchPlan best = plan_default(N, P.S, nl->capacity);
+  LaunchPlan best = plan_default(N, P, nl->capacity);
   if (N > 0) {
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -910,7 +911,9 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     a.D = P.D;
     const int h1 = model->mlp[0].width[1], h2 = model->mlp[0].width[2];
     float t_best = -1.f;
-    for (int w : {1, 2, 4}) {  // descriptor forward
+    const bool pk = packed_supported(P);
+    for (int w : {0, 1, 2, 4}) {  // descriptor forward
+      if (w == 0 && !pk) continue;
       const float t = time_of([&] { launch_desc_fwd(*sys, *nl, P, L.G, IdentityGroup{}, w, s); });
       if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_fwd = w;
     }
@@ -925,7 +928,8 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
       launch_mlp_layers(lay_args(a, L), N, true, s);  // no launch choice to tune; lambda for the adjoint
     }
     t_best = -1.f;
-    for (int w : {1, 2, 4}) {  // adjoint
+    for (int w : {0, 1, 2, 4}) {  // adjoint
+      if (w == 0 && !pk) continue;
       const float t = time_of([&] { launch_desc_adj(*sys, *nl, P, L.lam, L.pg, w, s); });
       if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_adj = w;
     }

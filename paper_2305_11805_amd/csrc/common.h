@@ -153,13 +153,15 @@ struct IdentityGroup {
 };
 // Launch choices that change the speed of a pass but not what it computes
 // (only the order of some sums): waves per atom of the descriptor forward
-// and adjoint passes (1, 2 or 4) and waves per MLP tile (4 or 8; 0 = the
+// and adjoint passes (1, 2 or 4; 0 = the packed passes, four short-row atoms
+// per wave, where packed_supported) and waves per MLP tile (4 or 8; 0 = the
 // default).  Defaults come from plan_default(); nn_autotune stores measured
 // ones per shape class.
 struct LaunchPlan {
   int wpa_fwd, wpa_adj, mlp_waves;
 };
-LaunchPlan plan_default(int64_t n_atoms, int n_species, int64_t capacity);
+bool packed_supported(const DescConst& P);
+LaunchPlan plan_default(int64_t n_atoms, const DescConst& P, int64_t capacity);
 void launch_desc_fwd(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
                      int wpa, hipStream_t s);
 void launch_desc_adj(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,

@@ -28,6 +28,8 @@
 //   reproducible.
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace nnp {
@@ -94,6 +96,44 @@ static inline unsigned atom_grid(int64_t N, const int32_t* order) {
 
 constexpr int kStageRounds = 2;  // rows up to 128 entries are staged in one pass
 
+// Packed passes: kPackAtoms atoms per wave, kPackLanes lanes per atom in the
+// per-atom phases.  An atom is packed when its row has at most kPackNb
+// entries; longer rows go to the one-atom kernels.
+constexpr int kPackAtoms = 4;
+constexpr int kPackLanes = 16;
+constexpr int kPackNb = 32;
+
+// sin and cos of x in [0, pi/2] by their Taylor series to x^11 and x^12
+// (truncation below 6e-8 at pi/2), without range reduction.
+__device__ __forceinline__ void sincos_quarter(float x, float& sn, float& cs) {
+  const float z = x * x;
+  sn = x * fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, -2.5052108e-8f, 2.7557319e-6f), -1.9841270e-4f), 8.3333333e-3f),
+                        -1.6666667e-1f), 1.0f);
+  cs = fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, 2.0876757e-9f, -2.7557319e-7f), 2.4801587e-5f), -1.3888889e-3f),
+                        4.1666667e-2f), -0.5f), 1.0f);
+}
+
+// The staged record of one neighbor inside rc from its FP64 displacement d
+// (|d|^2 = r2): (d/r, r hi), (fc, dfc/dr, r lo, entry << 4 | species), 1/r.
+// rc - r is formed in FP64 (no cancellation near rc); with x = pi (rc - r) /
+// (2 rc) in [0, pi/2], fc = sin^2 x and dfc/dr = -(pi / 2rc) sin 2x =
+// -(pi / rc) sin x cos x, from one polynomial sine and cosine.
+__device__ __forceinline__ void pair_record(const double (&d)[3], double r2, int e_rel, int sp, const DescConst& P,
+                                            float4& dd, float4& ff, float& irf) {
+  const double r = sqrt(r2);
+  const double ir = 1.0 / r;
+  const double u = P.rc64 - r;
+  const float r_hi = (float)r;
+  const float r_lo = (float)(r - (double)r_hi);
+  float sa, ca;
+  sincos_quarter((float)(P.half_pi_over_rc64 * u), sa, ca);
+  const float fc = sa * sa;
+  const float dfc = -P.pi_over_rc * (sa * ca);
+  dd = make_float4((float)(d[0] * ir), (float)(d[1] * ir), (float)(d[2] * ir), r_hi);
+  ff = make_float4(fc, dfc, r_lo, __int_as_float((e_rel << 4) | sp));
+  irf = (float)ir;
+}
+
 // Stage the neighbors of atom i inside rc into LDS, sorted by species.
 // Entries at r >= rc get a zero pair gradient if pg != nullptr; with d64
 // the FP64 displacements are staged too ([slot][3]).
@@ -105,9 +145,13 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   // wave 0 does the work; every thread of the block passes the barriers
   const int lane = threadIdx.x & 63;
   const bool w0 = threadIdx.x < 64;
-  const int c = struct_of_atom(sys.atom_ptr, sys.n_structs, i);
+  // the structure's cell: only image shifts need it (with all shifts zero
+  // displacement64 gives x_j - x_i exactly whatever the cell)
   double h[9];
-  for (int k = 0; k < 9; ++k) h[k] = sys.cell[9 * (int64_t)c + k];
+  auto load_cell = [&]() {
+    const int c = struct_of_atom(sys.atom_ptr, sys.n_structs, i);
+    for (int k = 0; k < 9; ++k) h[k] = sys.cell[9 * (int64_t)c + k];
+  };
   const double xi[3] = {sys.pos[3 * i], sys.pos[3 * i + 1], sys.pos[3 * i + 2]};
   const int64_t e0 = offsets[i], e1 = offsets[i + 1];
   const double rc2 = P.rc64 * P.rc64;
@@ -125,23 +169,16 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
   // entry e (neighbor j of species sp, FP64 displacement d, |d|^2 = r2 <
   // rc^2) into staging slot `slot`
   auto put = [&](int64_t e, int32_t j, int slot, const double (&d)[3], double r2, int sp) {
-    const double r = sqrt(r2);
-    const double ir = 1.0 / r;
-    const double u = P.rc64 - r;  // formed in FP64: no cancellation near rc
-    const float r_hi = (float)r;
-    const float r_lo = (float)(r - (double)r_hi);
-    const float sa = sinf((float)(P.half_pi_over_rc64 * u));
-    const float fc = sa * sa;  // sin^2(pi (rc - r) / (2 rc))
-    // dfc/dr = -(pi / 2rc) sin(pi r / rc), and sin(pi r / rc) = sin(pi (rc - r) / rc)
-    const float dfc = (float)(-0.5 * P.pi_over_rc64) * sinf((float)(P.pi_over_rc64 * u));
-    const float ux = (float)(d[0] * ir), uy = (float)(d[1] * ir), uz = (float)(d[2] * ir), irf = (float)ir;
-    nb.d[slot] = make_float4(ux, uy, uz, r_hi);
-    nb.f[slot] = make_float4(fc, dfc, r_lo, __int_as_float(((int)(e - e0) << 4) | sp));
+    float4 dd, ff;
+    float irf;
+    pair_record(d, r2, (int)(e - e0), sp, P, dd, ff, irf);
+    nb.d[slot] = dd;
+    nb.f[slot] = ff;
     nb.ir[slot] = irf;
     if (tw) {
       const float dx = field[3 * (int64_t)j] - vx, dy = field[3 * (int64_t)j + 1] - vy,
                   dz = field[3 * (int64_t)j + 2] - vz;
-      tw[slot] = make_float4(dx * irf, dy * irf, dz * irf, fmaf(ux, dx, fmaf(uy, dy, uz * dz)));
+      tw[slot] = make_float4(dx * irf, dy * irf, dz * irf, fmaf(dd.x, dx, fmaf(dd.y, dy, dd.z * dz)));
     }
     if (d64) {
       d64[3 * slot] = d[0];
@@ -157,20 +194,35 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
       bool valid[kStageRounds];
       int sp[kStageRounds];
       int32_t jr[kStageRounds];
+      char4 s4r[kStageRounds];
       double d[kStageRounds][3], r2[kStageRounds];
-      bool bad = false;
+      bool bad = false, shifted = false;
+#pragma unroll
+      for (int r = 0; r < kStageRounds; ++r) {
+        const int64_t e = e0 + r * kWave + lane;
+        jr[r] = 0;
+        s4r[r] = make_char4(0, 0, 0, 0);
+        if (e < e1) {
+          jr[r] = nbr[e];
+          s4r[r] = sh4[e];
+          shifted = shifted || (s4r[r].x | s4r[r].y | s4r[r].z) != 0;
+        }
+      }
+      if (__any(shifted)) {
+        load_cell();
+      } else {
+        for (int k = 0; k < 9; ++k) h[k] = 0.0;
+      }
 #pragma unroll
       for (int r = 0; r < kStageRounds; ++r) {
         const int64_t e = e0 + r * kWave + lane;
         valid[r] = false;
         sp[r] = 0;
-        jr[r] = 0;
         d[r][0] = d[r][1] = d[r][2] = 0.0;
         r2[r] = 0.0;
         if (e < e1) {
-          const int32_t j = nbr[e];
-          jr[r] = j;
-          const char4 s4 = sh4[e];
+          const int32_t j = jr[r];
+          const char4 s4 = s4r[r];
           displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d[r]);
           r2[r] = norm2_64(d[r]);
           valid[r] = r2[r] < rc2;
@@ -206,6 +258,7 @@ __device__ void stage_neighbors(AtomNb& nb, int64_t i, const nn_system& sys, con
     __syncthreads();
     return;
   }
+  load_cell();
   int cnt[NN_MAX_SPECIES];
   for (int s = 0; s < NN_MAX_SPECIES; ++s) cnt[s] = 0;
   bool bad = false;
@@ -397,15 +450,6 @@ __device__ __forceinline__ float ipow_uniform(float x, int e) {
   return r;
 }
 
-// sin and cos of x in [0, pi/2] by their Taylor series to x^11 and x^12
-// (truncation below 6e-8 at pi/2), without range reduction.
-__device__ __forceinline__ void sincos_quarter(float x, float& sn, float& cs) {
-  const float z = x * x;
-  sn = x * fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, -2.5052108e-8f, 2.7557319e-6f), -1.9841270e-4f), 8.3333333e-3f),
-                        -1.6666667e-1f), 1.0f);
-  cs = fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, fmaf(z, 2.0876757e-9f, -2.7557319e-7f), 2.4801587e-5f), -1.3888889e-3f),
-                        4.1666667e-2f), -0.5f), 1.0f);
-}
 
 // Standard BP triplet terms from the two staged neighbors (unit vector,
 // r): cos(theta), s2 = r_ij^2 + r_ik^2 + r_jk^2, the third side w = d_k -
@@ -464,25 +508,14 @@ __device__ __forceinline__ BpSide bp_side64(const double* __restrict__ dj, const
 
 constexpr int kFuseTriplets = 256;  // triplets per atom for the pair-block-per-MFMA-block forward
 
+// The descriptor row of atom i by the block (WPA waves).
 template <int NT, int NRA, int WPA, int ZC>
-__global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
-                                                       const int32_t* __restrict__ nbr,
-                                                       const int8_t* __restrict__ shift, DescConst P,
-                                                       float* __restrict__ G, int64_t* meta, IdentityGroup one,
-                                                       const int32_t* __restrict__ order) {
+__device__ __forceinline__ void desc_fwd_atom(int64_t i, bool list_ok, const nn_system& sys,
+                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ nbr,
+                                              const int8_t* __restrict__ shift, const DescConst& P,
+                                              float* __restrict__ G, int64_t* meta) {
   constexpr int NB = NT * NRA;
   __shared__ AtomNb nb;
-  const bool list_ok = meta[kMetaValid] == 1;
-  const int64_t i = atom_of_block(order, sys.n_atoms, list_ok);
-  if (i < 0) return;
-  if (one.perm && threadIdx.x == 0) {
-    one.perm[i] = (int32_t)i;
-    if (sys.species[i] != 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
-    if (i == 0) {
-      one.sp_start[0] = 0;
-      one.sp_start[1] = sys.n_atoms;
-    }
-  }
   // per-wave partial sums (radial bins: S * n_rad <= 512; angular block: NB)
   __shared__ float xch[WPA > 1 ? WPA * NN_MAX_SPECIES * kMaxRad : 1];
   __shared__ float4 tgeo[WPA][kWave];  // per chunk: cos, smoothed sine, average radius (hi, lo)
@@ -778,6 +811,55 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int6
         __syncthreads();
       }
     }
+  }
+}
+
+// With one species the descriptor launch also writes the identity grouping.
+__device__ __forceinline__ void identity_group(IdentityGroup one, const nn_system& sys, int64_t i, int64_t* meta) {
+  one.perm[i] = (int32_t)i;
+  if (sys.species[i] != 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+  if (i == 0) {
+    one.sp_start[0] = 0;
+    one.sp_start[1] = sys.n_atoms;
+  }
+}
+
+template <int NT, int NRA, int WPA, int ZC>
+__global__ void __launch_bounds__(64 * WPA) k_desc_fwd(nn_system sys, const int64_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const int8_t* __restrict__ shift, DescConst P,
+                                                       float* __restrict__ G, int64_t* meta, IdentityGroup one,
+                                                       const int32_t* __restrict__ order) {
+  const bool list_ok = meta[kMetaValid] == 1;
+  const int64_t i = atom_of_block(order, sys.n_atoms, list_ok);
+  if (i < 0) return;
+  if (one.perm && threadIdx.x == 0) identity_group(one, sys, i, meta);
+  desc_fwd_atom<NT, NRA, WPA, ZC>(i, list_ok, sys, offsets, nbr, shift, P, G, meta);
+}
+
+// The atoms a packed launch leaves out (rows over kPackNb entries), one
+// wave per block of 64 atom slots: the lanes test their slots' rows and the
+// wave then takes the long ones one after another.  Also writes the
+// identity grouping of all atoms.  Nothing else to do while the list is not
+// valid (the packed launch zeroes every row then).
+template <int NT, int NRA, int ZC>
+__global__ void __launch_bounds__(64) k_desc_fwd_long(nn_system sys, const int64_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ nbr,
+                                                      const int8_t* __restrict__ shift, DescConst P,
+                                                      float* __restrict__ G, int64_t* meta, IdentityGroup one,
+                                                      const int32_t* __restrict__ order) {
+  const bool list_ok = meta[kMetaValid] == 1;
+  const int64_t slot = (int64_t)blockIdx.x * kWave + threadIdx.x;
+  const bool in = slot < sys.n_atoms;
+  const int64_t i = !in ? -1 : (order && list_ok) ? (int64_t)order[slot] : slot;
+  if (one.perm && in) identity_group(one, sys, i, meta);
+  if (!list_ok) return;
+  uint64_t m = __ballot(in && offsets[i + 1] - offsets[i] > kPackNb);
+  while (m) {
+    const int b = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    desc_fwd_atom<NT, NRA, 1, ZC>(__shfl(i, b), true, sys, offsets, nbr, shift, P, G, meta);
+    __syncthreads();  // this atom's LDS reads are done before the next one's staging
   }
 }
 
@@ -1110,11 +1192,10 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
 // Per-pair energy gradients dE_i/dd_e (float4 per entry, w unused) from
 // lambda_i = dE_i/dG_i.
 template <int NT, int NRA, bool ONE_SPECIES, int WPA, int ZC>
-__global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int64_t* __restrict__ offsets,
-                                                       const int32_t* __restrict__ nbr,
-                                                       const int8_t* __restrict__ shift, DescConst P,
-                                                       const float* __restrict__ lambda, float4* __restrict__ pg,
-                                                       int64_t* meta, const int32_t* __restrict__ order) {
+__device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, const int64_t* __restrict__ offsets,
+                                              const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
+                                              const DescConst& P, const float* __restrict__ lambda,
+                                              float4* __restrict__ pg, int64_t* meta) {
   constexpr int NB = NT * NRA;
   constexpr int NBP = NB + 4;  // padded block stride in LDS (bank spread)
   __shared__ AtomNb nb;
@@ -1122,9 +1203,6 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   extern __shared__ float dyn_lds[];  // [S * n_rad] radial lambda, then the angular blocks
   float* lam_r = dyn_lds;
   float* lam_a = dyn_lds + P.S * P.n_rad;
-  if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
-  const int64_t i = atom_of_block(order, sys.n_atoms, true);
-  if (i < 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t e0 = offsets[i];
   // this atom's lambda is requested before the neighbor staging (whose
@@ -1361,6 +1439,719 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int6
   }
 }
 
+template <int NT, int NRA, bool ONE_SPECIES, int WPA, int ZC>
+__global__ void __launch_bounds__(64 * WPA) k_desc_adj(nn_system sys, const int64_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ nbr,
+                                                       const int8_t* __restrict__ shift, DescConst P,
+                                                       const float* __restrict__ lambda, float4* __restrict__ pg,
+                                                       int64_t* meta, const int32_t* __restrict__ order) {
+  if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
+  const int64_t i = atom_of_block(order, sys.n_atoms, true);
+  if (i < 0) return;
+  desc_adj_atom<NT, NRA, ONE_SPECIES, WPA, ZC>(i, sys, offsets, nbr, shift, P, lambda, pg, meta);
+}
+
+// The atoms a packed adjoint leaves out (rows over kPackNb entries), as in
+// k_desc_fwd_long.
+template <int NT, int NRA, bool ONE_SPECIES, int ZC>
+__global__ void __launch_bounds__(64) k_desc_adj_long(nn_system sys, const int64_t* __restrict__ offsets,
+                                                      const int32_t* __restrict__ nbr,
+                                                      const int8_t* __restrict__ shift, DescConst P,
+                                                      const float* __restrict__ lambda, float4* __restrict__ pg,
+                                                      int64_t* meta, const int32_t* __restrict__ order) {
+  if (meta[kMetaValid] != 1) return;
+  const int64_t slot = (int64_t)blockIdx.x * kWave + threadIdx.x;
+  const bool in = slot < sys.n_atoms;
+  const int64_t i = !in ? -1 : order ? (int64_t)order[slot] : slot;
+  uint64_t m = __ballot(in && offsets[i + 1] - offsets[i] > kPackNb);
+  while (m) {
+    const int b = __ffsll((unsigned long long)m) - 1;
+    m &= m - 1;
+    desc_adj_atom<NT, NRA, ONE_SPECIES, 1, ZC>(__shfl(i, b), sys, offsets, nbr, shift, P, lambda, pg, meta);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packed passes for short rows (small molecules): kPackAtoms atoms per
+// one-wave block, kPackLanes lanes per atom while staging and in the radial
+// terms; the triplets of all the wave's atoms are spread over all 64 lanes.
+// ---------------------------------------------------------------------------
+
+struct PackNb {
+  float4 d[kPackAtoms * kPackNb];  // as AtomNb; atom g's neighbors at g kPackNb + [0, n_g)
+  float4 f[kPackAtoms * kPackNb];
+  int seg[kPackAtoms][NN_MAX_SPECIES + 1];
+  int64_t atom[kPackAtoms];  // the atom of each group, -1 if the group has none to pack
+};
+
+// The atom of lane group g of a packed launch: atom kPackAtoms w + g, w the
+// wave's block of atoms, taken XCD by XCD as in atom_of_block (block b ->
+// w = (b mod 8) per + b / 8), or -1.  The atoms a wave packs together set
+// the order of its sums, so they follow the atom index, not the list's bin
+// order (whose order within a bin is that of the binning atomics).
+__device__ __forceinline__ int64_t packed_atom(int64_t N, int g) {
+  const int64_t w = (int64_t)(blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+  const int64_t i = w * kPackAtoms + g;
+  return i < N ? i : -1;
+}
+
+static inline unsigned packed_grid(int64_t N) {
+  const int64_t w = (N + kPackAtoms - 1) / kPackAtoms;
+  return (unsigned)((w + 7) / 8 * 8);
+}
+
+// struct_of_atom for every 16-lane group at once (its own atom i; groups
+// with has = false get 0): each round a group's lanes probe 16 evenly
+// spaced positions of its remaining range.
+__device__ __forceinline__ int struct_of_atom16(const int64_t* atom_ptr, int32_t B, int64_t i, bool has) {
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
+  int lo = 0, hi = has ? B : 1;
+  while (__any(hi - lo > 1)) {
+    const bool act = hi - lo > 1;
+    const int step = (hi - lo + 15) / 16;
+    const int p = lo + l * step;
+    const uint64_t le = __ballot(act && p < hi && atom_ptr[p] <= i);
+    if (act) {
+      lo += (__popcll((le >> (16 * g)) & 0xffffull) - 1) * step;
+      hi = min(hi, lo + step);
+    }
+  }
+  return lo;
+}
+
+// Group g's lanes stage atom i's row (take: it has at most kPackNb entries)
+// into slots g kPackNb + [0, n), sorted by species (stable, so in entry
+// order within a species, as stage_neighbors), with nb.seg[g]; with ir the
+// 1/r of each slot too.  Entries at r >= rc get a zero pair gradient if pg
+// != nullptr.  Groups that do not take their atom stage nothing (n = 0).
+__device__ void stage_packed(PackNb& nb, float* ir, int64_t i, bool take, const nn_system& sys,
+                             const int64_t* __restrict__ offsets, const int32_t* __restrict__ nbr,
+                             const int8_t* __restrict__ shift, const DescConst& P, int64_t* meta,
+                             float4* __restrict__ pg) {
+  constexpr int R = kPackNb / kPackLanes;
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
+  if (l == 0) nb.atom[g] = take ? i : -1;
+  double xi[3] = {0.0, 0.0, 0.0};
+  int64_t e0 = 0, e1 = 0;
+  if (take) {
+    xi[0] = sys.pos[3 * i];
+    xi[1] = sys.pos[3 * i + 1];
+    xi[2] = sys.pos[3 * i + 2];
+    e0 = offsets[i];
+    e1 = offsets[i + 1];
+  }
+  const double rc2 = P.rc64 * P.rc64;
+  const int S = P.S;
+  const char4* sh4 = reinterpret_cast<const char4*>(shift);
+  int32_t jr[R];
+  char4 s4r[R];
+  bool shifted = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t e = e0 + r * kPackLanes + l;
+    jr[r] = 0;
+    s4r[r] = make_char4(0, 0, 0, 0);
+    if (e < e1) {
+      jr[r] = nbr[e];
+      s4r[r] = sh4[e];
+      shifted = shifted || (s4r[r].x | s4r[r].y | s4r[r].z) != 0;
+    }
+  }
+  // the structure's cell only for rows with image shifts (with all shifts
+  // zero displacement64 gives x_j - x_i exactly whatever the cell)
+  const bool need = take && ((__ballot(shifted) >> (16 * g)) & 0xffffull) != 0;
+  const int c = struct_of_atom16(sys.atom_ptr, sys.n_structs, i, need);
+  double h[9];
+  for (int k = 0; k < 9; ++k) h[k] = need ? sys.cell[9 * (int64_t)c + k] : 0.0;
+  bool valid[R];
+  int sp[R];
+  double d[R][3], r2[R];
+  bool bad = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t e = e0 + r * kPackLanes + l;
+    valid[r] = false;
+    sp[r] = 0;
+    d[r][0] = d[r][1] = d[r][2] = 0.0;
+    r2[r] = 0.0;
+    if (e < e1) {
+      const int32_t j = jr[r];
+      const char4 s4 = s4r[r];
+      displacement64(xi, sys.pos + 3 * (int64_t)j, h, s4.x, s4.y, s4.z, d[r]);
+      r2[r] = norm2_64(d[r]);
+      valid[r] = r2[r] < rc2;
+      sp[r] = sys.species[j];
+      if (sp[r] < 0 || sp[r] >= S) {
+        bad = bad || valid[r];
+        valid[r] = false;
+      }
+      if (!valid[r] && pg) pg[e] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+  if (__any(bad) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrSpecies);
+  const uint32_t lt = (1u << l) - 1u;
+  int slot[R] = {};
+  int total = 0;
+  for (int s2 = 0; s2 < S; ++s2) {
+    if (l == 0) nb.seg[g][s2] = total;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t m = (uint32_t)(__ballot(valid[r] && sp[r] == s2) >> (16 * g)) & 0xffffu;
+      if (valid[r] && sp[r] == s2) slot[r] = total + __popc(m & lt);
+      total += __popc(m);
+    }
+  }
+  if (l == 0) nb.seg[g][S] = total;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (valid[r]) {
+      float4 dd, ff;
+      float irf;
+      pair_record(d[r], r2[r], r * kPackLanes + l, sp[r], P, dd, ff, irf);
+      const int t = g * kPackNb + slot[r];
+      nb.d[t] = dd;
+      nb.f[t] = ff;
+      if (ir) ir[t] = irf;
+    }
+  wave_lds_sync();
+}
+
+// x broadcast from lane R of each group of four lanes (DPP quad_perm).
+template <int R>
+__device__ __forceinline__ int quad_bcast(int x) {
+  return __builtin_amdgcn_mov_dpp(x, R * 0x55, 0xf, 0xf, false);
+}
+template <int R>
+__device__ __forceinline__ float quad_bcast(float x) {
+  return __int_as_float(quad_bcast<R>(__float_as_int(x)));
+}
+
+// Dynamic LDS of k_desc_fwd_packed: the segment table (int4 [nseg + 1],
+// float [nseg]; int4 [nseg] with each segment's start and place in G), then
+// the head and tail rows of the 16 MFMA blocks.
+static inline size_t packed_fwd_lds(int S, int NB) {
+  const int nseg = kPackAtoms * S * (S + 1) / 2;
+  return sizeof(int4) * (2 * nseg + 1) + sizeof(float) * ((nseg + 3) / 4 * 4) + sizeof(float) * 2 * 16 * NB;
+}
+
+// Descriptor rows of kPackAtoms atoms per one-wave block, for atoms whose
+// rows have at most kPackNb entries (k_desc_fwd_long takes the others).
+// The radial bins as in k_desc_fwd with one wave, 16 lanes per atom.  The
+// angular bins: the wave's triplets are numbered species-pair block after
+// block, atom after atom (one segment per atom and block), and the 16 4-lane
+// MFMA blocks take equal contiguous ranges of that numbering, so no block
+// idles while another walks a long segment.  Each round every lane forms one
+// triplet's geometry, then the four lanes of a block take their four
+// triplets in turn (broadcast within the quad), each lane supplying its
+// angle and radius factors to the 4x4x1 MFMA as in k_desc_fwd.  When a block
+// passes the end of a segment its accumulators hold the segment's last
+// piece: a segment that lies inside the block's range goes straight to G; a
+// piece that began in an earlier range goes to the block's head row, and the
+// piece still open at the end of a range to its tail row.  The segments
+// split over ranges are then written as head + the tails of the ranges
+// before, in range order, so every sum has a fixed order.
+template <int NT, int NRA, int ZC>
+__global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int64_t* __restrict__ offsets,
+                                                        const int32_t* __restrict__ nbr,
+                                                        const int8_t* __restrict__ shift, DescConst P,
+                                                        float* __restrict__ G, int64_t* meta) {
+  static_assert(ZC != kZcBP, "the packed forward takes the mBP term");
+  constexpr int NB = NT * NRA, NP = NT / 4, NQ = NRA / 4;
+  __shared__ PackNb nb;
+  __shared__ int hseg[16], tseg[16];
+  extern __shared__ float4 pk_lds[];
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
+  const bool list_ok = meta[kMetaValid] == 1;
+  const int64_t i = packed_atom(sys.n_atoms, g);
+  const int D = P.D;
+  if (!list_ok) {  // no valid list: never read its entries
+    if (i >= 0)
+      for (int d = l; d < D; d += kPackLanes) G[i * D + d] = 0.f;
+    return;
+  }
+  const bool take = i >= 0 && offsets[i + 1] - offsets[i] <= kPackNb;
+  if (!__any(take)) return;
+  if (lane < 16) hseg[lane] = tseg[lane] = -1;
+  stage_packed(nb, nullptr, i, take, sys, offsets, nbr, shift, P, meta, nullptr);
+  const int S = P.S, nblk = S * (S + 1) / 2, nseg = kPackAtoms * nblk, ang0 = P.n_rad * S;
+  // radial bins: lane l of group g owns bins l, l + 16, ... of its atom
+  {
+    float* Gi = G + (take ? i : 0) * (int64_t)D;
+    const float eta_r2 = P.eta_rad * 1.4426950408889634f;
+    for (int k0 = 0; k0 < P.n_rad; k0 += kPackLanes) {
+      const int k = k0 + l;
+      const bool kin = k < P.n_rad;
+      const float rs = kin ? P.rs_rad[k] : 0.f, rs_lo = kin ? P.rs_rad_lo[k] : 0.f;
+      for (int s = 0; s < S; ++s) {
+        float acc = 0.f;
+        const int t1 = g * kPackNb + nb.seg[g][s + 1];
+        for (int t = g * kPackNb + nb.seg[g][s]; t < t1; ++t) {
+          const float dr = (nb.d[t].w - rs) + (nb.f[t].z - rs_lo);
+          acc = fmaf(fexp2(-eta_r2 * dr * dr), nb.f[t].x, acc);
+        }
+        if (take && kin) Gi[s * P.n_rad + k] = acc;
+      }
+    }
+  }
+  // segment table: segment s = a nblk + (layout index of species pair
+  // (pa, pb)) holds its first triplet in the wave's numbering, the slots of
+  // its j and k runs, m | same << 16 and 1/m; empty segments are written as
+  // zeros here
+  int4* stab = reinterpret_cast<int4*>(pk_lds);
+  int4* sdst = stab + nseg + 1;  // start, offset of the segment's bins in G (lo, hi)
+  float* sinv = reinterpret_cast<float*>(sdst + nseg);
+  float* head = sinv + (nseg + 3) / 4 * 4;
+  float* tail = head + 16 * NB;
+  const bool vec4 = (ang0 & 3) == 0;  // then D is a multiple of 4 too: 16-byte bin stores
+  int carry = 0;
+  for (int s0 = 0; s0 < nseg; s0 += kWave) {
+    const int s = s0 + lane;
+    int cnt = 0;
+    if (s < nseg) {
+      const int a = s / nblk, pbi = s - a * nblk;
+      int pa = 0, rem = pbi;
+      while (rem >= S - pa) {
+        rem -= S - pa;
+        ++pa;
+      }
+      const int pb = pa + rem;
+      const int ja = nb.seg[a][pa], na = nb.seg[a][pa + 1] - ja;
+      const int kb = nb.seg[a][pb], nbb = nb.seg[a][pb + 1] - kb;
+      const bool same = pa == pb;
+      const int m = same ? na : nbb;
+      cnt = same ? na * (na - 1) / 2 : na * nbb;
+      stab[s] = make_int4(0, a * kPackNb + ja, a * kPackNb + kb, m | (same ? 1 << 16 : 0));
+      sinv[s] = m > 0 ? 1.0f / (float)m : 0.f;
+      const int64_t ia = nb.atom[a];
+      const int64_t go = (ia >= 0 ? ia : 0) * (int64_t)D + ang0 + pbi * NB;
+      sdst[s] = make_int4(0, (int)(uint32_t)go, (int)(go >> 32), 0);
+      if (cnt == 0 && ia >= 0) {
+        float* o = G + ia * (int64_t)D + ang0 + pbi * NB;
+        if (vec4) {
+          for (int x = 0; x < NB; x += 4) *reinterpret_cast<float4*>(o + x) = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+          for (int x = 0; x < NB; ++x) o[x] = 0.f;
+        }
+      }
+    }
+    int x = cnt;  // inclusive prefix sum over the wave
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (s < nseg) stab[s].x = sdst[s].x = carry + x - cnt;
+    carry += __shfl(x, kWave - 1);
+  }
+  if (lane == 0) stab[nseg] = make_int4(carry, 0, 0, 0);
+  wave_lds_sync();
+  const int Tw = carry;
+  const int blk = lane >> 2, li = lane & 3;
+  float xa[NP], xb[NP], rsq[NQ], rsq_lo[NQ];
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    xa[u] = P.x_a[4 * u + li];
+    xb[u] = P.x_b[4 * u + li];
+  }
+#pragma unroll
+  for (int v = 0; v < NQ; ++v) {
+    rsq[v] = P.rs_ang[4 * v + li];
+    rsq_lo[v] = P.rs_ang_lo[4 * v + li];
+  }
+  const float eta_a2 = P.eta_ang * 1.4426950408889634f;
+  const int L4 = (Tw + 63) / 64;  // rounds: block blk takes triplets [4 L4 blk, 4 L4 (blk + 1))
+  const int r_lo = 4 * L4 * blk, r_hi = min(r_lo + 4 * L4, Tw);
+  floatx4 acc[NP][NQ];
+#pragma unroll
+  for (int u = 0; u < NP; ++u)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int acc_seg = -1;
+  int4 acc_dst = make_int4(0, 0, 0, 0);  // sdst of acc_seg, read when the block enters it
+  // this block's accumulators into G (a whole segment), its head row (the
+  // last piece of a segment begun in an earlier range) or its tail row
+  // (open at the end of the range)
+  auto flush = [&](bool open) {
+    if (open || acc_dst.x < r_lo) {
+      float4* o4 = reinterpret_cast<float4*>((open ? tail : head) + blk * NB);
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+          o4[((4 * v + li) * NT + 4 * u) / 4] = make_float4(acc[u][v][0], acc[u][v][1], acc[u][v][2], acc[u][v][3]);
+      if (open) tseg[blk] = acc_seg;
+      else hseg[blk] = acc_seg;
+      return;
+    }
+    float* dst = G + (int64_t)(((uint64_t)(uint32_t)acc_dst.z << 32) | (uint32_t)acc_dst.y);
+    if (vec4) {
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+          *reinterpret_cast<float4*>(dst + (4 * v + li) * NT + 4 * u) =
+              make_float4(acc[u][v][0], acc[u][v][1], acc[u][v][2], acc[u][v][3]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dst[(4 * v + li) * NT + 4 * u + r] = acc[u][v][r];
+    }
+  };
+  // one triplet of this block, broadcast from quad lane R: flush on a new
+  // segment, then the lane's factors into the MFMA
+  auto substep = [&](auto rc, const float4& geo, float f2, int sg) {
+    constexpr int R = decltype(rc)::value;
+    const float4 q4 = make_float4(quad_bcast<R>(geo.x), quad_bcast<R>(geo.y), quad_bcast<R>(geo.z),
+                                  quad_bcast<R>(geo.w));
+    const float fr = quad_bcast<R>(f2);
+    const int sr = quad_bcast<R>(sg);
+    if (sr >= 0 && sr != acc_seg) {  // the same in the block's four lanes
+      if (acc_seg >= 0) flush(false);
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc_seg = sr;
+      acc_dst = sdst[sr];
+    }
+    float x[NP], A[NP], Rq[NQ];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) x[u] = fmaf(q4.x, xa[u], fmaf(q4.y, xb[u], P.x_c));
+    ipow_sel<(ZC > 0 ? ZC : 0), NP>(x, P.zeta, A);
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) {
+      const float dq = (q4.z - rsq[v]) + (q4.w - rsq_lo[v]);
+      Rq[v] = fexp2(-eta_a2 * dq * dq) * fr;
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int v = 0; v < NQ; ++v) acc[u][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(A[u], Rq[v], acc[u][v], 0, 0, 0);
+  };
+  // the segment of triplet r_lo: the last one starting at or before it
+  int cur = 0;
+  if (r_lo < r_hi) {
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (stab[mid].x <= r_lo) lo = mid;
+      else hi = mid;
+    }
+    cur = lo;
+  }
+  int4 ce = stab[cur];
+  int cend = stab[cur + 1].x;
+  float cinv = sinv[cur];
+  for (int it = 0; it < L4; ++it) {
+    const int idx = r_lo + 4 * it + li;
+    float4 geo = make_float4(1.f, 0.f, 0.f, 0.f);
+    float f2 = 0.f;  // past the range: F2 = 0 adds nothing
+    int sg = -1;
+    if (idx < r_hi) {
+      while (idx >= cend) {
+        ++cur;
+        ce = stab[cur];
+        cend = stab[cur + 1].x;
+        cinv = sinv[cur];
+      }
+      const int m = ce.w & 0xffff;
+      int q, r;
+      divmod_small(idx - ce.x, m, cinv, q, r);
+      int j, k;
+      if (ce.w >> 16) {  // one species: the unordered pairs {r, r + q + 1 mod m}
+        int kk = r + q + 1;
+        if (kk >= m) kk -= m;
+        j = ce.y + r;
+        k = ce.y + kk;
+      } else {
+        j = ce.y + q;
+        k = ce.z + r;
+      }
+      const float4 fu = nb.f[j], fv = nb.f[k];
+      const TripGeom tg = triplet_geom(nb.d[j], fu, nb.d[k], fv, P.eps_ang);
+      geo = make_float4(tg.c, tg.ssm, tg.rbar, tg.rbar_lo);
+      f2 = 2.0f * fu.x * fv.x;
+      sg = cur;
+    }
+    substep(std::integral_constant<int, 0>{}, geo, f2, sg);
+    substep(std::integral_constant<int, 1>{}, geo, f2, sg);
+    substep(std::integral_constant<int, 2>{}, geo, f2, sg);
+    substep(std::integral_constant<int, 3>{}, geo, f2, sg);
+  }
+  if (acc_seg >= 0) flush(stab[acc_seg + 1].x > r_hi);
+  wave_lds_sync();
+  // segments split over ranges: head of the range that ends them plus the
+  // tails of the ranges before, in range order (four bins per lane)
+  const float4* head4 = reinterpret_cast<const float4*>(head);
+  const float4* tail4 = reinterpret_cast<const float4*>(tail);
+  for (int x = lane; x < 16 * NB / 4; x += kWave) {
+    const int b = x / (NB / 4), bin4 = x - b * (NB / 4);
+    const int sgm = hseg[b];
+    if (sgm < 0) continue;
+    int b0 = b;
+    while (b0 > 0 && tseg[b0 - 1] == sgm) --b0;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int bb = b0; bb < b; ++bb) {
+      const float4 t = tail4[bb * (NB / 4) + bin4];
+      v.x += t.x;
+      v.y += t.y;
+      v.z += t.z;
+      v.w += t.w;
+    }
+    const float4 hd = head4[b * (NB / 4) + bin4];
+    v.x += hd.x;
+    v.y += hd.y;
+    v.z += hd.z;
+    v.w += hd.w;
+    const int4 ds = sdst[sgm];
+    float* o = G + (int64_t)(((uint64_t)(uint32_t)ds.z << 32) | (uint32_t)ds.y) + 4 * bin4;
+    if (vec4) {
+      *reinterpret_cast<float4*>(o) = v;
+    } else {
+      o[0] = v.x;
+      o[1] = v.y;
+      o[2] = v.z;
+      o[3] = v.w;
+    }
+  }
+}
+
+// Dynamic LDS of k_desc_adj_packed: the lambda rows, each [radial S n_rad,
+// padded to a multiple of 4][angular blocks].
+__host__ __device__ inline int packed_lam_stride(int S, int n_rad, int NB) {
+  return (S * n_rad + 3) / 4 * 4 + S * (S + 1) / 2 * NB;
+}
+
+// Per-pair energy gradients for kPackAtoms atoms per one-wave block (rows
+// of at most kPackNb entries; k_desc_adj_long takes the others).  Staging
+// and the radial terms take 16 lanes per atom (lane <-> neighbor).  The
+// triplets of the four atoms are numbered as in k_desc_adj, atom after
+// atom, and taken 64 at a time, one per lane, with the same arithmetic.
+// The gradients go to the per-neighbor LDS slots one step at a time, the
+// step counted from the first step of the lane's atom in the chunk: within
+// one such round every lane of an atom is at the same step (distinct j,
+// distinct k), and atoms own disjoint slots, so no two lanes of an add
+// share a slot and the order of all adds is fixed.
+template <int NT, int NRA, bool ONE_SPECIES, int ZC>
+__global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int64_t* __restrict__ offsets,
+                                                        const int32_t* __restrict__ nbr,
+                                                        const int8_t* __restrict__ shift, DescConst P,
+                                                        const float* __restrict__ lambda, float4* __restrict__ pg,
+                                                        int64_t* meta) {
+  static_assert(ZC != kZcBP, "the packed adjoint takes the mBP term");
+  constexpr int NB = NT * NRA;
+  constexpr int kLamPre4 = 4;  // float4 (or four values) of lambda per lane requested before the staging
+  __shared__ PackNb nb;
+  __shared__ float irs[kPackAtoms * kPackNb];
+  __shared__ float gx[kPackAtoms * kPackNb], gy[kPackAtoms * kPackNb], gz[kPackAtoms * kPackNb];
+  extern __shared__ float4 pk_lds[];
+  if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
+  const int64_t i = packed_atom(sys.n_atoms, g);
+  const bool take = i >= 0 && offsets[i + 1] - offsets[i] <= kPackNb;
+  if (!__any(take)) return;
+  const int S = P.S, D = P.D, ang0 = P.n_rad * S;
+  const int Dp = packed_lam_stride(S, P.n_rad, NB), angp = (ang0 + 3) / 4 * 4;
+  float* lam_s = reinterpret_cast<float*>(pk_lds);
+  // this group's lambda row, requested before the staging; with S n_rad a
+  // multiple of 4 the LDS row is the row itself (Dp = D), copied as float4
+  const bool vec4 = (ang0 & 3) == 0;
+  const float* lam = lambda + (take ? i : 0) * (int64_t)D;
+  const float4* lam4 = reinterpret_cast<const float4*>(lam);
+  float4 lp4[kLamPre4];
+#pragma unroll
+  for (int q = 0; q < kLamPre4; ++q) {
+    if (vec4) {
+      const int d4 = l + q * kPackLanes;
+      lp4[q] = (take && 4 * d4 < D) ? lam4[d4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      float c[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int d = l + (4 * q + k) * kPackLanes;
+        c[k] = (take && d < D) ? lam[d] : 0.f;
+      }
+      lp4[q] = make_float4(c[0], c[1], c[2], c[3]);
+    }
+  }
+  stage_packed(nb, irs, i, take, sys, offsets, nbr, shift, P, meta, pg);
+  float* lrow = lam_s + g * Dp;
+  if (take) {
+    if (vec4) {
+      float4* lr4 = reinterpret_cast<float4*>(lrow);
+#pragma unroll
+      for (int q = 0; q < kLamPre4; ++q) {
+        const int d4 = l + q * kPackLanes;
+        if (4 * d4 < D) lr4[d4] = lp4[q];
+      }
+      for (int d4 = l + kLamPre4 * kPackLanes; 4 * d4 < D; d4 += kPackLanes) lr4[d4] = lam4[d4];
+    } else {
+      auto put_lam = [&](int d, float x) { lrow[d < ang0 ? d : d - ang0 + angp] = x; };
+#pragma unroll
+      for (int q = 0; q < kLamPre4; ++q) {
+        const float c[4] = {lp4[q].x, lp4[q].y, lp4[q].z, lp4[q].w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int d = l + (4 * q + k) * kPackLanes;
+          if (d < D) put_lam(d, c[k]);
+        }
+      }
+      for (int d = l + 4 * kLamPre4 * kPackLanes; d < D; d += kPackLanes) put_lam(d, lam[d]);
+    }
+  }
+  wave_lds_sync();
+  const int ng = nb.seg[g][S];
+  // radial: lane <-> neighbor of its group's atom; dE/dd = (dE/dr) d/r
+  const float eta_r2 = P.eta_rad * 1.4426950408889634f;
+  for (int t = l; t < ng; t += kPackLanes) {
+    const int ts = g * kPackNb + t;
+    const float4 u = nb.d[ts], fu = nb.f[ts];
+    const float* lr = lrow + nb_species(fu) * P.n_rad;
+    float gr = 0.f;
+    for (int k = 0; k < P.n_rad; ++k) {
+      const float dr = (u.w - P.rs_rad[k]) + (fu.z - P.rs_rad_lo[k]);
+      const float gk = fexp2(-eta_r2 * dr * dr);
+      gr = fmaf(lr[k] * gk, fmaf(-2.0f * P.eta_rad * dr, fu.x, fu.y), gr);
+    }
+    gx[ts] = gr * u.x;
+    gy[ts] = gr * u.y;
+    gz[ts] = gr * u.z;
+  }
+  // the atoms' triplet counts and first triplets in the wave's numbering
+  int na[kPackAtoms], ts0[kPackAtoms + 1];
+  ts0[0] = 0;
+#pragma unroll
+  for (int a = 0; a < kPackAtoms; ++a) {
+    na[a] = nb.seg[a][S];
+    ts0[a + 1] = ts0[a] + na[a] * (na[a] - 1) / 2;
+  }
+  const int Tw = ts0[kPackAtoms];
+  const int zeta1 = P.zeta - 1;
+  const float zf = (float)P.zeta;
+  const float eta_a2 = P.eta_ang * 1.4426950408889634f;
+  const float sq_eta_a2 = sqrtf(eta_a2);
+  float rs_sc[NRA];
+#pragma unroll
+  for (int q = 0; q < NRA; ++q) rs_sc[q] = P.rs_ang[q] * sq_eta_a2;
+  wave_lds_sync();  // the radial terms are in the slots before the first angular add
+  for (int c0 = 0; c0 < Tw; c0 += kWave) {
+    const int idx = c0 + lane;
+    const bool tk = idx < Tw;
+    const int a = (idx >= ts0[1]) + (idx >= ts0[2]) + (idx >= ts0[3]);
+    int n = na[0], t0a = ts0[0];
+#pragma unroll
+    for (int b = 1; b < kPackAtoms; ++b)
+      if (a == b) {
+        n = na[b];
+        t0a = ts0[b];
+      }
+    int q = 0, j = 0;
+    if (tk) divmod_small(idx - t0a, n, 1.0f / (float)n, q, j);
+    const int step = q + 1;
+    int k = j + step;
+    if (k >= n) k -= n;
+    j += a * kPackNb;
+    k += a * kPackNb;
+    float gjx = 0.f, gjy = 0.f, gjz = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
+    if (tk) {
+      const float4 u = nb.d[j], fu = nb.f[j];
+      const float4 v = nb.d[k], fv = nb.f[k];
+      const float* La = lam_s + a * Dp + angp;
+      if (!ONE_SPECIES) La += pair_block(S, nb_species(fu), nb_species(fv)) * NB;
+      const float4* La4 = reinterpret_cast<const float4*>(La);
+      const float iru = irs[j], irv = irs[k];
+      const TripGeom tg = triplet_geom<false>(u, fu, v, fv, P.eps_ang);
+      const float c = tg.c;
+      const float F2 = 2.0f * fu.x * fv.x;
+      float x[NT], P1[NT], A[NT];
+#pragma unroll
+      for (int p = 0; p < NT; ++p) x[p] = fmaf(c, P.x_a[p], fmaf(tg.ssm, P.x_b[p], P.x_c));
+      ipow_sel<(ZC > 0 ? ZC - 1 : 0), NT>(x, zeta1, P1);
+#pragma unroll
+      for (int p = 0; p < NT; ++p) A[p] = P1[p] * x[p];
+      float R[NRA], dq[NRA];
+      const float rb = tg.rbar * sq_eta_a2;
+#pragma unroll
+      for (int qq = 0; qq < NRA; ++qq) {
+        dq[qq] = rb - rs_sc[qq];
+        R[qq] = fexp2(-dq[qq] * dq[qq]);
+      }
+      float Tq[NRA], U[NT];
+#pragma unroll
+      for (int p = 0; p < NT; ++p) U[p] = 0.f;
+#pragma unroll
+      for (int qq = 0; qq < NRA; ++qq) {
+        float tq = 0.f;
+#pragma unroll
+        for (int p4 = 0; p4 < NT / 4; ++p4) {
+          const float4 l4 = La4[(qq * NT) / 4 + p4];
+          const float lv[4] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            tq = fmaf(lv[e], A[4 * p4 + e], tq);
+            U[4 * p4 + e] = fmaf(lv[e], R[qq], U[4 * p4 + e]);
+          }
+        }
+        Tq[qq] = tq;
+      }
+      float dEdF2 = 0.f, dEdravg = 0.f;
+#pragma unroll
+      for (int qq = 0; qq < NRA; ++qq) {
+        dEdF2 = fmaf(Tq[qq], R[qq], dEdF2);
+        dEdravg = fmaf(Tq[qq] * R[qq], dq[qq], dEdravg);
+      }
+      dEdravg *= -2.0f * P.eta_ang / sq_eta_a2 * F2;
+      float dEdc = 0.f, dEdssm = 0.f;
+#pragma unroll
+      for (int p = 0; p < NT; ++p) {
+        const float gp = U[p] * P1[p];
+        dEdc = fmaf(gp, P.x_a[p], dEdc);
+        dEdssm = fmaf(gp, P.x_b[p], dEdssm);
+      }
+      dEdc *= zf * F2;
+      dEdssm *= zf * F2;
+      const float coef = dEdc - dEdssm * c * frcp(tg.ssm);
+      const float dEdru = 0.5f * dEdravg + dEdF2 * 2.0f * fu.y * fv.x;
+      const float dEdrv = 0.5f * dEdravg + dEdF2 * 2.0f * fu.x * fv.y;
+      const float cu = coef * iru, cv = coef * irv;
+      gjx = cu * (v.x - c * u.x) + dEdru * u.x;
+      gjy = cu * (v.y - c * u.y) + dEdru * u.y;
+      gjz = cu * (v.z - c * u.z) + dEdru * u.z;
+      gkx = cv * (u.x - c * v.x) + dEdrv * v.x;
+      gky = cv * (u.y - c * v.y) + dEdrv * v.y;
+      gkz = cv * (u.z - c * v.z) + dEdrv * v.z;
+    }
+    // rounds of equal step within each atom: lane fl is the atom's first in this chunk
+    const int fl = max(t0a - c0, 0);
+    const int rel = step - __shfl(step, fl);
+    for (int rr = 0; __any(tk && rel >= rr); ++rr) {
+      const bool mine = tk && rel == rr;
+      if (mine) {
+        gx[k] += gkx;
+        gy[k] += gky;
+        gz[k] += gkz;
+      }
+      wave_lds_sync();
+      if (mine) {
+        gx[j] += gjx;
+        gy[j] += gjy;
+        gz[j] += gjz;
+      }
+      wave_lds_sync();
+    }
+  }
+  if (take) {
+    const int64_t e0 = offsets[i];
+    for (int t = l; t < ng; t += kPackLanes) {
+      const int ts = g * kPackNb + t;
+      pg[e0 + nb_entry(nb.f[ts])] = make_float4(gx[ts], gy[ts], gz[ts], 0.f);
+    }
+  }
+}
+
 // F_k = sum over entries e of row k of (pg[e] - pg[rev[e]]).  Sixteen lanes
 // per atom take the row's entries round robin; the partial sums are combined
 // by a fixed xor-shuffle tree, so the result does not depend on scheduling.
@@ -1413,14 +2204,22 @@ __global__ void __launch_bounds__(256) k_force_gather(int64_t N, const int64_t* 
 // launchers
 // ---------------------------------------------------------------------------
 
+// The packed passes take the mBP term, with their LDS within 48 KB.
+bool packed_supported(const DescConst& P) {
+  if (P.kind == NN_DESC_BP) return false;
+  const int NB = P.n_theta * P.n_rs_ang;
+  const size_t adj = sizeof(float) * kPackAtoms * packed_lam_stride(P.S, P.n_rad, NB);
+  return packed_fwd_lds(P.S, NB) <= 48 * 1024 && adj <= 48 * 1024;
+}
+
 // Waves per atom: two when the atoms alone would leave the SIMDs with few
 // waves to switch between, one otherwise.
-LaunchPlan plan_default(int64_t n_atoms, int n_species, int64_t capacity) {
+LaunchPlan plan_default(int64_t n_atoms, const DescConst& P, int64_t capacity) {
   const int w = n_atoms <= 16384 ? 2 : 1;
   LaunchPlan plan{w, w, 0};
   // several species and short rows (small molecules): one wave per atom, so
   // that the forward and tangent passes take one MFMA block per species pair
-  if (n_species > 1 && n_atoms > 0 && capacity <= 24 * n_atoms) plan.wpa_fwd = 1;
+  if (P.S > 1 && n_atoms > 0 && capacity <= 24 * n_atoms) plan.wpa_fwd = 1;
   return plan;
 }
 
@@ -1431,9 +2230,25 @@ static void launch_fwd_w(const nn_system& sys, const nn_nlist& nl, const DescCon
                      sys, nl.offsets, nl.nbr, nl.shift, P, G, nl.meta, one, nl.order);
 }
 
+// The packed forward (atoms with rows of at most kPackNb entries) and the
+// one-atom pass over the longer rows.
+template <int NT, int NRA, int ZC>
+static void launch_fwd_packed(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G,
+                              IdentityGroup one, hipStream_t s) {
+  hipLaunchKernelGGL((k_desc_fwd_packed<NT, NRA, ZC>), dim3(packed_grid(sys.n_atoms)), dim3(64),
+                     packed_fwd_lds(P.S, NT * NRA), s, sys, nl.offsets, nl.nbr, nl.shift, P, G, nl.meta);
+  hipLaunchKernelGGL((k_desc_fwd_long<NT, NRA, ZC>), dim3((unsigned)((sys.n_atoms + kWave - 1) / kWave)), dim3(64), 0,
+                     s, sys, nl.offsets, nl.nbr, nl.shift, P, G, nl.meta, one, nl.order);
+}
+
 template <int NT, int NRA>
 static void launch_fwd_t(const nn_system& sys, const nn_nlist& nl, const DescConst& P, float* G, IdentityGroup one,
                          int wpa, hipStream_t s) {
+  if (wpa == 0 && packed_supported(P)) {
+    if (P.zeta == 50) launch_fwd_packed<NT, NRA, 50>(sys, nl, P, G, one, s);
+    else launch_fwd_packed<NT, NRA, 0>(sys, nl, P, G, one, s);
+    return;
+  }
   if (P.kind == NN_DESC_BP) {
     if (wpa == 4) launch_fwd_w<NT, NRA, 4, kZcBP>(sys, nl, P, G, one, s);
     else if (wpa == 2) launch_fwd_w<NT, NRA, 2, kZcBP>(sys, nl, P, G, one, s);
@@ -1482,9 +2297,25 @@ static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescCon
                      s, sys, nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta, nl.order);
 }
 
+template <int NT, int NRA, bool ONE, int ZC>
+static void launch_adj_packed(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam,
+                              float4* pg, hipStream_t s) {
+  const size_t lds = sizeof(float) * kPackAtoms * packed_lam_stride(P.S, P.n_rad, NT * NRA);
+  hipLaunchKernelGGL((k_desc_adj_packed<NT, NRA, ONE, ZC>), dim3(packed_grid(sys.n_atoms)), dim3(64), lds, s, sys,
+                     nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta);
+  const size_t lds1 = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
+  hipLaunchKernelGGL((k_desc_adj_long<NT, NRA, ONE, ZC>), dim3((unsigned)((sys.n_atoms + kWave - 1) / kWave)),
+                     dim3(64), lds1, s, sys, nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta, nl.order);
+}
+
 template <int NT, int NRA, bool ONE>
 static void launch_adj_o(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                          int wpa, hipStream_t s) {
+  if (wpa == 0 && packed_supported(P)) {
+    if (P.zeta == 50) launch_adj_packed<NT, NRA, ONE, 50>(sys, nl, P, lam, pg, s);
+    else launch_adj_packed<NT, NRA, ONE, 0>(sys, nl, P, lam, pg, s);
+    return;
+  }
   if (P.kind == NN_DESC_BP) {
     if (wpa == 4) launch_adj_w<NT, NRA, ONE, 4, kZcBP>(sys, nl, P, lam, pg, s);
     else if (wpa == 2) launch_adj_w<NT, NRA, ONE, 2, kZcBP>(sys, nl, P, lam, pg, s);

@@ -1,7 +1,7 @@
 """Every launch plan against the FP64 oracle.
 
-A plan (waves per atom of the descriptor forward and adjoint passes, waves
-per MLP tile) changes only the order of some sums, so each one must meet the
+A plan (waves per atom of the descriptor forward and adjoint passes, 0 for
+the packed passes, waves per MLP tile) changes only the order of some sums, so each one must meet the
 same bars; NNPOT_PLAN forces one on every call.  One-species bulk, a
 2-species bulk and the 4-species cluster batch cover the one-species,
 several-species and pair-block forward paths."""
@@ -18,7 +18,7 @@ from helpers import E_TOL, F_TOL
 
 pytestmark = pytest.mark.gpu
 
-PLANS = list(itertools.product((1, 2, 4), (1, 2, 4), (4, 8)))
+PLANS = list(itertools.product((0, 1, 2, 4), (0, 1, 2, 4), (4, 8)))
 _cache = {}
 
 
