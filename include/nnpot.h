@@ -306,26 +306,51 @@ nn_status nn_energy_forces_noalloc(const nn_system* sys, const nn_nlist* nl, con
 /*
  * Launch tuning (the tiles of the batching step): times the launch variants
  * of this workload's passes -- waves per atom of the descriptor forward and
- * adjoint passes (1, 2, 4) and waves per MLP tile (4, 8) -- on `stream`,
- * and keeps the fastest for workloads of the same shape class (atom count
- * within a factor of two, list entries per atom, descriptor sizes, MLP
- * widths and MLP mode) in a process-wide table that nn_energy_forces and
- * nn_energy_forces_grad then use; without an entry they use fixed rules.
- * Needs a valid list (nn_build_neighbors) and the nn_energy_forces
- * workspace; overwrites the workspace's descriptors and lambda.  Blocks
- * until the timings are done, so it must not be called while the stream is
- * being captured into a graph.  A plan changes only the order of some sums:
- * results stay bitwise reproducible for a fixed table.  plan_out [host]
- * (nullable) receives {waves/atom forward, waves/atom adjoint, waves/MLP tile}.
- * The environment variable NNPOT_PLAN="f,a,m" (f, a in {1, 2, 4}; m in
- * {4, 8}) overrides every plan, tuned or default, while it is set: a way to
- * run each launch variant in tests.
+ * adjoint passes (1, 2, 4, or 0: the packed passes, four atoms of at most
+ * 32 list entries per wave, mBP term) and waves per MLP tile (4, 8) -- on
+ * `stream`, and keeps the fastest for workloads of the same shape class
+ * (atom count within a factor of two, list entries per atom, descriptor
+ * sizes, MLP widths and MLP mode) in a process-wide table that
+ * nn_energy_forces and nn_energy_forces_grad then use; without an entry
+ * they use fixed rules.  Needs a valid list (nn_build_neighbors) and the
+ * nn_energy_forces workspace; overwrites the workspace's descriptors and
+ * lambda.  Blocks until the timings are done, so it must not be called while
+ * the stream is being captured into a graph.  A plan changes only the order
+ * of some sums: results stay bitwise reproducible for a fixed table.
+ * plan_out [host] (nullable) receives {waves/atom forward, waves/atom
+ * adjoint, waves/MLP tile}.
+ * Environment:
+ *   NNPOT_PLAN="f,a,m" (f, a in {0, 1, 2, 4}; m in {4, 8}) overrides every
+ *     plan, tuned or default, while it is set: a way to run each launch
+ *     variant in tests;
+ *   NN_AUTOTUNE_CACHE=<file> keeps the table in a file across processes:
+ *     read on the process's first lookup, rewritten (merged) after each
+ *     nn_autotune.  One JSON object per line of an array,
+ *       {"key": [n_log2, row4, S, n_theta, n_rs_ang, n_rad, h1, h2, mode],
+ *        "plan": [f, a, m]}
+ *     with n_log2 the bit length of the atom count, row4 =
+ *     (ceil(capacity / atoms) + 2) / 4, h1, h2 the first two hidden widths of
+ *     species 0 and mode 0 / 1 / 2 for FP32 / BF16 / split BF16.  Plans are
+ *     tuned on one GPU model: keep one file per machine type.  Best effort:
+ *     a file that cannot be read or written only costs speed.
  */
 nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
                       int32_t flags, void* ws, size_t ws_bytes, void* stream, int32_t* plan_out);
 
-/* Forgets every plan nn_autotune stored. */
+/* Forgets every plan in the process's table, including those read from
+ * NN_AUTOTUNE_CACHE (the file is left as it is and not read again by this
+ * process). */
 void nn_autotune_reset(void);
+
+/*
+ * The launch plan nn_energy_forces would use for these arguments (NNPOT_PLAN,
+ * else the table -- tuned or read from NN_AUTOTUNE_CACHE --, else the fixed
+ * rules) into plan_out [host] [3].  Host only: reads no device memory and
+ * enqueues nothing.  Errors: NN_E_INVALID / NN_E_UNSUPPORTED for arguments
+ * nn_energy_forces would reject.
+ */
+nn_status nn_launch_plan(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
+                         int32_t flags, int32_t* plan_out);
 
 /*
  * Backward of E_struct and F with respect to positions and weights, given

@@ -6,8 +6,10 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 
 #include <algorithm>
+#include <string>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -53,6 +55,73 @@ struct PlanKey {
 static std::mutex g_pmu;
 static std::map<PlanKey, LaunchPlan> g_plans;
 
+// NN_AUTOTUNE_CACHE=<file>: the table persists across processes.  The file
+// is read on the first lookup or tuning of the process and rewritten after
+// each nn_autotune (its entries merged with the process's, the process's
+// winning; written to a temporary file and renamed into place).  One entry
+// per line of a JSON array:
+//   {"key": [n_log2, row4, S, n_theta, n_rs_ang, n_rad, h1, h2, mode], "plan": [f, a, m]}
+// Lines that do not parse, or whose plan is out of range, are skipped.  The
+// cache is best effort: a file that cannot be read or written changes nothing
+// but the speed.
+static bool g_cache_loaded = false;
+
+static const char* cache_path() {
+  const char* e = getenv("NN_AUTOTUNE_CACHE");
+  return (e && *e) ? e : nullptr;
+}
+
+static bool plan_valid(const LaunchPlan& q) {
+  auto w = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
+  return w(q.wpa_fwd) && w(q.wpa_adj) && (q.mlp_waves == 0 || q.mlp_waves == 4 || q.mlp_waves == 8);
+}
+
+static void cache_read(const char* path, std::map<PlanKey, LaunchPlan>& into, bool overwrite) {
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    PlanKey k{};
+    LaunchPlan q{};
+    const int n = sscanf(line, " {\"key\": [%d, %d, %d, %d, %d, %d, %d, %d, %d], \"plan\": [%d, %d, %d]}", &k.n_log2,
+                         &k.row4, &k.S, &k.nt, &k.nra, &k.n_rad, &k.h1, &k.h2, &k.mode, &q.wpa_fwd, &q.wpa_adj,
+                         &q.mlp_waves);
+    if (n != 12 || !plan_valid(q)) continue;
+    if (overwrite) into[k] = q;
+    else into.emplace(k, q);
+  }
+  fclose(f);
+}
+
+static void cache_load_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  if (const char* path = cache_path()) cache_read(path, g_plans, false);
+}
+
+static void cache_store_locked() {
+  const char* path = cache_path();
+  if (!path) return;
+  std::map<PlanKey, LaunchPlan> all;
+  cache_read(path, all, true);  // entries other processes wrote meanwhile
+  for (const auto& kv : g_plans) all[kv.first] = kv.second;
+  const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  bool ok = fprintf(f, "[\n") > 0;
+  size_t left = all.size();
+  for (const auto& kv : all) {
+    const PlanKey& k = kv.first;
+    const LaunchPlan& q = kv.second;
+    ok = ok && fprintf(f, "{\"key\": [%d, %d, %d, %d, %d, %d, %d, %d, %d], \"plan\": [%d, %d, %d]}%s\n", k.n_log2,
+                       k.row4, k.S, k.nt, k.nra, k.n_rad, k.h1, k.h2, k.mode, q.wpa_fwd, q.wpa_adj, q.mlp_waves,
+                       --left ? "," : "") > 0;
+  }
+  ok = ok && fprintf(f, "]\n") > 0;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || rename(tmp.c_str(), path) != 0) remove(tmp.c_str());
+}
+
 static PlanKey plan_key(int64_t n_atoms, int64_t capacity, const DescConst& P, const nn_model* model, int mode) {
   PlanKey k{};
   int b = 0;
@@ -89,6 +158,7 @@ static LaunchPlan plan_for(int64_t n_atoms, int64_t capacity, const DescConst& P
   if (forced_plan(&forced)) return forced;
   const PlanKey k = plan_key(n_atoms, capacity, P, model, mode);
   std::lock_guard<std::mutex> g(g_pmu);
+  cache_load_locked();
   auto it = g_plans.find(k);
   return it != g_plans.end() ? it->second : plan_default(n_atoms, P, capacity);
 }
@@ -937,7 +1007,9 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     if ((st = check_launch("nn_autotune"))) return st;
     if (!destroyed) return fail(NN_E_HIP, "nn_autotune: event release failed");
     std::lock_guard<std::mutex> g(g_pmu);
+    cache_load_locked();
     g_plans[plan_key(N, nl->capacity, P, model, mode)] = best;
+    cache_store_locked();
   }
   if (plan_out) {
     plan_out[0] = best.wpa_fwd;
@@ -950,6 +1022,25 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
 void nn_autotune_reset(void) {
   std::lock_guard<std::mutex> g(g_pmu);
   g_plans.clear();
+  g_cache_loaded = true;  // the cache file is not read again by this process
+}
+
+nn_status nn_launch_plan(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p, const nn_model* model,
+                         int32_t flags, int32_t* plan_out) {
+  nn_status st = check_system(sys);
+  if (st) return st;
+  if ((st = check_nlist(nl, sys, false))) return st;
+  DescConst P;
+  if ((st = make_desc_const(p, &P))) return st;
+  if ((st = check_model(model, P))) return st;
+  if ((st = check_mode(model, flags))) return st;
+  if (!plan_out) return fail(NN_E_INVALID, "plan_out is NULL");
+  const int mode = (flags & NN_BF16X3_MLP) ? 2 : (flags & NN_BF16_MLP) ? 1 : 0;
+  const LaunchPlan q = plan_for(sys->n_atoms, nl->capacity, P, model, mode);
+  plan_out[0] = q.wpa_fwd;
+  plan_out[1] = q.wpa_adj;
+  plan_out[2] = q.mlp_waves;
+  return NN_OK;
 }
 
 nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const nn_mbp_params* p,

@@ -2213,13 +2213,19 @@ bool packed_supported(const DescConst& P) {
 }
 
 // Waves per atom: two when the atoms alone would leave the SIMDs with few
-// waves to switch between, one otherwise.
+// waves to switch between, one otherwise; the packed passes for short rows
+// (small molecules: at most 24 list entries per atom on average).
 LaunchPlan plan_default(int64_t n_atoms, const DescConst& P, int64_t capacity) {
   const int w = n_atoms <= 16384 ? 2 : 1;
   LaunchPlan plan{w, w, 0};
-  // several species and short rows (small molecules): one wave per atom, so
-  // that the forward and tangent passes take one MFMA block per species pair
-  if (P.S > 1 && n_atoms > 0 && capacity <= 24 * n_atoms) plan.wpa_fwd = 1;
+  const bool short_rows = n_atoms > 0 && capacity <= 24 * n_atoms;
+  if (short_rows && packed_supported(P)) {
+    plan.wpa_fwd = plan.wpa_adj = 0;
+  } else if (short_rows && P.S > 1) {
+    // several species: one wave per atom, so that the forward and tangent
+    // passes take one MFMA block per species pair
+    plan.wpa_fwd = 1;
+  }
   return plan;
 }
 

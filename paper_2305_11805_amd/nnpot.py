@@ -84,7 +84,8 @@ class nn_langevin(C.Structure):
 _lib = None
 EXPORTS = ("nn_descriptor_dim", "nn_workspace_size", "nn_count_neighbors", "nn_build_neighbors", "nn_descriptors",
            "nn_energy_forces", "nn_energy_forces_noalloc", "nn_energy_forces_grad", "nn_energy_forces_qeq",
-           "nn_energy_forces_qeq_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset", "nn_check",
+           "nn_energy_forces_qeq_grad", "nn_descriptor_tangent", "nn_md_langevin", "nn_loss", "nn_autotune", "nn_autotune_reset",
+           "nn_launch_plan", "nn_check",
            "nn_last_error", "nn_timing", "nn_timing_read",
            "nn_jacobian_stride")
 STAGES = ("neighbors", "species", "weights", "desc_fwd", "mlp", "energy", "desc_adj", "force_gather", "desc_jac",
@@ -129,6 +130,8 @@ def lib():
         L.nn_autotune.argtypes = [P, P, P, P, I32, P, SZ, P, P]
         L.nn_autotune_reset.restype = None
         L.nn_autotune_reset.argtypes = []
+        L.nn_launch_plan.restype = I32
+        L.nn_launch_plan.argtypes = [P, P, P, P, I32, P]
         L.nn_check.restype = I32
         L.nn_check.argtypes = [P, P, C.POINTER(I64)]
         L.nn_last_error.restype = C.c_char_p
@@ -255,6 +258,14 @@ def nn_autotune(sys, nl, params, model, flags, ws, stream=None) -> tuple:
 
 def nn_autotune_reset():
     lib().nn_autotune_reset()
+
+
+def nn_launch_plan(sys, nl, params, model, flags) -> tuple:
+    """The plan nn_energy_forces would use (forced, tuned or cached, else
+    the fixed rules): (waves/atom forward, waves/atom adjoint, waves/MLP tile)."""
+    plan = (C.c_int32 * 3)()
+    _ok(lib().nn_launch_plan(C.byref(sys), C.byref(nl), C.byref(params), C.byref(model), flags, plan))
+    return tuple(int(v) for v in plan)
 
 
 def nn_check(nl: nn_nlist, stream=None) -> int:
@@ -457,6 +468,11 @@ class Potential:
         f = self.flags if flags is None else flags
         self.evals += 1
         return nn_autotune(self.sys, self.nl, self.params, self.dmodel.struct, f, self.ws)
+
+    def launch_plan(self, flags: Optional[int] = None):
+        """The plan energy_forces would use now (nn_launch_plan)."""
+        f = self.flags if flags is None else flags
+        return nn_launch_plan(self.sys, self.nl, self.params, self.dmodel.struct, f)
 
     def energy_forces(self, flags: Optional[int] = None, forces: bool = True, mem_budget: Optional[int] = None):
         f = self.flags if flags is None else flags

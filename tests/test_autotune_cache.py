@@ -1,0 +1,108 @@
+"""NN_AUTOTUNE_CACHE and nn_launch_plan on the host (no GPU: nn_launch_plan
+reads no device memory, so the structs carry placeholder device pointers).
+
+Each case runs in a fresh interpreter, since the library reads the cache
+file once per process.  The key follows the header: bit length of the atom
+count, (ceil(capacity / atoms) + 2) / 4, S, n_theta, n_rs_ang, n_rad, the
+first two hidden widths and the MLP mode.
+"""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_2305_11805_amd import nnpot
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+QUERY = r"""
+import ctypes as C, json, sys
+from paper_2305_11805_amd import nnpot, synth
+w = synth.config(0)
+s, keep = nnpot.make_params(w.params)
+a = [C.c_void_p(0x10000 * k) for k in range(1, 16)]
+sysd = nnpot.nn_system(192, 16, a[0].value, a[1].value, a[2].value, a[3].value, a[4].value)
+nl = nnpot.nn_nlist(4000, a[5].value, a[6].value, a[7].value, a[8].value, a[9].value, a[10].value, None, 4.6)
+m = nnpot.nn_model()
+m.n_species = len(w.model)
+for sp, (widths, acts, Ws, bs) in enumerate(w.model):
+    q = m.mlp[sp]
+    q.n_layers = len(Ws)
+    for l, wd in enumerate(widths):
+        q.width[l] = wd
+    for l, act in enumerate(acts):
+        q.act[l] = nnpot.ACT[act]
+    for l in range(len(Ws)):
+        q.W[l] = a[11].value
+        q.b[l] = a[12].value
+out = {"plan": nnpot.nn_launch_plan(sysd, nl, s, m, 0)}
+if len(sys.argv) > 1 and sys.argv[1] == "reset":
+    nnpot.nn_autotune_reset()
+    out["after_reset"] = nnpot.nn_launch_plan(sysd, nl, s, m, 0)
+print(json.dumps(out))
+"""
+
+# config 0: 192 atoms (bit length 8), capacity 4000 (row4 = (21 + 2) / 4 = 5),
+# 4 species, 8 x 4 angular bins, 16 radial bins, MLP 64-32, FP32
+KEY = [8, 5, 4, 8, 4, 16, 64, 32, 0]
+
+
+def query(env_extra, *args):
+    env = {k: v for k, v in os.environ.items() if k not in ("NN_AUTOTUNE_CACHE", "NNPOT_PLAN")}
+    env.update(env_extra)
+    env["PYTHONPATH"] = ROOT + os.pathsep + env.get("PYTHONPATH", "")
+    r = subprocess.run([sys.executable, "-c", QUERY, *args], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(nnpot.LIB_PATH):
+        pytest.skip("libnnpot.so is not built")
+
+
+def write(path, lines):
+    with open(path, "w") as f:
+        f.write("[\n" + ",\n".join(lines) + "\n]\n")
+
+
+def test_default_rules_without_cache():
+    # short rows (capacity <= 24 per atom) with the mBP term: the packed passes
+    assert query({})["plan"] == [0, 0, 0]
+
+
+def test_cached_plan_is_used(tmp_path):
+    path = str(tmp_path / "plans.json")
+    write(path, ['{"key": %s, "plan": [2, 4, 8]}' % json.dumps(KEY)])
+    assert query({"NN_AUTOTUNE_CACHE": path})["plan"] == [2, 4, 8]
+
+
+def test_bad_lines_are_skipped(tmp_path):
+    path = str(tmp_path / "plans.json")
+    other = list(KEY)
+    other[0] = 17
+    write(path, ['{"key": %s, "plan": [3, 1, 4]}' % json.dumps(KEY),        # 3 waves per atom: not a plan
+                 'not json at all',
+                 '{"key": %s, "plan": [1, 1, 4]}' % json.dumps(other),      # another shape class
+                 '{"key": %s, "plan": [1, 2, 4]}' % json.dumps(KEY)])
+    assert query({"NN_AUTOTUNE_CACHE": path})["plan"] == [1, 2, 4]
+
+
+def test_missing_file_changes_nothing(tmp_path):
+    assert query({"NN_AUTOTUNE_CACHE": str(tmp_path / "absent.json")})["plan"] == [0, 0, 0]
+
+
+def test_forced_plan_wins_over_cache(tmp_path):
+    path = str(tmp_path / "plans.json")
+    write(path, ['{"key": %s, "plan": [2, 4, 8]}' % json.dumps(KEY)])
+    assert query({"NN_AUTOTUNE_CACHE": path, "NNPOT_PLAN": "1,2,4"})["plan"] == [1, 2, 4]
+
+
+def test_reset_forgets_cached_plans(tmp_path):
+    path = str(tmp_path / "plans.json")
+    write(path, ['{"key": %s, "plan": [2, 4, 8]}' % json.dumps(KEY)])
+    out = query({"NN_AUTOTUNE_CACHE": path}, "reset")
+    assert out["plan"] == [2, 4, 8] and out["after_reset"] == [0, 0, 0]

@@ -41,3 +41,36 @@ def test_autotuned_plan_matches_oracle(name, flags):
     nnpot.nn_autotune_reset()
     Es3, _, F3 = pot.energy_forces()
     assert torch.equal(Es3, Es0) and torch.equal(F3, F0)
+
+
+def test_autotune_writes_the_cache_file(tmp_path, monkeypatch):
+    """nn_autotune with NN_AUTOTUNE_CACHE set writes its plan under the
+    workload's key; a fresh process (host only) then reads it back through
+    nn_launch_plan."""
+    import json
+    import os
+    import subprocess
+    import sys
+    path = str(tmp_path / "plans.json")
+    monkeypatch.setenv("NN_AUTOTUNE_CACHE", path)
+    w = synth.config(0)
+    s, p = w.system, w.params
+    nnpot.nn_autotune_reset()
+    pot = nnpot.Potential(s, p, w.model, capacity=4000)
+    pot.build_neighbors()
+    plan = list(pot.autotune())
+    assert pot.launch_plan() == tuple(plan)
+    entries = json.load(open(path))
+    n = int(s.n_atoms)
+    key = [n.bit_length(), ((4000 + n - 1) // n + 2) // 4, p.n_species, p.n_theta,
+           p.n_rs_ang, p.n_rad, 64, 32, 0]
+    assert {"key": key, "plan": plan} in entries, (entries, key, plan)
+    nnpot.nn_autotune_reset()
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    from test_autotune_cache import QUERY
+    env = dict(os.environ, PYTHONPATH=os.path.dirname(here) + os.pathsep + os.environ.get("PYTHONPATH", ""))
+    env.pop("NNPOT_PLAN", None)
+    r = subprocess.run([sys.executable, "-c", QUERY], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert json.loads(r.stdout.strip().splitlines()[-1])["plan"] == plan
