@@ -981,7 +981,7 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     a.D = P.D;
     const int h1 = model->mlp[0].width[1], h2 = model->mlp[0].width[2];
     float t_best = -1.f;
-    const bool pk = packed_supported(P);
+    const bool pk = packed_supported(P) && nl->capacity <= 48 * N;  // rows short enough for any to be packed
     for (int w : {0, 1, 2, 4}) {  // descriptor forward
       if (w == 0 && !pk) continue;
       const float t = time_of([&] { launch_desc_fwd(*sys, *nl, P, L.G, IdentityGroup{}, w, s); });

@@ -238,6 +238,8 @@ __device__ void prep_flags(const int64_t* __restrict__ atom_ptr, int32_t B, int6
   } else {
     flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
   }
+  flag[2] = 0;  // the generic passes' predicate when the cluster passes are tried (set by k_cl_decide)
+  flag[3] = 0;  // structures the cluster passes could not take
   *cursor = 0;  // overflow area of the counting pass's row keys
 }
 
@@ -1064,8 +1066,9 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
                                                 const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
                                                 int8_t* __restrict__ shift, int32_t* __restrict__ rev,
                                                 const double* __restrict__ pos, double* __restrict__ ref_pos,
-                                                const int32_t* __restrict__ order, int64_t* meta, const int32_t* flag) {
-  if (!flag[1]) return;
+                                                const int32_t* __restrict__ order, int64_t* meta, const int32_t* flag,
+                                                const int32_t* gflag) {
+  if (!flag[1] || !*gflag) return;
   constexpr int kApw = kWave / LPA;  // atoms per wave
   const int lane = threadIdx.x, sl = lane % LPA;
   int64_t slot = (int64_t)blockIdx.x * kApw + lane / LPA;
@@ -1108,6 +1111,118 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
 }
 
 // ---------------------------------------------------------------------------
+// Cluster passes: batches of small molecules
+//
+// flag[0]: (re)build; flag[1]: the list fits (emit); flag[2]: the generic
+// passes run; flag[3]: structures the cluster passes cannot take.
+// ---------------------------------------------------------------------------
+
+constexpr int kClusterMax = 64;  // atoms of a structure the cluster passes take (one per lane)
+
+// One wave per structure.  A structure of at most 64 atoms with no periodic
+// direction has no images: lane i tests every j != i of its structure with
+// the same FP64 displacement and inclusion test as the generic passes, and
+// its row is the bit mask of the j inside the radius (ascending j is the
+// canonical row order).  counts[i] = its length; with masks, the mask is
+// kept for the emit pass.  Any other structure adds to flag[3] (the generic
+// passes then build the whole list).  Non-finite positions are reported as
+// in the generic binning (the list is then not valid).
+__global__ void __launch_bounds__(64) k_cl_count(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
+                                                 const uint8_t* __restrict__ pbc, double r2max,
+                                                 int64_t* __restrict__ counts, int64_t* __restrict__ masks,
+                                                 int64_t* meta, int32_t* flag) {
+  if (!flag[0]) return;
+  __shared__ double px[kClusterMax], py[kClusterMax], pz[kClusterMax];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int64_t a0 = atom_ptr[c], n = atom_ptr[c + 1] - a0;
+  const uint8_t* pb = pbc + 3 * (int64_t)c;
+  if (n > kClusterMax || pb[0] || pb[1] || pb[2]) {
+    if (lane == 0) atomicAdd(&flag[3], 1);
+    return;
+  }
+  const bool in = lane < n;
+  double xi[3] = {0.0, 0.0, 0.0};
+  bool fin = true;
+  if (in) {
+    for (int k = 0; k < 3; ++k) xi[k] = pos[3 * (a0 + lane) + k];
+    fin = isfinite(xi[0]) && isfinite(xi[1]) && isfinite(xi[2]);
+    px[lane] = xi[0];
+    py[lane] = xi[1];
+    pz[lane] = xi[2];
+  }
+  if (__any(!fin) && lane == 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrNonFinite);
+  wave_lds_sync();
+  uint64_t m = 0;
+  if (in) {
+#pragma clang fp contract(off)
+    for (int j = 0; j < (int)n; ++j) {
+      if (j == lane) continue;
+      const double dx = px[j] - xi[0], dy = py[j] - xi[1], dz = pz[j] - xi[2];
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      if (d2 < r2max) m |= 1ull << j;
+    }
+    counts[a0 + lane] = fin ? __popcll(m) : 0;
+    if (masks) masks[a0 + lane] = fin ? (int64_t)m : 0;
+  }
+}
+
+// flag[2] = the generic passes run: a (re)build with a structure the
+// cluster passes could not take.  (One thread after the count: a last-block
+// decision inside it would have every block update one counter.)
+__global__ void k_cl_decide(int32_t* flag) { flag[2] = (flag[0] && flag[3] > 0) ? 1 : 0; }
+
+// The rows from the masks (when the list fits and the cluster passes built
+// it): one wave per structure, one row at a time, lane j writing the entry
+// of j at its rank in the row.  The reverse of entry (i -> j) is the entry
+// (j -> i) at the rank of i in row j.  Also the skin reference positions,
+// the identity order, and the list marked valid.
+__global__ void __launch_bounds__(64) k_cl_emit(const int64_t* __restrict__ atom_ptr,
+                                                const int64_t* __restrict__ masks,
+                                                const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
+                                                int8_t* __restrict__ shift, int32_t* __restrict__ rev,
+                                                const double* __restrict__ pos, double* __restrict__ ref_pos,
+                                                int32_t* __restrict__ order, int64_t* meta, const int32_t* flag) {
+  if (!flag[1] || flag[2]) return;
+  __shared__ uint64_t ms[kClusterMax];
+  __shared__ int64_t off[kClusterMax];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int64_t a0 = atom_ptr[c];
+  const int n = (int)(atom_ptr[c + 1] - a0);
+  if (c == 0 && lane == 0) {
+    meta[kMetaValid] = 1;
+    meta[kMetaBuilds] += 1;
+  }
+  const bool in = lane < n;
+  uint64_t mine = 0;
+  int64_t mo = 0;
+  if (in) {
+    const int64_t i = a0 + lane;
+    mine = (uint64_t)masks[i];
+    mo = offsets[i];
+    ms[lane] = mine;
+    off[lane] = mo;
+    if (ref_pos)
+      for (int k = 0; k < 3; ++k) ref_pos[3 * i + k] = pos[3 * i + k];
+    if (order) order[i] = (int32_t)i;
+  }
+  wave_lds_sync();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // lane j: the entry (i -> j) of each row i that holds j, and its reverse
+  // (j -> i) at the rank of i among the bits of j's row
+  char4* sh4 = reinterpret_cast<char4*>(shift);
+  for (int r = 0; r < n; ++r) {
+    const uint64_t mr = ms[r];
+    if (in && ((mr >> lane) & 1)) {
+      const int64_t e = off[r] + __popcll(mr & lt);
+      nbr[e] = (int32_t)(a0 + lane);
+      sh4[e] = make_char4(0, 0, 0, 0);
+      const uint64_t below_r = (r == 0) ? 0ull : (~0ull >> (64 - r));
+      rev[e] = (int32_t)(mo + __popcll(mine & below_r));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
 
@@ -1124,13 +1239,23 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const int64_t N = sys->n_atoms;
   const int32_t B = sys->n_structs;
   const unsigned gN = (unsigned)((N + 255) / 256 > 0 ? (N + 255) / 256 : 1);
-  const bool sep_prep = use_skin || B == 0;  // else the geometry launch does it
+  // batches try the cluster passes first; the generic passes then run only
+  // on their predicate flag[2] (else on the build flag flag[0])
+  const bool try_cl = B > 1 && N > 0;
+  const int32_t* gflag = try_cl ? L.flag + 2 : L.flag;
+  int32_t* gflag_w = const_cast<int32_t*>(gflag);
+  const bool sep_prep = use_skin || B == 0 || try_cl;  // else the geometry launch does it
   if (sep_prep)
     hipLaunchKernelGGL(k_nb_prep, dim3(1), dim3(256), 0, s, sys->atom_ptr, B, N, L.meta, L.flag, L.cursor,
                        use_skin ? 1 : 0);
   if (use_skin && L.nl && L.nl->ref_pos && N > 0)
     hipLaunchKernelGGL(k_skin_check, dim3(gN), dim3(256), 0, s, sys->pos, L.nl->ref_pos, N, 0.25 * skin * skin,
                        L.meta, L.flag, 1);
+  if (try_cl) {
+    hipLaunchKernelGGL(k_cl_count, dim3((unsigned)B), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc,
+                       L.radius * L.radius, L.counts, count_only ? (int64_t*)nullptr : L.key_loc, L.meta, L.flag);
+    hipLaunchKernelGGL(k_cl_decide, dim3(1), dim3(1), 0, s, L.flag);
+  }
   int32_t* order = (count_only || !L.nl) ? (int32_t*)nullptr : L.nl->order;
   if (B == 1 && N <= kOneAtoms) {
     hipLaunchKernelGGL(k_nb_one, dim3(1), dim3(kOneThreads), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc,
@@ -1142,15 +1267,15 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
     if (B > 0)
       hipLaunchKernelGGL(k_nb_geom, dim3(gGeom), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->cell, sys->pbc, B,
                          L.radius, L.geom, L.n_bins, L.bin_count, n_zero, B == 1 ? L.bin_base : (int64_t*)nullptr,
-                         N, L.meta, L.flag, L.cursor, sep_prep ? 0 : 1);
-    if (B != 1) exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, L.flag);
+                         N, L.meta, sep_prep ? gflag_w : L.flag, L.cursor, sep_prep ? 0 : 1);
+    if (B != 1) exclusive_scan_i64(L.n_bins, L.bin_base, B, L.scan_tmp, s, gflag);
     if (N > 0)
       hipLaunchKernelGGL(k_nb_bin, dim3(gN), dim3(256), 0, s, sys->pos, sys->atom_ptr, sys->pbc, B, N, L.geom,
-                         L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.counts, L.meta, L.flag);
-    exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, L.flag, L.bin_base + B);
+                         L.bin_base, L.bin_count, L.atom_bin, L.bin_rank, L.counts, L.meta, gflag);
+    exclusive_scan_i64(L.bin_count, L.bin_start, L.max_bins, L.scan_tmp, s, gflag, L.bin_base + B);
     if (N > 0)
       hipLaunchKernelGGL(k_nb_scatter, dim3(gN), dim3(256), 0, s, N, sys->pos, L.atom_bin, L.bin_rank, L.bin_start,
-                         L.bin_m, L.bin_x, order, L.flag);
+                         L.bin_m, L.bin_x, order, gflag);
   }
   const double r2 = L.radius * L.radius;
   // groups (bins) are known on the device only: a grid-stride loop over them
@@ -1159,11 +1284,11 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
     if (count_only)
       hipLaunchKernelGGL(k_nb_rows<kRowsCount>, dim3(gRows, grp_split(N)), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N,
-                         (uint64_t*)nullptr, 0, (int64_t)0, (int64_t*)nullptr, L.cursor, L.meta, L.flag);
+                         (uint64_t*)nullptr, 0, (int64_t)0, (int64_t*)nullptr, L.cursor, L.meta, gflag);
     else
       hipLaunchKernelGGL(k_nb_rows<kRowsKeys>, dim3(gRows, grp_split(N)), dim3(kGrpThreads), 0, s, sys->atom_ptr,
                          sys->pbc, B, L.geom, L.bin_base, L.bin_start, L.bin_m, L.bin_x, r2, L.counts, N, L.row_keys,
-                         L.kslot, 2 * L.capacity, L.key_loc, L.cursor, L.meta, L.flag);
+                         L.kslot, 2 * L.capacity, L.key_loc, L.cursor, L.meta, gflag);
   }
   const CapacityJob cj{count_only ? (int64_t)INT64_MAX : L.capacity, L.meta, L.flag};
   if (N <= kScanSmall) {
@@ -1184,9 +1309,12 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const unsigned gEmit = nl->order ? (unsigned)((nw + 7) / 8 * 8) : (unsigned)nw;  // whole rounds of the 8 XCDs
   if (lpa == 16)
     hipLaunchKernelGGL(k_nb_emit<16>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
-                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
+                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
   else
     hipLaunchKernelGGL(k_nb_emit<32>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
+  if (try_cl)
+    hipLaunchKernelGGL(k_cl_emit, dim3((unsigned)B), dim3(64), 0, s, sys->atom_ptr, L.key_loc, nl->offsets, nl->nbr,
                        nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
 }
 
