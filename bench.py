@@ -97,7 +97,17 @@ def valid_neighbor_counts(pot, rc):
     return np.bincount(rows[valid], minlength=len(off) - 1)
 
 
-SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp": "mlp.hip", "k_nb": "neighbors.hip"}
+SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp_rows": "mlp_rows.hip", "k_mlp": "mlp.hip",
+           "k_nb": "neighbors.hip"}
+
+
+def mlp_rows_plan(plan, mode, w):
+    """True when the timed MLP is the FP32 row-block kernel (plan value 1 on
+    the widths and descriptor sizes it takes)."""
+    if plan is None or plan[2] != 1 or mode != "fp32":
+        return False
+    widths = w.model[0][0]
+    return len(widths) == 4 and tuple(widths[1:3]) in ((64, 32), (128, 128)) and w.params.dim % 4 == 0
 
 
 def source_hash(kernel="k_desc_adj"):
@@ -168,7 +178,7 @@ def read_pmc_csv(path, counter):
     return out
 
 
-def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernels=("k_desc_adj", "k_desc_fwd", "k_mlp")):
+def ingest_counters(fetch_csv, write_csv, calib_mib, workload, kernels=("k_desc_adj", "k_desc_fwd", "k_mlp_rows")):
     for k in kernels:
         ingest_kernel(fetch_csv, write_csv, calib_mib, workload, k)
 
@@ -182,7 +192,8 @@ def ingest_kernel(fetch_csv, write_csv, calib_mib, workload, kernel):
     # one instantiation for both counters: of those both runs dispatched, the
     # most frequent (the timed steps run one; the launch tuner also runs the
     # others a few times each)
-    names = {name: [k for k, _ in rows if f"nnp::{kernel}" in k] for name, rows in runs.items()}
+    names = {name: [k for k, _ in rows if f"nnp::{kernel}<" in k or f"nnp::{kernel}(" in k]
+             for name, rows in runs.items()}
     both = set(names["FETCH_SIZE"]) & set(names["WRITE_SIZE"])
     if not both:
         raise SystemExit(f"no {kernel} instantiation in both counter runs")
@@ -773,7 +784,7 @@ def headline(args):
         step()
     torch.cuda.synchronize()
     nnpot.nn_check(pot.nl)
-    plan = None if args.no_autotune else pot.autotune()  # launch plan for this shape class (untimed)
+    plan = pot.launch_plan() if args.no_autotune else pot.autotune()  # launch plan for this shape class (untimed)
     restart()
     for _ in range(max(args.warmup, 1)):
         step()
@@ -919,15 +930,17 @@ def headline(args):
         e = {"avg_launch_ms": round(ms_k, 5), "algorithmic_flops_per_launch": fl,
              "tflops": round(fl / (ms_k / 1e3) / 1e12, 3), "peak_mfma_tflops": peak,
              "frac_mfma": round(fl / (ms_k / 1e3) / 1e12 / peak, 4)}
-        b = hbm_bytes("k_mlp")
+        mlp_name = "k_mlp_rows" if mlp_rows_plan(plan, args.mode, w) else "k_mlp"
+        b = hbm_bytes(mlp_name)
         if b is not None:
             e["hbm_bytes_per_launch"] = b
             e["hbm_gbs"] = round(b / (ms_k / 1e3) / 1e9, 1)
-        kern["k_mlp"] = e
+        kern[mlp_name] = e
     cfg = {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
            "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed,
-           "launch_plan": None if plan is None else {"waves_per_atom_fwd": plan[0], "waves_per_atom_adj": plan[1],
-                                                     "waves_per_mlp_tile": plan[2]}}
+           "launch_plan": None if plan is None else {
+               "waves_per_atom_fwd": plan[0], "waves_per_atom_adj": plan[1],
+               "mlp": "row blocks of 64 atoms" if mlp_rows_plan(plan, args.mode, w) else f"tiles of 16 atoms, plan {plan[2]}"}}
     if walk:
         cfg["walk"] = {"steps_timed": args.steps, "sigma_A": w.extra["step_sigma"], "list_builds_timed": n_builds,
                        "rule": "rebuild on the device when an atom moved farther than skin/2 since the last build"}
@@ -997,7 +1010,7 @@ def main():
     ap.add_argument("--suite-out", default="suite.jsonl")
     ap.add_argument("--stored", action="store_true",
                     help="time the stored-Jacobian mode (store and reuse steps) on --config instead of the bench line")
-    ap.add_argument("--ingest-kernels", nargs="*", default=["k_desc_adj", "k_desc_fwd", "k_mlp"],
+    ap.add_argument("--ingest-kernels", nargs="*", default=["k_desc_adj", "k_desc_fwd", "k_mlp_rows"],
                     help="kernels whose counters --ingest-counters keeps")
     ap.add_argument("--md", action="store_true",
                     help="Langevin dynamics of 16-atom cells (the Table II shape) instead of the bench line")

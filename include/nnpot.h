@@ -307,7 +307,9 @@ nn_status nn_energy_forces_noalloc(const nn_system* sys, const nn_nlist* nl, con
  * Launch tuning (the tiles of the batching step): times the launch variants
  * of this workload's passes -- waves per atom of the descriptor forward and
  * adjoint passes (1, 2, 4, or 0: the packed passes, four atoms of at most
- * 32 list entries per wave, mBP term) and waves per MLP tile (4, 8) -- on
+ * 32 list entries per wave, mBP term) and waves per MLP tile (4, 8, or 1:
+ * the FP32 row-block MLP, 64 atoms per block with the weights staged in
+ * LDS, for widths (64, 32) and (128, 128) and D a multiple of 4) -- on
  * `stream`, and keeps the fastest for workloads of the same shape class
  * (atom count within a factor of two, list entries per atom, descriptor
  * sizes, MLP widths and MLP mode) in a process-wide table that
@@ -320,7 +322,7 @@ nn_status nn_energy_forces_noalloc(const nn_system* sys, const nn_nlist* nl, con
  * plan_out [host] (nullable) receives {waves/atom forward, waves/atom
  * adjoint, waves/MLP tile}.
  * Environment:
- *   NNPOT_PLAN="f,a,m" (f, a in {0, 1, 2, 4}; m in {4, 8}) overrides every
+ *   NNPOT_PLAN="f,a,m" (f, a in {0, 1, 2, 4}; m in {1, 4, 8}) overrides every
  *     plan, tuned or default, while it is set: a way to run each launch
  *     variant in tests;
  *   NN_AUTOTUNE_CACHE=<file> keeps the table in a file across processes:

@@ -9,6 +9,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <string>
 #include <map>
 #include <mutex>
@@ -73,7 +74,7 @@ static const char* cache_path() {
 
 static bool plan_valid(const LaunchPlan& q) {
   auto w = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4; };
-  return w(q.wpa_fwd) && w(q.wpa_adj) && (q.mlp_waves == 0 || q.mlp_waves == 4 || q.mlp_waves == 8);
+  return w(q.wpa_fwd) && w(q.wpa_adj) && (q.mlp_waves == 0 || q.mlp_waves == 1 || q.mlp_waves == 4 || q.mlp_waves == 8);
 }
 
 static void cache_read(const char* path, std::map<PlanKey, LaunchPlan>& into, bool overwrite) {
@@ -140,15 +141,15 @@ static PlanKey plan_key(int64_t n_atoms, int64_t capacity, const DescConst& P, c
 
 // NNPOT_PLAN="f,a,m" in the environment forces a plan on every call (waves
 // per atom of the forward and adjoint passes in {0 (packed), 1, 2, 4},
-// waves per MLP tile in {4, 8}): lets tests run each launch variant against
-// the oracle.
+// waves per MLP tile in {4, 8}, or 1 for the row-block MLP): lets tests run
+// each launch variant against the oracle.
 static bool forced_plan(LaunchPlan* out) {
   const char* e = getenv("NNPOT_PLAN");
   if (!e || !*e) return false;
   int f = 0, a = 0, m = 0;
   if (sscanf(e, "%d,%d,%d", &f, &a, &m) != 3) return false;
   auto ok = [](int w) { return w == 0 || w == 1 || w == 2 || w == 4; };
-  if (!ok(f) || !ok(a) || (m != 4 && m != 8)) return false;
+  if (!ok(f) || !ok(a) || (m != 1 && m != 4 && m != 8)) return false;
   *out = LaunchPlan{f, a, m};
   return true;
 }
@@ -284,6 +285,17 @@ static bool model_fused(const nn_model* m) {
     if (q.n_layers != 3 || q.width[1] != q0.width[1] || q.width[2] != q0.width[2] || q.width[3] != 1) return false;
   }
   return true;
+}
+
+// The fused two-hidden-layer MLP with this plan's launch: the FP32 row-block
+// kernel for plan value 1 (where it takes the shape), else the tile kernel.
+static void run_mlp(const MlpArgs& a, const nn_model* model, int mode, int64_t N, int waves, hipStream_t s) {
+  const int h1 = model->mlp[0].width[1], h2 = model->mlp[0].width[2];
+  if (waves == 1 && mode == 0 && mlp_rows_supported(h1, h2, a.D)) {
+    launch_mlp_rows(a, h1, h2, N, s);
+    return;
+  }
+  launch_mlp(a, h1, h2, mode, N, waves == 1 ? 0 : waves, s);
 }
 
 // Stashes of the layer-by-layer MLP: activations, act' and the adjoint of
@@ -733,7 +745,7 @@ static void ef_enqueue(const nn_system* sys, const nn_nlist* nl, const DescConst
   a.D = P.D;
   {
     StageTimer t(NN_STAGE_MLP, s);
-    if (model_fused(model)) launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
+    if (model_fused(model)) run_mlp(a, model, mode, N, plan.mlp_waves, s);
     else launch_mlp_layers(lay_args(a, L), N, F != nullptr, s);
   }
   if (!F) {
@@ -960,16 +972,6 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
       return fail(NN_E_HIP, "nn_autotune: event creation failed");
-    // mean time of three launches after one untimed one; -1 on an error
-    auto time_of = [&](auto&& launch) -> float {
-      launch();
-      if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
-      for (int r = 0; r < 3; ++r) launch();
-      if (hipEventRecord(e1, s) != hipSuccess) return -1.f;
-      float ms = -1.f;
-      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
-      return ms / 3.f;
-    };
     launch_species_group(sys->species, N, P.S, L.sp_cnt, L.sp_off, L.scan_tmp, L.perm, L.sp_start, s);
     MlpArgs a{};
     prepare_model(model, P, L, mode != 0, a, s);
@@ -980,29 +982,65 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     a.lambda = L.lam;
     a.D = P.D;
     const int h1 = model->mlp[0].width[1], h2 = model->mlp[0].width[2];
-    float t_best = -1.f;
-    const bool pk = packed_supported(P) && nl->capacity <= 48 * N;  // rows short enough for any to be packed
-    for (int w : {0, 1, 2, 4}) {  // descriptor forward
-      if (w == 0 && !pk) continue;
-      const float t = time_of([&] { launch_desc_fwd(*sys, *nl, P, L.G, IdentityGroup{}, w, s); });
-      if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_fwd = w;
-    }
-    t_best = -1.f;
-    if (model_fused(model)) {
-      for (int w : {4, 8}) {  // MLP (lambda for the adjoint timings comes from here)
-        if (w == 8 && h1 < 128) continue;
-        const float t = time_of([&] { launch_mlp(a, h1, h2, mode, N, w, s); });
-        if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.mlp_waves = w;
+    const bool fused = model_fused(model);
+    // one pass of the step's three tuned stages under plan q, with events
+    // around stage `which` (0 forward, 1 MLP, 2 adjoint; -1: none): each
+    // candidate is timed where it runs in a step, after the stage before it
+    // (timed back to back on its own, a launch overlapped the L2 state of the
+    // previous one and the adjoint's choice came out 8 % slower in the step)
+    auto step = [&](const LaunchPlan& q, int which) -> bool {
+      auto mark = [&](int stage, hipEvent_t e) { return which != stage || hipEventRecord(e, s) == hipSuccess; };
+      bool ok = mark(0, e0);
+      launch_desc_fwd(*sys, *nl, P, L.G, IdentityGroup{}, q.wpa_fwd, s);
+      ok = ok && mark(0, e1) && mark(1, e0);
+      if (fused) run_mlp(a, model, mode, N, q.mlp_waves, s);
+      else launch_mlp_layers(lay_args(a, L), N, true, s);
+      ok = ok && mark(1, e1) && mark(2, e0);
+      launch_desc_adj(*sys, *nl, P, L.lam, L.pg, q.wpa_adj, s);
+      return ok && mark(2, e1);
+    };
+    // mean time of stage `which` over three steps after one untimed one; -1 on an error
+    auto time_of = [&](const LaunchPlan& q, int which) -> float {
+      if (!step(q, -1)) return -1.f;
+      float tot = 0.f;
+      for (int r = 0; r < 3; ++r) {
+        float ms = -1.f;
+        if (!step(q, which) || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+          return -1.f;
+        tot += ms;
       }
-    } else {
-      launch_mlp_layers(lay_args(a, L), N, true, s);  // no launch choice to tune; lambda for the adjoint
-    }
-    t_best = -1.f;
-    for (int w : {0, 1, 2, 4}) {  // adjoint
-      if (w == 0 && !pk) continue;
-      const float t = time_of([&] { launch_desc_adj(*sys, *nl, P, L.lam, L.pg, w, s); });
-      if (t >= 0.f && (t_best < 0.f || t < t_best)) t_best = t, best.wpa_adj = w;
-    }
+      return tot / 3.f;
+    };
+    // the fastest candidate for one stage (the others at their current
+    // choice): two interleaved passes, each candidate's best time
+    auto pick = [&](std::initializer_list<int> cands, auto&& usable, int which, int LaunchPlan::*field) {
+      int wv[8];
+      float tb[8];
+      int n = 0;
+      for (int w : cands)
+        if (usable(w)) wv[n] = w, tb[n++] = -1.f;
+      for (int pass = 0; pass < 2; ++pass)
+        for (int c = 0; c < n; ++c) {
+          LaunchPlan q = best;
+          q.*field = wv[c];
+          const float t = time_of(q, which);
+          if (t >= 0.f && (tb[c] < 0.f || t < tb[c])) tb[c] = t;
+        }
+      float tbest = -1.f;
+      for (int c = 0; c < n; ++c)
+        if (tb[c] >= 0.f && (tbest < 0.f || tb[c] < tbest)) tbest = tb[c], best.*field = wv[c];
+    };
+    const bool pk = packed_supported(P) && nl->capacity <= 48 * N;  // rows short enough for any to be packed
+    auto desc_ok = [&](int w) { return w != 0 || pk; };
+    auto mlp_ok = [&](int w) {
+      if (!fused) return w == best.mlp_waves;  // no launch choice for the layer-by-layer MLP
+      if (w == 8) return h1 >= 128;
+      if (w == 1) return mode == 0 && mlp_rows_supported(h1, h2, P.D);
+      return true;
+    };
+    pick({0, 1, 2, 4}, desc_ok, 0, &LaunchPlan::wpa_fwd);
+    pick({4, 8, 1}, mlp_ok, 1, &LaunchPlan::mlp_waves);
+    pick({0, 1, 2, 4}, desc_ok, 2, &LaunchPlan::wpa_adj);
     const bool destroyed = hipEventDestroy(e0) == hipSuccess && hipEventDestroy(e1) == hipSuccess;
     if ((st = check_launch("nn_autotune"))) return st;
     if (!destroyed) return fail(NN_E_HIP, "nn_autotune: event release failed");
@@ -1144,7 +1182,7 @@ nn_status nn_energy_forces_grad(const nn_system* sys, const nn_nlist* nl, const 
       a.st_d1 = L.st_d1;
       a.st_a2 = L.st_a2;
       a.st_d2 = L.st_d2;
-      launch_mlp(a, model->mlp[0].width[1], model->mlp[0].width[2], mode, N, plan.mlp_waves, s);
+      run_mlp(a, model, mode, N, plan.mlp_waves, s);
     }
     WgradArgs g{};
     g.perm = L.perm;

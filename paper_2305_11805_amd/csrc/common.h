@@ -155,8 +155,9 @@ struct IdentityGroup {
 // (only the order of some sums): waves per atom of the descriptor forward
 // and adjoint passes (1, 2 or 4; 0 = the packed passes, four short-row atoms
 // per wave, where packed_supported) and waves per MLP tile (4 or 8; 0 = the
-// default).  Defaults come from plan_default(); nn_autotune stores measured
-// ones per shape class.
+// default; 1 = the FP32 row-block MLP where mlp_rows_supported).  Defaults
+// come from plan_default(); nn_autotune stores measured ones per shape
+// class.
 struct LaunchPlan {
   int wpa_fwd, wpa_adj, mlp_waves;
 };
@@ -241,6 +242,10 @@ void launch_species_group(const int32_t* species, int64_t N, int S, int64_t* cnt
 bool mlp_supported(int h1, int h2);
 // mode 0 FP32, 1 BF16, 2 split BF16; waves per tile 4 or 8 (0: default)
 void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, int waves, hipStream_t s);
+// mlp_rows.hip: the FP32 row-block MLP (64 atoms per block, weights staged in
+// LDS); shapes (64, 32) and (128, 128) with D a multiple of 4
+bool mlp_rows_supported(int h1, int h2, int D);
+void launch_mlp_rows(const MlpArgs& a, int h1, int h2, int64_t N, hipStream_t s);
 void launch_convert_bf16(const ConvJob& job, hipStream_t s);
 void launch_mlp_fm(const MlpFmArgs& a, int h1, int h2, int64_t N, int waves, hipStream_t s);
 // mlp_layers.hip: per-species networks of any depth (up to NN_MAX_LAYERS

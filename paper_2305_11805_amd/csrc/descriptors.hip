@@ -2214,10 +2214,11 @@ bool packed_supported(const DescConst& P) {
 
 // Waves per atom: two when the atoms alone would leave the SIMDs with few
 // waves to switch between, one otherwise; the packed passes for short rows
-// (small molecules: at most 24 list entries per atom on average).
+// (small molecules: at most 24 list entries per atom on average).  MLP: the
+// row-block kernel.
 LaunchPlan plan_default(int64_t n_atoms, const DescConst& P, int64_t capacity) {
   const int w = n_atoms <= 16384 ? 2 : 1;
-  LaunchPlan plan{w, w, 0};
+  LaunchPlan plan{w, w, 1};  // the row-block MLP where it takes the shape (FP32), else the tile kernel's default
   const bool short_rows = n_atoms > 0 && capacity <= 24 * n_atoms;
   if (short_rows && packed_supported(P)) {
     plan.wpa_fwd = plan.wpa_adj = 0;

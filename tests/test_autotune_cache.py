@@ -70,8 +70,8 @@ def write(path, lines):
 
 
 def test_default_rules_without_cache():
-    # short rows (capacity <= 24 per atom) with the mBP term: the packed passes
-    assert query({})["plan"] == [0, 0, 0]
+    # short rows (capacity <= 24 per atom) with the mBP term: the packed passes; the row-block MLP
+    assert query({})["plan"] == [0, 0, 1]
 
 
 def test_cached_plan_is_used(tmp_path):
@@ -92,7 +92,7 @@ def test_bad_lines_are_skipped(tmp_path):
 
 
 def test_missing_file_changes_nothing(tmp_path):
-    assert query({"NN_AUTOTUNE_CACHE": str(tmp_path / "absent.json")})["plan"] == [0, 0, 0]
+    assert query({"NN_AUTOTUNE_CACHE": str(tmp_path / "absent.json")})["plan"] == [0, 0, 1]
 
 
 def test_forced_plan_wins_over_cache(tmp_path):
@@ -105,4 +105,4 @@ def test_reset_forgets_cached_plans(tmp_path):
     path = str(tmp_path / "plans.json")
     write(path, ['{"key": %s, "plan": [2, 4, 8]}' % json.dumps(KEY)])
     out = query({"NN_AUTOTUNE_CACHE": path}, "reset")
-    assert out["plan"] == [2, 4, 8] and out["after_reset"] == [0, 0, 0]
+    assert out["plan"] == [2, 4, 8] and out["after_reset"] == [0, 0, 1]

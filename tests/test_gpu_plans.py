@@ -18,7 +18,7 @@ from helpers import E_TOL, F_TOL
 
 pytestmark = pytest.mark.gpu
 
-PLANS = list(itertools.product((0, 1, 2, 4), (0, 1, 2, 4), (4, 8)))
+PLANS = list(itertools.product((0, 1, 2, 4), (0, 1, 2, 4), (1, 4, 8)))
 _cache = {}
 
 
