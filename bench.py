@@ -939,7 +939,7 @@ def headline(args):
     cfg = {"workload": w.name, "n_atoms": s.n_atoms, "n_structs": s.n_structs, "mlp_mode": args.mode,
            "neighbor_build_each_step": skin == 0.0, "skin": skin, "seed": w.seed,
            "launch_plan": None if plan is None else {
-               "waves_per_atom_fwd": plan[0], "waves_per_atom_adj": plan[1],
+               "plan": list(plan), "waves_per_atom_fwd": plan[0], "waves_per_atom_adj": plan[1],
                "mlp": "row blocks of 64 atoms" if mlp_rows_plan(plan, args.mode, w) else f"tiles of 16 atoms, plan {plan[2]}"}}
     if walk:
         cfg["walk"] = {"steps_timed": args.steps, "sigma_A": w.extra["step_sigma"], "list_builds_timed": n_builds,
