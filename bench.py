@@ -97,17 +97,22 @@ def valid_neighbor_counts(pot, rc):
     return np.bincount(rows[valid], minlength=len(off) - 1)
 
 
-SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp_rows": "mlp_rows.hip", "k_mlp": "mlp.hip",
+SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp_rows_bf": "mlp_rows.hip", "k_mlp_rows": "mlp_rows.hip", "k_mlp": "mlp.hip",
            "k_nb": "neighbors.hip"}
 
 
 def mlp_rows_plan(plan, mode, w):
-    """True when the timed MLP is the FP32 row-block kernel (plan value 1 on
-    the widths and descriptor sizes it takes)."""
-    if plan is None or plan[2] != 1 or mode != "fp32":
-        return False
+    """The row-block MLP kernel the timed steps run (plan value 1 on the
+    widths and descriptor sizes it takes: k_mlp_rows in FP32, k_mlp_rows_bf
+    in the BF16 modes), else None (the tile kernel k_mlp)."""
+    if plan is None or plan[2] != 1:
+        return None
     widths = w.model[0][0]
-    return len(widths) == 4 and tuple(widths[1:3]) in ((64, 32), (128, 128)) and w.params.dim % 4 == 0
+    if len(widths) != 4 or tuple(widths[1:3]) not in ((64, 32), (128, 128)):
+        return None
+    if mode == "fp32":
+        return "k_mlp_rows" if w.params.dim % 4 == 0 else None
+    return "k_mlp_rows_bf" if w.params.dim % 8 == 0 else None
 
 
 def source_hash(kernel="k_desc_adj"):
@@ -930,7 +935,7 @@ def headline(args):
         e = {"avg_launch_ms": round(ms_k, 5), "algorithmic_flops_per_launch": fl,
              "tflops": round(fl / (ms_k / 1e3) / 1e12, 3), "peak_mfma_tflops": peak,
              "frac_mfma": round(fl / (ms_k / 1e3) / 1e12 / peak, 4)}
-        mlp_name = "k_mlp_rows" if mlp_rows_plan(plan, args.mode, w) else "k_mlp"
+        mlp_name = mlp_rows_plan(plan, args.mode, w) or "k_mlp"
         b = hbm_bytes(mlp_name)
         if b is not None:
             e["hbm_bytes_per_launch"] = b

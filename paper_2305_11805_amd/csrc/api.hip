@@ -287,12 +287,17 @@ static bool model_fused(const nn_model* m) {
   return true;
 }
 
-// The fused two-hidden-layer MLP with this plan's launch: the FP32 row-block
-// kernel for plan value 1 (where it takes the shape), else the tile kernel.
+// The fused two-hidden-layer MLP with this plan's launch: the row-block
+// kernel (FP32 or BF16) for plan value 1 where it takes the shape, else the
+// tile kernel.
 static void run_mlp(const MlpArgs& a, const nn_model* model, int mode, int64_t N, int waves, hipStream_t s) {
   const int h1 = model->mlp[0].width[1], h2 = model->mlp[0].width[2];
   if (waves == 1 && mode == 0 && mlp_rows_supported(h1, h2, a.D)) {
     launch_mlp_rows(a, h1, h2, N, s);
+    return;
+  }
+  if (waves == 1 && mode != 0 && mlp_rows_bf_supported(h1, h2, a.D)) {
+    launch_mlp_rows_bf(a, h1, h2, mode, N, s);
     return;
   }
   launch_mlp(a, h1, h2, mode, N, waves == 1 ? 0 : waves, s);
@@ -1035,7 +1040,7 @@ nn_status nn_autotune(const nn_system* sys, const nn_nlist* nl, const nn_mbp_par
     auto mlp_ok = [&](int w) {
       if (!fused) return w == best.mlp_waves;  // no launch choice for the layer-by-layer MLP
       if (w == 8) return h1 >= 128;
-      if (w == 1) return mode == 0 && mlp_rows_supported(h1, h2, P.D);
+      if (w == 1) return mode == 0 ? mlp_rows_supported(h1, h2, P.D) : mlp_rows_bf_supported(h1, h2, P.D);
       return true;
     };
     pick({0, 1, 2, 4}, desc_ok, 0, &LaunchPlan::wpa_fwd);

@@ -246,6 +246,10 @@ void launch_mlp(const MlpArgs& a, int h1, int h2, int mode, int64_t N, int waves
 // LDS); shapes (64, 32) and (128, 128) with D a multiple of 4
 bool mlp_rows_supported(int h1, int h2, int D);
 void launch_mlp_rows(const MlpArgs& a, int h1, int h2, int64_t N, hipStream_t s);
+// its BF16 modes (mode 1 plain, 2 split; the BF16 weight copies prepared),
+// D a multiple of 8
+bool mlp_rows_bf_supported(int h1, int h2, int D);
+void launch_mlp_rows_bf(const MlpArgs& a, int h1, int h2, int mode, int64_t N, hipStream_t s);
 void launch_convert_bf16(const ConvJob& job, hipStream_t s);
 void launch_mlp_fm(const MlpFmArgs& a, int h1, int h2, int64_t N, int waves, hipStream_t s);
 // mlp_layers.hip: per-species networks of any depth (up to NN_MAX_LAYERS

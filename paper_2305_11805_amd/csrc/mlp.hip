@@ -18,8 +18,6 @@
 
 namespace nnp {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 constexpr int kTile = 16;
 
 // ---------------------------------------------------------------------------
@@ -115,33 +113,6 @@ __global__ void __launch_bounds__(kSpThreads) k_sp_group_small(const int32_t* __
 // fused MLP tile kernel
 // ---------------------------------------------------------------------------
 
-
-// Products in the MLP run in one of three modes:
-//   kFp32  - FP32 operands, v_mfma_f32_16x16x4_f32;
-//   kBf16  - operands rounded to BF16, v_mfma_f32_16x16x32_bf16, FP32 sums;
-//   kBf16x3 - each operand split x = hi + lo with hi, lo in BF16 and the
-//            product taken as hi*hi + hi*lo + lo*hi (three BF16 MFMAs, FP32
-//            sums): about 16 significant bits per operand.
-enum { kFp32 = 0, kBf16 = 1, kBf16x3 = 2 };
-
-__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const __bf16 h = (__bf16)x[q];
-    hi[q] = h;
-    lo[q] = (__bf16)(x[q] - (float)h);
-  }
-}
-
-template <int MODE>
-__device__ __forceinline__ floatx4 mma_bf16(floatx4 acc, const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
-                                            const bf16x8& bl) {
-  if constexpr (MODE == kBf16x3) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-  }
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-}
 
 // A fragment (row lm, 8 consecutive k from kb) of a row-major FP32 LDS buffer.
 template <int MODE>

@@ -9,6 +9,7 @@
 namespace nnp {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ float act_f(int code, float z) {
   switch (code) {
@@ -55,6 +56,33 @@ __device__ __forceinline__ floatx4 mma4_f32(floatx4 acc, const float4& a, const 
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+}
+
+// Products in the MLP run in one of three modes:
+//   kFp32  - FP32 operands, v_mfma_f32_16x16x4_f32;
+//   kBf16  - operands rounded to BF16, v_mfma_f32_16x16x32_bf16, FP32 sums;
+//   kBf16x3 - each operand split x = hi + lo with hi, lo in BF16 and the
+//            product taken as hi*hi + hi*lo + lo*hi (three BF16 MFMAs, FP32
+//            sums): about 16 significant bits per operand.
+enum { kFp32 = 0, kBf16 = 1, kBf16x3 = 2 };
+
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const __bf16 h = (__bf16)x[q];
+    hi[q] = h;
+    lo[q] = (__bf16)(x[q] - (float)h);
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ floatx4 mma_bf16(floatx4 acc, const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                            const bf16x8& bl) {
+  if constexpr (MODE == kBf16x3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
 }
 
 }  // namespace nnp

@@ -1,10 +1,10 @@
-"""The FP32 row-block MLP (plan value 1: 64 atoms per block, the weights
-staged in LDS) against the FP64 oracle, forced with NNPOT_PLAN="f,a,1":
-energies, forces and the weight gradient of an energy loss for both fused
-shapes (64-32 on the 4-species clusters, 128-128 on the one- and
-two-species bulk cells), the Gaussian, ReLU and tanh activations, species
-tiles with a ragged last block, and bitwise repeatability.  The split-BF16
-flags with plan value 1 take the tile kernel (the row-block MLP is FP32)."""
+"""The row-block MLP (plan value 1: 64 atoms per block, the weights staged in
+LDS) against the FP64 oracle, forced with NNPOT_PLAN="f,a,1": energies,
+forces and the weight gradient of an energy loss for both fused shapes
+(64-32 on the 4-species clusters, 128-128 on the one- and two-species bulk
+cells), the Gaussian, ReLU and tanh activations, species tiles with a ragged
+last block, and bitwise repeatability; then its BF16 modes, split (hi + lo)
+operands to the stated tolerances and plain BF16 to its rounding model."""
 import os
 
 import numpy as np
@@ -77,15 +77,32 @@ def test_row_block_mlp_matches_oracle(name):
     assert worst <= 1e-4
 
 
-def test_split_bf16_with_row_plan_takes_the_tile_kernel():
-    w = synth.config(2, scale=0.03)
+@pytest.mark.parametrize("name", ["cfg2s", "cfg1s", "cfg4s", "act_tanh"])
+def test_row_block_bf16_modes(name):
+    w = workload(name)
     s, p = w.system, w.params
     nl = oracle.neighbors_cells(s, p.rc)
-    Es_ref, _, F_ref = oracle.energy_forces(p, w.model, s, nl)
+    Es_ref, Ea_ref, F_ref = oracle.energy_forces(p, w.model, s, nl)
     pot = nnpot.Potential(s, p, w.model)
     pot.build_neighbors()
-    with plan("0,0,1"):
+    n_c = np.maximum(np.diff(s.atom_ptr), 1)
+    fw = "0" if name.startswith(("cfg2", "act")) else "1"
+    with plan(f"{fw},{fw},1"):
+        # split operands: about 16 significant bits each, the stated tolerances
         Es, _, F = [t.cpu().numpy() for t in pot.energy_forces(flags=nnpot.NN_BF16X3_MLP)]
+        e = float(np.max(np.abs(Es - Es_ref) / n_c))
+        f = float(np.abs(F - F_ref).max())
+        print(f"[mlp rows] {name} bf16x3: E/atom {e:.2e} F {f:.2e}", flush=True)
+        assert e <= E_TOL and f <= F_TOL
+        again = [t.cpu().numpy() for t in pot.energy_forces(flags=nnpot.NN_BF16X3_MLP)]
+        assert np.array_equal(again[0], Es) and np.array_equal(again[2], F)
+        # plain BF16 (unit roundoff u = 2^-9 on every operand): 16 u of the
+        # largest atomic energy / force component, as for the tile kernel
+        _, Ea, F = [t.cpu().numpy() for t in pot.energy_forces(flags=nnpot.NN_BF16_MLP)]
+        u = 2.0 ** -9
+        e = float(np.abs(Ea - Ea_ref).max())
+        f = float(np.abs(F - F_ref).max())
+        print(f"[mlp rows] {name} bf16: E/atom {e:.2e} F {f:.2e}", flush=True)
+        assert e <= 16 * u * max(1.0, np.abs(Ea_ref).max())
+        assert f <= 16 * u * max(1.0, np.abs(F_ref).max())
     nnpot.nn_check(pot.nl)
-    assert np.max(np.abs(Es - Es_ref) / np.maximum(np.diff(s.atom_ptr), 1)) <= E_TOL
-    assert np.abs(F - F_ref).max() <= F_TOL
