@@ -56,11 +56,14 @@ enum {
                             2.7e-2 eV/A on a 32768-atom 4-species bulk cell and 1.3e-2 on a
                             262144-atom one, 13-27x over a 1e-3 eV/A force tolerance (energies
                             stay within 1e-4 eV/atom).  Use NN_BF16X3_MLP where forces must
-                            meet 1e-3 eV/A.                                                   */
+                            meet 1e-3 eV/A.  Fastest MLP mode (about half the FP32 MLP
+                            time on batches of small molecules).                              */
   NN_STORE_JACOBIAN = 2, /* store dG/dx during the descriptor pass if it fits mem_budget        */
   NN_BF16X3_MLP = 4,     /* MLP products on BF16 MFMA with every operand split into BF16 hi + lo
                             and three products (hi*hi + hi*lo + lo*hi), FP32 sums: about 16
-                            significant bits per operand.  Exclusive with NN_BF16_MLP.
+                            significant bits per operand (forces within 1e-3 eV/A), and with
+                            the row-block MLP faster than FP32 (the MLP in about 0.65x the
+                            FP32 time).  Exclusive with NN_BF16_MLP.
                             Neither flag: FP32 MFMA.                                           */
   NN_REUSE_DESCRIPTORS = 8 /* skip the descriptor pass: use G and the Jacobian that an earlier
                               NN_STORE_JACOBIAN call with the same positions and list left in
@@ -308,8 +311,9 @@ nn_status nn_energy_forces_noalloc(const nn_system* sys, const nn_nlist* nl, con
  * of this workload's passes -- waves per atom of the descriptor forward and
  * adjoint passes (1, 2, 4, or 0: the packed passes, four atoms of at most
  * 32 list entries per wave, mBP term) and waves per MLP tile (4, 8, or 1:
- * the FP32 row-block MLP, 64 atoms per block with the weights staged in
- * LDS, for widths (64, 32) and (128, 128) and D a multiple of 4) -- on
+ * the row-block MLP, 64 atoms per block with the weights staged in LDS, for
+ * widths (64, 32) and (128, 128) and D a multiple of 4 in FP32, of 8 in the
+ * BF16 modes) -- on
  * `stream`, and keeps the fastest for workloads of the same shape class
  * (atom count within a factor of two, list entries per atom, descriptor
  * sizes, MLP widths and MLP mode) in a process-wide table that
