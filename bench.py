@@ -30,8 +30,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
-PEAK_FP32_PACKED_TFLOPS = 157.3  # the same with two-wide packed FP32 FMA
+# 256 CU x 4 SIMD x 32 lanes x 2 flop (FMA) x 2.4 GHz: an unpacked v_fma_f32
+# retires a wave64 in 2 clocks on gfx950 (paper_2305_11805_amd/probe/issue_rates)
+PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_BF16_MFMA_TFLOPS = 2500.0
@@ -895,8 +896,7 @@ def headline(args):
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
                 "avg_launch_ms": round(dom_ms, 5), "algorithmic_flops_per_launch": fm[dom],
-                "flops_per_triplet": fm["per_triplet"][dom],
-                "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED_TFLOPS, 4)}
+                "flops_per_triplet": fm["per_triplet"][dom]}
     else:
         roof = {"kernel": dom, "bound": "mfma", "achieved": None, "peak": None, "unit": None, "frac": None,
                 "traffic": None, "avg_launch_ms": round(dom_ms, 5)}

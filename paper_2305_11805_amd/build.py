@@ -3,7 +3,8 @@
     python -m paper_2305_11805_amd.build
 
 Each .hip source is compiled with hipcc for gfx950 with packed-FP32
-instructions disabled, then linked into a shared library next to this file.
+instructions disabled, then linked into a shared library next to this file;
+the issue-rate probe (probe/issue_rates) is built beside it.
 """
 from __future__ import annotations
 
@@ -18,6 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnnpot.so")
+PROBE_SRC = os.path.join(HERE, "probe", "issue_rates.hip")
+PROBE = os.path.join(HERE, "probe", "issue_rates")
 ARCH = os.environ.get("NNPOT_ARCH", "gfx950")
 
 CFLAGS = [
@@ -54,9 +57,21 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
+    build_probe()
     if verbose:
         print(LIB)
     return LIB
+
+
+def build_probe() -> str:
+    """The issue-rate probe behind the FP32 VALU and MFMA peaks of the
+    rooflines (a standalone program, not part of the library)."""
+    cmd = ["hipcc", *CFLAGS, PROBE_SRC, "-o", PROBE + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("probe build failed:\n" + r.stdout + r.stderr)
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
 
 
 if __name__ == "__main__":
