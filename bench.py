@@ -98,7 +98,7 @@ def valid_neighbor_counts(pot, rc):
     return np.bincount(rows[valid], minlength=len(off) - 1)
 
 
-SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp_rows_bf": "mlp_rows.hip", "k_mlp_rows": "mlp_rows.hip", "k_mlp": "mlp.hip",
+SOURCES = {"k_desc": "descriptors.hip", "k_jac": "descriptors.hip", "k_mlp_rows_bf": "mlp_rows.hip", "k_mlp_rows": "mlp_rows.hip", "k_mlp": "mlp.hip", "k_force_gather": "descriptors.hip",
            "k_nb": "neighbors.hip"}
 
 
