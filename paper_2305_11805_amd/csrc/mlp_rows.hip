@@ -208,10 +208,17 @@ __global__ void __launch_bounds__(64 * kRwWaves) k_mlp_rows(MlpArgs args) {
 #pragma unroll
   for (int u = 0; u < H1T; ++u) acc1[u] = floatx4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < H2; k0 += KC) {
-    // stage W2[k0:k0+KC][0:H1] transposed: ws[n][k] = W2[k0 + k][n]
-    for (int x = tid; x < KC * H1; x += 64 * kRwWaves) {
-      const int k = x / H1, n = x - k * H1;
-      ws[n * LDW + k] = k0 + k < H2 ? W2[(int64_t)(k0 + k) * H1 + n] : 0.f;
+    // stage W2[k0:k0+KC][0:H1] transposed: ws[n][k] = W2[k0 + k][n], four k
+    // per thread (each load coalesced over n) as one 16-byte LDS store: a
+    // thread per value would put lanes n and n + 16 on one bank
+    for (int x = tid; x < KC / 4 * H1; x += 64 * kRwWaves) {
+      const int kq = x / H1, n = x - kq * H1, k = k0 + 4 * kq;
+      float4 v;
+      v.x = k < H2 ? W2[(int64_t)k * H1 + n] : 0.f;
+      v.y = k + 1 < H2 ? W2[(int64_t)(k + 1) * H1 + n] : 0.f;
+      v.z = k + 2 < H2 ? W2[(int64_t)(k + 2) * H1 + n] : 0.f;
+      v.w = k + 3 < H2 ? W2[(int64_t)(k + 3) * H1 + n] : 0.f;
+      *reinterpret_cast<float4*>(ws + n * LDW + 4 * kq) = v;
     }
     __syncthreads();
 #pragma unroll
@@ -247,23 +254,26 @@ __global__ void __launch_bounds__(64 * kRwWaves) k_mlp_rows(MlpArgs args) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) orow[j] = rows[16 * wv + 4 * lk + j];
   // each chunk W1[0:H1][c0:c0+KC] staged transposed, ws[n][k] = W1[k][c0 + n],
-  // the next one requested before this one's products
-  constexpr int NS4 = H1 * KC / NT;
-  static_assert(H1 * KC % NT == 0, "whole values per thread");
-  float wp4[NS4];
+  // four k per thread as one 16-byte LDS store (as in P3), the next chunk
+  // requested before this one's products
+  constexpr int NS4 = H1 * KC / (4 * NT);
+  static_assert(H1 * KC % (4 * NT) == 0, "whole groups of four values per thread");
+  float4 wp4[NS4];
   auto fetch4 = [&](int c0) {
 #pragma unroll
     for (int q = 0; q < NS4; ++q) {
-      const int x = tid + q * NT, k = x / KC, n = x - k * KC;
-      wp4[q] = c0 + n < D ? W1[(int64_t)k * D + c0 + n] : 0.f;
+      const int x = tid + q * NT, kq = x / KC, n = x - kq * KC;
+      const bool in = c0 + n < D;
+      const float* w = W1 + (int64_t)(4 * kq) * D + c0 + n;
+      wp4[q] = in ? make_float4(w[0], w[D], w[2 * D], w[3 * D]) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
   fetch4(0);
   for (int c0 = 0; c0 < D; c0 += KC) {
 #pragma unroll
     for (int q = 0; q < NS4; ++q) {
-      const int x = tid + q * NT, k = x / KC;
-      ws[(x - k * KC) * LDT + k] = wp4[q];
+      const int x = tid + q * NT, kq = x / KC;
+      *reinterpret_cast<float4*>(ws + (x - kq * KC) * LDT + 4 * kq) = wp4[q];
     }
     __syncthreads();
     if (c0 + KC < D) fetch4(c0 + KC);

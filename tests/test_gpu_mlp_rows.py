@@ -106,3 +106,28 @@ def test_row_block_bf16_modes(name):
         assert e <= 16 * u * max(1.0, np.abs(Ea_ref).max())
         assert f <= 16 * u * max(1.0, np.abs(F_ref).max())
     nnpot.nn_check(pot.nl)
+
+
+# Descriptor lengths the row-block kernels do not take: D = 76 (a multiple of 4,
+# not of 8: the FP32 row-block kernel, the split-BF16 mode falls back to the
+# tile kernel) and D = 77 (both fall back), with plan value 1 forced.
+@pytest.mark.parametrize("n_rad,hidden", [(12, [64, 32]), (13, [64, 32]), (12, [128, 128]), (13, [128, 128])])
+def test_row_plan_on_descriptor_lengths_it_does_not_take(n_rad, hidden):
+    rng = np.random.Generator(np.random.PCG64(5100 + n_rad))
+    s = synth.bulk_system(rng, 432, 0.1, 1.2, [432])
+    p = synth.mbp_params(1, 5.0, n_rad, 8, 8)
+    G = oracle.descriptors(p, s, oracle.neighbors_cells(s, p.rc))
+    scale = float(np.sqrt(p.dim) / np.sqrt(np.mean(np.sum(G * G, axis=1))))
+    model = synth.random_model(1, p.dim, hidden, 91 + n_rad, in_scale=scale)
+    nl = oracle.neighbors_cells(s, p.rc)
+    Es_ref, _, F_ref = oracle.energy_forces(p, model, s, nl)
+    pot = nnpot.Potential(s, p, model)
+    pot.build_neighbors()
+    with plan("1,1,1"):
+        for flags in (0, nnpot.NN_BF16X3_MLP):
+            Es, _, F = [t.cpu().numpy() for t in pot.energy_forces(flags=flags)]
+            e = float(np.max(np.abs(Es - Es_ref)) / s.n_atoms)
+            f = float(np.abs(F - F_ref).max())
+            print(f"[mlp rows] D {p.dim} {hidden} flags {flags}: E/atom {e:.2e} F {f:.2e}", flush=True)
+            assert e <= E_TOL and f <= F_TOL
+    nnpot.nn_check(pot.nl)
