@@ -102,6 +102,11 @@ constexpr int kStageRounds = 2;  // rows up to 128 entries are staged in one pas
 constexpr int kPackAtoms = 4;
 constexpr int kPackLanes = 16;
 constexpr int kPackNb = 32;
+// LDS stride of a group's neighbor slots: one spare slot per group puts the
+// same slot of the four groups on different LDS banks (at 32 the four
+// regions start on one bank, and lanes of different atoms at the same
+// offset conflict)
+constexpr int kPackSlots = kPackNb + 1;
 
 // sin and cos of x in [0, pi/2] by their Taylor series to x^11 and x^12
 // (truncation below 6e-8 at pi/2), without range reduction.
@@ -1479,8 +1484,8 @@ __global__ void __launch_bounds__(64) k_desc_adj_long(nn_system sys, const int64
 // ---------------------------------------------------------------------------
 
 struct PackNb {
-  float4 d[kPackAtoms * kPackNb];  // as AtomNb; atom g's neighbors at g kPackNb + [0, n_g)
-  float4 f[kPackAtoms * kPackNb];
+  float4 d[kPackAtoms * kPackSlots];  // as AtomNb; atom g's neighbors at g kPackSlots + [0, n_g)
+  float4 f[kPackAtoms * kPackSlots];
   int seg[kPackAtoms][NN_MAX_SPECIES + 1];
   int64_t atom[kPackAtoms];  // the atom of each group, -1 if the group has none to pack
 };
@@ -1521,7 +1526,7 @@ __device__ __forceinline__ int struct_of_atom16(const int64_t* atom_ptr, int32_t
 }
 
 // Group g's lanes stage atom i's row (take: it has at most kPackNb entries)
-// into slots g kPackNb + [0, n), sorted by species (stable, so in entry
+// into slots g kPackSlots + [0, n), sorted by species (stable, so in entry
 // order within a species, as stage_neighbors), with nb.seg[g]; with ir the
 // 1/r of each slot too.  Entries at r >= rc get a zero pair gradient if pg
 // != nullptr.  Groups that do not take their atom stage nothing (n = 0).
@@ -1609,7 +1614,7 @@ __device__ void stage_packed(PackNb& nb, float* ir, int64_t i, bool take, const 
       float4 dd, ff;
       float irf;
       pair_record(d[r], r2[r], r * kPackLanes + l, sp[r], P, dd, ff, irf);
-      const int t = g * kPackNb + slot[r];
+      const int t = g * kPackSlots + slot[r];
       nb.d[t] = dd;
       nb.f[t] = ff;
       if (ir) ir[t] = irf;
@@ -1685,8 +1690,8 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
       const float rs = kin ? P.rs_rad[k] : 0.f, rs_lo = kin ? P.rs_rad_lo[k] : 0.f;
       for (int s = 0; s < S; ++s) {
         float acc = 0.f;
-        const int t1 = g * kPackNb + nb.seg[g][s + 1];
-        for (int t = g * kPackNb + nb.seg[g][s]; t < t1; ++t) {
+        const int t1 = g * kPackSlots + nb.seg[g][s + 1];
+        for (int t = g * kPackSlots + nb.seg[g][s]; t < t1; ++t) {
           const float dr = (nb.d[t].w - rs) + (nb.f[t].z - rs_lo);
           acc = fmaf(fexp2(-eta_r2 * dr * dr), nb.f[t].x, acc);
         }
@@ -1721,7 +1726,7 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
       const bool same = pa == pb;
       const int m = same ? na : nbb;
       cnt = same ? na * (na - 1) / 2 : na * nbb;
-      stab[s] = make_int4(0, a * kPackNb + ja, a * kPackNb + kb, m | (same ? 1 << 16 : 0));
+      stab[s] = make_int4(0, a * kPackSlots + ja, a * kPackSlots + kb, m | (same ? 1 << 16 : 0));
       sinv[s] = m > 0 ? 1.0f / (float)m : 0.f;
       const int64_t ia = nb.atom[a];
       const int64_t go = (ia >= 0 ? ia : 0) * (int64_t)D + ang0 + pbi * NB;
@@ -1920,9 +1925,14 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
 }
 
 // Dynamic LDS of k_desc_adj_packed: the lambda rows, each [radial S n_rad,
-// padded to a multiple of 4][angular blocks].
+// padded to a multiple of 4][angular blocks][4 spare floats].  The spare
+// floats move each row by four banks: a row of a multiple of 64 floats would
+// start every group's row on one bank.  (Padding each pair block to NB + 4
+// as well removed most of the remaining bank conflicts but cost a block per
+// CU of occupancy, and the pass got slower; reading the radial part from
+// global memory instead of LDS gained a block per CU and was slower too.)
 __host__ __device__ inline int packed_lam_stride(int S, int n_rad, int NB) {
-  return (S * n_rad + 3) / 4 * 4 + S * (S + 1) / 2 * NB;
+  return (S * n_rad + 3) / 4 * 4 + S * (S + 1) / 2 * NB + 4;
 }
 
 // Per-pair energy gradients for kPackAtoms atoms per one-wave block (rows
@@ -1945,8 +1955,8 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
   constexpr int NB = NT * NRA;
   constexpr int kLamPre4 = 4;  // float4 (or four values) of lambda per lane requested before the staging
   __shared__ PackNb nb;
-  __shared__ float irs[kPackAtoms * kPackNb];
-  __shared__ float gx[kPackAtoms * kPackNb], gy[kPackAtoms * kPackNb], gz[kPackAtoms * kPackNb];
+  __shared__ float irs[kPackAtoms * kPackSlots];
+  __shared__ float gx[kPackAtoms * kPackSlots], gy[kPackAtoms * kPackSlots], gz[kPackAtoms * kPackSlots];
   extern __shared__ float4 pk_lds[];
   if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
   const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
@@ -1957,7 +1967,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
   const int Dp = packed_lam_stride(S, P.n_rad, NB), angp = (ang0 + 3) / 4 * 4;
   float* lam_s = reinterpret_cast<float*>(pk_lds);
   // this group's lambda row, requested before the staging; with S n_rad a
-  // multiple of 4 the LDS row is the row itself (Dp = D), copied as float4
+  // multiple of 4 it is copied to LDS as float4
   const bool vec4 = (ang0 & 3) == 0;
   const float* lam = lambda + (take ? i : 0) * (int64_t)D;
   const float4* lam4 = reinterpret_cast<const float4*>(lam);
@@ -1980,7 +1990,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
   stage_packed(nb, irs, i, take, sys, offsets, nbr, shift, P, meta, pg);
   float* lrow = lam_s + g * Dp;
   if (take) {
-    if (vec4) {
+    if (vec4) {  // then the LDS row is the row itself
       float4* lr4 = reinterpret_cast<float4*>(lrow);
 #pragma unroll
       for (int q = 0; q < kLamPre4; ++q) {
@@ -2007,7 +2017,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
   // radial: lane <-> neighbor of its group's atom; dE/dd = (dE/dr) d/r
   const float eta_r2 = P.eta_rad * 1.4426950408889634f;
   for (int t = l; t < ng; t += kPackLanes) {
-    const int ts = g * kPackNb + t;
+    const int ts = g * kPackSlots + t;
     const float4 u = nb.d[ts], fu = nb.f[ts];
     const float* lr = lrow + nb_species(fu) * P.n_rad;
     float gr = 0.f;
@@ -2053,8 +2063,8 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
     const int step = q + 1;
     int k = j + step;
     if (k >= n) k -= n;
-    j += a * kPackNb;
-    k += a * kPackNb;
+    j += a * kPackSlots;
+    k += a * kPackSlots;
     float gjx = 0.f, gjy = 0.f, gjz = 0.f, gkx = 0.f, gky = 0.f, gkz = 0.f;
     if (tk) {
       const float4 u = nb.d[j], fu = nb.f[j];
@@ -2146,7 +2156,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
   if (take) {
     const int64_t e0 = offsets[i];
     for (int t = l; t < ng; t += kPackLanes) {
-      const int ts = g * kPackNb + t;
+      const int ts = g * kPackSlots + t;
       pg[e0 + nb_entry(nb.f[ts])] = make_float4(gx[ts], gy[ts], gz[ts], 0.f);
     }
   }
