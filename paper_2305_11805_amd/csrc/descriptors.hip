@@ -1634,10 +1634,10 @@ __device__ __forceinline__ float quad_bcast(float x) {
 
 // Dynamic LDS of k_desc_fwd_packed: the segment table (int4 [nseg + 1],
 // float [nseg]; int4 [nseg] with each segment's start and place in G), then
-// the head and tail rows of the 16 MFMA blocks.
+// the tail rows of the 16 MFMA blocks (the heads stay in registers).
 static inline size_t packed_fwd_lds(int S, int NB) {
   const int nseg = kPackAtoms * S * (S + 1) / 2;
-  return sizeof(int4) * (2 * nseg + 1) + sizeof(float) * ((nseg + 3) / 4 * 4) + sizeof(float) * 2 * 16 * NB;
+  return sizeof(int4) * (2 * nseg + 1) + sizeof(float) * ((nseg + 3) / 4 * 4) + sizeof(float) * 16 * NB;
 }
 
 // Descriptor rows of kPackAtoms atoms per one-wave block, for atoms whose
@@ -1652,7 +1652,8 @@ static inline size_t packed_fwd_lds(int S, int NB) {
 // angle and radius factors to the 4x4x1 MFMA as in k_desc_fwd.  When a block
 // passes the end of a segment its accumulators hold the segment's last
 // piece: a segment that lies inside the block's range goes straight to G; a
-// piece that began in an earlier range goes to the block's head row, and the
+// piece that began in an earlier range is kept in the block's registers (its
+// head), and the
 // piece still open at the end of a range to its tail row.  The segments
 // split over ranges are then written as head + the tails of the ranges
 // before, in range order, so every sum has a fixed order.
@@ -1706,8 +1707,7 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
   int4* stab = reinterpret_cast<int4*>(pk_lds);
   int4* sdst = stab + nseg + 1;  // start, offset of the segment's bins in G (lo, hi)
   float* sinv = reinterpret_cast<float*>(sdst + nseg);
-  float* head = sinv + (nseg + 3) / 4 * 4;
-  float* tail = head + 16 * NB;
+  float* tail = sinv + (nseg + 3) / 4 * 4;
   const bool vec4 = (ang0 & 3) == 0;  // then D is a multiple of 4 too: 16-byte bin stores
   int carry = 0;
   for (int s0 = 0; s0 < nseg; s0 += kWave) {
@@ -1773,37 +1773,48 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
     for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
   int acc_seg = -1;
   int4 acc_dst = make_int4(0, 0, 0, 0);  // sdst of acc_seg, read when the block enters it
-  // this block's accumulators into G (a whole segment), its head row (the
-  // last piece of a segment begun in an earlier range) or its tail row
-  // (open at the end of the range)
-  auto flush = [&](bool open) {
-    if (open || acc_dst.x < r_lo) {
-      float4* o4 = reinterpret_cast<float4*>((open ? tail : head) + blk * NB);
-#pragma unroll
-      for (int u = 0; u < NP; ++u)
-#pragma unroll
-        for (int v = 0; v < NQ; ++v)
-          o4[((4 * v + li) * NT + 4 * u) / 4] = make_float4(acc[u][v][0], acc[u][v][1], acc[u][v][2], acc[u][v][3]);
-      if (open) tseg[blk] = acc_seg;
-      else hseg[blk] = acc_seg;
-      return;
-    }
-    float* dst = G + (int64_t)(((uint64_t)(uint32_t)acc_dst.z << 32) | (uint32_t)acc_dst.y);
+  floatx4 hacc[NP][NQ];  // this block's head: the last piece of a segment begun in an earlier range
+  // a segment's bins (this lane's: (4 v + li) NT + 4 u + r) into G at its sdst entry
+  auto store_g = [&](const int4& sd, const floatx4 (&val)[NP][NQ]) {
+    float* dst = G + (int64_t)(((uint64_t)(uint32_t)sd.z << 32) | (uint32_t)sd.y);
     if (vec4) {
 #pragma unroll
       for (int u = 0; u < NP; ++u)
 #pragma unroll
         for (int v = 0; v < NQ; ++v)
           *reinterpret_cast<float4*>(dst + (4 * v + li) * NT + 4 * u) =
-              make_float4(acc[u][v][0], acc[u][v][1], acc[u][v][2], acc[u][v][3]);
+              make_float4(val[u][v][0], val[u][v][1], val[u][v][2], val[u][v][3]);
     } else {
 #pragma unroll
       for (int u = 0; u < NP; ++u)
 #pragma unroll
         for (int v = 0; v < NQ; ++v)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dst[(4 * v + li) * NT + 4 * u + r] = acc[u][v][r];
+          for (int r = 0; r < 4; ++r) dst[(4 * v + li) * NT + 4 * u + r] = val[u][v][r];
     }
+  };
+  // this block's accumulators into G (a whole segment), its tail row (open
+  // at the end of the range) or its head registers
+  auto flush = [&](bool open) {
+    if (open) {
+      float4* o4 = reinterpret_cast<float4*>(tail + blk * NB);
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v)
+          o4[((4 * v + li) * NT + 4 * u) / 4] = make_float4(acc[u][v][0], acc[u][v][1], acc[u][v][2], acc[u][v][3]);
+      tseg[blk] = acc_seg;
+      return;
+    }
+    if (acc_dst.x < r_lo) {
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int v = 0; v < NQ; ++v) hacc[u][v] = acc[u][v];
+      hseg[blk] = acc_seg;
+      return;
+    }
+    store_g(acc_dst, acc);
   };
   // one triplet of this block, broadcast from quad lane R: flush on a new
   // segment, then the lane's factors into the MFMA
@@ -1888,39 +1899,35 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
   }
   if (acc_seg >= 0) flush(stab[acc_seg + 1].x > r_hi);
   wave_lds_sync();
-  // segments split over ranges: head of the range that ends them plus the
-  // tails of the ranges before, in range order (four bins per lane)
-  const float4* head4 = reinterpret_cast<const float4*>(head);
-  const float4* tail4 = reinterpret_cast<const float4*>(tail);
-  for (int x = lane; x < 16 * NB / 4; x += kWave) {
-    const int b = x / (NB / 4), bin4 = x - b * (NB / 4);
-    const int sgm = hseg[b];
-    if (sgm < 0) continue;
-    int b0 = b;
-    while (b0 > 0 && tseg[b0 - 1] == sgm) --b0;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int bb = b0; bb < b; ++bb) {
-      const float4 t = tail4[bb * (NB / 4) + bin4];
-      v.x += t.x;
-      v.y += t.y;
-      v.z += t.z;
-      v.w += t.w;
+  // segments split over ranges: the tails of the ranges before, in range
+  // order, plus the head of the range that ends them, by that range's block
+  const int hs = hseg[blk];
+  if (hs >= 0) {
+    int b0 = blk;
+    while (b0 > 0 && tseg[b0 - 1] == hs) --b0;
+    floatx4 v[NP][NQ];
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int w = 0; w < NQ; ++w) v[u][w] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int bb = b0; bb < blk; ++bb) {
+      const float4* t4 = reinterpret_cast<const float4*>(tail + bb * NB);
+#pragma unroll
+      for (int u = 0; u < NP; ++u)
+#pragma unroll
+        for (int w = 0; w < NQ; ++w) {
+          const float4 t = t4[((4 * w + li) * NT + 4 * u) / 4];
+          v[u][w][0] += t.x;
+          v[u][w][1] += t.y;
+          v[u][w][2] += t.z;
+          v[u][w][3] += t.w;
+        }
     }
-    const float4 hd = head4[b * (NB / 4) + bin4];
-    v.x += hd.x;
-    v.y += hd.y;
-    v.z += hd.z;
-    v.w += hd.w;
-    const int4 ds = sdst[sgm];
-    float* o = G + (int64_t)(((uint64_t)(uint32_t)ds.z << 32) | (uint32_t)ds.y) + 4 * bin4;
-    if (vec4) {
-      *reinterpret_cast<float4*>(o) = v;
-    } else {
-      o[0] = v.x;
-      o[1] = v.y;
-      o[2] = v.z;
-      o[3] = v.w;
-    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u)
+#pragma unroll
+      for (int w = 0; w < NQ; ++w) v[u][w] += hacc[u][w];
+    store_g(sdst[hs], v);
   }
 }
 
