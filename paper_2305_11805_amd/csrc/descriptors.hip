@@ -1633,11 +1633,12 @@ __device__ __forceinline__ float quad_bcast(float x) {
 }
 
 // Dynamic LDS of k_desc_fwd_packed: the segment table (int4 [nseg + 1],
-// float [nseg]; int4 [nseg] with each segment's start and place in G), then
-// the tail rows of the 16 MFMA blocks (the heads stay in registers).
+// float [nseg]; int4 [nseg] with each segment's start and place in G).  The
+// heads and tails of split segments stay in registers.
 static inline size_t packed_fwd_lds(int S, int NB) {
   const int nseg = kPackAtoms * S * (S + 1) / 2;
-  return sizeof(int4) * (2 * nseg + 1) + sizeof(float) * ((nseg + 3) / 4 * 4) + sizeof(float) * 16 * NB;
+  (void)NB;
+  return sizeof(int4) * (2 * nseg + 1) + sizeof(float) * ((nseg + 3) / 4 * 4);
 }
 
 // Descriptor rows of kPackAtoms atoms per one-wave block, for atoms whose
@@ -1652,11 +1653,11 @@ static inline size_t packed_fwd_lds(int S, int NB) {
 // angle and radius factors to the 4x4x1 MFMA as in k_desc_fwd.  When a block
 // passes the end of a segment its accumulators hold the segment's last
 // piece: a segment that lies inside the block's range goes straight to G; a
-// piece that began in an earlier range is kept in the block's registers (its
-// head), and the
-// piece still open at the end of a range to its tail row.  The segments
-// split over ranges are then written as head + the tails of the ranges
-// before, in range order, so every sum has a fixed order.
+// piece that began in an earlier range (the block's head) and the piece still
+// open at the end of its range (its tail) stay in the block's registers.  A
+// segment split over ranges is then written by the block that ends it, as the
+// tails of the ranges before in range order plus its head, so every sum has a
+// fixed order.
 template <int NT, int NRA, int ZC>
 __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int64_t* __restrict__ offsets,
                                                         const int32_t* __restrict__ nbr,
@@ -1707,7 +1708,6 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
   int4* stab = reinterpret_cast<int4*>(pk_lds);
   int4* sdst = stab + nseg + 1;  // start, offset of the segment's bins in G (lo, hi)
   float* sinv = reinterpret_cast<float*>(sdst + nseg);
-  float* tail = sinv + (nseg + 3) / 4 * 4;
   const bool vec4 = (ang0 & 3) == 0;  // then D is a multiple of 4 too: 16-byte bin stores
   int carry = 0;
   for (int s0 = 0; s0 < nseg; s0 += kWave) {
@@ -1773,7 +1773,13 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
     for (int v = 0; v < NQ; ++v) acc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
   int acc_seg = -1;
   int4 acc_dst = make_int4(0, 0, 0, 0);  // sdst of acc_seg, read when the block enters it
-  floatx4 hacc[NP][NQ];  // this block's head: the last piece of a segment begun in an earlier range
+  // this block's head (the last piece of a segment begun in an earlier range)
+  // and tail (the piece open at the end of its range)
+  floatx4 hacc[NP][NQ], tacc[NP][NQ];
+#pragma unroll
+  for (int u = 0; u < NP; ++u)
+#pragma unroll
+    for (int v = 0; v < NQ; ++v) hacc[u][v] = tacc[u][v] = floatx4{0.f, 0.f, 0.f, 0.f};
   // a segment's bins (this lane's: (4 v + li) NT + 4 u + r) into G at its sdst entry
   auto store_g = [&](const int4& sd, const floatx4 (&val)[NP][NQ]) {
     float* dst = G + (int64_t)(((uint64_t)(uint32_t)sd.z << 32) | (uint32_t)sd.y);
@@ -1793,16 +1799,14 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
           for (int r = 0; r < 4; ++r) dst[(4 * v + li) * NT + 4 * u + r] = val[u][v][r];
     }
   };
-  // this block's accumulators into G (a whole segment), its tail row (open
-  // at the end of the range) or its head registers
+  // this block's accumulators into G (a whole segment), its tail (open at
+  // the end of the range) or its head
   auto flush = [&](bool open) {
     if (open) {
-      float4* o4 = reinterpret_cast<float4*>(tail + blk * NB);
 #pragma unroll
       for (int u = 0; u < NP; ++u)
 #pragma unroll
-        for (int v = 0; v < NQ; ++v)
-          o4[((4 * v + li) * NT + 4 * u) / 4] = make_float4(acc[u][v][0], acc[u][v][1], acc[u][v][2], acc[u][v][3]);
+        for (int v = 0; v < NQ; ++v) tacc[u][v] = acc[u][v];
       tseg[blk] = acc_seg;
       return;
     }
@@ -1900,29 +1904,34 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
   if (acc_seg >= 0) flush(stab[acc_seg + 1].x > r_hi);
   wave_lds_sync();
   // segments split over ranges: the tails of the ranges before, in range
-  // order, plus the head of the range that ends them, by that range's block
+  // order, plus the head of the range that ends them, by that range's block.
+  // A tail's bins sit in the same lane position of its block (lane 4 bb +
+  // li holds the bins of lane li of block blk), so each lane fetches them
+  // with a shuffle; the loop runs the same number of times in every lane.
   const int hs = hseg[blk];
-  if (hs >= 0) {
-    int b0 = blk;
+  int b0 = blk;
+  if (hs >= 0)
     while (b0 > 0 && tseg[b0 - 1] == hs) --b0;
-    floatx4 v[NP][NQ];
+  const int ntl = blk - b0;  // tails this block adds (0 without a head)
+  floatx4 v[NP][NQ];
+#pragma unroll
+  for (int u = 0; u < NP; ++u)
+#pragma unroll
+    for (int w = 0; w < NQ; ++w) v[u][w] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int it = 0; __any(it < ntl); ++it) {
+    const bool add = it < ntl;
+    const int src = 4 * (add ? b0 + it : blk) + li;
 #pragma unroll
     for (int u = 0; u < NP; ++u)
 #pragma unroll
-      for (int w = 0; w < NQ; ++w) v[u][w] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int bb = b0; bb < blk; ++bb) {
-      const float4* t4 = reinterpret_cast<const float4*>(tail + bb * NB);
+      for (int w = 0; w < NQ; ++w)
 #pragma unroll
-      for (int u = 0; u < NP; ++u)
-#pragma unroll
-        for (int w = 0; w < NQ; ++w) {
-          const float4 t = t4[((4 * w + li) * NT + 4 * u) / 4];
-          v[u][w][0] += t.x;
-          v[u][w][1] += t.y;
-          v[u][w][2] += t.z;
-          v[u][w][3] += t.w;
+        for (int r = 0; r < 4; ++r) {
+          const float t = __shfl(tacc[u][w][r], src);
+          if (add) v[u][w][r] += t;
         }
-    }
+  }
+  if (hs >= 0) {
 #pragma unroll
     for (int u = 0; u < NP; ++u)
 #pragma unroll
