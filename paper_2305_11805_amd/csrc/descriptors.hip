@@ -1527,10 +1527,13 @@ __device__ __forceinline__ int struct_of_atom16(const int64_t* atom_ptr, int32_t
 
 // Group g's lanes stage atom i's row (take: it has at most kPackNb entries)
 // into slots g kPackSlots + [0, n), sorted by species (stable, so in entry
-// order within a species, as stage_neighbors), with nb.seg[g]; with ir the
-// 1/r of each slot too.  Entries at r >= rc get a zero pair gradient if pg
-// != nullptr.  Groups that do not take their atom stage nothing (n = 0).
-__device__ void stage_packed(PackNb& nb, float* ir, int64_t i, bool take, const nn_system& sys,
+// order within a species, as stage_neighbors), with nb.seg[g].  With
+// ir_in_f (the adjoint) the record's third float holds 1/r instead of the
+// low part of r: the gradient passes do not need that part, and the
+// separate 1/r array would cost the one-wave block LDS it needs for
+// occupancy.  Entries at r >= rc get a zero pair gradient if pg != nullptr.
+// Groups that do not take their atom stage nothing (n = 0).
+__device__ void stage_packed(PackNb& nb, bool ir_in_f, int64_t i, bool take, const nn_system& sys,
                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ nbr,
                              const int8_t* __restrict__ shift, const DescConst& P, int64_t* meta,
                              float4* __restrict__ pg) {
@@ -1616,8 +1619,7 @@ __device__ void stage_packed(PackNb& nb, float* ir, int64_t i, bool take, const 
       pair_record(d[r], r2[r], r * kPackLanes + l, sp[r], P, dd, ff, irf);
       const int t = g * kPackSlots + slot[r];
       nb.d[t] = dd;
-      nb.f[t] = ff;
-      if (ir) ir[t] = irf;
+      nb.f[t] = ir_in_f ? make_float4(ff.x, ff.y, irf, ff.w) : ff;
     }
   wave_lds_sync();
 }
@@ -1680,7 +1682,7 @@ __global__ void __launch_bounds__(64) k_desc_fwd_packed(nn_system sys, const int
   const bool take = i >= 0 && offsets[i + 1] - offsets[i] <= kPackNb;
   if (!__any(take)) return;
   if (lane < 16) hseg[lane] = tseg[lane] = -1;
-  stage_packed(nb, nullptr, i, take, sys, offsets, nbr, shift, P, meta, nullptr);
+  stage_packed(nb, false, i, take, sys, offsets, nbr, shift, P, meta, nullptr);
   const int S = P.S, nblk = S * (S + 1) / 2, nseg = kPackAtoms * nblk, ang0 = P.n_rad * S;
   // radial bins: lane l of group g owns bins l, l + 16, ... of its atom
   {
@@ -1971,7 +1973,6 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
   constexpr int NB = NT * NRA;
   constexpr int kLamPre4 = 4;  // float4 (or four values) of lambda per lane requested before the staging
   __shared__ PackNb nb;
-  __shared__ float irs[kPackAtoms * kPackSlots];
   __shared__ float gx[kPackAtoms * kPackSlots], gy[kPackAtoms * kPackSlots], gz[kPackAtoms * kPackSlots];
   extern __shared__ float4 pk_lds[];
   if (meta[kMetaValid] != 1) return;  // no valid list: the gather writes zero forces
@@ -2003,7 +2004,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
       lp4[q] = make_float4(c[0], c[1], c[2], c[3]);
     }
   }
-  stage_packed(nb, irs, i, take, sys, offsets, nbr, shift, P, meta, pg);
+  stage_packed(nb, true, i, take, sys, offsets, nbr, shift, P, meta, pg);
   float* lrow = lam_s + g * Dp;
   if (take) {
     if (vec4) {  // then the LDS row is the row itself
@@ -2038,7 +2039,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
     const float* lr = lrow + nb_species(fu) * P.n_rad;
     float gr = 0.f;
     for (int k = 0; k < P.n_rad; ++k) {
-      const float dr = (u.w - P.rs_rad[k]) + (fu.z - P.rs_rad_lo[k]);
+      const float dr = (u.w - P.rs_rad[k]) - P.rs_rad_lo[k];  // r hi only: fu.z holds 1/r here
       const float gk = fexp2(-eta_r2 * dr * dr);
       gr = fmaf(lr[k] * gk, fmaf(-2.0f * P.eta_rad * dr, fu.x, fu.y), gr);
     }
@@ -2088,7 +2089,7 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
       const float* La = lam_s + a * Dp + angp;
       if (!ONE_SPECIES) La += pair_block(S, nb_species(fu), nb_species(fv)) * NB;
       const float4* La4 = reinterpret_cast<const float4*>(La);
-      const float iru = irs[j], irv = irs[k];
+      const float iru = fu.z, irv = fv.z;  // 1/r (staged in place of the low part of r)
       const TripGeom tg = triplet_geom<false>(u, fu, v, fv, P.eps_ang);
       const float c = tg.c;
       const float F2 = 2.0f * fu.x * fv.x;
