@@ -35,7 +35,7 @@ template <int H1T, int H2T>
 struct RowsShape {
   static constexpr int H1 = 16 * H1T, H2 = 16 * H2T;
   static constexpr int HM = H1 > H2 ? H1 : H2;
-  static constexpr int KC = H1 >= 128 ? 32 : 64;   // k (P1-P3) or column (P4) chunk of a staged block (LDS <= 64 KB)
+  static constexpr int KC = 32;   // k (P1-P3) or column (P4) chunk of a staged block (LDS <= 64 KB)
   static constexpr int LDW = KC + 4;               // staged [n][k] rows of P1-P3
   static constexpr int LDT = H1 + 4;               // staged [n][k] rows of P4 (k over H1)
   static constexpr int LDA = HM + 4;               // the wave's activation rows
@@ -307,7 +307,7 @@ template <int H1T, int H2T>
 struct RowsShapeBf {
   static constexpr int H1 = 16 * H1T, H2 = 16 * H2T;
   static constexpr int HM = H1 > H2 ? H1 : H2;
-  static constexpr int KC = H1 >= 128 ? 32 : 64;    // k chunk (P1-P3), column chunk (P4)
+  static constexpr int KC = 32;                     // k chunk (P1-P3), column chunk (P4)
   static constexpr int LDB = KC + 8;                // staged BF16 [n][k] rows of P1-P3
   static constexpr int LDT = H1 + 8;                // staged BF16 [n][k] rows of P4
   static constexpr int LDA = HM + 4;                // the wave's FP32 rows
