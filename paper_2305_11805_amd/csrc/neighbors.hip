@@ -238,7 +238,7 @@ __device__ void prep_flags(const int64_t* __restrict__ atom_ptr, int32_t B, int6
   } else {
     flag[0] = (use_skin && meta[kMetaValid] == 1) ? 0 : 1;
   }
-  flag[2] = 0;  // the generic passes' predicate when the cluster passes are tried (set by k_cl_decide)
+  flag[2] = 0;  // the generic passes' predicate when the cluster passes are tried (set by k_cl_count)
   flag[3] = 0;  // structures the cluster passes could not take
   *cursor = 0;  // overflow area of the counting pass's row keys
 }
@@ -1124,8 +1124,8 @@ constexpr int kClusterMax = 64;  // atoms of a structure the cluster passes take
 // the same FP64 displacement and inclusion test as the generic passes, and
 // its row is the bit mask of the j inside the radius (ascending j is the
 // canonical row order).  counts[i] = its length; with masks, the mask is
-// kept for the emit pass.  Any other structure adds to flag[3] (the generic
-// passes then build the whole list).  Non-finite positions are reported as
+// kept for the emit pass.  Any other structure adds to flag[3] and sets
+// flag[2] (the generic passes then build the whole list).  Non-finite positions are reported as
 // in the generic binning (the list is then not valid).
 __global__ void __launch_bounds__(64) k_cl_count(const double* __restrict__ pos, const int64_t* __restrict__ atom_ptr,
                                                  const uint8_t* __restrict__ pbc, double r2max,
@@ -1137,7 +1137,10 @@ __global__ void __launch_bounds__(64) k_cl_count(const double* __restrict__ pos,
   const int64_t a0 = atom_ptr[c], n = atom_ptr[c + 1] - a0;
   const uint8_t* pb = pbc + 3 * (int64_t)c;
   if (n > kClusterMax || pb[0] || pb[1] || pb[2]) {
-    if (lane == 0) atomicAdd(&flag[3], 1);
+    if (lane == 0) {
+      atomicAdd(&flag[3], 1);
+      atomicOr(&flag[2], 1);  // the generic passes run (every such block sets the same value)
+    }
     return;
   }
   const bool in = lane < n;
@@ -1165,11 +1168,6 @@ __global__ void __launch_bounds__(64) k_cl_count(const double* __restrict__ pos,
     if (masks) masks[a0 + lane] = fin ? (int64_t)m : 0;
   }
 }
-
-// flag[2] = the generic passes run: a (re)build with a structure the
-// cluster passes could not take.  (One thread after the count: a last-block
-// decision inside it would have every block update one counter.)
-__global__ void k_cl_decide(int32_t* flag) { flag[2] = (flag[0] && flag[3] > 0) ? 1 : 0; }
 
 // The rows from the masks (when the list fits and the cluster passes built
 // it): one wave per structure, one row at a time, lane j writing the entry
@@ -1254,7 +1252,6 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   if (try_cl) {
     hipLaunchKernelGGL(k_cl_count, dim3((unsigned)B), dim3(64), 0, s, sys->pos, sys->atom_ptr, sys->pbc,
                        L.radius * L.radius, L.counts, count_only ? (int64_t*)nullptr : L.key_loc, L.meta, L.flag);
-    hipLaunchKernelGGL(k_cl_decide, dim3(1), dim3(1), 0, s, L.flag);
   }
   int32_t* order = (count_only || !L.nl) ? (int32_t*)nullptr : L.nl->order;
   if (B == 1 && N <= kOneAtoms) {
