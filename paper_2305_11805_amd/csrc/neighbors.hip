@@ -708,8 +708,9 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry
 // it, with the image implied by the bin wrap and the whole-cell offsets of
 // both atoms), or a whole small structure (candidates: every atom of the
 // structure in every image with |n_d| <= K_d).  The candidates are staged
-// in LDS once per group; each wave then takes the group's atoms one at a
-// time, 64 candidates per step, with the FP64 inclusion test.
+// in LDS once per group (of a binned group the first kCandMax; the steps
+// past them read bin_m / bin_x from HBM); each wave then takes the group's
+// atoms one at a time, 64 candidates per step, with the FP64 inclusion test.
 //   kRowsCount: row_count[i] = number of entries.
 //   kRowsKeys : also the row's keys (j, n_a, n_b, n_c), collected in LDS and
 //               put in order by each key's rank among them, go to the
@@ -724,7 +725,7 @@ constexpr int kGrpThreads = 64 * kGrpWaves;
 // two from 16384 atoms on, where the groups alone are enough and each block
 // stages its candidates for more atoms.
 static int grp_split(int64_t n_atoms) { return n_atoms >= 16384 ? 2 : 4; }
-constexpr int kCandMax = 768;   // binned groups with more candidates read them from HBM
+constexpr int kCandMax = 768;   // a binned group's candidates past this many are read from HBM
 constexpr int kKeyLds = 256;    // row keys kept in LDS; longer rows take a second pass through HBM
 
 // Orders this wave's LDS writes before its later LDS reads of other lanes'
@@ -778,7 +779,7 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
     const int w1 = 2 * K1 + 1, w2 = 2 * K2 + 1;
     const int64_t nimg = (int64_t)(2 * K0 + 1) * w1 * w2;
     int64_t total;
-    bool staged = true;
+    int64_t n_st = 0;  // binned: the candidates staged in LDS, the first kCandMax
     if (small) {
       const int n_at = (int)(a_hi - a_lo);  // <= kSmallMax <= kCandMax
       for (int t = tid; t < n_at; t += kGrpThreads) {
@@ -833,26 +834,25 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
       }
       __syncthreads();
       total = b_pre[27];
-      staged = total <= kCandMax;
-      if (staged)
-        for (int t = tid; t < total; t += kGrpThreads) {
-          int lo = 0, hi = 26;  // largest b with b_pre[b] <= t
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (b_pre[mid] <= t) lo = mid;
-            else hi = mid - 1;
-          }
-          const int64_t k = b_start[lo] + (t - b_pre[lo]);
-          const int4 m4 = bin_m[k];
-          const double4 x4 = bin_x[k];
-          cx[t] = x4.x;
-          cy[t] = x4.y;
-          cz[t] = x4.z;
-          cj[t] = m4.x;
-          cw[0][t] = p3[0] ? b_wr[lo][0] - m4.y : 0;
-          cw[1][t] = p3[1] ? b_wr[lo][1] - m4.z : 0;
-          cw[2][t] = p3[2] ? b_wr[lo][2] - m4.w : 0;
+      n_st = total < kCandMax ? total : kCandMax;
+      for (int t = tid; t < n_st; t += kGrpThreads) {
+        int lo = 0, hi = 26;  // largest b with b_pre[b] <= t
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (b_pre[mid] <= t) lo = mid;
+          else hi = mid - 1;
         }
+        const int64_t k = b_start[lo] + (t - b_pre[lo]);
+        const int4 m4 = bin_m[k];
+        const double4 x4 = bin_x[k];
+        cx[t] = x4.x;
+        cy[t] = x4.y;
+        cz[t] = x4.z;
+        cj[t] = m4.x;
+        cw[0][t] = p3[0] ? b_wr[lo][0] - m4.y : 0;
+        cw[1][t] = p3[1] ? b_wr[lo][1] - m4.z : 0;
+        cw[2][t] = p3[2] ? b_wr[lo][2] - m4.w : 0;
+      }
     }
     __syncthreads();
     for (int64_t a = a_lo + (int64_t)blockIdx.y * kGrpWaves + wv; a < a_hi; a += (int64_t)kGrpWaves * gridDim.y) {
@@ -884,7 +884,7 @@ __global__ void __launch_bounds__(kGrpThreads) k_nb_rows(const int64_t* __restri
               xj[0] = cx[jj];
               xj[1] = cy[jj];
               xj[2] = cz[jj];
-            } else if (staged) {
+            } else if (t < n_st) {
               j = cj[t];
               xj[0] = cx[t];
               xj[1] = cy[t];
