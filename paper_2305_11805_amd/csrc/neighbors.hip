@@ -1051,6 +1051,25 @@ __device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t wa
   return r;
 }
 
+// Position of `want` in the sorted keys[0, len), or -1, by bisection: one
+// read per halving (about log2(len) + 1 in all, against about 16 for
+// find_key8 on a row of 100), for lists large enough that the searches are
+// bound by the number of scattered reads rather than by their latency.
+template <class KeyAt>
+__device__ __forceinline__ int find_key2(const KeyAt& keys, int len, uint64_t want) {
+  int lo = 0, n = len;  // the first position whose key is not below want is in [lo, lo + n]
+  while (n > 0) {
+    const int h = n >> 1;
+    if (keys(lo + h) < want) {
+      lo += h + 1;
+      n -= h + 1;
+    } else {
+      n = h;
+    }
+  }
+  return lo < len && keys(lo) == want ? lo : -1;
+}
+
 // Writes the rows from the keys the counting pass left (key_loc), with the
 // reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
 // whose position is found among row j's sorted keys.  Also records the
@@ -1059,8 +1078,9 @@ __device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t wa
 // every LPA-th entry of the row; with
 // the bin order, block b takes the atoms at slots ((b mod 8) * per + b / 8)
 // * 64 / LPA + (0 .. 64 / LPA - 1), so each XCD walks a contiguous stretch
-// of space and the neighbor rows it searches stay in its L2.
-template <int LPA>
+// of space and the neighbor rows it searches stay in its L2.  BISECT: the
+// reverse entries are found by find_key2 instead of find_key8.
+template <int LPA, bool BISECT>
 __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys,
                                                 const int64_t* __restrict__ key_loc,
                                                 const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
@@ -1102,7 +1122,8 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
     const int64_t f0 = offsets[j];
     const int lj = (int)(offsets[j + 1] - f0);
     const uint64_t* theirs = row_keys + key_loc[j];
-    const int r = find_key8([&](int p) { return theirs[p]; }, lj, want);
+    const auto key_at = [&](int p) { return theirs[p]; };
+    const int r = BISECT ? find_key2(key_at, lj, want) : find_key8(key_at, lj, want);
     // a missing reverse entry cannot happen for an exactly symmetric list;
     // point at the entry itself (zero net force) and flag it
     rev[e0 + t] = (int32_t)(r >= 0 ? f0 + r : e0 + t);
@@ -1232,6 +1253,10 @@ int row_key_slot(int64_t n_atoms, int64_t capacity) {
   return k;
 }
 
+// From this many atoms the emit pass bisects (its scattered reads, not their
+// latency, bound it there).
+constexpr int64_t kEmitBisectAtoms = 16384;
+
 void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_only, hipStream_t s) {
   const nn_system* sys = L.sys;
   const int64_t N = sys->n_atoms;
@@ -1304,12 +1329,16 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const int lpa = (L.capacity <= 16 * N || N >= 16384) ? 16 : 32;
   const int64_t nw = (N + kWave / lpa - 1) / (kWave / lpa);
   const unsigned gEmit = nl->order ? (unsigned)((nw + 7) / 8 * 8) : (unsigned)nw;  // whole rounds of the 8 XCDs
-  if (lpa == 16)
-    hipLaunchKernelGGL(k_nb_emit<16>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
-                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
+  const bool bisect = N >= kEmitBisectAtoms;
+  if (lpa == 16 && bisect)
+    hipLaunchKernelGGL((k_nb_emit<16, true>), dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets,
+                       nl->nbr, nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
+  else if (lpa == 16)
+    hipLaunchKernelGGL((k_nb_emit<16, false>), dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets,
+                       nl->nbr, nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
   else
-    hipLaunchKernelGGL(k_nb_emit<32>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
-                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
+    hipLaunchKernelGGL((k_nb_emit<32, false>), dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets,
+                       nl->nbr, nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
   if (try_cl)
     hipLaunchKernelGGL(k_cl_emit, dim3((unsigned)B), dim3(64), 0, s, sys->atom_ptr, L.key_loc, nl->offsets, nl->nbr,
                        nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
