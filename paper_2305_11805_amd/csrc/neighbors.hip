@@ -701,7 +701,6 @@ __device__ __forceinline__ uint64_t entry_key(int32_t j, int na, int nb, int nc)
   return ((uint64_t)(uint32_t)j << 24) | ((uint64_t)(uint8_t)(na + 128) << 16) | ((uint64_t)(uint8_t)(nb + 128) << 8) |
          (uint64_t)(uint8_t)(nc + 128);
 }
-__device__ __forceinline__ uint64_t entry_key(int32_t j, char4 s) { return entry_key(j, s.x, s.y, s.z); }
 
 // Row passes, one block per group of atoms that share their candidates: a
 // bin of a binned structure (candidates: the atoms of the 27 bins around
@@ -1018,69 +1017,22 @@ __device__ __forceinline__ void decode_key(uint64_t k, int32_t& j, char4& sv) {
   sv.w = 0;
 }
 
-// Position of `want` in the sorted keys[0, len), or -1: rounds of seven
-// independent probes cut the range eightfold, then at most eight keys are
-// compared directly.
-template <class KeyAt>
-__device__ __forceinline__ int find_key8(const KeyAt& keys, int len, uint64_t want) {
-  int lo = 0, hi = len;  // keys[< lo] < want < keys[>= hi]
-  while (hi - lo > 8) {
-    const int step = (hi - lo + 7) >> 3;
-    uint64_t kq[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) {
-      const int p = lo + step * (q + 1);
-      kq[q] = p < hi ? keys(p) : ~0ull;
-    }
-    int c = 0;  // probes below want
-#pragma unroll
-    for (int q = 0; q < 7; ++q) c += kq[q] < want ? 1 : 0;
-    if (c < 7 && kq[c] == want) return lo + step * (c + 1);
-    const int nlo = c > 0 ? lo + step * c + 1 : lo;
-    const int nhi = min(hi, lo + step * (c + 1));
-    lo = nlo;
-    hi = nhi;
-  }
-  uint64_t kq[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) kq[q] = lo + q < hi ? keys(lo + q) : ~0ull;
-  int r = -1;
-#pragma unroll
-  for (int q = 0; q < 8; ++q)
-    if (kq[q] == want) r = lo + q;
-  return r;
-}
-
-// Position of `want` in the sorted keys[0, len), or -1, by bisection: one
-// read per halving (about log2(len) + 1 in all, against about 16 for
-// find_key8 on a row of 100), for lists large enough that the searches are
-// bound by the number of scattered reads rather than by their latency.
-template <class KeyAt>
-__device__ __forceinline__ int find_key2(const KeyAt& keys, int len, uint64_t want) {
-  int lo = 0, n = len;  // the first position whose key is not below want is in [lo, lo + n]
-  while (n > 0) {
-    const int h = n >> 1;
-    if (keys(lo + h) < want) {
-      lo += h + 1;
-      n -= h + 1;
-    } else {
-      n = h;
-    }
-  }
-  return lo < len && keys(lo) == want ? lo : -1;
-}
-
 // Writes the rows from the keys the counting pass left (key_loc), with the
 // reverse entry of every entry (i -> j, n): the entry (j -> i, -n) of row j,
-// whose position is found among row j's sorted keys.  Also records the
-// positions of this build (skin reference) and marks the list valid.  LPA
-// lanes per atom (64 / LPA atoms per one-wave block), each lane taking
-// every LPA-th entry of the row; with
+// whose position is found among row j's sorted keys by bisection (about
+// log2(len) + 1 reads; rounds of seven independent probes, fewer dependent
+// rounds but about 16 reads on a row of 100, were slower from 4096 atoms up).
+// Each lane runs the searches of kEmitU entries in lockstep, so that their
+// chains of dependent reads overlap.  Also records the positions of this
+// build (skin reference) and marks the list valid.  LPA lanes per atom
+// (64 / LPA atoms per one-wave block), each lane taking every LPA-th entry
+// of the row; with
 // the bin order, block b takes the atoms at slots ((b mod 8) * per + b / 8)
 // * 64 / LPA + (0 .. 64 / LPA - 1), so each XCD walks a contiguous stretch
-// of space and the neighbor rows it searches stay in its L2.  BISECT: the
-// reverse entries are found by find_key2 instead of find_key8.
-template <int LPA, bool BISECT>
+// of space and the neighbor rows it searches stay in its L2.
+constexpr int kEmitU = 4;
+
+template <int LPA>
 __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __restrict__ row_keys,
                                                 const int64_t* __restrict__ key_loc,
                                                 const int64_t* __restrict__ offsets, int32_t* __restrict__ nbr,
@@ -1107,27 +1059,66 @@ __global__ void __launch_bounds__(64) k_nb_emit(int64_t N, const uint64_t* __res
   const int len = (int)(offsets[i + 1] - e0);
   const uint64_t* mine = row_keys + key_loc[i];
   char4* sh4 = reinterpret_cast<char4*>(shift);
-  for (int t = sl; t < len; t += LPA) {
-    int32_t j;
-    char4 sv;
-    decode_key(mine[t], j, sv);
-    nbr[e0 + t] = j;
-    sh4[e0 + t] = sv;
-    char4 ns;
-    ns.x = (signed char)(-sv.x);
-    ns.y = (signed char)(-sv.y);
-    ns.z = (signed char)(-sv.z);
-    ns.w = 0;
-    const uint64_t want = entry_key((int32_t)i, ns);
-    const int64_t f0 = offsets[j];
-    const int lj = (int)(offsets[j + 1] - f0);
-    const uint64_t* theirs = row_keys + key_loc[j];
-    const auto key_at = [&](int p) { return theirs[p]; };
-    const int r = BISECT ? find_key2(key_at, lj, want) : find_key8(key_at, lj, want);
-    // a missing reverse entry cannot happen for an exactly symmetric list;
-    // point at the entry itself (zero net force) and flag it
-    rev[e0 + t] = (int32_t)(r >= 0 ? f0 + r : e0 + t);
-    if (r < 0) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+  for (int t0 = sl; t0 < len; t0 += kEmitU * LPA) {
+    uint64_t want[kEmitU];
+    const uint64_t* theirs[kEmitU];
+    int64_t f0[kEmitU];
+    int lj[kEmitU], lo[kEmitU], n[kEmitU];
+#pragma unroll
+    for (int u = 0; u < kEmitU; ++u) {
+      const int t = t0 + u * LPA;
+      lo[u] = 0;
+      n[u] = 0;
+      lj[u] = 0;
+      f0[u] = 0;
+      want[u] = 0;
+      theirs[u] = row_keys;
+      if (t < len) {
+        int32_t j;
+        char4 sv;
+        decode_key(mine[t], j, sv);
+        nbr[e0 + t] = j;
+        sh4[e0 + t] = sv;
+        want[u] = entry_key((int32_t)i, -sv.x, -sv.y, -sv.z);
+        f0[u] = offsets[j];
+        lj[u] = (int)(offsets[j + 1] - f0[u]);
+        n[u] = lj[u];
+        theirs[u] = row_keys + key_loc[j];
+      }
+    }
+    // lower bounds: the first position whose key is not below want[u] is in
+    // [lo[u], lo[u] + n[u]]
+    while (true) {
+      bool more = false;
+      uint64_t k[kEmitU];
+#pragma unroll
+      for (int u = 0; u < kEmitU; ++u) k[u] = n[u] > 0 ? theirs[u][lo[u] + (n[u] >> 1)] : 0;
+#pragma unroll
+      for (int u = 0; u < kEmitU; ++u) {
+        if (n[u] > 0) {
+          const int h = n[u] >> 1;
+          if (k[u] < want[u]) {
+            lo[u] += h + 1;
+            n[u] -= h + 1;
+          } else {
+            n[u] = h;
+          }
+        }
+        more |= n[u] > 0;
+      }
+      if (!more) break;
+    }
+#pragma unroll
+    for (int u = 0; u < kEmitU; ++u) {
+      const int t = t0 + u * LPA;
+      if (t < len) {
+        const bool found = lo[u] < lj[u] && theirs[u][lo[u]] == want[u];
+        // a missing reverse entry cannot happen for an exactly symmetric
+        // list; point at the entry itself (zero net force) and flag it
+        rev[e0 + t] = (int32_t)(found ? f0[u] + lo[u] : e0 + t);
+        if (!found) atomicOr((unsigned long long*)&meta[kMetaErr], (unsigned long long)kErrTooMany);
+      }
+    }
   }
 }
 
@@ -1253,10 +1244,6 @@ int row_key_slot(int64_t n_atoms, int64_t capacity) {
   return k;
 }
 
-// From this many atoms the emit pass bisects (its scattered reads, not their
-// latency, bound it there).
-constexpr int64_t kEmitBisectAtoms = 16384;
-
 void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_only, hipStream_t s) {
   const nn_system* sys = L.sys;
   const int64_t N = sys->n_atoms;
@@ -1329,16 +1316,12 @@ void launch_neighbors(const NbLaunch& L, bool use_skin, double skin, bool count_
   const int lpa = (L.capacity <= 16 * N || N >= 16384) ? 16 : 32;
   const int64_t nw = (N + kWave / lpa - 1) / (kWave / lpa);
   const unsigned gEmit = nl->order ? (unsigned)((nw + 7) / 8 * 8) : (unsigned)nw;  // whole rounds of the 8 XCDs
-  const bool bisect = N >= kEmitBisectAtoms;
-  if (lpa == 16 && bisect)
-    hipLaunchKernelGGL((k_nb_emit<16, true>), dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets,
-                       nl->nbr, nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
-  else if (lpa == 16)
-    hipLaunchKernelGGL((k_nb_emit<16, false>), dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets,
-                       nl->nbr, nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
+  if (lpa == 16)
+    hipLaunchKernelGGL(k_nb_emit<16>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
   else
-    hipLaunchKernelGGL((k_nb_emit<32, false>), dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets,
-                       nl->nbr, nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
+    hipLaunchKernelGGL(k_nb_emit<32>, dim3(gEmit), dim3(64), 0, s, N, L.row_keys, L.key_loc, nl->offsets, nl->nbr,
+                       nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag, gflag);
   if (try_cl)
     hipLaunchKernelGGL(k_cl_emit, dim3((unsigned)B), dim3(64), 0, s, sys->atom_ptr, L.key_loc, nl->offsets, nl->nbr,
                        nl->shift, nl->rev, sys->pos, nl->ref_pos, nl->order, L.meta, L.flag);
