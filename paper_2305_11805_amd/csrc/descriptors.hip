@@ -1196,6 +1196,10 @@ __global__ void __launch_bounds__(64 * WPA) k_desc_tan(nn_system sys, const int6
 
 // Per-pair energy gradients dE_i/dd_e (float4 per entry, w unused) from
 // lambda_i = dE_i/dG_i.
+// Floats of the adjoint's radial lambda in LDS: S n_rad rounded up to a
+// multiple of 4, so that the angular blocks after it are float4-aligned.
+__host__ __device__ constexpr int adj_lam_radial(int S, int n_rad) { return (S * n_rad + 3) / 4 * 4; }
+
 template <int NT, int NRA, bool ONE_SPECIES, int WPA, int ZC>
 __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, const int64_t* __restrict__ offsets,
                                               const int32_t* __restrict__ nbr, const int8_t* __restrict__ shift,
@@ -1205,9 +1209,11 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
   constexpr int NBP = NB + 4;  // padded block stride in LDS (bank spread)
   __shared__ AtomNb nb;
   __shared__ float gx[WPA][kMaxNb], gy[WPA][kMaxNb], gz[WPA][kMaxNb];  // one accumulator set per wave
-  extern __shared__ float dyn_lds[];  // [S * n_rad] radial lambda, then the angular blocks
-  float* lam_r = dyn_lds;
-  float* lam_a = dyn_lds + P.S * P.n_rad;
+  // [S * n_rad] radial lambda, padded to a multiple of 4 floats, then the
+  // angular blocks (16-byte aligned, read as float4)
+  extern __shared__ float4 dyn_lds4[];
+  float* lam_r = reinterpret_cast<float*>(dyn_lds4);
+  float* lam_a = lam_r + adj_lam_radial(P.S, P.n_rad);
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t e0 = offsets[i];
   // this atom's lambda is requested before the neighbor staging (whose
@@ -1349,6 +1355,7 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
       const float4 v = nb.d[k], fv = nb.f[k];
       const float* La = lam_a;
       if (!ONE_SPECIES) La = lam_a + pair_block(S, nb_species(fu), nb_species(fv)) * NBP;
+      const float4* La4 = reinterpret_cast<const float4*>(La);  // NBP and the block base are multiples of 4
       const float iru = nb.ir[j], irv = nb.ir[k];
       const TripGeom g = triplet_geom<false>(u, fu, v, fv, P.eps_ang);
       const float c = g.c;
@@ -1376,10 +1383,15 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
       for (int q = 0; q < NRA; ++q) {
         float tq = 0.f;
 #pragma unroll
-        for (int p = 0; p < NT; ++p) {
-          const float l = La[q * NT + p];  // LDS (a broadcast with one species)
-          tq = fmaf(l, A[p], tq);
-          U[p] = fmaf(l, R[q], U[p]);
+        for (int p4 = 0; p4 < NT / 4; ++p4) {
+          const float4 l4 = La4[q * (NT / 4) + p4];  // LDS (a broadcast with one species)
+          const float l[4] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int p = 4 * p4 + c;
+            tq = fmaf(l[c], A[p], tq);
+            U[p] = fmaf(l[c], R[q], U[p]);
+          }
         }
         Tq[q] = tq;
       }
@@ -2326,7 +2338,8 @@ static void launch_tan_t(const nn_system& sys, const nn_nlist& nl, const DescCon
 template <int NT, int NRA, bool ONE, int WPA, int ZC>
 static void launch_adj_w(const nn_system& sys, const nn_nlist& nl, const DescConst& P, const float* lam, float4* pg,
                          hipStream_t s) {
-  const size_t lds = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
+  const size_t lds =
+      sizeof(float) * ((size_t)adj_lam_radial(P.S, P.n_rad) + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
   hipLaunchKernelGGL((k_desc_adj<NT, NRA, ONE, WPA, ZC>), dim3(atom_grid(sys.n_atoms, nl.order)), dim3(64 * WPA), lds,
                      s, sys, nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta, nl.order);
 }
@@ -2337,7 +2350,8 @@ static void launch_adj_packed(const nn_system& sys, const nn_nlist& nl, const De
   const size_t lds = sizeof(float) * kPackAtoms * packed_lam_stride(P.S, P.n_rad, NT * NRA);
   hipLaunchKernelGGL((k_desc_adj_packed<NT, NRA, ONE, ZC>), dim3(packed_grid(sys.n_atoms)), dim3(64), lds, s, sys,
                      nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta);
-  const size_t lds1 = sizeof(float) * ((size_t)P.S * P.n_rad + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
+  const size_t lds1 =
+      sizeof(float) * ((size_t)adj_lam_radial(P.S, P.n_rad) + (size_t)(P.S * (P.S + 1) / 2) * (NT * NRA + 4));
   hipLaunchKernelGGL((k_desc_adj_long<NT, NRA, ONE, ZC>), dim3((unsigned)((sys.n_atoms + kWave - 1) / kWave)),
                      dim3(64), lds1, s, sys, nl.offsets, nl.nbr, nl.shift, P, lam, pg, nl.meta, nl.order);
 }
