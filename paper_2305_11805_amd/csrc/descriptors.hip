@@ -1208,7 +1208,7 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
   constexpr int NB = NT * NRA;
   constexpr int NBP = NB + 4;  // padded block stride in LDS (bank spread)
   __shared__ AtomNb nb;
-  __shared__ float gx[WPA][kMaxNb], gy[WPA][kMaxNb], gz[WPA][kMaxNb];  // one accumulator set per wave
+  __shared__ float4 gxyz[WPA][kMaxNb];  // one accumulator set per wave: dE/dd of each slot (x, y, z, -)
   // [S * n_rad] radial lambda, padded to a multiple of 4 floats, then the
   // angular blocks (16-byte aligned, read as float4)
   extern __shared__ float4 dyn_lds4[];
@@ -1248,11 +1248,7 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
     if (d < P.D) put_lam(d, lpre[q]);
   }
   for (int d = tid + kLamPre * 64 * WPA; d < P.D; d += 64 * WPA) put_lam(d, lam[d]);
-  for (int t = lane; t < n; t += kWave) {
-    gx[wv][t] = 0.f;
-    gy[wv][t] = 0.f;
-    gz[wv][t] = 0.f;
-  }
+  for (int t = lane; t < n; t += kWave) gxyz[wv][t] = make_float4(0.f, 0.f, 0.f, 0.f);
   __syncthreads();
   const float eta_r2 = P.eta_rad * 1.4426950408889634f;
   const float eta_a2 = P.eta_ang * 1.4426950408889634f;
@@ -1268,9 +1264,11 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
         const float g = fexp2(-eta_r2 * dr * dr);
         gr = fmaf(lr[k] * g, fmaf(-2.0f * P.eta_rad * dr, fu.x, fu.y), gr);
       }
-      gx[wv][t] += gr * u.x;
-      gy[wv][t] += gr * u.y;
-      gz[wv][t] += gr * u.z;
+      float4 a = gxyz[wv][t];
+      a.x += gr * u.x;
+      a.y += gr * u.y;
+      a.z += gr * u.z;
+      gxyz[wv][t] = a;
     }
   }
   const int zeta1 = P.zeta - 1;
@@ -1430,15 +1428,19 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
     const int s_lo = __shfl(sj_step, 0), s_hi = __shfl(sj_step, last);
     for (int ss = s_lo; ss <= s_hi; ++ss) {
       if (take && sj_step == ss) {  // plain read-add-write: no two lanes share a slot here
-        gx[wv][k] += gkx;
-        gy[wv][k] += gky;
-        gz[wv][k] += gkz;
+        float4 a = gxyz[wv][k];
+        a.x += gkx;
+        a.y += gky;
+        a.z += gkz;
+        gxyz[wv][k] = a;
       }
       wave_lds_sync();
       if (take && sj_step == ss) {
-        gx[wv][j] += gjx;
-        gy[wv][j] += gjy;
-        gz[wv][j] += gjz;
+        float4 a = gxyz[wv][j];
+        a.x += gjx;
+        a.y += gjy;
+        a.z += gjz;
+        gxyz[wv][j] = a;
       }
       wave_lds_sync();
     }
@@ -1448,9 +1450,10 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
     float x = 0.f, y = 0.f, z = 0.f;
 #pragma unroll
     for (int w = 0; w < WPA; ++w) {
-      x += gx[w][t];
-      y += gy[w][t];
-      z += gz[w][t];
+      const float4 a = gxyz[w][t];
+      x += a.x;
+      y += a.y;
+      z += a.z;
     }
     pg[e0 + nb_entry(nb.f[t])] = make_float4(x, y, z, 0.f);
   }
