@@ -54,6 +54,12 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
+// Keeps this wave's LDS accesses in program order without waiting for them
+// to complete: the LDS serves one wave's instructions in the order they are
+// issued, so a read issued after a write of the same address by any lane of
+// the wave returns the written value.  Only the compiler has to be kept from
+// moving or caching accesses across it.
+__device__ __forceinline__ void wave_lds_order() { __asm__ volatile("" ::: "memory"); }
 __device__ __forceinline__ int nb_species(const float4& f) { return __float_as_int(f.w) & 15; }
 __device__ __forceinline__ int nb_entry(const float4& f) { return __float_as_int(f.w) >> 4; }
 
@@ -1434,7 +1440,7 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
         a.z += gkz;
         gxyz[wv][k] = a;
       }
-      wave_lds_sync();
+      wave_lds_order();
       if (take && sj_step == ss) {
         float4 a = gxyz[wv][j];
         a.x += gjx;
@@ -1442,7 +1448,7 @@ __device__ __forceinline__ void desc_adj_atom(int64_t i, const nn_system& sys, c
         a.z += gjz;
         gxyz[wv][j] = a;
       }
-      wave_lds_sync();
+      wave_lds_order();
     }
   }
   __syncthreads();
@@ -2176,13 +2182,13 @@ __global__ void __launch_bounds__(64) k_desc_adj_packed(nn_system sys, const int
         gy[k] += gky;
         gz[k] += gkz;
       }
-      wave_lds_sync();
+      wave_lds_order();
       if (mine) {
         gx[j] += gjx;
         gy[j] += gjy;
         gz[j] += gjz;
       }
-      wave_lds_sync();
+      wave_lds_order();
     }
   }
   if (take) {
